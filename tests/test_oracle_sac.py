@@ -1,0 +1,197 @@
+"""Pins of the oracle's full update: optimiser closed forms, the temperature
+direction, and every gradient of one update against torch autograd on an
+independently stated graph (target recomputed in torch, projection by the
+scatter form)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+from oracle import layout, nets, philox, sac
+from oracle.squint import squint
+from paper_2602_21203_amd import synthetic
+from tests import torch_ref
+
+torch.set_default_dtype(torch.float64)
+
+
+def T(x, grad=False):
+    return torch.tensor(np.asarray(x), dtype=torch.float64, requires_grad=grad)
+
+
+def np_replay(d, cap, seed=0):
+    rep = synthetic.replay(cap, d.H, d.W, d.C, d.proprio, d.action, seed=seed)
+    return {k: (v.numpy() if torch.is_tensor(v) else v) for k, v in rep.items()}
+
+
+def table(d):
+    return [(n, o, s) for n, (o, s) in layout.offsets(d)[0].items()]
+
+
+def test_adam_first_step_closed_form():
+    hp = sac.hparams(layout.dims(**layout.TINY))
+    g = np.array([1e-3, -2.0, 5e-9, 0.0, 3.0])
+    p, m, v = np.zeros(5), np.zeros(5), np.zeros(5)
+    sac.adam(p, g, m, v, 1, hp)
+    np.testing.assert_allclose(p, -hp.lr * g / (np.abs(g) + hp.adam_eps), rtol=1e-12, atol=0)
+
+
+def test_adam_matches_torch_optim_10_steps():
+    hp = sac.hparams(layout.dims(**layout.TINY))
+    rng = np.random.default_rng(0)
+    p0 = rng.normal(size=50)
+    gs = rng.normal(size=(10, 50))
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    pt = torch.tensor(p0.copy(), requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=hp.lr, betas=(hp.beta1, hp.beta2), eps=hp.adam_eps)
+    for t in range(10):
+        sac.adam(p, gs[t], m, v, t + 1, hp)
+        pt.grad = torch.tensor(gs[t])
+        opt.step()
+    np.testing.assert_allclose(p, pt.detach().numpy(), rtol=1e-12, atol=1e-15)
+
+
+def test_ema_closed_form():
+    rng = np.random.default_rng(1)
+    t0, th = rng.normal(size=20), rng.normal(size=20)
+    t = t0.copy()
+    for _ in range(37):
+        sac.ema(t, th, 0.995)
+    np.testing.assert_allclose(t, 0.995 ** 37 * t0 + (1 - 0.995 ** 37) * th, rtol=1e-12)
+
+
+def _setup(cfg, B, cap=256, seed=0, **hpkw):
+    d = layout.dims(**getattr(layout, cfg))
+    rep = np_replay(d, cap, seed)
+    p = synthetic.init_params(table(d), seed=1).astype(np.float64)
+    st = sac.new_state(d, p)
+    hp = sac.hparams(d, **hpkw)
+    return d, rep, st, hp
+
+
+def test_temperature_moves_toward_target_entropy():
+    d, rep, st, hp = _setup("TINY", 32)
+    probe = sac.copy_state(st)
+    ent = sac.sac_update(probe, rep, d, hp, 32)["stats"][4]
+    for delta, sign in ((+1.0, +1), (-1.0, -1)):
+        s2 = sac.copy_state(st)
+        hp2 = sac.hparams(d, target_entropy=ent + delta)
+        out = sac.sac_update(s2, rep, d, hp2, 32)
+        assert out["stats"][4] == pytest.approx(ent)
+        alpha1 = out["stats"][3]
+        assert np.sign(alpha1 - 1.0) == sign  # log alpha starts at 0
+
+
+def _torch_update_grads(d, rep, st, hp, B, out):
+    """Gradients of one update from torch autograd on an independently stated graph."""
+    tab = layout.offsets(d)[0]
+    idx = philox.sample_indices(hp.seed, st.u, rep["size"], B)
+    eps_n = T(philox.gaussian(hp.seed, st.u, 1, B * d.action).reshape(B, d.action))
+    eps = T(philox.gaussian(hp.seed, st.u, 2, B * d.action).reshape(B, d.action))
+    g = lambda k: T(rep[k][idx].astype(np.float64))
+    s, s2, a, r, done = g("proprio"), g("next_proprio"), g("action"), g("reward"), g("done")
+    x = T(np.concatenate([squint(rep["obs"][idx], d.k), squint(rep["next_obs"][idx], d.k)]))
+    pt = T(st.params, True)
+    P = torch_ref.views(pt, tab)
+    feat = torch_ref.encoder(P, x, d.n_conv)
+    f_t, f_n = feat[:B], feat[B:]
+    log_alpha = P["log_alpha"][0]
+    alpha = log_alpha.detach().exp()
+    with torch.no_grad():
+        a_n, lp_n = torch_ref.actor(P, f_n, s2, eps_n, hp.log_std_min, hp.log_std_max)
+        base = layout.blocks(d)["critic"][0]
+        Tt = torch_ref.views(T(st.target), {k: (o - base, sh) for k, (o, sh) in tab.items()
+                                            if k.startswith(("critic.", "q1.", "q2."))})
+        lbar = torch_ref.critic(Tt, f_n, s2, a_n)
+        pbar = 0.5 * (torch.softmax(lbar[0], -1) + torch.softmax(lbar[1], -1))
+        N = d.atoms
+        dz = (d.v_max - d.v_min) / (N - 1)
+        z = d.v_min + torch.arange(N) * dz
+        Tz = (r[:, None] + hp.gamma * (1 - done[:, None]) * (z[None] - alpha * lp_n[:, None]))
+        bpos = ((Tz.clamp(d.v_min, d.v_max) - d.v_min) / dz)
+        lo, hi = bpos.floor().long(), bpos.ceil().long()
+        m = torch.zeros(B, N)
+        wl = torch.where(lo == hi, pbar, pbar * (hi - bpos))
+        m.scatter_add_(1, lo, wl)
+        m.scatter_add_(1, hi, torch.where(lo == hi, torch.zeros_like(pbar), pbar * (bpos - lo)))
+    np.testing.assert_allclose(out["m"], m.numpy(), atol=1e-12)
+    logits = torch_ref.critic(P, f_t, s, a)
+    loss_c = -(m[None] * F.log_softmax(logits, -1)).sum(-1).mean(1).sum()
+    loss_c.backward()
+    g_ec = pt.grad.numpy()[: layout.blocks(d)["critic"][1]].copy()
+    # temperature
+    la = T([st.params[layout.blocks(d)["log_alpha"][0]]], True)
+    a_t, lp_t = torch_ref.actor(torch_ref.views(T(st.params), tab), f_t.detach(), s, eps,
+                                hp.log_std_min, hp.log_std_max)
+    (la.exp() * (-lp_t.detach() - hp.target_entropy).mean()).sum().backward()
+    # actor against the updated critic (post-step params from the oracle's state)
+    pn = T(out["params_after"])
+    pa = T(st.params, True)
+    Pa = torch_ref.views(pa, tab)
+    a_t, lp_t = torch_ref.actor(Pa, f_t.detach(), s, eps, hp.log_std_min, hp.log_std_max)
+    lq = torch_ref.critic(torch_ref.views(pn, tab), f_t.detach(), s, a_t)
+    q = torch.softmax(lq, -1) @ z
+    alpha_new = math.exp(out["params_after"][layout.blocks(d)["log_alpha"][0]])
+    loss_pi = (alpha_new * lp_t - 0.5 * (q[0] + q[1])).mean()
+    loss_pi.backward()
+    a0, a1 = layout.blocks(d)["actor"]
+    return dict(g_ec=g_ec, g_la=la.grad.numpy(), g_actor=pa.grad.numpy()[a0:a1],
+                loss_c=float(loss_c.detach()), loss_pi=float(loss_pi.detach()))
+
+
+@pytest.mark.parametrize("cfg,B", [("TINY", 32), ("FULL", 24)])
+def test_full_update_gradients_vs_autograd(cfg, B):
+    d, rep, st, hp = _setup(cfg, B, cap=128)
+    st0 = sac.copy_state(st)
+    out = sac.sac_update(st, rep, d, hp, B)
+    out["params_after"] = st.params
+    ref = _torch_update_grads(d, rep, st0, hp, B, out)
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    assert rel(out["g_enc_critic"], ref["g_ec"]) < 1e-10
+    assert rel(out["g_log_alpha"], ref["g_la"]) < 1e-10
+    assert rel(out["g_actor"], ref["g_actor"]) < 1e-10
+    assert out["stats"][0] == pytest.approx(ref["loss_c"], rel=1e-12)
+    assert out["stats"][1] == pytest.approx(ref["loss_pi"], rel=1e-10, abs=1e-14)
+    # per-tensor check of every gradient block that is non-trivially routed
+    tab = layout.offsets(d)[0]
+    for name in ("enc.conv1.W", "critic.trunk.ln.g", "q2.l1.W", "q1.out.b"):
+        o, sh = tab[name]
+        n = math.prod(sh)
+        assert rel(out["g_enc_critic"][o:o + n], ref["g_ec"][o:o + n]) < 1e-10
+
+
+def test_critic_loss_finite_differences_tiny():
+    """Central differences of the critic loss (target frozen) on 40 coordinates."""
+    d, rep, st, hp = _setup("TINY", 16, cap=64)
+    B = 16
+    st0 = sac.copy_state(st)
+    out = sac.sac_update(st, rep, d, hp, B)
+    m = out["m"]
+    idx = out["idx"]
+    x = np.concatenate([squint(rep["obs"][idx], d.k), squint(rep["next_obs"][idx], d.k)])
+    s = rep["proprio"][idx].astype(np.float64)
+    a = rep["action"][idx].astype(np.float64)
+
+    def loss(p):
+        P = layout.view(p, d)
+        feat, _ = nets.encoder_fwd(P, x, d.n_conv)
+        logits, _ = nets.critic_fwd(P, feat[:B], s, a)
+        return nets.cross_entropy(logits, m)[0]
+
+    rng = np.random.default_rng(3)
+    hi = layout.blocks(d)["critic"][1]
+    coords = rng.choice(hi, 40, replace=False)
+    h = 1e-6
+    fd = []
+    for c in coords:
+        pp, pm = st0.params.copy(), st0.params.copy()
+        pp[c] += h
+        pm[c] -= h
+        fd.append((loss(pp) - loss(pm)) / (2 * h))
+    fd = np.array(fd)
+    g = out["g_enc_critic"][coords]
+    assert np.linalg.norm(fd - g) <= 1e-6 * np.linalg.norm(g) + 1e-9
