@@ -1,0 +1,248 @@
+/* squint.h -- C ABI of libsquint, an MI355X (gfx950) implementation of the
+ * batched visual Soft Actor-Critic update of Squint (arXiv 2602.21203) and its
+ * policy query.
+ *
+ * Conventions (apply to every call unless stated otherwise)
+ *   Pointers      every T* is a DEVICE pointer unless marked [host].
+ *   Ownership     the caller allocates and frees every buffer it passes; the
+ *                 library only borrows them for the call (an sq_agent borrows
+ *                 the buffers given to sq_agent_create for its lifetime).  The
+ *                 library allocates device memory only in sq_agent_create and
+ *                 sq_server_create and frees it in the matching *_destroy.
+ *   Streams       calls are asynchronous on `stream` (a hipStream_t; NULL is the
+ *                 null stream).  No call synchronises the device except the
+ *                 sq_server_* host waits.
+ *   Gradients     gradient outputs are overwritten, never accumulated.
+ *   Errors        0 = SQ_OK.  SQ_EINVAL: bad argument, nothing was enqueued.
+ *                 SQ_ENOMEM: allocation failed or a request exceeds a budget.
+ *                 SQ_EDEVICE: a HIP runtime error (launch or API).
+ *                 SQ_ECAPTURE: a call that cannot be captured was made while the
+ *                 stream is capturing.  sq_last_error() returns a message for the
+ *                 last failure on the calling thread.
+ *   Precision     sq_prec selects how GEMM and convolution operands are rounded:
+ *                 SQ_F32 multiplies FP32 operands; SQ_BF16 rounds weights,
+ *                 activations and upstream gradients to bfloat16 (nearest even)
+ *                 and accumulates in FP32.  LayerNorm, softmax, the categorical
+ *                 projection, the tanh-Gaussian head and Adam are FP32 in both.
+ *   Determinism   no kernel uses floating-point atomics; every reduction has a
+ *                 fixed order, so a call is bitwise reproducible.
+ *   Threads       an sq_agent must not be used by two threads at once.
+ *
+ * Layouts
+ *   frames        [rows, H, W, C] uint8, HWC, channel c = 3*s + rgb for stack
+ *                 slot s (oldest first).  H/k == W/k == 16.
+ *   images        [n, C, 16, 16] float (or bfloat16 bits), CHW.
+ *   features      [n, flat] float, flattened (channel, y, x).
+ *   parameters    one flat float vector in the canonical order reported by
+ *                 sq_param_offsets (encoder convs, critic projection, twin
+ *                 critic MLPs, actor projection, actor MLP, log alpha).  The
+ *                 target critic is a copy of the critic block.
+ */
+#ifndef SQUINT_H
+#define SQUINT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SQ_API __attribute__((visibility("default")))
+#else
+#define SQ_API
+#endif
+
+typedef struct ihipStream_t* sq_stream_t; /* identical to hipStream_t */
+
+enum { SQ_OK = 0, SQ_EINVAL = 1, SQ_ENOMEM = 2, SQ_EDEVICE = 3, SQ_ECAPTURE = 4 };
+typedef enum { SQ_F32 = 0, SQ_BF16 = 1 } sq_prec;
+
+/* Network and data dimensions (Sec. IV: 16x16 network input reached by area
+ * downsampling, a small conv encoder, LayerNorm MLPs, C51 critics).
+ *   C        channels of a frame stack (3 per RGB frame)
+ *   H, W, k  source frame size and squint factor; H/k = W/k = 16
+ *   n_conv   number of 3x3 valid convs (first has stride 2), 1..4
+ *   F        conv channels; proj: projection width; hidden: MLP width
+ *   atoms    C51 atoms on [v_min, v_max]; proprio / action: vector sizes */
+typedef struct {
+  int C, H, W, k;
+  int n_conv, F, proj, hidden, atoms, proprio, action;
+  float v_min, v_max;
+} sq_dims;
+
+/* Update hyperparameters.  target_entropy is usually -action; log_std_min/max
+ * bound the squashed log standard deviation of the policy; policy_freq delays
+ * the actor step to updates u with u % policy_freq == 0 (u = global counter);
+ * seed keys the Philox4x32-10 draws (replay indices, policy noise). */
+typedef struct {
+  float gamma, lr, beta1, beta2, adam_eps, rho, target_entropy, log_std_min, log_std_max;
+  int policy_freq;
+  sq_prec prec;
+  unsigned long long seed;
+} sq_hparams;
+
+/* Replay view, all device pointers, caller-owned; rows [0, size) are valid. */
+typedef struct {
+  const uint8_t* obs;          /* [capacity, H, W, C] */
+  const uint8_t* next_obs;     /* [capacity, H, W, C] */
+  const float* proprio;        /* [capacity, proprio] */
+  const float* next_proprio;   /* [capacity, proprio] */
+  const float* action;         /* [capacity, action] */
+  const float* reward;         /* [capacity] */
+  const uint8_t* done;         /* [capacity], 0 or 1 */
+  int capacity, size;
+} sq_replay;
+
+typedef struct sq_agent sq_agent;
+typedef struct sq_server sq_server;
+
+/* ---------------------------------------------------------------- host-side */
+SQ_API const char* sq_last_error(void);
+SQ_API int sq_version(void);
+
+/* Number of floats in the flat parameter vector.  n: [host]. */
+SQ_API int sq_param_count(const sq_dims* dims, long long* n);
+/* Number of tensors in the canonical layout.  count: [host]. */
+SQ_API int sq_param_tensor_count(const sq_dims* dims, int* count);
+/* Offsets (in floats) of every tensor, canonical order, plus the end: off has
+ * count + 1 entries [host].  Also reports the block boundaries [host, 4 each]:
+ * blocks = {enc_begin, critic_begin, actor_begin, log_alpha}. */
+SQ_API int sq_param_offsets(const sq_dims* dims, long long* off, long long* blocks);
+
+enum { SQ_OP_ENCODER = 0, SQ_OP_CRITIC = 1, SQ_OP_ACTOR = 2 };
+/* Bytes of workspace that encoder_*, critic_* or actor_* need for n rows. */
+SQ_API int sq_workspace_bytes(const sq_dims* dims, int op, int n, size_t* bytes);
+
+/* ---------------------------------------------------------------- operations */
+
+/* Resolution squinting (Sec. IV Resolution Squinting; Alg. 1 downsampling):
+ * mean of every disjoint k x k block, scaled to [-0.5, 0.5]:
+ *   S = exact integer block sum, x = fl32(fl32(S / (255 k^2)) - 0.5).
+ * frames: [rows, H, W, C] uint8; idx: [n] row indices into frames (NULL = rows
+ * 0..n-1; every index must be in [0, rows), not checked on the device);
+ * out: [n, C, 16, 16], float (out_prec SQ_F32) or bfloat16 bits (SQ_BF16,
+ * rounded to nearest even from the FP32 value). */
+SQ_API int squint_downsample(const sq_dims* dims, const uint8_t* frames, const int* idx, int n, sq_prec out_prec,
+                      void* out, sq_stream_t stream);
+
+/* Shared conv encoder f_psi (Sec. III; Sec. IV Encoder Design Choices): n_conv
+ * 3x3 valid convolutions, the first with stride 2, each followed by ReLU.
+ * enc_params: the encoder block of the flat vector; x: [n, C, 16, 16] float;
+ * feat: [n, flat] float.  ws: sq_workspace_bytes(SQ_OP_ENCODER, n) bytes; it
+ * keeps the activations for encoder_bwd and must not change in between. */
+SQ_API int encoder_fwd(const sq_dims* dims, sq_prec prec, const float* enc_params, const float* x, int n,
+                float* feat, void* ws, sq_stream_t stream);
+/* Gradient of the encoder parameters for upstream dfeat [n, flat] (same n as the
+ * forward).  denc_params: encoder block of a flat gradient vector.  The image
+ * receives no gradient. */
+SQ_API int encoder_bwd(const sq_dims* dims, sq_prec prec, const float* enc_params, const void* ws, const float* dfeat,
+                int n, float* denc_params, sq_stream_t stream);
+
+/* Twin C51 critics (Sec. IV Critic Design Choices, Normalization; Alg. 1):
+ * h = tanh(LN(W_c feat + b)); per twin i: ReLU(LN(L2(ReLU(LN(L1 [h; s; a])))))
+ * -> atoms logits.  critic_params: the critic block (projection + both twins),
+ * either online or target parameters.  feat [n, flat], proprio [n, P],
+ * action [n, A]; logits [2, n, atoms].  ws: SQ_OP_CRITIC bytes. */
+SQ_API int critic_fwd(const sq_dims* dims, sq_prec prec, const float* critic_params, const float* feat,
+               const float* proprio, const float* action, int n, float* logits, void* ws, sq_stream_t stream);
+/* Backward of critic_fwd for upstream dlogits [2, n, atoms].  Outputs (each
+ * nullable): dparams (critic block layout), dfeat [n, flat], daction [n, A]. */
+SQ_API int critic_bwd(const sq_dims* dims, sq_prec prec, const float* critic_params, const void* ws,
+               const float* dlogits, int n, float* dparams, float* dfeat, float* daction, sq_stream_t stream);
+
+/* Categorical (C51) projection of the soft Bellman target (Eq. (1) in
+ * distributional form; Sec. IV Critic Design Choices):
+ *   z_j = v_min + j dz, Tz_j = r + gamma (1 - d)(z_j + bonus),
+ *   b_j = clamp((Tz_j - v_min) / dz, 0, N - 1),
+ *   m_i = sum_j p_j max(0, 1 - |b_j - i|).
+ * p_next [n, atoms], reward [n], done [n] uint8, bonus [n] (nullable = 0; the
+ * update passes -alpha log pi(a'|s')), m [n, atoms].  FP32. */
+SQ_API int c51_project(const sq_dims* dims, const float* p_next, const float* reward, const uint8_t* done,
+                const float* bonus, float gamma, int n, float* m, sq_stream_t stream);
+
+/* Tanh-Gaussian actor (Sec. III Eq. (3)): h = tanh(LN(W_a feat + b)); MLP on
+ * [h; s] -> [mu, u_s]; log sigma = lo + (hi - lo)(tanh(u_s) + 1)/2;
+ * u = mu + sigma eps; action = tanh(u);
+ * log pi = sum_d (-eps_d^2/2 - log sigma_d - log(2 pi)/2 - log(1 - tanh(u_d)^2)).
+ * actor_params: the actor block.  eps [n, A] standard normal (NULL: the mean
+ * action tanh(mu), logp not written).  action [n, A]; logp [n] (nullable).
+ * ws: SQ_OP_ACTOR bytes, kept for actor_bwd. */
+SQ_API int actor_fwd(const sq_dims* dims, sq_prec prec, const sq_hparams* hp, const float* actor_params,
+              const float* feat, const float* proprio, const float* eps, int n, float* action, float* logp,
+              void* ws, sq_stream_t stream);
+/* Backward of a sampled actor_fwd for upstream daction [n, A] and dlogp [n]
+ * (nullable = 0).  dparams: actor block layout.  No gradient to feat. */
+SQ_API int actor_bwd(const sq_dims* dims, sq_prec prec, const sq_hparams* hp, const float* actor_params,
+              const void* ws, const float* daction, const float* dlogp, int n, float* dparams,
+              sq_stream_t stream);
+
+/* Adam with bias correction (the paper's gradient steps, read as Adam):
+ *   t = *step + 1 (the counter itself is NOT modified),
+ *   m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ *   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ * Optionally updates an EMA target (Alg. 1 target update) for i >= ema_begin:
+ *   ema_target[i - ema_begin] = rho ema_target[i - ema_begin] + (1 - rho) p_new[i],
+ * and writes bfloat16 bits of p_new to p_bf16.  n elements; step: [1] int. */
+SQ_API int adam_step(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp,
+              const int* step, uint16_t* p_bf16, float* ema_target, long long ema_begin, sq_stream_t stream);
+
+/* ---------------------------------------------------------------- agent */
+
+/* An agent bundles the caller's state buffers and the library's workspace for
+ * batch `batch`:
+ *   params [n], target [critic block size], adam_m, adam_v [n]: float;
+ *   grads [n] float (nullable: internal), written by every update;
+ *   counters [4] int: {u, critic+encoder Adam steps, actor steps, alpha steps}.
+ * The caller initialises params, sets target = critic block of params, zeroes
+ * the moments and counters. */
+SQ_API int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float* params, float* target,
+                    float* adam_m, float* adam_v, float* grads, int* counters, sq_agent** out /*[host]*/);
+SQ_API int sq_agent_destroy(sq_agent* agent);
+
+/* n_updates SAC updates (Alg. 1 inner loop, with the readings stated in the
+ * design notes): per update, draw batch replay indices and noise from Philox
+ * keyed by (seed, u), squint obs and next_obs, encode both, build the C51 soft
+ * target from the averaged twin target critics, step critic + encoder on the
+ * summed cross entropy, step log alpha, step the actor when u % policy_freq
+ * == 0, update the target EMA, write stats[u_local, 0..7] = {critic loss,
+ * actor loss, alpha loss, alpha, entropy, mean Q, mean target, non-finite}.
+ * The first call for a given (n_updates, replay, stats, stream) captures a HIP
+ * graph; later identical calls replay it.  stats: [n_updates, 8] float. */
+SQ_API int sac_update(sq_agent* agent, const sq_replay* replay, int n_updates, float* stats, sq_stream_t stream);
+/* The same sequence launched kernel by kernel, without a graph. */
+SQ_API int sac_update_eager(sq_agent* agent, const sq_replay* replay, int n_updates, float* stats, sq_stream_t stream);
+
+/* Policy query (Alg. 1 action sampling): squint frames [n, H, W, C] uint8,
+ * encode, actor mean (sample = 0) or tanh-Gaussian sample (sample = 1, noise
+ * keyed by (seed, request_id, row)) -> action_out [n, A].  BF16 operands when
+ * hp.prec is SQ_BF16.  n <= the agent's act capacity (see sq_agent_act_capacity). */
+SQ_API int act(sq_agent* agent, const uint8_t* frames, const float* proprio, int n, int sample,
+        unsigned long long request_id, float* action_out, sq_stream_t stream);
+SQ_API int sq_agent_act_capacity(sq_agent* agent, int* n /*[host]*/);
+
+/* ---------------------------------------------------------------- serving */
+typedef void (*sq_done_cb)(unsigned long long request_id, double t_done_s, void* user);
+/* Continuous-batching act() server: a host scheduler thread fuses queued
+ * requests (FIFO, no skipping) into one launch on a free stream slot when the
+ * batch's workspace fits mem_budget; batches on different slots overlap. */
+SQ_API int sq_server_create(sq_agent* agent, size_t mem_budget, int max_batch_obs, int n_slots, sq_server** out);
+SQ_API int sq_server_submit(sq_server* srv, const uint8_t* frames, const float* proprio, int n, int sample,
+                     unsigned long long request_id, float* action_out, sq_done_cb cb, void* user);
+SQ_API int sq_server_drain(sq_server* srv);
+SQ_API int sq_server_destroy(sq_server* srv);
+
+/* ---------------------------------------------------------------- test hooks */
+/* idx[b] = mulhi32(Philox4x32_10(ctr = (update, 0, b, 0), key = seed).w0, size). */
+SQ_API int sq_sample_indices(unsigned long long seed, unsigned int update, int size, int n, int* idx,
+                      sq_stream_t stream);
+/* Box-Muller on Philox words (w0, w1) of ctr = (update, stream_id, e, 0):
+ * eps[e] = sqrt(-2 ln u1) cos(2 pi u2), u = ((w >> 9) + 0.5) 2^-23 (exact in FP32). */
+SQ_API int sq_gaussian(unsigned long long seed, unsigned int update, unsigned int stream_id, int n, float* eps,
+                sq_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SQUINT_H */

@@ -12,7 +12,8 @@ sampling law is unstated and read as uniform with replacement; Eq. (1) and
 Eq. (3) need reparameterised actions drawn from the stochastic policy):
   replay index   idx[b] = mulhi32(w0, size), counter (u, 0, b, 0), key = seed
   Gaussian noise stream s in {1, 2}, element e: counter (u, s, e, 0);
-                 Box-Muller on words w0, w1 with uniforms ((w >> 8) + 0.5) / 2^24
+                 Box-Muller on words w0, w1 with uniforms ((w >> 9) + 0.5) / 2^23
+                 (23 random bits plus a half: exact in FP32, strictly inside (0, 1))
   act() sample   element e = row*A + d of a request: counter (e, 3, id_lo, id_hi),
                  so a row's noise depends only on (request id, row), not on batching
 Pinned by: rocRAND's host-side Philox4x32-10 engine, a second scalar
@@ -71,14 +72,14 @@ def sample_indices(seed, update, size, n):
     return ((w[0].astype(np.uint64) * np.uint64(size)) >> np.uint64(32)).astype(np.int64)
 
 
-def _uniform24(w):
-    """(w >> 8) + 0.5 scaled by 2^-24: strictly inside (0, 1), exact in FP32."""
-    return ((w.astype(np.uint64) >> np.uint64(8)).astype(np.float64) + 0.5) * 2.0 ** -24
+def _uniform23(w):
+    """(w >> 9) + 0.5 scaled by 2^-23: strictly inside (0, 1), exact in FP32."""
+    return ((w.astype(np.uint64) >> np.uint64(9)).astype(np.float64) + 0.5) * 2.0 ** -23
 
 
 def box_muller(w0, w1):
-    u1 = _uniform24(w0)
-    u2 = _uniform24(w1)
+    u1 = _uniform23(w0)
+    u2 = _uniform23(w1)
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
 
 

@@ -1,0 +1,239 @@
+"""Python face of libsquint: the C entry points under the same names, taking
+torch tensors.  Marshalling only -- shapes are checked on the host, outputs are
+allocated with torch, and every step runs in the library's kernels on the
+current HIP stream.
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+from ._lib import SQ_BF16, SQ_F32, check, ptr, stream_handle
+
+
+def _dims(cfg):
+    return ctypes.byref(L.make_dims(cfg))
+
+
+def _req(t, dtype, shape=None, name="tensor"):
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t
+
+
+def _side(cfg):
+    return cfg["H"] // cfg["k"]
+
+
+def squint_downsample(cfg, frames, idx=None, n=None, prec=SQ_F32, out=None, stream=None):
+    """[rows, H, W, C] uint8 (+ optional idx [n] int32) -> [n, C, 16, 16] f32 or bf16."""
+    _req(frames, torch.uint8, name="frames")
+    if frames.dim() != 4 or tuple(frames.shape[1:]) != (cfg["H"], cfg["W"], cfg["C"]):
+        raise ValueError(f"frames shape {tuple(frames.shape)} does not match the dims")
+    if idx is not None:
+        _req(idx, torch.int32, name="idx")
+        n = idx.numel() if n is None else n
+    n = frames.shape[0] if n is None else n
+    s = _side(cfg)
+    dt = torch.float32 if prec == SQ_F32 else torch.bfloat16
+    if out is None:
+        out = torch.empty((n, cfg["C"], s, s), dtype=dt, device=frames.device)
+    _req(out, dt, (n, cfg["C"], s, s), "out")
+    check(L.LIB.squint_downsample(_dims(cfg), ptr(frames), ptr(idx), n, prec, ptr(out), stream_handle(stream)))
+    return out
+
+
+def encoder_fwd(cfg, prec, enc_params, x, ws=None, stream=None):
+    n = x.shape[0]
+    s = _side(cfg)
+    _req(x, torch.float32, (n, cfg["C"], s, s), "x")
+    _req(enc_params, torch.float32, name="enc_params")
+    if ws is None:
+        ws = torch.empty(L.workspace_bytes(cfg, L.SQ_OP_ENCODER, n), dtype=torch.uint8, device=x.device)
+    feat = torch.empty((n, L.feat_width(cfg)), dtype=torch.float32, device=x.device)
+    check(L.LIB.encoder_fwd(_dims(cfg), prec, ptr(enc_params), ptr(x), n, ptr(feat), ptr(ws), stream_handle(stream)))
+    return feat, ws
+
+
+def encoder_bwd(cfg, prec, enc_params, ws, dfeat, n_enc_params, stream=None):
+    n = dfeat.shape[0]
+    _req(dfeat, torch.float32, (n, L.feat_width(cfg)), "dfeat")
+    d = torch.empty(n_enc_params, dtype=torch.float32, device=dfeat.device)
+    check(L.LIB.encoder_bwd(_dims(cfg), prec, ptr(enc_params), ptr(ws), ptr(dfeat), n, ptr(d), stream_handle(stream)))
+    return d
+
+
+def critic_fwd(cfg, prec, critic_params, feat, proprio, action, ws=None, stream=None):
+    n = feat.shape[0]
+    _req(feat, torch.float32, (n, L.feat_width(cfg)), "feat")
+    _req(proprio, torch.float32, (n, cfg["proprio"]), "proprio")
+    _req(action, torch.float32, (n, cfg["action"]), "action")
+    _req(critic_params, torch.float32, name="critic_params")
+    if ws is None:
+        ws = torch.empty(L.workspace_bytes(cfg, L.SQ_OP_CRITIC, n), dtype=torch.uint8, device=feat.device)
+    logits = torch.empty((2, n, cfg["atoms"]), dtype=torch.float32, device=feat.device)
+    check(L.LIB.critic_fwd(_dims(cfg), prec, ptr(critic_params), ptr(feat), ptr(proprio), ptr(action), n, ptr(logits),
+                           ptr(ws), stream_handle(stream)))
+    return logits, ws
+
+
+def critic_bwd(cfg, prec, critic_params, ws, dlogits, want_params=True, want_feat=True, want_action=True,
+               stream=None):
+    n = dlogits.shape[1]
+    _req(dlogits, torch.float32, (2, n, cfg["atoms"]), "dlogits")
+    dev = dlogits.device
+    dp = torch.empty_like(critic_params) if want_params else None
+    df = torch.empty((n, L.feat_width(cfg)), dtype=torch.float32, device=dev) if want_feat else None
+    da = torch.empty((n, cfg["action"]), dtype=torch.float32, device=dev) if want_action else None
+    check(L.LIB.critic_bwd(_dims(cfg), prec, ptr(critic_params), ptr(ws), ptr(dlogits), n, ptr(dp), ptr(df), ptr(da),
+                           stream_handle(stream)))
+    return dp, df, da
+
+
+def c51_project(cfg, p_next, reward, done, bonus, gamma, stream=None):
+    n = p_next.shape[0]
+    _req(p_next, torch.float32, (n, cfg["atoms"]), "p_next")
+    _req(reward, torch.float32, (n,), "reward")
+    _req(done, torch.uint8, (n,), "done")
+    if bonus is not None:
+        _req(bonus, torch.float32, (n,), "bonus")
+    m = torch.empty_like(p_next)
+    check(L.LIB.c51_project(_dims(cfg), ptr(p_next), ptr(reward), ptr(done), ptr(bonus), float(gamma), n, ptr(m),
+                            stream_handle(stream)))
+    return m
+
+
+def actor_fwd(cfg, prec, hp, actor_params, feat, proprio, eps=None, ws=None, stream=None):
+    n = feat.shape[0]
+    _req(feat, torch.float32, (n, L.feat_width(cfg)), "feat")
+    _req(proprio, torch.float32, (n, cfg["proprio"]), "proprio")
+    if eps is not None:
+        _req(eps, torch.float32, (n, cfg["action"]), "eps")
+    if ws is None:
+        ws = torch.empty(L.workspace_bytes(cfg, L.SQ_OP_ACTOR, n), dtype=torch.uint8, device=feat.device)
+    action = torch.empty((n, cfg["action"]), dtype=torch.float32, device=feat.device)
+    logp = torch.empty((n,), dtype=torch.float32, device=feat.device) if eps is not None else None
+    check(L.LIB.actor_fwd(_dims(cfg), prec, ctypes.byref(hp), ptr(actor_params), ptr(feat), ptr(proprio), ptr(eps), n,
+                          ptr(action), ptr(logp), ptr(ws), stream_handle(stream)))
+    return action, logp, ws
+
+
+def actor_bwd(cfg, prec, hp, actor_params, ws, daction, dlogp, stream=None):
+    n = daction.shape[0]
+    _req(daction, torch.float32, (n, cfg["action"]), "daction")
+    if dlogp is not None:
+        _req(dlogp, torch.float32, (n,), "dlogp")
+    dp = torch.empty_like(actor_params)
+    check(L.LIB.actor_bwd(_dims(cfg), prec, ctypes.byref(hp), ptr(actor_params), ptr(ws), ptr(daction), ptr(dlogp), n,
+                          ptr(dp), stream_handle(stream)))
+    return dp
+
+
+def adam_step(p, g, m, v, hp, step, p_bf16=None, ema_target=None, ema_begin=0, stream=None):
+    n = p.numel()
+    for t, nm in ((p, "p"), (g, "g"), (m, "m"), (v, "v")):
+        _req(t, torch.float32, (n,), nm)
+    _req(step, torch.int32, name="step")
+    check(L.LIB.adam_step(ptr(p), ptr(g), ptr(m), ptr(v), n, ctypes.byref(hp), ptr(step), ptr(p_bf16), ptr(ema_target),
+                          int(ema_begin), stream_handle(stream)))
+
+
+def sample_indices(seed, update, size, n, device="cuda", stream=None):
+    idx = torch.empty(n, dtype=torch.int32, device=device)
+    check(L.LIB.sq_sample_indices(seed, update, size, n, ptr(idx), stream_handle(stream)))
+    return idx
+
+
+def gaussian(seed, update, stream_id, n, device="cuda", stream=None):
+    e = torch.empty(n, dtype=torch.float32, device=device)
+    check(L.LIB.sq_gaussian(seed, update, stream_id, n, ptr(e), stream_handle(stream)))
+    return e
+
+
+def replay_struct(rep):
+    """sq_replay view of a dict of device tensors (synthetic.replay layout)."""
+    cap = rep["obs"].shape[0]
+    for k, dt in (("obs", torch.uint8), ("next_obs", torch.uint8), ("proprio", torch.float32),
+                  ("next_proprio", torch.float32), ("action", torch.float32), ("reward", torch.float32),
+                  ("done", torch.uint8)):
+        _req(rep[k], dt, name=k)
+        if rep[k].shape[0] != cap:
+            raise ValueError(f"replay field {k} has {rep[k].shape[0]} rows, expected {cap}")
+    return L.Replay(*(ptr(rep[k]) for k in ("obs", "next_obs", "proprio", "next_proprio", "action", "reward",
+                                            "done")), cap, int(rep.get("size", cap)))
+
+
+class Agent:
+    """Owns the state tensors of one agent and the library handle.
+
+    params: flat FP32 vector in the library's layout; the target starts as a
+    copy of the critic block, moments and counters at zero."""
+
+    def __init__(self, cfg, params, batch, prec=SQ_F32, device="cuda", **hp_kw):
+        self.cfg = cfg
+        self.table, self.blocks = L.param_table(cfg)
+        self.batch = batch
+        self.hp = L.make_hparams(cfg["action"], prec=prec, **hp_kw)
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(device).contiguous()
+        if self.params.numel() != self.blocks["total"]:
+            raise ValueError("params has the wrong length")
+        c0, c1 = self.blocks["critic"]
+        self.target = self.params[c0:c1].clone()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grads = torch.zeros_like(self.params)
+        self.counters = torch.zeros(4, dtype=torch.int32, device=device)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        check(L.LIB.sq_agent_create(_dims(cfg), ctypes.byref(self.hp), batch, ptr(self.params), ptr(self.target),
+                                    ptr(self.m), ptr(self.v), ptr(self.grads), ptr(self.counters), ctypes.byref(h)))
+        self.handle = h
+        self._replays = {}
+        # graphs cannot be captured on the null stream: updates run on a side
+        # stream ordered against the caller's current stream
+        self.stream = torch.cuda.Stream(device=self.params.device)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize()
+            L.LIB.sq_agent_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sac_update(self, replay, n_updates, stats=None, graph=True, stream=None):
+        key = id(replay)
+        if key not in self._replays:
+            self._replays[key] = (replay, replay_struct(replay))
+        rs = self._replays[key][1]
+        if stats is None:
+            stats = torch.empty((n_updates, L.N_STATS), dtype=torch.float32, device=self.params.device)
+        _req(stats, torch.float32, (n_updates, L.N_STATS), "stats")
+        fn = L.LIB.sac_update if graph else L.LIB.sac_update_eager
+        caller = stream if stream is not None else torch.cuda.current_stream()
+        self.stream.wait_stream(caller)
+        check(fn(self.handle, ctypes.byref(rs), n_updates, ptr(stats), stream_handle(self.stream)))
+        caller.wait_stream(self.stream)
+        return stats
+
+    def act(self, frames, proprio, sample=False, request_id=0, out=None, stream=None):
+        n = frames.shape[0]
+        _req(frames, torch.uint8, (n, self.cfg["H"], self.cfg["W"], self.cfg["C"]), "frames")
+        _req(proprio, torch.float32, (n, self.cfg["proprio"]), "proprio")
+        if out is None:
+            out = torch.empty((n, self.cfg["action"]), dtype=torch.float32, device=frames.device)
+        check(L.LIB.act(self.handle, ptr(frames), ptr(proprio), n, int(bool(sample)), int(request_id), ptr(out),
+                        stream_handle(stream)))
+        return out

@@ -1,0 +1,353 @@
+// The SAC agent: workspace of the fused update, the per-update kernel sequence,
+// HIP-graph capture of a block of updates, and the act() policy query.
+//
+// Per update (Alg. 1 inner loop):
+//   sample batch (Philox indices, gather small replay fields, policy noise)
+//   squint obs + next_obs -> encoder on 2B images (one pass, current encoder)
+//   actor on all 2B rows (next half: target action and log pi; first half:
+//     the sample used by the temperature and actor losses)
+//   target twin critics on the next half -> averaged softmax -> C51 projection
+//   online twin critics on the first half -> cross entropy -> backward into the
+//     critic and the encoder -> Adam on (encoder, critic) fused with target EMA
+//   temperature step on log alpha
+//   [actor step] updated critic scores the sampled action -> expected-Q gradient
+//     -> backward to the action only -> policy backward -> Adam on the actor
+//   statistics row, counters
+// Everything that changes between updates (update index, Adam step counts)
+// lives in device counters, so a captured graph is replayed unchanged.
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "ops.h"
+
+namespace sq {
+
+void plan_act(const Net& net, int n, Bump& b, ActBufs* w) {
+  w->x = b.take<float>((size_t)n * net.img);
+  plan_encoder(net, n, b, &w->e, false);
+  plan_actor(net, n, b, &w->a, false);
+  w->noise = b.take<float>((size_t)n * net.d.action);
+}
+
+int enqueue_act(const Net& net, const Layout& L, const sq_hparams& hp, const float* params, const ActBufs& w,
+                const uint8_t* frames, const float* proprio, int n, int sample, unsigned long long request_id,
+                float* action_out, hipStream_t st) {
+  const sq_dims& d = net.d;
+  const int bf = hp.prec == SQ_BF16;
+  SQ_TRY(launch_squint(frames, nullptr, n, d.H, d.W, d.C, d.k, 0, w.x, net.img, st));
+  SQ_TRY(encoder_forward(net, bf, params, L, w.x, n, w.e, st));
+  if (sample) SQ_TRY(launch_act_noise(hp.seed, request_id, n, d.action, w.noise, st));
+  return actor_forward(net, bf, params + L.actor_begin, L, w.e.h[d.n_conv - 1], net.flat, proprio, d.proprio,
+                       sample ? w.noise : nullptr, n, hp.log_std_min, hp.log_std_max, action_out, nullptr, w.a, st);
+}
+
+size_t act_bytes_per_obs(const Net& net) {
+  Bump b{nullptr};
+  ActBufs w;
+  plan_act(net, 1024, b, &w);
+  return (b.off + 1023) / 1024;
+}
+
+}  // namespace sq
+
+using namespace sq;
+
+struct GraphEntry {
+  int n_updates, phase;
+  sq_replay rep;
+  float* stats;
+  hipStream_t stream;
+  hipGraphExec_t exec;
+};
+
+struct sq_agent {
+  Net net;
+  Layout L;
+  sq_hparams hp;
+  int B;
+  float *params, *target, *m, *v, *grads;
+  int* ctr;
+  void* ws = nullptr;
+  bool own_grads = false;
+  long long u_host = 0;
+  // update buffers
+  int* idx;
+  float *eps2B, *S2, *Arep, *r, *dn, *x, *dfeat, *act2B, *logp2B, *logits_t, *logits, *logits_q, *mt, *dlogits,
+      *dlogits_q, *loss_row, *q_row, *tgt_row, *qa_row, *scal, *da;
+  EncBufs enc;
+  ActorBufs actor;
+  CriticBufs crit, aux;
+  // act()
+  int act_cap;
+  ActBufs actw;
+  std::vector<GraphEntry> graphs;
+};
+
+static size_t plan_agent(sq_agent* g, char* base) {
+  const Net& net = g->net;
+  const sq_dims& d = net.d;
+  const int B = g->B, A = d.action, S = d.proprio, N = d.atoms;
+  Bump b{base};
+  g->idx = b.take<int>(B);
+  g->eps2B = b.take<float>((size_t)2 * B * A);
+  g->S2 = b.take<float>((size_t)2 * B * (S > 0 ? S : 1));
+  g->Arep = b.take<float>((size_t)B * A);
+  g->r = b.take<float>(B);
+  g->dn = b.take<float>(B);
+  g->x = b.take<float>((size_t)2 * B * net.img);
+  plan_encoder(net, 2 * B, b, &g->enc, true);
+  g->dfeat = b.take<float>((size_t)B * net.flat);
+  g->act2B = b.take<float>((size_t)2 * B * A);
+  g->logp2B = b.take<float>((size_t)2 * B);
+  plan_actor(net, 2 * B, b, &g->actor, true);
+  plan_critic(net, B, b, &g->crit, true);
+  plan_critic(net, B, b, &g->aux, true);
+  g->logits_t = b.take<float>((size_t)2 * B * N);
+  g->logits = b.take<float>((size_t)2 * B * N);
+  g->logits_q = b.take<float>((size_t)2 * B * N);
+  g->mt = b.take<float>((size_t)B * N);
+  g->dlogits = b.take<float>((size_t)2 * B * N);
+  g->dlogits_q = b.take<float>((size_t)2 * B * N);
+  g->loss_row = b.take<float>((size_t)2 * B);
+  g->q_row = b.take<float>((size_t)2 * B);
+  g->tgt_row = b.take<float>(B);
+  g->qa_row = b.take<float>(B);
+  g->scal = b.take<float>(8);
+  g->da = b.take<float>((size_t)B * A);
+  if (!g->own_grads) {
+  } else {
+    g->grads = b.take<float>(g->L.total);
+  }
+  plan_act(net, g->act_cap, b, &g->actw);
+  return b.off + 256;
+}
+
+static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int actor_step, hipStream_t st) {
+  const Net& net = g->net;
+  const sq_dims& d = net.d;
+  const Layout& L = g->L;
+  const sq_hparams& hp = g->hp;
+  const int B = g->B, A = d.action, S = d.proprio, N = d.atoms, flat = net.flat;
+  const int bf = hp.prec == SQ_BF16;
+  const float lo = hp.log_std_min, hi = hp.log_std_max;
+  float* P = g->params;
+  float* G = g->grads;
+  SQ_TRY(launch_sample_batch(hp.seed, g->ctr, R->size, B, A, S, R->proprio, R->next_proprio, R->action, R->reward,
+                             R->done, g->idx, g->eps2B, g->S2, g->Arep, g->r, g->dn, st));
+  SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, d.H, d.W, d.C, d.k, g->x, st));
+  SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st));
+  const float* feat = g->enc.h[d.n_conv - 1];
+  SQ_TRY(actor_forward(net, bf, P + L.actor_begin, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
+                       g->logp2B, g->actor, st));
+  // distributional soft target from the averaged twin target critics
+  SQ_TRY(critic_forward(net, bf, g->target, L, feat + (size_t)B * flat, flat, g->S2 + (size_t)B * S, S,
+                        g->act2B + (size_t)B * A, A, B, g->logits_t, g->aux, st));
+  SQ_TRY(project_target(g->logits_t, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma,
+                        g->mt, g->tgt_row, st));
+  // critic + encoder step
+  SQ_TRY(critic_forward(net, bf, P + L.critic_begin, L, feat, flat, g->S2, S, g->Arep, A, B, g->logits, g->crit, st));
+  SQ_TRY(ce_loss(g->logits, g->mt, B, N, d.v_min, d.v_max, g->dlogits, g->loss_row, g->q_row, st));
+  SQ_TRY(critic_backward(net, bf, P + L.critic_begin, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
+                         g->dfeat, nullptr, st));
+  SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st));
+  SQ_TRY(adam(P, G, g->m, g->v, L.critic_end, &hp, g->ctr + CTR_TC, g->target, L.critic_begin, nullptr, st));
+  // temperature
+  SQ_TRY(alpha_step(g->logp2B, B, hp.target_entropy, P + L.log_alpha, G + L.log_alpha, g->m + L.log_alpha,
+                    g->v + L.log_alpha, g->ctr, &hp, g->scal, st));
+  // delayed actor step against the updated critic
+  if (actor_step) {
+    SQ_TRY(critic_forward(net, bf, P + L.critic_begin, L, feat, flat, g->S2, S, g->act2B, A, B, g->logits_q, g->aux,
+                          st));
+    SQ_TRY(expected_q_grad(g->logits_q, B, N, d.v_min, d.v_max, g->dlogits_q, g->qa_row, st));
+    SQ_TRY(critic_backward(net, bf, P + L.critic_begin, L, feat, flat, g->dlogits_q, B, g->aux, nullptr, nullptr,
+                           g->da, st));
+    SQ_TRY(actor_backward(net, bf, P + L.actor_begin, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
+                          1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st));
+    SQ_TRY(adam(P + L.actor_begin, G + L.actor_begin, g->m + L.actor_begin, g->v + L.actor_begin,
+                L.actor_end - L.actor_begin, &hp, g->ctr + CTR_TA, nullptr, 0, nullptr, st));
+  }
+  return finish_update(g->loss_row, g->q_row, g->tgt_row, g->logp2B, g->qa_row, g->scal, B, actor_step, g->ctr, stats,
+                       st);
+}
+
+static int check_replay(const sq_agent* g, const sq_replay* R) {
+  if (!R) { set_error("replay is NULL"); return SQ_EINVAL; }
+  if (!R->obs || !R->next_obs || !R->action || !R->reward || !R->done ||
+      (g->net.d.proprio > 0 && (!R->proprio || !R->next_proprio))) {
+    set_error("replay has a NULL field");
+    return SQ_EINVAL;
+  }
+  if (R->size <= 0 || R->size > R->capacity) {
+    set_error("replay size %d outside (0, capacity=%d]", R->size, R->capacity);
+    return SQ_EINVAL;
+  }
+  return SQ_OK;
+}
+
+static int enqueue_block(sq_agent* g, const sq_replay* R, int n, float* stats, hipStream_t st) {
+  const int pf = g->hp.policy_freq;
+  for (int j = 0; j < n; ++j) {
+    const int actor_step = ((g->u_host + j) % pf) == 0;
+    SQ_TRY(enqueue_update(g, R, stats + 8 * (size_t)j, actor_step, st));
+  }
+  return SQ_OK;
+}
+
+extern "C" {
+
+int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float* params, float* target,
+                    float* adam_m, float* adam_v, float* grads, int* counters, sq_agent** out) {
+  Net net;
+  SQ_TRY(make_net(dims, &net));
+  if (!hp || !out || !params || !target || !adam_m || !adam_v || !counters) {
+    set_error("NULL argument to sq_agent_create");
+    return SQ_EINVAL;
+  }
+  if (batch <= 0 || hp->policy_freq <= 0 || (hp->prec != SQ_F32 && hp->prec != SQ_BF16)) {
+    set_error("bad batch %d / policy_freq %d / prec", batch, hp->policy_freq);
+    return SQ_EINVAL;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+    set_error("sq_agent_create allocates and cannot run while the null stream captures");
+    return SQ_ECAPTURE;
+  }
+  sq_agent* g = new sq_agent();
+  g->net = net;
+  make_layout(net, &g->L);
+  g->hp = *hp;
+  g->B = batch;
+  g->params = params;
+  g->target = target;
+  g->m = adam_m;
+  g->v = adam_v;
+  g->grads = grads;
+  g->own_grads = grads == nullptr;
+  g->ctr = counters;
+  g->act_cap = 4096;
+  const size_t bytes = plan_agent(g, nullptr);
+  if (hipMalloc(&g->ws, bytes) != hipSuccess) {
+    delete g;
+    set_error("hipMalloc of %zu workspace bytes failed", bytes);
+    return SQ_ENOMEM;
+  }
+  char* base = (char*)(((uintptr_t)g->ws + 255) & ~(uintptr_t)255);
+  plan_agent(g, base);
+  int host_ctr[CTR_N];
+  if (hipMemcpy(host_ctr, counters, sizeof(host_ctr), hipMemcpyDeviceToHost) != hipSuccess) {
+    (void)hipFree(g->ws);
+    delete g;
+    set_error("reading the counters failed");
+    return SQ_EDEVICE;
+  }
+  g->u_host = host_ctr[CTR_U];
+  *out = g;
+  return SQ_OK;
+}
+
+int sq_agent_destroy(sq_agent* g) {
+  if (!g) return SQ_OK;
+  for (auto& e : g->graphs) (void)hipGraphExecDestroy(e.exec);
+  if (g->ws) (void)hipFree(g->ws);
+  delete g;
+  return SQ_OK;
+}
+
+int sac_update_eager(sq_agent* g, const sq_replay* R, int n_updates, float* stats, sq_stream_t stream) {
+  if (!g || !stats || n_updates < 0) {
+    set_error("bad agent / stats / n_updates");
+    return SQ_EINVAL;
+  }
+  SQ_TRY(check_replay(g, R));
+  SQ_TRY(enqueue_block(g, R, n_updates, stats, (hipStream_t)stream));
+  g->u_host += n_updates;
+  return SQ_OK;
+}
+
+int sac_update(sq_agent* g, const sq_replay* R, int n_updates, float* stats, sq_stream_t stream) {
+  if (!g || !stats || n_updates < 0) {
+    set_error("bad agent / stats / n_updates");
+    return SQ_EINVAL;
+  }
+  SQ_TRY(check_replay(g, R));
+  if (n_updates == 0) return SQ_OK;
+  hipStream_t st = (hipStream_t)stream;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  SQ_TRY_HIP(hipStreamIsCapturing(st, &cs));
+  if (st == nullptr || cs != hipStreamCaptureStatusNone) {
+    // the null stream cannot be captured; inside a caller's capture the
+    // kernels simply become part of the caller's graph
+    return sac_update_eager(g, R, n_updates, stats, stream);
+  }
+  const int phase = (int)(g->u_host % g->hp.policy_freq);
+  GraphEntry* hit = nullptr;
+  for (auto& e : g->graphs)
+    if (e.n_updates == n_updates && e.phase == phase && e.stats == stats && e.stream == st &&
+        memcmp(&e.rep, R, sizeof(sq_replay)) == 0)
+      hit = &e;
+  if (!hit) {
+    GraphEntry e;
+    e.n_updates = n_updates;
+    e.phase = phase;
+    e.rep = *R;
+    e.stats = stats;
+    e.stream = st;
+    SQ_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int s = enqueue_block(g, R, n_updates, stats, st);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    if (s != SQ_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (ce != hipSuccess) {
+      set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
+      return SQ_EDEVICE;
+    }
+    const hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+      return SQ_EDEVICE;
+    }
+    g->graphs.push_back(e);
+    hit = &g->graphs.back();
+  }
+  SQ_TRY_HIP(hipGraphLaunch(hit->exec, st));
+  g->u_host += n_updates;
+  return SQ_OK;
+}
+
+int act(sq_agent* g, const uint8_t* frames, const float* proprio, int n, int sample, unsigned long long request_id,
+        float* action_out, sq_stream_t stream) {
+  if (!g) { set_error("agent is NULL"); return SQ_EINVAL; }
+  if (n < 0 || n > g->act_cap) {
+    set_error("n = %d outside [0, %d]", n, g->act_cap);
+    return SQ_EINVAL;
+  }
+  if (n == 0) return SQ_OK;
+  if (!frames || !action_out || (g->net.d.proprio > 0 && !proprio)) {
+    set_error("NULL argument to act");
+    return SQ_EINVAL;
+  }
+  return enqueue_act(g->net, g->L, g->hp, g->params, g->actw, frames, proprio, n, sample ? 1 : 0, request_id,
+                     action_out, (hipStream_t)stream);
+}
+
+int sq_agent_act_capacity(sq_agent* g, int* n) {
+  if (!g || !n) { set_error("NULL argument"); return SQ_EINVAL; }
+  *n = g->act_cap;
+  return SQ_OK;
+}
+
+}  // extern "C"
+
+// used by the serving loop
+namespace sq {
+const Net& agent_net(const sq_agent* g) { return g->net; }
+const Layout& agent_layout(const sq_agent* g) { return g->L; }
+const sq_hparams& agent_hp(const sq_agent* g) { return g->hp; }
+const float* agent_params(const sq_agent* g) { return g->params; }
+}  // namespace sq

@@ -1,0 +1,187 @@
+// Internal declarations shared by the HIP kernels and the host orchestration.
+// Not part of the public C ABI (that is include/squint.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "squint.h"
+
+namespace sq {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+#define SQ_TRY_HIP(expr)                                                        \
+  do {                                                                          \
+    hipError_t _e = (expr);                                                     \
+    if (_e != hipSuccess) {                                                     \
+      ::sq::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(_e),    \
+                      __FILE__, __LINE__);                                      \
+      return SQ_EDEVICE;                                                        \
+    }                                                                           \
+  } while (0)
+#define SQ_TRY(expr)            \
+  do {                          \
+    int _s = (expr);            \
+    if (_s != SQ_OK) return _s; \
+  } while (0)
+
+inline int launch_status(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("launch of %s failed: %s", what, hipGetErrorString(e));
+    return SQ_EDEVICE;
+  }
+  return SQ_OK;
+}
+
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// ------------------------------------------------------------------ derived dims
+struct Net {
+  sq_dims d;
+  int side;            // squinted side (16)
+  int conv_side[4];    // output side of each conv
+  int flat;            // encoder feature width
+  int cin_critic;      // proj + proprio + action
+  int cin_actor;       // proj + proprio
+  int img;             // C * side * side (one squinted image)
+};
+int make_net(const sq_dims* d, Net* n);   // validates; SQ_EINVAL on bad dims
+
+// canonical flat parameter layout (offsets in floats)
+struct Dense { long long W, b, g, beta; int out, in; };
+struct Head { long long W, b; int out, in; };
+struct Twin { Dense l1, l2; Head out; };
+struct Layout {
+  long long conv_W[4], conv_b[4];
+  Dense ctrunk; Twin q[2];
+  Dense atrunk; Dense al1, al2; Head aout;
+  long long log_alpha;
+  long long enc_begin, enc_end, critic_begin, critic_end, actor_begin, actor_end, total;
+  int n_tensors;
+  long long tensor_off[64];
+};
+void make_layout(const Net& n, Layout* L);
+
+// ------------------------------------------------------------------ bump allocator
+struct Bump {
+  char* base;     // nullptr while measuring
+  size_t off = 0;
+  template <class T> T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------ kernel launchers
+// Every launcher enqueues on `st` and returns SQ_OK or SQ_EDEVICE.
+
+// counters layout (int32 device array)
+enum { CTR_U = 0, CTR_TC = 1, CTR_TA = 2, CTR_TALPHA = 3, CTR_N = 4 };
+
+// rng.hip
+int launch_sample_batch(unsigned long long seed, const int* ctr, int size, int B, int A, int S,
+                        const float* proprio, const float* next_proprio, const float* action,
+                        const float* reward, const uint8_t* done, int* idx, float* eps2B, float* S2,
+                        float* Arep, float* r, float* d, hipStream_t st);
+int launch_indices(unsigned long long seed, unsigned update, int size, int n, int* idx, hipStream_t st);
+int launch_gaussian(unsigned long long seed, unsigned update, unsigned stream_id, int n, float* out,
+                    hipStream_t st);
+int launch_act_noise(unsigned long long seed, unsigned long long request_id, int rows, int A, float* out,
+                     hipStream_t st);
+
+// squint.hip: frames [*, H, W, C] uint8, rows idx (nullable) -> out [n, C, side, side]
+int squint_ok(int H, int W, int C, int k);
+int launch_squint(const uint8_t* frames, const int* idx, int n, int H, int W, int C, int k, int bf16_out,
+                  void* out, long long out_row_stride, hipStream_t st);
+// 2B images: obs rows idx[0..B) then next_obs rows idx[0..B)
+int launch_squint_pair(const uint8_t* obs, const uint8_t* next_obs, const int* idx, int B, int H, int W,
+                       int C, int k, float* out, hipStream_t st);
+
+// serving: frames gathered through per-row pointers
+int launch_squint_rows(const uint8_t* const* rows, int n, int H, int W, int C, int k, float* out, hipStream_t st);
+// serve.hip: per-row gather / scatter of small vectors, per-row act noise
+int gather_rows(const float* const* src, int width, int n, float* dst, hipStream_t st);
+int scatter_rows(const float* src, int width, int n, float* const* dst, hipStream_t st);
+int act_noise_rows(unsigned long long seed, const unsigned long long* ids, const int* rows, const int* sample, int n,
+                   int A, float* eps, hipStream_t st);
+
+// gemm.hip
+struct MatArg {            // element (r, k) at p[z*sz + r*lr + k*lk]
+  const float* p; long long lr, lk, sz;
+};
+struct OutArg {            // C(r, c) at p[z*sz + r*ld + c]
+  float* p; long long ld, sz;
+  const float* bias; long long bias_sz;  // bias[c] (+ z*bias_sz), nullable
+  int accumulate;                        // C += result
+  int relu;                              // C = max(C, 0) after bias / accumulate
+};
+// C(r, c) = sum_k A(r, k) * B(c, k)   (B is addressed by output column, then k).
+// scratch (nullable) enables a deterministic split over K for small outputs.
+int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
+         size_t scratch_floats, hipStream_t st);
+// convolutions (3x3 valid, NCHW, W [F, Cin, 3, 3]) as implicit GEMMs
+int conv_fwd(int bf16, const float* x, int n, int Cin, int H, int stride, const float* W, const float* b,
+             int F, float* out, hipStream_t st);
+size_t conv_dw_scratch_floats(int n, int Cin, int H, int stride, int F);
+// weight gradient of a conv whose (post-ReLU) output is `out`, upstream grad `dout`
+int conv_dw(int bf16, const float* x, int n, int Cin, int H, int stride, const float* dout, const float* out,
+            int F, float* dW, float* part, size_t part_floats, hipStream_t st);
+// input gradient of a stride-1 conv, through its ReLU
+int conv_dx(int bf16, const float* dout, const float* out, int n, int Cin, int H, const float* W, int F,
+            float* dx, hipStream_t st);
+
+// rowops.hip
+int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch,
+               const float* g, const float* beta, long long sz_par, int act_tanh,
+               float* y, long long ld_y, long long sz_y, float* xhat, float* rstd,
+               const float* e1, long long ld_e1, int w1, const float* e2, long long ld_e2, int w2,
+               hipStream_t st);
+int ln_bwd_partial_rows(int rows);
+int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y, long long ld_y,
+               long long sz_y, const float* xhat, const float* rstd, const float* g, long long sz_par,
+               int rows, int H, int batch, int act_tanh, float* dpre, float* partials, hipStream_t st);
+int col_partials(const float* src, long long ld, long long sz, int rows, int N, int batch, float* part,
+                 hipStream_t st);
+// column sums of partial rows: part [batch][k][nrows][H] -> out[kk][z*out_sz + c]
+struct ColSeg {
+  const float* part; int nrows, H, k, batch;
+  float* out[3]; long long out_sz;
+  long long count;   // filled by colsum()
+};
+struct ColSegs { int n; ColSeg s[12]; };
+int colsum(ColSegs segs, hipStream_t st);
+
+int tanh_gauss_fwd(const float* head, int rows, int A, const float* eps, float lo, float hi, float* action,
+                   float* logp, float* save, hipStream_t st);
+int tanh_gauss_bwd(const float* save, const float* eps, const float* da, long long ld_da, const float* dlogp_vec,
+                   const float* dlogp_scalar, float scale, float lo, float hi, int rows, int A, float* dhead,
+                   hipStream_t st);
+int mean_action(const float* head, int rows, int A, float* action, hipStream_t st);
+
+int project_target(const float* logits2, int B, int N, float v_min, float v_max, const float* reward,
+                   const float* done, const float* logp_next, const float* log_alpha, float gamma,
+                   float* m, float* tgt_row, hipStream_t st);
+int c51_project_raw(const float* p, const float* reward, const uint8_t* done, const float* bonus,
+                    float gamma, int B, int N, float v_min, float v_max, float* m, hipStream_t st);
+int ce_loss(const float* logits2, const float* m, int B, int N, float v_min, float v_max,
+            float* dlogits2, float* loss_row, float* q_row, hipStream_t st);
+int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max, float* dlogits2,
+                    float* qa_row, hipStream_t st);
+// scal: [0] alpha before, [1] alpha after, [2] alpha loss, [3] mean(-log pi)
+int alpha_step(const float* logp, int B, float target_entropy, float* log_alpha, float* grad, float* m,
+               float* v, const int* ctr, const sq_hparams* hp, float* scal, hipStream_t st);
+int finish_update(const float* loss_row, const float* q_row, const float* tgt_row, const float* logp,
+                  const float* qa_row, const float* scal, int B, int actor_step, int* ctr, float* stats,
+                  hipStream_t st);
+int conv_bias_grad(const float* dout, const float* out, int n, int F, int HW, float* db, hipStream_t st);
+
+// adam.hip: step t = *step + 1 (not modified); EMA over i >= ema_begin
+int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
+         float* ema_target, long long ema_begin, uint16_t* shadow, hipStream_t st);
+
+}  // namespace sq

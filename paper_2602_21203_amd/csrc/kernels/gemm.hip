@@ -1,0 +1,330 @@
+// Dense products on the matrix cores (MFMA) of gfx950.
+//
+// One kernel template covers every contraction of the update: the linear layers
+// (forward, input gradient, weight gradient) and the 3x3 convolutions as implicit
+// GEMMs.  Operands are read through "fetchers" that map a logical element
+// (row, k) to memory, so transposes, concatenated inputs, im2col patches and the
+// ReLU mask of a convolution's gradient are all folded into the tile loads.
+//
+// Tiling: a 256-thread workgroup owns a 32 x 32 output tile.  Each K step stages
+// a 32 x BK slice of both operands in LDS (converted to the compute type: FP32,
+// or bfloat16 rounded to nearest even), and the four waves each contract a
+// quarter of the slice (16 k for FP32 with v_mfma_f32_16x16x4_f32, 32 k for
+// bfloat16 with v_mfma_f32_16x16x32_bf16), accumulating in FP32 registers.  At
+// the end the four partial tiles are summed through LDS in a fixed order, so the
+// result is independent of scheduling.  Long reductions (conv weight gradients)
+// are split over K across workgroups into a scratch buffer and summed in order
+// by a second kernel.
+#include "../common.h"
+#include "bf16.h"
+
+namespace sq {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kThreads = 256;
+constexpr int kTile = 32;
+
+template <bool BF16> struct Cfg;
+template <> struct Cfg<false> {
+  using T = float;
+  static constexpr int KW = 16;   // k per wave per step
+  static constexpr int PAD = 1;
+};
+template <> struct Cfg<true> {
+  using T = uint16_t;             // bfloat16 bits
+  static constexpr int KW = 32;
+  static constexpr int PAD = 8;   // keeps 16-byte alignment of every 8-element group
+};
+
+__device__ __forceinline__ float to_t(float v, float*) { return v; }
+__device__ __forceinline__ uint16_t to_t(float v, uint16_t*) { return bf16_bits(v); }
+
+// ---------------------------------------------------------------- fetchers
+// KFAST: consecutive k are adjacent in memory (coalesce along k), else along rows.
+template <bool KF> struct FMat {
+  const float* p; long long lr, lk, sz;
+  static constexpr bool KFAST = KF;
+  __device__ __forceinline__ float get(int z, int r, int k) const { return p[z * sz + r * lr + k * lk]; }
+};
+
+// im2col of an NCHW input: row = (n, oy, ox), k = (c, ky, kx)
+struct FConvPatch {
+  const float* x; int Cin, H, Ho, stride;
+  static constexpr bool KFAST = false;
+  __device__ __forceinline__ float get(int, int r, int k) const {
+    const int HoWo = Ho * Ho;
+    const int n = r / HoWo, p = r - n * HoWo, oy = p / Ho, ox = p - oy * Ho;
+    const int c = k / 9, t = k - 9 * c, ky = t / 3, kx = t - 3 * ky;
+    return x[(((long long)n * Cin + c) * H + oy * stride + ky) * H + ox * stride + kx];
+  }
+};
+// the same patch matrix transposed: row = (c, ky, kx), k = (n, oy, ox)
+struct FConvPatchT {
+  FConvPatch f;
+  static constexpr bool KFAST = true;
+  __device__ __forceinline__ float get(int z, int r, int k) const { return f.get(z, k, r); }
+};
+// gradient at a conv's pre-activation, transposed: row = f, k = (n, p); the
+// upstream gradient is masked by the conv's ReLU output
+struct FConvGradT {
+  const float* dout; const float* out; int F, HoWo;
+  static constexpr bool KFAST = true;
+  __device__ __forceinline__ float get(int, int r, int k) const {
+    const int n = k / HoWo, p = k - n * HoWo;
+    const long long i = ((long long)n * F + r) * HoWo + p;
+    return out[i] > 0.f ? dout[i] : 0.f;
+  }
+};
+// input gradient of a stride-1 conv: row = (n, iy, ix), k = (f, ky, kx)
+struct FConvDxA {
+  const float* dout; const float* out; int F, Hin, Ho;
+  static constexpr bool KFAST = false;
+  __device__ __forceinline__ float get(int, int r, int k) const {
+    const int HW = Hin * Hin;
+    const int n = r / HW, q = r - n * HW, iy = q / Hin, ix = q - iy * Hin;
+    const int f = k / 9, t = k - 9 * f, ky = t / 3, kx = t - 3 * ky;
+    const int oy = iy - ky, ox = ix - kx;
+    if (oy < 0 || oy >= Ho || ox < 0 || ox >= Ho) return 0.f;
+    const long long i = (((long long)n * F + f) * Ho + oy) * Ho + ox;
+    return out[i] > 0.f ? dout[i] : 0.f;
+  }
+};
+// conv weights seen as B(c, (f, ky, kx)) = W[f][c][ky][kx]
+struct FConvDxB {
+  const float* W; int Cin;
+  static constexpr bool KFAST = true;
+  __device__ __forceinline__ float get(int, int r, int k) const {
+    const int f = k / 9, t = k - 9 * f;
+    return W[((long long)f * Cin + r) * 9 + t];
+  }
+};
+
+// ---------------------------------------------------------------- stores
+struct StMat {
+  float* p; long long ld, sz; const float* bias; long long bias_sz; int acc, relu;
+  static constexpr bool ROW_FAST = false;
+  __device__ __forceinline__ void put(int z, int r, int c, float v) const {
+    const long long i = z * sz + (long long)r * ld + c;
+    if (bias) v += bias[z * bias_sz + c];
+    if (acc) v += p[i];
+    if (relu) v = fmaxf(v, 0.f);
+    p[i] = v;
+  }
+};
+// C((n, p), c) -> out[n][c][p] (NCHW), optional bias + ReLU
+struct StConv {
+  float* out; int Cout, HW; const float* bias; int relu;
+  static constexpr bool ROW_FAST = true;
+  __device__ __forceinline__ void put(int, int r, int c, float v) const {
+    const int n = r / HW, p = r - n * HW;
+    if (bias) v += bias[c];
+    if (relu) v = fmaxf(v, 0.f);
+    out[((long long)n * Cout + c) * HW + p] = v;
+  }
+};
+// split-K partial: part[(z * splits + s) * M * N + r * N + c]
+struct StPart {
+  float* part; int M, N, splits;
+  __device__ __forceinline__ void put(int z, int s, int r, int c, float v) const {
+    part[(((long long)z * splits + s) * M + r) * N + c] = v;
+  }
+};
+
+// ---------------------------------------------------------------- kernel
+template <bool BF16, class FA, class FB, class ST, bool SPLIT>
+__global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart sp, int M, int N, int K,
+                                                   int kchunk) {
+  using C = Cfg<BF16>;
+  using T = typename C::T;
+  constexpr int BK = 4 * C::KW;
+  constexpr int LD = BK + C::PAD;
+  constexpr int TILE_BYTES = 2 * kTile * LD * (int)sizeof(T);
+  constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
+  constexpr int LDS_BYTES = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
+  __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
+  T* As = reinterpret_cast<T*>(lds);
+  T* Bs = As + kTile * LD;
+
+  const int z = blockIdx.z / (SPLIT ? sp.splits : 1);
+  const int split = SPLIT ? blockIdx.z % sp.splits : 0;
+  const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    for (int e = threadIdx.x; e < kTile * BK; e += kThreads) {
+      int r, k;
+      if (FA::KFAST) { r = e / BK; k = e - r * BK; } else { k = e / kTile; r = e - k * kTile; }
+      const int gr = m0 + r, gk = k0 + k;
+      As[r * LD + k] = to_t((gr < M && gk < kend) ? fa.get(z, gr, gk) : 0.f, (T*)nullptr);
+    }
+    for (int e = threadIdx.x; e < kTile * BK; e += kThreads) {
+      int r, k;
+      if (FB::KFAST) { r = e / BK; k = e - r * BK; } else { k = e / kTile; r = e - k * kTile; }
+      const int gr = n0 + r, gk = k0 + k;
+      Bs[r * LD + k] = to_t((gr < N && gk < kend) ? fb.get(z, gr, gk) : 0.f, (T*)nullptr);
+    }
+    __syncthreads();
+    if constexpr (!BF16) {
+#pragma unroll
+      for (int kk = 0; kk < C::KW; kk += 4) {
+        const int kq = wave * C::KW + kk + lq;
+        const float a0 = As[li * LD + kq], a1 = As[(16 + li) * LD + kq];
+        const float b0 = Bs[li * LD + kq], b1 = Bs[(16 + li) * LD + kq];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else {
+      const int kq = wave * 32 + 8 * lq;
+      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[li * LD + kq]);
+      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(16 + li) * LD + kq]);
+      const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[li * LD + kq]);
+      const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[(16 + li) * LD + kq]);
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // fixed-order sum of the four waves' partial tiles
+  float* red = reinterpret_cast<float*>(lds);
+  constexpr int RLD = kTile + 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        red[(wave * kTile + i * 16 + 4 * lq + q) * RLD + j * 16 + li] = acc[i][j][q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
+    int r, c;
+    if constexpr (!SPLIT && ST::ROW_FAST) { c = e / kTile; r = e - c * kTile; } else { r = e / kTile; c = e - r * kTile; }
+    const float v = ((red[(0 * kTile + r) * RLD + c] + red[(1 * kTile + r) * RLD + c]) +
+                     red[(2 * kTile + r) * RLD + c]) + red[(3 * kTile + r) * RLD + c];
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < M && gc < N) {
+      if constexpr (SPLIT) sp.put(z, split, gr, gc, v); else st.put(z, gr, gc, v);
+    }
+  }
+}
+
+// sum of split-K partials in split order, then the real store
+template <class ST>
+__global__ void k_split_reduce(StPart sp, ST st, int batch) {
+  const long long MN = (long long)sp.M * sp.N;
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= MN * batch) return;
+  const int z = (int)(e / MN);
+  const long long rc = e - z * MN;
+  const int r = (int)(rc / sp.N), c = (int)(rc - (long long)r * sp.N);
+  const float* p = sp.part + (long long)z * sp.splits * MN + rc;
+  float v = 0.f;
+  for (int s = 0; s < sp.splits; ++s) v += p[s * MN];
+  st.put(z, r, c, v);
+}
+
+template <class FA, class FB, class ST>
+static int run(int bf16, int M, int N, int K, int batch, FA fa, FB fb, ST st, float* scratch,
+               size_t scratch_floats, hipStream_t stream, const char* what) {
+  if (M <= 0 || N <= 0 || batch <= 0) return SQ_OK;
+  const int bk = bf16 ? 4 * Cfg<true>::KW : 4 * Cfg<false>::KW;
+  const int tiles = cdiv(M, kTile) * cdiv(N, kTile) * batch;
+  int splits = 1;
+  if (scratch && tiles < 192 && K > 8 * bk) {
+    splits = cdiv(256, tiles);
+    const int most = K / (2 * bk);
+    splits = splits < most ? splits : most;
+    while (splits > 1 && (size_t)splits * M * N * batch > scratch_floats) --splits;
+  }
+  int kchunk = K > 0 ? K : 1;
+  if (splits > 1) {
+    kchunk = cdiv(cdiv(K, splits), bk) * bk;
+    splits = cdiv(K, kchunk);
+  }
+  StPart sp{scratch, M, N, splits};
+  dim3 grid(cdiv(M, kTile), cdiv(N, kTile), batch * splits);
+  if (splits <= 1) {
+    if (bf16)
+      k_gemm<true, FA, FB, ST, false><<<grid, kThreads, 0, stream>>>(fa, fb, st, sp, M, N, K, kchunk);
+    else
+      k_gemm<false, FA, FB, ST, false><<<grid, kThreads, 0, stream>>>(fa, fb, st, sp, M, N, K, kchunk);
+    return launch_status(what);
+  }
+  if (bf16)
+    k_gemm<true, FA, FB, ST, true><<<grid, kThreads, 0, stream>>>(fa, fb, st, sp, M, N, K, kchunk);
+  else
+    k_gemm<false, FA, FB, ST, true><<<grid, kThreads, 0, stream>>>(fa, fb, st, sp, M, N, K, kchunk);
+  SQ_TRY(launch_status(what));
+  const long long total = (long long)M * N * batch;
+  k_split_reduce<ST><<<cdiv(total, 256), 256, 0, stream>>>(sp, st, batch);
+  return launch_status("split_reduce");
+}
+
+// ---------------------------------------------------------------- public launchers
+int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
+         size_t scratch_floats, hipStream_t st) {
+  StMat out{C.p, C.ld, C.sz, C.bias, C.bias_sz, C.accumulate, C.relu};
+  // pick the coalescing direction of each operand from its strides
+  if (A.lk == 1 && B.lk == 1)
+    return run(bf16, M, N, K, batch, FMat<true>{A.p, A.lr, A.lk, A.sz}, FMat<true>{B.p, B.lr, B.lk, B.sz}, out,
+               scratch, scratch_floats, st, "gemm_tt");
+  if (A.lk == 1)
+    return run(bf16, M, N, K, batch, FMat<true>{A.p, A.lr, A.lk, A.sz}, FMat<false>{B.p, B.lr, B.lk, B.sz}, out,
+               scratch, scratch_floats, st, "gemm_tn");
+  if (B.lk == 1)
+    return run(bf16, M, N, K, batch, FMat<false>{A.p, A.lr, A.lk, A.sz}, FMat<true>{B.p, B.lr, B.lk, B.sz}, out,
+               scratch, scratch_floats, st, "gemm_nt");
+  return run(bf16, M, N, K, batch, FMat<false>{A.p, A.lr, A.lk, A.sz}, FMat<false>{B.p, B.lr, B.lk, B.sz}, out,
+             scratch, scratch_floats, st, "gemm_nn");
+}
+
+int conv_fwd(int bf16, const float* x, int n, int Cin, int H, int stride, const float* W, const float* b, int F,
+             float* out, hipStream_t st) {
+  const int Ho = (H - 3) / stride + 1;
+  const int K = Cin * 9;
+  FConvPatch fa{x, Cin, H, Ho, stride};
+  FMat<true> fb{W, K, 1, 0};
+  StConv sc{out, F, Ho * Ho, b, 1};
+  return run(bf16, n * Ho * Ho, F, K, 1, fa, fb, sc, nullptr, 0, st, "conv_fwd");
+}
+
+size_t conv_dw_scratch_floats(int n, int Cin, int H, int stride, int F) {
+  (void)n; (void)H; (void)stride;
+  return (size_t)256 * F * (Cin * 9);
+}
+
+int conv_dw(int bf16, const float* x, int n, int Cin, int H, int stride, const float* dout, const float* out,
+            int F, float* dW, float* part, size_t part_floats, hipStream_t st) {
+  const int Ho = (H - 3) / stride + 1;
+  const int K = Cin * 9;
+  FConvGradT fa{dout, out, F, Ho * Ho};
+  FConvPatchT fb{FConvPatch{x, Cin, H, Ho, stride}};
+  StMat sm{dW, K, 0, nullptr, 0, 0, 0};
+  return run(bf16, F, K, n * Ho * Ho, 1, fa, fb, sm, part, part_floats, st, "conv_dw");
+}
+
+int conv_dx(int bf16, const float* dout, const float* out, int n, int Cin, int H, const float* W, int F, float* dx,
+            hipStream_t st) {
+  const int Ho = H - 2;
+  FConvDxA fa{dout, out, F, H, Ho};
+  FConvDxB fb{W, Cin};
+  StConv sc{dx, Cin, H * H, nullptr, 0};
+  return run(bf16, n * H * H, Cin, F * 9, 1, fa, fb, sc, nullptr, 0, st, "conv_dx");
+}
+
+}  // namespace sq

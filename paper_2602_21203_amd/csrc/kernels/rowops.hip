@@ -1,0 +1,658 @@
+// Row-wise and small reduction kernels of the update, one wavefront (64 lanes)
+// per row with shuffle reductions:
+//   LayerNorm + activation forward / backward (Sec. IV Normalization)
+//   column sums of gradient partials (bias, LayerNorm gain / shift gradients)
+//   tanh-Gaussian policy head forward / backward (Sec. III Eq. (3))
+//   twin-target softmax average + C51 projection (Eq. (1), categorical form)
+//   cross entropy to the projected target, expected Q and its gradient
+//   temperature step, per-update statistics and counters
+// Every reduction has a fixed order: shuffle butterflies whose result is taken
+// from lane 0, and partial sums written per (row block, wave) and summed in order.
+#include <math.h>
+
+#include "../common.h"
+
+namespace sq {
+
+constexpr int kMaxPerLane = 16;   // LayerNorm widths up to 1024
+constexpr int kLnBwdRows = 16;    // rows per workgroup in backward kernels
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return __shfl(v, 0, 64);
+}
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return __shfl(v, 0, 64);
+}
+
+// fixed-order block sum of 256 threads; result valid in every thread
+__device__ float block_sum256(float v, float* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const float r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// ---------------------------------------------------------------- LayerNorm forward
+__global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, long long ld_pre, long long sz_pre,
+                                                int rows, int H, const float* __restrict__ g,
+                                                const float* __restrict__ beta, long long sz_par, int act_tanh,
+                                                float* __restrict__ y, long long ld_y, long long sz_y,
+                                                float* __restrict__ xhat, float* __restrict__ rstd,
+                                                const float* __restrict__ e1, long long ld_e1, int w1,
+                                                const float* __restrict__ e2, long long ld_e2, int w2) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int z = blockIdx.y;
+  if (row >= rows) return;
+  const float* p = pre + z * sz_pre + row * ld_pre;
+  float v[kMaxPerLane];
+  float s = 0.f;
+#pragma unroll
+  for (int t = 0; t < kMaxPerLane; ++t) {
+    const int j = lane + 64 * t;
+    v[t] = j < H ? p[j] : 0.f;
+    s += v[t];
+  }
+  const float mean = wave_sum(s) / (float)H;
+  float q = 0.f;
+#pragma unroll
+  for (int t = 0; t < kMaxPerLane; ++t) {
+    const int j = lane + 64 * t;
+    const float dv = j < H ? v[t] - mean : 0.f;
+    q += dv * dv;
+  }
+  const float var = wave_sum(q) / (float)H;
+  const float rs = 1.0f / sqrtf(var + 1e-5f);
+  const float* gz = g + z * sz_par;
+  const float* bz = beta + z * sz_par;
+  float* yr = y + z * sz_y + row * ld_y;
+  float* xr = xhat + ((long long)z * rows + row) * H;
+#pragma unroll
+  for (int t = 0; t < kMaxPerLane; ++t) {
+    const int j = lane + 64 * t;
+    if (j < H) {
+      const float xh = (v[t] - mean) * rs;
+      const float o = gz[j] * xh + bz[j];
+      xr[j] = xh;
+      yr[j] = act_tanh ? tanhf(o) : fmaxf(o, 0.f);
+    }
+  }
+  if (lane == 0) rstd[(long long)z * rows + row] = rs;
+  for (int j = lane; j < w1; j += 64) yr[H + j] = e1[row * ld_e1 + j];
+  for (int j = lane; j < w2; j += 64) yr[H + w1 + j] = e2[row * ld_e2 + j];
+}
+
+int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch, const float* g,
+               const float* beta, long long sz_par, int act_tanh, float* y, long long ld_y, long long sz_y,
+               float* xhat, float* rstd, const float* e1, long long ld_e1, int w1, const float* e2,
+               long long ld_e2, int w2, hipStream_t st) {
+  if (rows <= 0) return SQ_OK;
+  dim3 grid(cdiv(rows, 4), batch);
+  k_ln_fwd<<<grid, 256, 0, st>>>(pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat,
+                                 rstd, e1, ld_e1, w1, e2, ld_e2, w2);
+  return launch_status("ln_fwd");
+}
+
+// ---------------------------------------------------------------- LayerNorm backward
+// Per row: dz = dy * act'(y), dxh = dz * g,
+//   dpre = rstd * (dxh - mean(dxh) - xhat * mean(dxh * xhat)).
+// Column partials per (row block, wave): [3][nblk * 4][H] = (dpre, dz * xhat, dz)
+// for the bias, gain and shift gradients.
+__global__ __launch_bounds__(256) void k_ln_bwd(const float* __restrict__ dy, long long ld_dy, long long sz_dy,
+                                                const float* __restrict__ y, long long ld_y, long long sz_y,
+                                                const float* __restrict__ xhat, const float* __restrict__ rstd,
+                                                const float* __restrict__ g, long long sz_par, int rows, int H,
+                                                int act_tanh, float* __restrict__ dpre,
+                                                float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int blk = blockIdx.x, z = blockIdx.y;
+  const int nblk = gridDim.x;
+  const float* gz = g + z * sz_par;
+  float pb[kMaxPerLane], pg[kMaxPerLane], pz[kMaxPerLane];
+#pragma unroll
+  for (int t = 0; t < kMaxPerLane; ++t) pb[t] = pg[t] = pz[t] = 0.f;
+  for (int rr = wave; rr < kLnBwdRows; rr += 4) {
+    const int row = blk * kLnBwdRows + rr;
+    if (row >= rows) break;
+    const float* dyr = dy + z * sz_dy + row * ld_dy;
+    const float* yr = y + z * sz_y + row * ld_y;
+    const float* xr = xhat + ((long long)z * rows + row) * H;
+    const float rs = rstd[(long long)z * rows + row];
+    float dz[kMaxPerLane], xh[kMaxPerLane];
+    float s1 = 0.f, s2 = 0.f;
+#pragma unroll
+    for (int t = 0; t < kMaxPerLane; ++t) {
+      const int j = lane + 64 * t;
+      if (j < H) {
+        const float yy = yr[j];
+        const float d = dyr[j] * (act_tanh ? (1.f - yy * yy) : (yy > 0.f ? 1.f : 0.f));
+        dz[t] = d;
+        xh[t] = xr[j];
+        const float dx = d * gz[j];
+        s1 += dx;
+        s2 += dx * xh[t];
+      } else {
+        dz[t] = 0.f;
+        xh[t] = 0.f;
+      }
+    }
+    const float c1 = wave_sum(s1) / (float)H;
+    const float c2 = wave_sum(s2) / (float)H;
+    float* dp = dpre + ((long long)z * rows + row) * H;
+#pragma unroll
+    for (int t = 0; t < kMaxPerLane; ++t) {
+      const int j = lane + 64 * t;
+      if (j < H) {
+        const float v = rs * (dz[t] * gz[j] - c1 - xh[t] * c2);
+        dp[j] = v;
+        pb[t] += v;
+        pg[t] += dz[t] * xh[t];
+        pz[t] += dz[t];
+      }
+    }
+  }
+  if (part) {
+    const long long prow = (long long)blk * 4 + wave;
+    const long long plane = (long long)nblk * 4 * H;
+    float* pp = part + (long long)z * 3 * plane + prow * H;
+#pragma unroll
+    for (int t = 0; t < kMaxPerLane; ++t) {
+      const int j = lane + 64 * t;
+      if (j < H) {
+        pp[j] = pb[t];
+        pp[plane + j] = pg[t];
+        pp[2 * plane + j] = pz[t];
+      }
+    }
+  }
+}
+
+int ln_bwd_partial_rows(int rows) { return cdiv(rows, kLnBwdRows) * 4; }
+
+int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y, long long ld_y, long long sz_y,
+               const float* xhat, const float* rstd, const float* g, long long sz_par, int rows, int H, int batch,
+               int act_tanh, float* dpre, float* partials, hipStream_t st) {
+  if (rows <= 0) return SQ_OK;
+  dim3 grid(cdiv(rows, kLnBwdRows), batch);
+  k_ln_bwd<<<grid, 256, 0, st>>>(dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, sz_par, rows, H, act_tanh, dpre,
+                                 partials);
+  return launch_status("ln_bwd");
+}
+
+// ---------------------------------------------------------------- column partials
+// Partial column sums of a [batch][rows][N] matrix: [batch][nblk * 4][N] (same
+// blocking as the LayerNorm backward) -- used for output-head bias gradients.
+__global__ __launch_bounds__(256) void k_col_partials(const float* __restrict__ src, long long ld, long long sz,
+                                                      int rows, int N, float* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int blk = blockIdx.x, z = blockIdx.y, nblk = gridDim.x;
+  for (int j0 = 0; j0 < N; j0 += 64) {
+    const int j = j0 + lane;
+    float s = 0.f;
+    for (int rr = wave; rr < kLnBwdRows; rr += 4) {
+      const int row = blk * kLnBwdRows + rr;
+      if (row >= rows) break;
+      if (j < N) s += src[z * sz + row * ld + j];
+    }
+    if (j < N) part[((long long)z * nblk * 4 + blk * 4 + wave) * N + j] = s;
+  }
+}
+
+int col_partials(const float* src, long long ld, long long sz, int rows, int N, int batch, float* part,
+                 hipStream_t st) {
+  if (rows <= 0) return SQ_OK;
+  dim3 grid(cdiv(rows, kLnBwdRows), batch);
+  k_col_partials<<<grid, 256, 0, st>>>(src, ld, sz, rows, N, part);
+  return launch_status("col_partials");
+}
+
+// Sum partial rows in order.  Segment s: part [batch][k][nrows][H] -> out[k][z * out_sz + c].
+__global__ void k_colsum(ColSegs segs) {
+  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  int s = 0;
+  while (s < segs.n && e >= segs.s[s].count) { e -= segs.s[s].count; ++s; }
+  if (s >= segs.n) return;
+  const ColSeg& g = segs.s[s];
+  const int kh = g.k * g.H;
+  const int z = (int)(e / kh);
+  const int rem = (int)(e - (long long)z * kh);
+  const int kk = rem / g.H, c = rem - kk * g.H;
+  const float* p = g.part + ((long long)z * g.k + kk) * g.nrows * g.H + c;
+  float v = 0.f;
+  for (int r = 0; r < g.nrows; ++r) v += p[(long long)r * g.H];
+  if (g.out[kk]) g.out[kk][z * g.out_sz + c] = v;
+}
+
+int colsum(ColSegs segs, hipStream_t st) {
+  long long total = 0;
+  for (int i = 0; i < segs.n; ++i) {
+    segs.s[i].count = (long long)segs.s[i].batch * segs.s[i].k * segs.s[i].H;
+    total += segs.s[i].count;
+  }
+  if (total == 0) return SQ_OK;
+  k_colsum<<<cdiv(total, 256), 256, 0, st>>>(segs);
+  return launch_status("colsum");
+}
+
+// ---------------------------------------------------------------- tanh-Gaussian head
+__device__ __forceinline__ float softplusf(float x) {
+  return x > 0.f ? x + log1pf(expf(-x)) : log1pf(expf(x));
+}
+
+// head [rows][2A] = [mu | u_s]; save [rows][3A] = (tanh u_s, sigma, action)
+__global__ void k_tg_fwd(const float* __restrict__ head, int rows, int A, const float* __restrict__ eps, float lo,
+                         float hi, float* __restrict__ action, float* __restrict__ logp, float* __restrict__ save) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const float half_log_2pi = 0.91893853320467274f;
+  const float log2 = 0.69314718055994531f;
+  float lp = 0.f;
+  for (int d = 0; d < A; ++d) {
+    const float mu = head[(long long)r * 2 * A + d];
+    const float us = head[(long long)r * 2 * A + A + d];
+    const float e = eps[(long long)r * A + d];
+    const float tus = tanhf(us);
+    const float ls = lo + 0.5f * (hi - lo) * (tus + 1.f);
+    const float sd = expf(ls);
+    const float u = mu + sd * e;
+    const float a = tanhf(u);
+    lp += -0.5f * e * e - ls - half_log_2pi - 2.f * (log2 - u - softplusf(-2.f * u));
+    action[(long long)r * A + d] = a;
+    save[(long long)r * 3 * A + d] = tus;
+    save[(long long)r * 3 * A + A + d] = sd;
+    save[(long long)r * 3 * A + 2 * A + d] = a;
+  }
+  if (logp) logp[r] = lp;
+}
+
+int tanh_gauss_fwd(const float* head, int rows, int A, const float* eps, float lo, float hi, float* action,
+                   float* logp, float* save, hipStream_t st) {
+  if (rows <= 0) return SQ_OK;
+  k_tg_fwd<<<cdiv(rows, 64), 64, 0, st>>>(head, rows, A, eps, lo, hi, action, logp, save);
+  return launch_status("tanh_gauss_fwd");
+}
+
+// d log pi / du = 2 tanh(u); d log pi / d log sigma = -1 (direct term).
+// dlogp per row = (dlogp_vec ? dlogp_vec[r] : 0) + (dlogp_scalar ? *dlogp_scalar * scale : 0)
+__global__ void k_tg_bwd(const float* __restrict__ save, const float* __restrict__ eps,
+                         const float* __restrict__ da, long long ld_da, const float* __restrict__ dlogp_vec,
+                         const float* __restrict__ dlogp_scalar, float scale, float lo, float hi, int rows, int A,
+                         float* __restrict__ dhead) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  float dl = 0.f;
+  if (dlogp_vec) dl += dlogp_vec[r];
+  if (dlogp_scalar) dl += *dlogp_scalar * scale;
+  for (int d = 0; d < A; ++d) {
+    const float tus = save[(long long)r * 3 * A + d];
+    const float sd = save[(long long)r * 3 * A + A + d];
+    const float a = save[(long long)r * 3 * A + 2 * A + d];
+    const float e = eps[(long long)r * A + d];
+    const float dav = da ? da[r * ld_da + d] : 0.f;
+    const float du = dav * (1.f - a * a) + dl * 2.f * a;
+    const float dls = du * sd * e - dl;
+    dhead[(long long)r * 2 * A + d] = du;
+    dhead[(long long)r * 2 * A + A + d] = dls * 0.5f * (hi - lo) * (1.f - tus * tus);
+  }
+}
+
+int tanh_gauss_bwd(const float* save, const float* eps, const float* da, long long ld_da, const float* dlogp_vec,
+                   const float* dlogp_scalar, float scale, float lo, float hi, int rows, int A, float* dhead,
+                   hipStream_t st) {
+  if (rows <= 0) return SQ_OK;
+  k_tg_bwd<<<cdiv(rows, 64), 64, 0, st>>>(save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, rows, A,
+                                          dhead);
+  return launch_status("tanh_gauss_bwd");
+}
+
+__global__ void k_mean_action(const float* __restrict__ head, int rows, int A, float* __restrict__ action) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * A) return;
+  const int r = e / A, d = e - r * A;
+  action[e] = tanhf(head[(long long)r * 2 * A + d]);
+}
+
+int mean_action(const float* head, int rows, int A, float* action, hipStream_t st) {
+  if (rows <= 0) return SQ_OK;
+  k_mean_action<<<cdiv((long long)rows * A, 256), 256, 0, st>>>(head, rows, A, action);
+  return launch_status("mean_action");
+}
+
+// ---------------------------------------------------------------- C51 heads
+constexpr int kMaxAtomsPerLane = 4;   // atoms up to 256
+
+__device__ __forceinline__ void softmax_row(const float* l, int N, int lane, float* p) {
+  float mx = -INFINITY;
+#pragma unroll
+  for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+    const int j = lane + 64 * t;
+    if (j < N) mx = fmaxf(mx, l[j]);
+  }
+  mx = wave_max(mx);
+  float s = 0.f;
+#pragma unroll
+  for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+    const int j = lane + 64 * t;
+    p[t] = j < N ? expf(l[j] - mx) : 0.f;
+    s += p[t];
+  }
+  s = wave_sum(s);
+#pragma unroll
+  for (int t = 0; t < kMaxAtomsPerLane; ++t) p[t] /= s;
+}
+
+__device__ __forceinline__ float lane_value(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// projection of one row, given the probabilities in registers (lane-strided:
+// atom j lives in lane j % 64, slot j / 64).  Every lane walks all atoms j in
+// order, reading p_j and b_j from their owner lane, so the sum order is fixed.
+// Writes m and returns sum_i m_i z_i.
+__device__ float project_row(const float* p, int N, int lane, float v_min, float dz, float r, float d, float gamma,
+                             float bonus, float* m_out) {
+  float bpos[kMaxAtomsPerLane];
+#pragma unroll
+  for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+    const int j = lane + 64 * t;
+    const float zj = v_min + (float)j * dz;
+    const float tz = r + gamma * (1.f - d) * (zj + bonus);
+    bpos[t] = fminf(fmaxf((tz - v_min) / dz, 0.f), (float)(N - 1));
+  }
+  float mi[kMaxAtomsPerLane];
+#pragma unroll
+  for (int t = 0; t < kMaxAtomsPerLane; ++t) mi[t] = 0.f;
+#pragma unroll
+  for (int ts = 0; ts < kMaxAtomsPerLane; ++ts) {
+    if (64 * ts >= N) break;
+    const int lim = N - 64 * ts < 64 ? N - 64 * ts : 64;
+    for (int l = 0; l < lim; ++l) {
+      const float pj = lane_value(p[ts], l);
+      const float bj = lane_value(bpos[ts], l);
+#pragma unroll
+      for (int t = 0; t < kMaxAtomsPerLane; ++t)
+        mi[t] += pj * fmaxf(0.f, 1.f - fabsf(bj - (float)(lane + 64 * t)));
+    }
+  }
+  float mz = 0.f;
+#pragma unroll
+  for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+    const int i = lane + 64 * t;
+    if (i < N) {
+      m_out[i] = mi[t];
+      mz += mi[t] * (v_min + (float)i * dz);
+    }
+  }
+  return wave_sum(mz);
+}
+
+// target path: p = (softmax(l1) + softmax(l2)) / 2, bonus = -exp(log_alpha) * logp_next
+__global__ __launch_bounds__(256) void k_project_target(const float* __restrict__ logits2, int B, int N, float v_min,
+                                                        float v_max, const float* __restrict__ reward,
+                                                        const float* __restrict__ done,
+                                                        const float* __restrict__ logp_next,
+                                                        const float* __restrict__ log_alpha, float gamma,
+                                                        float* __restrict__ m, float* __restrict__ tgt_row) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = blockIdx.x * 4 + wave;
+  if (b >= B) return;
+  float p0[kMaxAtomsPerLane], p1[kMaxAtomsPerLane];
+  softmax_row(logits2 + (long long)b * N, N, lane, p0);
+  softmax_row(logits2 + ((long long)B + b) * N, N, lane, p1);
+#pragma unroll
+  for (int t = 0; t < kMaxAtomsPerLane; ++t) p0[t] = 0.5f * (p0[t] + p1[t]);
+  const float alpha = expf(*log_alpha);
+  const float dz = (v_max - v_min) / (float)(N - 1);
+  const float mz = project_row(p0, N, lane, v_min, dz, reward[b], done[b], gamma, -alpha * logp_next[b],
+                               m + (long long)b * N);
+  if (lane == 0 && tgt_row) tgt_row[b] = mz;
+}
+
+int project_target(const float* logits2, int B, int N, float v_min, float v_max, const float* reward,
+                   const float* done, const float* logp_next, const float* log_alpha, float gamma, float* m,
+                   float* tgt_row, hipStream_t st) {
+  if (B <= 0) return SQ_OK;
+  k_project_target<<<cdiv(B, 4), 256, 0, st>>>(logits2, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
+                                               gamma, m, tgt_row);
+  return launch_status("project_target");
+}
+
+// plain projection of given probabilities (library entry point)
+__global__ __launch_bounds__(256) void k_project(const float* __restrict__ p, const float* __restrict__ reward,
+                                                 const uint8_t* __restrict__ done, const float* __restrict__ bonus,
+                                                 float gamma, int B, int N, float v_min, float v_max,
+                                                 float* __restrict__ m) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = blockIdx.x * 4 + wave;
+  if (b >= B) return;
+  float pr[kMaxAtomsPerLane];
+#pragma unroll
+  for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+    const int j = lane + 64 * t;
+    pr[t] = j < N ? p[(long long)b * N + j] : 0.f;
+  }
+  const float dz = (v_max - v_min) / (float)(N - 1);
+  project_row(pr, N, lane, v_min, dz, reward[b], done[b] ? 1.f : 0.f, gamma, bonus ? bonus[b] : 0.f,
+              m + (long long)b * N);
+}
+
+int c51_project_raw(const float* p, const float* reward, const uint8_t* done, const float* bonus, float gamma, int B,
+                    int N, float v_min, float v_max, float* m, hipStream_t st) {
+  if (B <= 0) return SQ_OK;
+  k_project<<<cdiv(B, 4), 256, 0, st>>>(p, reward, done, bonus, gamma, B, N, v_min, v_max, m);
+  return launch_status("c51_project");
+}
+
+// cross entropy of both twins to m: loss_row[i][b] = -sum_j m_j log softmax_j;
+// dlogits = (softmax - m) / B; q_row[i][b] = sum_j softmax_j z_j
+__global__ __launch_bounds__(256) void k_ce(const float* __restrict__ logits2, const float* __restrict__ m, int B,
+                                            int N, float v_min, float v_max, float* __restrict__ dlogits2,
+                                            float* __restrict__ loss_row, float* __restrict__ q_row) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = blockIdx.x * 4 + wave;
+  if (b >= B) return;
+  const float dz = (v_max - v_min) / (float)(N - 1);
+  const float invB = 1.0f / (float)B;
+  for (int i = 0; i < 2; ++i) {
+    const float* l = logits2 + ((long long)i * B + b) * N;
+    float mx = -INFINITY;
+#pragma unroll
+    for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+      const int j = lane + 64 * t;
+      if (j < N) mx = fmaxf(mx, l[j]);
+    }
+    mx = wave_max(mx);
+    float e[kMaxAtomsPerLane], s = 0.f;
+#pragma unroll
+    for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+      const int j = lane + 64 * t;
+      e[t] = j < N ? expf(l[j] - mx) : 0.f;
+      s += e[t];
+    }
+    s = wave_sum(s);
+    const float lse = logf(s);
+    float ce = 0.f, q = 0.f;
+#pragma unroll
+    for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+      const int j = lane + 64 * t;
+      if (j < N) {
+        const float mj = m[(long long)b * N + j];
+        const float pj = e[t] / s;
+        ce -= mj * (l[j] - mx - lse);
+        q += pj * (v_min + (float)j * dz);
+        dlogits2[((long long)i * B + b) * N + j] = (pj - mj) * invB;
+      }
+    }
+    ce = wave_sum(ce);
+    q = wave_sum(q);
+    if (lane == 0) {
+      loss_row[(long long)i * B + b] = ce;
+      q_row[(long long)i * B + b] = q;
+    }
+  }
+}
+
+int ce_loss(const float* logits2, const float* m, int B, int N, float v_min, float v_max, float* dlogits2,
+            float* loss_row, float* q_row, hipStream_t st) {
+  if (B <= 0) return SQ_OK;
+  k_ce<<<cdiv(B, 4), 256, 0, st>>>(logits2, m, B, N, v_min, v_max, dlogits2, loss_row, q_row);
+  return launch_status("ce_loss");
+}
+
+// actor-loss head: Q_i = sum_j p_ij z_j, dL/dl_ij = -(1 / (2B)) p_ij (z_j - Q_i),
+// qa_row[b] = (Q_1 + Q_2) / 2
+__global__ __launch_bounds__(256) void k_expq(const float* __restrict__ logits2, int B, int N, float v_min,
+                                              float v_max, float* __restrict__ dlogits2, float* __restrict__ qa_row) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = blockIdx.x * 4 + wave;
+  if (b >= B) return;
+  const float dz = (v_max - v_min) / (float)(N - 1);
+  const float c = -0.5f / (float)B;
+  float qsum = 0.f;
+  for (int i = 0; i < 2; ++i) {
+    float p[kMaxAtomsPerLane];
+    softmax_row(logits2 + ((long long)i * B + b) * N, N, lane, p);
+    float q = 0.f;
+#pragma unroll
+    for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+      const int j = lane + 64 * t;
+      if (j < N) q += p[t] * (v_min + (float)j * dz);
+    }
+    q = wave_sum(q);
+#pragma unroll
+    for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+      const int j = lane + 64 * t;
+      if (j < N) dlogits2[((long long)i * B + b) * N + j] = c * p[t] * ((v_min + (float)j * dz) - q);
+    }
+    qsum += q;
+  }
+  if (lane == 0) qa_row[b] = 0.5f * qsum;
+}
+
+int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max, float* dlogits2, float* qa_row,
+                    hipStream_t st) {
+  if (B <= 0) return SQ_OK;
+  k_expq<<<cdiv(B, 4), 256, 0, st>>>(logits2, B, N, v_min, v_max, dlogits2, qa_row);
+  return launch_status("expected_q");
+}
+
+// ---------------------------------------------------------------- temperature step
+// L_alpha = alpha * mean(-log pi - H_target); d L / d log alpha = the same value.
+// One Adam step on log alpha with step t = ctr[CTR_TALPHA] + 1.
+// scal: [0] alpha before, [1] alpha after, [2] L_alpha, [3] mean(-log pi)
+__global__ __launch_bounds__(256) void k_alpha(const float* __restrict__ logp, int B, float target_entropy,
+                                               float* __restrict__ log_alpha, float* __restrict__ grad,
+                                               float* __restrict__ m, float* __restrict__ v,
+                                               const int* __restrict__ ctr, float lr, float b1, float b2,
+                                               float eps, float* __restrict__ scal) {
+  __shared__ float sh[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < B; i += 256) s += logp[i];
+  s = block_sum256(s, sh);
+  if (threadIdx.x != 0) return;
+  const float ent = -s / (float)B;
+  const float la = *log_alpha;
+  const float alpha = expf(la);
+  const float gr = alpha * (ent - target_entropy);
+  const float t = (float)(ctr[CTR_TALPHA] + 1);
+  const float mm = b1 * (*m) + (1.f - b1) * gr;
+  const float vv = b2 * (*v) + (1.f - b2) * gr * gr;
+  const float mh = mm / (1.f - powf(b1, t));
+  const float vh = vv / (1.f - powf(b2, t));
+  const float la2 = la - lr * mh / (sqrtf(vh) + eps);
+  *m = mm;
+  *v = vv;
+  *log_alpha = la2;
+  if (grad) *grad = gr;
+  scal[0] = alpha;
+  scal[1] = expf(la2);
+  scal[2] = gr;
+  scal[3] = ent;
+}
+
+int alpha_step(const float* logp, int B, float target_entropy, float* log_alpha, float* grad, float* m, float* v,
+               const int* ctr, const sq_hparams* hp, float* scal, hipStream_t st) {
+  k_alpha<<<1, 256, 0, st>>>(logp, B, target_entropy, log_alpha, grad, m, v, ctr, hp->lr, hp->beta1, hp->beta2,
+                             hp->adam_eps, scal);
+  return launch_status("alpha_step");
+}
+
+// ---------------------------------------------------------------- end of an update
+// stats = {L_c, L_pi, L_alpha, alpha_new, entropy, mean Q, mean target, non-finite}
+__global__ __launch_bounds__(256) void k_finish(const float* __restrict__ loss_row, const float* __restrict__ q_row,
+                                                const float* __restrict__ tgt_row, const float* __restrict__ logp,
+                                                const float* __restrict__ qa_row, const float* __restrict__ scal,
+                                                int B, int actor_step, int* __restrict__ ctr,
+                                                float* __restrict__ stats) {
+  __shared__ float sh[256];
+  float a = 0.f, q = 0.f, tg = 0.f, pi = 0.f;
+  const float alpha_new = scal[1];
+  for (int i = threadIdx.x; i < B; i += 256) {
+    a += loss_row[i] + loss_row[B + i];
+    q += q_row[i] + q_row[B + i];
+    tg += tgt_row[i];
+    if (actor_step) pi += alpha_new * logp[i] - qa_row[i];
+  }
+  a = block_sum256(a, sh);
+  q = block_sum256(q, sh);
+  tg = block_sum256(tg, sh);
+  pi = block_sum256(pi, sh);
+  if (threadIdx.x != 0) return;
+  float o[8];
+  o[0] = a / (float)B;
+  o[1] = actor_step ? pi / (float)B : 0.f;
+  o[2] = scal[2];
+  o[3] = alpha_new;
+  o[4] = scal[3];
+  o[5] = q / (float)(2 * B);
+  o[6] = tg / (float)B;
+  int bad = 0;
+  for (int i = 0; i < 7; ++i) bad |= !isfinite(o[i]);
+  o[7] = bad ? 1.f : 0.f;
+  for (int i = 0; i < 8; ++i) stats[i] = o[i];
+  ctr[CTR_U] += 1;
+  ctr[CTR_TC] += 1;
+  ctr[CTR_TALPHA] += 1;
+  if (actor_step) ctr[CTR_TA] += 1;
+}
+
+int finish_update(const float* loss_row, const float* q_row, const float* tgt_row, const float* logp,
+                  const float* qa_row, const float* scal, int B, int actor_step, int* ctr, float* stats,
+                  hipStream_t st) {
+  k_finish<<<1, 256, 0, st>>>(loss_row, q_row, tgt_row, logp, qa_row, scal, B, actor_step, ctr, stats);
+  return launch_status("finish_update");
+}
+
+// ---------------------------------------------------------------- conv bias gradient
+// db[f] = sum over (n, p) of dout * (out > 0)
+__global__ __launch_bounds__(256) void k_conv_bias(const float* __restrict__ dout, const float* __restrict__ out,
+                                                   int n, int F, int HW, float* __restrict__ db) {
+  __shared__ float sh[256];
+  const int f = blockIdx.x;
+  const long long total = (long long)n * HW;
+  float s = 0.f;
+  for (long long e = threadIdx.x; e < total; e += 256) {
+    const long long nn = e / HW, p = e - nn * HW;
+    const long long i = (nn * F + f) * HW + p;
+    s += out[i] > 0.f ? dout[i] : 0.f;
+  }
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) db[f] = s;
+}
+
+int conv_bias_grad(const float* dout, const float* out, int n, int F, int HW, float* db, hipStream_t st) {
+  if (n <= 0) return SQ_OK;
+  k_conv_bias<<<F, 256, 0, st>>>(dout, out, n, F, HW, db);
+  return launch_status("conv_bias_grad");
+}
+
+}  // namespace sq

@@ -1,0 +1,114 @@
+// Resolution squinting: gather replay frames and take k x k block means.
+// A workgroup owns `ry` output rows of one image: it streams the k*ry source pixel
+// rows (contiguous in the HWC frame) into LDS with 16-byte loads, then each thread
+// forms exact integer block sums from LDS and writes x = S / (255 k^2) - 0.5.
+#include "../common.h"
+#include "bf16.h"
+
+namespace sq {
+
+constexpr int kSquintThreads = 256;
+constexpr int kSquintLdsBytes = 16384;
+
+__global__ __launch_bounds__(kSquintThreads) void k_squint(
+    const uint8_t* __restrict__ src0, const uint8_t* __restrict__ src1, const int* __restrict__ idx,
+    const uint8_t* const* __restrict__ row_ptrs, int nsplit, int H, int W, int C, int k, int side, int ry, int vec16, int bf16_out, void* __restrict__ out,
+    long long out_row_stride) {
+  __shared__ __attribute__((aligned(16))) uint8_t tile[kSquintLdsBytes];
+  const int img = blockIdx.y;
+  const int y0 = blockIdx.x * ry;
+  const uint8_t* src;
+  long long row;
+  if (row_ptrs) {
+    src = row_ptrs[img];
+    row = 0;
+  } else if (img < nsplit) {
+    src = src0;
+    row = idx ? idx[img] : img;
+  } else {
+    src = src1;
+    row = idx[img - nsplit];
+  }
+  const long long frame_bytes = (long long)H * W * C;
+  const long long chunk_off = (long long)y0 * k * W * C;
+  const int chunk_bytes = ry * k * W * C;
+  const uint8_t* g = src + row * frame_bytes + chunk_off;
+  if (vec16) {
+    const uint4* g4 = reinterpret_cast<const uint4*>(g);
+    uint4* t4 = reinterpret_cast<uint4*>(tile);
+    for (int i = threadIdx.x; i < chunk_bytes / 16; i += kSquintThreads) t4[i] = g4[i];
+  } else {
+    for (int i = threadIdx.x; i < chunk_bytes; i += kSquintThreads) tile[i] = g[i];
+  }
+  __syncthreads();
+  const int n_out = C * ry * side;
+  const float scale = (float)(255 * k * k);
+  for (int o = threadIdx.x; o < n_out; o += kSquintThreads) {
+    const int x = o % side;
+    const int yl = (o / side) % ry;
+    const int c = o / (side * ry);
+    int s = 0;
+    for (int i = 0; i < k; ++i) {
+      const uint8_t* p = tile + ((yl * k + i) * W + x * k) * C + c;
+      for (int j = 0; j < k; ++j) s += p[j * C];
+    }
+    const float v = (float)s / scale - 0.5f;
+    const long long oi = (long long)img * out_row_stride + ((long long)c * side + y0 + yl) * side + x;
+    if (bf16_out)
+      reinterpret_cast<uint16_t*>(out)[oi] = bf16_bits(v);
+    else
+      reinterpret_cast<float*>(out)[oi] = v;
+  }
+}
+
+static int squint_rows_per_chunk(int W, int C, int k, int side) {
+  const int row_bytes = k * W * C;
+  int ry = side;
+  // halve (keeping ry a divisor of side) while the chunk exceeds the LDS tile or
+  // while halves would still carry >= 2 KB each: many small workgroups keep
+  // enough loads in flight
+  while (ry % 2 == 0 && (ry * row_bytes > kSquintLdsBytes || (ry / 2) * row_bytes >= 2048)) ry /= 2;
+  if (ry * row_bytes > kSquintLdsBytes) ry = 1;
+  return ry;
+}
+
+int squint_ok(int H, int W, int C, int k) {
+  const int side = H / k;
+  return (k * W * C) <= kSquintLdsBytes && side * k == H && (W / k) == side && side <= 64;
+}
+
+static int launch(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
+                  int n, int H, int W, int C, int k, int bf16_out, void* out, long long out_row_stride,
+                  hipStream_t st) {
+  const int side = H / k;
+  const int ry = squint_rows_per_chunk(W, C, k, side);
+  const long long chunk_bytes = (long long)ry * k * W * C;
+  const long long frame_bytes = (long long)H * W * C;
+  // per-row pointers (serving) are only known on the device: take the byte path
+  const int vec16 = rows == nullptr && (chunk_bytes % 16 == 0) && (frame_bytes % 16 == 0) &&
+                    ((uintptr_t)s0 % 16 == 0) && (s1 == nullptr || (uintptr_t)s1 % 16 == 0);
+  dim3 grid(side / ry, n);
+  k_squint<<<grid, kSquintThreads, 0, st>>>(s0, s1, idx, rows, nsplit, H, W, C, k, side, ry, vec16, bf16_out,
+                                            out, out_row_stride);
+  return launch_status("squint");
+}
+
+int launch_squint(const uint8_t* frames, const int* idx, int n, int H, int W, int C, int k, int bf16_out,
+                  void* out, long long out_row_stride, hipStream_t st) {
+  if (n == 0) return SQ_OK;
+  return launch(frames, nullptr, idx, nullptr, n, n, H, W, C, k, bf16_out, out, out_row_stride, st);
+}
+
+int launch_squint_pair(const uint8_t* obs, const uint8_t* next_obs, const int* idx, int B, int H, int W, int C,
+                       int k, float* out, hipStream_t st) {
+  const int side = H / k;
+  return launch(obs, next_obs, idx, nullptr, B, 2 * B, H, W, C, k, 0, out, (long long)C * side * side, st);
+}
+
+int launch_squint_rows(const uint8_t* const* rows, int n, int H, int W, int C, int k, float* out, hipStream_t st) {
+  if (n == 0) return SQ_OK;
+  const int side = H / k;
+  return launch(nullptr, nullptr, nullptr, rows, n, n, H, W, C, k, 0, out, (long long)C * side * side, st);
+}
+
+}  // namespace sq

@@ -1,0 +1,117 @@
+// Dimension checks and the canonical flat parameter layout.
+//
+// Order: encoder convs {W[F, Cin, 3, 3], b}; critic projection {W[proj, flat],
+// b, ln gain, ln shift}; twin critics q1, q2 each {l1 W[hidden, proj+P+A], b,
+// gain, shift; l2 W[hidden, hidden], b, gain, shift; out W[atoms, hidden], b};
+// actor projection (critic projection shapes); actor {l1 W[hidden, proj+P], ...,
+// out W[2A, hidden], b}; log alpha.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "common.h"
+
+namespace sq {
+
+static thread_local char g_err[512];
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+const char* last_error() { return g_err; }
+
+int make_net(const sq_dims* d, Net* n) {
+  if (!d) { set_error("dims is NULL"); return SQ_EINVAL; }
+  if (d->C <= 0 || d->H <= 0 || d->W <= 0 || d->k <= 0 || d->H % d->k || d->W % d->k || d->H != d->W) {
+    set_error("bad frame dims C=%d H=%d W=%d k=%d (need square frames with H %% k == 0)", d->C, d->H, d->W, d->k);
+    return SQ_EINVAL;
+  }
+  if (d->n_conv < 1 || d->n_conv > 4 || d->F <= 0 || d->proj <= 0 || d->hidden <= 0 || d->proprio < 0 ||
+      d->action <= 0 || d->atoms < 2) {
+    set_error("bad network dims n_conv=%d F=%d proj=%d hidden=%d atoms=%d proprio=%d action=%d", d->n_conv, d->F,
+              d->proj, d->hidden, d->atoms, d->proprio, d->action);
+    return SQ_EINVAL;
+  }
+  if (d->proj > 1024 || d->hidden > 1024 || d->atoms > 256) {
+    set_error("widths above the kernel limits (proj, hidden <= 1024, atoms <= 256)");
+    return SQ_EINVAL;
+  }
+  if (!(d->v_max > d->v_min)) { set_error("need v_max > v_min"); return SQ_EINVAL; }
+  if (!squint_ok(d->H, d->W, d->C, d->k)) {
+    set_error("frame geometry %dx%dx%d / k=%d exceeds the squint kernel's tile", d->H, d->W, d->C, d->k);
+    return SQ_EINVAL;
+  }
+  n->d = *d;
+  n->side = d->H / d->k;
+  int s = (n->side - 3) / 2 + 1;
+  if (n->side < 3 || s < 1) { set_error("squinted side %d too small", n->side); return SQ_EINVAL; }
+  n->conv_side[0] = s;
+  for (int i = 1; i < d->n_conv; ++i) {
+    s -= 2;
+    if (s < 1) { set_error("conv stack too deep for a %d x %d input", n->side, n->side); return SQ_EINVAL; }
+    n->conv_side[i] = s;
+  }
+  n->flat = d->F * s * s;
+  n->cin_critic = d->proj + d->proprio + d->action;
+  n->cin_actor = d->proj + d->proprio;
+  n->img = d->C * n->side * n->side;
+  return SQ_OK;
+}
+
+void make_layout(const Net& n, Layout* L) {
+  const sq_dims& d = n.d;
+  long long off = 0;
+  int t = 0;
+  auto take = [&](long long count) {
+    L->tensor_off[t++] = off;
+    const long long o = off;
+    off += count;
+    return o;
+  };
+  L->enc_begin = 0;
+  int cin = d.C;
+  for (int i = 0; i < d.n_conv; ++i) {
+    L->conv_W[i] = take((long long)d.F * cin * 9);
+    L->conv_b[i] = take(d.F);
+    cin = d.F;
+  }
+  L->enc_end = L->critic_begin = off;
+  auto dense = [&](int out, int in) {
+    Dense x;
+    x.out = out;
+    x.in = in;
+    x.W = take((long long)out * in);
+    x.b = take(out);
+    x.g = take(out);
+    x.beta = take(out);
+    return x;
+  };
+  auto head = [&](int out, int in) {
+    Head x;
+    x.out = out;
+    x.in = in;
+    x.W = take((long long)out * in);
+    x.b = take(out);
+    return x;
+  };
+  L->ctrunk = dense(d.proj, n.flat);
+  for (int q = 0; q < 2; ++q) {
+    L->q[q].l1 = dense(d.hidden, n.cin_critic);
+    L->q[q].l2 = dense(d.hidden, d.hidden);
+    L->q[q].out = head(d.atoms, d.hidden);
+  }
+  L->critic_end = L->actor_begin = off;
+  L->atrunk = dense(d.proj, n.flat);
+  L->al1 = dense(d.hidden, n.cin_actor);
+  L->al2 = dense(d.hidden, d.hidden);
+  L->aout = head(2 * d.action, d.hidden);
+  L->actor_end = off;
+  L->log_alpha = take(1);
+  L->total = off;
+  L->n_tensors = t;
+  L->tensor_off[t] = off;
+}
+
+}  // namespace sq

@@ -1,0 +1,300 @@
+// Network passes composed from the kernels (see ops.h).
+//
+// Linear layers keep torch's layout, W [out, in] row-major, so
+//   forward      Y = X W^T + b            gemm(A = X,    B(c, k) = W[c][k])
+//   input grad   dX = dY W                gemm(A = dY,   B(c, k) = W[k][c])
+//   weight grad  dW = dY^T X              gemm(A(r, k) = dY[k][r], B(c, k) = X[k][c])
+// The twin critics run as batch 2 of the same launch (twin parameter blocks
+// are a fixed stride apart in the flat vector).
+#include "ops.h"
+
+#include <algorithm>
+
+namespace sq {
+
+static int linear_fwd(int bf16, int n, int out, int in, int batch, const float* X, long long ldx, long long szx,
+                      const float* W, const float* b, long long szw, float* Y, long long ldy, long long szy,
+                      hipStream_t st) {
+  MatArg A{X, ldx, 1, szx};
+  MatArg Bm{W, in, 1, szw};
+  OutArg C{Y, ldy, szy, b, szw, 0, 0};
+  return gemm(bf16, n, out, in, batch, A, Bm, C, nullptr, 0, st);
+}
+
+static int linear_dw(int bf16, int n, int out, int in, int batch, const float* dY, long long lddy, long long szdy,
+                     const float* X, long long ldx, long long szx, float* dW, long long ldw, long long szw,
+                     float* split, hipStream_t st) {
+  MatArg A{dY, 1, lddy, szdy};
+  MatArg Bm{X, 1, ldx, szx};
+  OutArg C{dW, ldw, szw, nullptr, 0, 0, 0};
+  return gemm(bf16, out, in, n, batch, A, Bm, C, split, split ? kSplitFloats : 0, st);
+}
+
+// dX[:, 0:cols] (+)= dY W[:, 0:cols]; W given at its first wanted column, row stride ldw
+static int linear_dx(int bf16, int n, int out, int cols, int batch, const float* dY, long long lddy, long long szdy,
+                     const float* W, long long ldw, long long szw, float* dX, long long lddx, long long szdx,
+                     int accumulate, hipStream_t st) {
+  MatArg A{dY, lddy, 1, szdy};
+  MatArg Bm{W, 1, ldw, szw};
+  OutArg C{dX, lddx, szdx, nullptr, 0, accumulate, 0};
+  return gemm(bf16, n, cols, out, batch, A, Bm, C, nullptr, 0, st);
+}
+
+// ---------------------------------------------------------------- encoder
+void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
+  const sq_dims& d = net.d;
+  for (int i = 0; i < 4; ++i) e->h[i] = nullptr;
+  for (int i = 0; i < d.n_conv; ++i)
+    e->h[i] = b.take<float>((size_t)n * d.F * net.conv_side[i] * net.conv_side[i]);
+  e->dh[0] = e->dh[1] = nullptr;
+  e->split = nullptr;
+  if (with_bwd) {
+    const size_t big = (size_t)n * d.F * net.conv_side[0] * net.conv_side[0];
+    e->dh[0] = b.take<float>(big);
+    e->dh[1] = b.take<float>(big);
+    e->split = b.take<float>(kSplitFloats);
+  }
+}
+
+int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
+                    const EncBufs& e, hipStream_t st) {
+  const sq_dims& d = net.d;
+  const float* in = x;
+  int cin = d.C, hs = net.side;
+  for (int i = 0; i < d.n_conv; ++i) {
+    SQ_TRY(conv_fwd(bf16, in, n, cin, hs, i ? 1 : 2, ep + L.conv_W[i], ep + L.conv_b[i], d.F, e.h[i], st));
+    in = e.h[i];
+    cin = d.F;
+    hs = net.conv_side[i];
+  }
+  return SQ_OK;
+}
+
+int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
+                     const float* dfeat, const EncBufs& e, float* dep, hipStream_t st) {
+  const sq_dims& d = net.d;
+  const float* dh = dfeat;
+  for (int i = d.n_conv - 1; i >= 0; --i) {
+    const float* in = i ? e.h[i - 1] : x;
+    const int cin = i ? d.F : d.C;
+    const int hin = i ? net.conv_side[i - 1] : net.side;
+    const int hw = net.conv_side[i] * net.conv_side[i];
+    SQ_TRY(conv_dw(bf16, in, n, cin, hin, i ? 1 : 2, dh, e.h[i], d.F, dep + L.conv_W[i], e.split, kSplitFloats, st));
+    SQ_TRY(conv_bias_grad(dh, e.h[i], n, d.F, hw, dep + L.conv_b[i], st));
+    if (i > 0) {
+      float* dx = e.dh[i & 1];
+      SQ_TRY(conv_dx(bf16, dh, e.h[i], n, d.F, hin, ep + L.conv_W[i], d.F, dx, st));
+      dh = dx;
+    }
+  }
+  return SQ_OK;
+}
+
+// ---------------------------------------------------------------- critic
+void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic;
+  const int wmax = std::max(std::max(H, P), N);
+  c->pre = b.take<float>((size_t)2 * n * wmax);
+  c->X1 = b.take<float>((size_t)n * cin);
+  c->t.xhat = b.take<float>((size_t)n * P);
+  c->t.rstd = b.take<float>(n);
+  c->l1.xhat = b.take<float>((size_t)2 * n * H);
+  c->l1.rstd = b.take<float>((size_t)2 * n);
+  c->l2.xhat = b.take<float>((size_t)2 * n * H);
+  c->l2.rstd = b.take<float>((size_t)2 * n);
+  c->g1 = b.take<float>((size_t)2 * n * H);
+  c->g2 = b.take<float>((size_t)2 * n * H);
+  c->dA = c->dB = c->dX1 = c->part_t = c->part_l1 = c->part_l2 = c->part_out = c->split = nullptr;
+  if (with_bwd) {
+    const int pr = ln_bwd_partial_rows(n);
+    const int w = std::max(H, P);
+    c->dA = b.take<float>((size_t)2 * n * w);
+    c->dB = b.take<float>((size_t)2 * n * w);
+    c->dX1 = b.take<float>((size_t)n * cin);
+    c->part_t = b.take<float>((size_t)3 * pr * P);
+    c->part_l1 = b.take<float>((size_t)2 * 3 * pr * H);
+    c->part_l2 = b.take<float>((size_t)2 * 3 * pr * H);
+    c->part_out = b.take<float>((size_t)2 * pr * N);
+    c->split = b.take<float>(kSplitFloats);
+  }
+}
+
+int critic_forward(const Net& net, int bf16, const float* cp, const Layout& L, const float* feat, long long ld_feat,
+                   const float* s, long long ld_s, const float* a, long long ld_a, int n, float* logits,
+                   const CriticBufs& c, hipStream_t st) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic;
+  const long long c0 = L.critic_begin;
+  const long long tw = L.q[1].l1.W - L.q[0].l1.W;
+  const Dense& T = L.ctrunk;
+  const Twin& q = L.q[0];
+  SQ_TRY(linear_fwd(bf16, n, P, net.flat, 1, feat, ld_feat, 0, cp + (T.W - c0), cp + (T.b - c0), 0, c.pre, P, 0, st));
+  SQ_TRY(ln_act_fwd(c.pre, P, 0, n, P, 1, cp + (T.g - c0), cp + (T.beta - c0), 0, 1, c.X1, cin, 0, c.t.xhat, c.t.rstd,
+                    s, ld_s, d.proprio, a, ld_a, d.action, st));
+  SQ_TRY(linear_fwd(bf16, n, H, cin, 2, c.X1, cin, 0, cp + (q.l1.W - c0), cp + (q.l1.b - c0), tw, c.pre, H,
+                    (long long)n * H, st));
+  SQ_TRY(ln_act_fwd(c.pre, H, (long long)n * H, n, H, 2, cp + (q.l1.g - c0), cp + (q.l1.beta - c0), tw, 0, c.g1, H,
+                    (long long)n * H, c.l1.xhat, c.l1.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
+  SQ_TRY(linear_fwd(bf16, n, H, H, 2, c.g1, H, (long long)n * H, cp + (q.l2.W - c0), cp + (q.l2.b - c0), tw, c.pre, H,
+                    (long long)n * H, st));
+  SQ_TRY(ln_act_fwd(c.pre, H, (long long)n * H, n, H, 2, cp + (q.l2.g - c0), cp + (q.l2.beta - c0), tw, 0, c.g2, H,
+                    (long long)n * H, c.l2.xhat, c.l2.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
+  return linear_fwd(bf16, n, N, H, 2, c.g2, H, (long long)n * H, cp + (q.out.W - c0), cp + (q.out.b - c0), tw,
+                    logits, N, (long long)n * N, st);
+}
+
+int critic_backward(const Net& net, int bf16, const float* cp, const Layout& L, const float* feat, long long ld_feat,
+                    const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat, float* daction,
+                    hipStream_t st) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic, A = d.action;
+  const long long c0 = L.critic_begin;
+  const long long tw = L.q[1].l1.W - L.q[0].l1.W;
+  const long long nH = (long long)n * H, nN = (long long)n * N;
+  const Dense& T = L.ctrunk;
+  const Twin& q = L.q[0];
+  const bool params = dcp != nullptr;
+  const bool trunk = params || dfeat != nullptr;
+  // output heads
+  if (params) {
+    SQ_TRY(linear_dw(bf16, n, N, H, 2, dlogits, N, nN, c.g2, H, nH, dcp + (q.out.W - c0), H, tw, c.split, st));
+    SQ_TRY(col_partials(dlogits, N, nN, n, N, 2, c.part_out, st));
+  }
+  SQ_TRY(linear_dx(bf16, n, N, H, 2, dlogits, N, nN, cp + (q.out.W - c0), H, tw, c.dA, H, nH, 0, st));
+  // second hidden layer
+  SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g2, H, nH, c.l2.xhat, c.l2.rstd, cp + (q.l2.g - c0), tw, n, H, 2, 0, c.dB,
+                    params ? c.part_l2 : nullptr, st));
+  if (params)
+    SQ_TRY(linear_dw(bf16, n, H, H, 2, c.dB, H, nH, c.g1, H, nH, dcp + (q.l2.W - c0), H, tw, c.split, st));
+  SQ_TRY(linear_dx(bf16, n, H, H, 2, c.dB, H, nH, cp + (q.l2.W - c0), H, tw, c.dA, H, nH, 0, st));
+  // first hidden layer
+  SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g1, H, nH, c.l1.xhat, c.l1.rstd, cp + (q.l1.g - c0), tw, n, H, 2, 0, c.dB,
+                    params ? c.part_l1 : nullptr, st));
+  if (params)
+    SQ_TRY(linear_dw(bf16, n, H, cin, 2, c.dB, H, nH, c.X1, cin, 0, dcp + (q.l1.W - c0), cin, tw, c.split, st));
+  const float* W1a = cp + (L.q[0].l1.W - c0);
+  const float* W1b = cp + (L.q[1].l1.W - c0);
+  if (trunk) {
+    // the shared input [h | s | a] collects the gradient of both twins
+    SQ_TRY(linear_dx(bf16, n, H, cin, 1, c.dB, H, 0, W1a, cin, 0, c.dX1, cin, 0, 0, st));
+    SQ_TRY(linear_dx(bf16, n, H, cin, 1, c.dB + nH, H, 0, W1b, cin, 0, c.dX1, cin, 0, 1, st));
+    if (daction)
+      SQ_TRY_HIP(hipMemcpy2DAsync(daction, (size_t)A * 4, c.dX1 + P + d.proprio, (size_t)cin * 4, (size_t)A * 4, n,
+                                  hipMemcpyDeviceToDevice, st));
+  } else if (daction) {
+    const int a0 = P + d.proprio;
+    SQ_TRY(linear_dx(bf16, n, H, A, 1, c.dB, H, 0, W1a + a0, cin, 0, daction, A, 0, 0, st));
+    SQ_TRY(linear_dx(bf16, n, H, A, 1, c.dB + nH, H, 0, W1b + a0, cin, 0, daction, A, 0, 1, st));
+  }
+  if (trunk) {
+    SQ_TRY(ln_act_bwd(c.dX1, cin, 0, c.X1, cin, 0, c.t.xhat, c.t.rstd, cp + (T.g - c0), 0, n, P, 1, 1, c.dA,
+                      params ? c.part_t : nullptr, st));
+    if (params)
+      SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, c.dA, P, 0, feat, ld_feat, 0, dcp + (T.W - c0), net.flat, 0, c.split,
+                       st));
+    if (dfeat)
+      SQ_TRY(linear_dx(bf16, n, P, net.flat, 1, c.dA, P, 0, cp + (T.W - c0), net.flat, 0, dfeat, net.flat, 0, 0, st));
+  }
+  if (params) {
+    const int pr = ln_bwd_partial_rows(n);
+    ColSegs s{};
+    s.n = 4;
+    s.s[0] = ColSeg{c.part_out, pr, N, 1, 2, {dcp + (q.out.b - c0), nullptr, nullptr}, tw, 0};
+    s.s[1] = ColSeg{c.part_l2, pr, H, 3, 2, {dcp + (q.l2.b - c0), dcp + (q.l2.g - c0), dcp + (q.l2.beta - c0)}, tw, 0};
+    s.s[2] = ColSeg{c.part_l1, pr, H, 3, 2, {dcp + (q.l1.b - c0), dcp + (q.l1.g - c0), dcp + (q.l1.beta - c0)}, tw, 0};
+    s.s[3] = ColSeg{c.part_t, pr, P, 3, 1, {dcp + (T.b - c0), dcp + (T.g - c0), dcp + (T.beta - c0)}, 0, 0};
+    SQ_TRY(colsum(s, st));
+  }
+  return SQ_OK;
+}
+
+// ---------------------------------------------------------------- actor
+void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor;
+  const int w = std::max(H, P);
+  a->pre = b.take<float>((size_t)n * std::max(w, 2 * A));
+  a->X1 = b.take<float>((size_t)n * cin);
+  a->t.xhat = b.take<float>((size_t)n * P);
+  a->t.rstd = b.take<float>(n);
+  a->l1.xhat = b.take<float>((size_t)n * H);
+  a->l1.rstd = b.take<float>(n);
+  a->l2.xhat = b.take<float>((size_t)n * H);
+  a->l2.rstd = b.take<float>(n);
+  a->g1 = b.take<float>((size_t)n * H);
+  a->g2 = b.take<float>((size_t)n * H);
+  a->head = b.take<float>((size_t)n * 2 * A);
+  a->save = b.take<float>((size_t)n * 3 * A);
+  a->dA = a->dB = a->dX1 = a->dhead = a->part_t = a->part_l1 = a->part_l2 = a->part_out = a->split = nullptr;
+  if (with_bwd) {
+    const int pr = ln_bwd_partial_rows(n);
+    a->dA = b.take<float>((size_t)n * w);
+    a->dB = b.take<float>((size_t)n * w);
+    a->dX1 = b.take<float>((size_t)n * P);
+    a->dhead = b.take<float>((size_t)n * 2 * A);
+    a->part_t = b.take<float>((size_t)3 * pr * P);
+    a->part_l1 = b.take<float>((size_t)3 * pr * H);
+    a->part_l2 = b.take<float>((size_t)3 * pr * H);
+    a->part_out = b.take<float>((size_t)pr * 2 * A);
+    a->split = b.take<float>(kSplitFloats);
+  }
+}
+
+int actor_forward(const Net& net, int bf16, const float* ap, const Layout& L, const float* feat, long long ld_feat,
+                  const float* s, long long ld_s, const float* eps, int n, float lo, float hi, float* action,
+                  float* logp, const ActorBufs& a, hipStream_t st) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor;
+  const long long a0 = L.actor_begin;
+  const Dense& T = L.atrunk;
+  SQ_TRY(linear_fwd(bf16, n, P, net.flat, 1, feat, ld_feat, 0, ap + (T.W - a0), ap + (T.b - a0), 0, a.pre, P, 0, st));
+  SQ_TRY(ln_act_fwd(a.pre, P, 0, n, P, 1, ap + (T.g - a0), ap + (T.beta - a0), 0, 1, a.X1, cin, 0, a.t.xhat, a.t.rstd,
+                    s, ld_s, d.proprio, nullptr, 0, 0, st));
+  SQ_TRY(linear_fwd(bf16, n, H, cin, 1, a.X1, cin, 0, ap + (L.al1.W - a0), ap + (L.al1.b - a0), 0, a.pre, H, 0, st));
+  SQ_TRY(ln_act_fwd(a.pre, H, 0, n, H, 1, ap + (L.al1.g - a0), ap + (L.al1.beta - a0), 0, 0, a.g1, H, 0, a.l1.xhat,
+                    a.l1.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
+  SQ_TRY(linear_fwd(bf16, n, H, H, 1, a.g1, H, 0, ap + (L.al2.W - a0), ap + (L.al2.b - a0), 0, a.pre, H, 0, st));
+  SQ_TRY(ln_act_fwd(a.pre, H, 0, n, H, 1, ap + (L.al2.g - a0), ap + (L.al2.beta - a0), 0, 0, a.g2, H, 0, a.l2.xhat,
+                    a.l2.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
+  SQ_TRY(linear_fwd(bf16, n, 2 * A, H, 1, a.g2, H, 0, ap + (L.aout.W - a0), ap + (L.aout.b - a0), 0, a.head, 2 * A, 0,
+                    st));
+  if (eps) return tanh_gauss_fwd(a.head, n, A, eps, lo, hi, action, logp, a.save, st);
+  return mean_action(a.head, n, A, action, st);
+}
+
+int actor_backward(const Net& net, int bf16, const float* ap, const Layout& L, const float* feat, long long ld_feat,
+                   const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
+                   const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
+                   hipStream_t st) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor;
+  const long long a0 = L.actor_begin;
+  const Dense& T = L.atrunk;
+  SQ_TRY(tanh_gauss_bwd(a.save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, n, A, a.dhead, st));
+  SQ_TRY(linear_dw(bf16, n, 2 * A, H, 1, a.dhead, 2 * A, 0, a.g2, H, 0, dap + (L.aout.W - a0), H, 0, a.split, st));
+  SQ_TRY(col_partials(a.dhead, 2 * A, 0, n, 2 * A, 1, a.part_out, st));
+  SQ_TRY(linear_dx(bf16, n, 2 * A, H, 1, a.dhead, 2 * A, 0, ap + (L.aout.W - a0), H, 0, a.dA, H, 0, 0, st));
+  SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g2, H, 0, a.l2.xhat, a.l2.rstd, ap + (L.al2.g - a0), 0, n, H, 1, 0, a.dB, a.part_l2,
+                    st));
+  SQ_TRY(linear_dw(bf16, n, H, H, 1, a.dB, H, 0, a.g1, H, 0, dap + (L.al2.W - a0), H, 0, a.split, st));
+  SQ_TRY(linear_dx(bf16, n, H, H, 1, a.dB, H, 0, ap + (L.al2.W - a0), H, 0, a.dA, H, 0, 0, st));
+  SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g1, H, 0, a.l1.xhat, a.l1.rstd, ap + (L.al1.g - a0), 0, n, H, 1, 0, a.dB, a.part_l1,
+                    st));
+  SQ_TRY(linear_dw(bf16, n, H, cin, 1, a.dB, H, 0, a.X1, cin, 0, dap + (L.al1.W - a0), cin, 0, a.split, st));
+  // only the projection columns of the actor input need a gradient
+  SQ_TRY(linear_dx(bf16, n, H, P, 1, a.dB, H, 0, ap + (L.al1.W - a0), cin, 0, a.dX1, P, 0, 0, st));
+  SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, cin, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), 0, n, P, 1, 1, a.dA, a.part_t,
+                    st));
+  SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, a.dA, P, 0, feat, ld_feat, 0, dap + (T.W - a0), net.flat, 0, a.split, st));
+  const int pr = ln_bwd_partial_rows(n);
+  ColSegs s{};
+  s.n = 4;
+  s.s[0] = ColSeg{a.part_out, pr, 2 * A, 1, 1, {dap + (L.aout.b - a0), nullptr, nullptr}, 0, 0};
+  s.s[1] = ColSeg{a.part_l2, pr, H, 3, 1, {dap + (L.al2.b - a0), dap + (L.al2.g - a0), dap + (L.al2.beta - a0)}, 0, 0};
+  s.s[2] = ColSeg{a.part_l1, pr, H, 3, 1, {dap + (L.al1.b - a0), dap + (L.al1.g - a0), dap + (L.al1.beta - a0)}, 0, 0};
+  s.s[3] = ColSeg{a.part_t, pr, P, 3, 1, {dap + (T.b - a0), dap + (T.g - a0), dap + (T.beta - a0)}, 0, 0};
+  return colsum(s, st);
+}
+
+}  // namespace sq

@@ -1,0 +1,73 @@
+// Host-side composition of the network passes from the kernels: encoder,
+// twin critics and actor, forward and backward, plus their workspace plans.
+#pragma once
+
+#include "common.h"
+
+namespace sq {
+
+constexpr size_t kSplitFloats = (size_t)4 << 20;   // split-K scratch (16 MB)
+
+struct EncBufs {
+  float* h[4];        // post-ReLU conv outputs [n][F][s_i][s_i]; h[n_conv-1] is the feature
+  float* dh[2];       // ping-pong input gradients
+  float* split;       // split-K scratch, kSplitFloats
+};
+void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd);
+int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
+                    const EncBufs& e, hipStream_t st);
+int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
+                     const float* dfeat, const EncBufs& e, float* dep, hipStream_t st);
+
+struct DenseSave { float* xhat; float* rstd; };
+struct CriticBufs {
+  float* pre;         // [2][n][max(proj, hidden, atoms)]
+  float* X1;          // [n][proj + P + A]  = [h | s | a]
+  DenseSave t, l1, l2;
+  float* g1; float* g2;   // [2][n][hidden]
+  float* dA; float* dB;   // [2][n][max(hidden, proj)]
+  float* dX1;             // [n][proj + P + A]
+  float* part_t; float* part_l1; float* part_l2; float* part_out;
+  float* split;
+};
+void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd);
+// cp: base of a critic block (online params + critic_begin, or the target vector)
+int critic_forward(const Net& net, int bf16, const float* cp, const Layout& L, const float* feat, long long ld_feat,
+                   const float* s, long long ld_s, const float* a, long long ld_a, int n, float* logits,
+                   const CriticBufs& c, hipStream_t st);
+// dcp / dfeat / daction nullable; dcp is laid out like the critic block
+int critic_backward(const Net& net, int bf16, const float* cp, const Layout& L, const float* feat, long long ld_feat,
+                    const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat, float* daction,
+                    hipStream_t st);
+
+struct ActorBufs {
+  float* pre;          // [n][max(proj, hidden)]
+  float* X1;           // [n][proj + P] = [h | s]
+  DenseSave t, l1, l2;
+  float* g1; float* g2;  // [n][hidden]
+  float* head;         // [n][2A]
+  float* save;         // [n][3A]
+  float* dA; float* dB;  // [n][max(hidden, proj)]
+  float* dX1;          // [n][proj]
+  float* dhead;        // [n][2A]
+  float* part_t; float* part_l1; float* part_l2; float* part_out;
+  float* split;
+};
+void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd);
+// ap: base of the actor block; eps nullable (mean action)
+int actor_forward(const Net& net, int bf16, const float* ap, const Layout& L, const float* feat, long long ld_feat,
+                  const float* s, long long ld_s, const float* eps, int n, float lo, float hi, float* action,
+                  float* logp, const ActorBufs& a, hipStream_t st);
+int actor_backward(const Net& net, int bf16, const float* ap, const Layout& L, const float* feat, long long ld_feat,
+                   const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
+                   const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
+                   hipStream_t st);
+
+// act(): squint -> encoder -> actor, forward only
+struct ActBufs {
+  float* x; EncBufs e; ActorBufs a; float* noise;
+};
+void plan_act(const Net& net, int n, Bump& b, ActBufs* w);
+size_t act_bytes_per_obs(const Net& net);
+
+}  // namespace sq

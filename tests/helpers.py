@@ -1,0 +1,59 @@
+"""Shared helpers of the GPU parity tests (inputs come from the synthetic
+generators; expected values only from oracle/)."""
+import numpy as np
+import torch
+
+from oracle import layout as olayout
+from paper_2602_21203_amd import configs, synthetic
+
+LOSS_RTOL, LOSS_ATOL = 1e-4, 1e-6      # losses: |d| <= 1e-4 |ref| + 1e-6
+GRAD_RTOL = 1e-3                       # gradients: ||d||_2 <= 1e-3 ||ref||_2 per tensor
+
+
+def cfg(name):
+    return configs.CONFIGS[name]
+
+
+def odims(name):
+    return olayout.dims(**cfg(name))
+
+
+def table(name):
+    return [(n, o, s) for n, (o, s) in olayout.offsets(odims(name))[0].items()]
+
+
+def params(name, seed=1):
+    return synthetic.init_params(table(name), seed=seed)
+
+
+def np_replay(rep):
+    out = {k: (v.cpu().numpy() if torch.is_tensor(v) else v) for k, v in rep.items()}
+    return out
+
+
+def rel_norm(got, ref):
+    got, ref = np.asarray(got, np.float64), np.asarray(ref, np.float64)
+    return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30))
+
+
+def assert_loss(got, ref, what=""):
+    assert abs(got - ref) <= LOSS_RTOL * abs(ref) + LOSS_ATOL, f"{what}: got {got!r} ref {ref!r}"
+
+
+def assert_grads_per_tensor(got_flat, ref_flat, name, base, lo, hi, rtol=GRAD_RTOL):
+    """Per-tensor relative-norm check of flat gradient slices [lo, hi) (offsets absolute)."""
+    tab = olayout.offsets(odims(name))[0]
+    bad = []
+    worst = 0.0
+    for n, (o, s) in tab.items():
+        if o < lo or o >= hi:
+            continue
+        k = int(np.prod(s))
+        g = got_flat[o - base:o - base + k]
+        r = ref_flat[o - lo:o - lo + k]
+        e = rel_norm(g, r)
+        worst = max(worst, e)
+        if e > rtol:
+            bad.append((n, e))
+    assert not bad, f"gradient tensors over tolerance {rtol}: {bad}"
+    return worst

@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI: the library loads on a machine without a GPU,
+exports every declared entry point, validates arguments, and its parameter
+layout matches the oracle's independently built layout."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "squint.h")
+LIB = os.path.join(ROOT, "paper_2602_21203_amd", "libsquint.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libsquint.so not built")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^SQ_API\s+(?:const\s+)?\w+\*?\s+(\w+)\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared()
+    assert len(names) >= 25
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_layout_matches_oracle():
+    from oracle import layout
+    from paper_2602_21203_amd import _lib, configs
+    for name, cfg in configs.CONFIGS.items():
+        t, blocks = _lib.param_table(cfg)
+        d = layout.dims(**cfg)
+        ot, total = layout.offsets(d)
+        assert [(n, o, tuple(s)) for n, o, s in t] == [(n, o, tuple(s)) for n, (o, s) in ot.items()]
+        assert blocks == layout.blocks(d)
+    assert _lib.param_count(configs.FULL) == 1493335
+    assert _lib.param_count(configs.TINY) == 90563
+
+
+def test_invalid_dims_are_rejected_without_work():
+    from paper_2602_21203_amd import _lib, configs
+    bad = dict(configs.FULL, k=3)            # 64 is not a multiple of 3
+    with pytest.raises(_lib.SquintError, match="frame dims"):
+        _lib.param_count(bad)
+    with pytest.raises(_lib.SquintError):
+        _lib.param_count(dict(configs.FULL, atoms=1))
+    with pytest.raises(_lib.SquintError):
+        _lib.param_count(dict(configs.FULL, hidden=2048))
+    with pytest.raises(_lib.SquintError):
+        _lib.workspace_bytes(configs.FULL, 7, 10)
+    # null pointers / negative sizes: EINVAL before anything touches the device
+    d = _lib.make_dims(configs.FULL)
+    assert _lib.LIB.squint_downsample(ctypes.byref(d), None, None, 4, 0, None, None) == _lib.SQ_EINVAL
+    assert _lib.LIB.encoder_fwd(ctypes.byref(d), 0, None, None, -1, None, None, None) == _lib.SQ_EINVAL
+    assert _lib.LIB.sq_sample_indices(1, 0, 0, 10, None, None) == _lib.SQ_EINVAL
+    assert _lib.LIB.sac_update(None, None, 1, None, None) == _lib.SQ_EINVAL
+    assert _lib.LIB.act(None, None, None, 1, 0, 0, None, None) == _lib.SQ_EINVAL
+    assert b"NULL" in _lib.LIB.sq_last_error() or b"agent" in _lib.LIB.sq_last_error()
+
+
+def test_workspace_sizes_grow_with_rows():
+    from paper_2602_21203_amd import _lib, configs
+    for op in (0, 1, 2):
+        a = _lib.workspace_bytes(configs.FULL, op, 16)
+        b = _lib.workspace_bytes(configs.FULL, op, 512)
+        assert b > a > 0
+
+
+def test_missing_library_fails_loudly():
+    code = "import paper_2602_21203_amd._lib"
+    env = dict(os.environ, SQ_LIB_PATH="/nonexistent/libsquint.so")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True)
+    assert r.returncode != 0 and "missing" in r.stderr

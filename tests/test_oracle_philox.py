@@ -107,10 +107,10 @@ def test_gaussian_moments_and_ks():
 
 
 def test_box_muller_closed_form_points():
-    # u1 = ((w >> 8) + 0.5) 2^-24: for w0 >> 8 = 2^23 - 1, u1 = 1/2 - 2^-25;
-    # for w1 >> 8 = 0, u2 = 2^-25 so cos(2 pi u2) ~ 1.
-    w0 = np.array([(2 ** 23 - 1) << 8], dtype=np.uint32)
-    w1 = np.array([0], dtype=np.uint32)
-    u1 = 0.5 - 2.0 ** -25
-    want = np.sqrt(-2 * np.log(u1)) * np.cos(2 * np.pi * 2.0 ** -25)
+    # u = ((w >> 9) + 0.5) 2^-23: for w0 >> 9 = 2^22 - 1, u1 = 1/2 - 2^-24;
+    # for w1 >> 9 = 2^21 (and low bits set, which are dropped), u2 = 1/4 + 2^-24.
+    w0 = np.array([((2 ** 22 - 1) << 9) | 0x1FF], dtype=np.uint32)
+    w1 = np.array([(2 ** 21) << 9 | 0x155], dtype=np.uint32)
+    u1, u2 = 0.5 - 2.0 ** -24, 0.25 + 2.0 ** -24
+    want = np.sqrt(-2 * np.log(u1)) * np.cos(2 * np.pi * u2)
     assert philox.box_muller(w0, w1)[0] == pytest.approx(want, rel=1e-15)
