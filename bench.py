@@ -1,0 +1,203 @@
+#!/usr/bin/env python
+"""Throughput of the fused Squint SAC update on one MI355X.
+
+A step is one sac_update call of UTD (default 4) updates at batch 512 on the
+full-size network (64x64x9 uint8 frames squinted 4x, 3 convs of 32 channels,
+projection 256, twin 512-512 C51 critics with 101 atoms, 512-512 tanh-Gaussian
+actor), replayed from a captured HIP graph; replay rows are seeded synthetic
+frames resident in HBM (capacity 65,536 transitions).  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--prec bf16|fp32]
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic counts per update at the full-size network, batch B (see design notes)
+FULL = dict(C=9, H=64, W=64, k=4, n_conv=3, F=32, proj=256, hidden=512, atoms=101, proprio=12, action=6,
+            v_min=-20.0, v_max=20.0)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--prec", choices=["bf16", "fp32"], default="bf16")
+    ap.add_argument("--utd", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--capacity", type=int, default=65536)
+    ap.add_argument("--frame", type=int, default=64, help="source frame side (64: k=4, 128: k=8)")
+    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other-precision timing")
+    ap.add_argument("--kernel-reps", type=int, default=200)
+    return ap.parse_args()
+
+
+def cfg_for(frame):
+    c = dict(FULL)
+    c["H"] = c["W"] = frame
+    c["k"] = frame // 16
+    return c
+
+
+def time_updates(agent, rep, utd, steps, warmup):
+    import torch
+    stats = torch.empty((utd, 8), dtype=torch.float32, device="cuda")
+    for _ in range(warmup):
+        agent.sac_update(rep, utd, stats=stats)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(agent.stream)
+    for _ in range(steps):
+        agent.sac_update(rep, utd, stats=stats)
+    ev1.record(agent.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu = ev0.elapsed_time(ev1) / 1e3
+    s = stats.cpu().numpy()
+    return wall, gpu, s
+
+
+def squint_kernel_time(cfg, rep, B, reps):
+    """Average duration of the squint gather kernel (2B frames, as inside the
+    update) from HIP events on the stream it runs on."""
+    import torch
+
+    from paper_2602_21203_amd import api
+    idx = torch.randint(0, rep["obs"].shape[0], (2 * B,), dtype=torch.int32, device="cuda")
+    out = torch.empty((2 * B, cfg["C"], 16, 16), dtype=torch.float32, device="cuda")
+    for _ in range(10):
+        api.squint_downsample(cfg, rep["obs"], idx, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        api.squint_downsample(cfg, rep["obs"], idx, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def serve_latency(agent, cfg, n_req, seed=3):
+    """Closed-loop burst of n_req pools (sizes U{1..4096}) through the server."""
+    import numpy as np
+    import torch
+
+    from paper_2602_21203_amd import api, synthetic
+    rng = np.random.default_rng(seed)
+    pool = synthetic.frames(4096, cfg["H"], cfg["W"], cfg["C"], seed=11, device="cuda")
+    prop = torch.randn(4096, cfg["proprio"], device="cuda")
+    srv = api.Server(agent, mem_budget=16 << 30, max_batch_obs=8192, n_slots=4)
+    sizes = rng.integers(1, 4097, n_req)
+    t_sub = {}
+    t0 = time.monotonic()
+    for i, n in enumerate(sizes):
+        t_sub[i] = time.monotonic()
+        srv.submit(pool[:n], prop[:n], i, sample=True)
+    srv.drain()
+    t1 = time.monotonic()
+    lat = [srv.done[i] - t_sub[i] for i in range(n_req)]
+    srv.close()
+    lat.sort()
+    p = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+    return dict(p50_ms=p(0.5) * 1e3, p99_ms=p(0.99) * 1e3, obs_per_s=float(sizes.sum()) / (t1 - t0),
+                requests=int(n_req), mode="burst of pools U{1..4096}, 4 slots")
+
+
+def cpu_baseline(cfg, B, budget_s=20.0):
+    """The FP64 oracle timed on the host cores on a bounded sample of updates."""
+    import numpy as np
+    import torch
+
+    from oracle import layout as olayout
+    from oracle import sac
+    from paper_2602_21203_amd import synthetic
+    d = olayout.dims(**cfg)
+    table = [(n, o, s) for n, (o, s) in olayout.offsets(d)[0].items()]
+    params = synthetic.init_params(table, seed=1).astype(np.float64)
+    cpu = synthetic.replay(2048, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=0)
+    rep = {k: (v.numpy() if torch.is_tensor(v) else v) for k, v in cpu.items()}
+    st = sac.new_state(d, params)
+    hp = sac.hparams(d)
+    sac.sac_update(st, rep, d, hp, B)          # warm-up (not timed)
+    n, t0 = 0, time.perf_counter()
+    while n < 1 or (time.perf_counter() - t0 < budget_s and n < 20):
+        sac.sac_update(st, rep, d, hp, B)
+        n += 1
+        if time.perf_counter() - t0 > budget_s / 2 and n >= 2:
+            break
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return dict(value=n / dt, unit="updates/s", cores=int(cores), kind="oracle",
+                sample=f"{n} FP64 oracle updates at batch {B} (full network, 64x64x9 frames) after 1 warm-up")
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+
+    from paper_2602_21203_amd import _lib, api, synthetic
+    cfg = cfg_for(a.frame)
+    B = a.batch
+    torch.cuda.init()
+    rep = synthetic.replay(a.capacity, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=0,
+                           device="cuda")
+    table, _ = _lib.param_table(cfg)
+    params = synthetic.init_params(table, seed=1)
+    prec = _lib.SQ_BF16 if a.prec == "bf16" else _lib.SQ_F32
+    agent = api.Agent(cfg, params, B, prec=prec)
+    wall, gpu, stats = time_updates(agent, rep, a.utd, a.steps, a.warmup)
+    ups = a.utd * a.steps / wall
+    result = {
+        "metric": "SAC updates/sec at batch 512 (BF16 vs FP32, 1 GPU); act() p50/p99 latency",
+        "value": round(ups, 2), "unit": "updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(wall / a.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": a.prec, "data": "synthetic",
+        "config": {"workload": f"visual SAC update, full network, batch {B}, {a.frame}x{a.frame}x9 uint8 frames "
+                               f"squinted to 16x16, UTD {a.utd} per HIP-graph launch, replay {a.capacity} rows",
+                   "global_batch": B, "utd": a.utd, "precision": a.prec},
+        "gpu_event_updates_per_s": round(a.utd * a.steps / gpu, 2),
+        "final_stats": {n: float(v) for n, v in zip(_lib.STAT_NAMES, stats[-1])},
+    }
+    if not a.no_compare:
+        other = _lib.SQ_F32 if prec == _lib.SQ_BF16 else _lib.SQ_BF16
+        ag2 = api.Agent(cfg, params, B, prec=other)
+        w2, _, _ = time_updates(ag2, rep, a.utd, max(5, a.steps // 2), max(2, a.warmup // 2))
+        result["fp32_updates_per_s" if other == _lib.SQ_F32 else "bf16_updates_per_s"] = \
+            round(a.utd * max(5, a.steps // 2) / w2, 2)
+        ag2.close()
+    # roofline of the squint gather (HBM bound): frames read + FP32 images written
+    t_k = squint_kernel_time(cfg, rep, B, a.kernel_reps)
+    bytes_per_launch = 2 * B * (cfg["H"] * cfg["W"] * cfg["C"] + cfg["C"] * 16 * 16 * 4)
+    achieved = bytes_per_launch / t_k / 1e9
+    result["roofline"] = {"kernel": "k_squint (gather + 4x4 area sum of 2B frames)", "bound": "hbm",
+                          "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                          "frac": round(achieved / 8000.0, 4), "traffic": None,
+                          "avg_us": round(t_k * 1e6, 3), "algorithmic_bytes": bytes_per_launch}
+    if a.serve_requests > 0:
+        result["act_serving"] = serve_latency(agent, cfg, a.serve_requests)
+    agent.close()
+    if not a.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(cfg, B)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

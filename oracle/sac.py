@@ -169,10 +169,17 @@ def sac_update(state, replay, d, hp, batch, bf=False):
     stats = np.array([loss_c, loss_pi, loss_alpha, alpha_new, float(np.mean(-logp_t)),
                       float(np.mean(q_rep)), float(np.mean(m @ z)), 0.0])
     stats[7] = 0.0 if np.all(np.isfinite(stats[:7])) else 1.0
+    # magnitude of the terms each statistic averages: a mean of signed terms can
+    # sit near zero, so its rounding error scales with these, not with the mean
+    qa = 0.5 * (q[0] + q[1]) if actor_step else np.zeros(B)
+    stat_scale = np.array([abs(loss_c), float(np.mean(np.abs(alpha_new * logp_t) + np.abs(qa))),
+                           alpha * float(np.mean(np.abs(-logp_t - hp.target_entropy))), abs(alpha_new),
+                           float(np.mean(np.abs(logp_t))), float(np.mean(np.abs(q_rep))),
+                           float(np.mean(np.abs(m @ z)))])
     state.u = u + 1
     return dict(idx=idx, eps_next=eps_next, eps=eps, x=x, feat=feat, m=m, logits=logits,
                 dlogits=dlogits, g_enc_critic=g_ec, g_log_alpha=g_la, g_actor=g_actor,
-                stats=stats, actor_step=actor_step, a_next=a_n, logp_next=logp_n,
+                stats=stats, stat_scale=stat_scale, actor_step=actor_step, a_next=a_n, logp_next=logp_n,
                 a_t=a_t, logp_t=logp_t)
 
 

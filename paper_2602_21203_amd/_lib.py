@@ -39,6 +39,9 @@ class Replay(ctypes.Structure):
                [("capacity", c_int), ("size", c_int)]
 
 
+DONE_CB = ctypes.CFUNCTYPE(None, ctypes.c_ulonglong, ctypes.c_double, ctypes.c_void_p)
+
+
 class SquintError(RuntimeError):
     pass
 
@@ -70,6 +73,10 @@ def _load():
         "sac_update_eager": (c_int, [c_vp, P(Replay), c_int, c_vp, c_vp]),
         "act": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_ull, c_vp, c_vp]),
         "sq_agent_act_capacity": (c_int, [c_vp, P(c_int)]),
+        "sq_server_create": (c_int, [c_vp, c_size, c_int, c_int, P(c_vp)]),
+        "sq_server_submit": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_ull, c_vp, DONE_CB, c_vp]),
+        "sq_server_drain": (c_int, [c_vp]),
+        "sq_server_destroy": (c_int, [c_vp]),
         "sq_sample_indices": (c_int, [c_ull, ctypes.c_uint, c_int, c_int, c_vp, c_vp]),
         "sq_gaussian": (c_int, [c_ull, ctypes.c_uint, ctypes.c_uint, c_int, c_vp, c_vp]),
     }

@@ -237,3 +237,51 @@ class Agent:
         check(L.LIB.act(self.handle, ptr(frames), ptr(proprio), n, int(bool(sample)), int(request_id), ptr(out),
                         stream_handle(stream)))
         return out
+
+
+class Server:
+    """Continuous-batching act() server over an Agent's resident weights.
+
+    submit() enqueues a request (its buffers must stay alive until done);
+    completion times (host steady clock, seconds) are collected in `done`."""
+
+    def __init__(self, agent, mem_budget=8 << 30, max_batch_obs=8192, n_slots=4):
+        self.agent = agent
+        self.done = {}
+        self._keep = {}
+        self._cb = L.DONE_CB(self._on_done)
+        h = ctypes.c_void_p()
+        torch.cuda.synchronize()
+        check(L.LIB.sq_server_create(agent.handle, int(mem_budget), int(max_batch_obs), int(n_slots),
+                                     ctypes.byref(h)))
+        self.handle = h
+
+    def _on_done(self, rid, t, _user):
+        self.done[int(rid)] = float(t)
+        self._keep.pop(int(rid), None)
+
+    def submit(self, frames, proprio, request_id, sample=False, out=None):
+        n = frames.shape[0]
+        cfg = self.agent.cfg
+        _req(frames, torch.uint8, (n, cfg["H"], cfg["W"], cfg["C"]), "frames")
+        _req(proprio, torch.float32, (n, cfg["proprio"]), "proprio")
+        if out is None:
+            out = torch.empty((n, cfg["action"]), dtype=torch.float32, device=frames.device)
+        self._keep[int(request_id)] = (frames, proprio, out)
+        check(L.LIB.sq_server_submit(self.handle, ptr(frames), ptr(proprio), n, int(bool(sample)), int(request_id),
+                                     ptr(out), self._cb, None))
+        return out
+
+    def drain(self):
+        check(L.LIB.sq_server_drain(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            L.LIB.sq_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -158,9 +158,13 @@ def test_c51_projection_vs_oracle_and_invariants(N, lo, hi, n):
     assert np.abs(m - ref).max() < 1e-5
     assert m.min() >= 0
     np.testing.assert_allclose(m.sum(1), 1.0, atol=2e-6)
-    # identity projection at reward 0, gamma 1, not done, no bonus
+    # identity projection at reward 0, gamma 1, not done, no bonus: exact in real
+    # arithmetic; in FP32 each atom position b_j = (z_j - v_min) / dz carries the
+    # rounding of z_j, about ulp(max|v|) / dz, which moves that much of p_j
     mi = api.c51_project(cfg, dev(p), dev(np.zeros(n)), dev(np.zeros(n), torch.uint8), None, 1.0).cpu().numpy()
-    assert np.abs(mi - p).max() < 1e-6
+    dz = (hi - lo) / (N - 1)
+    bound = 4 * np.spacing(np.float32(max(abs(lo), abs(hi)))) / dz
+    assert np.abs(mi - p).max() <= bound * p.max() + 1e-7
 
 
 def test_adam_step_vs_oracle_with_ema_and_shadow():
@@ -177,8 +181,10 @@ def test_adam_step_vs_oracle_with_ema_and_shadow():
     P, M, V = p0.astype(np.float64), m0.astype(np.float64), v0.astype(np.float64)
     ohp = sac.hparams(olayout.dims(**H.cfg("tiny")))
     sac.adam(P, g.astype(np.float64), M, V, 5, ohp)
+    # beta1 = 0.9 and 1 - beta1 are inexact in FP32 (relative 3e-8 / 2.4e-7)
     assert np.abs(p.cpu().numpy() - P).max() < 1e-6
-    assert np.abs(m.cpu().numpy() - M).max() < 1e-7
+    assert np.abs(m.cpu().numpy() - M).max() < 1e-6
+    assert np.abs(v.cpu().numpy() - V).max() < 1e-7
     T = tgt0.astype(np.float64)
     sac.ema(T, P[1000:], 0.995)
     assert np.abs(tgt.cpu().numpy() - T).max() < 1e-6
