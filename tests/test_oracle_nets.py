@@ -12,7 +12,6 @@ from oracle.bf16 import round_bf16
 from paper_2602_21203_amd import synthetic
 from tests import torch_ref
 
-torch.set_default_dtype(torch.float64)
 RTOL = 1e-10
 
 

@@ -14,7 +14,6 @@ from oracle.squint import squint
 from paper_2602_21203_amd import synthetic
 from tests import torch_ref
 
-torch.set_default_dtype(torch.float64)
 
 
 def T(x, grad=False):
@@ -108,11 +107,11 @@ def _torch_update_grads(d, rep, st, hp, B, out):
         pbar = 0.5 * (torch.softmax(lbar[0], -1) + torch.softmax(lbar[1], -1))
         N = d.atoms
         dz = (d.v_max - d.v_min) / (N - 1)
-        z = d.v_min + torch.arange(N) * dz
+        z = d.v_min + torch.arange(N, dtype=torch.float64) * dz
         Tz = (r[:, None] + hp.gamma * (1 - done[:, None]) * (z[None] - alpha * lp_n[:, None]))
         bpos = ((Tz.clamp(d.v_min, d.v_max) - d.v_min) / dz)
         lo, hi = bpos.floor().long(), bpos.ceil().long()
-        m = torch.zeros(B, N)
+        m = torch.zeros(B, N, dtype=torch.float64)
         wl = torch.where(lo == hi, pbar, pbar * (hi - bpos))
         m.scatter_add_(1, lo, wl)
         m.scatter_add_(1, hi, torch.where(lo == hi, torch.zeros_like(pbar), pbar * (bpos - lo)))
