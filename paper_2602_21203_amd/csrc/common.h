@@ -151,7 +151,7 @@ int col_partials(const float* src, long long ld, long long sz, int rows, int N, 
 struct ColSeg {
   const float* part; int nrows, H, k, batch;
   float* out[3]; long long out_sz;
-  long long count;   // filled by colsum()
+  long long count;   // workgroups, filled by colsum()
 };
 struct ColSegs { int n; ColSeg s[12]; };
 int colsum(ColSegs segs, hipStream_t st);
@@ -178,7 +178,10 @@ int alpha_step(const float* logp, int B, float target_entropy, float* log_alpha,
 int finish_update(const float* loss_row, const float* q_row, const float* tgt_row, const float* logp,
                   const float* qa_row, const float* scal, int B, int actor_step, int* ctr, float* stats,
                   hipStream_t st);
-int conv_bias_grad(const float* dout, const float* out, int n, int F, int HW, float* db, hipStream_t st);
+// part: conv_bias_chunks(n, HW) * F floats of scratch
+int conv_bias_chunks(int n, int HW);
+int conv_bias_grad(const float* dout, const float* out, int n, int F, int HW, float* db, float* part,
+                   hipStream_t st);
 
 // adam.hip: step t = *step + 1 (not modified); EMA over i >= ema_begin
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,

@@ -133,6 +133,33 @@ struct StPart {
 };
 
 // ---------------------------------------------------------------- kernel
+// Global -> register staging of one 32 x BK operand slice.  Each thread owns
+// EL = 32 * BK / 256 elements at fixed positions; all EL loads are issued back
+// to back (bounds give zero), so their latencies overlap, and the next slice is
+// fetched while the current one is being multiplied.
+template <class F, int BK, int EL>
+__device__ __forceinline__ void fetch(const F& f, float (&r)[EL], int z, int row0, int rows, int k0, int kend) {
+#pragma unroll
+  for (int i = 0; i < EL; ++i) {
+    const int e = (int)threadIdx.x + kThreads * i;
+    int rr, kk;
+    if constexpr (F::KFAST) { rr = e / BK; kk = e - rr * BK; } else { kk = e / kTile; rr = e - kk * kTile; }
+    const int gr = row0 + rr, gk = k0 + kk;
+    r[i] = (gr < rows && gk < kend) ? f.get(z, gr, gk) : 0.f;
+  }
+}
+
+template <class F, int BK, int LD, int EL, class T>
+__device__ __forceinline__ void stage(const float (&r)[EL], T* tile) {
+#pragma unroll
+  for (int i = 0; i < EL; ++i) {
+    const int e = (int)threadIdx.x + kThreads * i;
+    int rr, kk;
+    if constexpr (F::KFAST) { rr = e / BK; kk = e - rr * BK; } else { kk = e / kTile; rr = e - kk * kTile; }
+    tile[rr * LD + kk] = to_t(r[i], (T*)nullptr);
+  }
+}
+
 template <bool BF16, class FA, class FB, class ST, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart sp, int M, int N, int K,
                                                    int kchunk) {
@@ -140,6 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
   using T = typename C::T;
   constexpr int BK = 4 * C::KW;
   constexpr int LD = BK + C::PAD;
+  constexpr int EL = kTile * BK / kThreads;
   constexpr int TILE_BYTES = 2 * kTile * LD * (int)sizeof(T);
   constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
   constexpr int LDS_BYTES = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
@@ -161,20 +189,19 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
+  float ra[EL], rb[EL];
+  if (kbeg < kend) {
+    fetch<FA, BK, EL>(fa, ra, z, m0, M, kbeg, kend);
+    fetch<FB, BK, EL>(fb, rb, z, n0, N, kbeg, kend);
+  }
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    for (int e = threadIdx.x; e < kTile * BK; e += kThreads) {
-      int r, k;
-      if (FA::KFAST) { r = e / BK; k = e - r * BK; } else { k = e / kTile; r = e - k * kTile; }
-      const int gr = m0 + r, gk = k0 + k;
-      As[r * LD + k] = to_t((gr < M && gk < kend) ? fa.get(z, gr, gk) : 0.f, (T*)nullptr);
-    }
-    for (int e = threadIdx.x; e < kTile * BK; e += kThreads) {
-      int r, k;
-      if (FB::KFAST) { r = e / BK; k = e - r * BK; } else { k = e / kTile; r = e - k * kTile; }
-      const int gr = n0 + r, gk = k0 + k;
-      Bs[r * LD + k] = to_t((gr < N && gk < kend) ? fb.get(z, gr, gk) : 0.f, (T*)nullptr);
-    }
+    stage<FA, BK, LD, EL>(ra, As);
+    stage<FB, BK, LD, EL>(rb, Bs);
     __syncthreads();
+    if (k0 + BK < kend) {
+      fetch<FA, BK, EL>(fa, ra, z, m0, M, k0 + BK, kend);
+      fetch<FB, BK, EL>(fb, rb, z, n0, N, k0 + BK, kend);
+    }
     if constexpr (!BF16) {
 #pragma unroll
       for (int kk = 0; kk < C::KW; kk += 4) {

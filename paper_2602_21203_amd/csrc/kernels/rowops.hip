@@ -15,7 +15,7 @@
 namespace sq {
 
 constexpr int kMaxPerLane = 16;   // LayerNorm widths up to 1024
-constexpr int kLnBwdRows = 16;    // rows per workgroup in backward kernels
+constexpr int kLnRowsPerBlock = 4; // rows per workgroup (one per wave) in row-partial kernels
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -105,24 +105,25 @@ int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, i
 // ---------------------------------------------------------------- LayerNorm backward
 // Per row: dz = dy * act'(y), dxh = dz * g,
 //   dpre = rstd * (dxh - mean(dxh) - xhat * mean(dxh * xhat)).
-// Column partials per (row block, wave): [3][nblk * 4][H] = (dpre, dz * xhat, dz)
-// for the bias, gain and shift gradients.
+// One row per wave, four rows per workgroup.  Column partials of the
+// workgroup's rows, summed over its waves in order, go to part[z][3][blk][H] =
+// (dpre, dz * xhat, dz) for the bias, gain and shift gradients.
 __global__ __launch_bounds__(256) void k_ln_bwd(const float* __restrict__ dy, long long ld_dy, long long sz_dy,
                                                 const float* __restrict__ y, long long ld_y, long long sz_y,
                                                 const float* __restrict__ xhat, const float* __restrict__ rstd,
                                                 const float* __restrict__ g, long long sz_par, int rows, int H,
                                                 int act_tanh, float* __restrict__ dpre,
                                                 float* __restrict__ part) {
+  extern __shared__ float shp[];   // [3][4][H] when partials are wanted
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int blk = blockIdx.x, z = blockIdx.y;
   const int nblk = gridDim.x;
+  const int row = blk * kLnRowsPerBlock + wave;
   const float* gz = g + z * sz_par;
   float pb[kMaxPerLane], pg[kMaxPerLane], pz[kMaxPerLane];
 #pragma unroll
   for (int t = 0; t < kMaxPerLane; ++t) pb[t] = pg[t] = pz[t] = 0.f;
-  for (int rr = wave; rr < kLnBwdRows; rr += 4) {
-    const int row = blk * kLnBwdRows + rr;
-    if (row >= rows) break;
+  if (row < rows) {
     const float* dyr = dy + z * sz_dy + row * ld_dy;
     const float* yr = y + z * sz_y + row * ld_y;
     const float* xr = xhat + ((long long)z * rows + row) * H;
@@ -154,92 +155,104 @@ __global__ __launch_bounds__(256) void k_ln_bwd(const float* __restrict__ dy, lo
       if (j < H) {
         const float v = rs * (dz[t] * gz[j] - c1 - xh[t] * c2);
         dp[j] = v;
-        pb[t] += v;
-        pg[t] += dz[t] * xh[t];
-        pz[t] += dz[t];
+        pb[t] = v;
+        pg[t] = dz[t] * xh[t];
+        pz[t] = dz[t];
       }
     }
   }
-  if (part) {
-    const long long prow = (long long)blk * 4 + wave;
-    const long long plane = (long long)nblk * 4 * H;
-    float* pp = part + (long long)z * 3 * plane + prow * H;
+  if (!part) return;
 #pragma unroll
-    for (int t = 0; t < kMaxPerLane; ++t) {
-      const int j = lane + 64 * t;
-      if (j < H) {
-        pp[j] = pb[t];
-        pp[plane + j] = pg[t];
-        pp[2 * plane + j] = pz[t];
-      }
+  for (int t = 0; t < kMaxPerLane; ++t) {
+    const int j = lane + 64 * t;
+    if (j < H) {
+      shp[(0 * 4 + wave) * H + j] = pb[t];
+      shp[(1 * 4 + wave) * H + j] = pg[t];
+      shp[(2 * 4 + wave) * H + j] = pz[t];
     }
+  }
+  __syncthreads();
+  float* pp = part + (long long)z * 3 * nblk * H + (long long)blk * H;
+  for (int e = threadIdx.x; e < 3 * H; e += 256) {
+    const int k = e / H, j = e - k * H;
+    const float* q = shp + k * 4 * H + j;
+    pp[(long long)k * nblk * H + j] = ((q[0] + q[H]) + q[2 * H]) + q[3 * H];
   }
 }
 
-int ln_bwd_partial_rows(int rows) { return cdiv(rows, kLnBwdRows) * 4; }
+int ln_bwd_partial_rows(int rows) { return cdiv(rows, kLnRowsPerBlock); }
 
 int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y, long long ld_y, long long sz_y,
                const float* xhat, const float* rstd, const float* g, long long sz_par, int rows, int H, int batch,
                int act_tanh, float* dpre, float* partials, hipStream_t st) {
   if (rows <= 0) return SQ_OK;
-  dim3 grid(cdiv(rows, kLnBwdRows), batch);
-  k_ln_bwd<<<grid, 256, 0, st>>>(dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, sz_par, rows, H, act_tanh, dpre,
-                                 partials);
+  dim3 grid(cdiv(rows, kLnRowsPerBlock), batch);
+  const size_t lds = partials ? (size_t)3 * 4 * H * sizeof(float) : 0;
+  k_ln_bwd<<<grid, 256, lds, st>>>(dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, sz_par, rows, H, act_tanh, dpre,
+                                   partials);
   return launch_status("ln_bwd");
 }
 
 // ---------------------------------------------------------------- column partials
-// Partial column sums of a [batch][rows][N] matrix: [batch][nblk * 4][N] (same
-// blocking as the LayerNorm backward) -- used for output-head bias gradients.
+// Partial column sums of a [batch][rows][N] matrix over blocks of 4 rows:
+// part[z][blk][N] (same blocking as the LayerNorm backward) -- used for the
+// output-head bias gradients.
 __global__ __launch_bounds__(256) void k_col_partials(const float* __restrict__ src, long long ld, long long sz,
                                                       int rows, int N, float* __restrict__ part) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int blk = blockIdx.x, z = blockIdx.y, nblk = gridDim.x;
-  for (int j0 = 0; j0 < N; j0 += 64) {
-    const int j = j0 + lane;
+  for (int j = threadIdx.x; j < N; j += 256) {
     float s = 0.f;
-    for (int rr = wave; rr < kLnBwdRows; rr += 4) {
-      const int row = blk * kLnBwdRows + rr;
-      if (row >= rows) break;
-      if (j < N) s += src[z * sz + row * ld + j];
+    for (int rr = 0; rr < kLnRowsPerBlock; ++rr) {
+      const int row = blk * kLnRowsPerBlock + rr;
+      if (row < rows) s += src[z * sz + row * ld + j];
     }
-    if (j < N) part[((long long)z * nblk * 4 + blk * 4 + wave) * N + j] = s;
+    part[((long long)z * nblk + blk) * N + j] = s;
   }
 }
 
 int col_partials(const float* src, long long ld, long long sz, int rows, int N, int batch, float* part,
                  hipStream_t st) {
   if (rows <= 0) return SQ_OK;
-  dim3 grid(cdiv(rows, kLnBwdRows), batch);
+  dim3 grid(cdiv(rows, kLnRowsPerBlock), batch);
   k_col_partials<<<grid, 256, 0, st>>>(src, ld, sz, rows, N, part);
   return launch_status("col_partials");
 }
 
 // Sum partial rows in order.  Segment s: part [batch][k][nrows][H] -> out[k][z * out_sz + c].
-__global__ void k_colsum(ColSegs segs) {
-  long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// A workgroup owns 64 columns of one (segment, z, k): wave w sums rows w, w+4, ...
+// for its lane's column, then the four waves are added in order.
+__global__ __launch_bounds__(256) void k_colsum(ColSegs segs) {
+  __shared__ float sh[4][64];
+  long long b = blockIdx.x;
   int s = 0;
-  while (s < segs.n && e >= segs.s[s].count) { e -= segs.s[s].count; ++s; }
+  while (s < segs.n && b >= segs.s[s].count) { b -= segs.s[s].count; ++s; }
   if (s >= segs.n) return;
   const ColSeg& g = segs.s[s];
-  const int kh = g.k * g.H;
-  const int z = (int)(e / kh);
-  const int rem = (int)(e - (long long)z * kh);
-  const int kk = rem / g.H, c = rem - kk * g.H;
-  const float* p = g.part + ((long long)z * g.k + kk) * g.nrows * g.H + c;
+  const int cb = (g.H + 63) / 64;
+  const int zk = (int)(b / cb);
+  const int c0 = (int)(b - (long long)zk * cb) * 64;
+  const int z = zk / g.k, kk = zk - z * g.k;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = c0 + lane;
   float v = 0.f;
-  for (int r = 0; r < g.nrows; ++r) v += p[(long long)r * g.H];
-  if (g.out[kk]) g.out[kk][z * g.out_sz + c] = v;
+  if (c < g.H) {
+    const float* p = g.part + ((long long)z * g.k + kk) * g.nrows * g.H + c;
+    for (int r = wave; r < g.nrows; r += 4) v += p[(long long)r * g.H];
+  }
+  sh[wave][lane] = v;
+  __syncthreads();
+  if (wave == 0 && c < g.H && g.out[kk])
+    g.out[kk][z * g.out_sz + c] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
 }
 
 int colsum(ColSegs segs, hipStream_t st) {
   long long total = 0;
   for (int i = 0; i < segs.n; ++i) {
-    segs.s[i].count = (long long)segs.s[i].batch * segs.s[i].k * segs.s[i].H;
+    segs.s[i].count = (long long)segs.s[i].batch * segs.s[i].k * ((segs.s[i].H + 63) / 64);
     total += segs.s[i].count;
   }
   if (total == 0) return SQ_OK;
-  k_colsum<<<cdiv(total, 256), 256, 0, st>>>(segs);
+  k_colsum<<<(unsigned)total, 256, 0, st>>>(segs);
   return launch_status("colsum");
 }
 
@@ -633,26 +646,42 @@ int finish_update(const float* loss_row, const float* q_row, const float* tgt_ro
 }
 
 // ---------------------------------------------------------------- conv bias gradient
-// db[f] = sum over (n, p) of dout * (out > 0)
+// db[f] = sum over (n, p) of dout * (out > 0): workgroup (chunk, f) sums a fixed
+// chunk of the (n, p) range into part[chunk][f]; colsum adds the chunks in order.
 __global__ __launch_bounds__(256) void k_conv_bias(const float* __restrict__ dout, const float* __restrict__ out,
-                                                   int n, int F, int HW, float* __restrict__ db) {
+                                                   int n, int F, int HW, int per_chunk, float* __restrict__ part) {
   __shared__ float sh[256];
-  const int f = blockIdx.x;
+  const int f = blockIdx.y, ch = blockIdx.x;
   const long long total = (long long)n * HW;
+  const long long e0 = (long long)ch * per_chunk;
+  const long long e1 = e0 + per_chunk < total ? e0 + per_chunk : total;
   float s = 0.f;
-  for (long long e = threadIdx.x; e < total; e += 256) {
+  for (long long e = e0 + threadIdx.x; e < e1; e += 256) {
     const long long nn = e / HW, p = e - nn * HW;
     const long long i = (nn * F + f) * HW + p;
     s += out[i] > 0.f ? dout[i] : 0.f;
   }
   s = block_sum256(s, sh);
-  if (threadIdx.x == 0) db[f] = s;
+  if (threadIdx.x == 0) part[(long long)ch * F + f] = s;
 }
 
-int conv_bias_grad(const float* dout, const float* out, int n, int F, int HW, float* db, hipStream_t st) {
+int conv_bias_chunks(int n, int HW) {
+  const long long total = (long long)n * HW;
+  int chunks = cdiv(total, 2048);
+  return chunks < 1 ? 1 : (chunks > 256 ? 256 : chunks);
+}
+
+int conv_bias_grad(const float* dout, const float* out, int n, int F, int HW, float* db, float* part,
+                   hipStream_t st) {
   if (n <= 0) return SQ_OK;
-  k_conv_bias<<<F, 256, 0, st>>>(dout, out, n, F, HW, db);
-  return launch_status("conv_bias_grad");
+  const int chunks = conv_bias_chunks(n, HW);
+  const int per = cdiv((long long)n * HW, chunks);
+  k_conv_bias<<<dim3(chunks, F), 256, 0, st>>>(dout, out, n, F, HW, per, part);
+  SQ_TRY(launch_status("conv_bias_grad"));
+  ColSegs s{};
+  s.n = 1;
+  s.s[0] = ColSeg{part, chunks, F, 1, 1, {db, nullptr, nullptr}, 0, 0};
+  return colsum(s, st);
 }
 
 }  // namespace sq

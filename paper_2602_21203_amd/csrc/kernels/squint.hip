@@ -61,6 +61,93 @@ __global__ __launch_bounds__(kSquintThreads) void k_squint(
   }
 }
 
+// Specialised path for a compile-time (channels C, factor K): a workgroup owns
+// ry output rows (all 16 columns) of one image; thread t owns output pixel
+// (t / 16, t % 16) for every channel.  The source rows are copied to LDS with
+// batched 16-byte loads; each thread then reads its K x (K*C)-byte block rows as
+// 32-bit words (K*C % 4 == 0) and adds each byte into its channel's sum, with
+// every index known at compile time.
+template <int C, int K>
+__global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ src0,
+                                                   const uint8_t* __restrict__ src1, const int* __restrict__ idx,
+                                                   const uint8_t* const* __restrict__ row_ptrs, int nsplit, int W,
+                                                   int ry, int bf16_out, void* __restrict__ out) {
+  constexpr int SIDE = 16;
+  constexpr int SEG = K * C;          // bytes of one block row
+  static_assert(SEG % 4 == 0, "32-bit block rows");
+  extern __shared__ __attribute__((aligned(16))) uint8_t tile[];
+  const int img = blockIdx.y;
+  const int y0 = blockIdx.x * ry;
+  const uint8_t* src;
+  long long row;
+  if (row_ptrs) {
+    src = row_ptrs[img];
+    row = 0;
+  } else if (img < nsplit) {
+    src = src0;
+    row = idx ? idx[img] : img;
+  } else {
+    src = src1;
+    row = idx[img - nsplit];
+  }
+  const int row_bytes = W * C;            // one source pixel row
+  const long long frame_bytes = (long long)row_bytes * W;
+  const int chunk16 = ry * K * row_bytes / 16;
+  const uint4* g4 = reinterpret_cast<const uint4*>(src + row * frame_bytes + (long long)y0 * K * row_bytes);
+  uint4* t4 = reinterpret_cast<uint4*>(tile);
+  int i = threadIdx.x;
+  for (; i + 3 * 256 < chunk16; i += 4 * 256) {
+    const uint4 a = g4[i], b = g4[i + 256], c = g4[i + 512], d = g4[i + 768];
+    t4[i] = a;
+    t4[i + 256] = b;
+    t4[i + 512] = c;
+    t4[i + 768] = d;
+  }
+  for (; i < chunk16; i += 256) t4[i] = g4[i];
+  __syncthreads();
+  const int yl = threadIdx.x / SIDE, x = threadIdx.x % SIDE;
+  if (yl >= ry) return;
+  int sum[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) sum[c] = 0;
+#pragma unroll
+  for (int r = 0; r < K; ++r) {
+    const unsigned* w = reinterpret_cast<const unsigned*>(tile + (yl * K + r) * row_bytes + x * SEG);
+#pragma unroll
+    for (int q = 0; q < SEG / 4; ++q) {
+      const unsigned v = w[q];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) sum[(4 * q + b) % C] += (int)((v >> (8 * b)) & 0xFFu);
+    }
+  }
+  const float scale = (float)(255 * K * K);
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const float v = (float)sum[c] / scale - 0.5f;
+    const long long oi = (long long)img * C * SIDE * SIDE + ((long long)c * SIDE + y0 + yl) * SIDE + x;
+    if (bf16_out)
+      reinterpret_cast<uint16_t*>(out)[oi] = bf16_bits(v);
+    else
+      reinterpret_cast<float*>(out)[oi] = v;
+  }
+}
+
+template <int C, int K>
+static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
+                   int n, int H, int W, int Cr, int kr, int bf16_out, void* out, long long out_row_stride,
+                   hipStream_t st) {
+  if (Cr != C || kr != K || H / K != 16 || out_row_stride != (long long)C * 256) return false;
+  const long long frame_bytes = (long long)H * W * C;
+  if (frame_bytes % 16 != 0 || (uintptr_t)s0 % 16 != 0 || (s1 && (uintptr_t)s1 % 16 != 0)) return false;
+  const int row_bytes = K * W * C;
+  int ry = 16;
+  while (ry > 1 && ry * row_bytes > 40960) ry /= 2;
+  if ((ry * row_bytes) % 16 != 0) return false;
+  dim3 grid(16 / ry, n);
+  k_squint_ck<C, K><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, bf16_out, out);
+  return true;
+}
+
 static int squint_rows_per_chunk(int W, int C, int k, int side) {
   const int row_bytes = k * W * C;
   int ry = side;
@@ -80,6 +167,13 @@ int squint_ok(int H, int W, int C, int k) {
 static int launch(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
                   int n, int H, int W, int C, int k, int bf16_out, void* out, long long out_row_stride,
                   hipStream_t st) {
+  // per-row pointers (serving) are only known on the device and may be unaligned:
+  // they take the generic byte path
+  if (rows == nullptr &&
+      (try_ck<9, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, bf16_out, out, out_row_stride, st) ||
+       try_ck<9, 8>(s0, s1, idx, rows, nsplit, n, H, W, C, k, bf16_out, out, out_row_stride, st) ||
+       try_ck<3, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, bf16_out, out, out_row_stride, st)))
+    return launch_status("squint_ck");
   const int side = H / k;
   const int ry = squint_rows_per_chunk(W, C, k, side);
   const long long chunk_bytes = (long long)ry * k * W * C;

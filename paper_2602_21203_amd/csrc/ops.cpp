@@ -48,11 +48,13 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
     e->h[i] = b.take<float>((size_t)n * d.F * net.conv_side[i] * net.conv_side[i]);
   e->dh[0] = e->dh[1] = nullptr;
   e->split = nullptr;
+  e->bias_part = nullptr;
   if (with_bwd) {
     const size_t big = (size_t)n * d.F * net.conv_side[0] * net.conv_side[0];
     e->dh[0] = b.take<float>(big);
     e->dh[1] = b.take<float>(big);
     e->split = b.take<float>(kSplitFloats);
+    e->bias_part = b.take<float>((size_t)256 * d.F);
   }
 }
 
@@ -80,7 +82,7 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
     const int hin = i ? net.conv_side[i - 1] : net.side;
     const int hw = net.conv_side[i] * net.conv_side[i];
     SQ_TRY(conv_dw(bf16, in, n, cin, hin, i ? 1 : 2, dh, e.h[i], d.F, dep + L.conv_W[i], e.split, kSplitFloats, st));
-    SQ_TRY(conv_bias_grad(dh, e.h[i], n, d.F, hw, dep + L.conv_b[i], st));
+    SQ_TRY(conv_bias_grad(dh, e.h[i], n, d.F, hw, dep + L.conv_b[i], e.bias_part, st));
     if (i > 0) {
       float* dx = e.dh[i & 1];
       SQ_TRY(conv_dx(bf16, dh, e.h[i], n, d.F, hin, ep + L.conv_W[i], d.F, dx, st));

@@ -12,6 +12,7 @@ struct EncBufs {
   float* h[4];        // post-ReLU conv outputs [n][F][s_i][s_i]; h[n_conv-1] is the feature
   float* dh[2];       // ping-pong input gradients
   float* split;       // split-K scratch, kSplitFloats
+  float* bias_part;   // conv bias partial sums, 256 * F
 };
 void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd);
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
