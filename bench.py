@@ -38,6 +38,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision timing")
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--sweep", action="store_true",
+                    help="UTD sweep {1,4,8,16} at batch 1024 on 128x128x9 frames (prints one JSON line)")
+    ap.add_argument("--serve", action="store_true",
+                    help="Poisson act() load at 2k..50k obs/s, pools U{1..4096} (prints one JSON line)")
+    ap.add_argument("--serve-seconds", type=float, default=12.0)
+    ap.add_argument("--report", action="store_true",
+                    help="errors after 1 and N updates vs the FP64 oracle, BF16 and FP32 (prints one JSON line)")
+    ap.add_argument("--report-updates", type=int, default=100)
     return ap.parse_args()
 
 
@@ -145,8 +153,141 @@ def cpu_baseline(cfg, B, budget_s=20.0):
                 sample=f"{n} FP64 oracle updates at batch {B} (full network, 64x64x9 frames) after 1 warm-up")
 
 
+def run_sweep(a):
+    import torch
+
+    from paper_2602_21203_amd import _lib, api, synthetic
+    cfg = cfg_for(128)
+    B = 1024
+    rep = synthetic.replay(32768, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=0,
+                           device="cuda")
+    table, _ = _lib.param_table(cfg)
+    params = synthetic.init_params(table, seed=1)
+    out = {"mode": "utd_sweep", "workload": "full network, batch 1024, 128x128x9 frames squinted 8x, "
+                                            "replay 32768 rows", "unit": "updates/s", "points": []}
+    for prec_name, prec in (("bf16", _lib.SQ_BF16), ("fp32", _lib.SQ_F32)):
+        for utd in (1, 4, 8, 16):
+            ag = api.Agent(cfg, params, B, prec=prec)
+            steps = max(4, 64 // utd)
+            wall, gpu, _ = time_updates(ag, rep, utd, steps, 2)
+            out["points"].append({"precision": prec_name, "utd": utd, "updates_per_s": round(utd * steps / wall, 2),
+                                  "ms_per_launch": round(wall / steps * 1e3, 3)})
+            ag.close()
+    print(json.dumps(out))
+
+
+def run_serve(a):
+    import numpy as np
+    import torch
+
+    from paper_2602_21203_amd import _lib, api, synthetic
+    cfg = cfg_for(64)
+    table, _ = _lib.param_table(cfg)
+    params = synthetic.init_params(table, seed=1)
+    agent = api.Agent(cfg, params, 32, prec=_lib.SQ_BF16)
+    pool = synthetic.frames(4096, cfg["H"], cfg["W"], cfg["C"], seed=11, device="cuda")
+    prop = torch.randn(4096, cfg["proprio"], device="cuda")
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    out = {"mode": "act_serving", "workload": "act() of BF16 full network on 64x64x9 frames, pools U{1..4096}, "
+                                              "Poisson arrivals, 4 stream slots, weights resident",
+           "points": []}
+    for rate in (2000, 5000, 10000, 20000, 50000):
+        srv = api.Server(agent, mem_budget=16 << 30, max_batch_obs=8192, n_slots=4)
+        lam = rate / 2048.5
+        t_sub, sizes = {}, []
+        t0 = time.monotonic()
+        t_next = t0
+        i = 0
+        while time.monotonic() - t0 < a.serve_seconds:
+            t_next += rng.exponential(1.0 / lam)
+            while True:
+                now = time.monotonic()
+                if now >= t_next:
+                    break
+                time.sleep(min(0.0005, t_next - now))
+            n = int(rng.integers(1, 4097))
+            t_sub[i] = t_next
+            sizes.append(n)
+            srv.submit(pool[:n], prop[:n], i, sample=True)
+            i += 1
+        srv.drain()
+        t1 = time.monotonic()
+        lat = sorted(srv.done[j] - t_sub[j] for j in range(i))
+        srv.close()
+        pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))] * 1e3
+        out["points"].append({"offered_obs_per_s": rate, "requests": i, "p50_ms": round(pct(0.5), 3),
+                              "p99_ms": round(pct(0.99), 3), "achieved_obs_per_s": round(sum(sizes) / (t1 - t0), 1)})
+    agent.close()
+    print(json.dumps(out))
+
+
+def run_report(a):
+    """Losses, gradients and parameters after 1 and N updates: GPU BF16 and FP32 vs the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    from oracle import layout as olayout
+    from oracle import sac
+    from paper_2602_21203_amd import _lib, api, synthetic
+    cfg = cfg_for(64)
+    B = a.batch
+    d = olayout.dims(**cfg)
+    table = [(n, o, s) for n, (o, s) in olayout.offsets(d)[0].items()]
+    params = synthetic.init_params(table, seed=1)
+    cpu = synthetic.replay(8192, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=0)
+    gpu = {k: (v.cuda() if torch.is_tensor(v) else v) for k, v in cpu.items()}
+    npr = {k: (v.numpy() if torch.is_tensor(v) else v) for k, v in cpu.items()}
+    N = a.report_updates
+    st = sac.new_state(d, params.astype(np.float64))
+    hp = sac.hparams(d)
+    ref_stats, ref_g1, ref_p1 = [], None, None
+    for u in range(N):
+        if u % 10 == 0:
+            print(f"oracle update {u}/{N}", file=sys.stderr, flush=True)
+        o = sac.sac_update(st, npr, d, hp, B)
+        ref_stats.append(o["stats"])
+        if u == 0:
+            ref_g1 = np.concatenate([o["g_enc_critic"], o["g_actor"]])
+            ref_p1 = st.params.copy()
+    ref_stats = np.array(ref_stats)
+    out = {"mode": "precision_report", "batch": B, "updates": N, "workload": "full network, 64x64x9 frames",
+           "results": {}}
+    for name, prec in (("bf16", _lib.SQ_BF16), ("fp32", _lib.SQ_F32)):
+        ag = api.Agent(cfg, params, B, prec=prec)
+        s1 = ag.sac_update(gpu, 1, graph=False).cpu().numpy()
+        torch.cuda.synchronize()
+        g1 = ag.grads.double().cpu().numpy()
+        p1 = ag.params.double().cpu().numpy()
+        sN = ag.sac_update(gpu, N - 1, graph=True).cpu().numpy() if N > 1 else s1
+        torch.cuda.synchronize()
+        pN = ag.params.double().cpu().numpy()
+        stats = np.concatenate([s1, sN]) if N > 1 else s1
+        ga = g1[:olayout.blocks(d)["actor"][1]]
+        rel = lambda x, y: float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-30))
+        out["results"][name] = {
+            "critic_loss_rel_err_update1": float(abs(s1[0, 0] - ref_stats[0, 0]) / abs(ref_stats[0, 0])),
+            "critic_loss_rel_err_last": float(abs(stats[-1, 0] - ref_stats[-1, 0]) / abs(ref_stats[-1, 0])),
+            "actor_loss_abs_err_update1": float(abs(s1[0, 1] - ref_stats[0, 1])),
+            "actor_loss_abs_err_last": float(abs(stats[-1, 1] - ref_stats[-1, 1])),
+            "grad_rel_err_update1": rel(ga, ref_g1),
+            "param_max_abs_err_update1": float(np.abs(p1 - ref_p1).max()),
+            "param_rel_err_last": rel(pN, st.params),
+            "max_critic_loss_rel_err_all_updates": float(np.max(np.abs(stats[:, 0] - ref_stats[:, 0]) /
+                                                                np.abs(ref_stats[:, 0]))),
+        }
+        ag.close()
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
+    if a.sweep or a.serve or a.report:
+        if a.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU", "n_gpus": a.gpus}))
+            sys.exit(2)
+        (run_sweep if a.sweep else run_serve if a.serve else run_report)(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": a.gpus}))

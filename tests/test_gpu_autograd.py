@@ -1,0 +1,141 @@
+"""Differentiation form: the hand-written backward behind torch.autograd.Function,
+checked against central finite differences of the FP64 oracle (h = 1e-3, 200
+random parameter coordinates of the full-size network) and against the oracle's
+own gradient."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import layout as olayout
+from oracle import nets
+from oracle.squint import squint
+from paper_2602_21203_amd import synthetic
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2602_21203_amd import _lib
+    from paper_2602_21203_amd import autograd as AG
+
+LO, HI, ALPHA = -5.0, 2.0, 0.7
+
+
+def make_case(name, n, seed=0):
+    cfg = H.cfg(name)
+    d = H.odims(name)
+    rng = np.random.default_rng(seed)
+    frames = synthetic.frames(n, cfg["H"], cfg["W"], cfg["C"], seed=seed + 5).numpy()
+    x = squint(frames, cfg["k"]).astype(np.float32).astype(np.float64)
+    s = rng.normal(size=(n, cfg["proprio"])).astype(np.float32).astype(np.float64)
+    a = rng.uniform(-1, 1, size=(n, cfg["action"])).astype(np.float32).astype(np.float64)
+    eps = rng.normal(size=(n, cfg["action"])).astype(np.float32).astype(np.float64)
+    m = nets.softmax(rng.normal(size=(n, cfg["atoms"])) * 2).astype(np.float32).astype(np.float64)
+    p = H.params(name).astype(np.float64)
+    # exercise LayerNorm affine gradients away from the (1, 0) initialisation
+    for nm, (o, sh) in olayout.offsets(d)[0].items():
+        if ".ln." in nm:
+            p[o:o + math.prod(sh)] += rng.normal(size=math.prod(sh)).astype(np.float32) * 0.1
+    return cfg, d, x, s, a, eps, m, p
+
+
+def oracle_loss(p, d, x, s, a, eps, m):
+    """L = CE(critic(enc(x), s, a), m) + mean(alpha log pi - Q(enc(x) stop-grad, s, a_pi))."""
+    P = olayout.view(p, d)
+    feat, _ = nets.encoder_fwd(P, x, d.n_conv)
+    logits, _ = nets.critic_fwd(P, feat, s, a)
+    lc = nets.cross_entropy(logits, m)[0]
+    a_pi, logp, _ = nets.actor_fwd(P, feat, s, eps, LO, HI)
+    lq, _ = nets.critic_fwd(P, feat, s, a_pi)
+    q, _ = nets.expected_q(lq, nets.atoms(d.atoms, d.v_min, d.v_max))
+    return lc + float(np.mean(ALPHA * logp - 0.5 * (q[0] + q[1])))
+
+
+def gpu_grad(cfg, d, x, s, a, eps, m, p):
+    blk = olayout.blocks(d)
+    pt = torch.tensor(p, dtype=torch.float32, device="cuda", requires_grad=True)
+    hp = _lib.make_hparams(cfg["action"], log_std_min=LO, log_std_max=HI)
+    dev = lambda v: torch.tensor(v, dtype=torch.float32, device="cuda")
+    xt, st, at, et, mt = dev(x), dev(s), dev(a), dev(eps), dev(m)
+    enc = pt[blk["enc"][0]:blk["enc"][1]]
+    crit = pt[blk["critic"][0]:blk["critic"][1]]
+    act = pt[blk["actor"][0]:blk["actor"][1]]
+    feat = AG.encoder(enc, xt, cfg)
+    logits = AG.critic(crit, feat, st, at, cfg)
+    lc = -(mt[None] * torch.log_softmax(logits, -1)).sum(-1).mean(1).sum()
+    a_pi, logp = AG.actor(act, feat.detach(), st, et, cfg, hp)
+    lq = AG.critic(crit, feat.detach(), st, a_pi, cfg)
+    z = cfg["v_min"] + torch.arange(cfg["atoms"], device="cuda", dtype=torch.float32) * \
+        ((cfg["v_max"] - cfg["v_min"]) / (cfg["atoms"] - 1))
+    q = torch.softmax(lq, -1) @ z
+    loss = lc + (ALPHA * logp - 0.5 * (q[0] + q[1])).mean()
+    loss.backward()
+    return float(loss), pt.grad.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("name,n", [("tiny", 12), ("full", 8)])
+def test_autograd_wrappers_vs_finite_differences(name, n):
+    cfg, d, x, s, a, eps, m, p = make_case(name, n)
+    loss_gpu, g = gpu_grad(cfg, d, x, s, a, eps, m, p)
+    loss_ref = oracle_loss(p, d, x, s, a, eps, m)
+    assert abs(loss_gpu - loss_ref) <= 1e-4 * abs(loss_ref) + 1e-5
+    rng = np.random.default_rng(1)
+    total = olayout.blocks(d)["actor"][1]
+    # sample coordinates tensor-weighted so that small tensors (biases, LN) appear too
+    tab = [(nm, o, math.prod(sh)) for nm, (o, sh) in olayout.offsets(d)[0].items() if o < total]
+    coords = sorted({int(o + rng.integers(0, k)) for _ in range(4) for nm, o, k in tab} |
+                    set(rng.choice(total, 200, replace=False).tolist()))[:260]
+    coords = rng.permutation(coords)[:200]
+    h = 1e-3
+    fd, kept, kinks = [], [], 0
+    for c in coords:
+        vals = []
+        for hh in (h, h / 2):
+            pp, pm = p.copy(), p.copy()
+            pp[c] += hh
+            pm[c] -= hh
+            vals.append((oracle_loss(pp, d, x, s, a, eps, m) - oracle_loss(pm, d, x, s, a, eps, m)) / (2 * hh))
+        # a ReLU kink inside [-h, h] makes the two step sizes disagree: excluded, counted
+        if abs(vals[0] - vals[1]) > 1e-4 * max(abs(vals[1]), 1e-3):
+            kinks += 1
+            continue
+        fd.append(vals[1])
+        kept.append(c)
+    fd = np.array(fd)
+    gk = g[np.array(kept)]
+    err = np.linalg.norm(gk - fd) / np.linalg.norm(fd)
+    print(f"  {name}: {len(kept)} coordinates, {kinks} excluded at kinks, rel err {err:.2e}")
+    assert len(kept) >= 150
+    assert err <= 1e-3
+
+
+def test_autograd_gradient_vs_oracle_analytic():
+    name, n = "full", 16
+    cfg, d, x, s, a, eps, m, p = make_case(name, n, seed=3)
+    _, g = gpu_grad(cfg, d, x, s, a, eps, m, p)
+    # the oracle's hand-written backward of the same loss
+    P = olayout.view(p, d)
+    feat, ec = nets.encoder_fwd(P, x, d.n_conv)
+    logits, cc = nets.critic_fwd(P, feat, s, a)
+    _, dl = nets.cross_entropy(logits, m)
+    gc, dfeat, _ = nets.critic_bwd(P, cc, dl)
+    ge = nets.encoder_bwd(P, ec, dfeat, d.n_conv)
+    a_pi, logp, acache = nets.actor_fwd(P, feat, s, eps, LO, HI)
+    lq, qc = nets.critic_fwd(P, feat, s, a_pi)
+    _, dq = nets.expected_q(lq, nets.atoms(d.atoms, d.v_min, d.v_max))
+    gq, _, da = nets.critic_bwd(P, qc, -0.5 / n * dq, need_params=True, need_dfeat=False)
+    ga = nets.actor_bwd(P, acache, da, np.full(n, ALPHA / n))
+    tab = olayout.offsets(d)[0]
+    ref = np.zeros(olayout.blocks(d)["total"])
+    for dct in (gc, ge, ga):
+        for nm, v in dct.items():
+            o, sh = tab[nm]
+            ref[o:o + v.size] += v.ravel()
+    for nm, v in gq.items():
+        o, sh = tab[nm]
+        ref[o:o + v.size] += v.ravel()
+    blk = olayout.blocks(d)
+    worst = H.assert_grads_per_tensor(g, ref[:blk["actor"][1]], name, 0, 0, blk["actor"][1])
+    print(f"  worst per-tensor rel err {worst:.2e}")
