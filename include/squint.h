@@ -188,6 +188,17 @@ SQ_API int actor_bwd(const sq_dims* dims, sq_prec prec, const sq_hparams* hp, co
 SQ_API int adam_step(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp,
               const int* step, uint16_t* p_bf16, float* ema_target, long long ema_begin, sq_stream_t stream);
 
+/* Batched dense product on the matrix cores, the building block of every
+ * linear layer above (exposed for tests and measurement):
+ *   C[z](r, c) (+)= sum_k A[z](r, k) * B[z](c, k) + bias[z][c]
+ * with A[z](r, k) = A[z*a_sz + r*a_lr + k*a_lk] and B[z](c, k) likewise; C is
+ * row-major with leading dimension ldc.  SQ_BF16 rounds A and B to bfloat16;
+ * accumulation is FP32 in a fixed order.  bias nullable; accumulate adds to C. */
+SQ_API int sq_gemm(sq_prec prec, int M, int N, int K, int batch, const float* A, long long a_lr, long long a_lk,
+                   long long a_sz, const float* B, long long b_lr, long long b_lk, long long b_sz, float* C,
+                   long long ldc, long long c_sz, const float* bias, long long bias_sz, int accumulate,
+                   sq_stream_t stream);
+
 /* ---------------------------------------------------------------- agent */
 
 /* An agent bundles the caller's state buffers and the library's workspace for

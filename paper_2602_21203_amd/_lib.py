@@ -77,6 +77,8 @@ def _load():
         "sq_server_submit": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_ull, c_vp, DONE_CB, c_vp]),
         "sq_server_drain": (c_int, [c_vp]),
         "sq_server_destroy": (c_int, [c_vp]),
+        "sq_gemm": (c_int, [c_int, c_int, c_int, c_int, c_int, c_vp, c_ll, c_ll, c_ll, c_vp, c_ll, c_ll, c_ll,
+                            c_vp, c_ll, c_ll, c_vp, c_ll, c_int, c_vp]),
         "sq_sample_indices": (c_int, [c_ull, ctypes.c_uint, c_int, c_int, c_vp, c_vp]),
         "sq_gaussian": (c_int, [c_ull, ctypes.c_uint, ctypes.c_uint, c_int, c_vp, c_vp]),
     }

@@ -146,6 +146,33 @@ def adam_step(p, g, m, v, hp, step, p_bf16=None, ema_target=None, ema_begin=0, s
                           int(ema_begin), stream_handle(stream)))
 
 
+def gemm(prec, A, B, C=None, bias=None, accumulate=False, transpose_b=True, stream=None):
+    """C[z] = A[z] @ op(B[z]) (+ bias), op(B) = B^T (B given as [N, K]) or B ([K, N]).
+
+    A: [batch, M, K] or [M, K]; strides are passed through, so views work."""
+    a3 = A if A.dim() == 3 else A.unsqueeze(0)
+    b3 = B if B.dim() == 3 else B.unsqueeze(0)
+    batch, M, K = a3.shape
+    N = b3.shape[1] if transpose_b else b3.shape[2]
+    if C is None:
+        C = torch.zeros((batch, M, N), dtype=torch.float32, device=A.device)
+    c3 = C if C.dim() == 3 else C.unsqueeze(0)
+    for t in (a3, b3, c3):
+        if t.dtype != torch.float32 or not t.is_cuda:
+            raise ValueError("gemm takes float32 device tensors")
+    b_lr, b_lk = (b3.stride(1), b3.stride(2)) if transpose_b else (b3.stride(2), b3.stride(1))
+    if c3.stride(2) != 1:
+        raise ValueError("C must be row-major")
+    bz = b3.stride(0) if b3.shape[0] > 1 else 0
+    bias_sz = 0
+    if bias is not None:
+        bias_sz = bias.stride(0) if bias.dim() == 2 and bias.shape[0] > 1 else 0
+    check(L.LIB.sq_gemm(prec, M, N, K, batch, ptr(a3), a3.stride(1), a3.stride(2), a3.stride(0) if batch > 1 else 0,
+                        ptr(b3), b_lr, b_lk, bz, ptr(c3), c3.stride(1), c3.stride(0) if batch > 1 else 0, ptr(bias),
+                        bias_sz, int(bool(accumulate)), stream_handle(stream)))
+    return C
+
+
 def sample_indices(seed, update, size, n, device="cuda", stream=None):
     idx = torch.empty(n, dtype=torch.int32, device=device)
     check(L.LIB.sq_sample_indices(seed, update, size, n, ptr(idx), stream_handle(stream)))

@@ -236,6 +236,19 @@ int adam_step(float* p, const float* g, float* m, float* v, long long n, const s
   return adam(p, g, m, v, n, hp, step, ema_target, ema_begin, p_bf16, (hipStream_t)stream);
 }
 
+int sq_gemm(sq_prec prec, int M, int N, int K, int batch, const float* A, long long a_lr, long long a_lk,
+            long long a_sz, const float* B, long long b_lr, long long b_lk, long long b_sz, float* C, long long ldc,
+            long long c_sz, const float* bias, long long bias_sz, int accumulate, sq_stream_t stream) {
+  SQ_REQUIRE(M >= 0 && N >= 0 && K >= 0 && batch >= 0, "negative size");
+  if (M == 0 || N == 0 || batch == 0) return SQ_OK;
+  SQ_REQUIRE(C && (K == 0 || (A && B)), "NULL argument");
+  SQ_REQUIRE(ldc >= N, "ldc < N");
+  MatArg a{A, a_lr, a_lk, a_sz};
+  MatArg b{B, b_lr, b_lk, b_sz};
+  OutArg c{C, ldc, c_sz, bias, bias_sz, accumulate, 0};
+  return gemm(prec == SQ_BF16, M, N, K, batch, a, b, c, nullptr, 0, (hipStream_t)stream);
+}
+
 int sq_sample_indices(unsigned long long seed, unsigned int update, int size, int n, int* idx, sq_stream_t stream) {
   SQ_REQUIRE(size > 0 && n >= 0, "need size > 0 and n >= 0");
   if (n == 0) return SQ_OK;

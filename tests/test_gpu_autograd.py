@@ -41,14 +41,17 @@ def make_case(name, n, seed=0):
     return cfg, d, x, s, a, eps, m, p
 
 
-def oracle_loss(p, d, x, s, a, eps, m):
-    """L = CE(critic(enc(x), s, a), m) + mean(alpha log pi - Q(enc(x) stop-grad, s, a_pi))."""
+def oracle_loss(p, d, x, s, a, eps, m, feat_sg):
+    """L = CE(critic(enc(x), s, a), m) + mean(alpha log pi - Q(feat_sg, s, a_pi)).
+
+    feat_sg are the features at the unperturbed parameters: the actor path sees
+    stop-gradient features, so a perturbation of the encoder must not reach it."""
     P = olayout.view(p, d)
     feat, _ = nets.encoder_fwd(P, x, d.n_conv)
     logits, _ = nets.critic_fwd(P, feat, s, a)
     lc = nets.cross_entropy(logits, m)[0]
-    a_pi, logp, _ = nets.actor_fwd(P, feat, s, eps, LO, HI)
-    lq, _ = nets.critic_fwd(P, feat, s, a_pi)
+    a_pi, logp, _ = nets.actor_fwd(P, feat_sg, s, eps, LO, HI)
+    lq, _ = nets.critic_fwd(P, feat_sg, s, a_pi)
     q, _ = nets.expected_q(lq, nets.atoms(d.atoms, d.v_min, d.v_max))
     return lc + float(np.mean(ALPHA * logp - 0.5 * (q[0] + q[1])))
 
@@ -79,7 +82,8 @@ def gpu_grad(cfg, d, x, s, a, eps, m, p):
 def test_autograd_wrappers_vs_finite_differences(name, n):
     cfg, d, x, s, a, eps, m, p = make_case(name, n)
     loss_gpu, g = gpu_grad(cfg, d, x, s, a, eps, m, p)
-    loss_ref = oracle_loss(p, d, x, s, a, eps, m)
+    feat_sg, _ = nets.encoder_fwd(olayout.view(p, d), x, d.n_conv)
+    loss_ref = oracle_loss(p, d, x, s, a, eps, m, feat_sg)
     assert abs(loss_gpu - loss_ref) <= 1e-4 * abs(loss_ref) + 1e-5
     rng = np.random.default_rng(1)
     total = olayout.blocks(d)["actor"][1]
@@ -96,7 +100,8 @@ def test_autograd_wrappers_vs_finite_differences(name, n):
             pp, pm = p.copy(), p.copy()
             pp[c] += hh
             pm[c] -= hh
-            vals.append((oracle_loss(pp, d, x, s, a, eps, m) - oracle_loss(pm, d, x, s, a, eps, m)) / (2 * hh))
+            vals.append((oracle_loss(pp, d, x, s, a, eps, m, feat_sg) -
+                         oracle_loss(pm, d, x, s, a, eps, m, feat_sg)) / (2 * hh))
         # a ReLU kink inside [-h, h] makes the two step sizes disagree: excluded, counted
         if abs(vals[0] - vals[1]) > 1e-4 * max(abs(vals[1]), 1e-3):
             kinks += 1
