@@ -97,6 +97,34 @@ def squint_kernel_time(cfg, rep, B, reps):
     return e0.elapsed_time(e1) / 1e3 / reps
 
 
+def measured_traffic(kernel_key, source):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, each counter scaled by what it reads for a 256 MiB copy; None when
+    the kernel's source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_counters_gemm_squint.txt")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    fetch_f = float(re_search(r"copy FETCH_SIZE [\d.]+ KiB -> factor ([\d.]+)", text))
+    write_f = float(re_search(r"copy WRITE_SIZE [\d.]+ KiB -> factor ([\d.]+)", text))
+    m = re_search(kernel_key + r" source=(\w+)\s+([\d.]+)\s+([\d.]+)", text, groups=True)
+    if m is None:
+        return None
+    digest = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()[:16]
+    if m[0] != digest:
+        return None
+    return round((float(m[1]) * fetch_f + float(m[2]) * write_f) * 1024)
+
+
+def re_search(pat, text, groups=False):
+    import re
+    m = re.search(pat, text)
+    if m is None:
+        return None
+    return m.groups() if groups else m.group(1)
+
+
 def gemm_kernel_time(prec, reps):
     """Average duration of the largest linear-layer product of the update -- the
     twin critics' second hidden layer, C[2, 512, 512] = A[2, 512, 512] W[2]^T + b
@@ -359,14 +387,19 @@ def main():
     ach = flops / t_g / 1e12
     result["roofline"] = {"kernel": "k_gemm (twin critic layer 2 forward, 2 x 512x512x512)", "bound": "mfma",
                           "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 5),
-                          "traffic": None, "avg_us": round(t_g * 1e6, 3), "algorithmic_flops": flops}
+                          "traffic": measured_traffic("gemm_twin_l2_fwd_bf16", "paper_2602_21203_amd/csrc/kernels/gemm.hip")
+                          if a.prec == "bf16" else None,
+                          "avg_us": round(t_g * 1e6, 3), "algorithmic_flops": flops,
+                          "algorithmic_bytes": 3 * 2 * 512 * 512 * 4 + 2 * 512 * 4}
     # the HBM-bound step: squint gather of 2B frames (frames read + FP32 images written)
     t_k = squint_kernel_time(cfg, rep, B, a.kernel_reps)
     bytes_per_launch = 2 * B * (cfg["H"] * cfg["W"] * cfg["C"] + cfg["C"] * 16 * 16 * 4)
     achieved = bytes_per_launch / t_k / 1e9
     result["roofline_squint"] = {"kernel": "k_squint_ck<9,4> (gather + 4x4 area sum of 2B frames)", "bound": "hbm",
                                  "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
-                                 "frac": round(achieved / 8000.0, 4), "traffic": None,
+                                 "frac": round(achieved / 8000.0, 4),
+                                 "traffic": measured_traffic("squint_2B_frames",
+                                                             "paper_2602_21203_amd/csrc/kernels/squint.hip"),
                                  "avg_us": round(t_k * 1e6, 3), "algorithmic_bytes": bytes_per_launch}
     if a.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
