@@ -108,7 +108,7 @@ def measured_traffic(kernel_key, source):
     text = open(path).read()
     fetch_f = float(re_search(r"copy FETCH_SIZE [\d.]+ KiB -> factor ([\d.]+)", text))
     write_f = float(re_search(r"copy WRITE_SIZE [\d.]+ KiB -> factor ([\d.]+)", text))
-    m = re_search(kernel_key + r" source=(\w+)\s+([\d.]+)\s+([\d.]+)", text, groups=True)
+    m = re_search(kernel_key + r"\s+source=(\w+)\s+([\d.]+)\s+([\d.]+)", text, groups=True)
     if m is None:
         return None
     digest = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()[:16]
