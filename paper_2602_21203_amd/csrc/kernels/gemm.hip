@@ -49,40 +49,51 @@ template <bool KF> struct FMat {
   __device__ __forceinline__ float get(int z, int r, int k) const { return p[z * sz + r * lr + k * lk]; }
 };
 
+// Convolution geometry: input side H, output side HO, stride S.  The encoder's
+// shapes are compile-time constants (so the index divisions become multiplies);
+// Geo<0, 0, 0> carries them at run time for any other shape.
+template <int H_, int HO_, int S_> struct Geo {
+  int h, ho, s;
+  __device__ __forceinline__ int H() const { return H_ ? H_ : h; }
+  __device__ __forceinline__ int HO() const { return HO_ ? HO_ : ho; }
+  __device__ __forceinline__ int S() const { return S_ ? S_ : s; }
+};
+
 // im2col of an NCHW input: row = (n, oy, ox), k = (c, ky, kx)
-struct FConvPatch {
-  const float* x; int Cin, H, Ho, stride;
+template <class G> struct FConvPatch {
+  const float* x; int Cin; G g;
   static constexpr bool KFAST = false;
   __device__ __forceinline__ float get(int, int r, int k) const {
-    const int HoWo = Ho * Ho;
+    const int Ho = g.HO(), H = g.H(), HoWo = Ho * Ho;
     const int n = r / HoWo, p = r - n * HoWo, oy = p / Ho, ox = p - oy * Ho;
     const int c = k / 9, t = k - 9 * c, ky = t / 3, kx = t - 3 * ky;
-    return x[(((long long)n * Cin + c) * H + oy * stride + ky) * H + ox * stride + kx];
+    return x[(((long long)n * Cin + c) * H + oy * g.S() + ky) * H + ox * g.S() + kx];
   }
 };
 // the same patch matrix transposed: row = (c, ky, kx), k = (n, oy, ox)
-struct FConvPatchT {
-  FConvPatch f;
+template <class G> struct FConvPatchT {
+  FConvPatch<G> f;
   static constexpr bool KFAST = true;
   __device__ __forceinline__ float get(int z, int r, int k) const { return f.get(z, k, r); }
 };
 // gradient at a conv's pre-activation, transposed: row = f, k = (n, p); the
 // upstream gradient is masked by the conv's ReLU output
-struct FConvGradT {
-  const float* dout; const float* out; int F, HoWo;
+template <class G> struct FConvGradT {
+  const float* dout; const float* out; int F; G g;
   static constexpr bool KFAST = true;
   __device__ __forceinline__ float get(int, int r, int k) const {
+    const int HoWo = g.HO() * g.HO();
     const int n = k / HoWo, p = k - n * HoWo;
     const long long i = ((long long)n * F + r) * HoWo + p;
     return out[i] > 0.f ? dout[i] : 0.f;
   }
 };
 // input gradient of a stride-1 conv: row = (n, iy, ix), k = (f, ky, kx)
-struct FConvDxA {
-  const float* dout; const float* out; int F, Hin, Ho;
+template <class G> struct FConvDxA {
+  const float* dout; const float* out; int F; G g;
   static constexpr bool KFAST = false;
   __device__ __forceinline__ float get(int, int r, int k) const {
-    const int HW = Hin * Hin;
+    const int Hin = g.H(), Ho = g.HO(), HW = Hin * Hin;
     const int n = r / HW, q = r - n * HW, iy = q / Hin, ix = q - iy * Hin;
     const int f = k / 9, t = k - 9 * f, ky = t / 3, kx = t - 3 * ky;
     const int oy = iy - ky, ox = ix - kx;
@@ -160,6 +171,39 @@ __device__ __forceinline__ void stage(const float (&r)[EL], T* tile) {
   }
 }
 
+// Main loop: the operand slices of the next STAGES K-steps are in flight in
+// registers at any time (the loop is unrolled by STAGES so every register slot
+// is a compile-time index), so the global-load latency is paid about once per
+// STAGES steps instead of once per step.
+template <bool BF16>
+__device__ __forceinline__ void mma_step(const typename Cfg<BF16>::T* As, const typename Cfg<BF16>::T* Bs,
+                                         v4f (&acc)[2][2], int wave, int li, int lq) {
+  using C = Cfg<BF16>;
+  constexpr int LD = 4 * C::KW + C::PAD;
+  if constexpr (!BF16) {
+#pragma unroll
+    for (int kk = 0; kk < C::KW; kk += 4) {
+      const int kq = wave * C::KW + kk + lq;
+      const float a0 = As[li * LD + kq], a1 = As[(16 + li) * LD + kq];
+      const float b0 = Bs[li * LD + kq], b1 = Bs[(16 + li) * LD + kq];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+  } else {
+    const int kq = wave * 32 + 8 * lq;
+    const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[li * LD + kq]);
+    const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(16 + li) * LD + kq]);
+    const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[li * LD + kq]);
+    const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[(16 + li) * LD + kq]);
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
 template <bool BF16, class FA, class FB, class ST, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart sp, int M, int N, int K,
                                                    int kchunk) {
@@ -168,6 +212,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
   constexpr int BK = 4 * C::KW;
   constexpr int LD = BK + C::PAD;
   constexpr int EL = kTile * BK / kThreads;
+  constexpr int STAGES = BF16 ? 4 : 6;
   constexpr int TILE_BYTES = 2 * kTile * LD * (int)sizeof(T);
   constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
   constexpr int LDS_BYTES = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
@@ -180,6 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
   const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
+  const int nk = kend > kbeg ? (kend - kbeg + BK - 1) / BK : 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
 
@@ -189,42 +235,30 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  float ra[EL], rb[EL];
-  if (kbeg < kend) {
-    fetch<FA, BK, EL>(fa, ra, z, m0, M, kbeg, kend);
-    fetch<FB, BK, EL>(fb, rb, z, n0, N, kbeg, kend);
-  }
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    stage<FA, BK, LD, EL>(ra, As);
-    stage<FB, BK, LD, EL>(rb, Bs);
-    __syncthreads();
-    if (k0 + BK < kend) {
-      fetch<FA, BK, EL>(fa, ra, z, m0, M, k0 + BK, kend);
-      fetch<FB, BK, EL>(fb, rb, z, n0, N, k0 + BK, kend);
-    }
-    if constexpr (!BF16) {
+  float ra[STAGES][EL], rb[STAGES][EL];
 #pragma unroll
-      for (int kk = 0; kk < C::KW; kk += 4) {
-        const int kq = wave * C::KW + kk + lq;
-        const float a0 = As[li * LD + kq], a1 = As[(16 + li) * LD + kq];
-        const float b0 = Bs[li * LD + kq], b1 = Bs[(16 + li) * LD + kq];
-        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
-      }
-    } else {
-      const int kq = wave * 32 + 8 * lq;
-      const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&As[li * LD + kq]);
-      const bf16x8 a1 = *reinterpret_cast<const bf16x8*>(&As[(16 + li) * LD + kq]);
-      const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bs[li * LD + kq]);
-      const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&Bs[(16 + li) * LD + kq]);
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+  for (int s = 0; s < STAGES; ++s) {
+    if (s < nk) {
+      fetch<FA, BK, EL>(fa, ra[s], z, m0, M, kbeg + s * BK, kend);
+      fetch<FB, BK, EL>(fb, rb[s], z, n0, N, kbeg + s * BK, kend);
     }
-    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; kt += STAGES) {
+#pragma unroll
+    for (int s = 0; s < STAGES; ++s) {
+      const int t = kt + s;
+      if (t < nk) {
+        stage<FA, BK, LD, EL>(ra[s], As);
+        stage<FB, BK, LD, EL>(rb[s], Bs);
+        __syncthreads();
+        if (t + STAGES < nk) {
+          fetch<FA, BK, EL>(fa, ra[s], z, m0, M, kbeg + (t + STAGES) * BK, kend);
+          fetch<FB, BK, EL>(fb, rb[s], z, n0, N, kbeg + (t + STAGES) * BK, kend);
+        }
+        mma_step<BF16>(As, Bs, acc, wave, li, lq);
+        __syncthreads();
+      }
+    }
   }
 
   // fixed-order sum of the four waves' partial tiles
@@ -320,14 +354,25 @@ int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C,
              scratch, scratch_floats, st, "gemm_nn");
 }
 
+template <class F>
+static int with_geo(int H, int Ho, int stride, F&& f) {
+  if (H == 16 && Ho == 7 && stride == 2) return f(Geo<16, 7, 2>{16, 7, 2});
+  if (H == 7 && Ho == 5 && stride == 1) return f(Geo<7, 5, 1>{7, 5, 1});
+  if (H == 5 && Ho == 3 && stride == 1) return f(Geo<5, 3, 1>{5, 3, 1});
+  return f(Geo<0, 0, 0>{H, Ho, stride});
+}
+
 int conv_fwd(int bf16, const float* x, int n, int Cin, int H, int stride, const float* W, const float* b, int F,
              float* out, hipStream_t st) {
   const int Ho = (H - 3) / stride + 1;
   const int K = Cin * 9;
-  FConvPatch fa{x, Cin, H, Ho, stride};
-  FMat<true> fb{W, K, 1, 0};
-  StConv sc{out, F, Ho * Ho, b, 1};
-  return run(bf16, n * Ho * Ho, F, K, 1, fa, fb, sc, nullptr, 0, st, "conv_fwd");
+  return with_geo(H, Ho, stride, [&](auto g) {
+    using G = decltype(g);
+    FConvPatch<G> fa{x, Cin, g};
+    FMat<true> fb{W, K, 1, 0};
+    StConv sc{out, F, Ho * Ho, b, 1};
+    return run(bf16, n * Ho * Ho, F, K, 1, fa, fb, sc, nullptr, 0, st, "conv_fwd");
+  });
 }
 
 size_t conv_dw_scratch_floats(int n, int Cin, int H, int stride, int F) {
@@ -339,19 +384,25 @@ int conv_dw(int bf16, const float* x, int n, int Cin, int H, int stride, const f
             int F, float* dW, float* part, size_t part_floats, hipStream_t st) {
   const int Ho = (H - 3) / stride + 1;
   const int K = Cin * 9;
-  FConvGradT fa{dout, out, F, Ho * Ho};
-  FConvPatchT fb{FConvPatch{x, Cin, H, Ho, stride}};
-  StMat sm{dW, K, 0, nullptr, 0, 0, 0};
-  return run(bf16, F, K, n * Ho * Ho, 1, fa, fb, sm, part, part_floats, st, "conv_dw");
+  return with_geo(H, Ho, stride, [&](auto g) {
+    using G = decltype(g);
+    FConvGradT<G> fa{dout, out, F, g};
+    FConvPatchT<G> fb{FConvPatch<G>{x, Cin, g}};
+    StMat sm{dW, K, 0, nullptr, 0, 0, 0};
+    return run(bf16, F, K, n * Ho * Ho, 1, fa, fb, sm, part, part_floats, st, "conv_dw");
+  });
 }
 
 int conv_dx(int bf16, const float* dout, const float* out, int n, int Cin, int H, const float* W, int F, float* dx,
             hipStream_t st) {
   const int Ho = H - 2;
-  FConvDxA fa{dout, out, F, H, Ho};
-  FConvDxB fb{W, Cin};
-  StConv sc{dx, Cin, H * H, nullptr, 0};
-  return run(bf16, n * H * H, Cin, F * 9, 1, fa, fb, sc, nullptr, 0, st, "conv_dx");
+  return with_geo(H, Ho, 1, [&](auto g) {
+    using G = decltype(g);
+    FConvDxA<G> fa{dout, out, F, g};
+    FConvDxB fb{W, Cin};
+    StConv sc{dx, Cin, H * H, nullptr, 0};
+    return run(bf16, n * H * H, Cin, F * 9, 1, fa, fb, sc, nullptr, 0, st, "conv_dx");
+  });
 }
 
 }  // namespace sq
