@@ -211,6 +211,11 @@ SQ_API int sq_gemm(sq_prec prec, int M, int N, int K, int batch, const float* A,
 SQ_API int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float* params, float* target,
                     float* adam_m, float* adam_v, float* grads, int* counters, sq_agent** out /*[host]*/);
 SQ_API int sq_agent_destroy(sq_agent* agent);
+/* The agent keeps a packed copy of the linear weights (rows padded and aligned
+ * for 16-byte loads) that its updates refresh.  After the caller changes params
+ * or target itself (e.g. loading a checkpoint), call sq_agent_sync before the
+ * next sac_update or act. */
+SQ_API int sq_agent_sync(sq_agent* agent, sq_stream_t stream);
 
 /* n_updates SAC updates (Alg. 1 inner loop, with the readings stated in the
  * design notes): per update, draw batch replay indices and noise from Philox

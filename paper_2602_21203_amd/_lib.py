@@ -69,6 +69,7 @@ def _load():
         "adam_step": (c_int, [c_vp, c_vp, c_vp, c_vp, c_ll, P(HParams), c_vp, c_vp, c_vp, c_ll, c_vp]),
         "sq_agent_create": (c_int, [P(Dims), P(HParams), c_int, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, P(c_vp)]),
         "sq_agent_destroy": (c_int, [c_vp]),
+        "sq_agent_sync": (c_int, [c_vp, c_vp]),
         "sac_update": (c_int, [c_vp, P(Replay), c_int, c_vp, c_vp]),
         "sac_update_eager": (c_int, [c_vp, P(Replay), c_int, c_vp, c_vp]),
         "act": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_ull, c_vp, c_vp]),

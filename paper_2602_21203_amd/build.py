@@ -41,21 +41,25 @@ def _compile(src):
     return obj, err
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, extra=()):
+    """Compile every source and link libsquint.so (or `out`); `extra` adds
+    compiler flags (e.g. -D tuning macros for experiments)."""
     os.makedirs(OBJ, exist_ok=True)
+    FLAGS.extend(extra)
     with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as ex:
         results = list(ex.map(_compile, SOURCES))
     for _, err in results:
         if verbose and err.strip():
             print(err)
     objs = [o for o, _ in results]
-    tmp = OUT + ".tmp"
+    target = out or OUT
+    tmp = target + ".tmp"
     cmd = [hipcc(), "-shared", f"--offload-arch={ARCH}", "-fvisibility=hidden", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed\n" + r.stdout + r.stderr)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -162,7 +162,7 @@ int critic_fwd(const sq_dims* dims, sq_prec prec, const float* critic_params, co
   plan_op(net, SQ_OP_CRITIC, n, ws_base(ws), &w);
   hipStream_t st = (hipStream_t)stream;
   SQ_TRY_HIP(hipMemcpyAsync(w.feat, feat, (size_t)n * net.flat * 4, hipMemcpyDeviceToDevice, st));
-  return critic_forward(net, prec == SQ_BF16, critic_params, L, w.feat, net.flat, proprio, dims->proprio, action,
+  return critic_forward(net, prec == SQ_BF16, critic_params, nullptr, L, w.feat, net.flat, proprio, dims->proprio, action,
                         dims->action, n, logits, w.c, st);
 }
 
@@ -176,7 +176,7 @@ int critic_bwd(const sq_dims* dims, sq_prec prec, const float* critic_params, co
   make_layout(net, &L);
   CriticWs w;
   plan_op(net, SQ_OP_CRITIC, n, ws_base((void*)ws), &w);
-  return critic_backward(net, prec == SQ_BF16, critic_params, L, w.feat, net.flat, dlogits, n, w.c, dparams, dfeat,
+  return critic_backward(net, prec == SQ_BF16, critic_params, nullptr, L, w.feat, net.flat, dlogits, n, w.c, dparams, dfeat,
                          daction, (hipStream_t)stream);
 }
 
@@ -207,7 +207,7 @@ int actor_fwd(const sq_dims* dims, sq_prec prec, const sq_hparams* hp, const flo
   hipStream_t st = (hipStream_t)stream;
   SQ_TRY_HIP(hipMemcpyAsync(w.feat, feat, (size_t)n * net.flat * 4, hipMemcpyDeviceToDevice, st));
   if (eps) SQ_TRY_HIP(hipMemcpyAsync(w.eps, eps, (size_t)n * dims->action * 4, hipMemcpyDeviceToDevice, st));
-  return actor_forward(net, prec == SQ_BF16, actor_params, L, w.feat, net.flat, proprio, dims->proprio,
+  return actor_forward(net, prec == SQ_BF16, actor_params, nullptr, L, w.feat, net.flat, proprio, dims->proprio,
                        eps ? w.eps : nullptr, n, hp->log_std_min, hp->log_std_max, action, logp, w.a, st);
 }
 
@@ -222,7 +222,7 @@ int actor_bwd(const sq_dims* dims, sq_prec prec, const sq_hparams* hp, const flo
   make_layout(net, &L);
   ActorWs w;
   plan_op(net, SQ_OP_ACTOR, n, ws_base((void*)ws), &w);
-  return actor_backward(net, prec == SQ_BF16, actor_params, L, w.feat, net.flat, w.eps, n, daction, dims->action,
+  return actor_backward(net, prec == SQ_BF16, actor_params, nullptr, L, w.feat, net.flat, w.eps, n, daction, dims->action,
                         dlogp, nullptr, 0.f, hp->log_std_min, hp->log_std_max, w.a, dparams, (hipStream_t)stream);
 }
 
@@ -233,7 +233,7 @@ int adam_step(float* p, const float* g, float* m, float* v, long long n, const s
   if (n == 0) return SQ_OK;
   SQ_REQUIRE(p && g && m && v && step, "NULL argument");
   SQ_REQUIRE(ema_begin >= 0 && ema_begin <= n, "ema_begin out of range");
-  return adam(p, g, m, v, n, hp, step, ema_target, ema_begin, p_bf16, (hipStream_t)stream);
+  return adam(p, g, m, v, n, hp, step, ema_target, ema_begin, p_bf16, nullptr, (hipStream_t)stream);
 }
 
 int sq_gemm(sq_prec prec, int M, int N, int K, int batch, const float* A, long long a_lr, long long a_lk,

@@ -31,15 +31,15 @@ void plan_act(const Net& net, int n, Bump& b, ActBufs* w) {
   w->noise = b.take<float>((size_t)n * net.d.action);
 }
 
-int enqueue_act(const Net& net, const Layout& L, const sq_hparams& hp, const float* params, const ActBufs& w,
-                const uint8_t* frames, const float* proprio, int n, int sample, unsigned long long request_id,
-                float* action_out, hipStream_t st) {
+int enqueue_act(const Net& net, const Layout& L, const sq_hparams& hp, const float* params, const float* pack,
+                const ActBufs& w, const uint8_t* frames, const float* proprio, int n, int sample,
+                unsigned long long request_id, float* action_out, hipStream_t st) {
   const sq_dims& d = net.d;
   const int bf = hp.prec == SQ_BF16;
   SQ_TRY(launch_squint(frames, nullptr, n, d.H, d.W, d.C, d.k, 0, w.x, net.img, st));
   SQ_TRY(encoder_forward(net, bf, params, L, w.x, n, w.e, st));
   if (sample) SQ_TRY(launch_act_noise(hp.seed, request_id, n, d.action, w.noise, st));
-  return actor_forward(net, bf, params + L.actor_begin, L, w.e.h[d.n_conv - 1], net.flat, proprio, d.proprio,
+  return actor_forward(net, bf, params + L.actor_begin, pack, L, w.e.h[d.n_conv - 1], net.flat, proprio, d.proprio,
                        sample ? w.noise : nullptr, n, hp.log_std_min, hp.log_std_max, action_out, nullptr, w.a, st);
 }
 
@@ -68,6 +68,7 @@ struct sq_agent {
   sq_hparams hp;
   int B;
   float *params, *target, *m, *v, *grads;
+  float *pack, *tpack;   // packed linear weights of params and of the target critic
   int* ctr;
   void* ws = nullptr;
   bool own_grads = false;
@@ -83,6 +84,7 @@ struct sq_agent {
   int act_cap;
   ActBufs actw;
   std::vector<GraphEntry> graphs;
+  PackArgs pk_critic, pk_actor;   // pack refresh tables of the two Adam launches
 };
 
 static size_t plan_agent(sq_agent* g, char* base) {
@@ -116,6 +118,8 @@ static size_t plan_agent(sq_agent* g, char* base) {
   g->qa_row = b.take<float>(B);
   g->scal = b.take<float>(8);
   g->da = b.take<float>((size_t)B * A);
+  g->pack = b.take<float>(g->L.pack_total);
+  g->tpack = b.take<float>(g->L.pack_critic_end);
   if (!g->own_grads) {
   } else {
     g->grads = b.take<float>(g->L.total);
@@ -139,34 +143,36 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, d.H, d.W, d.C, d.k, g->x, st));
   SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st));
   const float* feat = g->enc.h[d.n_conv - 1];
-  SQ_TRY(actor_forward(net, bf, P + L.actor_begin, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
+  SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
                        g->logp2B, g->actor, st));
   // distributional soft target from the averaged twin target critics
-  SQ_TRY(critic_forward(net, bf, g->target, L, feat + (size_t)B * flat, flat, g->S2 + (size_t)B * S, S,
+  SQ_TRY(critic_forward(net, bf, g->target, g->tpack, L, feat + (size_t)B * flat, flat, g->S2 + (size_t)B * S, S,
                         g->act2B + (size_t)B * A, A, B, g->logits_t, g->aux, st));
   SQ_TRY(project_target(g->logits_t, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma,
                         g->mt, g->tgt_row, st));
   // critic + encoder step
-  SQ_TRY(critic_forward(net, bf, P + L.critic_begin, L, feat, flat, g->S2, S, g->Arep, A, B, g->logits, g->crit, st));
+  SQ_TRY(critic_forward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->S2, S, g->Arep, A, B, g->logits,
+                        g->crit, st));
   SQ_TRY(ce_loss(g->logits, g->mt, B, N, d.v_min, d.v_max, g->dlogits, g->loss_row, g->q_row, st));
-  SQ_TRY(critic_backward(net, bf, P + L.critic_begin, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
+  SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
                          g->dfeat, nullptr, st));
   SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st));
-  SQ_TRY(adam(P, G, g->m, g->v, L.critic_end, &hp, g->ctr + CTR_TC, g->target, L.critic_begin, nullptr, st));
+  SQ_TRY(adam(P, G, g->m, g->v, L.critic_end, &hp, g->ctr + CTR_TC, g->target, L.critic_begin, nullptr, &g->pk_critic,
+              st));
   // temperature
   SQ_TRY(alpha_step(g->logp2B, B, hp.target_entropy, P + L.log_alpha, G + L.log_alpha, g->m + L.log_alpha,
                     g->v + L.log_alpha, g->ctr, &hp, g->scal, st));
   // delayed actor step against the updated critic
   if (actor_step) {
-    SQ_TRY(critic_forward(net, bf, P + L.critic_begin, L, feat, flat, g->S2, S, g->act2B, A, B, g->logits_q, g->aux,
-                          st));
+    SQ_TRY(critic_forward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->S2, S, g->act2B, A, B, g->logits_q,
+                          g->aux, st));
     SQ_TRY(expected_q_grad(g->logits_q, B, N, d.v_min, d.v_max, g->dlogits_q, g->qa_row, st));
-    SQ_TRY(critic_backward(net, bf, P + L.critic_begin, L, feat, flat, g->dlogits_q, B, g->aux, nullptr, nullptr,
+    SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits_q, B, g->aux, nullptr, nullptr,
                            g->da, st));
-    SQ_TRY(actor_backward(net, bf, P + L.actor_begin, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
+    SQ_TRY(actor_backward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
                           1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st));
     SQ_TRY(adam(P + L.actor_begin, G + L.actor_begin, g->m + L.actor_begin, g->v + L.actor_begin,
-                L.actor_end - L.actor_begin, &hp, g->ctr + CTR_TA, nullptr, 0, nullptr, st));
+                L.actor_end - L.actor_begin, &hp, g->ctr + CTR_TA, nullptr, 0, nullptr, &g->pk_actor, st));
   }
   return finish_update(g->loss_row, g->q_row, g->tgt_row, g->logp2B, g->qa_row, g->scal, B, actor_step, g->ctr, stats,
                        st);
@@ -235,6 +241,25 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
   }
   char* base = (char*)(((uintptr_t)g->ws + 255) & ~(uintptr_t)255);
   plan_agent(g, base);
+  {
+    const Layout& L = g->L;
+    g->pk_critic = PackArgs{};
+    g->pk_actor = PackArgs{};
+    for (int i = 0; i < L.n_pack; ++i) {
+      PackArgs& t = L.pack[i].critic ? g->pk_critic : g->pk_actor;
+      t.seg[t.n++] = L.pack[i];
+    }
+    g->pk_critic.pack = g->pk_actor.pack = g->pack;
+    g->pk_critic.tpack = g->tpack;
+    g->pk_critic.p_begin = 0;
+    g->pk_actor.p_begin = L.actor_begin;
+  }
+  if (pack_weights(g->L, params, target, g->pack, g->tpack, nullptr) != SQ_OK ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(g->ws);
+    delete g;
+    return SQ_EDEVICE;
+  }
   int host_ctr[CTR_N];
   if (hipMemcpy(host_ctr, counters, sizeof(host_ctr), hipMemcpyDeviceToHost) != hipSuccess) {
     (void)hipFree(g->ws);
@@ -332,8 +357,13 @@ int act(sq_agent* g, const uint8_t* frames, const float* proprio, int n, int sam
     set_error("NULL argument to act");
     return SQ_EINVAL;
   }
-  return enqueue_act(g->net, g->L, g->hp, g->params, g->actw, frames, proprio, n, sample ? 1 : 0, request_id,
-                     action_out, (hipStream_t)stream);
+  return enqueue_act(g->net, g->L, g->hp, g->params, g->pack, g->actw, frames, proprio, n, sample ? 1 : 0,
+                     request_id, action_out, (hipStream_t)stream);
+}
+
+int sq_agent_sync(sq_agent* g, sq_stream_t stream) {
+  if (!g) { set_error("agent is NULL"); return SQ_EINVAL; }
+  return pack_weights(g->L, g->params, g->target, g->pack, g->tpack, (hipStream_t)stream);
 }
 
 int sq_agent_act_capacity(sq_agent* g, int* n) {
@@ -350,4 +380,5 @@ const Net& agent_net(const sq_agent* g) { return g->net; }
 const Layout& agent_layout(const sq_agent* g) { return g->L; }
 const sq_hparams& agent_hp(const sq_agent* g) { return g->hp; }
 const float* agent_params(const sq_agent* g) { return g->params; }
+const float* agent_pack(const sq_agent* g) { return g->pack; }
 }  // namespace sq

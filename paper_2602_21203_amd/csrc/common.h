@@ -46,14 +46,18 @@ struct Net {
   int flat;            // encoder feature width
   int cin_critic;      // proj + proprio + action
   int cin_actor;       // proj + proprio
+  int cpad, apad;      // their row strides in workspace buffers (multiples of 8)
   int img;             // C * side * side (one squinted image)
 };
 int make_net(const sq_dims* d, Net* n);   // validates; SQ_EINVAL on bad dims
 
-// canonical flat parameter layout (offsets in floats)
-struct Dense { long long W, b, g, beta; int out, in; };
-struct Head { long long W, b; int out, in; };
+// canonical flat parameter layout (offsets in floats).  Wp / ldp: the weight's
+// place in the packed copy (rows padded to a multiple of 8 floats, every
+// tensor 64-float aligned) that the vector GEMM path reads.
+struct Dense { long long W, b, g, beta; int out, in; long long Wp; int ldp; };
+struct Head { long long W, b; int out, in; long long Wp; int ldp; };
 struct Twin { Dense l1, l2; Head out; };
+struct PackSeg { long long src, dst; int rows, cols, ldp, critic; };
 struct Layout {
   long long conv_W[4], conv_b[4];
   Dense ctrunk; Twin q[2];
@@ -62,6 +66,11 @@ struct Layout {
   long long enc_begin, enc_end, critic_begin, critic_end, actor_begin, actor_end, total;
   int n_tensors;
   long long tensor_off[64];
+  // packed linear weights: critic block first ([0, pack_critic_end), also the
+  // layout of the target critic's pack), then the actor block
+  int n_pack;
+  PackSeg pack[16];
+  long long pack_critic_end, pack_total;
 };
 void make_layout(const Net& n, Layout* L);
 
@@ -183,8 +192,18 @@ int conv_bias_chunks(int n, int HW);
 int conv_bias_grad(const float* dout, const float* out, int n, int F, int HW, float* db, float* part,
                    hipStream_t st);
 
-// adam.hip: step t = *step + 1 (not modified); EMA over i >= ema_begin
+// adam.hip: step t = *step + 1 (not modified); EMA over i >= ema_begin.
+// Packed weight copies (nullable): segments of `pk` whose src lies in
+// [p_begin, p_begin + n) are refreshed in `pack` with the new parameters and,
+// for critic segments, in `tpack` with the new target values.
+struct PackArgs {
+  int n; PackSeg seg[16];
+  float* pack; float* tpack; long long p_begin;
+};
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
-         float* ema_target, long long ema_begin, uint16_t* shadow, hipStream_t st);
+         float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st);
+// copy the linear weights of `params` (and the critic block of `target`) into packs
+int pack_weights(const Layout& L, const float* params, const float* target, float* pack, float* tpack,
+                 hipStream_t st);
 
 }  // namespace sq

@@ -8,11 +8,27 @@
 
 namespace sq {
 
+// the packed position of flat index i (relative to the optimiser's range), or -1
+__device__ __forceinline__ long long pack_pos(const PackArgs& pk, long long i, int* critic) {
+  const long long gi = i + pk.p_begin;
+  for (int s = 0; s < pk.n; ++s) {
+    const PackSeg& q = pk.seg[s];
+    const long long loc = gi - q.src;
+    if (loc >= 0 && loc < (long long)q.rows * q.cols) {
+      const long long r = loc / q.cols;
+      *critic = q.critic;
+      return q.dst + r * q.ldp + (loc - r * q.cols);
+    }
+  }
+  return -1;
+}
+
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, long long n,
                                               float lr, float b1, float b2, float eps,
                                               const int* __restrict__ step, float* __restrict__ ema,
-                                              long long ema_begin, float rho, uint16_t* __restrict__ shadow) {
+                                              long long ema_begin, float rho, uint16_t* __restrict__ shadow,
+                                              PackArgs pk) {
   const float t = (float)(*step + 1);
   const float bc1 = 1.f - powf(b1, t);
   const float bc2 = 1.f - powf(b2, t);
@@ -25,22 +41,57 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
     v[i] = vi;
     const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
     p[i] = pi;
+    float ei = 0.f;
     if (ema && i >= ema_begin) {
       float* e = ema + (i - ema_begin);
-      *e = rho * *e + (1.f - rho) * pi;
+      ei = rho * *e + (1.f - rho) * pi;
+      *e = ei;
     }
     if (shadow) shadow[i] = bf16_bits(pi);
+    if (pk.n) {
+      int critic = 0;
+      const long long d = pack_pos(pk, i, &critic);
+      if (d >= 0) {
+        pk.pack[d] = pi;
+        if (critic && pk.tpack && ema && i >= ema_begin) pk.tpack[d] = ei;
+      }
+    }
   }
 }
 
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
-         float* ema_target, long long ema_begin, uint16_t* shadow, hipStream_t st) {
+         float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st) {
   if (n <= 0) return SQ_OK;
   long long blocks = (n + 255) / 256;
   if (blocks > 2048) blocks = 2048;
+  PackArgs none{};
   k_adam<<<(int)blocks, 256, 0, st>>>(p, g, m, v, n, hp->lr, hp->beta1, hp->beta2, hp->adam_eps, step, ema_target,
-                                      ema_begin, hp->rho, shadow);
+                                      ema_begin, hp->rho, shadow, pk ? *pk : none);
   return launch_status("adam");
+}
+
+// rows of every packed segment; padding columns are written as zero
+__global__ void k_pack(PackArgs pk, const float* __restrict__ params, const float* __restrict__ target,
+                       long long critic_begin) {
+  const PackSeg q = pk.seg[blockIdx.y];
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < (long long)q.rows * q.ldp;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / q.ldp, c = e - r * q.ldp;
+    const bool in = c < q.cols;
+    pk.pack[q.dst + e] = in ? params[q.src + r * q.cols + c] : 0.f;
+    if (q.critic && pk.tpack) pk.tpack[q.dst + e] = in ? target[q.src - critic_begin + r * q.cols + c] : 0.f;
+  }
+}
+
+int pack_weights(const Layout& L, const float* params, const float* target, float* pack, float* tpack,
+                 hipStream_t st) {
+  PackArgs pk{};
+  pk.n = L.n_pack;
+  for (int i = 0; i < L.n_pack; ++i) pk.seg[i] = L.pack[i];
+  pk.pack = pack;
+  pk.tpack = target ? tpack : nullptr;
+  k_pack<<<dim3(64, L.n_pack), 256, 0, st>>>(pk, params, target, L.critic_begin);
+  return launch_status("pack_weights");
 }
 
 }  // namespace sq

@@ -175,11 +175,10 @@ __device__ __forceinline__ void stage(const float (&r)[EL], T* tile) {
 // registers at any time (the loop is unrolled by STAGES so every register slot
 // is a compile-time index), so the global-load latency is paid about once per
 // STAGES steps instead of once per step.
-template <bool BF16>
+template <bool BF16, int LD>
 __device__ __forceinline__ void mma_step(const typename Cfg<BF16>::T* As, const typename Cfg<BF16>::T* Bs,
                                          v4f (&acc)[2][2], int wave, int li, int lq) {
   using C = Cfg<BF16>;
-  constexpr int LD = 4 * C::KW + C::PAD;
   if constexpr (!BF16) {
 #pragma unroll
     for (int kk = 0; kk < C::KW; kk += 4) {
@@ -212,7 +211,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
   constexpr int BK = 4 * C::KW;
   constexpr int LD = BK + C::PAD;
   constexpr int EL = kTile * BK / kThreads;
-  constexpr int STAGES = BF16 ? 4 : 6;
+#ifdef SQ_GEMM_STAGES
+  constexpr int STAGES = SQ_GEMM_STAGES;
+#else
+  constexpr int STAGES = 2;
+#endif
   constexpr int TILE_BYTES = 2 * kTile * LD * (int)sizeof(T);
   constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
   constexpr int LDS_BYTES = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
           fetch<FA, BK, EL>(fa, ra[s], z, m0, M, kbeg + (t + STAGES) * BK, kend);
           fetch<FB, BK, EL>(fb, rb[s], z, n0, N, kbeg + (t + STAGES) * BK, kend);
         }
-        mma_step<BF16>(As, Bs, acc, wave, li, lq);
+        mma_step<BF16, LD>(As, Bs, acc, wave, li, lq);
         __syncthreads();
       }
     }
@@ -281,6 +284,155 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
     if (gr < M && gc < N) {
       if constexpr (SPLIT) sp.put(z, split, gr, gc, v); else st.put(z, gr, gc, v);
     }
+  }
+}
+
+// ---------------------------------------------------------------- vector-load kernel
+// Plain strided operands whose contiguous dimension is 16-byte aligned (the
+// activations and the packed weight copies): every load brings 4 elements,
+// interior tiles take no per-element branch, and 4 consecutive k of one row go
+// to LDS in one store.  Same tiling, wave split and fixed reduction order as
+// k_gemm, so the two produce identical results.
+template <bool KF> struct VMat {
+  const float* p; long long lr, lk, sz;
+};
+
+template <bool KF, int BK, int VE>
+__device__ __forceinline__ void vfetch(const VMat<KF>& f, float4 (&r)[VE], int z, int row0, int rows, int k0,
+                                       int kend) {
+  const float* base = f.p + z * f.sz;
+#pragma unroll
+  for (int i = 0; i < VE; ++i) {
+    const int v = (int)threadIdx.x + kThreads * i;
+    int rr, kk;
+    if constexpr (KF) { rr = v / (BK / 4); kk = (v - rr * (BK / 4)) * 4; }
+    else { kk = v / (kTile / 4); rr = (v - kk * (kTile / 4)) * 4; }
+    const int gr = row0 + rr, gk = k0 + kk;
+    float4 x;
+    if constexpr (KF) {
+      const float* q = base + gr * f.lr + gk;
+      if (gr < rows && gk + 4 <= kend) {
+        x = *reinterpret_cast<const float4*>(q);
+      } else {
+        const bool rv = gr < rows;
+        x.x = (rv && gk + 0 < kend) ? q[0] : 0.f;
+        x.y = (rv && gk + 1 < kend) ? q[1] : 0.f;
+        x.z = (rv && gk + 2 < kend) ? q[2] : 0.f;
+        x.w = (rv && gk + 3 < kend) ? q[3] : 0.f;
+      }
+    } else {
+      const float* q = base + gk * f.lk + gr;
+      if (gk < kend && gr + 4 <= rows) {
+        x = *reinterpret_cast<const float4*>(q);
+      } else {
+        const bool kv = gk < kend;
+        x.x = (kv && gr + 0 < rows) ? q[0] : 0.f;
+        x.y = (kv && gr + 1 < rows) ? q[1] : 0.f;
+        x.z = (kv && gr + 2 < rows) ? q[2] : 0.f;
+        x.w = (kv && gr + 3 < rows) ? q[3] : 0.f;
+      }
+    }
+    r[i] = x;
+  }
+}
+
+template <bool KF, int BK, int LD, int VE, bool BF16>
+__device__ __forceinline__ void vstage(const float4 (&r)[VE], typename Cfg<BF16>::T* tile) {
+#pragma unroll
+  for (int i = 0; i < VE; ++i) {
+    const int v = (int)threadIdx.x + kThreads * i;
+    int rr, kk;
+    if constexpr (KF) { rr = v / (BK / 4); kk = (v - rr * (BK / 4)) * 4; }
+    else { kk = v / (kTile / 4); rr = (v - kk * (kTile / 4)) * 4; }
+    const float4 x = r[i];
+    if constexpr (KF) {
+      if constexpr (BF16) {
+        uint2 w;
+        w.x = (unsigned)bf16_bits(x.x) | ((unsigned)bf16_bits(x.y) << 16);
+        w.y = (unsigned)bf16_bits(x.z) | ((unsigned)bf16_bits(x.w) << 16);
+        *reinterpret_cast<uint2*>(&tile[rr * LD + kk]) = w;
+      } else {
+        *reinterpret_cast<float4*>(&tile[rr * LD + kk]) = x;
+      }
+    } else {
+      using T = typename Cfg<BF16>::T;
+      tile[(rr + 0) * LD + kk] = to_t(x.x, (T*)nullptr);
+      tile[(rr + 1) * LD + kk] = to_t(x.y, (T*)nullptr);
+      tile[(rr + 2) * LD + kk] = to_t(x.z, (T*)nullptr);
+      tile[(rr + 3) * LD + kk] = to_t(x.w, (T*)nullptr);
+    }
+  }
+}
+
+template <bool BF16, bool AKF, bool BKF, class ST>
+__global__ __launch_bounds__(kThreads) void k_gemm_v(VMat<AKF> fa, VMat<BKF> fb, ST st, int M, int N, int K) {
+  using C = Cfg<BF16>;
+  using T = typename C::T;
+  constexpr int BK = 4 * C::KW;
+  constexpr int LD = BK + (BF16 ? 8 : 4);     // 16-byte aligned rows, conflict-free MFMA reads
+  constexpr int VE = kTile * BK / 4 / kThreads;
+  constexpr int STAGES = 2;
+  constexpr int TILE_BYTES = 2 * kTile * LD * (int)sizeof(T);
+  constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
+  constexpr int LDS_BYTES = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
+  __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
+  T* As = reinterpret_cast<T*>(lds);
+  T* Bs = As + kTile * LD;
+
+  const int z = blockIdx.z;
+  const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
+  const int nk = K > 0 ? (K + BK - 1) / BK : 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  float4 ra[STAGES][VE], rb[STAGES][VE];
+#pragma unroll
+  for (int s = 0; s < STAGES; ++s) {
+    if (s < nk) {
+      vfetch<AKF, BK, VE>(fa, ra[s], z, m0, M, s * BK, K);
+      vfetch<BKF, BK, VE>(fb, rb[s], z, n0, N, s * BK, K);
+    }
+  }
+  for (int kt = 0; kt < nk; kt += STAGES) {
+#pragma unroll
+    for (int s = 0; s < STAGES; ++s) {
+      const int t = kt + s;
+      if (t < nk) {
+        vstage<AKF, BK, LD, VE, BF16>(ra[s], As);
+        vstage<BKF, BK, LD, VE, BF16>(rb[s], Bs);
+        __syncthreads();
+        if (t + STAGES < nk) {
+          vfetch<AKF, BK, VE>(fa, ra[s], z, m0, M, (t + STAGES) * BK, K);
+          vfetch<BKF, BK, VE>(fb, rb[s], z, n0, N, (t + STAGES) * BK, K);
+        }
+        mma_step<BF16, LD>(As, Bs, acc, wave, li, lq);
+        __syncthreads();
+      }
+    }
+  }
+
+  float* red = reinterpret_cast<float*>(lds);
+  constexpr int RLD = kTile + 1;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        red[(wave * kTile + i * 16 + 4 * lq + q) * RLD + j * 16 + li] = acc[i][j][q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
+    const int r = e / kTile, c = e - r * kTile;
+    const float v = ((red[(0 * kTile + r) * RLD + c] + red[(1 * kTile + r) * RLD + c]) +
+                     red[(2 * kTile + r) * RLD + c]) + red[(3 * kTile + r) * RLD + c];
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < M && gc < N) st.put(z, gr, gc, v);
   }
 }
 
@@ -337,9 +489,39 @@ static int run(int bf16, int M, int N, int K, int batch, FA fa, FB fb, ST st, fl
 }
 
 // ---------------------------------------------------------------- public launchers
+// 1: contiguous along k, 0: contiguous along rows, -1: no 16-byte vector access
+static int vec_kind(const MatArg& a) {
+  if ((uintptr_t)a.p % 16 != 0 || a.sz % 4 != 0) return -1;
+  if (a.lk == 1 && a.lr % 4 == 0) return 1;
+  if (a.lr == 1 && a.lk % 4 == 0) return 0;
+  return -1;
+}
+
+template <bool BF16, bool AK, bool BKF>
+static int run_v(int M, int N, int K, int batch, const MatArg& A, const MatArg& B, const StMat& out, hipStream_t st) {
+  dim3 grid(cdiv(M, kTile), cdiv(N, kTile), batch);
+  k_gemm_v<BF16, AK, BKF, StMat><<<grid, kThreads, 0, st>>>(VMat<AK>{A.p, A.lr, A.lk, A.sz},
+                                                            VMat<BKF>{B.p, B.lr, B.lk, B.sz}, out, M, N, K);
+  return launch_status("gemm_v");
+}
+
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st) {
   StMat out{C.p, C.ld, C.sz, C.bias, C.bias_sz, C.accumulate, C.relu};
+  const int va = vec_kind(A), vb = vec_kind(B);
+  const bool small = cdiv(M, kTile) * cdiv(N, kTile) * batch < 96 && K > 1024;   // wants a K split
+  if (va >= 0 && vb >= 0 && M > 0 && N > 0 && batch > 0 && !(small && scratch)) {
+    if (bf16) {
+      if (va && vb) return run_v<true, true, true>(M, N, K, batch, A, B, out, st);
+      if (va) return run_v<true, true, false>(M, N, K, batch, A, B, out, st);
+      if (vb) return run_v<true, false, true>(M, N, K, batch, A, B, out, st);
+      return run_v<true, false, false>(M, N, K, batch, A, B, out, st);
+    }
+    if (va && vb) return run_v<false, true, true>(M, N, K, batch, A, B, out, st);
+    if (va) return run_v<false, true, false>(M, N, K, batch, A, B, out, st);
+    if (vb) return run_v<false, false, true>(M, N, K, batch, A, B, out, st);
+    return run_v<false, false, false>(M, N, K, batch, A, B, out, st);
+  }
   // pick the coalescing direction of each operand from its strides
   if (A.lk == 1 && B.lk == 1)
     return run(bf16, M, N, K, batch, FMat<true>{A.p, A.lr, A.lk, A.sz}, FMat<true>{B.p, B.lr, B.lk, B.sz}, out,

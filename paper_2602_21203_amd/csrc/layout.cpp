@@ -56,6 +56,8 @@ int make_net(const sq_dims* d, Net* n) {
   n->flat = d->F * s * s;
   n->cin_critic = d->proj + d->proprio + d->action;
   n->cin_actor = d->proj + d->proprio;
+  n->cpad = (n->cin_critic + 7) / 8 * 8;
+  n->apad = (n->cin_actor + 7) / 8 * 8;
   n->img = d->C * n->side * n->side;
   return SQ_OK;
 }
@@ -112,6 +114,30 @@ void make_layout(const Net& n, Layout* L) {
   L->total = off;
   L->n_tensors = t;
   L->tensor_off[t] = off;
+  // packed copy of the linear weights
+  long long poff = 0;
+  L->n_pack = 0;
+  auto pk = [&](long long src, int rows, int cols, int critic, long long* Wp, int* ldp) {
+    const int ld = (cols + 7) / 8 * 8;
+    poff = (poff + 63) / 64 * 64;
+    L->pack[L->n_pack++] = PackSeg{src, poff, rows, cols, ld, critic};
+    *Wp = poff;
+    *ldp = ld;
+    poff += (long long)rows * ld;
+  };
+  pk(L->ctrunk.W, L->ctrunk.out, L->ctrunk.in, 1, &L->ctrunk.Wp, &L->ctrunk.ldp);
+  for (int q = 0; q < 2; ++q) {
+    Twin& tq = L->q[q];
+    pk(tq.l1.W, tq.l1.out, tq.l1.in, 1, &tq.l1.Wp, &tq.l1.ldp);
+    pk(tq.l2.W, tq.l2.out, tq.l2.in, 1, &tq.l2.Wp, &tq.l2.ldp);
+    pk(tq.out.W, tq.out.out, tq.out.in, 1, &tq.out.Wp, &tq.out.ldp);
+  }
+  L->pack_critic_end = (poff + 63) / 64 * 64;
+  pk(L->atrunk.W, L->atrunk.out, L->atrunk.in, 0, &L->atrunk.Wp, &L->atrunk.ldp);
+  pk(L->al1.W, L->al1.out, L->al1.in, 0, &L->al1.Wp, &L->al1.ldp);
+  pk(L->al2.W, L->al2.out, L->al2.in, 0, &L->al2.Wp, &L->al2.ldp);
+  pk(L->aout.W, L->aout.out, L->aout.in, 0, &L->aout.Wp, &L->aout.ldp);
+  L->pack_total = (poff + 63) / 64 * 64;
 }
 
 }  // namespace sq

@@ -12,14 +12,23 @@
 
 namespace sq {
 
+// Y = X W^T + b; W rows `ldw` apart (the packed copy pads them), twins `szw` apart,
+// biases `szb` apart
 static int linear_fwd(int bf16, int n, int out, int in, int batch, const float* X, long long ldx, long long szx,
-                      const float* W, const float* b, long long szw, float* Y, long long ldy, long long szy,
-                      hipStream_t st) {
+                      const float* W, long long ldw, long long szw, const float* b, long long szb, float* Y,
+                      long long ldy, long long szy, hipStream_t st) {
   MatArg A{X, ldx, 1, szx};
-  MatArg Bm{W, in, 1, szw};
-  OutArg C{Y, ldy, szy, b, szw, 0, 0};
+  MatArg Bm{W, ldw, 1, szw};
+  OutArg C{Y, ldy, szy, b, szb, 0, 0};
   return gemm(bf16, n, out, in, batch, A, Bm, C, nullptr, 0, st);
 }
+
+// where a linear weight is read from: the packed copy when there is one
+struct WRef {
+  const float* base; const float* pack; long long base_begin;
+  const float* W(long long raw, long long packed) const { return pack ? pack + packed : base + (raw - base_begin); }
+  long long ld(int in, int ldp) const { return pack ? ldp : in; }
+};
 
 static int linear_dw(int bf16, int n, int out, int in, int batch, const float* dY, long long lddy, long long szdy,
                      const float* X, long long ldx, long long szx, float* dW, long long ldw, long long szw,
@@ -95,7 +104,7 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
 // ---------------------------------------------------------------- critic
 void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd) {
   const sq_dims& d = net.d;
-  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic;
+  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cpad;
   const int wmax = std::max(std::max(H, P), N);
   c->pre = b.take<float>((size_t)2 * n * wmax);
   c->X1 = b.take<float>((size_t)n * cin);
@@ -122,37 +131,43 @@ void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd) {
   }
 }
 
-int critic_forward(const Net& net, int bf16, const float* cp, const Layout& L, const float* feat, long long ld_feat,
-                   const float* s, long long ld_s, const float* a, long long ld_a, int n, float* logits,
-                   const CriticBufs& c, hipStream_t st) {
+int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
+                   long long ld_feat, const float* s, long long ld_s, const float* a, long long ld_a, int n,
+                   float* logits, const CriticBufs& c, hipStream_t st) {
   const sq_dims& d = net.d;
-  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic;
+  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic, cld = net.cpad;
   const long long c0 = L.critic_begin;
   const long long tw = L.q[1].l1.W - L.q[0].l1.W;
+  const WRef w{cp, cpack, c0};
+  const long long twW = cpack ? L.q[1].l1.Wp - L.q[0].l1.Wp : tw;
+  const long long nH = (long long)n * H;
   const Dense& T = L.ctrunk;
   const Twin& q = L.q[0];
-  SQ_TRY(linear_fwd(bf16, n, P, net.flat, 1, feat, ld_feat, 0, cp + (T.W - c0), cp + (T.b - c0), 0, c.pre, P, 0, st));
-  SQ_TRY(ln_act_fwd(c.pre, P, 0, n, P, 1, cp + (T.g - c0), cp + (T.beta - c0), 0, 1, c.X1, cin, 0, c.t.xhat, c.t.rstd,
-                    s, ld_s, d.proprio, a, ld_a, d.action, st));
-  SQ_TRY(linear_fwd(bf16, n, H, cin, 2, c.X1, cin, 0, cp + (q.l1.W - c0), cp + (q.l1.b - c0), tw, c.pre, H,
-                    (long long)n * H, st));
-  SQ_TRY(ln_act_fwd(c.pre, H, (long long)n * H, n, H, 2, cp + (q.l1.g - c0), cp + (q.l1.beta - c0), tw, 0, c.g1, H,
-                    (long long)n * H, c.l1.xhat, c.l1.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
-  SQ_TRY(linear_fwd(bf16, n, H, H, 2, c.g1, H, (long long)n * H, cp + (q.l2.W - c0), cp + (q.l2.b - c0), tw, c.pre, H,
-                    (long long)n * H, st));
-  SQ_TRY(ln_act_fwd(c.pre, H, (long long)n * H, n, H, 2, cp + (q.l2.g - c0), cp + (q.l2.beta - c0), tw, 0, c.g2, H,
-                    (long long)n * H, c.l2.xhat, c.l2.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
-  return linear_fwd(bf16, n, N, H, 2, c.g2, H, (long long)n * H, cp + (q.out.W - c0), cp + (q.out.b - c0), tw,
-                    logits, N, (long long)n * N, st);
+  SQ_TRY(linear_fwd(bf16, n, P, net.flat, 1, feat, ld_feat, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0,
+                    cp + (T.b - c0), 0, c.pre, P, 0, st));
+  SQ_TRY(ln_act_fwd(c.pre, P, 0, n, P, 1, cp + (T.g - c0), cp + (T.beta - c0), 0, 1, c.X1, cld, 0, c.t.xhat,
+                    c.t.rstd, s, ld_s, d.proprio, a, ld_a, d.action, st));
+  SQ_TRY(linear_fwd(bf16, n, H, cin, 2, c.X1, cld, 0, w.W(q.l1.W, q.l1.Wp), w.ld(q.l1.in, q.l1.ldp), twW,
+                    cp + (q.l1.b - c0), tw, c.pre, H, nH, st));
+  SQ_TRY(ln_act_fwd(c.pre, H, nH, n, H, 2, cp + (q.l1.g - c0), cp + (q.l1.beta - c0), tw, 0, c.g1, H, nH, c.l1.xhat,
+                    c.l1.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
+  SQ_TRY(linear_fwd(bf16, n, H, H, 2, c.g1, H, nH, w.W(q.l2.W, q.l2.Wp), w.ld(q.l2.in, q.l2.ldp), twW,
+                    cp + (q.l2.b - c0), tw, c.pre, H, nH, st));
+  SQ_TRY(ln_act_fwd(c.pre, H, nH, n, H, 2, cp + (q.l2.g - c0), cp + (q.l2.beta - c0), tw, 0, c.g2, H, nH, c.l2.xhat,
+                    c.l2.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
+  return linear_fwd(bf16, n, N, H, 2, c.g2, H, nH, w.W(q.out.W, q.out.Wp), w.ld(q.out.in, q.out.ldp), twW,
+                    cp + (q.out.b - c0), tw, logits, N, (long long)n * N, st);
 }
 
-int critic_backward(const Net& net, int bf16, const float* cp, const Layout& L, const float* feat, long long ld_feat,
-                    const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat, float* daction,
-                    hipStream_t st) {
+int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
+                    long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
+                    float* daction, hipStream_t st) {
   const sq_dims& d = net.d;
-  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic, A = d.action;
+  const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic, cld = net.cpad, A = d.action;
   const long long c0 = L.critic_begin;
   const long long tw = L.q[1].l1.W - L.q[0].l1.W;
+  const WRef w{cp, cpack, c0};
+  const long long twW = cpack ? L.q[1].l1.Wp - L.q[0].l1.Wp : tw;
   const long long nH = (long long)n * H, nN = (long long)n * N;
   const Dense& T = L.ctrunk;
   const Twin& q = L.q[0];
@@ -163,50 +178,54 @@ int critic_backward(const Net& net, int bf16, const float* cp, const Layout& L, 
     SQ_TRY(linear_dw(bf16, n, N, H, 2, dlogits, N, nN, c.g2, H, nH, dcp + (q.out.W - c0), H, tw, c.split, st));
     SQ_TRY(col_partials(dlogits, N, nN, n, N, 2, c.part_out, st));
   }
-  SQ_TRY(linear_dx(bf16, n, N, H, 2, dlogits, N, nN, cp + (q.out.W - c0), H, tw, c.dA, H, nH, 0, st));
+  SQ_TRY(linear_dx(bf16, n, N, H, 2, dlogits, N, nN, w.W(q.out.W, q.out.Wp), w.ld(q.out.in, q.out.ldp), twW, c.dA, H,
+                   nH, 0, st));
   // second hidden layer
   SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g2, H, nH, c.l2.xhat, c.l2.rstd, cp + (q.l2.g - c0), tw, n, H, 2, 0, c.dB,
                     params ? c.part_l2 : nullptr, st));
   if (params)
     SQ_TRY(linear_dw(bf16, n, H, H, 2, c.dB, H, nH, c.g1, H, nH, dcp + (q.l2.W - c0), H, tw, c.split, st));
-  SQ_TRY(linear_dx(bf16, n, H, H, 2, c.dB, H, nH, cp + (q.l2.W - c0), H, tw, c.dA, H, nH, 0, st));
+  SQ_TRY(linear_dx(bf16, n, H, H, 2, c.dB, H, nH, w.W(q.l2.W, q.l2.Wp), w.ld(q.l2.in, q.l2.ldp), twW, c.dA, H, nH, 0,
+                   st));
   // first hidden layer
   SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g1, H, nH, c.l1.xhat, c.l1.rstd, cp + (q.l1.g - c0), tw, n, H, 2, 0, c.dB,
                     params ? c.part_l1 : nullptr, st));
   if (params)
-    SQ_TRY(linear_dw(bf16, n, H, cin, 2, c.dB, H, nH, c.X1, cin, 0, dcp + (q.l1.W - c0), cin, tw, c.split, st));
-  const float* W1a = cp + (L.q[0].l1.W - c0);
-  const float* W1b = cp + (L.q[1].l1.W - c0);
+    SQ_TRY(linear_dw(bf16, n, H, cin, 2, c.dB, H, nH, c.X1, cld, 0, dcp + (q.l1.W - c0), cin, tw, c.split, st));
+  const float* W1a = w.W(L.q[0].l1.W, L.q[0].l1.Wp);
+  const float* W1b = w.W(L.q[1].l1.W, L.q[1].l1.Wp);
+  const long long ld1 = w.ld(q.l1.in, q.l1.ldp);
   if (trunk) {
     // the shared input [h | s | a] collects the gradient of both twins
-    SQ_TRY(linear_dx(bf16, n, H, cin, 1, c.dB, H, 0, W1a, cin, 0, c.dX1, cin, 0, 0, st));
-    SQ_TRY(linear_dx(bf16, n, H, cin, 1, c.dB + nH, H, 0, W1b, cin, 0, c.dX1, cin, 0, 1, st));
+    SQ_TRY(linear_dx(bf16, n, H, cin, 1, c.dB, H, 0, W1a, ld1, 0, c.dX1, cld, 0, 0, st));
+    SQ_TRY(linear_dx(bf16, n, H, cin, 1, c.dB + nH, H, 0, W1b, ld1, 0, c.dX1, cld, 0, 1, st));
     if (daction)
-      SQ_TRY_HIP(hipMemcpy2DAsync(daction, (size_t)A * 4, c.dX1 + P + d.proprio, (size_t)cin * 4, (size_t)A * 4, n,
+      SQ_TRY_HIP(hipMemcpy2DAsync(daction, (size_t)A * 4, c.dX1 + P + d.proprio, (size_t)cld * 4, (size_t)A * 4, n,
                                   hipMemcpyDeviceToDevice, st));
   } else if (daction) {
     const int a0 = P + d.proprio;
-    SQ_TRY(linear_dx(bf16, n, H, A, 1, c.dB, H, 0, W1a + a0, cin, 0, daction, A, 0, 0, st));
-    SQ_TRY(linear_dx(bf16, n, H, A, 1, c.dB + nH, H, 0, W1b + a0, cin, 0, daction, A, 0, 1, st));
+    SQ_TRY(linear_dx(bf16, n, H, A, 1, c.dB, H, 0, W1a + a0, ld1, 0, daction, A, 0, 0, st));
+    SQ_TRY(linear_dx(bf16, n, H, A, 1, c.dB + nH, H, 0, W1b + a0, ld1, 0, daction, A, 0, 1, st));
   }
   if (trunk) {
-    SQ_TRY(ln_act_bwd(c.dX1, cin, 0, c.X1, cin, 0, c.t.xhat, c.t.rstd, cp + (T.g - c0), 0, n, P, 1, 1, c.dA,
+    SQ_TRY(ln_act_bwd(c.dX1, cld, 0, c.X1, cld, 0, c.t.xhat, c.t.rstd, cp + (T.g - c0), 0, n, P, 1, 1, c.dA,
                       params ? c.part_t : nullptr, st));
     if (params)
       SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, c.dA, P, 0, feat, ld_feat, 0, dcp + (T.W - c0), net.flat, 0, c.split,
                        st));
     if (dfeat)
-      SQ_TRY(linear_dx(bf16, n, P, net.flat, 1, c.dA, P, 0, cp + (T.W - c0), net.flat, 0, dfeat, net.flat, 0, 0, st));
+      SQ_TRY(linear_dx(bf16, n, P, net.flat, 1, c.dA, P, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0, dfeat, net.flat, 0,
+                       0, st));
   }
   if (params) {
     const int pr = ln_bwd_partial_rows(n);
-    ColSegs s{};
-    s.n = 4;
-    s.s[0] = ColSeg{c.part_out, pr, N, 1, 2, {dcp + (q.out.b - c0), nullptr, nullptr}, tw, 0};
-    s.s[1] = ColSeg{c.part_l2, pr, H, 3, 2, {dcp + (q.l2.b - c0), dcp + (q.l2.g - c0), dcp + (q.l2.beta - c0)}, tw, 0};
-    s.s[2] = ColSeg{c.part_l1, pr, H, 3, 2, {dcp + (q.l1.b - c0), dcp + (q.l1.g - c0), dcp + (q.l1.beta - c0)}, tw, 0};
-    s.s[3] = ColSeg{c.part_t, pr, P, 3, 1, {dcp + (T.b - c0), dcp + (T.g - c0), dcp + (T.beta - c0)}, 0, 0};
-    SQ_TRY(colsum(s, st));
+    ColSegs sg{};
+    sg.n = 4;
+    sg.s[0] = ColSeg{c.part_out, pr, N, 1, 2, {dcp + (q.out.b - c0), nullptr, nullptr}, tw, 0};
+    sg.s[1] = ColSeg{c.part_l2, pr, H, 3, 2, {dcp + (q.l2.b - c0), dcp + (q.l2.g - c0), dcp + (q.l2.beta - c0)}, tw, 0};
+    sg.s[2] = ColSeg{c.part_l1, pr, H, 3, 2, {dcp + (q.l1.b - c0), dcp + (q.l1.g - c0), dcp + (q.l1.beta - c0)}, tw, 0};
+    sg.s[3] = ColSeg{c.part_t, pr, P, 3, 1, {dcp + (T.b - c0), dcp + (T.g - c0), dcp + (T.beta - c0)}, 0, 0};
+    SQ_TRY(colsum(sg, st));
   }
   return SQ_OK;
 }
@@ -214,7 +233,7 @@ int critic_backward(const Net& net, int bf16, const float* cp, const Layout& L, 
 // ---------------------------------------------------------------- actor
 void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd) {
   const sq_dims& d = net.d;
-  const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor;
+  const int H = d.hidden, P = d.proj, A = d.action, cin = net.apad;
   const int w = std::max(H, P);
   a->pre = b.take<float>((size_t)n * std::max(w, 2 * A));
   a->X1 = b.take<float>((size_t)n * cin);
@@ -243,60 +262,68 @@ void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd) {
   }
 }
 
-int actor_forward(const Net& net, int bf16, const float* ap, const Layout& L, const float* feat, long long ld_feat,
-                  const float* s, long long ld_s, const float* eps, int n, float lo, float hi, float* action,
-                  float* logp, const ActorBufs& a, hipStream_t st) {
+int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
+                  long long ld_feat, const float* s, long long ld_s, const float* eps, int n, float lo, float hi,
+                  float* action, float* logp, const ActorBufs& a, hipStream_t st) {
   const sq_dims& d = net.d;
-  const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor;
+  const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor, ald = net.apad;
   const long long a0 = L.actor_begin;
+  const WRef w{ap, pack, a0};
   const Dense& T = L.atrunk;
-  SQ_TRY(linear_fwd(bf16, n, P, net.flat, 1, feat, ld_feat, 0, ap + (T.W - a0), ap + (T.b - a0), 0, a.pre, P, 0, st));
-  SQ_TRY(ln_act_fwd(a.pre, P, 0, n, P, 1, ap + (T.g - a0), ap + (T.beta - a0), 0, 1, a.X1, cin, 0, a.t.xhat, a.t.rstd,
-                    s, ld_s, d.proprio, nullptr, 0, 0, st));
-  SQ_TRY(linear_fwd(bf16, n, H, cin, 1, a.X1, cin, 0, ap + (L.al1.W - a0), ap + (L.al1.b - a0), 0, a.pre, H, 0, st));
+  SQ_TRY(linear_fwd(bf16, n, P, net.flat, 1, feat, ld_feat, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0, ap + (T.b - a0),
+                    0, a.pre, P, 0, st));
+  SQ_TRY(ln_act_fwd(a.pre, P, 0, n, P, 1, ap + (T.g - a0), ap + (T.beta - a0), 0, 1, a.X1, ald, 0, a.t.xhat,
+                    a.t.rstd, s, ld_s, d.proprio, nullptr, 0, 0, st));
+  SQ_TRY(linear_fwd(bf16, n, H, cin, 1, a.X1, ald, 0, w.W(L.al1.W, L.al1.Wp), w.ld(L.al1.in, L.al1.ldp), 0,
+                    ap + (L.al1.b - a0), 0, a.pre, H, 0, st));
   SQ_TRY(ln_act_fwd(a.pre, H, 0, n, H, 1, ap + (L.al1.g - a0), ap + (L.al1.beta - a0), 0, 0, a.g1, H, 0, a.l1.xhat,
                     a.l1.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
-  SQ_TRY(linear_fwd(bf16, n, H, H, 1, a.g1, H, 0, ap + (L.al2.W - a0), ap + (L.al2.b - a0), 0, a.pre, H, 0, st));
+  SQ_TRY(linear_fwd(bf16, n, H, H, 1, a.g1, H, 0, w.W(L.al2.W, L.al2.Wp), w.ld(L.al2.in, L.al2.ldp), 0,
+                    ap + (L.al2.b - a0), 0, a.pre, H, 0, st));
   SQ_TRY(ln_act_fwd(a.pre, H, 0, n, H, 1, ap + (L.al2.g - a0), ap + (L.al2.beta - a0), 0, 0, a.g2, H, 0, a.l2.xhat,
                     a.l2.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
-  SQ_TRY(linear_fwd(bf16, n, 2 * A, H, 1, a.g2, H, 0, ap + (L.aout.W - a0), ap + (L.aout.b - a0), 0, a.head, 2 * A, 0,
-                    st));
+  SQ_TRY(linear_fwd(bf16, n, 2 * A, H, 1, a.g2, H, 0, w.W(L.aout.W, L.aout.Wp), w.ld(L.aout.in, L.aout.ldp), 0,
+                    ap + (L.aout.b - a0), 0, a.head, 2 * A, 0, st));
   if (eps) return tanh_gauss_fwd(a.head, n, A, eps, lo, hi, action, logp, a.save, st);
   return mean_action(a.head, n, A, action, st);
 }
 
-int actor_backward(const Net& net, int bf16, const float* ap, const Layout& L, const float* feat, long long ld_feat,
-                   const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
+int actor_backward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
+                   long long ld_feat, const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
                    hipStream_t st) {
   const sq_dims& d = net.d;
-  const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor;
+  const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor, ald = net.apad;
   const long long a0 = L.actor_begin;
+  const WRef w{ap, pack, a0};
   const Dense& T = L.atrunk;
   SQ_TRY(tanh_gauss_bwd(a.save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, n, A, a.dhead, st));
   SQ_TRY(linear_dw(bf16, n, 2 * A, H, 1, a.dhead, 2 * A, 0, a.g2, H, 0, dap + (L.aout.W - a0), H, 0, a.split, st));
   SQ_TRY(col_partials(a.dhead, 2 * A, 0, n, 2 * A, 1, a.part_out, st));
-  SQ_TRY(linear_dx(bf16, n, 2 * A, H, 1, a.dhead, 2 * A, 0, ap + (L.aout.W - a0), H, 0, a.dA, H, 0, 0, st));
+  SQ_TRY(linear_dx(bf16, n, 2 * A, H, 1, a.dhead, 2 * A, 0, w.W(L.aout.W, L.aout.Wp), w.ld(L.aout.in, L.aout.ldp), 0,
+                   a.dA, H, 0, 0, st));
   SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g2, H, 0, a.l2.xhat, a.l2.rstd, ap + (L.al2.g - a0), 0, n, H, 1, 0, a.dB, a.part_l2,
                     st));
   SQ_TRY(linear_dw(bf16, n, H, H, 1, a.dB, H, 0, a.g1, H, 0, dap + (L.al2.W - a0), H, 0, a.split, st));
-  SQ_TRY(linear_dx(bf16, n, H, H, 1, a.dB, H, 0, ap + (L.al2.W - a0), H, 0, a.dA, H, 0, 0, st));
+  SQ_TRY(linear_dx(bf16, n, H, H, 1, a.dB, H, 0, w.W(L.al2.W, L.al2.Wp), w.ld(L.al2.in, L.al2.ldp), 0, a.dA, H, 0, 0,
+                   st));
   SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g1, H, 0, a.l1.xhat, a.l1.rstd, ap + (L.al1.g - a0), 0, n, H, 1, 0, a.dB, a.part_l1,
                     st));
-  SQ_TRY(linear_dw(bf16, n, H, cin, 1, a.dB, H, 0, a.X1, cin, 0, dap + (L.al1.W - a0), cin, 0, a.split, st));
+  SQ_TRY(linear_dw(bf16, n, H, cin, 1, a.dB, H, 0, a.X1, ald, 0, dap + (L.al1.W - a0), cin, 0, a.split, st));
   // only the projection columns of the actor input need a gradient
-  SQ_TRY(linear_dx(bf16, n, H, P, 1, a.dB, H, 0, ap + (L.al1.W - a0), cin, 0, a.dX1, P, 0, 0, st));
-  SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, cin, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), 0, n, P, 1, 1, a.dA, a.part_t,
+  SQ_TRY(linear_dx(bf16, n, H, P, 1, a.dB, H, 0, w.W(L.al1.W, L.al1.Wp), w.ld(L.al1.in, L.al1.ldp), 0, a.dX1, P, 0, 0,
+                   st));
+  SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, ald, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), 0, n, P, 1, 1, a.dA, a.part_t,
                     st));
   SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, a.dA, P, 0, feat, ld_feat, 0, dap + (T.W - a0), net.flat, 0, a.split, st));
   const int pr = ln_bwd_partial_rows(n);
-  ColSegs s{};
-  s.n = 4;
-  s.s[0] = ColSeg{a.part_out, pr, 2 * A, 1, 1, {dap + (L.aout.b - a0), nullptr, nullptr}, 0, 0};
-  s.s[1] = ColSeg{a.part_l2, pr, H, 3, 1, {dap + (L.al2.b - a0), dap + (L.al2.g - a0), dap + (L.al2.beta - a0)}, 0, 0};
-  s.s[2] = ColSeg{a.part_l1, pr, H, 3, 1, {dap + (L.al1.b - a0), dap + (L.al1.g - a0), dap + (L.al1.beta - a0)}, 0, 0};
-  s.s[3] = ColSeg{a.part_t, pr, P, 3, 1, {dap + (T.b - a0), dap + (T.g - a0), dap + (T.beta - a0)}, 0, 0};
-  return colsum(s, st);
+  ColSegs sg{};
+  sg.n = 4;
+  sg.s[0] = ColSeg{a.part_out, pr, 2 * A, 1, 1, {dap + (L.aout.b - a0), nullptr, nullptr}, 0, 0};
+  sg.s[1] = ColSeg{a.part_l2, pr, H, 3, 1, {dap + (L.al2.b - a0), dap + (L.al2.g - a0), dap + (L.al2.beta - a0)}, 0, 0};
+  sg.s[2] = ColSeg{a.part_l1, pr, H, 3, 1, {dap + (L.al1.b - a0), dap + (L.al1.g - a0), dap + (L.al1.beta - a0)}, 0, 0};
+  sg.s[3] = ColSeg{a.part_t, pr, P, 3, 1, {dap + (T.b - a0), dap + (T.g - a0), dap + (T.beta - a0)}, 0, 0};
+  return colsum(sg, st);
 }
 
 }  // namespace sq

@@ -23,27 +23,28 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
 struct DenseSave { float* xhat; float* rstd; };
 struct CriticBufs {
   float* pre;         // [2][n][max(proj, hidden, atoms)]
-  float* X1;          // [n][proj + P + A]  = [h | s | a]
+  float* X1;          // [n][cpad]  = [h | s | a]
   DenseSave t, l1, l2;
   float* g1; float* g2;   // [2][n][hidden]
   float* dA; float* dB;   // [2][n][max(hidden, proj)]
-  float* dX1;             // [n][proj + P + A]
+  float* dX1;             // [n][cpad]
   float* part_t; float* part_l1; float* part_l2; float* part_out;
   float* split;
 };
 void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd);
-// cp: base of a critic block (online params + critic_begin, or the target vector)
-int critic_forward(const Net& net, int bf16, const float* cp, const Layout& L, const float* feat, long long ld_feat,
-                   const float* s, long long ld_s, const float* a, long long ld_a, int n, float* logits,
-                   const CriticBufs& c, hipStream_t st);
+// cp: base of a critic block (online params + critic_begin, or the target vector);
+// cpack: the matching packed weights (nullable: weights are read from cp)
+int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
+                   long long ld_feat, const float* s, long long ld_s, const float* a, long long ld_a, int n,
+                   float* logits, const CriticBufs& c, hipStream_t st);
 // dcp / dfeat / daction nullable; dcp is laid out like the critic block
-int critic_backward(const Net& net, int bf16, const float* cp, const Layout& L, const float* feat, long long ld_feat,
-                    const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat, float* daction,
-                    hipStream_t st);
+int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
+                    long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
+                    float* daction, hipStream_t st);
 
 struct ActorBufs {
   float* pre;          // [n][max(proj, hidden)]
-  float* X1;           // [n][proj + P] = [h | s]
+  float* X1;           // [n][apad] = [h | s]
   DenseSave t, l1, l2;
   float* g1; float* g2;  // [n][hidden]
   float* head;         // [n][2A]
@@ -55,12 +56,13 @@ struct ActorBufs {
   float* split;
 };
 void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd);
-// ap: base of the actor block; eps nullable (mean action)
-int actor_forward(const Net& net, int bf16, const float* ap, const Layout& L, const float* feat, long long ld_feat,
-                  const float* s, long long ld_s, const float* eps, int n, float lo, float hi, float* action,
-                  float* logp, const ActorBufs& a, hipStream_t st);
-int actor_backward(const Net& net, int bf16, const float* ap, const Layout& L, const float* feat, long long ld_feat,
-                   const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
+// ap: base of the actor block; pack: the whole packed-weight buffer (nullable);
+// eps nullable (mean action)
+int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
+                  long long ld_feat, const float* s, long long ld_s, const float* eps, int n, float lo, float hi,
+                  float* action, float* logp, const ActorBufs& a, hipStream_t st);
+int actor_backward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
+                   long long ld_feat, const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
                    hipStream_t st);
 

@@ -27,6 +27,7 @@ const Net& agent_net(const sq_agent* g);
 const Layout& agent_layout(const sq_agent* g);
 const sq_hparams& agent_hp(const sq_agent* g);
 const float* agent_params(const sq_agent* g);
+const float* agent_pack(const sq_agent* g);
 }  // namespace sq
 
 using namespace sq;
@@ -117,7 +118,8 @@ static int launch_batch(sq_server* s, Slot& sl) {
   SQ_TRY(encoder_forward(s->net, bf, s->params, s->L, sl.w.x, n, sl.w.e, st));
   if (d.proprio > 0) SQ_TRY(gather_rows((const float* const*)t.prop, d.proprio, n, sl.prop_stage, st));
   SQ_TRY(act_noise_rows(s->hp.seed, t.ids, t.rows, t.sample, n, d.action, sl.w.noise, st));
-  SQ_TRY(actor_forward(s->net, bf, s->params + s->L.actor_begin, s->L, sl.w.e.h[d.n_conv - 1], s->net.flat,
+  SQ_TRY(actor_forward(s->net, bf, s->params + s->L.actor_begin, agent_pack(s->agent), s->L, sl.w.e.h[d.n_conv - 1],
+                       s->net.flat,
                        sl.prop_stage, d.proprio, sl.w.noise, n, s->hp.log_std_min, s->hp.log_std_max, sl.act_stage,
                        nullptr, sl.w.a, st));
   SQ_TRY(scatter_rows(sl.act_stage, d.action, n, t.out, st));
