@@ -297,10 +297,28 @@ template <bool KF> struct VMat {
   const float* p; long long lr, lk, sz;
 };
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// One operand slice of 32 rows x BK k into registers.  A slice that lies wholly
+// inside the matrix (the common case; the test is uniform over the workgroup)
+// takes unconditional 16-byte loads; edge slices load element by element.
 template <bool KF, int BK, int VE>
-__device__ __forceinline__ void vfetch(const VMat<KF>& f, float4 (&r)[VE], int z, int row0, int rows, int k0,
+__device__ __forceinline__ void vfetch(const VMat<KF>& f, f4v (&r)[VE], int z, int row0, int rows, int k0,
                                        int kend) {
   const float* base = f.p + z * f.sz;
+  const bool interior = row0 + kTile <= rows && k0 + BK <= kend;
+  if (interior) {
+#pragma unroll
+    for (int i = 0; i < VE; ++i) {
+      const int v = (int)threadIdx.x + kThreads * i;
+      int rr, kk;
+      if constexpr (KF) { rr = v / (BK / 4); kk = (v - rr * (BK / 4)) * 4; }
+      else { kk = v / (kTile / 4); rr = (v - kk * (kTile / 4)) * 4; }
+      const float* q = KF ? base + (row0 + rr) * f.lr + (k0 + kk) : base + (k0 + kk) * f.lk + (row0 + rr);
+      r[i] = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(q, 16));
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < VE; ++i) {
     const int v = (int)threadIdx.x + kThreads * i;
@@ -308,58 +326,40 @@ __device__ __forceinline__ void vfetch(const VMat<KF>& f, float4 (&r)[VE], int z
     if constexpr (KF) { rr = v / (BK / 4); kk = (v - rr * (BK / 4)) * 4; }
     else { kk = v / (kTile / 4); rr = (v - kk * (kTile / 4)) * 4; }
     const int gr = row0 + rr, gk = k0 + kk;
-    float4 x;
-    if constexpr (KF) {
-      const float* q = base + gr * f.lr + gk;
-      if (gr < rows && gk + 4 <= kend) {
-        x = *reinterpret_cast<const float4*>(q);
-      } else {
-        const bool rv = gr < rows;
-        x.x = (rv && gk + 0 < kend) ? q[0] : 0.f;
-        x.y = (rv && gk + 1 < kend) ? q[1] : 0.f;
-        x.z = (rv && gk + 2 < kend) ? q[2] : 0.f;
-        x.w = (rv && gk + 3 < kend) ? q[3] : 0.f;
-      }
-    } else {
-      const float* q = base + gk * f.lk + gr;
-      if (gk < kend && gr + 4 <= rows) {
-        x = *reinterpret_cast<const float4*>(q);
-      } else {
-        const bool kv = gk < kend;
-        x.x = (kv && gr + 0 < rows) ? q[0] : 0.f;
-        x.y = (kv && gr + 1 < rows) ? q[1] : 0.f;
-        x.z = (kv && gr + 2 < rows) ? q[2] : 0.f;
-        x.w = (kv && gr + 3 < rows) ? q[3] : 0.f;
-      }
+    f4v x;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int er = KF ? gr : gr + e, ek = KF ? gk + e : gk;
+      x[e] = (er < rows && ek < kend) ? base[KF ? er * f.lr + ek : ek * f.lk + er] : 0.f;
     }
     r[i] = x;
   }
 }
 
 template <bool KF, int BK, int LD, int VE, bool BF16>
-__device__ __forceinline__ void vstage(const float4 (&r)[VE], typename Cfg<BF16>::T* tile) {
+__device__ __forceinline__ void vstage(const f4v (&r)[VE], typename Cfg<BF16>::T* tile) {
 #pragma unroll
   for (int i = 0; i < VE; ++i) {
     const int v = (int)threadIdx.x + kThreads * i;
     int rr, kk;
     if constexpr (KF) { rr = v / (BK / 4); kk = (v - rr * (BK / 4)) * 4; }
     else { kk = v / (kTile / 4); rr = (v - kk * (kTile / 4)) * 4; }
-    const float4 x = r[i];
+    const f4v x = r[i];
     if constexpr (KF) {
       if constexpr (BF16) {
         uint2 w;
-        w.x = (unsigned)bf16_bits(x.x) | ((unsigned)bf16_bits(x.y) << 16);
-        w.y = (unsigned)bf16_bits(x.z) | ((unsigned)bf16_bits(x.w) << 16);
+        w.x = (unsigned)bf16_bits(x[0]) | ((unsigned)bf16_bits(x[1]) << 16);
+        w.y = (unsigned)bf16_bits(x[2]) | ((unsigned)bf16_bits(x[3]) << 16);
         *reinterpret_cast<uint2*>(&tile[rr * LD + kk]) = w;
       } else {
-        *reinterpret_cast<float4*>(&tile[rr * LD + kk]) = x;
+        *reinterpret_cast<f4v*>(&tile[rr * LD + kk]) = x;
       }
     } else {
       using T = typename Cfg<BF16>::T;
-      tile[(rr + 0) * LD + kk] = to_t(x.x, (T*)nullptr);
-      tile[(rr + 1) * LD + kk] = to_t(x.y, (T*)nullptr);
-      tile[(rr + 2) * LD + kk] = to_t(x.z, (T*)nullptr);
-      tile[(rr + 3) * LD + kk] = to_t(x.w, (T*)nullptr);
+      tile[(rr + 0) * LD + kk] = to_t(x[0], (T*)nullptr);
+      tile[(rr + 1) * LD + kk] = to_t(x[1], (T*)nullptr);
+      tile[(rr + 2) * LD + kk] = to_t(x[2], (T*)nullptr);
+      tile[(rr + 3) * LD + kk] = to_t(x[3], (T*)nullptr);
     }
   }
 }
@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_v(VMat<AKF> fa, VMat<BKF> fb,
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  float4 ra[STAGES][VE], rb[STAGES][VE];
+  f4v ra[STAGES][VE], rb[STAGES][VE];
 #pragma unroll
   for (int s = 0; s < STAGES; ++s) {
     if (s < nk) {
