@@ -144,6 +144,16 @@ int conv_dw(int bf16, const float* x, int n, int Cin, int H, int stride, const f
 int conv_dx(int bf16, const float* dout, const float* out, int n, int Cin, int H, const float* W, int F,
             float* dx, hipStream_t st);
 
+// encoder.hip: fused encoder for 16x16 inputs and the (C, F, n_conv) shapes it is built for
+bool encoder_fused_ok(int C, int F, int n_conv, int side);
+size_t encoder_fused_part_floats(int n, long long enc_total);
+int encoder_fused_fwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* const* W,
+                      const float* const* b, float* const* h, hipStream_t st);
+// partial gradients of every workgroup in part, their ordered sum in grad[0, total)
+int encoder_fused_bwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* dfeat,
+                      const float* const* W, const float* const* h, const long long* Woff, const long long* boff,
+                      long long total, float* part, float* grad, hipStream_t st);
+
 // rowops.hip
 int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch,
                const float* g, const float* beta, long long sz_par, int act_tanh,

@@ -58,6 +58,13 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
   e->dh[0] = e->dh[1] = nullptr;
   e->split = nullptr;
   e->bias_part = nullptr;
+  e->enc_part = nullptr;
+  if (with_bwd && encoder_fused_ok(d.C, d.F, d.n_conv, net.side)) {
+    Layout L;
+    make_layout(net, &L);
+    e->enc_part = b.take<float>(encoder_fused_part_floats(n, L.enc_end));
+    return;
+  }
   if (with_bwd) {
     const size_t big = (size_t)n * d.F * net.conv_side[0] * net.conv_side[0];
     e->dh[0] = b.take<float>(big);
@@ -70,6 +77,17 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                     const EncBufs& e, hipStream_t st) {
   const sq_dims& d = net.d;
+  if (encoder_fused_ok(d.C, d.F, d.n_conv, net.side)) {
+    const float* W[4];
+    const float* b[4];
+    float* h[4];
+    for (int i = 0; i < d.n_conv; ++i) {
+      W[i] = ep + L.conv_W[i];
+      b[i] = ep + L.conv_b[i];
+      h[i] = e.h[i];
+    }
+    return encoder_fused_fwd(bf16, d.C, d.F, d.n_conv, x, n, W, b, h, st);
+  }
   const float* in = x;
   int cin = d.C, hs = net.side;
   for (int i = 0; i < d.n_conv; ++i) {
@@ -84,6 +102,18 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
 int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                      const float* dfeat, const EncBufs& e, float* dep, hipStream_t st) {
   const sq_dims& d = net.d;
+  if (e.enc_part) {
+    const float* W[4];
+    const float* h[4];
+    long long Wo[4], bo[4];
+    for (int i = 0; i < d.n_conv; ++i) {
+      W[i] = ep + L.conv_W[i];
+      h[i] = e.h[i];
+      Wo[i] = L.conv_W[i];
+      bo[i] = L.conv_b[i];
+    }
+    return encoder_fused_bwd(bf16, d.C, d.F, d.n_conv, x, n, dfeat, W, h, Wo, bo, L.enc_end, e.enc_part, dep, st);
+  }
   const float* dh = dfeat;
   for (int i = d.n_conv - 1; i >= 0; --i) {
     const float* in = i ? e.h[i - 1] : x;

@@ -13,6 +13,7 @@ struct EncBufs {
   float* dh[2];       // ping-pong input gradients
   float* split;       // split-K scratch, kSplitFloats
   float* bias_part;   // conv bias partial sums, 256 * F
+  float* enc_part;    // per-workgroup partial gradients of the fused encoder backward
 };
 void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd);
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
