@@ -26,28 +26,23 @@ constexpr int kEncThreads = 256;
 
 // 16x16 output tile += A(16 x K) B(K x 16); A(r, k) and B(k, c) are gathered by
 // functors (zero outside the valid range).  Wave-level: every lane participates.
+// The bfloat16 form rounds both operands to bfloat16 values and multiplies them
+// on the FP32 matrix cores: a product of two bfloat16 values is exact in FP32
+// and the accumulation is FP32, as on the bfloat16 units, while the gathers keep
+// the register footprint (and occupancy) of the FP32 form.
 template <bool BF16, class FA, class FB>
 __device__ __forceinline__ v4f mma_tile(const FA& fa, const FB& fb, int K, v4f acc) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
-  if constexpr (!BF16) {
-    for (int k0 = 0; k0 < K; k0 += 4) {
-      const int k = k0 + lq;
-      const float a = k < K ? fa(li, k) : 0.f;
-      const float b = k < K ? fb(k, li) : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + lq;
+    float a = k < K ? fa(li, k) : 0.f;
+    float b = k < K ? fb(k, li) : 0.f;
+    if constexpr (BF16) {
+      a = bf16_round(a);
+      b = bf16_round(b);
     }
-  } else {
-    for (int k0 = 0; k0 < K; k0 += 32) {
-      bf16x8 a, b;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int k = k0 + 8 * lq + e;
-        a[e] = __builtin_bit_cast(__bf16, bf16_bits(k < K ? fa(li, k) : 0.f));
-        b[e] = __builtin_bit_cast(__bf16, bf16_bits(k < K ? fb(k, li) : 0.f));
-      }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
   }
   return acc;
 }
