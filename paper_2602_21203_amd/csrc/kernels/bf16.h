@@ -1,19 +1,13 @@
-// bfloat16 helpers: round-to-nearest-even from FP32, kept as raw 16-bit patterns.
+// bfloat16 helpers: round-to-nearest-even from FP32 on the gfx950 conversion
+// instruction (v_cvt_pk_bf16_f32), kept as raw 16-bit patterns.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace sq {
 
-__device__ __forceinline__ uint16_t bf16_bits(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+__device__ __forceinline__ uint16_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
-__device__ __forceinline__ float bf16_round(float f) {
-  return __uint_as_float(((unsigned)bf16_bits(f)) << 16);
-}
+__device__ __forceinline__ float bf16_round(float f) { return (float)(__bf16)f; }
 
 }  // namespace sq

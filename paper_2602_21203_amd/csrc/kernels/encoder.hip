@@ -1,301 +1,447 @@
 // Fused conv encoder for 16x16 squinted images (Sec. IV Encoder Design Choices):
 // 3x3 valid convolutions, the first with stride 2, ReLU after each.
 //
-// Forward: a workgroup owns G images.  The images and every intermediate
-// activation stay in LDS; each convolution is an implicit GEMM on the matrix
-// cores (rows = output pixels of the G images, columns = output channels,
-// k = (input channel, ky, kx)) whose operand fragments are gathered straight
-// from LDS (activations) and from the weight rows (L1/L2 resident).  Outputs of
-// every layer are also written to HBM for the backward pass.
+// Data layout.  Inside a workgroup every activation and gradient lives in LDS
+// channel-innermost ([image][y][x][channel], pixels padded to a multiple of 16
+// channels plus 4 floats so that 16-byte reads of neighbouring pixels spread
+// over the banks).  A small preparation kernel rewrites the conv weights into
+// the two orders the contractions read with 16-byte loads: [f][tap][c] for the
+// forward and [tap][c][f] for the input gradient (bfloat16-rounded in the
+// bfloat16 form).
 //
-// Backward: the same workgroup shape.  Per layer, from the gradient at the
-// layer's output: the ReLU mask, the weight-gradient contribution of the G
-// images (contraction over their output pixels), the bias contribution, and the
-// input gradient (a transposed convolution) for the layer below -- all in LDS.
-// Each workgroup writes its partial encoder gradient; a second kernel adds the
-// partials in workgroup order, so the result is deterministic.
+// Contractions run on v_mfma_f32_16x16x4_f32.  In a chunk of 16 consecutive
+// channels of one tap, lane (li, lq) loads channels 4*lq .. 4*lq + 3 of its row
+// and of its column with one 16-byte load each and feeds them to four
+// consecutive MFMA steps, so the gather costs one LDS read and one global read
+// per four steps, at addresses fixed at compile time up to a per-lane base.
+// In the bfloat16 form every operand is rounded to a bfloat16 value once, when
+// it is written to LDS (inputs, activations, gradients after their bias sums)
+// or prepared (weights); products of bfloat16 values are exact in FP32, so the
+// FP32 matrix cores then give the bfloat16 contraction with FP32 accumulation.
+//
+// Forward: a workgroup owns G images.  Layer outputs go to LDS (next layer's
+// operand) and to HBM (FP32; [n][pixel][F] for the inner layers, NCHW for the
+// last one, which is the flattened feature vector).
+//
+// Backward: per layer, from the gradient at its post-ReLU output (masked by
+// output > 0): the bias sum, the weight gradient of the G images (contraction
+// over their output pixels, whose LDS offsets come from a per-layer table) and,
+// above the first layer, the input gradient (a transposed convolution over a
+// zero-bordered copy of the gradient, masked by the layer's input > 0 on the
+// way out).  Each workgroup writes its partial encoder gradient; a second
+// kernel adds the partials in workgroup order, so the result is deterministic.
 #include "../common.h"
 #include "bf16.h"
 
 namespace sq {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
 
-constexpr int kEncThreads = 256;
+__host__ __device__ constexpr int r16(int x) { return (x + 15) / 16 * 16; }
+__host__ __device__ constexpr int enc_in(int l) { return l == 0 ? 16 : (l == 1 ? 7 : (l == 2 ? 5 : 3)); }
+__host__ __device__ constexpr int enc_out(int l) { return l == 0 ? 7 : (l == 1 ? 5 : (l == 2 ? 3 : 1)); }
 
-// 16x16 output tile += A(16 x K) B(K x 16); A(r, k) and B(k, c) are gathered by
-// functors (zero outside the valid range).  Wave-level: every lane participates.
-// The bfloat16 form rounds both operands to bfloat16 values and multiplies them
-// on the FP32 matrix cores: a product of two bfloat16 values is exact in FP32
-// and the accumulation is FP32, as on the bfloat16 units, while the gathers keep
-// the register footprint (and occupancy) of the FP32 form.
-template <bool BF16, class FA, class FB>
-__device__ __forceinline__ v4f mma_tile(const FA& fa, const FB& fb, int K, v4f acc) {
-  const int lane = threadIdx.x & 63;
-  const int li = lane & 15, lq = lane >> 4;
-  for (int k0 = 0; k0 < K; k0 += 4) {
-    const int k = k0 + lq;
-    float a = k < K ? fa(li, k) : 0.f;
-    float b = k < K ? fb(k, li) : 0.f;
-    if constexpr (BF16) {
-      a = bf16_round(a);
-      b = bf16_round(b);
-    }
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
-  }
+// layer l of an encoder with C input channels and F filters
+template <int C, int F, int l> struct LG {
+  static constexpr int CIN = l == 0 ? C : F;
+  static constexpr int CP = r16(CIN);         // channels per pixel held in LDS (zero padded)
+  static constexpr int PS = CP + 4;           // LDS floats per input pixel
+  static constexpr int HI = enc_in(l), HO = enc_out(l), S = l == 0 ? 2 : 1;
+  static constexpr int P = HO * HO;           // output pixels per image
+  static constexpr int K = CIN * 9;           // weights per filter
+  static constexpr int DS = HO + 4;           // side of the zero-bordered output-gradient buffer
+  static constexpr int WF = F * 9 * CP;       // prepared forward weights [f][tap][CP]
+  static constexpr int WB = l == 0 ? 0 : 9 * CIN * F;   // prepared input-gradient weights [tap][c][f]
+};
+
+// offsets of the prepared weight blocks
+template <int C, int F, int NC> struct EncPrep {
+  static constexpr int F0 = 0;
+  static constexpr int F1 = F0 + LG<C, F, 0>::WF;
+  static constexpr int F2 = F1 + LG<C, F, 1>::WF;
+  static constexpr int B1 = F2 + (NC > 2 ? LG<C, F, 2>::WF : 0);
+  static constexpr int B2 = B1 + LG<C, F, 1>::WB;
+  static constexpr int TOTAL = B2 + (NC > 2 ? LG<C, F, 2>::WB : 0);
+};
+
+__device__ __forceinline__ float rnd(float v, bool on) { return on ? bf16_round(v) : v; }
+
+__device__ __forceinline__ v4f mma4(const f4v& a, const f4v& b, v4f acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], acc, 0, 0, 0);
   return acc;
 }
 
-// geometry of layer l (0-based): input side, output side, stride
-__host__ __device__ constexpr int enc_in(int l) { return l == 0 ? 16 : (l == 1 ? 7 : (l == 2 ? 5 : 3)); }
-__host__ __device__ constexpr int enc_out(int l) { return l == 0 ? 7 : (l == 1 ? 5 : (l == 2 ? 3 : 1)); }
-__host__ __device__ constexpr int enc_stride(int l) { return l == 0 ? 2 : 1; }
+// ---------------------------------------------------------------- weight preparation
+struct EncW {
+  const float* W[3];
+};
+
+template <int C, int F, int NC>
+__global__ __launch_bounds__(256) void k_enc_prep(EncW w, float* __restrict__ wp, int bf16) {
+  using E = EncPrep<C, F, NC>;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < E::TOTAL; e += gridDim.x * 256) {
+    float v;
+    if (e < E::B1) {                       // forward order [f][tap][CP]
+      int l, o, cin, cp;
+      if (e < E::F1) { l = 0; o = e; cin = C; cp = LG<C, F, 0>::CP; }
+      else if (e < E::F2) { l = 1; o = e - E::F1; cin = F; cp = LG<C, F, 1>::CP; }
+      else { l = 2; o = e - E::F2; cin = F; cp = LG<C, F, 2>::CP; }
+      const int f = o / (9 * cp), r = o - f * 9 * cp, tap = r / cp, c = r - tap * cp;
+      v = c < cin ? w.W[l][(f * cin + c) * 9 + tap] : 0.f;
+    } else {                               // input-gradient order [tap][c][f]
+      const int l = e < E::B2 ? 1 : 2;
+      const int o = e - (l == 1 ? E::B1 : E::B2);
+      const int tap = o / (F * F), r = o - tap * F * F, c = r / F, f = r - c * F;
+      v = w.W[l][(f * F + c) * 9 + tap];
+    }
+    wp[e] = bf16 ? bf16_round(v) : v;
+  }
+}
 
 // ---------------------------------------------------------------- forward
-// One conv layer of the gn (<= G) present images: in_lds [G][CIN][HI][HI] ->
-// post-ReLU out_lds [G][F][HO][HO] (nullable) and out_g (NCHW rows of the images).
-template <bool BF16, int G, int CIN, int F, int HI, int HO, int S>
-__device__ void conv_layer_fwd(const float* in_lds, float* out_lds, const float* __restrict__ W,
+// One conv layer of G images: in [G][HI][HI][PS] (LDS) -> post-ReLU
+// out_lds [G][HO][HO][F + 4] (the next layer's operand, rounded in the bfloat16
+// form) and out_g (FP32; [img][pixel][F], or NCHW for the last layer).
+template <bool BF16, int G, int C, int F, int l, bool TO_LDS, bool LAST, int NT>
+__device__ void conv_fwd_layer(const float* in, float* out_lds, const float* __restrict__ wf,
                                const float* __restrict__ bias, float* __restrict__ out_g, int gn) {
-  constexpr int P = HO * HO;            // output pixels per image
-  constexpr int ROWS = G * P;
-  constexpr int K = CIN * 9;
-  constexpr int RT = (ROWS + 15) / 16, CT = F / 16;
+  using Y = LG<C, F, l>;
+  constexpr int ROWS = G * Y::P, RT = (ROWS + 15) / 16, CT = F / 16, NW = NT / 64;
+  constexpr int PSO = F + 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int t = wave; t < RT * CT; t += kEncThreads / 64) {
+  const int li = lane & 15, lq = lane >> 4;
+  for (int t = wave; t < RT * CT; t += NW) {
     const int rt = t / CT, ct = t - rt * CT;
     const int r0 = rt * 16, c0 = ct * 16;
-    auto fa = [&](int r, int k) -> float {
-      const int row = r0 + r;
-      if (row >= ROWS) return 0.f;
-      const int g = row / P, p = row - g * P, oy = p / HO, ox = p - oy * HO;
-      const int c = k / 9, tt = k - 9 * c, ky = tt / 3, kx = tt - 3 * ky;
-      return in_lds[((g * CIN + c) * HI + oy * S + ky) * HI + ox * S + kx];
-    };
-    auto fb = [&](int k, int c) -> float { return W[(c0 + c) * K + k]; };
-    v4f acc = mma_tile<BF16>(fa, fb, K, v4f{0.f, 0.f, 0.f, 0.f});
-    const int col = c0 + (lane & 15);
-    const float bv = bias[col];
+    const int row = min(r0 + li, ROWS - 1);
+    const int g = row / Y::P, p = row - g * Y::P, oy = p / Y::HO, ox = p - oy * Y::HO;
+    const float* ap = in + ((g * Y::HI + oy * Y::S) * Y::HI + ox * Y::S) * Y::PS + 4 * lq;
+    const float* bp = wf + (c0 + li) * 9 * Y::CP + 4 * lq;
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap - 3 * ky;
+#pragma unroll
+      for (int cg = 0; cg < Y::CP / 16; ++cg) {
+        const f4v a = *reinterpret_cast<const f4v*>(ap + (ky * Y::HI + kx) * Y::PS + 16 * cg);
+        const f4v b = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(bp + tap * Y::CP + 16 * cg, 16));
+        acc = mma4(a, b, acc);
+      }
+    }
+    const int f = c0 + li;
+    const float bv = bias[f];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int row = r0 + 4 * (lane >> 4) + q;
-      if (row < ROWS) {
-        const int g = row / P, p = row - g * P;
+      const int r = r0 + 4 * lq + q;
+      if (r < ROWS) {
+        const int gg = r / Y::P, pp = r - gg * Y::P;
         const float v = fmaxf(acc[q] + bv, 0.f);
-        if (out_lds) out_lds[(g * F + col) * P + p] = v;
-        if (g < gn) out_g[((long long)g * F + col) * P + p] = v;
-      }
-    }
-  }
-}
-
-template <bool BF16, int G, int C, int F, int NC>
-__global__ __launch_bounds__(kEncThreads) void k_encoder_fwd(const float* __restrict__ x, int n,
-                                                             const float* __restrict__ W0, const float* __restrict__ b0,
-                                                             const float* __restrict__ W1, const float* __restrict__ b1,
-                                                             const float* __restrict__ W2, const float* __restrict__ b2,
-                                                             float* __restrict__ h0, float* __restrict__ h1,
-                                                             float* __restrict__ h2) {
-  constexpr int X = G * C * 256, A0 = G * F * 49, A1 = G * F * 25;
-  __shared__ float lx[X];
-  __shared__ float la0[A0];
-  __shared__ float la1[A1];
-  const int img0 = blockIdx.x * G;
-  const int gn = n - img0 < G ? n - img0 : G;
-  // images of this group; the missing images of a ragged tail read as zeros
-  for (int e = threadIdx.x; e < X; e += kEncThreads) {
-    const int g = e / (C * 256);
-    lx[e] = g < gn ? x[(long long)img0 * C * 256 + e] : 0.f;
-  }
-  __syncthreads();
-  conv_layer_fwd<BF16, G, C, F, 16, 7, 2>(lx, la0, W0, b0, h0 + (long long)img0 * F * 49, gn);
-  __syncthreads();
-  conv_layer_fwd<BF16, G, F, F, 7, 5, 1>(la0, NC > 2 ? la1 : nullptr, W1, b1, h1 + (long long)img0 * F * 25, gn);
-  if constexpr (NC > 2) {
-    __syncthreads();
-    conv_layer_fwd<BF16, G, F, F, 5, 3, 1>(la1, nullptr, W2, b2, h2 + (long long)img0 * F * 9, gn);
-  }
-}
-
-// ---------------------------------------------------------------- backward
-// Layer l of the G images, from dcur = gradient at its post-ReLU output:
-//   dpre = dcur * (out > 0)                                   (in place)
-//   part[W_off + f*K + k] = sum_{g,p} dpre[g][f][p] patch(in)[g][p][k]
-//   part[b_off + f]       = sum_{g,p} dpre[g][f][p]
-//   dprev[g][c][iy][ix]   = sum_{f,ky,kx} dpre[g][f][iy-ky][ix-kx] W[f][c][ky][kx]   (stride-1 layers, if wanted)
-template <bool BF16, int G, int CIN, int F, int HI, int HO, int S, bool DX>
-__device__ void conv_layer_bwd(float* dcur, const float* __restrict__ out_g, const float* in_lds,
-                               const float* __restrict__ W, float* __restrict__ partW, float* __restrict__ partb,
-                               float* dprev, int gn) {
-  constexpr int P = HO * HO;
-  constexpr int K = CIN * 9;
-  constexpr int NPOS = G * P;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // ReLU mask (tail images carry zero gradient)
-  for (int e = threadIdx.x; e < G * F * P; e += kEncThreads) {
-    const int g = e / (F * P);
-    dcur[e] = (g < gn && out_g[e] > 0.f) ? dcur[e] : 0.f;
-  }
-  __syncthreads();
-  // bias: thread f sums its channel over the G images in order
-  if (threadIdx.x < F) {
-    const int f = threadIdx.x;
-    float sb = 0.f;
-    for (int g = 0; g < G; ++g)
-      for (int p = 0; p < P; ++p) sb += dcur[(g * F + f) * P + p];
-    partb[f] = sb;
-  }
-  // weights: rows f (F/16 tiles), columns k (K padded to 16), contraction over positions
-  {
-    constexpr int RT = F / 16, CT = (K + 15) / 16;
-    for (int t = wave; t < RT * CT; t += kEncThreads / 64) {
-      const int rt = t / CT, ct = t - rt * CT;
-      const int f0 = rt * 16, k0 = ct * 16;
-      auto fa = [&](int r, int q) -> float {      // A(f, pos) = dpre
-        const int g = q / P, p = q - g * P;
-        return dcur[(g * F + f0 + r) * P + p];
-      };
-      auto fb = [&](int q, int c) -> float {      // B(pos, k) = patch
-        const int k = k0 + c;
-        if (k >= K) return 0.f;
-        const int g = q / P, p = q - g * P, oy = p / HO, ox = p - oy * HO;
-        const int ci = k / 9, tt = k - 9 * ci, ky = tt / 3, kx = tt - 3 * ky;
-        return in_lds[((g * CIN + ci) * HI + oy * S + ky) * HI + ox * S + kx];
-      };
-      const v4f acc = mma_tile<BF16>(fa, fb, NPOS, v4f{0.f, 0.f, 0.f, 0.f});
-      const int kk = k0 + (lane & 15);
-      if (kk < K) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) partW[(f0 + 4 * (lane >> 4) + q) * K + kk] = acc[q];
-      }
-    }
-  }
-  if constexpr (DX) {
-    static_assert(S == 1, "input gradients are needed for stride-1 layers only");
-    // rows (g, iy, ix), columns c (CIN/16 tiles), contraction k = (f, ky, kx)
-    constexpr int ROWS = G * HI * HI;
-    constexpr int RT = (ROWS + 15) / 16, CT = CIN / 16, KT = F * 9;
-    for (int t = wave; t < RT * CT; t += kEncThreads / 64) {
-      const int rt = t / CT, ct = t - rt * CT;
-      const int r0 = rt * 16, c0 = ct * 16;
-      auto fa = [&](int r, int k) -> float {
-        const int row = r0 + r;
-        if (row >= ROWS) return 0.f;
-        const int g = row / (HI * HI), q = row - g * HI * HI, iy = q / HI, ix = q - iy * HI;
-        const int f = k / 9, tt = k - 9 * f, ky = tt / 3, kx = tt - 3 * ky;
-        const int oy = iy - ky, ox = ix - kx;
-        if (oy < 0 || oy >= HO || ox < 0 || ox >= HO) return 0.f;
-        return dcur[(g * F + f) * P + oy * HO + ox];
-      };
-      auto fb = [&](int k, int c) -> float {
-        const int f = k / 9, tt = k - 9 * f;
-        return W[(f * CIN + c0 + c) * 9 + tt];
-      };
-      const v4f acc = mma_tile<BF16>(fa, fb, KT, v4f{0.f, 0.f, 0.f, 0.f});
-      const int c = c0 + (lane & 15);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = r0 + 4 * (lane >> 4) + q;
-        if (row < ROWS) {
-          const int g = row / (HI * HI), pq = row - g * HI * HI;
-          dprev[(g * CIN + c) * HI * HI + pq] = acc[q];
+        if constexpr (TO_LDS) out_lds[(gg * Y::P + pp) * PSO + f] = rnd(v, BF16);
+        if (gg < gn) {
+          if constexpr (LAST) out_g[((long long)gg * F + f) * Y::P + pp] = v;
+          else out_g[((long long)gg * Y::P + pp) * F + f] = v;
         }
       }
     }
   }
-  __syncthreads();
 }
 
-template <bool BF16, int G, int C, int F, int NC>
-__global__ __launch_bounds__(kEncThreads) void k_encoder_bwd(const float* __restrict__ x, int n,
-                                                             const float* __restrict__ dfeat,
-                                                             const float* __restrict__ W0, const float* __restrict__ W1,
-                                                             const float* __restrict__ W2,
-                                                             const float* __restrict__ h0, const float* __restrict__ h1,
-                                                             const float* __restrict__ h2, long long W_off0,
-                                                             long long b_off0, long long W_off1, long long b_off1,
-                                                             long long W_off2, long long b_off2, long long enc_total,
-                                                             float* __restrict__ part) {
-  constexpr int BIG = G * F * 49 > G * C * 256 ? G * F * 49 : G * C * 256;
-  __shared__ float ld_a[G * F * 49];    // gradient at the current layer's output
-  __shared__ float ld_b[G * F * 49];    // gradient at its input
-  __shared__ float ld_in[BIG];          // the current layer's input activation
+template <bool BF16, int G, int C, int F, int NC, int NT>
+__global__ __launch_bounds__(NT) void k_encoder_fwd(const float* __restrict__ x, int n, const float* __restrict__ wp,
+                                                    const float* __restrict__ b0, const float* __restrict__ b1,
+                                                    const float* __restrict__ b2, float* __restrict__ h0,
+                                                    float* __restrict__ h1, float* __restrict__ h2) {
+  using L0 = LG<C, F, 0>;
+  using L1 = LG<C, F, 1>;
+  using E = EncPrep<C, F, NC>;
+  constexpr int X = G * 256 * L0::PS, A0 = G * L0::P * (F + 4), A1 = NC > 2 ? G * L1::P * (F + 4) : 4;
+  __shared__ __attribute__((aligned(16))) float lx[X];
+  __shared__ __attribute__((aligned(16))) float la0[A0];
+  __shared__ __attribute__((aligned(16))) float la1[A1];
+  const int img0 = blockIdx.x * G;
+  const int gn = n - img0 < G ? n - img0 : G;
+  // images of this group, NCHW -> [g][pixel][channel]; absent images and padding channels read as zero
+  for (int e = threadIdx.x; e < G * C * 256; e += NT) {
+    const int g = e / (C * 256), r = e - g * C * 256, c = r >> 8, pix = r & 255;
+    lx[(g * 256 + pix) * L0::PS + c] = g < gn ? rnd(x[(long long)img0 * C * 256 + e], BF16) : 0.f;
+  }
+  for (int e = threadIdx.x; e < G * 256 * (L0::CP - C); e += NT) {
+    const int gp = e / (L0::CP - C), c = C + e - gp * (L0::CP - C);
+    lx[gp * L0::PS + c] = 0.f;
+  }
+  __syncthreads();
+  conv_fwd_layer<BF16, G, C, F, 0, true, false, NT>(lx, la0, wp + E::F0, b0, h0 + (long long)img0 * F * L0::P, gn);
+  __syncthreads();
+  if constexpr (NC > 2) {
+    conv_fwd_layer<BF16, G, C, F, 1, true, false, NT>(la0, la1, wp + E::F1, b1, h1 + (long long)img0 * F * L1::P, gn);
+    __syncthreads();
+    conv_fwd_layer<BF16, G, C, F, 2, false, true, NT>(la1, nullptr, wp + E::F2, b2,
+                                                      h2 + (long long)img0 * F * LG<C, F, 2>::P, gn);
+  } else {
+    conv_fwd_layer<BF16, G, C, F, 1, false, true, NT>(la0, nullptr, wp + E::F1, b1, h1 + (long long)img0 * F * L1::P,
+                                                      gn);
+  }
+}
+
+// ---------------------------------------------------------------- backward
+// Gradient buffers: layer l's output gradient D_l as [G][DS][DS][F + 4] with a
+// zero border of 2 (interior pixel (y, x) at (y + 2, x + 2)).
+
+// From D_l (interior filled, border zero): bias partial, bfloat16 rounding of
+// D_l in that form, weight partial over the images' output pixels.  `in` is the
+// layer's input [G][HI][HI][PS].
+template <bool BF16, int G, int C, int F, int l, int NT>
+__device__ void conv_bwd_weights(float* D, const float* in, int2* qtab, float* __restrict__ partW,
+                                 float* __restrict__ partb) {
+  using Y = LG<C, F, l>;
+  constexpr int PSF = F + 4;
+  constexpr int NPOS = G * Y::P, NQ = (NPOS + 3) / 4 * 4, NW = NT / 64;
+  // bias: thread f sums its channel over the images' pixels in order (unrounded)
+  if (threadIdx.x < F) {
+    const int f = threadIdx.x;
+    float sb = 0.f;
+    for (int g = 0; g < G; ++g)
+      for (int p = 0; p < Y::P; ++p) {
+        const int oy = p / Y::HO, ox = p - oy * Y::HO;
+        sb += D[((g * Y::DS + oy + 2) * Y::DS + ox + 2) * PSF + f];
+      }
+    partb[f] = sb;
+  }
+  // contraction table: output pixel q -> (offset in D, offset of its input patch
+  // origin); the pad entries point at a zero border pixel of D
+  for (int q = threadIdx.x; q < NQ; q += NT) {
+    int2 e = make_int2(0, 0);
+    if (q < NPOS) {
+      const int g = q / Y::P, p = q - g * Y::P, oy = p / Y::HO, ox = p - oy * Y::HO;
+      e.x = ((g * Y::DS + oy + 2) * Y::DS + ox + 2) * PSF;
+      e.y = ((g * Y::HI + oy * Y::S) * Y::HI + ox * Y::S) * Y::PS;
+    }
+    qtab[q] = e;
+  }
+  __syncthreads();
+  if constexpr (BF16) {
+    for (int e = threadIdx.x; e < G * Y::DS * Y::DS * PSF; e += NT) D[e] = bf16_round(D[e]);
+    __syncthreads();
+  }
+  // weights: rows f (F / 16 tiles), columns kc = tap * CIN + c, contraction over output pixels
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  constexpr int RT = F / 16, CT = (Y::K + 15) / 16;
+  for (int t = wave; t < RT * CT; t += NW) {
+    const int rt = t / CT, ct = t - rt * CT;
+    const int f0 = rt * 16, k0 = ct * 16;
+    const int kc = min(k0 + li, Y::K - 1);
+    const int tap = kc / Y::CIN, c = kc - tap * Y::CIN, ky = tap / 3, kx = tap - 3 * ky;
+    const float* ap = D + f0 + li;
+    const float* bp = in + (ky * Y::HI + kx) * Y::PS + c;
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+    for (int s = 0; s < NQ / 4; ++s) {
+      const int2 e = qtab[4 * s + lq];
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[e.x], bp[e.y], acc, 0, 0, 0);
+    }
+    const int kk = k0 + li;
+    if (kk < Y::K) {
+      const int tp = kk / Y::CIN, cc = kk - tp * Y::CIN;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) partW[(f0 + 4 * lq + q) * Y::K + cc * 9 + tp] = acc[q];
+    }
+  }
+}
+
+// Input gradient of layer l >= 1 from D_l (rounded in the bfloat16 form):
+// E[g][iy][ix][c] = sum_{tap, f} D_l[g][iy - ky][ix - kx][f] W[f][c][ky][kx],
+// masked by the layer's input (hin = layer l-1's output, [img][pixel][F]) > 0
+// and written into the interior of Dn (zero-bordered [G][HI + 4][HI + 4][F + 4]).
+template <int G, int C, int F, int l, int NT>
+__device__ void conv_bwd_input(const float* D, const float* __restrict__ wb, const float* __restrict__ hin, float* Dn,
+                               int gn) {
+  using Y = LG<C, F, l>;
+  static_assert(l >= 1, "input gradients are needed above the first layer only");
+  constexpr int PSF = F + 4, DSN = Y::HI + 4;
+  constexpr int ROWS = G * Y::HI * Y::HI, RT = (ROWS + 15) / 16, CT = F / 16, NW = NT / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  for (int t = wave; t < RT * CT; t += NW) {
+    const int rt = t / CT, ct = t - rt * CT;
+    const int r0 = rt * 16, c0 = ct * 16;
+    const int row = min(r0 + li, ROWS - 1);
+    const int g = row / (Y::HI * Y::HI), pq = row - g * Y::HI * Y::HI, iy = pq / Y::HI, ix = pq - iy * Y::HI;
+    const float* ap = D + ((g * Y::DS + iy + 2) * Y::DS + ix + 2) * PSF + 4 * lq;
+    const float* bp = wb + (c0 + li) * F + 4 * lq;
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int ky = tap / 3, kx = tap - 3 * ky;
+#pragma unroll
+      for (int fg = 0; fg < F / 16; ++fg) {
+        const f4v a = *reinterpret_cast<const f4v*>(ap - (ky * Y::DS + kx) * PSF + 16 * fg);
+        const f4v b = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(bp + tap * F * F + 16 * fg, 16));
+        acc = mma4(a, b, acc);
+      }
+    }
+    const int c = c0 + li;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + 4 * lq + q;
+      if (r < ROWS) {
+        const int gg = r / (Y::HI * Y::HI), pp = r - gg * Y::HI * Y::HI, yy = pp / Y::HI, xx = pp - yy * Y::HI;
+        const bool live = gg < gn && hin[((long long)gg * Y::HI * Y::HI + pp) * F + c] > 0.f;
+        Dn[((gg * DSN + yy + 2) * DSN + xx + 2) * PSF + c] = live ? acc[q] : 0.f;
+      }
+    }
+  }
+}
+
+struct EncOffs {
+  long long W[3], b[3];
+};
+
+template <bool BF16, int G, int C, int F, int NC, int NT>
+__global__ __launch_bounds__(NT) void k_encoder_bwd(const float* __restrict__ x, int n,
+                                                    const float* __restrict__ dfeat, const float* __restrict__ wp,
+                                                    const float* __restrict__ h0, const float* __restrict__ h1,
+                                                    const float* __restrict__ h2, EncOffs off, long long enc_total,
+                                                    float* __restrict__ part) {
+  using L0 = LG<C, F, 0>;
+  using L1 = LG<C, F, 1>;
+  using LL = LG<C, F, NC - 1>;
+  using E = EncPrep<C, F, NC>;
+  constexpr int PSF = F + 4;
+  constexpr int SZ0 = G * L0::DS * L0::DS * PSF;                                  // D_0
+  constexpr int SZ1 = G * L1::DS * L1::DS * PSF;                                  // D_1
+  constexpr int SZ2 = NC > 2 ? G * LG<C, F, 2>::DS * LG<C, F, 2>::DS * PSF : 4;   // D_2
+  // region r0 holds D_2 first and D_0 last (never live together); r1 holds D_1
+  constexpr int R0 = SZ0 > SZ2 ? SZ0 : SZ2;
+  constexpr int IN0 = G * 256 * L0::PS, IN1 = G * L1::HI * L1::HI * L1::PS;
+  constexpr int RIN = IN0 > IN1 ? IN0 : IN1;
+  constexpr int NQ = (G * L0::P + 3) / 4 * 4;
+  __shared__ __attribute__((aligned(16))) float r0[R0];
+  __shared__ __attribute__((aligned(16))) float r1[SZ1];
+  __shared__ __attribute__((aligned(16))) float rin[RIN];
+  __shared__ int2 qtab[NQ];
   const int img0 = blockIdx.x * G;
   const int gn = n - img0 < G ? n - img0 : G;
   float* pp = part + (long long)blockIdx.x * enc_total;
-  constexpr int FL = NC > 2 ? 9 : 25;   // pixels of the last layer's output
-  const float* hl = NC > 2 ? h2 : h1;
-  for (int e = threadIdx.x; e < G * F * FL; e += kEncThreads) {
-    const int g = e / (F * FL);
-    ld_a[e] = g < gn ? dfeat[(long long)img0 * F * FL + e] : 0.f;
-  }
-  float* dcur = ld_a;
-  float* dnext = ld_b;
-  if constexpr (NC > 2) {
-    for (int e = threadIdx.x; e < G * F * 25; e += kEncThreads) {
-      const int g = e / (F * 25);
-      ld_in[e] = g < gn ? h1[(long long)img0 * F * 25 + e] : 0.f;
+
+  // D_{NC-1}: zero, then the upstream gradient (NCHW) masked by the output > 0 into the interior
+  float* Dl = NC > 2 ? r0 : r1;
+  for (int e = threadIdx.x; e < (NC > 2 ? SZ2 : SZ1); e += NT) Dl[e] = 0.f;
+  __syncthreads();
+  {
+    const float* hl = NC > 2 ? h2 : h1;
+    for (int e = threadIdx.x; e < G * F * LL::P; e += NT) {
+      const int g = e / (F * LL::P), r = e - g * F * LL::P, f = r / LL::P, p = r - f * LL::P;
+      const int oy = p / LL::HO, ox = p - oy * LL::HO;
+      const long long gi = (long long)img0 * F * LL::P + e;
+      const float v = (g < gn && hl[gi] > 0.f) ? dfeat[gi] : 0.f;
+      Dl[((g * LL::DS + oy + 2) * LL::DS + ox + 2) * PSF + f] = v;
     }
+  }
+  if constexpr (NC > 2) {
+    using L2 = LG<C, F, 2>;
+    // layer 2: input h1 ([img][pixel][F] -> [g][pixel][PS]); D_2 in r0, D_1 -> r1
+    for (int e = threadIdx.x; e < G * L2::HI * L2::HI * F; e += NT) {
+      const int gp = e / F, c = e - gp * F, g = gp / (L2::HI * L2::HI);
+      rin[gp * L2::PS + c] = g < gn ? rnd(h1[(long long)img0 * L2::HI * L2::HI * F + e], BF16) : 0.f;
+    }
+    for (int e = threadIdx.x; e < SZ1; e += NT) r1[e] = 0.f;
     __syncthreads();
-    conv_layer_bwd<BF16, G, F, F, 5, 3, 1, true>(dcur, hl + (long long)img0 * F * 9, ld_in, W2, pp + W_off2,
-                                                 pp + b_off2, dnext, gn);
-    float* t = dcur; dcur = dnext; dnext = t;
+    conv_bwd_weights<BF16, G, C, F, 2, NT>(r0, rin, qtab, pp + off.W[2], pp + off.b[2]);
+    __syncthreads();
+    conv_bwd_input<G, C, F, 2, NT>(r0, wp + E::B2, h1 + (long long)img0 * L2::HI * L2::HI * F, r1, gn);
+    __syncthreads();
   }
-  for (int e = threadIdx.x; e < G * F * 49; e += kEncThreads) {
-    const int g = e / (F * 49);
-    ld_in[e] = g < gn ? h0[(long long)img0 * F * 49 + e] : 0.f;
+  // layer 1: input h0; D_1 in r1, D_0 -> r0
+  for (int e = threadIdx.x; e < G * L1::HI * L1::HI * F; e += NT) {
+    const int gp = e / F, c = e - gp * F, g = gp / (L1::HI * L1::HI);
+    rin[gp * L1::PS + c] = g < gn ? rnd(h0[(long long)img0 * L1::HI * L1::HI * F + e], BF16) : 0.f;
+  }
+  for (int e = threadIdx.x; e < SZ0; e += NT) r0[e] = 0.f;
+  __syncthreads();
+  conv_bwd_weights<BF16, G, C, F, 1, NT>(r1, rin, qtab, pp + off.W[1], pp + off.b[1]);
+  __syncthreads();
+  conv_bwd_input<G, C, F, 1, NT>(r1, wp + E::B1, h0 + (long long)img0 * L1::HI * L1::HI * F, r0, gn);
+  __syncthreads();
+  // layer 0: input x (NCHW -> [g][pixel][channel], padding channels zero); D_0 in r0
+  for (int e = threadIdx.x; e < G * C * 256; e += NT) {
+    const int g = e / (C * 256), r = e - g * C * 256, c = r >> 8, pix = r & 255;
+    rin[(g * 256 + pix) * L0::PS + c] = g < gn ? rnd(x[(long long)img0 * C * 256 + e], BF16) : 0.f;
+  }
+  for (int e = threadIdx.x; e < G * 256 * (L0::CP - C); e += NT) {
+    const int gp = e / (L0::CP - C), c = C + e - gp * (L0::CP - C);
+    rin[gp * L0::PS + c] = 0.f;
   }
   __syncthreads();
-  conv_layer_bwd<BF16, G, F, F, 7, 5, 1, true>(dcur, h1 + (long long)img0 * F * 25, ld_in, W1, pp + W_off1,
-                                               pp + b_off1, dnext, gn);
-  { float* t = dcur; dcur = dnext; dnext = t; }
-  for (int e = threadIdx.x; e < G * C * 256; e += kEncThreads) {
-    const int g = e / (C * 256);
-    ld_in[e] = g < gn ? x[(long long)img0 * C * 256 + e] : 0.f;
-  }
-  __syncthreads();
-  conv_layer_bwd<BF16, G, C, F, 16, 7, 2, false>(dcur, h0 + (long long)img0 * F * 49, ld_in, W0, pp + W_off0,
-                                                 pp + b_off0, nullptr, gn);
+  conv_bwd_weights<BF16, G, C, F, 0, NT>(r0, rin, qtab, pp + off.W[0], pp + off.b[0]);
 }
 
-// grad[e] = sum over workgroups (in order) of part[wg][e]
+// grad[e] = sum over workgroups (in order) of part[wg][e]: four consecutive
+// elements per lane, the workgroup rows split over the four waves by residue,
+// the four wave sums added in wave order
 __global__ __launch_bounds__(256) void k_enc_reduce(const float* __restrict__ part, int nwg, long long total,
                                                     float* __restrict__ grad) {
-  __shared__ float sh[4][64];
+  __shared__ f4v sh[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const long long e = (long long)blockIdx.x * 64 + lane;
-  float v = 0.f;
-  if (e < total)
-    for (int w = wave; w < nwg; w += 4) v += part[(long long)w * total + e];
+  const long long e = ((long long)blockIdx.x * 64 + lane) * 4;
+  const bool vec = total % 4 == 0 && e + 4 <= total;
+  f4v v = f4v{0.f, 0.f, 0.f, 0.f};
+  if (vec) {
+#pragma unroll 8
+    for (int w = wave; w < nwg; w += 4)
+      v += *reinterpret_cast<const f4v*>(__builtin_assume_aligned(part + (long long)w * total + e, 16));
+  } else {
+    for (int w = wave; w < nwg; w += 4)
+      for (int j = 0; j < 4; ++j)
+        if (e + j < total) v[j] += part[(long long)w * total + e + j];
+  }
   sh[wave][lane] = v;
   __syncthreads();
-  if (wave == 0 && e < total) grad[e] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+  if (wave == 0) {
+    const f4v s = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+    for (int j = 0; j < 4; ++j)
+      if (e + j < total) grad[e + j] = s[j];
+  }
 }
 
 // ---------------------------------------------------------------- launchers
-constexpr int kEncG = 2;
+constexpr int kEncFwdG = 2, kEncFwdThreads = 256;
+constexpr int kEncBwdG = 2, kEncBwdThreads = 256;
+
+template <int C, int F, int NC>
+static int prep_t(const float* const* W, float* wp, int bf16, hipStream_t st) {
+  EncW w{{W[0], W[1], NC > 2 ? W[2] : W[1]}};
+  const int tot = EncPrep<C, F, NC>::TOTAL;
+  k_enc_prep<C, F, NC><<<cdiv(tot, 256), 256, 0, st>>>(w, wp, bf16);
+  return launch_status("encoder_prep");
+}
 
 template <bool BF16, int C, int F, int NC>
-static int enc_fwd_t(const float* x, int n, const float* const* W, const float* const* b, float* const* h,
-                     hipStream_t st) {
-  const int nwg = cdiv(n, kEncG);
-  k_encoder_fwd<BF16, kEncG, C, F, NC><<<nwg, kEncThreads, 0, st>>>(x, n, W[0], b[0], W[1], b[1], NC > 2 ? W[2] : W[1],
-                                                                    NC > 2 ? b[2] : b[1], h[0], h[1],
-                                                                    NC > 2 ? h[2] : h[1]);
+static int enc_fwd_t(const float* x, int n, const float* wp, const float* const* b, float* const* h, hipStream_t st) {
+  const int nwg = cdiv(n, kEncFwdG);
+  k_encoder_fwd<BF16, kEncFwdG, C, F, NC, kEncFwdThreads><<<nwg, kEncFwdThreads, 0, st>>>(
+      x, n, wp, b[0], b[1], NC > 2 ? b[2] : b[1], h[0], h[1], NC > 2 ? h[2] : h[1]);
   return launch_status("encoder_fwd");
 }
 
 template <bool BF16, int C, int F, int NC>
-static int enc_bwd_t(const float* x, int n, const float* dfeat, const float* const* W, const float* const* h,
+static int enc_bwd_t(const float* x, int n, const float* dfeat, const float* wp, const float* const* h,
                      const long long* Woff, const long long* boff, long long total, float* part, float* grad,
                      hipStream_t st) {
-  const int nwg = cdiv(n, kEncG);
-  k_encoder_bwd<BF16, kEncG, C, F, NC><<<nwg, kEncThreads, 0, st>>>(
-      x, n, dfeat, W[0], W[1], NC > 2 ? W[2] : W[1], h[0], h[1], NC > 2 ? h[2] : h[1], Woff[0], boff[0], Woff[1],
-      boff[1], NC > 2 ? Woff[2] : 0, NC > 2 ? boff[2] : 0, total, part);
+  const int nwg = cdiv(n, kEncBwdG);
+  EncOffs off{};
+  for (int i = 0; i < NC; ++i) {
+    off.W[i] = Woff[i];
+    off.b[i] = boff[i];
+  }
+  k_encoder_bwd<BF16, kEncBwdG, C, F, NC, kEncBwdThreads><<<nwg, kEncBwdThreads, 0, st>>>(
+      x, n, dfeat, wp, h[0], h[1], NC > 2 ? h[2] : h[1], off, total, part);
   SQ_TRY(launch_status("encoder_bwd"));
-  k_enc_reduce<<<cdiv(total, 64), 256, 0, st>>>(part, nwg, total, grad);
+  k_enc_reduce<<<(int)cdiv(total, 256), 256, 0, st>>>(part, nwg, total, grad);
   return launch_status("encoder_reduce");
 }
 
@@ -303,25 +449,35 @@ bool encoder_fused_ok(int C, int F, int n_conv, int side) {
   return side == 16 && ((C == 9 && F == 32 && n_conv == 3) || (C == 3 && F == 16 && n_conv == 2));
 }
 
-size_t encoder_fused_part_floats(int n, long long enc_total) { return (size_t)cdiv(n, kEncG) * enc_total; }
+size_t encoder_fused_part_floats(int n, long long enc_total) { return (size_t)cdiv(n, kEncBwdG) * enc_total; }
 
-int encoder_fused_fwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* const* W,
+size_t encoder_fused_prep_floats(int C, int F, int n_conv) {
+  if (C == 9 && F == 32 && n_conv == 3) return EncPrep<9, 32, 3>::TOTAL;
+  return EncPrep<3, 16, 2>::TOTAL;
+}
+
+int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W, float* wp, hipStream_t st) {
+  if (C == 9 && F == 32 && n_conv == 3) return prep_t<9, 32, 3>(W, wp, bf16, st);
+  return prep_t<3, 16, 2>(W, wp, bf16, st);
+}
+
+int encoder_fused_fwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* wp,
                       const float* const* b, float* const* h, hipStream_t st) {
   if (n <= 0) return SQ_OK;
   if (C == 9 && F == 32 && n_conv == 3)
-    return bf16 ? enc_fwd_t<true, 9, 32, 3>(x, n, W, b, h, st) : enc_fwd_t<false, 9, 32, 3>(x, n, W, b, h, st);
-  return bf16 ? enc_fwd_t<true, 3, 16, 2>(x, n, W, b, h, st) : enc_fwd_t<false, 3, 16, 2>(x, n, W, b, h, st);
+    return bf16 ? enc_fwd_t<true, 9, 32, 3>(x, n, wp, b, h, st) : enc_fwd_t<false, 9, 32, 3>(x, n, wp, b, h, st);
+  return bf16 ? enc_fwd_t<true, 3, 16, 2>(x, n, wp, b, h, st) : enc_fwd_t<false, 3, 16, 2>(x, n, wp, b, h, st);
 }
 
-int encoder_fused_bwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* dfeat,
-                      const float* const* W, const float* const* h, const long long* Woff, const long long* boff,
-                      long long total, float* part, float* grad, hipStream_t st) {
+int encoder_fused_bwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* dfeat, const float* wp,
+                      const float* const* h, const long long* Woff, const long long* boff, long long total,
+                      float* part, float* grad, hipStream_t st) {
   if (n <= 0) return SQ_OK;
   if (C == 9 && F == 32 && n_conv == 3)
-    return bf16 ? enc_bwd_t<true, 9, 32, 3>(x, n, dfeat, W, h, Woff, boff, total, part, grad, st)
-                : enc_bwd_t<false, 9, 32, 3>(x, n, dfeat, W, h, Woff, boff, total, part, grad, st);
-  return bf16 ? enc_bwd_t<true, 3, 16, 2>(x, n, dfeat, W, h, Woff, boff, total, part, grad, st)
-              : enc_bwd_t<false, 3, 16, 2>(x, n, dfeat, W, h, Woff, boff, total, part, grad, st);
+    return bf16 ? enc_bwd_t<true, 9, 32, 3>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st)
+                : enc_bwd_t<false, 9, 32, 3>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st);
+  return bf16 ? enc_bwd_t<true, 3, 16, 2>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st)
+              : enc_bwd_t<false, 3, 16, 2>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st);
 }
 
 }  // namespace sq

@@ -18,6 +18,8 @@
 #include "../common.h"
 #include "bf16.h"
 
+#include <algorithm>
+
 namespace sq {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
@@ -287,103 +289,116 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
   }
 }
 
-// ---------------------------------------------------------------- vector-load kernel
-// Plain strided operands whose contiguous dimension is 16-byte aligned (the
-// activations and the packed weight copies): every load brings 4 elements,
-// interior tiles take no per-element branch, and 4 consecutive k of one row go
-// to LDS in one store.  Same tiling, wave split and fixed reduction order as
-// k_gemm, so the two produce identical results.
-template <bool KF> struct VMat {
+// ---------------------------------------------------------------- register-direct kernel
+// For plain strided operands (every linear layer).  Each wave contracts its
+// quarter of K straight from global memory into the MFMA operand registers: in
+// a chunk of KC k (16 for FP32, 32 for bfloat16) lane (li, lq) holds rows li and
+// 16 + li of both operands at EK = KC / 4 consecutive k starting at EK * lq
+// (one or two 16-byte loads when k is the contiguous dimension of a 16-byte
+// aligned operand, element loads otherwise).  A wave's K range is fetched in
+// groups of chunks, the next group in flight while the current one is
+// multiplied, so there is no LDS staging and no barrier in the main loop; the
+// four partial tiles are summed through LDS in a fixed order at the end.
+// FP32: step j of a chunk multiplies k = EK * lq + j on v_mfma_f32_16x16x4_f32.
+// bfloat16: the 8 values are rounded to nearest even (v_cvt_pk_bf16_f32) into
+// the operand of v_mfma_f32_16x16x32_bf16.
+struct RMat {
   const float* p; long long lr, lk, sz;
 };
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
-// One operand slice of 32 rows x BK k into registers.  A slice that lies wholly
-// inside the matrix (the common case; the test is uniform over the workgroup)
-// takes unconditional 16-byte loads; edge slices load element by element.
-template <bool KF, int BK, int VE>
-__device__ __forceinline__ void vfetch(const VMat<KF>& f, f4v (&r)[VE], int z, int row0, int rows, int k0,
-                                       int kend) {
-  const float* base = f.p + z * f.sz;
-  const bool interior = row0 + kTile <= rows && k0 + BK <= kend;
-  if (interior) {
-#pragma unroll
-    for (int i = 0; i < VE; ++i) {
-      const int v = (int)threadIdx.x + kThreads * i;
-      int rr, kk;
-      if constexpr (KF) { rr = v / (BK / 4); kk = (v - rr * (BK / 4)) * 4; }
-      else { kk = v / (kTile / 4); rr = (v - kk * (kTile / 4)) * 4; }
-      const float* q = KF ? base + (row0 + rr) * f.lr + (k0 + kk) : base + (k0 + kk) * f.lk + (row0 + rr);
-      r[i] = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(q, 16));
-    }
-    return;
-  }
-#pragma unroll
-  for (int i = 0; i < VE; ++i) {
-    const int v = (int)threadIdx.x + kThreads * i;
-    int rr, kk;
-    if constexpr (KF) { rr = v / (BK / 4); kk = (v - rr * (BK / 4)) * 4; }
-    else { kk = v / (kTile / 4); rr = (v - kk * (kTile / 4)) * 4; }
-    const int gr = row0 + rr, gk = k0 + kk;
-    f4v x;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int er = KF ? gr : gr + e, ek = KF ? gk + e : gk;
-      x[e] = (er < rows && ek < kend) ? base[KF ? er * f.lr + ek : ek * f.lk + er] : 0.f;
-    }
-    r[i] = x;
-  }
-}
+template <bool BF16> struct RCfg {
+  static constexpr int EK = BF16 ? 8 : 4;   // k per lane per chunk
+  static constexpr int KC = 4 * EK;         // k per chunk
+  static constexpr int G = BF16 ? 2 : 4;    // chunks per register group
+};
 
-template <bool KF, int BK, int LD, int VE, bool BF16>
-__device__ __forceinline__ void vstage(const f4v (&r)[VE], typename Cfg<BF16>::T* tile) {
+// rows r0 + li and r0 + 16 + li (clamped into the matrix: rows past the end are
+// computed on valid data and never stored), k in [k0 + EK*lq, +EK), zero past kend
+template <bool BF16, int V>
+__device__ __forceinline__ void rload(const RMat& m, float (&x)[2][RCfg<BF16>::EK], int z, int r0, int rows,
+                                      int k0, int kend, int li, int lq) {
+  constexpr int EK = RCfg<BF16>::EK;
+  const float* base = m.p + (long long)z * m.sz;
+  const int kq = k0 + EK * lq;
+  const bool inside = k0 + 4 * EK <= kend;   // uniform over the wave
 #pragma unroll
-  for (int i = 0; i < VE; ++i) {
-    const int v = (int)threadIdx.x + kThreads * i;
-    int rr, kk;
-    if constexpr (KF) { rr = v / (BK / 4); kk = (v - rr * (BK / 4)) * 4; }
-    else { kk = v / (kTile / 4); rr = (v - kk * (kTile / 4)) * 4; }
-    const f4v x = r[i];
-    if constexpr (KF) {
-      if constexpr (BF16) {
-        uint2 w;
-        w.x = (unsigned)bf16_bits(x[0]) | ((unsigned)bf16_bits(x[1]) << 16);
-        w.y = (unsigned)bf16_bits(x[2]) | ((unsigned)bf16_bits(x[3]) << 16);
-        *reinterpret_cast<uint2*>(&tile[rr * LD + kk]) = w;
+  for (int i = 0; i < 2; ++i) {
+    int r = r0 + 16 * i + li;
+    r = r < rows ? r : rows - 1;
+    const float* q = base + (long long)r * m.lr;
+    if (inside) {
+      if constexpr (V) {
+#pragma unroll
+        for (int v = 0; v < EK / 4; ++v) {
+          const f4v t = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(q + kq + 4 * v, 16));
+#pragma unroll
+          for (int e = 0; e < 4; ++e) x[i][4 * v + e] = t[e];
+        }
       } else {
-        *reinterpret_cast<f4v*>(&tile[rr * LD + kk]) = x;
+#pragma unroll
+        for (int e = 0; e < EK; ++e) x[i][e] = q[(long long)(kq + e) * m.lk];
       }
     } else {
-      using T = typename Cfg<BF16>::T;
-      tile[(rr + 0) * LD + kk] = to_t(x[0], (T*)nullptr);
-      tile[(rr + 1) * LD + kk] = to_t(x[1], (T*)nullptr);
-      tile[(rr + 2) * LD + kk] = to_t(x[2], (T*)nullptr);
-      tile[(rr + 3) * LD + kk] = to_t(x[3], (T*)nullptr);
+#pragma unroll
+      for (int e = 0; e < EK; ++e) {
+        const int k = kq + e;
+        x[i][e] = k < kend ? q[(long long)k * m.lk] : 0.f;
+      }
     }
   }
 }
 
-template <bool BF16, bool AKF, bool BKF, class ST>
-__global__ __launch_bounds__(kThreads) void k_gemm_v(VMat<AKF> fa, VMat<BKF> fb, ST st, int M, int N, int K) {
-  using C = Cfg<BF16>;
-  using T = typename C::T;
-  constexpr int BK = 4 * C::KW;
-  constexpr int LD = BK + (BF16 ? 8 : 4);     // 16-byte aligned rows, conflict-free MFMA reads
-  constexpr int VE = kTile * BK / 4 / kThreads;
-  constexpr int STAGES = 2;
-  constexpr int TILE_BYTES = 2 * kTile * LD * (int)sizeof(T);
-  constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
-  constexpr int LDS_BYTES = TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
-  __shared__ __attribute__((aligned(16))) char lds[LDS_BYTES];
-  T* As = reinterpret_cast<T*>(lds);
-  T* Bs = As + kTile * LD;
+template <bool BF16>
+__device__ __forceinline__ void rmma(const float (&a)[2][RCfg<BF16>::EK], const float (&b)[2][RCfg<BF16>::EK],
+                                     v4f (&acc)[2][2]) {
+  if constexpr (!BF16) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][j], b[jj][j], acc[i][jj], 0, 0, 0);
+  } else {
+    bf16x8 av[2], bv[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        av[i][e] = (__bf16)a[i][e];
+        bv[i][e] = (__bf16)b[i][e];
+      }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int jj = 0; jj < 2; ++jj)
+        acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[jj], acc[i][jj], 0, 0, 0);
+  }
+}
 
-  const int z = blockIdx.z;
+template <bool BF16, int AV, int BV, class ST, bool SPLIT>
+__global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, StPart sp, int M, int N, int K,
+                                                     int kchunk) {
+  constexpr int EK = RCfg<BF16>::EK, KC = RCfg<BF16>::KC, G = RCfg<BF16>::G;
+  constexpr int RLD = kTile + 1;
+  __shared__ float red[4 * kTile * RLD];
+
+  const int z = blockIdx.z / (SPLIT ? sp.splits : 1);
+  const int split = SPLIT ? blockIdx.z % sp.splits : 0;
   const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
-  const int nk = K > 0 ? (K + BK - 1) / BK : 0;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
+  // this wave's k range: a quarter of the workgroup's, in whole chunks
+  const int span = kend > kbeg ? kend - kbeg : 0;
+  const int per = ((span + 3) / 4 + KC - 1) / KC * KC;
+  const int wb = kbeg + wave * per;
+  const int we = min(kend, wb + per);
+  const int nch = we > wb ? (we - wb + KC - 1) / KC : 0;
+  const int ng = (nch + G - 1) / G;
 
   v4f acc[2][2];
 #pragma unroll
@@ -391,34 +406,31 @@ __global__ __launch_bounds__(kThreads) void k_gemm_v(VMat<AKF> fa, VMat<BKF> fb,
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  f4v ra[STAGES][VE], rb[STAGES][VE];
+  float xa[2][G][2][EK], xb[2][G][2][EK];
+  auto load = [&](int g, int buf) {
 #pragma unroll
-  for (int s = 0; s < STAGES; ++s) {
-    if (s < nk) {
-      vfetch<AKF, BK, VE>(fa, ra[s], z, m0, M, s * BK, K);
-      vfetch<BKF, BK, VE>(fb, rb[s], z, n0, N, s * BK, K);
-    }
-  }
-  for (int kt = 0; kt < nk; kt += STAGES) {
-#pragma unroll
-    for (int s = 0; s < STAGES; ++s) {
-      const int t = kt + s;
-      if (t < nk) {
-        vstage<AKF, BK, LD, VE, BF16>(ra[s], As);
-        vstage<BKF, BK, LD, VE, BF16>(rb[s], Bs);
-        __syncthreads();
-        if (t + STAGES < nk) {
-          vfetch<AKF, BK, VE>(fa, ra[s], z, m0, M, (t + STAGES) * BK, K);
-          vfetch<BKF, BK, VE>(fb, rb[s], z, n0, N, (t + STAGES) * BK, K);
-        }
-        mma_step<BF16, LD>(As, Bs, acc, wave, li, lq);
-        __syncthreads();
+    for (int c = 0; c < G; ++c) {
+      const int ch = g * G + c;
+      if (ch < nch) {
+        rload<BF16, AV>(fa, xa[buf][c], z, m0, M, wb + ch * KC, we, li, lq);
+        rload<BF16, BV>(fb, xb[buf][c], z, n0, N, wb + ch * KC, we, li, lq);
       }
     }
+  };
+  auto mult = [&](int g, int buf) {
+#pragma unroll
+    for (int c = 0; c < G; ++c)
+      if (g * G + c < nch) rmma<BF16>(xa[buf][c], xb[buf][c], acc);
+  };
+  if (ng > 0) load(0, 0);
+  for (int g = 0; g < ng; g += 2) {
+    if (g + 1 < ng) load(g + 1, 1);
+    mult(g, 0);
+    if (g + 2 < ng) load(g + 2, 0);
+    if (g + 1 < ng) mult(g + 1, 1);
   }
 
-  float* red = reinterpret_cast<float*>(lds);
-  constexpr int RLD = kTile + 1;
+  // fixed-order sum of the four waves' partial tiles
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -432,7 +444,9 @@ __global__ __launch_bounds__(kThreads) void k_gemm_v(VMat<AKF> fa, VMat<BKF> fb,
     const float v = ((red[(0 * kTile + r) * RLD + c] + red[(1 * kTile + r) * RLD + c]) +
                      red[(2 * kTile + r) * RLD + c]) + red[(3 * kTile + r) * RLD + c];
     const int gr = m0 + r, gc = n0 + c;
-    if (gr < M && gc < N) st.put(z, gr, gc, v);
+    if (gr < M && gc < N) {
+      if constexpr (SPLIT) sp.put(z, split, gr, gc, v); else st.put(z, gr, gc, v);
+    }
   }
 }
 
@@ -489,51 +503,55 @@ static int run(int bf16, int M, int N, int K, int batch, FA fa, FB fb, ST st, fl
 }
 
 // ---------------------------------------------------------------- public launchers
-// 1: contiguous along k, 0: contiguous along rows, -1: no 16-byte vector access
-static int vec_kind(const MatArg& a) {
-  if ((uintptr_t)a.p % 16 != 0 || a.sz % 4 != 0) return -1;
-  if (a.lk == 1 && a.lr % 4 == 0) return 1;
-  if (a.lr == 1 && a.lk % 4 == 0) return 0;
-  return -1;
+// 1: k is the contiguous dimension of 16-byte aligned rows (vector loads), else 0
+static int rkind(const MatArg& a) {
+  return ((uintptr_t)a.p % 16 == 0 && a.sz % 4 == 0 && a.lk == 1 && a.lr % 4 == 0) ? 1 : 0;
 }
 
-template <bool BF16, bool AK, bool BKF>
-static int run_v(int M, int N, int K, int batch, const MatArg& A, const MatArg& B, const StMat& out, hipStream_t st) {
-  dim3 grid(cdiv(M, kTile), cdiv(N, kTile), batch);
-  k_gemm_v<BF16, AK, BKF, StMat><<<grid, kThreads, 0, st>>>(VMat<AK>{A.p, A.lr, A.lk, A.sz},
-                                                            VMat<BKF>{B.p, B.lr, B.lk, B.sz}, out, M, N, K);
-  return launch_status("gemm_v");
+template <bool BF16, int AV, int BV>
+static int run_r(int M, int N, int K, int batch, const MatArg& A, const MatArg& B, const StMat& out, float* scratch,
+                 size_t scratch_floats, hipStream_t st) {
+  const int tiles = cdiv(M, kTile) * cdiv(N, kTile) * batch;
+  // few output tiles over a long contraction: split K across workgroups
+  int splits = 1;
+  if (scratch && tiles < 128 && K >= 2048) {
+    splits = std::min(cdiv(256, tiles), K / 1024);
+    while (splits > 1 && (size_t)splits * M * N * batch > scratch_floats) --splits;
+  }
+  int kchunk = K > 0 ? K : 1;
+  if (splits > 1) {
+    kchunk = cdiv(cdiv(K, splits), 4 * RCfg<BF16>::KC) * 4 * RCfg<BF16>::KC;
+    splits = cdiv(K, kchunk);
+  }
+  const RMat a{A.p, A.lr, A.lk, A.sz}, b{B.p, B.lr, B.lk, B.sz};
+  StPart sp{scratch, M, N, splits};
+  dim3 grid(cdiv(M, kTile), cdiv(N, kTile), batch * splits);
+  if (splits <= 1) {
+    k_gemm_r<BF16, AV, BV, StMat, false><<<grid, kThreads, 0, st>>>(a, b, out, sp, M, N, K, kchunk);
+    return launch_status("gemm");
+  }
+  k_gemm_r<BF16, AV, BV, StMat, true><<<grid, kThreads, 0, st>>>(a, b, out, sp, M, N, K, kchunk);
+  SQ_TRY(launch_status("gemm_split"));
+  const long long total = (long long)M * N * batch;
+  k_split_reduce<StMat><<<cdiv(total, 256), 256, 0, st>>>(sp, out, batch);
+  return launch_status("split_reduce");
 }
 
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return SQ_OK;
   StMat out{C.p, C.ld, C.sz, C.bias, C.bias_sz, C.accumulate, C.relu};
-  const int va = vec_kind(A), vb = vec_kind(B);
-  const bool small = cdiv(M, kTile) * cdiv(N, kTile) * batch < 96 && K > 1024;   // wants a K split
-  if (va >= 0 && vb >= 0 && M > 0 && N > 0 && batch > 0 && !(small && scratch)) {
-    if (bf16) {
-      if (va && vb) return run_v<true, true, true>(M, N, K, batch, A, B, out, st);
-      if (va) return run_v<true, true, false>(M, N, K, batch, A, B, out, st);
-      if (vb) return run_v<true, false, true>(M, N, K, batch, A, B, out, st);
-      return run_v<true, false, false>(M, N, K, batch, A, B, out, st);
-    }
-    if (va && vb) return run_v<false, true, true>(M, N, K, batch, A, B, out, st);
-    if (va) return run_v<false, true, false>(M, N, K, batch, A, B, out, st);
-    if (vb) return run_v<false, false, true>(M, N, K, batch, A, B, out, st);
-    return run_v<false, false, false>(M, N, K, batch, A, B, out, st);
+  const int va = rkind(A), vb = rkind(B);
+  if (bf16) {
+    if (va && vb) return run_r<true, 1, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
+    if (va) return run_r<true, 1, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
+    if (vb) return run_r<true, 0, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
+    return run_r<true, 0, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
   }
-  // pick the coalescing direction of each operand from its strides
-  if (A.lk == 1 && B.lk == 1)
-    return run(bf16, M, N, K, batch, FMat<true>{A.p, A.lr, A.lk, A.sz}, FMat<true>{B.p, B.lr, B.lk, B.sz}, out,
-               scratch, scratch_floats, st, "gemm_tt");
-  if (A.lk == 1)
-    return run(bf16, M, N, K, batch, FMat<true>{A.p, A.lr, A.lk, A.sz}, FMat<false>{B.p, B.lr, B.lk, B.sz}, out,
-               scratch, scratch_floats, st, "gemm_tn");
-  if (B.lk == 1)
-    return run(bf16, M, N, K, batch, FMat<false>{A.p, A.lr, A.lk, A.sz}, FMat<true>{B.p, B.lr, B.lk, B.sz}, out,
-               scratch, scratch_floats, st, "gemm_nt");
-  return run(bf16, M, N, K, batch, FMat<false>{A.p, A.lr, A.lk, A.sz}, FMat<false>{B.p, B.lr, B.lk, B.sz}, out,
-             scratch, scratch_floats, st, "gemm_nn");
+  if (va && vb) return run_r<false, 1, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
+  if (va) return run_r<false, 1, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
+  if (vb) return run_r<false, 0, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
+  return run_r<false, 0, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
 }
 
 template <class F>

@@ -59,10 +59,14 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
   e->split = nullptr;
   e->bias_part = nullptr;
   e->enc_part = nullptr;
-  if (with_bwd && encoder_fused_ok(d.C, d.F, d.n_conv, net.side)) {
-    Layout L;
-    make_layout(net, &L);
-    e->enc_part = b.take<float>(encoder_fused_part_floats(n, L.enc_end));
+  e->wprep = nullptr;
+  if (encoder_fused_ok(d.C, d.F, d.n_conv, net.side)) {
+    e->wprep = b.take<float>(encoder_fused_prep_floats(d.C, d.F, d.n_conv));
+    if (with_bwd) {
+      Layout L;
+      make_layout(net, &L);
+      e->enc_part = b.take<float>(encoder_fused_part_floats(n, L.enc_end));
+    }
     return;
   }
   if (with_bwd) {
@@ -77,7 +81,7 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                     const EncBufs& e, hipStream_t st) {
   const sq_dims& d = net.d;
-  if (encoder_fused_ok(d.C, d.F, d.n_conv, net.side)) {
+  if (e.wprep) {
     const float* W[4];
     const float* b[4];
     float* h[4];
@@ -86,7 +90,8 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
       b[i] = ep + L.conv_b[i];
       h[i] = e.h[i];
     }
-    return encoder_fused_fwd(bf16, d.C, d.F, d.n_conv, x, n, W, b, h, st);
+    SQ_TRY(encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st));
+    return encoder_fused_fwd(bf16, d.C, d.F, d.n_conv, x, n, e.wprep, b, h, st);
   }
   const float* in = x;
   int cin = d.C, hs = net.side;
@@ -112,7 +117,9 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
       Wo[i] = L.conv_W[i];
       bo[i] = L.conv_b[i];
     }
-    return encoder_fused_bwd(bf16, d.C, d.F, d.n_conv, x, n, dfeat, W, h, Wo, bo, L.enc_end, e.enc_part, dep, st);
+    SQ_TRY(encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st));
+    return encoder_fused_bwd(bf16, d.C, d.F, d.n_conv, x, n, dfeat, e.wprep, h, Wo, bo, L.enc_end, e.enc_part, dep,
+                             st);
   }
   const float* dh = dfeat;
   for (int i = d.n_conv - 1; i >= 0; --i) {

@@ -9,7 +9,8 @@ namespace sq {
 constexpr size_t kSplitFloats = (size_t)4 << 20;   // split-K scratch (16 MB)
 
 struct EncBufs {
-  float* h[4];        // post-ReLU conv outputs [n][F][s_i][s_i]; h[n_conv-1] is the feature
+  float* h[4];        // post-ReLU conv outputs; h[n_conv-1] is the feature [n][F][s][s]
+  float* wprep;       // fused encoder: rearranged conv weights
   float* dh[2];       // ping-pong input gradients
   float* split;       // split-K scratch, kSplitFloats
   float* bias_part;   // conv bias partial sums, 256 * F
