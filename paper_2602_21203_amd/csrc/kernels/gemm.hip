@@ -315,36 +315,35 @@ template <bool BF16> struct RCfg {
 };
 
 // rows r0 + li and r0 + 16 + li (clamped into the matrix: rows past the end are
-// computed on valid data and never stored), k in [k0 + EK*lq, +EK), zero past kend
-template <bool BF16, int V>
+// computed on valid data and never stored), k in [k0 + EK*lq, +EK).  FULL: the
+// chunk lies inside the contraction; otherwise k >= kend reads as zero.
+template <bool BF16, int V, bool FULL>
 __device__ __forceinline__ void rload(const RMat& m, float (&x)[2][RCfg<BF16>::EK], int z, int r0, int rows,
                                       int k0, int kend, int li, int lq) {
   constexpr int EK = RCfg<BF16>::EK;
   const float* base = m.p + (long long)z * m.sz;
   const int kq = k0 + EK * lq;
-  const bool inside = k0 + 4 * EK <= kend;   // uniform over the wave
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     int r = r0 + 16 * i + li;
     r = r < rows ? r : rows - 1;
     const float* q = base + (long long)r * m.lr;
-    if (inside) {
-      if constexpr (V) {
+    if constexpr (FULL && V) {
 #pragma unroll
-        for (int v = 0; v < EK / 4; ++v) {
-          const f4v t = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(q + kq + 4 * v, 16));
+      for (int v = 0; v < EK / 4; ++v) {
+        const f4v t = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(q + kq + 4 * v, 16));
 #pragma unroll
-          for (int e = 0; e < 4; ++e) x[i][4 * v + e] = t[e];
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < EK; ++e) x[i][e] = q[(long long)(kq + e) * m.lk];
+        for (int e = 0; e < 4; ++e) x[i][4 * v + e] = t[e];
       }
+    } else if constexpr (FULL) {
+#pragma unroll
+      for (int e = 0; e < EK; ++e) x[i][e] = q[(long long)(kq + e) * m.lk];
     } else {
 #pragma unroll
       for (int e = 0; e < EK; ++e) {
         const int k = kq + e;
-        x[i][e] = k < kend ? q[(long long)k * m.lk] : 0.f;
+        const float v = q[(long long)min(k, kend - 1) * m.lk];   // kend > k0: always a valid element
+        x[i][e] = k < kend ? v : 0.f;
       }
     }
   }
@@ -390,15 +389,16 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
   const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: chunk tests stay scalar
   const int li = lane & 15, lq = lane >> 4;
   // this wave's k range: a quarter of the workgroup's, in whole chunks
   const int span = kend > kbeg ? kend - kbeg : 0;
   const int per = ((span + 3) / 4 + KC - 1) / KC * KC;
   const int wb = kbeg + wave * per;
   const int we = min(kend, wb + per);
-  const int nch = we > wb ? (we - wb + KC - 1) / KC : 0;
-  const int ng = (nch + G - 1) / G;
+  const int wspan = we > wb ? we - wb : 0;
+  const int ngf = wspan / KC / G;      // groups of G chunks wholly inside the range
 
   v4f acc[2][2];
 #pragma unroll
@@ -410,24 +410,38 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
   auto load = [&](int g, int buf) {
 #pragma unroll
     for (int c = 0; c < G; ++c) {
-      const int ch = g * G + c;
-      if (ch < nch) {
-        rload<BF16, AV>(fa, xa[buf][c], z, m0, M, wb + ch * KC, we, li, lq);
-        rload<BF16, BV>(fb, xb[buf][c], z, n0, N, wb + ch * KC, we, li, lq);
-      }
+      rload<BF16, AV, true>(fa, xa[buf][c], z, m0, M, wb + (g * G + c) * KC, we, li, lq);
+      rload<BF16, BV, true>(fb, xb[buf][c], z, n0, N, wb + (g * G + c) * KC, we, li, lq);
     }
   };
-  auto mult = [&](int g, int buf) {
+  auto mult = [&](int buf) {
 #pragma unroll
-    for (int c = 0; c < G; ++c)
-      if (g * G + c < nch) rmma<BF16>(xa[buf][c], xb[buf][c], acc);
+    for (int c = 0; c < G; ++c) rmma<BF16>(xa[buf][c], xb[buf][c], acc);
   };
-  if (ng > 0) load(0, 0);
-  for (int g = 0; g < ng; g += 2) {
-    if (g + 1 < ng) load(g + 1, 1);
-    mult(g, 0);
-    if (g + 2 < ng) load(g + 2, 0);
-    if (g + 1 < ng) mult(g + 1, 1);
+  // two register groups in flight: group g + 1 loads while group g multiplies
+  if (ngf > 0) load(0, 0);
+  if (ngf > 1) load(1, 1);
+  for (int g = 0; g < ngf; g += 2) {
+    mult(0);
+    if (g + 2 < ngf) load(g + 2, 0);
+    if (g + 1 < ngf) {
+      mult(1);
+      if (g + 3 < ngf) load(g + 3, 1);
+    }
+  }
+  // the rest of the range chunk by chunk, then the partial last chunk
+  int k0 = wb + ngf * G * KC;
+  for (; k0 + KC <= we; k0 += KC) {
+    float ta[2][EK], tb[2][EK];
+    rload<BF16, AV, true>(fa, ta, z, m0, M, k0, we, li, lq);
+    rload<BF16, BV, true>(fb, tb, z, n0, N, k0, we, li, lq);
+    rmma<BF16>(ta, tb, acc);
+  }
+  if (k0 < we) {
+    float ta[2][EK], tb[2][EK];
+    rload<BF16, AV, false>(fa, ta, z, m0, M, k0, we, li, lq);
+    rload<BF16, BV, false>(fb, tb, z, n0, N, k0, we, li, lq);
+    rmma<BF16>(ta, tb, acc);
   }
 
   // fixed-order sum of the four waves' partial tiles
