@@ -19,6 +19,7 @@
 #include "bf16.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace sq {
 
@@ -289,100 +290,169 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
   }
 }
 
-// ---------------------------------------------------------------- register-direct kernel
+// ---------------------------------------------------------------- plain-matrix kernel
 // For plain strided operands (every linear layer).  Each wave contracts its
-// quarter of K straight from global memory into the MFMA operand registers: in
-// a chunk of KC k (16 for FP32, 32 for bfloat16) lane (li, lq) holds rows li and
-// 16 + li of both operands at EK = KC / 4 consecutive k starting at EK * lq
-// (one or two 16-byte loads when k is the contiguous dimension of a 16-byte
-// aligned operand, element loads otherwise).  A wave's K range is fetched in
-// groups of chunks, the next group in flight while the current one is
-// multiplied, so there is no LDS staging and no barrier in the main loop; the
-// four partial tiles are summed through LDS in a fixed order at the end.
-// FP32: step j of a chunk multiplies k = EK * lq + j on v_mfma_f32_16x16x4_f32.
-// bfloat16: the 8 values are rounded to nearest even (v_cvt_pk_bf16_f32) into
-// the operand of v_mfma_f32_16x16x32_bf16.
+// quarter of the workgroup's K range for the whole 32 x 32 tile, in chunks of
+// 32 k; lane (li, lq) feeds rows li and 16 + li at k = 8*lq .. 8*lq + 7 of a
+// chunk to the matrix cores (one v_mfma_f32_16x16x32_bf16, or eight
+// v_mfma_f32_16x16x4_f32 steps with step e taking k = 8*lq + e).
+//
+// Operand loads.  An operand whose rows are k-contiguous and 16-byte aligned is
+// read row-coalesced -- eight consecutive lanes cover the 128 bytes of one row's
+// chunk -- and rearranged into the fragment order through a small LDS tile that
+// belongs to the wave alone (no workgroup barrier; the wave waits for its own
+// LDS writes before reading back).  Reading the fragment order straight from
+// memory would send each lane to a different row and costs the load unit several
+// times more.  Other operands (k strided, rows contiguous) are read in fragment
+// order directly, which is already coalesced across li.
+//
+// Chunks are fetched in groups of two, the next group in flight while the
+// current one is multiplied.  The four partial tiles are summed through LDS in a
+// fixed order at the end.  bfloat16 operands are rounded to nearest even
+// (v_cvt_pk_bf16_f32) on the way to LDS or to the fragment.
 struct RMat {
   const float* p; long long lr, lk, sz;
 };
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-template <bool BF16> struct RCfg {
-  static constexpr int EK = BF16 ? 8 : 4;   // k per lane per chunk
-  static constexpr int KC = 4 * EK;         // k per chunk
-  static constexpr int G = BF16 ? 2 : 4;    // chunks per register group
+constexpr int kRKC = 32;   // k per chunk
+constexpr int kRG = 2;     // chunks per register group
+
+template <bool BF16> struct RLds {
+  using T = typename std::conditional<BF16, __bf16, float>::type;
+  static constexpr int LDT = BF16 ? 40 : 36;              // row stride of a transposition tile (elements)
+  static constexpr int TILE = 32 * LDT;                   // one operand's 32 x 32 chunk
+  static constexpr int WAVE = 2 * 2 * TILE;               // two operands, two alternating chunks
 };
 
-// rows r0 + li and r0 + 16 + li (clamped into the matrix: rows past the end are
-// computed on valid data and never stored), k in [k0 + EK*lq, +EK).  FULL: the
-// chunk lies inside the contraction; otherwise k >= kend reads as zero.
-template <bool BF16, int V, bool FULL>
-__device__ __forceinline__ void rload(const RMat& m, float (&x)[2][RCfg<BF16>::EK], int z, int r0, int rows,
-                                      int k0, int kend, int li, int lq) {
-  constexpr int EK = RCfg<BF16>::EK;
+template <bool BF16> struct RFrag;
+template <> struct RFrag<true> { bf16x8 v[2]; };
+template <> struct RFrag<false> { float v[2][8]; };
+
+// raw chunk of one operand: V = 1: raw[4 j + e] = row r0 + 8 j + lane / 8, k = k0 + 4 (lane % 8) + e;
+// V = 0: raw[8 i + e] = row r0 + 16 i + li, k = k0 + 8 lq + e.  Rows past the end are
+// clamped into the matrix (computed on valid data, never stored).  FULL: the chunk
+// lies inside the contraction, else k >= kend reads as zero.
+template <int V, bool FULL>
+__device__ __forceinline__ void rload(const RMat& m, float (&raw)[16], int z, int r0, int rows, int k0, int kend,
+                                      int lane) {
   const float* base = m.p + (long long)z * m.sz;
-  const int kq = k0 + EK * lq;
+  if constexpr (V) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    int r = r0 + 16 * i + li;
-    r = r < rows ? r : rows - 1;
-    const float* q = base + (long long)r * m.lr;
-    if constexpr (FULL && V) {
+    for (int j = 0; j < 4; ++j) {
+      const int r = min(r0 + 8 * j + (lane >> 3), rows - 1);
+      const int kq = k0 + 4 * (lane & 7);
+      const float* q = base + (long long)r * m.lr;
+      if constexpr (FULL) {
+        const f4v t = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(q + kq, 16));
 #pragma unroll
-      for (int v = 0; v < EK / 4; ++v) {
-        const f4v t = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(q + kq + 4 * v, 16));
+        for (int e = 0; e < 4; ++e) raw[4 * j + e] = t[e];
+      } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[i][4 * v + e] = t[e];
+        for (int e = 0; e < 4; ++e) {
+          const int k = kq + e;
+          const float v = q[min(k, kend - 1)];   // kend > k0: always a valid element
+          raw[4 * j + e] = k < kend ? v : 0.f;
+        }
       }
-    } else if constexpr (FULL) {
+    }
+  } else {
+    const int li = lane & 15, lq = lane >> 4;
 #pragma unroll
-      for (int e = 0; e < EK; ++e) x[i][e] = q[(long long)(kq + e) * m.lk];
-    } else {
+    for (int i = 0; i < 2; ++i) {
+      const int r = min(r0 + 16 * i + li, rows - 1);
+      const float* q = base + r * m.lr;
 #pragma unroll
-      for (int e = 0; e < EK; ++e) {
-        const int k = kq + e;
-        const float v = q[(long long)min(k, kend - 1) * m.lk];   // kend > k0: always a valid element
-        x[i][e] = k < kend ? v : 0.f;
+      for (int e = 0; e < 8; ++e) {
+        const int k = k0 + 8 * lq + e;
+        if constexpr (FULL) {
+          raw[8 * i + e] = q[(long long)k * m.lk];
+        } else {
+          const float v = q[(long long)min(k, kend - 1) * m.lk];
+          raw[8 * i + e] = k < kend ? v : 0.f;
+        }
       }
     }
   }
 }
 
-template <bool BF16>
-__device__ __forceinline__ void rmma(const float (&a)[2][RCfg<BF16>::EK], const float (&b)[2][RCfg<BF16>::EK],
-                                     v4f (&acc)[2][2]) {
-  if constexpr (!BF16) {
+// raw chunk -> MFMA fragments (through the wave's LDS tile when V = 1)
+template <bool BF16, int V>
+__device__ __forceinline__ void to_frag(const float (&raw)[16], typename RLds<BF16>::T* tile, int lane,
+                                        RFrag<BF16>& f) {
+  using LL = RLds<BF16>;
+  const int li = lane & 15, lq = lane >> 4;
+  if constexpr (V) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 4; ++j) {
+      auto* dst = tile + (8 * j + (lane >> 3)) * LL::LDT + 4 * (lane & 7);
+      if constexpr (BF16) {
+        bf16x4 h;
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int e = 0; e < 4; ++e) h[e] = (__bf16)raw[4 * j + e];
+        *reinterpret_cast<bf16x4*>(dst) = h;
+      } else {
+        *reinterpret_cast<f4v*>(dst) = f4v{raw[4 * j], raw[4 * j + 1], raw[4 * j + 2], raw[4 * j + 3]};
+      }
+    }
+    // the wave's own LDS writes complete before any lane reads them back
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj)
-          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i][j], b[jj][j], acc[i][jj], 0, 0, 0);
+    for (int i = 0; i < 2; ++i) {
+      const auto* src = tile + (16 * i + li) * LL::LDT + 8 * lq;
+      if constexpr (BF16) {
+        f.v[i] = *reinterpret_cast<const bf16x8*>(src);
+      } else {
+        const f4v a = *reinterpret_cast<const f4v*>(src), b = *reinterpret_cast<const f4v*>(src + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          f.v[i][e] = a[e];
+          f.v[i][4 + e] = b[e];
+        }
+      }
+    }
   } else {
-    bf16x8 av[2], bv[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        av[i][e] = (__bf16)a[i][e];
-        bv[i][e] = (__bf16)b[i][e];
+        if constexpr (BF16) f.v[i][e] = (__bf16)raw[8 * i + e];
+        else f.v[i][e] = raw[8 * i + e];
       }
+  }
+}
+
+template <bool BF16>
+__device__ __forceinline__ void rmma(const RFrag<BF16>& a, const RFrag<BF16>& b, v4f (&acc)[2][2]) {
+  if constexpr (BF16) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int jj = 0; jj < 2; ++jj)
-        acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[jj], acc[i][jj], 0, 0, 0);
+        acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v[i], b.v[jj], acc[i][jj], 0, 0, 0);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[i][e], b.v[jj][e], acc[i][jj], 0, 0, 0);
   }
 }
 
 template <bool BF16, int AV, int BV, class ST, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, StPart sp, int M, int N, int K,
                                                      int kchunk) {
-  constexpr int EK = RCfg<BF16>::EK, KC = RCfg<BF16>::KC, G = RCfg<BF16>::G;
+  using LL = RLds<BF16>;
+  using T = typename LL::T;
+  constexpr int KC = kRKC, G = kRG;
   constexpr int RLD = kTile + 1;
-  __shared__ float red[4 * kTile * RLD];
+  constexpr int RED_BYTES = 4 * kTile * RLD * 4;
+  constexpr int TILE_BYTES = (AV || BV) ? 4 * LL::WAVE * (int)sizeof(T) : 0;
+  __shared__ __attribute__((aligned(16))) char lds[TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES];
 
   const int z = blockIdx.z / (SPLIT ? sp.splits : 1);
   const int split = SPLIT ? blockIdx.z % sp.splits : 0;
@@ -392,6 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: chunk tests stay scalar
   const int li = lane & 15, lq = lane >> 4;
+  T* wt = reinterpret_cast<T*>(lds) + wave * LL::WAVE;   // this wave's tiles: [chunk parity][operand]
   // this wave's k range: a quarter of the workgroup's, in whole chunks
   const int span = kend > kbeg ? kend - kbeg : 0;
   const int per = ((span + 3) / 4 + KC - 1) / KC * KC;
@@ -406,17 +477,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  float xa[2][G][2][EK], xb[2][G][2][EK];
+  float ra[2][G][16], rb[2][G][16];
   auto load = [&](int g, int buf) {
 #pragma unroll
     for (int c = 0; c < G; ++c) {
-      rload<BF16, AV, true>(fa, xa[buf][c], z, m0, M, wb + (g * G + c) * KC, we, li, lq);
-      rload<BF16, BV, true>(fb, xb[buf][c], z, n0, N, wb + (g * G + c) * KC, we, li, lq);
+      rload<AV, true>(fa, ra[buf][c], z, m0, M, wb + (g * G + c) * KC, we, lane);
+      rload<BV, true>(fb, rb[buf][c], z, n0, N, wb + (g * G + c) * KC, we, lane);
     }
+  };
+  auto chunk = [&](const float (&a)[16], const float (&b)[16], int parity) {
+    RFrag<BF16> fa_, fb_;
+    to_frag<BF16, AV>(a, wt + (2 * parity) * LL::TILE, lane, fa_);
+    to_frag<BF16, BV>(b, wt + (2 * parity + 1) * LL::TILE, lane, fb_);
+    rmma<BF16>(fa_, fb_, acc);
   };
   auto mult = [&](int buf) {
 #pragma unroll
-    for (int c = 0; c < G; ++c) rmma<BF16>(xa[buf][c], xb[buf][c], acc);
+    for (int c = 0; c < G; ++c) chunk(ra[buf][c], rb[buf][c], c & 1);
   };
   // two register groups in flight: group g + 1 loads while group g multiplies
   if (ngf > 0) load(0, 0);
@@ -431,20 +508,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
   }
   // the rest of the range chunk by chunk, then the partial last chunk
   int k0 = wb + ngf * G * KC;
-  for (; k0 + KC <= we; k0 += KC) {
-    float ta[2][EK], tb[2][EK];
-    rload<BF16, AV, true>(fa, ta, z, m0, M, k0, we, li, lq);
-    rload<BF16, BV, true>(fb, tb, z, n0, N, k0, we, li, lq);
-    rmma<BF16>(ta, tb, acc);
+  int par = 0;
+  for (; k0 + KC <= we; k0 += KC, par ^= 1) {
+    float ta[16], tb[16];
+    rload<AV, true>(fa, ta, z, m0, M, k0, we, lane);
+    rload<BV, true>(fb, tb, z, n0, N, k0, we, lane);
+    chunk(ta, tb, par);
   }
   if (k0 < we) {
-    float ta[2][EK], tb[2][EK];
-    rload<BF16, AV, false>(fa, ta, z, m0, M, k0, we, li, lq);
-    rload<BF16, BV, false>(fb, tb, z, n0, N, k0, we, li, lq);
-    rmma<BF16>(ta, tb, acc);
+    float ta[16], tb[16];
+    rload<AV, false>(fa, ta, z, m0, M, k0, we, lane);
+    rload<BV, false>(fb, tb, z, n0, N, k0, we, lane);
+    chunk(ta, tb, par);
   }
 
-  // fixed-order sum of the four waves' partial tiles
+  // fixed-order sum of the four waves' partial tiles (the buffer overlays the waves' tiles)
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -534,7 +614,7 @@ static int run_r(int M, int N, int K, int batch, const MatArg& A, const MatArg& 
   }
   int kchunk = K > 0 ? K : 1;
   if (splits > 1) {
-    kchunk = cdiv(cdiv(K, splits), 4 * RCfg<BF16>::KC) * 4 * RCfg<BF16>::KC;
+    kchunk = cdiv(cdiv(K, splits), 4 * kRKC) * 4 * kRKC;
     splits = cdiv(K, kchunk);
   }
   const RMat a{A.p, A.lr, A.lk, A.sz}, b{B.p, B.lr, B.lk, B.sz};
