@@ -23,6 +23,12 @@ __device__ __forceinline__ long long pack_pos(const PackArgs& pk, long long i, i
   return -1;
 }
 
+// Each workgroup updates 256 * kAdamPer consecutive parameters.  The packed
+// segment holding the workgroup's first parameter is found once; parameters of
+// that segment map to their packed position with one division, the rare others
+// (a workgroup straddling a segment boundary) search the table.
+constexpr int kAdamPer = 4;
+
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v, long long n,
                                               float lr, float b1, float b2, float eps,
@@ -32,8 +38,16 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
   const float t = (float)(*step + 1);
   const float bc1 = 1.f - powf(b1, t);
   const float bc2 = 1.f - powf(b2, t);
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  const long long b0 = (long long)blockIdx.x * 256 * kAdamPer;
+  int s0 = -1;
+  for (int s = 0; s < pk.n; ++s) {
+    const long long loc = b0 + pk.p_begin - pk.seg[s].src;
+    if (loc >= 0 && loc < (long long)pk.seg[s].rows * pk.seg[s].cols) { s0 = s; break; }
+  }
+#pragma unroll
+  for (int u = 0; u < kAdamPer; ++u) {
+    const long long i = b0 + u * 256 + threadIdx.x;
+    if (i >= n) break;
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.f - b1) * gi;
     const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
@@ -50,7 +64,17 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
     if (shadow) shadow[i] = bf16_bits(pi);
     if (pk.n) {
       int critic = 0;
-      const long long d = pack_pos(pk, i, &critic);
+      long long d = -1;
+      if (s0 >= 0) {
+        const PackSeg& q = pk.seg[s0];
+        const long long loc = i + pk.p_begin - q.src;
+        if (loc < (long long)q.rows * q.cols) {
+          const unsigned r = (unsigned)loc / (unsigned)q.cols;
+          d = q.dst + (long long)r * q.ldp + (loc - (long long)r * q.cols);
+          critic = q.critic;
+        }
+      }
+      if (d < 0) d = pack_pos(pk, i, &critic);
       if (d >= 0) {
         pk.pack[d] = pi;
         if (critic && pk.tpack && ema && i >= ema_begin) pk.tpack[d] = ei;
@@ -62,11 +86,10 @@ __global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
          float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st) {
   if (n <= 0) return SQ_OK;
-  long long blocks = (n + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
+  const long long blocks = (n + 256 * kAdamPer - 1) / (256 * kAdamPer);
   PackArgs none{};
-  k_adam<<<(int)blocks, 256, 0, st>>>(p, g, m, v, n, hp->lr, hp->beta1, hp->beta2, hp->adam_eps, step, ema_target,
-                                      ema_begin, hp->rho, shadow, pk ? *pk : none);
+  k_adam<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, n, hp->lr, hp->beta1, hp->beta2, hp->adam_eps, step,
+                                           ema_target, ema_begin, hp->rho, shadow, pk ? *pk : none);
   return launch_status("adam");
 }
 

@@ -10,12 +10,15 @@
 // from lane 0, and partial sums written per (row block, wave) and summed in order.
 #include <math.h>
 
+#include <type_traits>
+
 #include "../common.h"
 
 namespace sq {
 
-constexpr int kMaxPerLane = 16;   // LayerNorm widths up to 1024
-constexpr int kLnRowsPerBlock = 4; // rows per workgroup (one per wave) in row-partial kernels
+constexpr int kLnRowsPerBlock = 8; // rows per workgroup (one per wave) in row-partial kernels
+
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
@@ -42,6 +45,50 @@ __device__ float block_sum256(float v, float* sh) {
 }
 
 // ---------------------------------------------------------------- LayerNorm forward
+// Lane j-mapping of a row of H floats: VEC (H a multiple of 256, 16-byte aligned
+// rows): element t of the lane is column 256 (t / 4) + 4 lane + t % 4, read and
+// written as float4; otherwise column lane + 64 t.  E = elements per lane.
+template <int E, bool VEC>
+__device__ __forceinline__ int ln_col(int lane, int t) {
+  return VEC ? 256 * (t >> 2) + 4 * lane + (t & 3) : lane + 64 * t;
+}
+
+template <int E, bool VEC>
+__device__ __forceinline__ void ln_load_row(const float* __restrict__ p, int H, int lane, float (&v)[E]) {
+  if constexpr (VEC) {
+#pragma unroll
+    for (int c = 0; c < E / 4; ++c) {
+      const f4v x = *reinterpret_cast<const f4v*>(__builtin_assume_aligned(p + 256 * c + 4 * lane, 16));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[4 * c + e] = x[e];
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int j = lane + 64 * t;
+      v[t] = j < H ? p[j] : 0.f;
+    }
+  }
+}
+
+template <int E, bool VEC>
+__device__ __forceinline__ void ln_store_row(float* __restrict__ p, int H, int lane, const float (&v)[E]) {
+  if constexpr (VEC) {
+#pragma unroll
+    for (int c = 0; c < E / 4; ++c)
+      *reinterpret_cast<f4v*>(__builtin_assume_aligned(p + 256 * c + 4 * lane, 16)) =
+          f4v{v[4 * c], v[4 * c + 1], v[4 * c + 2], v[4 * c + 3]};
+  } else {
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int j = lane + 64 * t;
+      if (j < H) p[j] = v[t];
+    }
+  }
+}
+
+// one row per wave; the row, gain and shift are all requested before the reductions
+template <int E, bool VEC>
 __global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, long long ld_pre, long long sz_pre,
                                                 int rows, int H, const float* __restrict__ g,
                                                 const float* __restrict__ beta, long long sz_par, int act_tanh,
@@ -53,42 +100,58 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, l
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int z = blockIdx.y;
   if (row >= rows) return;
-  const float* p = pre + z * sz_pre + row * ld_pre;
-  float v[kMaxPerLane];
+  const float* gz = g + z * sz_par;
+  const float* bz = beta + z * sz_par;
+  float v[E], gv[E], bv[E];
+  ln_load_row<E, VEC>(pre + z * sz_pre + row * ld_pre, H, lane, v);
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int j = ln_col<E, VEC>(lane, t);
+    gv[t] = j < H ? gz[j] : 0.f;
+    bv[t] = j < H ? bz[j] : 0.f;
+  }
   float s = 0.f;
 #pragma unroll
-  for (int t = 0; t < kMaxPerLane; ++t) {
-    const int j = lane + 64 * t;
-    v[t] = j < H ? p[j] : 0.f;
-    s += v[t];
-  }
+  for (int t = 0; t < E; ++t) s += v[t];
   const float mean = wave_sum(s) / (float)H;
   float q = 0.f;
 #pragma unroll
-  for (int t = 0; t < kMaxPerLane; ++t) {
-    const int j = lane + 64 * t;
-    const float dv = j < H ? v[t] - mean : 0.f;
+  for (int t = 0; t < E; ++t) {
+    const float dv = ln_col<E, VEC>(lane, t) < H ? v[t] - mean : 0.f;
     q += dv * dv;
   }
   const float var = wave_sum(q) / (float)H;
   const float rs = 1.0f / sqrtf(var + 1e-5f);
-  const float* gz = g + z * sz_par;
-  const float* bz = beta + z * sz_par;
-  float* yr = y + z * sz_y + row * ld_y;
-  float* xr = xhat + ((long long)z * rows + row) * H;
+  float xh[E], o[E];
 #pragma unroll
-  for (int t = 0; t < kMaxPerLane; ++t) {
-    const int j = lane + 64 * t;
-    if (j < H) {
-      const float xh = (v[t] - mean) * rs;
-      const float o = gz[j] * xh + bz[j];
-      xr[j] = xh;
-      yr[j] = act_tanh ? tanhf(o) : fmaxf(o, 0.f);
-    }
+  for (int t = 0; t < E; ++t) {
+    xh[t] = (v[t] - mean) * rs;
+    const float a = gv[t] * xh[t] + bv[t];
+    o[t] = act_tanh ? tanhf(a) : fmaxf(a, 0.f);
   }
+  float* yr = y + z * sz_y + row * ld_y;
+  ln_store_row<E, VEC>(xhat + ((long long)z * rows + row) * H, H, lane, xh);
+  ln_store_row<E, VEC>(yr, H, lane, o);
   if (lane == 0) rstd[(long long)z * rows + row] = rs;
   for (int j = lane; j < w1; j += 64) yr[H + j] = e1[row * ld_e1 + j];
   for (int j = lane; j < w2; j += 64) yr[H + w1 + j] = e2[row * ld_e2 + j];
+}
+
+static bool al16(const void* p, long long a = 0, long long b = 0) {
+  return (uintptr_t)p % 16 == 0 && a % 4 == 0 && b % 4 == 0;
+}
+
+// E = elements per lane (a power of two covering H), VEC as above
+template <class F>
+static int ln_dispatch(int H, bool vec_ok, F&& f) {
+  if (vec_ok && H == 256) return f(std::integral_constant<int, 4>{}, std::true_type{});
+  if (vec_ok && H == 512) return f(std::integral_constant<int, 8>{}, std::true_type{});
+  if (vec_ok && H == 1024) return f(std::integral_constant<int, 16>{}, std::true_type{});
+  if (H <= 64) return f(std::integral_constant<int, 1>{}, std::false_type{});
+  if (H <= 128) return f(std::integral_constant<int, 2>{}, std::false_type{});
+  if (H <= 256) return f(std::integral_constant<int, 4>{}, std::false_type{});
+  if (H <= 512) return f(std::integral_constant<int, 8>{}, std::false_type{});
+  return f(std::integral_constant<int, 16>{}, std::false_type{});
 }
 
 int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch, const float* g,
@@ -96,87 +159,81 @@ int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, i
                float* xhat, float* rstd, const float* e1, long long ld_e1, int w1, const float* e2,
                long long ld_e2, int w2, hipStream_t st) {
   if (rows <= 0) return SQ_OK;
+  const bool vec = al16(pre, ld_pre, sz_pre) && al16(y, ld_y, sz_y) && al16(xhat, H);
   dim3 grid(cdiv(rows, 4), batch);
-  k_ln_fwd<<<grid, 256, 0, st>>>(pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat,
-                                 rstd, e1, ld_e1, w1, e2, ld_e2, w2);
-  return launch_status("ln_fwd");
+  return ln_dispatch(H, vec, [&](auto e, auto v) {
+    k_ln_fwd<decltype(e)::value, decltype(v)::value><<<grid, 256, 0, st>>>(
+        pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1, ld_e1, w1, e2, ld_e2,
+        w2);
+    return launch_status("ln_fwd");
+  });
 }
 
 // ---------------------------------------------------------------- LayerNorm backward
 // Per row: dz = dy * act'(y), dxh = dz * g,
 //   dpre = rstd * (dxh - mean(dxh) - xhat * mean(dxh * xhat)).
-// One row per wave, four rows per workgroup.  Column partials of the
-// workgroup's rows, summed over its waves in order, go to part[z][3][blk][H] =
-// (dpre, dz * xhat, dz) for the bias, gain and shift gradients.
-__global__ __launch_bounds__(256) void k_ln_bwd(const float* __restrict__ dy, long long ld_dy, long long sz_dy,
-                                                const float* __restrict__ y, long long ld_y, long long sz_y,
-                                                const float* __restrict__ xhat, const float* __restrict__ rstd,
-                                                const float* __restrict__ g, long long sz_par, int rows, int H,
-                                                int act_tanh, float* __restrict__ dpre,
-                                                float* __restrict__ part) {
-  extern __shared__ float shp[];   // [3][4][H] when partials are wanted
+// One row per wave, kLnRowsPerBlock rows (waves) per workgroup.  Column partials
+// of the workgroup's rows, summed over its waves in order, go to
+// part[z][3][blk][H] = (dpre, dz * xhat, dz) for the bias, gain and shift gradients.
+template <int E, bool VEC>
+__global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_ln_bwd(
+    const float* __restrict__ dy, long long ld_dy, long long sz_dy, const float* __restrict__ y, long long ld_y,
+    long long sz_y, const float* __restrict__ xhat, const float* __restrict__ rstd, const float* __restrict__ g,
+    long long sz_par, int rows, int H, int act_tanh, float* __restrict__ dpre, float* __restrict__ part) {
+  extern __shared__ float shp[];   // [3][kLnRowsPerBlock][H] when partials are wanted
+  constexpr int R = kLnRowsPerBlock;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int blk = blockIdx.x, z = blockIdx.y;
   const int nblk = gridDim.x;
-  const int row = blk * kLnRowsPerBlock + wave;
+  const int row = blk * R + wave;
   const float* gz = g + z * sz_par;
-  float pb[kMaxPerLane], pg[kMaxPerLane], pz[kMaxPerLane];
+  float pb[E], pg[E], pz[E];
 #pragma unroll
-  for (int t = 0; t < kMaxPerLane; ++t) pb[t] = pg[t] = pz[t] = 0.f;
+  for (int t = 0; t < E; ++t) pb[t] = pg[t] = pz[t] = 0.f;
   if (row < rows) {
-    const float* dyr = dy + z * sz_dy + row * ld_dy;
-    const float* yr = y + z * sz_y + row * ld_y;
-    const float* xr = xhat + ((long long)z * rows + row) * H;
+    float dv[E], yv[E], xh[E], gv[E];
+    ln_load_row<E, VEC>(dy + z * sz_dy + row * ld_dy, H, lane, dv);
+    ln_load_row<E, VEC>(y + z * sz_y + row * ld_y, H, lane, yv);
+    ln_load_row<E, VEC>(xhat + ((long long)z * rows + row) * H, H, lane, xh);
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int j = ln_col<E, VEC>(lane, t);
+      gv[t] = j < H ? gz[j] : 0.f;
+    }
     const float rs = rstd[(long long)z * rows + row];
-    float dz[kMaxPerLane], xh[kMaxPerLane];
+    float dz[E];
     float s1 = 0.f, s2 = 0.f;
 #pragma unroll
-    for (int t = 0; t < kMaxPerLane; ++t) {
-      const int j = lane + 64 * t;
-      if (j < H) {
-        const float yy = yr[j];
-        const float d = dyr[j] * (act_tanh ? (1.f - yy * yy) : (yy > 0.f ? 1.f : 0.f));
-        dz[t] = d;
-        xh[t] = xr[j];
-        const float dx = d * gz[j];
-        s1 += dx;
-        s2 += dx * xh[t];
-      } else {
-        dz[t] = 0.f;
-        xh[t] = 0.f;
-      }
+    for (int t = 0; t < E; ++t) {
+      const float yy = yv[t];
+      dz[t] = dv[t] * (act_tanh ? (1.f - yy * yy) : (yy > 0.f ? 1.f : 0.f));
+      const float dx = dz[t] * gv[t];
+      s1 += dx;
+      s2 += dx * xh[t];
     }
     const float c1 = wave_sum(s1) / (float)H;
     const float c2 = wave_sum(s2) / (float)H;
-    float* dp = dpre + ((long long)z * rows + row) * H;
 #pragma unroll
-    for (int t = 0; t < kMaxPerLane; ++t) {
-      const int j = lane + 64 * t;
-      if (j < H) {
-        const float v = rs * (dz[t] * gz[j] - c1 - xh[t] * c2);
-        dp[j] = v;
-        pb[t] = v;
-        pg[t] = dz[t] * xh[t];
-        pz[t] = dz[t];
-      }
+    for (int t = 0; t < E; ++t) {
+      pb[t] = rs * (dz[t] * gv[t] - c1 - xh[t] * c2);
+      pg[t] = dz[t] * xh[t];
+      pz[t] = dz[t];
     }
+    ln_store_row<E, VEC>(dpre + ((long long)z * rows + row) * H, H, lane, pb);
   }
   if (!part) return;
-#pragma unroll
-  for (int t = 0; t < kMaxPerLane; ++t) {
-    const int j = lane + 64 * t;
-    if (j < H) {
-      shp[(0 * 4 + wave) * H + j] = pb[t];
-      shp[(1 * 4 + wave) * H + j] = pg[t];
-      shp[(2 * 4 + wave) * H + j] = pz[t];
-    }
-  }
+  ln_store_row<E, VEC>(shp + (0 * R + wave) * H, H, lane, pb);
+  ln_store_row<E, VEC>(shp + (1 * R + wave) * H, H, lane, pg);
+  ln_store_row<E, VEC>(shp + (2 * R + wave) * H, H, lane, pz);
   __syncthreads();
   float* pp = part + (long long)z * 3 * nblk * H + (long long)blk * H;
-  for (int e = threadIdx.x; e < 3 * H; e += 256) {
+  for (int e = threadIdx.x; e < 3 * H; e += 64 * R) {
     const int k = e / H, j = e - k * H;
-    const float* q = shp + k * 4 * H + j;
-    pp[(long long)k * nblk * H + j] = ((q[0] + q[H]) + q[2 * H]) + q[3 * H];
+    const float* q = shp + k * R * H + j;
+    float s = q[0];
+#pragma unroll
+    for (int w = 1; w < R; ++w) s += q[w * H];
+    pp[(long long)k * nblk * H + j] = s;
   }
 }
 
@@ -187,10 +244,13 @@ int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y
                int act_tanh, float* dpre, float* partials, hipStream_t st) {
   if (rows <= 0) return SQ_OK;
   dim3 grid(cdiv(rows, kLnRowsPerBlock), batch);
-  const size_t lds = partials ? (size_t)3 * 4 * H * sizeof(float) : 0;
-  k_ln_bwd<<<grid, 256, lds, st>>>(dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, sz_par, rows, H, act_tanh, dpre,
-                                   partials);
-  return launch_status("ln_bwd");
+  const size_t lds = partials ? (size_t)3 * kLnRowsPerBlock * H * sizeof(float) : 0;
+  const bool vec = al16(dy, ld_dy, sz_dy) && al16(y, ld_y, sz_y) && al16(xhat, H) && al16(dpre, H);
+  return ln_dispatch(H, vec, [&](auto e, auto v) {
+    k_ln_bwd<decltype(e)::value, decltype(v)::value><<<grid, 64 * kLnRowsPerBlock, lds, st>>>(
+        dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, sz_par, rows, H, act_tanh, dpre, partials);
+    return launch_status("ln_bwd");
+  });
 }
 
 // ---------------------------------------------------------------- column partials
