@@ -409,8 +409,8 @@ __global__ __launch_bounds__(256) void k_enc_reduce(const float* __restrict__ pa
 }
 
 // ---------------------------------------------------------------- launchers
-constexpr int kEncFwdG = 2, kEncFwdThreads = 256;
-constexpr int kEncBwdG = 2, kEncBwdThreads = 256;
+constexpr int kEncFwdG = 2, kEncFwdThreads = 512;
+constexpr int kEncBwdG = 2, kEncBwdThreads = 512;
 
 template <int C, int F, int NC>
 static int prep_t(const float* const* W, float* wp, int bf16, hipStream_t st) {
