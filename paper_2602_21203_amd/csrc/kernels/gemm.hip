@@ -324,7 +324,7 @@ template <bool BF16> struct RLds {
   using T = typename std::conditional<BF16, __bf16, float>::type;
   static constexpr int LDT = BF16 ? 40 : 36;              // row stride of a transposition tile (elements)
   static constexpr int TILE = 32 * LDT;                   // one operand's 32 x 32 chunk
-  static constexpr int WAVE = 2 * 2 * TILE;               // two operands, two alternating chunks
+  static constexpr int WAVE = 2 * kRG * TILE;             // two operands for each chunk of a group
 };
 
 template <bool BF16> struct RFrag;
@@ -378,12 +378,12 @@ __device__ __forceinline__ void rload(const RMat& m, float (&raw)[16], int z, in
   }
 }
 
-// raw chunk -> MFMA fragments (through the wave's LDS tile when V = 1)
+// raw chunk -> MFMA fragments.  V = 1 goes through the wave's LDS tile in two
+// steps, so that the LDS round trips of a whole register group overlap: stage()
+// writes the chunk, frag() reads the fragments back after the group's single wait.
 template <bool BF16, int V>
-__device__ __forceinline__ void to_frag(const float (&raw)[16], typename RLds<BF16>::T* tile, int lane,
-                                        RFrag<BF16>& f) {
+__device__ __forceinline__ void stage(const float (&raw)[16], typename RLds<BF16>::T* tile, int lane) {
   using LL = RLds<BF16>;
-  const int li = lane & 15, lq = lane >> 4;
   if constexpr (V) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -397,8 +397,15 @@ __device__ __forceinline__ void to_frag(const float (&raw)[16], typename RLds<BF
         *reinterpret_cast<f4v*>(dst) = f4v{raw[4 * j], raw[4 * j + 1], raw[4 * j + 2], raw[4 * j + 3]};
       }
     }
-    // the wave's own LDS writes complete before any lane reads them back
-    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  }
+}
+
+template <bool BF16, int V>
+__device__ __forceinline__ void frag(const float (&raw)[16], const typename RLds<BF16>::T* tile, int lane,
+                                     RFrag<BF16>& f) {
+  using LL = RLds<BF16>;
+  const int li = lane & 15, lq = lane >> 4;
+  if constexpr (V) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const auto* src = tile + (16 * i + li) * LL::LDT + 8 * lq;
@@ -423,6 +430,10 @@ __device__ __forceinline__ void to_frag(const float (&raw)[16], typename RLds<BF
       }
   }
 }
+
+// the wave's own LDS writes complete before any lane reads them back (and the
+// compiler keeps every LDS access on its side of this point)
+__device__ __forceinline__ void lds_wave_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 template <bool BF16>
 __device__ __forceinline__ void rmma(const RFrag<BF16>& a, const RFrag<BF16>& b, v4f (&acc)[2][2]) {
@@ -462,7 +473,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: chunk tests stay scalar
   const int li = lane & 15, lq = lane >> 4;
-  T* wt = reinterpret_cast<T*>(lds) + wave * LL::WAVE;   // this wave's tiles: [chunk parity][operand]
+  T* wt = reinterpret_cast<T*>(lds) + wave * LL::WAVE;   // this wave's tiles: [chunk of the group][operand]
   // this wave's k range: a quarter of the workgroup's, in whole chunks
   const int span = kend > kbeg ? kend - kbeg : 0;
   const int per = ((span + 3) / 4 + KC - 1) / KC * KC;
@@ -485,15 +496,36 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
       rload<BV, true>(fb, rb[buf][c], z, n0, N, wb + (g * G + c) * KC, we, lane);
     }
   };
-  auto chunk = [&](const float (&a)[16], const float (&b)[16], int parity) {
-    RFrag<BF16> fa_, fb_;
-    to_frag<BF16, AV>(a, wt + (2 * parity) * LL::TILE, lane, fa_);
-    to_frag<BF16, BV>(b, wt + (2 * parity + 1) * LL::TILE, lane, fb_);
-    rmma<BF16>(fa_, fb_, acc);
-  };
+  // a group's chunks: stage all (V = 1), one wait, then fragments and products
   auto mult = [&](int buf) {
+    if constexpr (AV || BV) {
 #pragma unroll
-    for (int c = 0; c < G; ++c) chunk(ra[buf][c], rb[buf][c], c & 1);
+      for (int c = 0; c < G; ++c) {
+        stage<BF16, AV>(ra[buf][c], wt + (2 * c) * LL::TILE, lane);
+        stage<BF16, BV>(rb[buf][c], wt + (2 * c + 1) * LL::TILE, lane);
+      }
+      lds_wave_sync();
+    }
+#pragma unroll
+    for (int c = 0; c < G; ++c) {
+      RFrag<BF16> fa_, fb_;
+      frag<BF16, AV>(ra[buf][c], wt + (2 * c) * LL::TILE, lane, fa_);
+      frag<BF16, BV>(rb[buf][c], wt + (2 * c + 1) * LL::TILE, lane, fb_);
+      rmma<BF16>(fa_, fb_, acc);
+    }
+    if constexpr (AV || BV) asm volatile("" ::: "memory");
+  };
+  auto chunk = [&](const float (&a)[16], const float (&b)[16]) {
+    RFrag<BF16> fa_, fb_;
+    if constexpr (AV || BV) {
+      stage<BF16, AV>(a, wt, lane);
+      stage<BF16, BV>(b, wt + LL::TILE, lane);
+      lds_wave_sync();
+    }
+    frag<BF16, AV>(a, wt, lane, fa_);
+    frag<BF16, BV>(b, wt + LL::TILE, lane, fb_);
+    rmma<BF16>(fa_, fb_, acc);
+    if constexpr (AV || BV) asm volatile("" ::: "memory");
   };
   // two register groups in flight: group g + 1 loads while group g multiplies
   if (ngf > 0) load(0, 0);
@@ -508,18 +540,17 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
   }
   // the rest of the range chunk by chunk, then the partial last chunk
   int k0 = wb + ngf * G * KC;
-  int par = 0;
-  for (; k0 + KC <= we; k0 += KC, par ^= 1) {
+  for (; k0 + KC <= we; k0 += KC) {
     float ta[16], tb[16];
     rload<AV, true>(fa, ta, z, m0, M, k0, we, lane);
     rload<BV, true>(fb, tb, z, n0, N, k0, we, lane);
-    chunk(ta, tb, par);
+    chunk(ta, tb);
   }
   if (k0 < we) {
     float ta[16], tb[16];
     rload<AV, false>(fa, ta, z, m0, M, k0, we, lane);
     rload<BV, false>(fb, tb, z, n0, N, k0, we, lane);
-    chunk(ta, tb, par);
+    chunk(ta, tb);
   }
 
   // fixed-order sum of the four waves' partial tiles (the buffer overlays the waves' tiles)
