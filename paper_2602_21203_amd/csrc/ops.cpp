@@ -105,7 +105,8 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
 }
 
 int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
-                     const float* dfeat, const EncBufs& e, float* dep, hipStream_t st) {
+                     const float* dfeat, const EncBufs& e, float* dep, hipStream_t st,
+                     bool prepared) {
   const sq_dims& d = net.d;
   if (e.enc_part) {
     const float* W[4];
@@ -117,7 +118,7 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
       Wo[i] = L.conv_W[i];
       bo[i] = L.conv_b[i];
     }
-    SQ_TRY(encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st));
+    if (!prepared) SQ_TRY(encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st));
     return encoder_fused_bwd(bf16, d.C, d.F, d.n_conv, x, n, dfeat, e.wprep, h, Wo, bo, L.enc_end, e.enc_part, dep,
                              st);
   }

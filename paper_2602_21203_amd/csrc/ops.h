@@ -19,8 +19,11 @@ struct EncBufs {
 void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd);
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                     const EncBufs& e, hipStream_t st);
+// prepared: the fused path's rearranged weights from encoder_forward of the same
+// parameters and precision are still in e.wprep (inside one update)
 int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
-                     const float* dfeat, const EncBufs& e, float* dep, hipStream_t st);
+                     const float* dfeat, const EncBufs& e, float* dep, hipStream_t st,
+                     bool prepared = false);
 
 struct DenseSave { float* xhat; float* rstd; };
 struct CriticBufs {
