@@ -104,10 +104,10 @@ static size_t plan_agent(sq_agent* g, char* base) {
   g->act2B = b.take<float>((size_t)2 * B * A);
   g->logp2B = b.take<float>((size_t)2 * B);
   plan_actor(net, 2 * B, b, &g->actor, true);
-  plan_critic(net, B, b, &g->crit, true);
+  plan_critic(net, B, b, &g->crit, true, 2);
   plan_critic(net, B, b, &g->aux, true);
-  g->logits_t = b.take<float>((size_t)2 * B * N);
-  g->logits = b.take<float>((size_t)2 * B * N);
+  g->logits = b.take<float>((size_t)4 * B * N);     // online twins, then target twins
+  g->logits_t = g->logits ? g->logits + (size_t)2 * B * N : nullptr;
   g->logits_q = b.take<float>((size_t)2 * B * N);
   g->mt = b.take<float>((size_t)B * N);
   g->dlogits = b.take<float>((size_t)2 * B * N);
@@ -145,14 +145,14 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   const float* feat = g->enc.h[d.n_conv - 1];
   SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
                        g->logp2B, g->actor, st));
+  // online critics on (z, s, a) and target critics on (z', s', a~') in one pass
+  SQ_TRY(critic_forward_pair(net, bf, P + L.critic_begin, g->target, g->pack, g->tpack, L, feat, flat,
+                             (long long)B * flat, g->S2, S, (long long)B * S, g->Arep, g->act2B + (size_t)B * A, A, B,
+                             g->logits, g->crit, st));
   // distributional soft target from the averaged twin target critics
-  SQ_TRY(critic_forward(net, bf, g->target, g->tpack, L, feat + (size_t)B * flat, flat, g->S2 + (size_t)B * S, S,
-                        g->act2B + (size_t)B * A, A, B, g->logits_t, g->aux, st));
   SQ_TRY(project_target(g->logits_t, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma,
                         g->mt, g->tgt_row, st));
   // critic + encoder step
-  SQ_TRY(critic_forward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->S2, S, g->Arep, A, B, g->logits,
-                        g->crit, st));
   SQ_TRY(ce_loss(g->logits, g->mt, B, N, d.v_min, d.v_max, g->dlogits, g->loss_row, g->q_row, st));
   SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
                          g->dfeat, nullptr, st));

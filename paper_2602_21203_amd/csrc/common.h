@@ -120,14 +120,21 @@ int act_noise_rows(unsigned long long seed, const unsigned long long* ids, const
                    int A, float* eps, hipStream_t st);
 
 // gemm.hip
-struct MatArg {            // element (r, k) at p[z*sz + r*lr + k*lk]
+// Batch index z of an operand: zi = z / zdiv; element (r, k) at
+// p[zi*sz + r*lr + k*lk] for zi < zalt, else alt[(zi - zalt)*sz + r*lr + k*lk]
+// (two groups of batches in separate allocations, e.g. online and target nets).
+constexpr int kNoAlt = 1 << 30;
+struct MatArg {
   const float* p; long long lr, lk, sz;
+  const float* alt = nullptr; int zalt = kNoAlt; int zdiv = 1;
 };
 struct OutArg {            // C(r, c) at p[z*sz + r*ld + c]
   float* p; long long ld, sz;
   const float* bias; long long bias_sz;  // bias[c] (+ z*bias_sz), nullable
   int accumulate;                        // C += result
   int relu;                              // C = max(C, 0) after bias / accumulate
+  const float* bias_alt = nullptr;       // bias of batches z >= bias_zalt: bias_alt + (z - bias_zalt)*bias_sz
+  int bias_zalt = kNoAlt;
 };
 // C(r, c) = sum_k A(r, k) * B(c, k)   (B is addressed by output column, then k).
 // scratch (nullable) enables a deterministic split over K for small outputs.
@@ -161,11 +168,17 @@ int encoder_fused_bwd(int bf16, int C, int F, int n_conv, const float* x, int n,
                       float* part, float* grad, hipStream_t st);
 
 // rowops.hip
+// Second parameter group of a LayerNorm batch (batches z >= zalt read their gain
+// and shift from g_alt / beta_alt, their second extra block from e2_alt), and the
+// batch stride of the first extra block.
+struct LnGroups {
+  int zalt; const float* g_alt; const float* beta_alt; long long sz_e1; const float* e2_alt;
+};
 int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch,
                const float* g, const float* beta, long long sz_par, int act_tanh,
                float* y, long long ld_y, long long sz_y, float* xhat, float* rstd,
                const float* e1, long long ld_e1, int w1, const float* e2, long long ld_e2, int w2,
-               hipStream_t st);
+               hipStream_t st, const struct LnGroups* grp = nullptr);
 int ln_bwd_partial_rows(int rows);
 int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y, long long ld_y,
                long long sz_y, const float* xhat, const float* rstd, const float* g, long long sz_par,

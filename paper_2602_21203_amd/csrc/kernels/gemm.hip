@@ -118,10 +118,11 @@ struct FConvDxB {
 // ---------------------------------------------------------------- stores
 struct StMat {
   float* p; long long ld, sz; const float* bias; long long bias_sz; int acc, relu;
+  const float* bias_alt = nullptr; int bias_zalt = kNoAlt;
   static constexpr bool ROW_FAST = false;
   __device__ __forceinline__ void put(int z, int r, int c, float v) const {
     const long long i = z * sz + (long long)r * ld + c;
-    if (bias) v += bias[z * bias_sz + c];
+    if (bias) v += z < bias_zalt ? bias[z * bias_sz + c] : bias_alt[(z - bias_zalt) * bias_sz + c];
     if (acc) v += p[i];
     if (relu) v = fmaxf(v, 0.f);
     p[i] = v;
@@ -312,6 +313,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
 // (v_cvt_pk_bf16_f32) on the way to LDS or to the fragment.
 struct RMat {
   const float* p; long long lr, lk, sz;
+  const float* alt; int zalt, zdiv;   // batch groups, as MatArg
+  __device__ __forceinline__ const float* batch(int z) const {
+    const int zi = z / zdiv;
+    return zi < zalt ? p + (long long)zi * sz : alt + (long long)(zi - zalt) * sz;
+  }
 };
 
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -338,7 +344,7 @@ template <> struct RFrag<false> { float v[2][8]; };
 template <int V, bool FULL>
 __device__ __forceinline__ void rload(const RMat& m, float (&raw)[16], int z, int r0, int rows, int k0, int kend,
                                       int lane) {
-  const float* base = m.p + (long long)z * m.sz;
+  const float* base = m.batch(z);
   if constexpr (V) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -630,7 +636,8 @@ static int run(int bf16, int M, int N, int K, int batch, FA fa, FB fb, ST st, fl
 // ---------------------------------------------------------------- public launchers
 // 1: k is the contiguous dimension of 16-byte aligned rows (vector loads), else 0
 static int rkind(const MatArg& a) {
-  return ((uintptr_t)a.p % 16 == 0 && a.sz % 4 == 0 && a.lk == 1 && a.lr % 4 == 0) ? 1 : 0;
+  return ((uintptr_t)a.p % 16 == 0 && (!a.alt || (uintptr_t)a.alt % 16 == 0) && a.sz % 4 == 0 && a.lk == 1 &&
+          a.lr % 4 == 0) ? 1 : 0;
 }
 
 template <bool BF16, int AV, int BV>
@@ -648,7 +655,7 @@ static int run_r(int M, int N, int K, int batch, const MatArg& A, const MatArg& 
     kchunk = cdiv(cdiv(K, splits), 4 * kRKC) * 4 * kRKC;
     splits = cdiv(K, kchunk);
   }
-  const RMat a{A.p, A.lr, A.lk, A.sz}, b{B.p, B.lr, B.lk, B.sz};
+  const RMat a{A.p, A.lr, A.lk, A.sz, A.alt, A.zalt, A.zdiv}, b{B.p, B.lr, B.lk, B.sz, B.alt, B.zalt, B.zdiv};
   StPart sp{scratch, M, N, splits};
   dim3 grid(cdiv(M, kTile), cdiv(N, kTile), batch * splits);
   if (splits <= 1) {
@@ -665,7 +672,7 @@ static int run_r(int M, int N, int K, int batch, const MatArg& A, const MatArg& 
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return SQ_OK;
-  StMat out{C.p, C.ld, C.sz, C.bias, C.bias_sz, C.accumulate, C.relu};
+  StMat out{C.p, C.ld, C.sz, C.bias, C.bias_sz, C.accumulate, C.relu, C.bias_alt, C.bias_zalt};
   const int va = rkind(A), vb = rkind(B);
   if (bf16) {
     if (va && vb) return run_r<true, 1, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);

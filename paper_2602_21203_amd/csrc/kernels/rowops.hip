@@ -95,13 +95,15 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, l
                                                 float* __restrict__ y, long long ld_y, long long sz_y,
                                                 float* __restrict__ xhat, float* __restrict__ rstd,
                                                 const float* __restrict__ e1, long long ld_e1, int w1,
-                                                const float* __restrict__ e2, long long ld_e2, int w2) {
+                                                const float* __restrict__ e2, long long ld_e2, int w2,
+                                                LnGroups grp) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int z = blockIdx.y;
   if (row >= rows) return;
-  const float* gz = g + z * sz_par;
-  const float* bz = beta + z * sz_par;
+  const bool second = z >= grp.zalt;
+  const float* gz = second ? grp.g_alt + (z - grp.zalt) * sz_par : g + z * sz_par;
+  const float* bz = second ? grp.beta_alt + (z - grp.zalt) * sz_par : beta + z * sz_par;
   float v[E], gv[E], bv[E];
   ln_load_row<E, VEC>(pre + z * sz_pre + row * ld_pre, H, lane, v);
 #pragma unroll
@@ -133,8 +135,10 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, l
   ln_store_row<E, VEC>(xhat + ((long long)z * rows + row) * H, H, lane, xh);
   ln_store_row<E, VEC>(yr, H, lane, o);
   if (lane == 0) rstd[(long long)z * rows + row] = rs;
-  for (int j = lane; j < w1; j += 64) yr[H + j] = e1[row * ld_e1 + j];
-  for (int j = lane; j < w2; j += 64) yr[H + w1 + j] = e2[row * ld_e2 + j];
+  const float* e1z = e1 + z * grp.sz_e1;
+  const float* e2z = second && grp.e2_alt ? grp.e2_alt : e2;
+  for (int j = lane; j < w1; j += 64) yr[H + j] = e1z[row * ld_e1 + j];
+  for (int j = lane; j < w2; j += 64) yr[H + w1 + j] = e2z[row * ld_e2 + j];
 }
 
 static bool al16(const void* p, long long a = 0, long long b = 0) {
@@ -157,14 +161,15 @@ static int ln_dispatch(int H, bool vec_ok, F&& f) {
 int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch, const float* g,
                const float* beta, long long sz_par, int act_tanh, float* y, long long ld_y, long long sz_y,
                float* xhat, float* rstd, const float* e1, long long ld_e1, int w1, const float* e2,
-               long long ld_e2, int w2, hipStream_t st) {
+               long long ld_e2, int w2, hipStream_t st, const LnGroups* groups) {
   if (rows <= 0) return SQ_OK;
+  const LnGroups grp = groups ? *groups : LnGroups{kNoAlt, nullptr, nullptr, 0, nullptr};
   const bool vec = al16(pre, ld_pre, sz_pre) && al16(y, ld_y, sz_y) && al16(xhat, H);
   dim3 grid(cdiv(rows, 4), batch);
   return ln_dispatch(H, vec, [&](auto e, auto v) {
     k_ln_fwd<decltype(e)::value, decltype(v)::value><<<grid, 256, 0, st>>>(
         pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1, ld_e1, w1, e2, ld_e2,
-        w2);
+        w2, grp);
     return launch_status("ln_fwd");
   });
 }

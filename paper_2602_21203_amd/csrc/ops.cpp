@@ -140,20 +140,21 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
 }
 
 // ---------------------------------------------------------------- critic
-void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd) {
+void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd, int nets) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cpad;
   const int wmax = std::max(std::max(H, P), N);
-  c->pre = b.take<float>((size_t)2 * n * wmax);
-  c->X1 = b.take<float>((size_t)n * cin);
-  c->t.xhat = b.take<float>((size_t)n * P);
-  c->t.rstd = b.take<float>(n);
-  c->l1.xhat = b.take<float>((size_t)2 * n * H);
-  c->l1.rstd = b.take<float>((size_t)2 * n);
-  c->l2.xhat = b.take<float>((size_t)2 * n * H);
-  c->l2.rstd = b.take<float>((size_t)2 * n);
-  c->g1 = b.take<float>((size_t)2 * n * H);
-  c->g2 = b.take<float>((size_t)2 * n * H);
+  const size_t k = (size_t)nets;
+  c->pre = b.take<float>(2 * k * n * wmax);
+  c->X1 = b.take<float>(k * n * cin);
+  c->t.xhat = b.take<float>(k * n * P);
+  c->t.rstd = b.take<float>(k * n);
+  c->l1.xhat = b.take<float>(2 * k * n * H);
+  c->l1.rstd = b.take<float>(2 * k * n);
+  c->l2.xhat = b.take<float>(2 * k * n * H);
+  c->l2.rstd = b.take<float>(2 * k * n);
+  c->g1 = b.take<float>(2 * k * n * H);
+  c->g2 = b.take<float>(2 * k * n * H);
   c->dA = c->dB = c->dX1 = c->part_t = c->part_l1 = c->part_l2 = c->part_out = c->split = nullptr;
   if (with_bwd) {
     const int pr = ln_bwd_partial_rows(n);
@@ -195,6 +196,49 @@ int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack
                     c.l2.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
   return linear_fwd(bf16, n, N, H, 2, c.g2, H, nH, w.W(q.out.W, q.out.Wp), w.ld(q.out.in, q.out.ldp), twW,
                     cp + (q.out.b - c0), tw, logits, N, (long long)n * N, st);
+}
+
+// Online (group 0) and target (group 1) twin critics in one pass: the trunk
+// runs as a batch of 2 nets, the twin layers as a batch of 4 (online twins, then
+// target twins), so every GEMM and LayerNorm launch covers both nets.  Both
+// weight sets are read from their packed copies.  logits4 [4][n][atoms].
+int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* tcp, const float* cpack,
+                        const float* tpack, const Layout& L, const float* feat, long long ld_feat, long long sz_feat,
+                        const float* s, long long ld_s, long long sz_s, const float* a, const float* ta,
+                        long long ld_a, int n, float* logits4, const CriticBufs& c, hipStream_t st) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj, N = d.atoms, cld = net.cpad;
+  const long long c0 = L.critic_begin;
+  const long long tw = L.q[1].l1.W - L.q[0].l1.W;
+  const long long twW = L.q[1].l1.Wp - L.q[0].l1.Wp;
+  const long long nH = (long long)n * H;
+  const Dense& T = L.ctrunk;
+  const Twin& q = L.q[0];
+  {
+    MatArg A{feat, ld_feat, 1, sz_feat};
+    MatArg Bm{cpack + T.Wp, T.ldp, 1, 0, tpack + T.Wp, 1};
+    OutArg C{c.pre, P, (long long)n * P, cp + (T.b - c0), 0, 0, 0, tcp + (T.b - c0), 1};
+    SQ_TRY(gemm(bf16, n, P, net.flat, 2, A, Bm, C, nullptr, 0, st));
+    const LnGroups grp{1, tcp + (T.g - c0), tcp + (T.beta - c0), sz_s, ta};
+    SQ_TRY(ln_act_fwd(c.pre, P, (long long)n * P, n, P, 2, cp + (T.g - c0), cp + (T.beta - c0), 0, 1, c.X1, cld,
+                      (long long)n * cld, c.t.xhat, c.t.rstd, s, ld_s, d.proprio, a, ld_a, d.action, st, &grp));
+  }
+  auto layer = [&](const Dense& D, const float* X, long long ldx, long long szx, int zdiv, int in, float* Y) -> int {
+    MatArg A{X, ldx, 1, szx, nullptr, kNoAlt, zdiv};
+    MatArg Bm{cpack + D.Wp, D.ldp, 1, twW, tpack + D.Wp, 2};
+    OutArg C{c.pre, H, nH, cp + (D.b - c0), tw, 0, 0, tcp + (D.b - c0), 2};
+    SQ_TRY(gemm(bf16, n, H, in, 4, A, Bm, C, nullptr, 0, st));
+    const LnGroups grp{2, tcp + (D.g - c0), tcp + (D.beta - c0), 0, nullptr};
+    const DenseSave& ln = &D == &q.l1 ? c.l1 : c.l2;
+    return ln_act_fwd(c.pre, H, nH, n, H, 4, cp + (D.g - c0), cp + (D.beta - c0), tw, 0, Y, H, nH, ln.xhat, ln.rstd,
+                      nullptr, 0, 0, nullptr, 0, 0, st, &grp);
+  };
+  SQ_TRY(layer(q.l1, c.X1, cld, (long long)n * cld, 2, net.cin_critic, c.g1));
+  SQ_TRY(layer(q.l2, c.g1, H, nH, 1, H, c.g2));
+  MatArg A{c.g2, H, 1, nH};
+  MatArg Bm{cpack + q.out.Wp, q.out.ldp, 1, twW, tpack + q.out.Wp, 2};
+  OutArg C{logits4, N, (long long)n * N, cp + (q.out.b - c0), tw, 0, 0, tcp + (q.out.b - c0), 2};
+  return gemm(bf16, n, N, H, 4, A, Bm, C, nullptr, 0, st);
 }
 
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,

@@ -36,9 +36,14 @@ struct CriticBufs {
   float* part_t; float* part_l1; float* part_l2; float* part_out;
   float* split;
 };
-void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd);
+// nets = 2 also sizes the forward buffers for critic_forward_pair (online, then target)
+void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd, int nets = 1);
 // cp: base of a critic block (online params + critic_begin, or the target vector);
 // cpack: the matching packed weights (nullable: weights are read from cp)
+int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* tcp, const float* cpack,
+                        const float* tpack, const Layout& L, const float* feat, long long ld_feat, long long sz_feat,
+                        const float* s, long long ld_s, long long sz_s, const float* a, const float* ta,
+                        long long ld_a, int n, float* logits4, const CriticBufs& c, hipStream_t st);
 int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                    long long ld_feat, const float* s, long long ld_s, const float* a, long long ld_a, int n,
                    float* logits, const CriticBufs& c, hipStream_t st);
