@@ -124,9 +124,12 @@ int act_noise_rows(unsigned long long seed, const unsigned long long* ids, const
 // p[zi*sz + r*lr + k*lk] for zi < zalt, else alt[(zi - zalt)*sz + r*lr + k*lk]
 // (two groups of batches in separate allocations, e.g. online and target nets).
 constexpr int kNoAlt = 1 << 30;
+// k >= kalt (a multiple of 32): element (r, k) read from kp as (r, k - kalt), with
+// the same strides -- a contraction over two blocks laid end to end along k.
 struct MatArg {
   const float* p; long long lr, lk, sz;
   const float* alt = nullptr; int zalt = kNoAlt; int zdiv = 1;
+  const float* kp = nullptr; int kalt = kNoAlt;
 };
 struct OutArg {            // C(r, c) at p[z*sz + r*ld + c]
   float* p; long long ld, sz;
@@ -140,6 +143,12 @@ struct OutArg {            // C(r, c) at p[z*sz + r*ld + c]
 // scratch (nullable) enables a deterministic split over K for small outputs.
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st);
+struct GemmProb {
+  int M, N, K, batch; MatArg A, B; OutArg C;
+};
+// two independent products; one launch when their operand kinds allow it
+int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, size_t scratch_floats,
+              hipStream_t st);
 // convolutions (3x3 valid, NCHW, W [F, Cin, 3, 3]) as implicit GEMMs
 int conv_fwd(int bf16, const float* x, int n, int Cin, int H, int stride, const float* W, const float* b,
              int F, float* out, hipStream_t st);

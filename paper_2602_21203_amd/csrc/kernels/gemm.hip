@@ -314,6 +314,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(FA fa, FB fb, ST st, StPart s
 struct RMat {
   const float* p; long long lr, lk, sz;
   const float* alt; int zalt, zdiv;   // batch groups, as MatArg
+  const float* kp; int kalt;          // k >= kalt read from kp at k - kalt, as MatArg
   __device__ __forceinline__ const float* batch(int z) const {
     const int zi = z / zdiv;
     return zi < zalt ? p + (long long)zi * sz : alt + (long long)(zi - zalt) * sz;
@@ -345,6 +346,11 @@ template <int V, bool FULL>
 __device__ __forceinline__ void rload(const RMat& m, float (&raw)[16], int z, int r0, int rows, int k0, int kend,
                                       int lane) {
   const float* base = m.batch(z);
+  if (k0 >= m.kalt) {   // uniform: kalt is a multiple of the chunk
+    base = m.kp + (long long)z * m.sz;
+    k0 -= m.kalt;
+    kend -= m.kalt;
+  }
   if constexpr (V) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -460,20 +466,26 @@ __device__ __forceinline__ void rmma(const RFrag<BF16>& a, const RFrag<BF16>& b,
   }
 }
 
+template <bool BF16, int AV, int BV>
+constexpr int gemm_lds_bytes() {
+  using LL = RLds<BF16>;
+  constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
+  constexpr int TILE_BYTES = (AV || BV) ? 4 * LL::WAVE * (int)sizeof(typename LL::T) : 0;
+  return TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
+}
+
+// one 32 x 32 output tile (bx, by) of batch / split index bz
 template <bool BF16, int AV, int BV, class ST, bool SPLIT>
-__global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, StPart sp, int M, int N, int K,
-                                                     int kchunk) {
+__device__ __forceinline__ void gemm_tile(const RMat& fa, const RMat& fb, const ST& st, const StPart& sp, int M,
+                                          int N, int K, int kchunk, int bx, int by, int bz, char* lds) {
   using LL = RLds<BF16>;
   using T = typename LL::T;
   constexpr int KC = kRKC, G = kRG;
   constexpr int RLD = kTile + 1;
-  constexpr int RED_BYTES = 4 * kTile * RLD * 4;
-  constexpr int TILE_BYTES = (AV || BV) ? 4 * LL::WAVE * (int)sizeof(T) : 0;
-  __shared__ __attribute__((aligned(16))) char lds[TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES];
 
-  const int z = blockIdx.z / (SPLIT ? sp.splits : 1);
-  const int split = SPLIT ? blockIdx.z % sp.splits : 0;
-  const int m0 = blockIdx.x * kTile, n0 = blockIdx.y * kTile;
+  const int z = bz / (SPLIT ? sp.splits : 1);
+  const int split = SPLIT ? bz % sp.splits : 0;
+  const int m0 = bx * kTile, n0 = by * kTile;
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63;
@@ -581,6 +593,36 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
   }
 }
 
+template <bool BF16, int AV, int BV, class ST, bool SPLIT>
+__global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, StPart sp, int M, int N, int K,
+                                                     int kchunk) {
+  __shared__ __attribute__((aligned(16))) char lds[gemm_lds_bytes<BF16, AV, BV>()];
+  gemm_tile<BF16, AV, BV, ST, SPLIT>(fa, fb, st, sp, M, N, K, kchunk, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+}
+
+// Two independent products in one launch (the input and weight gradients of one
+// layer): workgroups [0, tiles0) take problem 0 (row-coalesced A, k-strided B),
+// the rest problem 1 (both k-strided).
+struct RProb {
+  RMat a, b; StMat st; int M, N, K, gx, gy;
+};
+
+template <bool BF16>
+__global__ __launch_bounds__(kThreads) void k_gemm_pair(RProb p0, RProb p1, int tiles0) {
+  constexpr int L0 = gemm_lds_bytes<BF16, 1, 0>(), L1 = gemm_lds_bytes<BF16, 0, 0>();
+  __shared__ __attribute__((aligned(16))) char lds[L0 > L1 ? L0 : L1];
+  const StPart none{nullptr, 0, 0, 1};
+  int b = blockIdx.x;
+  if (b < tiles0) {
+    gemm_tile<BF16, 1, 0, StMat, false>(p0.a, p0.b, p0.st, none, p0.M, p0.N, p0.K, p0.K, b % p0.gx,
+                                        (b / p0.gx) % p0.gy, b / (p0.gx * p0.gy), lds);
+  } else {
+    b -= tiles0;
+    gemm_tile<BF16, 0, 0, StMat, false>(p1.a, p1.b, p1.st, none, p1.M, p1.N, p1.K, p1.K, b % p1.gx,
+                                        (b / p1.gx) % p1.gy, b / (p1.gx * p1.gy), lds);
+  }
+}
+
 // sum of split-K partials in split order, then the real store
 template <class ST>
 __global__ void k_split_reduce(StPart sp, ST st, int batch) {
@@ -636,26 +678,37 @@ static int run(int bf16, int M, int N, int K, int batch, FA fa, FB fb, ST st, fl
 // ---------------------------------------------------------------- public launchers
 // 1: k is the contiguous dimension of 16-byte aligned rows (vector loads), else 0
 static int rkind(const MatArg& a) {
-  return ((uintptr_t)a.p % 16 == 0 && (!a.alt || (uintptr_t)a.alt % 16 == 0) && a.sz % 4 == 0 && a.lk == 1 &&
-          a.lr % 4 == 0) ? 1 : 0;
+  return ((uintptr_t)a.p % 16 == 0 && (!a.alt || (uintptr_t)a.alt % 16 == 0) &&
+          (!a.kp || (uintptr_t)a.kp % 16 == 0) && a.sz % 4 == 0 && a.lk == 1 && a.lr % 4 == 0) ? 1 : 0;
 }
 
-template <bool BF16, int AV, int BV>
-static int run_r(int M, int N, int K, int batch, const MatArg& A, const MatArg& B, const StMat& out, float* scratch,
-                 size_t scratch_floats, hipStream_t st) {
+static RMat rmat(const MatArg& m) { return RMat{m.p, m.lr, m.lk, m.sz, m.alt, m.zalt, m.zdiv, m.kp, m.kalt}; }
+static StMat stmat(const OutArg& c) {
+  return StMat{c.p, c.ld, c.sz, c.bias, c.bias_sz, c.accumulate, c.relu, c.bias_alt, c.bias_zalt};
+}
+
+// the K split gemm() would choose (1: none)
+static int want_splits(int M, int N, int K, int batch, const float* scratch, size_t scratch_floats) {
   const int tiles = cdiv(M, kTile) * cdiv(N, kTile) * batch;
-  // few output tiles over a long contraction: split K across workgroups
   int splits = 1;
   if (scratch && tiles < 128 && K >= 2048) {
     splits = std::min(cdiv(256, tiles), K / 1024);
     while (splits > 1 && (size_t)splits * M * N * batch > scratch_floats) --splits;
   }
+  return splits;
+}
+
+template <bool BF16, int AV, int BV>
+static int run_r(int M, int N, int K, int batch, const MatArg& A, const MatArg& B, const StMat& out, float* scratch,
+                 size_t scratch_floats, hipStream_t st) {
+  // few output tiles over a long contraction: split K across workgroups
+  int splits = want_splits(M, N, K, batch, scratch, scratch_floats);
   int kchunk = K > 0 ? K : 1;
   if (splits > 1) {
     kchunk = cdiv(cdiv(K, splits), 4 * kRKC) * 4 * kRKC;
     splits = cdiv(K, kchunk);
   }
-  const RMat a{A.p, A.lr, A.lk, A.sz, A.alt, A.zalt, A.zdiv}, b{B.p, B.lr, B.lk, B.sz, B.alt, B.zalt, B.zdiv};
+  const RMat a = rmat(A), b = rmat(B);
   StPart sp{scratch, M, N, splits};
   dim3 grid(cdiv(M, kTile), cdiv(N, kTile), batch * splits);
   if (splits <= 1) {
@@ -672,7 +725,11 @@ static int run_r(int M, int N, int K, int batch, const MatArg& A, const MatArg& 
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return SQ_OK;
-  StMat out{C.p, C.ld, C.sz, C.bias, C.bias_sz, C.accumulate, C.relu, C.bias_alt, C.bias_zalt};
+  if ((A.kalt != kNoAlt && A.kalt % kRKC) || (B.kalt != kNoAlt && B.kalt % kRKC) || A.kalt != B.kalt) {
+    set_error("gemm: a k-split operand needs the same kalt on both sides, a multiple of %d", kRKC);
+    return SQ_EINVAL;
+  }
+  const StMat out = stmat(C);
   const int va = rkind(A), vb = rkind(B);
   if (bf16) {
     if (va && vb) return run_r<true, 1, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
@@ -684,6 +741,26 @@ int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C,
   if (va) return run_r<false, 1, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
   if (vb) return run_r<false, 0, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
   return run_r<false, 0, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
+}
+
+int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, size_t scratch_floats,
+              hipStream_t st) {
+  const bool e0 = p0.M <= 0 || p0.N <= 0 || p0.batch <= 0, e1 = p1.M <= 0 || p1.N <= 0 || p1.batch <= 0;
+  const bool kinds = rkind(p0.A) == 1 && rkind(p0.B) == 0 && rkind(p1.A) == 0 && rkind(p1.B) == 0;
+  const bool nosplit = want_splits(p0.M, p0.N, p0.K, p0.batch, scratch, scratch_floats) == 1 &&
+                       want_splits(p1.M, p1.N, p1.K, p1.batch, scratch, scratch_floats) == 1;
+  const bool kok = p0.A.kalt == p0.B.kalt && p1.A.kalt == p1.B.kalt &&
+                   (p0.A.kalt == kNoAlt || p0.A.kalt % kRKC == 0) && (p1.A.kalt == kNoAlt || p1.A.kalt % kRKC == 0);
+  if (e0 || e1 || !kinds || !nosplit || !kok) {
+    SQ_TRY(gemm(bf16, p0.M, p0.N, p0.K, p0.batch, p0.A, p0.B, p0.C, scratch, scratch_floats, st));
+    return gemm(bf16, p1.M, p1.N, p1.K, p1.batch, p1.A, p1.B, p1.C, scratch, scratch_floats, st);
+  }
+  RProb q0{rmat(p0.A), rmat(p0.B), stmat(p0.C), p0.M, p0.N, p0.K, cdiv(p0.M, kTile), cdiv(p0.N, kTile)};
+  RProb q1{rmat(p1.A), rmat(p1.B), stmat(p1.C), p1.M, p1.N, p1.K, cdiv(p1.M, kTile), cdiv(p1.N, kTile)};
+  const int t0 = q0.gx * q0.gy * p0.batch, t1 = q1.gx * q1.gy * p1.batch;
+  if (bf16) k_gemm_pair<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+  else k_gemm_pair<false><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+  return launch_status("gemm_pair");
 }
 
 template <class F>

@@ -49,6 +49,24 @@ static int linear_dx(int bf16, int n, int out, int cols, int batch, const float*
   return gemm(bf16, n, cols, out, batch, A, Bm, C, nullptr, 0, st);
 }
 
+// the same products as GemmProb values, for launching a layer's weight and input
+// gradients together
+static GemmProb prob_dw(int n, int out, int in, int batch, const float* dY, long long lddy, long long szdy,
+                        const float* X, long long ldx, long long szx, float* dW, long long ldw, long long szw) {
+  return GemmProb{out, in, n, batch, MatArg{dY, 1, lddy, szdy}, MatArg{X, 1, ldx, szx},
+                  OutArg{dW, ldw, szw, nullptr, 0, 0, 0}};
+}
+static GemmProb prob_dx(int n, int out, int cols, int batch, const float* dY, long long lddy, long long szdy,
+                        const float* W, long long ldw, long long szw, float* dX, long long lddx, long long szdx) {
+  return GemmProb{n, cols, out, batch, MatArg{dY, lddy, 1, szdy}, MatArg{W, 1, ldw, szw},
+                  OutArg{dX, lddx, szdx, nullptr, 0, 0, 0}};
+}
+// input gradient, and the weight gradient when dw is given, in one launch if possible
+static int grads(int bf16, const GemmProb& dx, const GemmProb* dw, float* split, hipStream_t st) {
+  if (dw) return gemm_pair(bf16, dx, *dw, split, split ? kSplitFloats : 0, st);
+  return gemm(bf16, dx.M, dx.N, dx.K, dx.batch, dx.A, dx.B, dx.C, nullptr, 0, st);
+}
+
 // ---------------------------------------------------------------- encoder
 void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
   const sq_dims& d = net.d;
@@ -256,48 +274,66 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
   const bool params = dcp != nullptr;
   const bool trunk = params || dfeat != nullptr;
   // output heads
-  if (params) {
-    SQ_TRY(linear_dw(bf16, n, N, H, 2, dlogits, N, nN, c.g2, H, nH, dcp + (q.out.W - c0), H, tw, c.split, st));
-    SQ_TRY(col_partials(dlogits, N, nN, n, N, 2, c.part_out, st));
+  if (params) SQ_TRY(col_partials(dlogits, N, nN, n, N, 2, c.part_out, st));
+  {
+    const GemmProb dx = prob_dx(n, N, H, 2, dlogits, N, nN, w.W(q.out.W, q.out.Wp), w.ld(q.out.in, q.out.ldp), twW,
+                                c.dA, H, nH);
+    const GemmProb dw = prob_dw(n, N, H, 2, dlogits, N, nN, c.g2, H, nH, dcp + (q.out.W - c0), H, tw);
+    SQ_TRY(grads(bf16, dx, params ? &dw : nullptr, c.split, st));
   }
-  SQ_TRY(linear_dx(bf16, n, N, H, 2, dlogits, N, nN, w.W(q.out.W, q.out.Wp), w.ld(q.out.in, q.out.ldp), twW, c.dA, H,
-                   nH, 0, st));
   // second hidden layer
   SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g2, H, nH, c.l2.xhat, c.l2.rstd, cp + (q.l2.g - c0), tw, n, H, 2, 0, c.dB,
                     params ? c.part_l2 : nullptr, st));
-  if (params)
-    SQ_TRY(linear_dw(bf16, n, H, H, 2, c.dB, H, nH, c.g1, H, nH, dcp + (q.l2.W - c0), H, tw, c.split, st));
-  SQ_TRY(linear_dx(bf16, n, H, H, 2, c.dB, H, nH, w.W(q.l2.W, q.l2.Wp), w.ld(q.l2.in, q.l2.ldp), twW, c.dA, H, nH, 0,
-                   st));
-  // first hidden layer
+  {
+    const GemmProb dx = prob_dx(n, H, H, 2, c.dB, H, nH, w.W(q.l2.W, q.l2.Wp), w.ld(q.l2.in, q.l2.ldp), twW, c.dA,
+                                H, nH);
+    const GemmProb dw = prob_dw(n, H, H, 2, c.dB, H, nH, c.g1, H, nH, dcp + (q.l2.W - c0), H, tw);
+    SQ_TRY(grads(bf16, dx, params ? &dw : nullptr, c.split, st));
+  }
+  // first hidden layer; the shared input [h | s | a] collects the gradient of both
+  // twins as one contraction over k = (twin, hidden unit)
   SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g1, H, nH, c.l1.xhat, c.l1.rstd, cp + (q.l1.g - c0), tw, n, H, 2, 0, c.dB,
                     params ? c.part_l1 : nullptr, st));
-  if (params)
-    SQ_TRY(linear_dw(bf16, n, H, cin, 2, c.dB, H, nH, c.X1, cld, 0, dcp + (q.l1.W - c0), cin, tw, c.split, st));
   const float* W1a = w.W(L.q[0].l1.W, L.q[0].l1.Wp);
   const float* W1b = w.W(L.q[1].l1.W, L.q[1].l1.Wp);
   const long long ld1 = w.ld(q.l1.in, q.l1.ldp);
-  if (trunk) {
-    // the shared input [h | s | a] collects the gradient of both twins
-    SQ_TRY(linear_dx(bf16, n, H, cin, 1, c.dB, H, 0, W1a, ld1, 0, c.dX1, cld, 0, 0, st));
-    SQ_TRY(linear_dx(bf16, n, H, cin, 1, c.dB + nH, H, 0, W1b, ld1, 0, c.dX1, cld, 0, 1, st));
-    if (daction)
+  const GemmProb dw1 = prob_dw(n, H, cin, 2, c.dB, H, nH, c.X1, cld, 0, dcp + (q.l1.W - c0), cin, tw);
+  if (trunk || daction) {
+    const int c0col = trunk ? 0 : P + d.proprio;   // without the trunk only the action columns are wanted
+    GemmProb dx = prob_dx(n, H, trunk ? cin : A, 1, c.dB, H, 0, W1a + c0col, ld1, 0, trunk ? c.dX1 : daction,
+                          trunk ? cld : A, 0);
+    if (H % 32 == 0) {
+      dx.K = 2 * H;
+      dx.A.kp = c.dB + nH;
+      dx.A.kalt = H;
+      dx.B.kp = W1b + c0col;
+      dx.B.kalt = H;
+      SQ_TRY(grads(bf16, dx, params ? &dw1 : nullptr, c.split, st));
+    } else {   // twin by twin, the second accumulating
+      SQ_TRY(grads(bf16, dx, params ? &dw1 : nullptr, c.split, st));
+      GemmProb dxb = dx;
+      dxb.A.p = c.dB + nH;
+      dxb.B.p = W1b + c0col;
+      dxb.C.accumulate = 1;
+      SQ_TRY(grads(bf16, dxb, nullptr, c.split, st));
+    }
+    if (trunk && daction)
       SQ_TRY_HIP(hipMemcpy2DAsync(daction, (size_t)A * 4, c.dX1 + P + d.proprio, (size_t)cld * 4, (size_t)A * 4, n,
                                   hipMemcpyDeviceToDevice, st));
-  } else if (daction) {
-    const int a0 = P + d.proprio;
-    SQ_TRY(linear_dx(bf16, n, H, A, 1, c.dB, H, 0, W1a + a0, ld1, 0, daction, A, 0, 0, st));
-    SQ_TRY(linear_dx(bf16, n, H, A, 1, c.dB + nH, H, 0, W1b + a0, ld1, 0, daction, A, 0, 1, st));
+  } else if (params) {
+    SQ_TRY(gemm(bf16, dw1.M, dw1.N, dw1.K, dw1.batch, dw1.A, dw1.B, dw1.C, c.split, kSplitFloats, st));
   }
   if (trunk) {
     SQ_TRY(ln_act_bwd(c.dX1, cld, 0, c.X1, cld, 0, c.t.xhat, c.t.rstd, cp + (T.g - c0), 0, n, P, 1, 1, c.dA,
                       params ? c.part_t : nullptr, st));
-    if (params)
-      SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, c.dA, P, 0, feat, ld_feat, 0, dcp + (T.W - c0), net.flat, 0, c.split,
-                       st));
-    if (dfeat)
-      SQ_TRY(linear_dx(bf16, n, P, net.flat, 1, c.dA, P, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0, dfeat, net.flat, 0,
-                       0, st));
+    const GemmProb dw = prob_dw(n, P, net.flat, 1, c.dA, P, 0, feat, ld_feat, 0, dcp + (T.W - c0), net.flat, 0);
+    if (dfeat) {
+      const GemmProb dx = prob_dx(n, P, net.flat, 1, c.dA, P, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0, dfeat,
+                                  net.flat, 0);
+      SQ_TRY(grads(bf16, dx, params ? &dw : nullptr, c.split, st));
+    } else if (params) {
+      SQ_TRY(gemm(bf16, dw.M, dw.N, dw.K, dw.batch, dw.A, dw.B, dw.C, c.split, kSplitFloats, st));
+    }
   }
   if (params) {
     const int pr = ln_bwd_partial_rows(n);
@@ -380,21 +416,30 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
   const WRef w{ap, pack, a0};
   const Dense& T = L.atrunk;
   SQ_TRY(tanh_gauss_bwd(a.save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, n, A, a.dhead, st));
-  SQ_TRY(linear_dw(bf16, n, 2 * A, H, 1, a.dhead, 2 * A, 0, a.g2, H, 0, dap + (L.aout.W - a0), H, 0, a.split, st));
   SQ_TRY(col_partials(a.dhead, 2 * A, 0, n, 2 * A, 1, a.part_out, st));
-  SQ_TRY(linear_dx(bf16, n, 2 * A, H, 1, a.dhead, 2 * A, 0, w.W(L.aout.W, L.aout.Wp), w.ld(L.aout.in, L.aout.ldp), 0,
-                   a.dA, H, 0, 0, st));
+  {
+    const GemmProb dx = prob_dx(n, 2 * A, H, 1, a.dhead, 2 * A, 0, w.W(L.aout.W, L.aout.Wp),
+                                w.ld(L.aout.in, L.aout.ldp), 0, a.dA, H, 0);
+    const GemmProb dw = prob_dw(n, 2 * A, H, 1, a.dhead, 2 * A, 0, a.g2, H, 0, dap + (L.aout.W - a0), H, 0);
+    SQ_TRY(grads(bf16, dx, &dw, a.split, st));
+  }
   SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g2, H, 0, a.l2.xhat, a.l2.rstd, ap + (L.al2.g - a0), 0, n, H, 1, 0, a.dB, a.part_l2,
                     st));
-  SQ_TRY(linear_dw(bf16, n, H, H, 1, a.dB, H, 0, a.g1, H, 0, dap + (L.al2.W - a0), H, 0, a.split, st));
-  SQ_TRY(linear_dx(bf16, n, H, H, 1, a.dB, H, 0, w.W(L.al2.W, L.al2.Wp), w.ld(L.al2.in, L.al2.ldp), 0, a.dA, H, 0, 0,
-                   st));
+  {
+    const GemmProb dx = prob_dx(n, H, H, 1, a.dB, H, 0, w.W(L.al2.W, L.al2.Wp), w.ld(L.al2.in, L.al2.ldp), 0, a.dA,
+                                H, 0);
+    const GemmProb dw = prob_dw(n, H, H, 1, a.dB, H, 0, a.g1, H, 0, dap + (L.al2.W - a0), H, 0);
+    SQ_TRY(grads(bf16, dx, &dw, a.split, st));
+  }
   SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g1, H, 0, a.l1.xhat, a.l1.rstd, ap + (L.al1.g - a0), 0, n, H, 1, 0, a.dB, a.part_l1,
                     st));
-  SQ_TRY(linear_dw(bf16, n, H, cin, 1, a.dB, H, 0, a.X1, ald, 0, dap + (L.al1.W - a0), cin, 0, a.split, st));
-  // only the projection columns of the actor input need a gradient
-  SQ_TRY(linear_dx(bf16, n, H, P, 1, a.dB, H, 0, w.W(L.al1.W, L.al1.Wp), w.ld(L.al1.in, L.al1.ldp), 0, a.dX1, P, 0, 0,
-                   st));
+  {
+    // only the projection columns of the actor input need a gradient
+    const GemmProb dx = prob_dx(n, H, P, 1, a.dB, H, 0, w.W(L.al1.W, L.al1.Wp), w.ld(L.al1.in, L.al1.ldp), 0,
+                                a.dX1, P, 0);
+    const GemmProb dw = prob_dw(n, H, cin, 1, a.dB, H, 0, a.X1, ald, 0, dap + (L.al1.W - a0), cin, 0);
+    SQ_TRY(grads(bf16, dx, &dw, a.split, st));
+  }
   SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, ald, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), 0, n, P, 1, 1, a.dA, a.part_t,
                     st));
   SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, a.dA, P, 0, feat, ld_feat, 0, dap + (T.W - a0), net.flat, 0, a.split, st));
