@@ -153,9 +153,10 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   SQ_TRY(project_target(g->logits_t, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma,
                         g->mt, g->tgt_row, st));
   // critic + encoder step
-  SQ_TRY(ce_loss(g->logits, g->mt, B, N, d.v_min, d.v_max, g->dlogits, g->loss_row, g->q_row, st));
+  SQ_TRY(ce_loss(g->logits, g->mt, B, N, d.v_min, d.v_max, g->dlogits, g->loss_row, g->q_row, g->crit.part_out,
+                 st));
   SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
-                         g->dfeat, nullptr, st));
+                         g->dfeat, nullptr, st, true));
   SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true));
   SQ_TRY(adam(P, G, g->m, g->v, L.critic_end, &hp, g->ctr + CTR_TC, g->target, L.critic_begin, nullptr, &g->pk_critic,
               st));

@@ -205,8 +205,11 @@ int colsum(ColSegs segs, hipStream_t st);
 
 int tanh_gauss_fwd(const float* head, int rows, int A, const float* eps, float lo, float hi, float* action,
                    float* logp, float* save, hipStream_t st);
+// part (nullable): column sums of dhead per block of tanh_gauss_partial_rows rows
+int tanh_gauss_partial_rows(int rows);
 int tanh_gauss_bwd(const float* save, const float* eps, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, int rows, int A, float* dhead,
+                   float* part,
                    hipStream_t st);
 int mean_action(const float* head, int rows, int A, float* action, hipStream_t st);
 
@@ -216,7 +219,7 @@ int project_target(const float* logits2, int B, int N, float v_min, float v_max,
 int c51_project_raw(const float* p, const float* reward, const uint8_t* done, const float* bonus,
                     float gamma, int B, int N, float v_min, float v_max, float* m, hipStream_t st);
 int ce_loss(const float* logits2, const float* m, int B, int N, float v_min, float v_max,
-            float* dlogits2, float* loss_row, float* q_row, hipStream_t st);
+            float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st);
 int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max, float* dlogits2,
                     float* qa_row, hipStream_t st);
 // scal: [0] alpha before, [1] alpha after, [2] alpha loss, [3] mean(-log pi)

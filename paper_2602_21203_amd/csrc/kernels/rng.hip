@@ -8,43 +8,57 @@
 
 namespace sq {
 
-// One thread per batch row: index draw, gather of the small replay fields and the
-// 2 x A noise values of that row.  eps2B rows [0, B) = stream 2, rows [B, 2B) = stream 1.
-__global__ void k_sample_batch(unsigned k0, unsigned k1, const int* __restrict__ ctr, int size, int B,
-                               int A, int S, const float* __restrict__ proprio,
-                               const float* __restrict__ next_proprio, const float* __restrict__ action,
-                               const float* __restrict__ reward, const uint8_t* __restrict__ done,
-                               int* __restrict__ idx, float* __restrict__ eps2B, float* __restrict__ S2,
-                               float* __restrict__ Arep, float* __restrict__ r, float* __restrict__ d) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+// One thread per (row, item): every thread redraws its row's index (one Philox
+// block) and moves one item -- a proprio value of s or s', an action value, one
+// of the row's 2 x A noise values, the reward or the done flag -- so the launch
+// is as wide as the batch's fields.  eps2B rows [0, B) = stream 2, rows [B, 2B) =
+// stream 1.
+__global__ __launch_bounds__(256) void k_sample_batch(unsigned k0, unsigned k1, const int* __restrict__ ctr,
+                                                      int size, int B, int A, int S,
+                                                      const float* __restrict__ proprio,
+                                                      const float* __restrict__ next_proprio,
+                                                      const float* __restrict__ action,
+                                                      const float* __restrict__ reward,
+                                                      const uint8_t* __restrict__ done, int* __restrict__ idx,
+                                                      float* __restrict__ eps2B, float* __restrict__ S2,
+                                                      float* __restrict__ Arep, float* __restrict__ r,
+                                                      float* __restrict__ d) {
+  const int W = 2 * S + 3 * A + 2;   // items per row
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)B * W) return;
+  const int b = (int)(t / W), it = (int)(t - (long long)b * W);
   const unsigned u = (unsigned)ctr[CTR_U];
+  if (it < 3 * A + 2 && it >= A && it < 3 * A) {   // noise: no replay access
+    const int j = (it - A) % A;
+    const unsigned s = it < 2 * A ? 2u : 1u;
+    const P4 g = philox10(P4{u, s, (unsigned)(b * A + j), 0u}, k0, k1);
+    eps2B[(long long)(s == 2u ? b : B + b) * A + j] = box_muller(g.x, g.y);
+    return;
+  }
   const P4 w = philox10(P4{u, 0u, (unsigned)b, 0u}, k0, k1);
   const int row = (int)__umulhi(w.x, (unsigned)size);
-  idx[b] = row;
-  for (int j = 0; j < S; ++j) {
-    S2[(long long)b * S + j] = proprio[(long long)row * S + j];
-    S2[(long long)(B + b) * S + j] = next_proprio[(long long)row * S + j];
+  if (it < A) {
+    Arep[(long long)b * A + it] = action[(long long)row * A + it];
+  } else if (it == 3 * A) {
+    r[b] = reward[row];
+    idx[b] = row;
+  } else if (it == 3 * A + 1) {
+    d[b] = done[row] ? 1.0f : 0.0f;
+  } else {
+    const int j = it - (3 * A + 2);
+    if (j < S) S2[(long long)b * S + j] = proprio[(long long)row * S + j];
+    else S2[(long long)(B + b) * S + (j - S)] = next_proprio[(long long)row * S + (j - S)];
   }
-  for (int j = 0; j < A; ++j) {
-    Arep[(long long)b * A + j] = action[(long long)row * A + j];
-    const unsigned e = (unsigned)(b * A + j);
-    const P4 g2 = philox10(P4{u, 2u, e, 0u}, k0, k1);
-    const P4 g1 = philox10(P4{u, 1u, e, 0u}, k0, k1);
-    eps2B[(long long)b * A + j] = box_muller(g2.x, g2.y);
-    eps2B[(long long)(B + b) * A + j] = box_muller(g1.x, g1.y);
-  }
-  r[b] = reward[row];
-  d[b] = done[row] ? 1.0f : 0.0f;
 }
 
 int launch_sample_batch(unsigned long long seed, const int* ctr, int size, int B, int A, int S,
                         const float* proprio, const float* next_proprio, const float* action,
                         const float* reward, const uint8_t* done, int* idx, float* eps2B, float* S2,
                         float* Arep, float* r, float* d, hipStream_t st) {
-  k_sample_batch<<<cdiv(B, 64), 64, 0, st>>>((unsigned)seed, (unsigned)(seed >> 32), ctr, size, B, A, S,
-                                             proprio, next_proprio, action, reward, done, idx, eps2B, S2,
-                                             Arep, r, d);
+  const long long items = (long long)B * (2 * S + 3 * A + 2);
+  k_sample_batch<<<(unsigned)((items + 255) / 256), 256, 0, st>>>((unsigned)seed, (unsigned)(seed >> 32), ctr, size,
+                                                                  B, A, S, proprio, next_proprio, action, reward,
+                                                                  done, idx, eps2B, S2, Arep, r, d);
   return launch_status("sample_batch");
 }
 

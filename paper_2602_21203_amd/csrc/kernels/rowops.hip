@@ -361,34 +361,58 @@ int tanh_gauss_fwd(const float* head, int rows, int A, const float* eps, float l
 
 // d log pi / du = 2 tanh(u); d log pi / d log sigma = -1 (direct term).
 // dlogp per row = (dlogp_vec ? dlogp_vec[r] : 0) + (dlogp_scalar ? *dlogp_scalar * scale : 0)
-__global__ void k_tg_bwd(const float* __restrict__ save, const float* __restrict__ eps,
-                         const float* __restrict__ da, long long ld_da, const float* __restrict__ dlogp_vec,
-                         const float* __restrict__ dlogp_scalar, float scale, float lo, float hi, int rows, int A,
-                         float* __restrict__ dhead) {
+// One row per thread, kTgRows rows per workgroup; with part, the workgroup also
+// writes the column sums of its rows of dhead (in row order) to part[blk][2A].
+constexpr int kTgRows = 64;
+__global__ __launch_bounds__(kTgRows) void k_tg_bwd(const float* __restrict__ save, const float* __restrict__ eps,
+                                                    const float* __restrict__ da, long long ld_da,
+                                                    const float* __restrict__ dlogp_vec,
+                                                    const float* __restrict__ dlogp_scalar, float scale, float lo,
+                                                    float hi, int rows, int A, float* __restrict__ dhead,
+                                                    float* __restrict__ part) {
+  extern __shared__ float sht[];   // [kTgRows][2A] when part is wanted
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
+  const bool live = r < rows;
   float dl = 0.f;
-  if (dlogp_vec) dl += dlogp_vec[r];
-  if (dlogp_scalar) dl += *dlogp_scalar * scale;
+  if (live && dlogp_vec) dl += dlogp_vec[r];
+  if (live && dlogp_scalar) dl += *dlogp_scalar * scale;
   for (int d = 0; d < A; ++d) {
-    const float tus = save[(long long)r * 3 * A + d];
-    const float sd = save[(long long)r * 3 * A + A + d];
-    const float a = save[(long long)r * 3 * A + 2 * A + d];
-    const float e = eps[(long long)r * A + d];
-    const float dav = da ? da[r * ld_da + d] : 0.f;
-    const float du = dav * (1.f - a * a) + dl * 2.f * a;
-    const float dls = du * sd * e - dl;
-    dhead[(long long)r * 2 * A + d] = du;
-    dhead[(long long)r * 2 * A + A + d] = dls * 0.5f * (hi - lo) * (1.f - tus * tus);
+    float du = 0.f, dls_out = 0.f;
+    if (live) {
+      const float tus = save[(long long)r * 3 * A + d];
+      const float sd = save[(long long)r * 3 * A + A + d];
+      const float a = save[(long long)r * 3 * A + 2 * A + d];
+      const float e = eps[(long long)r * A + d];
+      const float dav = da ? da[r * ld_da + d] : 0.f;
+      du = dav * (1.f - a * a) + dl * 2.f * a;
+      const float dls = du * sd * e - dl;
+      dls_out = dls * 0.5f * (hi - lo) * (1.f - tus * tus);
+      dhead[(long long)r * 2 * A + d] = du;
+      dhead[(long long)r * 2 * A + A + d] = dls_out;
+    }
+    if (part) {
+      sht[threadIdx.x * 2 * A + d] = du;
+      sht[threadIdx.x * 2 * A + A + d] = dls_out;
+    }
+  }
+  if (!part) return;
+  __syncthreads();
+  for (int j = threadIdx.x; j < 2 * A; j += blockDim.x) {
+    float sum = 0.f;
+    for (int t = 0; t < (int)blockDim.x; ++t) sum += sht[t * 2 * A + j];
+    part[(long long)blockIdx.x * 2 * A + j] = sum;
   }
 }
 
+int tanh_gauss_partial_rows(int rows) { return cdiv(rows, kTgRows); }
+
 int tanh_gauss_bwd(const float* save, const float* eps, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, int rows, int A, float* dhead,
-                   hipStream_t st) {
+                   float* part, hipStream_t st) {
   if (rows <= 0) return SQ_OK;
-  k_tg_bwd<<<cdiv(rows, 64), 64, 0, st>>>(save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, rows, A,
-                                          dhead);
+  const size_t lds = part ? (size_t)kTgRows * 2 * A * sizeof(float) : 0;
+  k_tg_bwd<<<cdiv(rows, kTgRows), kTgRows, lds, st>>>(save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi,
+                                                     rows, A, dhead, part);
   return launch_status("tanh_gauss_bwd");
 }
 
@@ -531,58 +555,88 @@ int c51_project_raw(const float* p, const float* reward, const uint8_t* done, co
 }
 
 // cross entropy of both twins to m: loss_row[i][b] = -sum_j m_j log softmax_j;
-// dlogits = (softmax - m) / B; q_row[i][b] = sum_j softmax_j z_j
-__global__ __launch_bounds__(256) void k_ce(const float* __restrict__ logits2, const float* __restrict__ m, int B,
-                                            int N, float v_min, float v_max, float* __restrict__ dlogits2,
-                                            float* __restrict__ loss_row, float* __restrict__ q_row) {
+// dlogits = (softmax - m) / B; q_row[i][b] = sum_j softmax_j z_j.  One row per
+// wave, kLnRowsPerBlock rows per workgroup; with part, the workgroup also writes
+// the column sums of its rows' dlogits (summed over its waves in order) to
+// part[i][blk][N], the output-head bias partials in the LayerNorm-backward blocking.
+__global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_ce(const float* __restrict__ logits2,
+                                                            const float* __restrict__ m, int B, int N, float v_min,
+                                                            float v_max, float* __restrict__ dlogits2,
+                                                            float* __restrict__ loss_row, float* __restrict__ q_row,
+                                                            float* __restrict__ part) {
+  extern __shared__ float shc[];   // [2][kLnRowsPerBlock][N] when part is wanted
+  constexpr int R = kLnRowsPerBlock;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int b = blockIdx.x * 4 + wave;
-  if (b >= B) return;
+  const int b = blockIdx.x * R + wave;
   const float dz = (v_max - v_min) / (float)(N - 1);
   const float invB = 1.0f / (float)B;
   for (int i = 0; i < 2; ++i) {
-    const float* l = logits2 + ((long long)i * B + b) * N;
-    float mx = -INFINITY;
+    float dl[kMaxAtomsPerLane];
 #pragma unroll
-    for (int t = 0; t < kMaxAtomsPerLane; ++t) {
-      const int j = lane + 64 * t;
-      if (j < N) mx = fmaxf(mx, l[j]);
-    }
-    mx = wave_max(mx);
-    float e[kMaxAtomsPerLane], s = 0.f;
+    for (int t = 0; t < kMaxAtomsPerLane; ++t) dl[t] = 0.f;
+    if (b < B) {
+      const float* l = logits2 + ((long long)i * B + b) * N;
+      float mx = -INFINITY;
 #pragma unroll
-    for (int t = 0; t < kMaxAtomsPerLane; ++t) {
-      const int j = lane + 64 * t;
-      e[t] = j < N ? expf(l[j] - mx) : 0.f;
-      s += e[t];
-    }
-    s = wave_sum(s);
-    const float lse = logf(s);
-    float ce = 0.f, q = 0.f;
+      for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+        const int j = lane + 64 * t;
+        if (j < N) mx = fmaxf(mx, l[j]);
+      }
+      mx = wave_max(mx);
+      float e[kMaxAtomsPerLane], s = 0.f;
 #pragma unroll
-    for (int t = 0; t < kMaxAtomsPerLane; ++t) {
-      const int j = lane + 64 * t;
-      if (j < N) {
-        const float mj = m[(long long)b * N + j];
-        const float pj = e[t] / s;
-        ce -= mj * (l[j] - mx - lse);
-        q += pj * (v_min + (float)j * dz);
-        dlogits2[((long long)i * B + b) * N + j] = (pj - mj) * invB;
+      for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+        const int j = lane + 64 * t;
+        e[t] = j < N ? expf(l[j] - mx) : 0.f;
+        s += e[t];
+      }
+      s = wave_sum(s);
+      const float lse = logf(s);
+      float ce = 0.f, q = 0.f;
+#pragma unroll
+      for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+        const int j = lane + 64 * t;
+        if (j < N) {
+          const float mj = m[(long long)b * N + j];
+          const float pj = e[t] / s;
+          ce -= mj * (l[j] - mx - lse);
+          q += pj * (v_min + (float)j * dz);
+          dl[t] = (pj - mj) * invB;
+          dlogits2[((long long)i * B + b) * N + j] = dl[t];
+        }
+      }
+      ce = wave_sum(ce);
+      q = wave_sum(q);
+      if (lane == 0) {
+        loss_row[(long long)i * B + b] = ce;
+        q_row[(long long)i * B + b] = q;
       }
     }
-    ce = wave_sum(ce);
-    q = wave_sum(q);
-    if (lane == 0) {
-      loss_row[(long long)i * B + b] = ce;
-      q_row[(long long)i * B + b] = q;
+    if (part) {
+#pragma unroll
+      for (int t = 0; t < kMaxAtomsPerLane; ++t) {
+        const int j = lane + 64 * t;
+        if (j < N) shc[(i * R + wave) * N + j] = dl[t];
+      }
     }
+  }
+  if (!part) return;
+  __syncthreads();
+  const int nblk = gridDim.x;
+  for (int e = threadIdx.x; e < 2 * N; e += 64 * R) {
+    const int i = e / N, j = e - i * N;
+    float sum = shc[(i * R) * N + j];
+    for (int w = 1; w < R; ++w) sum += shc[(i * R + w) * N + j];
+    part[((long long)i * nblk + blockIdx.x) * N + j] = sum;
   }
 }
 
 int ce_loss(const float* logits2, const float* m, int B, int N, float v_min, float v_max, float* dlogits2,
-            float* loss_row, float* q_row, hipStream_t st) {
+            float* loss_row, float* q_row, float* part, hipStream_t st) {
   if (B <= 0) return SQ_OK;
-  k_ce<<<cdiv(B, 4), 256, 0, st>>>(logits2, m, B, N, v_min, v_max, dlogits2, loss_row, q_row);
+  const size_t lds = part ? (size_t)2 * kLnRowsPerBlock * N * sizeof(float) : 0;
+  k_ce<<<cdiv(B, kLnRowsPerBlock), 64 * kLnRowsPerBlock, lds, st>>>(logits2, m, B, N, v_min, v_max, dlogits2,
+                                                                      loss_row, q_row, part);
   return launch_status("ce_loss");
 }
 

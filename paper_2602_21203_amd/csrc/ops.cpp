@@ -261,7 +261,8 @@ int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* 
 
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                     long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
-                    float* daction, hipStream_t st) {
+                    float* daction, hipStream_t st,
+                    bool out_partials_done) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic, cld = net.cpad, A = d.action;
   const long long c0 = L.critic_begin;
@@ -274,7 +275,7 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
   const bool params = dcp != nullptr;
   const bool trunk = params || dfeat != nullptr;
   // output heads
-  if (params) SQ_TRY(col_partials(dlogits, N, nN, n, N, 2, c.part_out, st));
+  if (params && !out_partials_done) SQ_TRY(col_partials(dlogits, N, nN, n, N, 2, c.part_out, st));
   {
     const GemmProb dx = prob_dx(n, N, H, 2, dlogits, N, nN, w.W(q.out.W, q.out.Wp), w.ld(q.out.in, q.out.ldp), twW,
                                 c.dA, H, nH);
@@ -415,8 +416,8 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
   const long long a0 = L.actor_begin;
   const WRef w{ap, pack, a0};
   const Dense& T = L.atrunk;
-  SQ_TRY(tanh_gauss_bwd(a.save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, n, A, a.dhead, st));
-  SQ_TRY(col_partials(a.dhead, 2 * A, 0, n, 2 * A, 1, a.part_out, st));
+  SQ_TRY(tanh_gauss_bwd(a.save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, n, A, a.dhead, a.part_out,
+                        st));
   {
     const GemmProb dx = prob_dx(n, 2 * A, H, 1, a.dhead, 2 * A, 0, w.W(L.aout.W, L.aout.Wp),
                                 w.ld(L.aout.in, L.aout.ldp), 0, a.dA, H, 0);
@@ -446,7 +447,8 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
   const int pr = ln_bwd_partial_rows(n);
   ColSegs sg{};
   sg.n = 4;
-  sg.s[0] = ColSeg{a.part_out, pr, 2 * A, 1, 1, {dap + (L.aout.b - a0), nullptr, nullptr}, 0, 0};
+  sg.s[0] = ColSeg{a.part_out, tanh_gauss_partial_rows(n), 2 * A, 1, 1, {dap + (L.aout.b - a0), nullptr, nullptr},
+                   0, 0};
   sg.s[1] = ColSeg{a.part_l2, pr, H, 3, 1, {dap + (L.al2.b - a0), dap + (L.al2.g - a0), dap + (L.al2.beta - a0)}, 0, 0};
   sg.s[2] = ColSeg{a.part_l1, pr, H, 3, 1, {dap + (L.al1.b - a0), dap + (L.al1.g - a0), dap + (L.al1.beta - a0)}, 0, 0};
   sg.s[3] = ColSeg{a.part_t, pr, P, 3, 1, {dap + (T.b - a0), dap + (T.g - a0), dap + (T.beta - a0)}, 0, 0};

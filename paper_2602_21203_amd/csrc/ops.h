@@ -48,9 +48,11 @@ int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack
                    long long ld_feat, const float* s, long long ld_s, const float* a, long long ld_a, int n,
                    float* logits, const CriticBufs& c, hipStream_t st);
 // dcp / dfeat / daction nullable; dcp is laid out like the critic block
+// out_partials_done: the output-head bias partials of dlogits are already in c.part_out (ce_loss)
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                     long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
-                    float* daction, hipStream_t st);
+                    float* daction, hipStream_t st,
+                    bool out_partials_done = false);
 
 struct ActorBufs {
   float* pre;          // [n][max(proj, hidden)]
