@@ -85,6 +85,7 @@ struct sq_agent {
   ActBufs actw;
   std::vector<GraphEntry> graphs;
   PackArgs pk_critic, pk_actor;   // pack refresh tables of the two Adam launches
+  GradSegs gs_critic, gs_actor;   // bias / gain / shift gradients the Adam launches sum from partials
 };
 
 static size_t plan_agent(sq_agent* g, char* base) {
@@ -156,13 +157,14 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   SQ_TRY(ce_loss(g->logits, g->mt, B, N, d.v_min, d.v_max, g->dlogits, g->loss_row, g->q_row, g->crit.part_out,
                  st));
   SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
-                         g->dfeat, nullptr, st, true));
+                         g->dfeat, nullptr, st, true, true));
   SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true));
+  // critic + encoder Adam (with the target EMA and the packed copies), and the
+  // temperature step in one extra workgroup of the same launch
+  const AlphaJob aj{g->logp2B, B, hp.target_entropy, P + L.log_alpha, G + L.log_alpha, g->m + L.log_alpha,
+                    g->v + L.log_alpha, g->ctr, g->scal};
   SQ_TRY(adam(P, G, g->m, g->v, L.critic_end, &hp, g->ctr + CTR_TC, g->target, L.critic_begin, nullptr, &g->pk_critic,
-              st));
-  // temperature
-  SQ_TRY(alpha_step(g->logp2B, B, hp.target_entropy, P + L.log_alpha, G + L.log_alpha, g->m + L.log_alpha,
-                    g->v + L.log_alpha, g->ctr, &hp, g->scal, st));
+              st, &g->gs_critic, &aj));
   // delayed actor step against the updated critic
   if (actor_step) {
     SQ_TRY(critic_forward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->S2, S, g->act2B, A, B, g->logits_q,
@@ -171,9 +173,9 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
     SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits_q, B, g->aux, nullptr, nullptr,
                            g->da, st));
     SQ_TRY(actor_backward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
-                          1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st));
+                          1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st, true));
     SQ_TRY(adam(P + L.actor_begin, G + L.actor_begin, g->m + L.actor_begin, g->v + L.actor_begin,
-                L.actor_end - L.actor_begin, &hp, g->ctr + CTR_TA, nullptr, 0, nullptr, &g->pk_actor, st));
+                L.actor_end - L.actor_begin, &hp, g->ctr + CTR_TA, nullptr, 0, nullptr, &g->pk_actor, st, &g->gs_actor));
   }
   return finish_update(g->loss_row, g->q_row, g->tgt_row, g->logp2B, g->qa_row, g->scal, B, actor_step, g->ctr, stats,
                        st);
@@ -254,6 +256,10 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
     g->pk_critic.tpack = g->tpack;
     g->pk_critic.p_begin = 0;
     g->pk_actor.p_begin = L.actor_begin;
+    critic_grad_segs(g->net, L, g->crit, g->B, &g->gs_critic);
+    actor_grad_segs(g->net, L, g->actor, g->B, &g->gs_actor);
+    g->gs_critic.gout = g->grads;
+    g->gs_actor.gout = g->grads + L.actor_begin;
   }
   if (pack_weights(g->L, params, target, g->pack, g->tpack, nullptr) != SQ_OK ||
       hipDeviceSynchronize() != hipSuccess) {

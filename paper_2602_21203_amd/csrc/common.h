@@ -241,8 +241,20 @@ struct PackArgs {
   int n; PackSeg seg[16];
   float* pack; float* tpack; long long p_begin;
 };
+// Gradients that are still row-block partials: parameter i in [begin, begin + H)
+// (relative to the optimiser's range) has gradient sum_{r < nrows} part[r * H + i - begin],
+// summed in r order (the same sum colsum() forms); the optimiser forms it and
+// stores it at gout[i] (the writable gradient vector of the range).
+struct GradSeg { long long begin; int H, nrows; const float* part; };
+struct GradSegs { int n; GradSeg s[20]; float* gout; };
+// The temperature step (Alg. 1), run by one extra workgroup of an Adam launch.
+struct AlphaJob {
+  const float* logp; int B; float target_entropy;
+  float* log_alpha; float* grad; float* m; float* v; const int* ctr; float* scal;
+};
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
-         float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st);
+         float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st,
+         const GradSegs* gs = nullptr, const AlphaJob* aj = nullptr);
 // copy the linear weights of `params` (and the critic block of `target`) into packs
 int pack_weights(const Layout& L, const float* params, const float* target, float* pack, float* tpack,
                  hipStream_t st);

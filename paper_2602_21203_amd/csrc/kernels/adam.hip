@@ -26,71 +26,200 @@ __device__ __forceinline__ long long pack_pos(const PackArgs& pk, long long i, i
 // Each workgroup updates 256 * kAdamPer consecutive parameters.  The packed
 // segment holding the workgroup's first parameter is found once; parameters of
 // that segment map to their packed position with one division, the rare others
-// (a workgroup straddling a segment boundary) search the table.
+// (a workgroup straddling a segment boundary) search the table.  Gradients given
+// as row-block partials (gs) are summed here, in row order.
 constexpr int kAdamPer = 4;
 
-__global__ __launch_bounds__(256) void k_adam(float* __restrict__ p, const float* __restrict__ g,
-                                              float* __restrict__ m, float* __restrict__ v, long long n,
-                                              float lr, float b1, float b2, float eps,
-                                              const int* __restrict__ step, float* __restrict__ ema,
-                                              long long ema_begin, float rho, uint16_t* __restrict__ shadow,
-                                              PackArgs pk) {
-  const float t = (float)(*step + 1);
-  const float bc1 = 1.f - powf(b1, t);
-  const float bc2 = 1.f - powf(b2, t);
+// fixed-order sum over the 256 threads; valid in thread 0
+__device__ float adam_block_sum(float v, float* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// Temperature step (Sec. III learned temperature; Alg. 1): L = alpha * mean(-log pi
+// - target entropy), so d L / d log alpha is the same value; one Adam step on log
+// alpha with step ctr[CTR_TALPHA] + 1.  scal: [0] alpha before, [1] alpha after,
+// [2] L_alpha, [3] mean entropy.
+__device__ void alpha_block(const AlphaJob& j, float lr, float b1, float b2, float eps) {
+  __shared__ float sh[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < j.B; i += 256) s += j.logp[i];
+  s = adam_block_sum(s, sh);
+  if (threadIdx.x != 0) return;
+  const float ent = -s / (float)j.B;
+  const float la = *j.log_alpha;
+  const float alpha = expf(la);
+  const float gr = alpha * (ent - j.target_entropy);
+  const float t = (float)(j.ctr[CTR_TALPHA] + 1);
+  const float mm = b1 * (*j.m) + (1.f - b1) * gr;
+  const float vv = b2 * (*j.v) + (1.f - b2) * gr * gr;
+  const float mh = mm / (1.f - powf(b1, t));
+  const float vh = vv / (1.f - powf(b2, t));
+  const float la2 = la - lr * mh / (sqrtf(vh) + eps);
+  *j.m = mm;
+  *j.v = vv;
+  *j.log_alpha = la2;
+  if (j.grad) *j.grad = gr;
+  j.scal[0] = alpha;
+  j.scal[1] = expf(la2);
+  j.scal[2] = gr;
+  j.scal[3] = ent;
+}
+
+__global__ __launch_bounds__(256) void k_alpha(AlphaJob j, float lr, float b1, float b2, float eps) {
+  alpha_block(j, lr, b1, b2, eps);
+}
+
+struct AdamArgs {
+  float* p; const float* g; float* m; float* v; long long n;
+  float lr, b1, b2, eps;
+  const int* step; float* ema; long long ema_begin; float rho; uint16_t* shadow;
+};
+
+// the update of parameter i with gradient gi (packed copy position from segment s0 when it holds i)
+__device__ __forceinline__ void adam_elem(const AdamArgs& A, const PackArgs& pk, long long i, float gi, float bc1,
+                                          float bc2, int s0) {
+  const float mi = A.b1 * A.m[i] + (1.f - A.b1) * gi;
+  const float vi = A.b2 * A.v[i] + (1.f - A.b2) * gi * gi;
+  A.m[i] = mi;
+  A.v[i] = vi;
+  const float pi = A.p[i] - A.lr * (mi / bc1) / (sqrtf(vi / bc2) + A.eps);
+  A.p[i] = pi;
+  float ei = 0.f;
+  if (A.ema && i >= A.ema_begin) {
+    float* e = A.ema + (i - A.ema_begin);
+    ei = A.rho * *e + (1.f - A.rho) * pi;
+    *e = ei;
+  }
+  if (A.shadow) A.shadow[i] = bf16_bits(pi);
+  if (pk.n) {
+    int critic = 0;
+    long long d = -1;
+    if (s0 >= 0) {
+      const PackSeg& ps = pk.seg[s0];
+      const long long loc = i + pk.p_begin - ps.src;
+      if (loc >= 0 && loc < (long long)ps.rows * ps.cols) {
+        const unsigned r = (unsigned)loc / (unsigned)ps.cols;
+        d = ps.dst + (long long)r * ps.ldp + (loc - (long long)r * ps.cols);
+        critic = ps.critic;
+      }
+    }
+    if (d < 0) d = pack_pos(pk, i, &critic);
+    if (d >= 0) {
+      pk.pack[d] = pi;
+      if (critic && pk.tpack && A.ema && i >= A.ema_begin) pk.tpack[d] = ei;
+    }
+  }
+}
+
+// Workgroups [0, main): 256 * kAdamPer consecutive parameters each, skipping the
+// partial-gradient segments.  Then one workgroup per 64 parameters of every
+// segment: wave w sums the partial rows w, w + 4, ... of its lane's parameter,
+// the four wave sums are added in wave order (the order colsum() uses), and wave
+// 0 applies the update.  With alpha_on, the last workgroup is the temperature step.
+__global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs gs, int main_blocks, AlphaJob aj,
+                                              int alpha_on) {
+  if (alpha_on && blockIdx.x == gridDim.x - 1) {
+    alpha_block(aj, A.lr, A.b1, A.b2, A.eps);
+    return;
+  }
+  const float t = (float)(*A.step + 1);
+  const float bc1 = 1.f - powf(A.b1, t);
+  const float bc2 = 1.f - powf(A.b2, t);
+  if ((int)blockIdx.x >= main_blocks) {
+    __shared__ float sh[4][64];
+    int b = (int)blockIdx.x - main_blocks, q = 0;
+    while (q < gs.n && b >= (gs.s[q].H + 63) / 64) b -= (gs.s[q++].H + 63) / 64;
+    if (q >= gs.n) return;
+    const GradSeg& e = gs.s[q];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int j = b * 64 + lane;
+    float sum = 0.f;
+    if (j < e.H) {
+      const float* pp = e.part + j;
+      int r = wave;
+      for (; r + 12 < e.nrows; r += 16) {
+        float w[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w[k] = pp[(long long)(r + 4 * k) * e.H];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sum += w[k];
+      }
+      for (; r < e.nrows; r += 4) sum += pp[(long long)r * e.H];
+    }
+    sh[wave][lane] = sum;
+    __syncthreads();
+    if (wave == 0 && j < e.H) {
+      const float gi = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+      const long long i = e.begin + j;
+      gs.gout[i] = gi;
+      adam_elem(A, pk, i, gi, bc1, bc2, -1);
+    }
+    return;
+  }
   const long long b0 = (long long)blockIdx.x * 256 * kAdamPer;
   int s0 = -1;
   for (int s = 0; s < pk.n; ++s) {
     const long long loc = b0 + pk.p_begin - pk.seg[s].src;
     if (loc >= 0 && loc < (long long)pk.seg[s].rows * pk.seg[s].cols) { s0 = s; break; }
   }
+  // first partial-gradient segment that ends after the workgroup's start (segments sorted by begin)
+  int q0 = 0;
+  while (q0 < gs.n && gs.s[q0].begin + gs.s[q0].H <= b0) ++q0;
 #pragma unroll
   for (int u = 0; u < kAdamPer; ++u) {
     const long long i = b0 + u * 256 + threadIdx.x;
-    if (i >= n) break;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-    p[i] = pi;
-    float ei = 0.f;
-    if (ema && i >= ema_begin) {
-      float* e = ema + (i - ema_begin);
-      ei = rho * *e + (1.f - rho) * pi;
-      *e = ei;
-    }
-    if (shadow) shadow[i] = bf16_bits(pi);
-    if (pk.n) {
-      int critic = 0;
-      long long d = -1;
-      if (s0 >= 0) {
-        const PackSeg& q = pk.seg[s0];
-        const long long loc = i + pk.p_begin - q.src;
-        if (loc < (long long)q.rows * q.cols) {
-          const unsigned r = (unsigned)loc / (unsigned)q.cols;
-          d = q.dst + (long long)r * q.ldp + (loc - (long long)r * q.cols);
-          critic = q.critic;
-        }
-      }
-      if (d < 0) d = pack_pos(pk, i, &critic);
-      if (d >= 0) {
-        pk.pack[d] = pi;
-        if (critic && pk.tpack && ema && i >= ema_begin) pk.tpack[d] = ei;
-      }
-    }
+    if (i >= A.n) break;
+    int q = q0;
+    while (q < gs.n && gs.s[q].begin + gs.s[q].H <= i) ++q;
+    if (q < gs.n && gs.s[q].begin <= i) continue;   // updated by its segment's workgroup
+    adam_elem(A, pk, i, A.g[i], bc1, bc2, s0);
   }
 }
 
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
-         float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st) {
-  if (n <= 0) return SQ_OK;
-  const long long blocks = (n + 256 * kAdamPer - 1) / (256 * kAdamPer);
+         float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st,
+         const GradSegs* gs, const AlphaJob* aj) {
+  if (n <= 0 && !aj) return SQ_OK;
+  const long long blocks = n > 0 ? (n + 256 * kAdamPer - 1) / (256 * kAdamPer) : 0;
   PackArgs none{};
-  k_adam<<<(unsigned)blocks, 256, 0, st>>>(p, g, m, v, n, hp->lr, hp->beta1, hp->beta2, hp->adam_eps, step,
-                                           ema_target, ema_begin, hp->rho, shadow, pk ? *pk : none);
+  GradSegs nogs{};
+  AlphaJob noaj{};
+  long long seg_blocks = 0;
+  if (gs) {
+    if (gs->n > 0 && !gs->gout) {
+      set_error("adam: partial-gradient segments need a gradient output");
+      return SQ_EINVAL;
+    }
+    for (int i = 0; i < gs->n; ++i) {
+      if (i > 0 && gs->s[i].begin < gs->s[i - 1].begin + gs->s[i - 1].H) {
+        set_error("adam: partial-gradient segments must be sorted and disjoint");
+        return SQ_EINVAL;
+      }
+      if (gs->s[i].begin < 0 || gs->s[i].begin + gs->s[i].H > n) {
+        set_error("adam: partial-gradient segment outside the parameter range");
+        return SQ_EINVAL;
+      }
+      seg_blocks += (gs->s[i].H + 63) / 64;
+    }
+  }
+  const AdamArgs A{p, g, m, v, n, hp->lr, hp->beta1, hp->beta2, hp->adam_eps, step, ema_target, ema_begin, hp->rho,
+                   shadow};
+  k_adam<<<(unsigned)(blocks + seg_blocks + (aj ? 1 : 0)), 256, 0, st>>>(A, pk ? *pk : none, gs ? *gs : nogs,
+                                                                         (int)blocks, aj ? *aj : noaj, aj ? 1 : 0);
   return launch_status("adam");
+}
+
+int alpha_step(const float* logp, int B, float target_entropy, float* log_alpha, float* grad, float* m, float* v,
+               const int* ctr, const sq_hparams* hp, float* scal, hipStream_t st) {
+  const AlphaJob j{logp, B, target_entropy, log_alpha, grad, m, v, ctr, scal};
+  k_alpha<<<1, 256, 0, st>>>(j, hp->lr, hp->beta1, hp->beta2, hp->adam_eps);
+  return launch_status("alpha_step");
 }
 
 // rows of every packed segment; padding columns are written as zero

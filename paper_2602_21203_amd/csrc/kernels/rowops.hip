@@ -677,47 +677,6 @@ int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max
   return launch_status("expected_q");
 }
 
-// ---------------------------------------------------------------- temperature step
-// L_alpha = alpha * mean(-log pi - H_target); d L / d log alpha = the same value.
-// One Adam step on log alpha with step t = ctr[CTR_TALPHA] + 1.
-// scal: [0] alpha before, [1] alpha after, [2] L_alpha, [3] mean(-log pi)
-__global__ __launch_bounds__(256) void k_alpha(const float* __restrict__ logp, int B, float target_entropy,
-                                               float* __restrict__ log_alpha, float* __restrict__ grad,
-                                               float* __restrict__ m, float* __restrict__ v,
-                                               const int* __restrict__ ctr, float lr, float b1, float b2,
-                                               float eps, float* __restrict__ scal) {
-  __shared__ float sh[256];
-  float s = 0.f;
-  for (int i = threadIdx.x; i < B; i += 256) s += logp[i];
-  s = block_sum256(s, sh);
-  if (threadIdx.x != 0) return;
-  const float ent = -s / (float)B;
-  const float la = *log_alpha;
-  const float alpha = expf(la);
-  const float gr = alpha * (ent - target_entropy);
-  const float t = (float)(ctr[CTR_TALPHA] + 1);
-  const float mm = b1 * (*m) + (1.f - b1) * gr;
-  const float vv = b2 * (*v) + (1.f - b2) * gr * gr;
-  const float mh = mm / (1.f - powf(b1, t));
-  const float vh = vv / (1.f - powf(b2, t));
-  const float la2 = la - lr * mh / (sqrtf(vh) + eps);
-  *m = mm;
-  *v = vv;
-  *log_alpha = la2;
-  if (grad) *grad = gr;
-  scal[0] = alpha;
-  scal[1] = expf(la2);
-  scal[2] = gr;
-  scal[3] = ent;
-}
-
-int alpha_step(const float* logp, int B, float target_entropy, float* log_alpha, float* grad, float* m, float* v,
-               const int* ctr, const sq_hparams* hp, float* scal, hipStream_t st) {
-  k_alpha<<<1, 256, 0, st>>>(logp, B, target_entropy, log_alpha, grad, m, v, ctr, hp->lr, hp->beta1, hp->beta2,
-                             hp->adam_eps, scal);
-  return launch_status("alpha_step");
-}
-
 // ---------------------------------------------------------------- end of an update
 // stats = {L_c, L_pi, L_alpha, alpha_new, entropy, mean Q, mean target, non-finite}
 __global__ __launch_bounds__(256) void k_finish(const float* __restrict__ loss_row, const float* __restrict__ q_row,

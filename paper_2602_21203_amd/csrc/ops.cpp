@@ -262,7 +262,7 @@ int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* 
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                     long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
                     float* daction, hipStream_t st,
-                    bool out_partials_done) {
+                    bool out_partials_done, bool defer_colsum) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic, cld = net.cpad, A = d.action;
   const long long c0 = L.critic_begin;
@@ -336,7 +336,7 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
       SQ_TRY(gemm(bf16, dw.M, dw.N, dw.K, dw.batch, dw.A, dw.B, dw.C, c.split, kSplitFloats, st));
     }
   }
-  if (params) {
+  if (params && !defer_colsum) {
     const int pr = ln_bwd_partial_rows(n);
     ColSegs sg{};
     sg.n = 4;
@@ -410,7 +410,8 @@ int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, 
 int actor_backward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
                    long long ld_feat, const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
-                   hipStream_t st) {
+                   hipStream_t st,
+                   bool defer_colsum) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor, ald = net.apad;
   const long long a0 = L.actor_begin;
@@ -444,6 +445,7 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
   SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, ald, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), 0, n, P, 1, 1, a.dA, a.part_t,
                     st));
   SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, a.dA, P, 0, feat, ld_feat, 0, dap + (T.W - a0), net.flat, 0, a.split, st));
+  if (defer_colsum) return SQ_OK;
   const int pr = ln_bwd_partial_rows(n);
   ColSegs sg{};
   sg.n = 4;
@@ -453,6 +455,47 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
   sg.s[2] = ColSeg{a.part_l1, pr, H, 3, 1, {dap + (L.al1.b - a0), dap + (L.al1.g - a0), dap + (L.al1.beta - a0)}, 0, 0};
   sg.s[3] = ColSeg{a.part_t, pr, P, 3, 1, {dap + (T.b - a0), dap + (T.g - a0), dap + (T.beta - a0)}, 0, 0};
   return colsum(sg, st);
+}
+
+static void sort_segs(GradSegs* gs) {
+  std::sort(gs->s, gs->s + gs->n, [](const GradSeg& x, const GradSeg& y) { return x.begin < y.begin; });
+}
+
+void critic_grad_segs(const Net& net, const Layout& L, const CriticBufs& c, int n, GradSegs* gs) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj, N = d.atoms;
+  const int pr = ln_bwd_partial_rows(n);
+  gs->n = 0;
+  auto add = [&](long long begin, int width, const float* part) { gs->s[gs->n++] = GradSeg{begin, width, pr, part}; };
+  for (int t = 0; t < 2; ++t) {
+    const Twin& q = L.q[t];
+    add(q.out.b, N, c.part_out + (size_t)t * pr * N);
+    const long long l2[3] = {q.l2.b, q.l2.g, q.l2.beta}, l1[3] = {q.l1.b, q.l1.g, q.l1.beta};
+    for (int k = 0; k < 3; ++k) {
+      add(l2[k], H, c.part_l2 + (size_t)(t * 3 + k) * pr * H);
+      add(l1[k], H, c.part_l1 + (size_t)(t * 3 + k) * pr * H);
+    }
+  }
+  const long long tr[3] = {L.ctrunk.b, L.ctrunk.g, L.ctrunk.beta};
+  for (int k = 0; k < 3; ++k) add(tr[k], P, c.part_t + (size_t)k * pr * P);
+  sort_segs(gs);
+}
+
+void actor_grad_segs(const Net& net, const Layout& L, const ActorBufs& a, int n, GradSegs* gs) {
+  const sq_dims& d = net.d;
+  const int H = d.hidden, P = d.proj;
+  const int pr = ln_bwd_partial_rows(n);
+  const long long a0 = L.actor_begin;
+  gs->n = 0;
+  gs->s[gs->n++] = GradSeg{L.aout.b - a0, 2 * d.action, tanh_gauss_partial_rows(n), a.part_out};
+  const long long l2[3] = {L.al2.b, L.al2.g, L.al2.beta}, l1[3] = {L.al1.b, L.al1.g, L.al1.beta};
+  const long long tr[3] = {L.atrunk.b, L.atrunk.g, L.atrunk.beta};
+  for (int k = 0; k < 3; ++k) {
+    gs->s[gs->n++] = GradSeg{l2[k] - a0, H, pr, a.part_l2 + (size_t)k * pr * H};
+    gs->s[gs->n++] = GradSeg{l1[k] - a0, H, pr, a.part_l1 + (size_t)k * pr * H};
+    gs->s[gs->n++] = GradSeg{tr[k] - a0, P, pr, a.part_t + (size_t)k * pr * P};
+  }
+  sort_segs(gs);
 }
 
 }  // namespace sq

@@ -48,11 +48,13 @@ int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack
                    long long ld_feat, const float* s, long long ld_s, const float* a, long long ld_a, int n,
                    float* logits, const CriticBufs& c, hipStream_t st);
 // dcp / dfeat / daction nullable; dcp is laid out like the critic block
-// out_partials_done: the output-head bias partials of dlogits are already in c.part_out (ce_loss)
+// out_partials_done: the output-head bias partials of dlogits are already in c.part_out (ce_loss).
+// defer_colsum: leave the bias / gain / shift gradients as row-block partials for the optimiser
+// (critic_grad_segs / actor_grad_segs describe them).
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                     long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
                     float* daction, hipStream_t st,
-                    bool out_partials_done = false);
+                    bool out_partials_done = false, bool defer_colsum = false);
 
 struct ActorBufs {
   float* pre;          // [n][max(proj, hidden)]
@@ -76,7 +78,8 @@ int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, 
 int actor_backward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
                    long long ld_feat, const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
-                   hipStream_t st);
+                   hipStream_t st,
+                   bool defer_colsum = false);
 
 // act(): squint -> encoder -> actor, forward only
 struct ActBufs {
@@ -84,5 +87,10 @@ struct ActBufs {
 };
 void plan_act(const Net& net, int n, Bump& b, ActBufs* w);
 size_t act_bytes_per_obs(const Net& net);
+
+// The partial-gradient segments left by a deferred colsum, relative to the start of
+// each optimiser's range (0 for encoder + critic, actor_begin for the actor).
+void critic_grad_segs(const Net& net, const Layout& L, const CriticBufs& c, int n, GradSegs* gs);
+void actor_grad_segs(const Net& net, const Layout& L, const ActorBufs& a, int n, GradSegs* gs);
 
 }  // namespace sq
