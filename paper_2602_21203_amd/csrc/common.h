@@ -143,6 +143,10 @@ struct OutArg {            // C(r, c) at p[z*sz + r*ld + c]
 // scratch (nullable) enables a deterministic split over K for small outputs.
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st);
+// policy head [n][2A] = X W^T + bias with the tanh-Gaussian sample (eps given) or the
+// mean action (eps null) applied per row in the same launch; head is also stored
+int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const float* bias, const float* eps, float lo,
+                    float hi, float* action, float* logp, float* save, float* head, hipStream_t st);
 struct GemmProb {
   int M, N, K, batch; MatArg A, B; OutArg C;
 };

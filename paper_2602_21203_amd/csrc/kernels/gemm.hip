@@ -17,6 +17,7 @@
 // by a second kernel.
 #include "../common.h"
 #include "bf16.h"
+#include "tgauss.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -120,12 +121,50 @@ struct StMat {
   float* p; long long ld, sz; const float* bias; long long bias_sz; int acc, relu;
   const float* bias_alt = nullptr; int bias_zalt = kNoAlt;
   static constexpr bool ROW_FAST = false;
+  static constexpr bool ROWS = false;   // element stores (put), not a tile epilogue
+  __device__ void rows(int, int, const float*, int, float*) const {}
   __device__ __forceinline__ void put(int z, int r, int c, float v) const {
     const long long i = z * sz + (long long)r * ld + c;
     if (bias) v += z < bias_zalt ? bias[z * bias_sz + c] : bias_alt[(z - bias_zalt) * bias_sz + c];
     if (acc) v += p[i];
     if (relu) v = fmaxf(v, 0.f);
     p[i] = v;
+  }
+};
+// Tile epilogue of the policy head (N = 2A <= 32, one column tile): every thread
+// takes one (row, dimension) of the tile: the head values (+ bias) go through the
+// tanh-Gaussian sample (eps given) or the mean action tanh(mu) (eps null); log pi
+// sums each row's dimension terms in d order; head itself is stored when wanted.
+// v: the tile's sums [32][ld]; tmp: >= 32 * 32 floats of LDS.  All threads call.
+struct StTanhGauss {
+  const float* bias; const float* eps; float lo, hi; float* action; float* logp; float* save; float* head; int A;
+  static constexpr bool ROW_FAST = false;
+  static constexpr bool ROWS = true;
+  __device__ void put(int, int, int, float) const {}
+  __device__ void rows(int r0, int nr, const float* v, int ld, float* tmp) const {
+    const int t = threadIdx.x, N = 2 * A;
+    for (int e = t; e < nr * N; e += blockDim.x) {
+      const int r = e / N, c = e - r * N;
+      if (head) head[(long long)(r0 + r) * N + c] = v[r * ld + c] + (bias ? bias[c] : 0.f);
+    }
+    for (int e = t; e < nr * A; e += blockDim.x) {
+      const int r = e / A, d = e - r * A;
+      const long long row = r0 + r;
+      const float mu = v[r * ld + d] + (bias ? bias[d] : 0.f);
+      if (eps) {
+        const float us = v[r * ld + A + d] + (bias ? bias[A + d] : 0.f);
+        tmp[r * 32 + d] = tanh_gauss_dim(mu, us, eps[row * A + d], A, d, lo, hi, action + row * A, save + row * 3 * A);
+      } else {
+        action[row * A + d] = tanhf(mu);
+      }
+    }
+    if (!eps || !logp) return;
+    __syncthreads();
+    if (t < nr) {
+      float lp = 0.f;
+      for (int d = 0; d < A; ++d) lp += tmp[t * 32 + d];
+      logp[r0 + t] = lp;
+    }
   }
 };
 // C((n, p), c) -> out[n][c][p] (NCHW), optional bias + ReLU
@@ -587,9 +626,15 @@ __device__ __forceinline__ void gemm_tile(const RMat& fa, const RMat& fb, const 
     const float v = ((red[(0 * kTile + r) * RLD + c] + red[(1 * kTile + r) * RLD + c]) +
                      red[(2 * kTile + r) * RLD + c]) + red[(3 * kTile + r) * RLD + c];
     const int gr = m0 + r, gc = n0 + c;
-    if (gr < M && gc < N) {
+    if constexpr (ST::ROWS && !SPLIT) {
+      red[r * RLD + c] = v;   // wave 0's slot of this element: read above by this thread only
+    } else if (gr < M && gc < N) {
       if constexpr (SPLIT) sp.put(z, split, gr, gc, v); else st.put(z, gr, gc, v);
     }
+  }
+  if constexpr (ST::ROWS && !SPLIT) {
+    __syncthreads();
+    st.rows(m0, min(kTile, M - m0), red, RLD, red + kTile * RLD);
   }
 }
 
@@ -741,6 +786,28 @@ int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C,
   if (va) return run_r<false, 1, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
   if (vb) return run_r<false, 0, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
   return run_r<false, 0, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
+}
+
+int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const float* bias, const float* eps, float lo,
+                    float hi, float* action, float* logp, float* save, float* head, hipStream_t st) {
+  if (n <= 0) return SQ_OK;
+  if (2 * A > kTile || rkind(X) != 1 || rkind(W) != 1 || !head) {
+    OutArg C{head, 2 * A, 0, bias, 0, 0, 0};
+    if (!head) {
+      set_error("gemm_tanh_gauss: the unfused form needs the head buffer");
+      return SQ_EINVAL;
+    }
+    SQ_TRY(gemm(bf16, n, 2 * A, K, 1, X, W, C, nullptr, 0, st));
+    return eps ? tanh_gauss_fwd(head, n, A, eps, lo, hi, action, logp, save, st) : mean_action(head, n, A, action, st);
+  }
+  const StTanhGauss tg{bias, eps, lo, hi, action, logp, save, head, A};
+  const StPart none{nullptr, 0, 0, 1};
+  dim3 grid(cdiv(n, kTile), 1, 1);
+  if (bf16)
+    k_gemm_r<true, 1, 1, StTanhGauss, false><<<grid, kThreads, 0, st>>>(rmat(X), rmat(W), tg, none, n, 2 * A, K, K);
+  else
+    k_gemm_r<false, 1, 1, StTanhGauss, false><<<grid, kThreads, 0, st>>>(rmat(X), rmat(W), tg, none, n, 2 * A, K, K);
+  return launch_status("gemm_tanh_gauss");
 }
 
 int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, size_t scratch_floats,

@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include "../common.h"
+#include "tgauss.h"
 
 namespace sq {
 
@@ -322,33 +323,17 @@ int colsum(ColSegs segs, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- tanh-Gaussian head
-__device__ __forceinline__ float softplusf(float x) {
-  return x > 0.f ? x + log1pf(expf(-x)) : log1pf(expf(x));
-}
 
 // head [rows][2A] = [mu | u_s]; save [rows][3A] = (tanh u_s, sigma, action)
 __global__ void k_tg_fwd(const float* __restrict__ head, int rows, int A, const float* __restrict__ eps, float lo,
                          float hi, float* __restrict__ action, float* __restrict__ logp, float* __restrict__ save) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
-  const float half_log_2pi = 0.91893853320467274f;
-  const float log2 = 0.69314718055994531f;
+  const float* h = head + (long long)r * 2 * A;
   float lp = 0.f;
-  for (int d = 0; d < A; ++d) {
-    const float mu = head[(long long)r * 2 * A + d];
-    const float us = head[(long long)r * 2 * A + A + d];
-    const float e = eps[(long long)r * A + d];
-    const float tus = tanhf(us);
-    const float ls = lo + 0.5f * (hi - lo) * (tus + 1.f);
-    const float sd = expf(ls);
-    const float u = mu + sd * e;
-    const float a = tanhf(u);
-    lp += -0.5f * e * e - ls - half_log_2pi - 2.f * (log2 - u - softplusf(-2.f * u));
-    action[(long long)r * A + d] = a;
-    save[(long long)r * 3 * A + d] = tus;
-    save[(long long)r * 3 * A + A + d] = sd;
-    save[(long long)r * 3 * A + 2 * A + d] = a;
-  }
+  for (int d = 0; d < A; ++d)
+    lp += tanh_gauss_dim(h[d], h[A + d], eps[(long long)r * A + d], A, d, lo, hi, action + (long long)r * A,
+                         save + (long long)r * 3 * A);
   if (logp) logp[r] = lp;
 }
 

@@ -401,10 +401,9 @@ int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, 
                     ap + (L.al2.b - a0), 0, a.pre, H, 0, st));
   SQ_TRY(ln_act_fwd(a.pre, H, 0, n, H, 1, ap + (L.al2.g - a0), ap + (L.al2.beta - a0), 0, 0, a.g2, H, 0, a.l2.xhat,
                     a.l2.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
-  SQ_TRY(linear_fwd(bf16, n, 2 * A, H, 1, a.g2, H, 0, w.W(L.aout.W, L.aout.Wp), w.ld(L.aout.in, L.aout.ldp), 0,
-                    ap + (L.aout.b - a0), 0, a.head, 2 * A, 0, st));
-  if (eps) return tanh_gauss_fwd(a.head, n, A, eps, lo, hi, action, logp, a.save, st);
-  return mean_action(a.head, n, A, action, st);
+  MatArg X{a.g2, H, 1, 0};
+  MatArg Wm{w.W(L.aout.W, L.aout.Wp), w.ld(L.aout.in, L.aout.ldp), 1, 0};
+  return gemm_tanh_gauss(bf16, n, A, H, X, Wm, ap + (L.aout.b - a0), eps, lo, hi, action, logp, a.save, a.head, st);
 }
 
 int actor_backward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
