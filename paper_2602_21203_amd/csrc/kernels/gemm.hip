@@ -381,12 +381,16 @@ template <> struct RFrag<false> { float v[2][8]; };
 // V = 0: raw[8 i + e] = row r0 + 16 i + li, k = k0 + 8 lq + e.  Rows past the end are
 // clamped into the matrix (computed on valid data, never stored).  FULL: the chunk
 // lies inside the contraction, else k >= kend reads as zero.
+// One operand of one batch: rows at base (k < kalt) or kbase (k >= kalt, read at k - kalt).
+struct ROp {
+  const float* base; const float* kbase; long long lr, lk; int kalt;
+};
+
 template <int V, bool FULL>
-__device__ __forceinline__ void rload(const RMat& m, float (&raw)[16], int z, int r0, int rows, int k0, int kend,
-                                      int lane) {
-  const float* base = m.batch(z);
+__device__ __forceinline__ void rload(const ROp& m, float (&raw)[16], int r0, int rows, int k0, int kend, int lane) {
+  const float* base = m.base;
   if (k0 >= m.kalt) {   // uniform: kalt is a multiple of the chunk
-    base = m.kp + (long long)z * m.sz;
+    base = m.kbase;
     k0 -= m.kalt;
     kend -= m.kalt;
   }
@@ -525,6 +529,8 @@ __device__ __forceinline__ void gemm_tile(const RMat& fa, const RMat& fb, const 
   const int z = bz / (SPLIT ? sp.splits : 1);
   const int split = SPLIT ? bz % sp.splits : 0;
   const int m0 = bx * kTile, n0 = by * kTile;
+  const ROp oa{fa.batch(z), fa.kp ? fa.kp + (long long)z * fa.sz : nullptr, fa.lr, fa.lk, fa.kalt};
+  const ROp ob{fb.batch(z), fb.kp ? fb.kp + (long long)z * fb.sz : nullptr, fb.lr, fb.lk, fb.kalt};
   const int kbeg = split * kchunk;
   const int kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63;
@@ -549,8 +555,8 @@ __device__ __forceinline__ void gemm_tile(const RMat& fa, const RMat& fb, const 
   auto load = [&](int g, int buf) {
 #pragma unroll
     for (int c = 0; c < G; ++c) {
-      rload<AV, true>(fa, ra[buf][c], z, m0, M, wb + (g * G + c) * KC, we, lane);
-      rload<BV, true>(fb, rb[buf][c], z, n0, N, wb + (g * G + c) * KC, we, lane);
+      rload<AV, true>(oa, ra[buf][c], m0, M, wb + (g * G + c) * KC, we, lane);
+      rload<BV, true>(ob, rb[buf][c], n0, N, wb + (g * G + c) * KC, we, lane);
     }
   };
   // a group's chunks: stage all (V = 1), one wait, then fragments and products
@@ -599,14 +605,14 @@ __device__ __forceinline__ void gemm_tile(const RMat& fa, const RMat& fb, const 
   int k0 = wb + ngf * G * KC;
   for (; k0 + KC <= we; k0 += KC) {
     float ta[16], tb[16];
-    rload<AV, true>(fa, ta, z, m0, M, k0, we, lane);
-    rload<BV, true>(fb, tb, z, n0, N, k0, we, lane);
+    rload<AV, true>(oa, ta, m0, M, k0, we, lane);
+    rload<BV, true>(ob, tb, n0, N, k0, we, lane);
     chunk(ta, tb);
   }
   if (k0 < we) {
     float ta[16], tb[16];
-    rload<AV, false>(fa, ta, z, m0, M, k0, we, lane);
-    rload<BV, false>(fb, tb, z, n0, N, k0, we, lane);
+    rload<AV, false>(oa, ta, m0, M, k0, we, lane);
+    rload<BV, false>(ob, tb, n0, N, k0, we, lane);
     chunk(ta, tb);
   }
 
