@@ -150,12 +150,10 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   SQ_TRY(critic_forward_pair(net, bf, P + L.critic_begin, g->target, g->pack, g->tpack, L, feat, flat,
                              (long long)B * flat, g->S2, S, (long long)B * S, g->Arep, g->act2B + (size_t)B * A, A, B,
                              g->logits, g->crit, st));
-  // distributional soft target from the averaged twin target critics
-  SQ_TRY(project_target(g->logits_t, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma,
-                        g->mt, g->tgt_row, st));
-  // critic + encoder step
-  SQ_TRY(ce_loss(g->logits, g->mt, B, N, d.v_min, d.v_max, g->dlogits, g->loss_row, g->q_row, g->crit.part_out,
-                 st));
+  // distributional soft target from the averaged twin target critics (projection),
+  // and the online critics' cross entropy to it, in one pass over the rows
+  SQ_TRY(target_ce(g->logits, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma, g->mt,
+                   g->tgt_row, g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st));
   SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
                          g->dfeat, nullptr, st, true, true));
   SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true));

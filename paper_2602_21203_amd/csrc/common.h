@@ -222,6 +222,10 @@ int project_target(const float* logits2, int B, int N, float v_min, float v_max,
                    float* m, float* tgt_row, hipStream_t st);
 int c51_project_raw(const float* p, const float* reward, const uint8_t* done, const float* bonus,
                     float gamma, int B, int N, float v_min, float v_max, float* m, hipStream_t st);
+// project_target and ce_loss in one launch: logits4 = [online twins | target twins]
+int target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward, const float* done,
+              const float* logp_next, const float* log_alpha, float gamma, float* m, float* tgt_row, float* dlogits2,
+              float* loss_row, float* q_row, float* part, hipStream_t st);
 int ce_loss(const float* logits2, const float* m, int B, int N, float v_min, float v_max,
             float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st);
 int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max, float* dlogits2,

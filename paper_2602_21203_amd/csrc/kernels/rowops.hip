@@ -513,6 +513,175 @@ int project_target(const float* logits2, int B, int N, float v_min, float v_max,
   return launch_status("project_target");
 }
 
+// Target projection and cross entropy of one row per wave, T atom slots per lane
+// (N <= 64 T): the same arithmetic as k_project_target followed by k_ce, with the
+// projected target kept in registers between the two.
+template <int T>
+__device__ float project_row_t(const float (&p)[T], int N, int lane, float v_min, float dz, float r, float d,
+                              float gamma, float bonus, float (&mi)[T]) {
+  float bpos[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int j = lane + 64 * t;
+    const float zj = v_min + (float)j * dz;
+    const float tz = r + gamma * (1.f - d) * (zj + bonus);
+    bpos[t] = fminf(fmaxf((tz - v_min) / dz, 0.f), (float)(N - 1));
+    mi[t] = 0.f;
+  }
+#pragma unroll
+  for (int ts = 0; ts < T; ++ts) {
+    const int lim = N - 64 * ts < 64 ? N - 64 * ts : 64;
+    for (int l = 0; l < lim; ++l) {
+      const float pj = lane_value(p[ts], l);
+      const float bj = lane_value(bpos[ts], l);
+#pragma unroll
+      for (int t = 0; t < T; ++t) mi[t] += pj * fmaxf(0.f, 1.f - fabsf(bj - (float)(lane + 64 * t)));
+    }
+  }
+  float mz = 0.f;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int i = lane + 64 * t;
+    if (i < N) mz += mi[t] * (v_min + (float)i * dz);
+  }
+  return wave_sum(mz);
+}
+
+template <int T>
+__device__ __forceinline__ void softmax_row_t(const float* l, int N, int lane, float (&p)[T]) {
+  float mx = -INFINITY;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int j = lane + 64 * t;
+    if (j < N) mx = fmaxf(mx, l[j]);
+  }
+  mx = wave_max(mx);
+  float s = 0.f;
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int j = lane + 64 * t;
+    p[t] = j < N ? expf(l[j] - mx) : 0.f;
+    s += p[t];
+  }
+  s = wave_sum(s);
+#pragma unroll
+  for (int t = 0; t < T; ++t) p[t] /= s;
+}
+
+// logits4 [4][B][N]: online twins (0, 1) then target twins (2, 3).  Per row b:
+// m = projection of the averaged target softmax (bonus -alpha log pi'), tgt_row = E_m[z];
+// for each online twin: loss_row = CE(m, softmax), dlogits = (softmax - m) / B,
+// q_row = E[z]; part (nullable): the workgroup's column sums of dlogits per twin.
+template <int T>
+__global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
+    const float* __restrict__ logits4, int B, int N, float v_min, float v_max, const float* __restrict__ reward,
+    const float* __restrict__ done, const float* __restrict__ logp_next, const float* __restrict__ log_alpha,
+    float gamma, float* __restrict__ m_out, float* __restrict__ tgt_row, float* __restrict__ dlogits2,
+    float* __restrict__ loss_row, float* __restrict__ q_row, float* __restrict__ part) {
+  extern __shared__ float shc2[];   // [2][kLnRowsPerBlock][N] when part is wanted
+  constexpr int R = kLnRowsPerBlock;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = blockIdx.x * R + wave;
+  const float dz = (v_max - v_min) / (float)(N - 1);
+  const float invB = 1.0f / (float)B;
+  float mi[T];
+  if (b < B) {
+    float p0[T], p1[T];
+    softmax_row_t<T>(logits4 + ((long long)2 * B + b) * N, N, lane, p0);
+    softmax_row_t<T>(logits4 + ((long long)3 * B + b) * N, N, lane, p1);
+#pragma unroll
+    for (int t = 0; t < T; ++t) p0[t] = 0.5f * (p0[t] + p1[t]);
+    const float alpha = expf(*log_alpha);
+    const float mz = project_row_t<T>(p0, N, lane, v_min, dz, reward[b], done[b], gamma, -alpha * logp_next[b], mi);
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int j = lane + 64 * t;
+      if (j < N) m_out[(long long)b * N + j] = mi[t];
+    }
+    if (lane == 0 && tgt_row) tgt_row[b] = mz;
+  }
+  for (int i = 0; i < 2; ++i) {
+    float dl[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) dl[t] = 0.f;
+    if (b < B) {
+      const float* l = logits4 + ((long long)i * B + b) * N;
+      float mx = -INFINITY;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int j = lane + 64 * t;
+        if (j < N) mx = fmaxf(mx, l[j]);
+      }
+      mx = wave_max(mx);
+      float e[T], s = 0.f;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int j = lane + 64 * t;
+        e[t] = j < N ? expf(l[j] - mx) : 0.f;
+        s += e[t];
+      }
+      s = wave_sum(s);
+      const float lse = logf(s);
+      float ce = 0.f, q = 0.f;
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int j = lane + 64 * t;
+        if (j < N) {
+          const float pj = e[t] / s;
+          ce -= mi[t] * (l[j] - mx - lse);
+          q += pj * (v_min + (float)j * dz);
+          dl[t] = (pj - mi[t]) * invB;
+          dlogits2[((long long)i * B + b) * N + j] = dl[t];
+        }
+      }
+      ce = wave_sum(ce);
+      q = wave_sum(q);
+      if (lane == 0) {
+        loss_row[(long long)i * B + b] = ce;
+        q_row[(long long)i * B + b] = q;
+      }
+    }
+    if (part) {
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int j = lane + 64 * t;
+        if (j < N) shc2[(i * R + wave) * N + j] = dl[t];
+      }
+    }
+  }
+  if (!part) return;
+  __syncthreads();
+  const int nblk = gridDim.x;
+  for (int e = threadIdx.x; e < 2 * N; e += 64 * R) {
+    const int i = e / N, j = e - i * N;
+    float sum = shc2[(i * R) * N + j];
+    for (int w = 1; w < R; ++w) sum += shc2[(i * R + w) * N + j];
+    part[((long long)i * nblk + blockIdx.x) * N + j] = sum;
+  }
+}
+
+int target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward, const float* done,
+              const float* logp_next, const float* log_alpha, float gamma, float* m, float* tgt_row, float* dlogits2,
+              float* loss_row, float* q_row, float* part, hipStream_t st) {
+  if (B <= 0) return SQ_OK;
+  if (N < 2 || N > 64 * kMaxAtomsPerLane) return SQ_EINVAL;
+  const size_t lds = part ? (size_t)2 * kLnRowsPerBlock * N * sizeof(float) : 0;
+  const dim3 grid(cdiv(B, kLnRowsPerBlock)), block(64 * kLnRowsPerBlock);
+  if (N <= 64)
+    k_target_ce<1><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
+                                             m, tgt_row, dlogits2, loss_row, q_row, part);
+  else if (N <= 128)
+    k_target_ce<2><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
+                                             m, tgt_row, dlogits2, loss_row, q_row, part);
+  else if (N <= 192)
+    k_target_ce<3><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
+                                             m, tgt_row, dlogits2, loss_row, q_row, part);
+  else
+    k_target_ce<4><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
+                                             m, tgt_row, dlogits2, loss_row, q_row, part);
+  return launch_status("target_ce");
+}
+
 // plain projection of given probabilities (library entry point)
 __global__ __launch_bounds__(256) void k_project(const float* __restrict__ p, const float* __restrict__ reward,
                                                  const uint8_t* __restrict__ done, const float* __restrict__ bonus,
