@@ -75,7 +75,8 @@ typedef struct {
 /* Update hyperparameters.  target_entropy is usually -action; log_std_min/max
  * bound the squashed log standard deviation of the policy; policy_freq delays
  * the actor step to updates u with u % policy_freq == 0 (u = global counter);
- * seed keys the Philox4x32-10 draws (replay indices, policy noise). */
+ * seed keys the Philox4x32-10 draws (replay indices, policy noise).  gamma must
+ * lie in [0, 1] (sq_agent_create returns SQ_EINVAL otherwise). */
 typedef struct {
   float gamma, lr, beta1, beta2, adam_eps, rho, target_entropy, log_std_min, log_std_max;
   int policy_freq;

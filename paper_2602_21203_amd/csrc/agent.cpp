@@ -216,6 +216,10 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
     set_error("bad batch %d / policy_freq %d / prec", batch, hp->policy_freq);
     return SQ_EINVAL;
   }
+  if (!(hp->gamma >= 0.f && hp->gamma <= 1.f)) {
+    set_error("discount gamma %g outside [0, 1]", (double)hp->gamma);
+    return SQ_EINVAL;
+  }
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
     set_error("sq_agent_create allocates and cannot run while the null stream captures");

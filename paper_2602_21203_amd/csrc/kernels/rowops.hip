@@ -1,13 +1,13 @@
 // Row-wise and small reduction kernels of the update, one wavefront (64 lanes)
-// per row with shuffle reductions:
+// per row with cross-lane (DPP) reductions:
 //   LayerNorm + activation forward / backward (Sec. IV Normalization)
 //   column sums of gradient partials (bias, LayerNorm gain / shift gradients)
 //   tanh-Gaussian policy head forward / backward (Sec. III Eq. (3))
 //   twin-target softmax average + C51 projection (Eq. (1), categorical form)
 //   cross entropy to the projected target, expected Q and its gradient
 //   temperature step, per-update statistics and counters
-// Every reduction has a fixed order: shuffle butterflies whose result is taken
-// from lane 0, and partial sums written per (row block, wave) and summed in order.
+// Every reduction has a fixed order: the DPP tree of wave_sum, and partial sums
+// written per (row block, wave) and summed in order.
 #include <math.h>
 
 #include <type_traits>
@@ -21,15 +21,32 @@ constexpr int kLnRowsPerBlock = 8; // rows per workgroup (one per wave) in row-p
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// Cross-lane moves inside 16-lane rows (DPP): quad_perm [1,0,3,2] and [2,3,0,1],
+// row_half_mirror, row_mirror.  Each step pairs lane i with a lane of the other
+// half of its current group, so after the four steps every lane of a row holds
+// the row's combined value (a + b and b + a round alike, so all lanes agree);
+// the four row values are then read from lanes 0, 16, 32, 48 and combined as
+// (r0 + r1) + (r2 + r3).  No LDS traffic, fixed order, result in every lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_read(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return __shfl(v, 0, 64);
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return __shfl(v, 0, 64);
+  v = fmaxf(v, dpp_move<0xB1>(v));
+  v = fmaxf(v, dpp_move<0x4E>(v));
+  v = fmaxf(v, dpp_move<0x141>(v));
+  v = fmaxf(v, dpp_move<0x140>(v));
+  return fmaxf(fmaxf(lane_read(v, 0), lane_read(v, 16)), fmaxf(lane_read(v, 32), lane_read(v, 48)));
 }
 
 // fixed-order block sum of 256 threads; result valid in every thread
@@ -437,9 +454,6 @@ __device__ __forceinline__ void softmax_row(const float* l, int N, int lane, flo
   for (int t = 0; t < kMaxAtomsPerLane; ++t) p[t] /= s;
 }
 
-__device__ __forceinline__ float lane_value(float v, int l) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
-}
 
 // projection of one row, given the probabilities in registers (lane-strided:
 // atom j lives in lane j % 64, slot j / 64).  Every lane walks all atoms j in
@@ -463,8 +477,8 @@ __device__ float project_row(const float* p, int N, int lane, float v_min, float
     if (64 * ts >= N) break;
     const int lim = N - 64 * ts < 64 ? N - 64 * ts : 64;
     for (int l = 0; l < lim; ++l) {
-      const float pj = lane_value(p[ts], l);
-      const float bj = lane_value(bpos[ts], l);
+      const float pj = lane_read(p[ts], l);
+      const float bj = lane_read(bpos[ts], l);
 #pragma unroll
       for (int t = 0; t < kMaxAtomsPerLane; ++t)
         mi[t] += pj * fmaxf(0.f, 1.f - fabsf(bj - (float)(lane + 64 * t)));
@@ -516,51 +530,67 @@ int project_target(const float* logits2, int B, int N, float v_min, float v_max,
 // Target projection and cross entropy of one row per wave, T atom slots per lane
 // (N <= 64 T): the same arithmetic as k_project_target followed by k_ce, with the
 // projected target kept in registers between the two.
+// Projection of one row with the hat weights of atom i restricted to the atoms j
+// that reach it.  The projected positions b_j are non-decreasing in j (every step
+// from z_j to b_j is monotone, and so is its rounding), so the j with
+// |b_j - i| < 1 form one run [lo, hi), found by bisection over b in the wave's
+// LDS slice; the terms skipped elsewhere are exact zeros, so m_i is the same sum,
+// in the same j order, as the walk over every atom.
 template <int T>
 __device__ float project_row_t(const float (&p)[T], int N, int lane, float v_min, float dz, float r, float d,
-                              float gamma, float bonus, float (&mi)[T]) {
-  float bpos[T];
+                              float gamma, float bonus, float* bl, float* pl, float (&mi)[T]) {
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int j = lane + 64 * t;
     const float zj = v_min + (float)j * dz;
     const float tz = r + gamma * (1.f - d) * (zj + bonus);
-    bpos[t] = fminf(fmaxf((tz - v_min) / dz, 0.f), (float)(N - 1));
-    mi[t] = 0.f;
-  }
-#pragma unroll
-  for (int ts = 0; ts < T; ++ts) {
-    const int lim = N - 64 * ts < 64 ? N - 64 * ts : 64;
-    for (int l = 0; l < lim; ++l) {
-      const float pj = lane_value(p[ts], l);
-      const float bj = lane_value(bpos[ts], l);
-#pragma unroll
-      for (int t = 0; t < T; ++t) mi[t] += pj * fmaxf(0.f, 1.f - fabsf(bj - (float)(lane + 64 * t)));
+    if (j < N) {
+      bl[j] = fminf(fmaxf((tz - v_min) / dz, 0.f), (float)(N - 1));
+      pl[j] = p[t];
     }
   }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   float mz = 0.f;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int i = lane + 64 * t;
-    if (i < N) mz += mi[t] * (v_min + (float)i * dz);
+    const float fi = (float)i;
+    // lo: first j with b_j - i > -1; hi: first j with b_j - i >= 1
+    int lo = 0, hi = 0;
+    if (i < N) {
+      int a = 0, c = N;
+      while (a < c) {
+        const int h = (a + c) >> 1;
+        if (bl[h] - fi > -1.f) c = h; else a = h + 1;
+      }
+      lo = a;
+      c = N;
+      while (a < c) {
+        const int h = (a + c) >> 1;
+        if (bl[h] - fi >= 1.f) c = h; else a = h + 1;
+      }
+      hi = a;
+    }
+    float acc = 0.f;
+    for (int j = lo; j < hi; ++j) acc += pl[j] * fmaxf(0.f, 1.f - fabsf(bl[j] - fi));
+    mi[t] = acc;
+    if (i < N) mz += acc * (v_min + fi * dz);
   }
   return wave_sum(mz);
 }
 
+// softmax of one row held lane-strided in registers (slots j >= N ignored)
 template <int T>
-__device__ __forceinline__ void softmax_row_t(const float* l, int N, int lane, float (&p)[T]) {
+__device__ __forceinline__ void softmax_regs(const float (&l)[T], int N, int lane, float (&p)[T]) {
   float mx = -INFINITY;
 #pragma unroll
-  for (int t = 0; t < T; ++t) {
-    const int j = lane + 64 * t;
-    if (j < N) mx = fmaxf(mx, l[j]);
-  }
+  for (int t = 0; t < T; ++t)
+    if (lane + 64 * t < N) mx = fmaxf(mx, l[t]);
   mx = wave_max(mx);
   float s = 0.f;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
-    const int j = lane + 64 * t;
-    p[t] = j < N ? expf(l[j] - mx) : 0.f;
+    p[t] = lane + 64 * t < N ? expf(l[t] - mx) : 0.f;
     s += p[t];
   }
   s = wave_sum(s);
@@ -572,52 +602,61 @@ __device__ __forceinline__ void softmax_row_t(const float* l, int N, int lane, f
 // m = projection of the averaged target softmax (bonus -alpha log pi'), tgt_row = E_m[z];
 // for each online twin: loss_row = CE(m, softmax), dlogits = (softmax - m) / B,
 // q_row = E[z]; part (nullable): the workgroup's column sums of dlogits per twin.
+// Every global input of a row is requested up front, so a wave waits on memory once.
 template <int T>
 __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
     const float* __restrict__ logits4, int B, int N, float v_min, float v_max, const float* __restrict__ reward,
     const float* __restrict__ done, const float* __restrict__ logp_next, const float* __restrict__ log_alpha,
     float gamma, float* __restrict__ m_out, float* __restrict__ tgt_row, float* __restrict__ dlogits2,
     float* __restrict__ loss_row, float* __restrict__ q_row, float* __restrict__ part) {
-  extern __shared__ float shc2[];   // [2][kLnRowsPerBlock][N] when part is wanted
+  // [kLnRowsPerBlock][2][N] projected positions and probabilities of each wave's
+  // row, then [2][kLnRowsPerBlock][N] head-bias partials when part is wanted
+  extern __shared__ float shc2[];
   constexpr int R = kLnRowsPerBlock;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int b = blockIdx.x * R + wave;
+  float* shp = shc2 + 2 * R * N;
   const float dz = (v_max - v_min) / (float)(N - 1);
   const float invB = 1.0f / (float)B;
-  float mi[T];
+  float dl[2][T];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int t = 0; t < T; ++t) dl[i][t] = 0.f;
   if (b < B) {
-    float p0[T], p1[T];
-    softmax_row_t<T>(logits4 + ((long long)2 * B + b) * N, N, lane, p0);
-    softmax_row_t<T>(logits4 + ((long long)3 * B + b) * N, N, lane, p1);
+    float lg[4][T];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int t = 0; t < T; ++t) {
+        const int j = lane + 64 * t;
+        lg[r][t] = j < N ? logits4[((long long)r * B + b) * N + j] : 0.f;
+      }
+    const float rb = reward[b], db = done[b], lpb = logp_next[b], la = *log_alpha;
+    float p0[T], p1[T], mi[T];
+    softmax_regs<T>(lg[2], N, lane, p0);
+    softmax_regs<T>(lg[3], N, lane, p1);
 #pragma unroll
     for (int t = 0; t < T; ++t) p0[t] = 0.5f * (p0[t] + p1[t]);
-    const float alpha = expf(*log_alpha);
-    const float mz = project_row_t<T>(p0, N, lane, v_min, dz, reward[b], done[b], gamma, -alpha * logp_next[b], mi);
+    const float mz = project_row_t<T>(p0, N, lane, v_min, dz, rb, db, gamma, -expf(la) * lpb, shc2 + 2 * wave * N,
+                                      shc2 + (2 * wave + 1) * N, mi);
 #pragma unroll
     for (int t = 0; t < T; ++t) {
       const int j = lane + 64 * t;
       if (j < N) m_out[(long long)b * N + j] = mi[t];
     }
     if (lane == 0 && tgt_row) tgt_row[b] = mz;
-  }
-  for (int i = 0; i < 2; ++i) {
-    float dl[T];
 #pragma unroll
-    for (int t = 0; t < T; ++t) dl[t] = 0.f;
-    if (b < B) {
-      const float* l = logits4 + ((long long)i * B + b) * N;
+    for (int i = 0; i < 2; ++i) {
       float mx = -INFINITY;
 #pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const int j = lane + 64 * t;
-        if (j < N) mx = fmaxf(mx, l[j]);
-      }
+      for (int t = 0; t < T; ++t)
+        if (lane + 64 * t < N) mx = fmaxf(mx, lg[i][t]);
       mx = wave_max(mx);
       float e[T], s = 0.f;
 #pragma unroll
       for (int t = 0; t < T; ++t) {
-        const int j = lane + 64 * t;
-        e[t] = j < N ? expf(l[j] - mx) : 0.f;
+        e[t] = lane + 64 * t < N ? expf(lg[i][t] - mx) : 0.f;
         s += e[t];
       }
       s = wave_sum(s);
@@ -628,10 +667,10 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
         const int j = lane + 64 * t;
         if (j < N) {
           const float pj = e[t] / s;
-          ce -= mi[t] * (l[j] - mx - lse);
+          ce -= mi[t] * (lg[i][t] - mx - lse);
           q += pj * (v_min + (float)j * dz);
-          dl[t] = (pj - mi[t]) * invB;
-          dlogits2[((long long)i * B + b) * N + j] = dl[t];
+          dl[i][t] = (pj - mi[t]) * invB;
+          dlogits2[((long long)i * B + b) * N + j] = dl[i][t];
         }
       }
       ce = wave_sum(ce);
@@ -641,21 +680,21 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
         q_row[(long long)i * B + b] = q;
       }
     }
-    if (part) {
-#pragma unroll
-      for (int t = 0; t < T; ++t) {
-        const int j = lane + 64 * t;
-        if (j < N) shc2[(i * R + wave) * N + j] = dl[t];
-      }
-    }
   }
   if (!part) return;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const int j = lane + 64 * t;
+      if (j < N) shp[(i * R + wave) * N + j] = dl[i][t];
+    }
   __syncthreads();
   const int nblk = gridDim.x;
   for (int e = threadIdx.x; e < 2 * N; e += 64 * R) {
     const int i = e / N, j = e - i * N;
-    float sum = shc2[(i * R) * N + j];
-    for (int w = 1; w < R; ++w) sum += shc2[(i * R + w) * N + j];
+    float sum = shp[(i * R) * N + j];
+    for (int w = 1; w < R; ++w) sum += shp[(i * R + w) * N + j];
     part[((long long)i * nblk + blockIdx.x) * N + j] = sum;
   }
 }
@@ -665,7 +704,7 @@ int target_ce(const float* logits4, int B, int N, float v_min, float v_max, cons
               float* loss_row, float* q_row, float* part, hipStream_t st) {
   if (B <= 0) return SQ_OK;
   if (N < 2 || N > 64 * kMaxAtomsPerLane) return SQ_EINVAL;
-  const size_t lds = part ? (size_t)2 * kLnRowsPerBlock * N * sizeof(float) : 0;
+  const size_t lds = (size_t)(part ? 4 : 2) * kLnRowsPerBlock * N * sizeof(float);
   const dim3 grid(cdiv(B, kLnRowsPerBlock)), block(64 * kLnRowsPerBlock);
   if (N <= 64)
     k_target_ce<1><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
