@@ -8,6 +8,7 @@ shares no code with the HIP path and must never be called by the product.
 Modules
   philox    Philox4x32-10 counter RNG, replay-index sampler, Box-Muller noise
   squint    area downsampling of uint8 frames
+  ring      squint at insertion (uint8 block means) and the FIFO replay ring
   layout    canonical flat parameter layout
   nets      conv / linear / LayerNorm / heads, forward and hand-written backward
   sac       one full SAC update (critic, temperature, actor, Adam, target EMA)

@@ -108,7 +108,9 @@ def sac_update(state, replay, d, hp, batch, bf=False):
     done = bt["done"].astype(np.float64)
 
     # 2-3. squint and encode both halves with the current encoder
-    x = np.concatenate([squint(bt["obs"], d.k), squint(bt["next_obs"], d.k)])
+    # (frames stored already squinted, as by squint at insertion, carry k = 1)
+    k = replay.get("k", d.k)
+    x = np.concatenate([squint(bt["obs"], k), squint(bt["next_obs"], k)])
     feat, enc_cache = nets.encoder_fwd(P, x, d.n_conv, bf)
     f_t, f_n = feat[:B], feat[B:]
 
