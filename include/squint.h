@@ -84,20 +84,28 @@ typedef struct {
   unsigned long long seed;
 } sq_hparams;
 
-/* Replay view, all device pointers, caller-owned; rows [0, size) are valid. */
+/* Replay view, all device pointers, caller-owned; rows [0, size) are valid.
+ * squinted = 0: frames are raw [capacity, H, W, C] and the update squints them.
+ * squinted = 1: frames were squinted at insertion (sq_ring) and are stored as
+ *   uint8 block means [capacity, H/k, W/k, C]; the update scales them by 1/255.
+ * dev_size (nullable): device int holding the row count, read by every update
+ *   in place of `size` (a ring that keeps growing between graph replays). */
 typedef struct {
-  const uint8_t* obs;          /* [capacity, H, W, C] */
-  const uint8_t* next_obs;     /* [capacity, H, W, C] */
+  const uint8_t* obs;          /* [capacity, H, W, C] or [capacity, H/k, W/k, C] */
+  const uint8_t* next_obs;     /* same shape as obs */
   const float* proprio;        /* [capacity, proprio] */
   const float* next_proprio;   /* [capacity, proprio] */
   const float* action;         /* [capacity, action] */
   const float* reward;         /* [capacity] */
   const uint8_t* done;         /* [capacity], 0 or 1 */
   int capacity, size;
+  int squinted;
+  const int* dev_size;
 } sq_replay;
 
 typedef struct sq_agent sq_agent;
 typedef struct sq_server sq_server;
+typedef struct sq_ring sq_ring;
 
 /* ---------------------------------------------------------------- host-side */
 SQ_API const char* sq_last_error(void);
@@ -238,6 +246,44 @@ SQ_API int sac_update_eager(sq_agent* agent, const sq_replay* replay, int n_upda
 SQ_API int act(sq_agent* agent, const uint8_t* frames, const float* proprio, int n, int sample,
         unsigned long long request_id, float* action_out, sq_stream_t stream);
 SQ_API int sq_agent_act_capacity(sq_agent* agent, int* n /*[host]*/);
+
+/* ---------------------------------------------------------------- insert path */
+/* GPU FIFO replay of squinted transitions (Alg. 1: each observation is
+ * downsampled when observed and the downsampled pair is what the buffer stores;
+ * Sec. V Replay Buffer Size: a simple FIFO held on the GPU).
+ * sq_ring_create allocates capacity rows (device memory, zero-filled; about
+ * 2 (H/k)(W/k) C + 4 (2 proprio + action + 1) + 1 bytes per row) and owns them
+ * until sq_ring_destroy.  capacity in [1, 2^31 - 1]. */
+SQ_API int sq_ring_create(const sq_dims* dims, int capacity, sq_ring** out);
+SQ_API int sq_ring_destroy(sq_ring* ring);
+/* Squint n transitions at insertion and append them: obs, next_obs [n, H, W, C]
+ * uint8 raw frames; proprio, next_proprio [n, proprio], action [n, A], reward [n]
+ * float; done [n] uint8 (all device pointers, read only).  Each frame is stored
+ * as its k x k block means, q = nearest integer to S / k^2 with ties to even
+ * (S the exact integer block sum), [H/k, W/k, C] uint8.  Transition i lands in
+ * row (pos + i) % capacity; then pos = (pos + n) % capacity and size =
+ * min(size + n, capacity).  n in [0, capacity] (SQ_EINVAL otherwise).  The write
+ * position is kept on the host, so the call cannot be captured (SQ_ECAPTURE);
+ * the row count the update samples from is also kept on the device. */
+SQ_API int sq_ring_insert(sq_ring* ring, const uint8_t* obs, const uint8_t* next_obs, const float* proprio,
+                          const float* next_proprio, const float* action, const float* reward, const uint8_t* done,
+                          int n, sq_stream_t stream);
+/* A replay view of the ring for sac_update: squinted = 1, dev_size set (and
+ * size = capacity, unused), so one captured graph keeps sampling the whole ring
+ * as it grows.  Sampling an empty ring reads its zero-filled rows.  out: [host]. */
+SQ_API int sq_ring_view(const sq_ring* ring, sq_replay* out);
+/* Host copy of the write position and row count after the inserts enqueued so
+ * far.  pos, size: [host]. */
+SQ_API int sq_ring_state(const sq_ring* ring, int* pos, int* size);
+/* Copy rows [row0, row0 + n) of one stored field into dst (device or host
+ * memory, caller-owned, densely packed rows), ordered on `stream`
+ * (hipMemcpyAsync; host dst needs a stream synchronisation before use).
+ * field: SQ_RING_OBS, SQ_RING_NEXT_OBS (uint8 [side, side, C] rows),
+ * SQ_RING_PROPRIO, SQ_RING_NEXT_PROPRIO, SQ_RING_ACTION, SQ_RING_REWARD (float
+ * rows), SQ_RING_DONE (uint8).  SQ_EINVAL when the rows leave [0, capacity). */
+enum { SQ_RING_OBS = 0, SQ_RING_NEXT_OBS = 1, SQ_RING_PROPRIO = 2, SQ_RING_NEXT_PROPRIO = 3, SQ_RING_ACTION = 4,
+       SQ_RING_REWARD = 5, SQ_RING_DONE = 6 };
+SQ_API int sq_ring_copy_out(const sq_ring* ring, int field, int row0, int n, void* dst, sq_stream_t stream);
 
 /* ---------------------------------------------------------------- serving */
 typedef void (*sq_done_cb)(unsigned long long request_id, double t_done_s, void* user);

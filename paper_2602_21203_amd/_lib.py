@@ -36,7 +36,7 @@ class HParams(ctypes.Structure):
 
 class Replay(ctypes.Structure):
     _fields_ = [(n, c_vp) for n in ("obs", "next_obs", "proprio", "next_proprio", "action", "reward", "done")] + \
-               [("capacity", c_int), ("size", c_int)]
+               [("capacity", c_int), ("size", c_int), ("squinted", c_int), ("dev_size", c_vp)]
 
 
 DONE_CB = ctypes.CFUNCTYPE(None, ctypes.c_ulonglong, ctypes.c_double, ctypes.c_void_p)
@@ -78,6 +78,12 @@ def _load():
         "sq_server_submit": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_ull, c_vp, DONE_CB, c_vp]),
         "sq_server_drain": (c_int, [c_vp]),
         "sq_server_destroy": (c_int, [c_vp]),
+        "sq_ring_create": (c_int, [P(Dims), c_int, P(c_vp)]),
+        "sq_ring_destroy": (c_int, [c_vp]),
+        "sq_ring_insert": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_int, c_vp]),
+        "sq_ring_view": (c_int, [c_vp, P(Replay)]),
+        "sq_ring_state": (c_int, [c_vp, P(c_int), P(c_int)]),
+        "sq_ring_copy_out": (c_int, [c_vp, c_int, c_int, c_int, c_vp, c_vp]),
         "sq_gemm": (c_int, [c_int, c_int, c_int, c_int, c_int, c_vp, c_ll, c_ll, c_ll, c_vp, c_ll, c_ll, c_ll,
                             c_vp, c_ll, c_ll, c_vp, c_ll, c_int, c_vp]),
         "sq_sample_indices": (c_int, [c_ull, ctypes.c_uint, c_int, c_int, c_vp, c_vp]),

@@ -198,6 +198,68 @@ def replay_struct(rep):
                                             "done")), cap, int(rep.get("size", cap)))
 
 
+class Ring:
+    """Device FIFO replay of transitions squinted at insertion (library-owned rows).
+
+    insert() squints raw [n, H, W, C] uint8 frames into uint8 block means and
+    appends the transitions; view is the sq_replay that Agent.sac_update samples."""
+
+    def __init__(self, cfg, capacity):
+        self.cfg = cfg
+        self.capacity = int(capacity)
+        h = ctypes.c_void_p()
+        check(L.LIB.sq_ring_create(_dims(cfg), self.capacity, ctypes.byref(h)))
+        self.handle = h
+        self.view = L.Replay()
+        check(L.LIB.sq_ring_view(self.handle, ctypes.byref(self.view)))
+        side = cfg["H"] // cfg["k"]
+        self.frame_shape = (side, side, cfg["C"])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize()
+            L.LIB.sq_ring_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def insert(self, obs, next_obs, proprio, next_proprio, action, reward, done, stream=None):
+        n = obs.shape[0]
+        c = self.cfg
+        _req(obs, torch.uint8, (n, c["H"], c["W"], c["C"]), "obs")
+        _req(next_obs, torch.uint8, (n, c["H"], c["W"], c["C"]), "next_obs")
+        _req(proprio, torch.float32, (n, c["proprio"]), "proprio")
+        _req(next_proprio, torch.float32, (n, c["proprio"]), "next_proprio")
+        _req(action, torch.float32, (n, c["action"]), "action")
+        _req(reward, torch.float32, (n,), "reward")
+        _req(done, torch.uint8, (n,), "done")
+        check(L.LIB.sq_ring_insert(self.handle, ptr(obs), ptr(next_obs), ptr(proprio), ptr(next_proprio),
+                                   ptr(action), ptr(reward), ptr(done), n, stream_handle(stream)))
+
+    FIELDS = ("obs", "next_obs", "proprio", "next_proprio", "action", "reward", "done")
+
+    def read(self, field, row0=0, n=None, stream=None):
+        """Rows [row0, row0 + n) of one stored field as a new device tensor."""
+        n = self.capacity - row0 if n is None else n
+        c = self.cfg
+        shape, dt = {"obs": ((n,) + self.frame_shape, torch.uint8), "next_obs": ((n,) + self.frame_shape, torch.uint8),
+                     "proprio": ((n, c["proprio"]), torch.float32), "next_proprio": ((n, c["proprio"]), torch.float32),
+                     "action": ((n, c["action"]), torch.float32), "reward": ((n,), torch.float32),
+                     "done": ((n,), torch.uint8)}[field]
+        out = torch.empty(shape, dtype=dt, device="cuda")
+        check(L.LIB.sq_ring_copy_out(self.handle, self.FIELDS.index(field), row0, n, ptr(out), stream_handle(stream)))
+        return out
+
+    def state(self):
+        pos, size = ctypes.c_int(), ctypes.c_int()
+        check(L.LIB.sq_ring_state(self.handle, ctypes.byref(pos), ctypes.byref(size)))
+        return pos.value, size.value
+
+
 class Agent:
     """Owns the state tensors of one agent and the library handle.
 
@@ -241,10 +303,14 @@ class Agent:
             pass
 
     def sac_update(self, replay, n_updates, stats=None, graph=True, stream=None):
-        key = id(replay)
-        if key not in self._replays:
-            self._replays[key] = (replay, replay_struct(replay))
-        rs = self._replays[key][1]
+        """replay: a dict of device tensors (raw frames) or a Ring."""
+        if isinstance(replay, Ring):
+            rs = replay.view
+        else:
+            key = id(replay)
+            if key not in self._replays:
+                self._replays[key] = (replay, replay_struct(replay))
+            rs = self._replays[key][1]
         if stats is None:
             stats = torch.empty((n_updates, L.N_STATS), dtype=torch.float32, device=self.params.device)
         _req(stats, torch.float32, (n_updates, L.N_STATS), "stats")

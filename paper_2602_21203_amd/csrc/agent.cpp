@@ -139,9 +139,13 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   const float lo = hp.log_std_min, hi = hp.log_std_max;
   float* P = g->params;
   float* G = g->grads;
-  SQ_TRY(launch_sample_batch(hp.seed, g->ctr, R->size, B, A, S, R->proprio, R->next_proprio, R->action, R->reward,
-                             R->done, g->idx, g->eps2B, g->S2, g->Arep, g->r, g->dn, st));
-  SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, d.H, d.W, d.C, d.k, g->x, st));
+  SQ_TRY(launch_sample_batch(hp.seed, g->ctr, R->size, R->dev_size, B, A, S, R->proprio, R->next_proprio, R->action,
+                             R->reward, R->done, g->idx, g->eps2B, g->S2, g->Arep, g->r, g->dn, st));
+  // frames squinted at insertion are the k = 1 squint of the stored block means
+  if (R->squinted)
+    SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, net.side, net.side, d.C, 1, g->x, st));
+  else
+    SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, d.H, d.W, d.C, d.k, g->x, st));
   SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st));
   const float* feat = g->enc.h[d.n_conv - 1];
   SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
@@ -188,6 +192,10 @@ static int check_replay(const sq_agent* g, const sq_replay* R) {
   }
   if (R->size <= 0 || R->size > R->capacity) {
     set_error("replay size %d outside (0, capacity=%d]", R->size, R->capacity);
+    return SQ_EINVAL;
+  }
+  if (R->squinted != 0 && R->squinted != 1) {
+    set_error("replay squinted flag %d is neither 0 nor 1", R->squinted);
     return SQ_EINVAL;
   }
   return SQ_OK;

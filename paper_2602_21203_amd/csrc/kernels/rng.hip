@@ -1,5 +1,6 @@
 // Replay-batch sampling and Gaussian policy noise from Philox4x32-10.
-//   replay index  idx[b] = mulhi32(w0, size), counter (u, 0, b, 0), key = seed
+//   replay index  idx[b] = mulhi32(w0, size), counter (u, 0, b, 0), key = seed;
+//                 size is read on the device when the replay is a growing ring
 //   noise         stream s, element e: Box-Muller on (w0, w1) of counter (u, s, e, 0);
 //                 s = 2 feeds the actor sample at s_t, s = 1 the target sample at s_{t+1}
 //   act() noise   element e of a request: counter (e, 3, id_lo, id_hi)
@@ -14,7 +15,8 @@ namespace sq {
 // is as wide as the batch's fields.  eps2B rows [0, B) = stream 2, rows [B, 2B) =
 // stream 1.
 __global__ __launch_bounds__(256) void k_sample_batch(unsigned k0, unsigned k1, const int* __restrict__ ctr,
-                                                      int size, int B, int A, int S,
+                                                      int size, const int* __restrict__ dev_size, int B, int A,
+                                                      int S,
                                                       const float* __restrict__ proprio,
                                                       const float* __restrict__ next_proprio,
                                                       const float* __restrict__ action,
@@ -36,7 +38,7 @@ __global__ __launch_bounds__(256) void k_sample_batch(unsigned k0, unsigned k1, 
     return;
   }
   const P4 w = philox10(P4{u, 0u, (unsigned)b, 0u}, k0, k1);
-  const int row = (int)__umulhi(w.x, (unsigned)size);
+  const int row = (int)__umulhi(w.x, (unsigned)(dev_size ? *dev_size : size));
   if (it < A) {
     Arep[(long long)b * A + it] = action[(long long)row * A + it];
   } else if (it == 3 * A) {
@@ -51,13 +53,13 @@ __global__ __launch_bounds__(256) void k_sample_batch(unsigned k0, unsigned k1, 
   }
 }
 
-int launch_sample_batch(unsigned long long seed, const int* ctr, int size, int B, int A, int S,
+int launch_sample_batch(unsigned long long seed, const int* ctr, int size, const int* dev_size, int B, int A, int S,
                         const float* proprio, const float* next_proprio, const float* action,
                         const float* reward, const uint8_t* done, int* idx, float* eps2B, float* S2,
                         float* Arep, float* r, float* d, hipStream_t st) {
   const long long items = (long long)B * (2 * S + 3 * A + 2);
   k_sample_batch<<<(unsigned)((items + 255) / 256), 256, 0, st>>>((unsigned)seed, (unsigned)(seed >> 32), ctr, size,
-                                                                  B, A, S, proprio, next_proprio, action, reward,
+                                                                  dev_size, B, A, S, proprio, next_proprio, action, reward,
                                                                   done, idx, eps2B, S2, Arep, r, d);
   return launch_status("sample_batch");
 }

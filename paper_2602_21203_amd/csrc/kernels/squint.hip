@@ -1,38 +1,60 @@
 // Resolution squinting: gather replay frames and take k x k block means.
 // A workgroup owns `ry` output rows of one image: it streams the k*ry source pixel
 // rows (contiguous in the HWC frame) into LDS with 16-byte loads, then each thread
-// forms exact integer block sums from LDS and writes x = S / (255 k^2) - 0.5.
+// forms exact integer block sums S from LDS and emits either the network input
+// x = S / (255 k^2) - 0.5 (CHW, FP32 or bfloat16) or, when frames are squinted at
+// insertion, the uint8 block mean (HWC, nearest with ties to even) into a FIFO ring.
 #include "../common.h"
 #include "bf16.h"
 
 namespace sq {
+
+// rounded block mean: nearest integer to s / kk, ties to even (s >= 0)
+__device__ __forceinline__ unsigned mean_u8(int s, int kk) {
+  const int q = s / kk, r = s - q * kk;
+  return (unsigned)(q + ((2 * r > kk) || (2 * r == kk && (q & 1))));
+}
+
+// one output value of image img at channel c, pixel (y, x) of the side x side grid
+__device__ __forceinline__ void emit(const SqDst& d, int img, int nsplit, int C, int side, int c, int y, int x, int s,
+                                     int kk, float scale) {
+  if (d.mode == kSqU8) {
+    const bool second = img >= nsplit;
+    const int row = (d.pos + (second ? img - nsplit : img)) % d.cap;
+    uint8_t* base = reinterpret_cast<uint8_t*>(second ? d.out1 : d.out) + (long long)row * side * side * C;
+    base[((long long)y * side + x) * C + c] = (uint8_t)mean_u8(s, kk);
+    return;
+  }
+  const float v = (float)s / scale - 0.5f;
+  const long long oi = (long long)img * d.row_stride + ((long long)c * side + y) * side + x;
+  if (d.mode == kSqBF16)
+    reinterpret_cast<uint16_t*>(d.out)[oi] = bf16_bits(v);
+  else
+    reinterpret_cast<float*>(d.out)[oi] = v;
+}
+
+__device__ __forceinline__ const uint8_t* source_row(const uint8_t* src0, const uint8_t* src1, const int* idx,
+                                                     const uint8_t* const* row_ptrs, int nsplit, int img,
+                                                     long long frame_bytes) {
+  if (row_ptrs) return row_ptrs[img];
+  if (img < nsplit) return src0 + (idx ? idx[img] : img) * frame_bytes;
+  return src1 + (idx ? idx[img - nsplit] : img - nsplit) * frame_bytes;
+}
 
 constexpr int kSquintThreads = 256;
 constexpr int kSquintLdsBytes = 16384;
 
 __global__ __launch_bounds__(kSquintThreads) void k_squint(
     const uint8_t* __restrict__ src0, const uint8_t* __restrict__ src1, const int* __restrict__ idx,
-    const uint8_t* const* __restrict__ row_ptrs, int nsplit, int H, int W, int C, int k, int side, int ry, int vec16, int bf16_out, void* __restrict__ out,
-    long long out_row_stride) {
+    const uint8_t* const* __restrict__ row_ptrs, int nsplit, int H, int W, int C, int k, int side, int ry, int vec16,
+    SqDst dst) {
   __shared__ __attribute__((aligned(16))) uint8_t tile[kSquintLdsBytes];
   const int img = blockIdx.y;
   const int y0 = blockIdx.x * ry;
-  const uint8_t* src;
-  long long row;
-  if (row_ptrs) {
-    src = row_ptrs[img];
-    row = 0;
-  } else if (img < nsplit) {
-    src = src0;
-    row = idx ? idx[img] : img;
-  } else {
-    src = src1;
-    row = idx[img - nsplit];
-  }
   const long long frame_bytes = (long long)H * W * C;
   const long long chunk_off = (long long)y0 * k * W * C;
   const int chunk_bytes = ry * k * W * C;
-  const uint8_t* g = src + row * frame_bytes + chunk_off;
+  const uint8_t* g = source_row(src0, src1, idx, row_ptrs, nsplit, img, frame_bytes) + chunk_off;
   if (vec16) {
     const uint4* g4 = reinterpret_cast<const uint4*>(g);
     uint4* t4 = reinterpret_cast<uint4*>(tile);
@@ -52,12 +74,7 @@ __global__ __launch_bounds__(kSquintThreads) void k_squint(
       const uint8_t* p = tile + ((yl * k + i) * W + x * k) * C + c;
       for (int j = 0; j < k; ++j) s += p[j * C];
     }
-    const float v = (float)s / scale - 0.5f;
-    const long long oi = (long long)img * out_row_stride + ((long long)c * side + y0 + yl) * side + x;
-    if (bf16_out)
-      reinterpret_cast<uint16_t*>(out)[oi] = bf16_bits(v);
-    else
-      reinterpret_cast<float*>(out)[oi] = v;
+    emit(dst, img, nsplit, C, side, c, y0 + yl, x, s, k * k, scale);
   }
 }
 
@@ -71,29 +88,18 @@ template <int C, int K>
 __global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ src0,
                                                    const uint8_t* __restrict__ src1, const int* __restrict__ idx,
                                                    const uint8_t* const* __restrict__ row_ptrs, int nsplit, int W,
-                                                   int ry, int bf16_out, void* __restrict__ out) {
+                                                   int ry, SqDst dst) {
   constexpr int SIDE = 16;
   constexpr int SEG = K * C;          // bytes of one block row
   static_assert(SEG % 4 == 0, "32-bit block rows");
   extern __shared__ __attribute__((aligned(16))) uint8_t tile[];
   const int img = blockIdx.y;
   const int y0 = blockIdx.x * ry;
-  const uint8_t* src;
-  long long row;
-  if (row_ptrs) {
-    src = row_ptrs[img];
-    row = 0;
-  } else if (img < nsplit) {
-    src = src0;
-    row = idx ? idx[img] : img;
-  } else {
-    src = src1;
-    row = idx[img - nsplit];
-  }
   const int row_bytes = W * C;            // one source pixel row
   const long long frame_bytes = (long long)row_bytes * W;
   const int chunk16 = ry * K * row_bytes / 16;
-  const uint4* g4 = reinterpret_cast<const uint4*>(src + row * frame_bytes + (long long)y0 * K * row_bytes);
+  const uint4* g4 = reinterpret_cast<const uint4*>(source_row(src0, src1, idx, row_ptrs, nsplit, img, frame_bytes) +
+                                                   (long long)y0 * K * row_bytes);
   uint4* t4 = reinterpret_cast<uint4*>(tile);
   int i = threadIdx.x;
   for (; i + 3 * 256 < chunk16; i += 4 * 256) {
@@ -122,21 +128,14 @@ __global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ s
   }
   const float scale = (float)(255 * K * K);
 #pragma unroll
-  for (int c = 0; c < C; ++c) {
-    const float v = (float)sum[c] / scale - 0.5f;
-    const long long oi = (long long)img * C * SIDE * SIDE + ((long long)c * SIDE + y0 + yl) * SIDE + x;
-    if (bf16_out)
-      reinterpret_cast<uint16_t*>(out)[oi] = bf16_bits(v);
-    else
-      reinterpret_cast<float*>(out)[oi] = v;
-  }
+  for (int c = 0; c < C; ++c) emit(dst, img, nsplit, C, SIDE, c, y0 + yl, x, sum[c], K * K, scale);
 }
 
 template <int C, int K>
 static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
-                   int n, int H, int W, int Cr, int kr, int bf16_out, void* out, long long out_row_stride,
-                   hipStream_t st) {
-  if (Cr != C || kr != K || H / K != 16 || out_row_stride != (long long)C * 256) return false;
+                   int n, int H, int W, int Cr, int kr, const SqDst& dst, hipStream_t st) {
+  if (Cr != C || kr != K || H / K != 16 || W != H) return false;
+  if (dst.mode != kSqU8 && dst.row_stride != (long long)C * 256) return false;
   const long long frame_bytes = (long long)H * W * C;
   if (frame_bytes % 16 != 0 || (uintptr_t)s0 % 16 != 0 || (s1 && (uintptr_t)s1 % 16 != 0)) return false;
   const int row_bytes = K * W * C;
@@ -144,7 +143,7 @@ static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const u
   while (ry > 1 && ry * row_bytes > 40960) ry /= 2;
   if ((ry * row_bytes) % 16 != 0) return false;
   dim3 grid(16 / ry, n);
-  k_squint_ck<C, K><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, bf16_out, out);
+  k_squint_ck<C, K><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, dst);
   return true;
 }
 
@@ -165,44 +164,50 @@ int squint_ok(int H, int W, int C, int k) {
 }
 
 static int launch(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
-                  int n, int H, int W, int C, int k, int bf16_out, void* out, long long out_row_stride,
-                  hipStream_t st) {
+                  int n, int H, int W, int C, int k, const SqDst& dst, hipStream_t st) {
   // per-row pointers (serving) are only known on the device and may be unaligned:
   // they take the generic byte path
-  if (rows == nullptr &&
-      (try_ck<9, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, bf16_out, out, out_row_stride, st) ||
-       try_ck<9, 8>(s0, s1, idx, rows, nsplit, n, H, W, C, k, bf16_out, out, out_row_stride, st) ||
-       try_ck<3, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, bf16_out, out, out_row_stride, st)))
+  if (rows == nullptr && (try_ck<9, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
+                          try_ck<9, 8>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
+                          try_ck<3, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st)))
     return launch_status("squint_ck");
   const int side = H / k;
   const int ry = squint_rows_per_chunk(W, C, k, side);
   const long long chunk_bytes = (long long)ry * k * W * C;
   const long long frame_bytes = (long long)H * W * C;
-  // per-row pointers (serving) are only known on the device: take the byte path
   const int vec16 = rows == nullptr && (chunk_bytes % 16 == 0) && (frame_bytes % 16 == 0) &&
                     ((uintptr_t)s0 % 16 == 0) && (s1 == nullptr || (uintptr_t)s1 % 16 == 0);
   dim3 grid(side / ry, n);
-  k_squint<<<grid, kSquintThreads, 0, st>>>(s0, s1, idx, rows, nsplit, H, W, C, k, side, ry, vec16, bf16_out,
-                                            out, out_row_stride);
+  k_squint<<<grid, kSquintThreads, 0, st>>>(s0, s1, idx, rows, nsplit, H, W, C, k, side, ry, vec16, dst);
   return launch_status("squint");
 }
 
 int launch_squint(const uint8_t* frames, const int* idx, int n, int H, int W, int C, int k, int bf16_out,
                   void* out, long long out_row_stride, hipStream_t st) {
   if (n == 0) return SQ_OK;
-  return launch(frames, nullptr, idx, nullptr, n, n, H, W, C, k, bf16_out, out, out_row_stride, st);
+  const SqDst dst{bf16_out ? kSqBF16 : kSqF32, out, nullptr, out_row_stride, 0, 1};
+  return launch(frames, nullptr, idx, nullptr, n, n, H, W, C, k, dst, st);
 }
 
 int launch_squint_pair(const uint8_t* obs, const uint8_t* next_obs, const int* idx, int B, int H, int W, int C,
                        int k, float* out, hipStream_t st) {
   const int side = H / k;
-  return launch(obs, next_obs, idx, nullptr, B, 2 * B, H, W, C, k, 0, out, (long long)C * side * side, st);
+  const SqDst dst{kSqF32, out, nullptr, (long long)C * side * side, 0, 1};
+  return launch(obs, next_obs, idx, nullptr, B, 2 * B, H, W, C, k, dst, st);
 }
 
 int launch_squint_rows(const uint8_t* const* rows, int n, int H, int W, int C, int k, float* out, hipStream_t st) {
   if (n == 0) return SQ_OK;
   const int side = H / k;
-  return launch(nullptr, nullptr, nullptr, rows, n, n, H, W, C, k, 0, out, (long long)C * side * side, st);
+  const SqDst dst{kSqF32, out, nullptr, (long long)C * side * side, 0, 1};
+  return launch(nullptr, nullptr, nullptr, rows, n, n, H, W, C, k, dst, st);
+}
+
+int launch_squint_insert(const uint8_t* obs, const uint8_t* next_obs, int n, int H, int W, int C, int k,
+                         uint8_t* ring_obs, uint8_t* ring_next, int pos, int cap, hipStream_t st) {
+  if (n == 0) return SQ_OK;
+  const SqDst dst{kSqU8, ring_obs, ring_next, 0, pos, cap};
+  return launch(obs, next_obs, nullptr, nullptr, n, 2 * n, H, W, C, k, dst, st);
 }
 
 }  // namespace sq

@@ -61,6 +61,11 @@ def test_invalid_dims_are_rejected_without_work():
     assert _lib.LIB.sac_update(None, None, 1, None, None) == _lib.SQ_EINVAL
     assert _lib.LIB.act(None, None, None, 1, 0, 0, None, None) == _lib.SQ_EINVAL
     assert b"NULL" in _lib.LIB.sq_last_error() or b"agent" in _lib.LIB.sq_last_error()
+    h = ctypes.c_void_p()
+    assert _lib.LIB.sq_ring_create(ctypes.byref(d), 0, ctypes.byref(h)) == _lib.SQ_EINVAL
+    assert _lib.LIB.sq_ring_insert(None, None, None, None, None, None, None, None, 1, None) == _lib.SQ_EINVAL
+    assert _lib.LIB.sq_ring_view(None, None) == _lib.SQ_EINVAL
+    assert _lib.LIB.sq_ring_copy_out(None, 0, 0, 1, None, None) == _lib.SQ_EINVAL
 
 
 def test_workspace_sizes_grow_with_rows():
