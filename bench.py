@@ -38,6 +38,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision timing")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--no-insert", action="store_true", help="skip the insert-path (squint at insertion) timing")
     ap.add_argument("--sweep", action="store_true",
                     help="UTD sweep {1,4,8,16} at batch 1024 on 128x128x9 frames (prints one JSON line)")
     ap.add_argument("--serve", action="store_true",
@@ -157,6 +158,55 @@ def gemm_kernel_time(prec, reps):
     b = torch.rand((2, 512), generator=g, device="cuda")
     C = torch.empty((2, 512, 512), device="cuda")
     return graph_time(lambda: api.gemm(prec, A, W, C, bias=b), reps)
+
+
+def insert_path(cfg, rep, agent, a, n_env=1024):
+    """The insert path: squint at insertion of n_env transitions per call (one
+    environment step of n_env parallel envs) into a device FIFO ring of uint8
+    block means, then UTD updates sampling the ring instead of raw frames."""
+    import torch
+
+    from paper_2602_21203_amd import api
+    cap = a.capacity
+    n_env = min(n_env, cap)
+    ring = api.Ring(cfg, cap)
+    names = ("obs", "next_obs", "proprio", "next_proprio", "action", "reward", "done")
+    chunks = max(1, cap // n_env)
+
+    def insert(i):
+        lo = (i % chunks) * n_env
+        ring.insert(*(rep[f][lo:lo + n_env] for f in names), stream=agent.stream)
+
+    for i in range(4):
+        insert(i)
+    torch.cuda.synchronize()
+    calls = 2 * chunks
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(agent.stream)
+    for i in range(calls):
+        insert(i)
+    e1.record(agent.stream)
+    torch.cuda.synchronize()
+    t_call = e0.elapsed_time(e1) / 1e3 / calls
+    P, A = cfg["proprio"], cfg["action"]
+    frame_bytes = 2 * (cfg["H"] * cfg["W"] * cfg["C"] + 16 * 16 * cfg["C"])
+    field_bytes = 2 * (4 * (2 * P + A + 1) + 1)
+    per_call = n_env * (frame_bytes + field_bytes)
+    ach = per_call / t_call / 1e9
+    wall, gpu, _ = time_updates(agent, ring, a.utd, a.steps, a.warmup)
+    out = {"transitions_per_insert": n_env, "ring_rows": cap,
+           "insert_transitions_per_s": round(n_env / t_call, 1), "insert_us": round(t_call * 1e6, 3),
+           "roofline_insert": {"kernel": "k_squint_ck<9,4> in uint8-ring mode (one insert call: frames and fields)",
+                               "bound": "hbm", "achieved": round(ach, 1), "peak": 8000.0, "unit": "GB/s",
+                               "frac": round(ach / 8000.0, 4),
+                               "traffic": measured_traffic("squint_insert_1024",
+                                                           "paper_2602_21203_amd/csrc/kernels/squint.hip")
+                               if n_env == 1024 else None,
+                               "algorithmic_bytes": per_call},
+           "ring_updates_per_s": round(a.utd * a.steps / wall, 2),
+           "ring_gpu_event_updates_per_s": round(a.utd * a.steps / gpu, 2)}
+    ring.close()
+    return out
 
 
 def serve_latency(agent, cfg, n_req, seed=3):
@@ -412,6 +462,8 @@ def main():
         dst = src.clone()
         torch.cuda.synchronize()
         del src, dst
+    if not a.no_insert:
+        result["insert_path"] = insert_path(cfg, rep, agent, a)
     if a.serve_requests > 0:
         result["act_serving"] = serve_latency(agent, cfg, a.serve_requests)
     agent.close()

@@ -114,19 +114,26 @@ int launch_squint_pair(const uint8_t* obs, const uint8_t* next_obs, const int* i
 
 // serving: frames gathered through per-row pointers
 int launch_squint_rows(const uint8_t* const* rows, int n, int H, int W, int C, int k, float* out, hipStream_t st);
-// squint at insertion: n transitions' obs and next_obs [n, H, W, C] -> uint8 block
-// means [side, side, C] in rows (pos + i) % cap of ring_obs / ring_next
-int launch_squint_insert(const uint8_t* obs, const uint8_t* next_obs, int n, int H, int W, int C, int k,
-                         uint8_t* ring_obs, uint8_t* ring_next, int pos, int cap, hipStream_t st);
+// the small fields of the transitions a squint-at-insertion launch stores, and
+// the ring's device counters {pos, size} after the insertion
+struct RingRows {
+  const float *proprio, *next_proprio, *action, *reward;
+  const uint8_t* done;
+  float *r_proprio, *r_next, *r_action, *r_reward;
+  uint8_t* r_done;
+  int P, A;
+  int* ctr;
+  int new_pos, new_size;
+};
 // where a squint launch writes (see squint.hip)
 enum { kSqF32 = 0, kSqBF16 = 1, kSqU8 = 2 };
-struct SqDst { int mode; void* out; void* out1; long long row_stride; int pos, cap; };
-// ring.hip: the small fields of n transitions into ring rows (pos + i) % cap, and
-// the ring's device counters {pos, size} set to the values after this insertion
-int launch_ring_fields(const float* proprio, const float* next_proprio, const float* action, const float* reward,
-                       const uint8_t* done, int n, int P, int A, float* r_proprio, float* r_next_proprio,
-                       float* r_action, float* r_reward, uint8_t* r_done, int pos, int cap, int* ctr, int new_pos,
-                       int new_size, hipStream_t st);
+struct SqDst { int mode; void* out; void* out1; long long row_stride; int pos, cap; RingRows f; };
+// squint at insertion: n transitions' obs and next_obs [n, H, W, C] -> uint8 block
+// means [side, side, C] in rows (pos + i) % cap of ring_obs / ring_next, and the
+// transitions' small fields into the same rows (f)
+int launch_squint_insert(const uint8_t* obs, const uint8_t* next_obs, int n, int H, int W, int C, int k,
+                         uint8_t* ring_obs, uint8_t* ring_next, int pos, int cap, const RingRows& f,
+                         hipStream_t st);
 // serve.hip: per-row gather / scatter of small vectors, per-row act noise
 int gather_rows(const float* const* src, int width, int n, float* dst, hipStream_t st);
 int scatter_rows(const float* src, int width, int n, float* const* dst, hipStream_t st);

@@ -33,6 +33,25 @@ __device__ __forceinline__ void emit(const SqDst& d, int img, int nsplit, int C,
     reinterpret_cast<float*>(d.out)[oi] = v;
 }
 
+// a transition's small fields into its ring row, by the first workgroup of its
+// obs image; image 0 also stores the ring's counters (nothing in the launch reads them)
+__device__ __forceinline__ void ring_fields(const SqDst& d, int i) {
+  const RingRows& f = d.f;
+  const int W = 2 * f.P + f.A + 2;
+  const long long row = (d.pos + i) % d.cap;
+  for (int it = threadIdx.x; it < W; it += blockDim.x) {
+    if (it < f.P) f.r_proprio[row * f.P + it] = f.proprio[(long long)i * f.P + it];
+    else if (it < 2 * f.P) f.r_next[row * f.P + it - f.P] = f.next_proprio[(long long)i * f.P + it - f.P];
+    else if (it < 2 * f.P + f.A) f.r_action[row * f.A + it - 2 * f.P] = f.action[(long long)i * f.A + it - 2 * f.P];
+    else if (it == 2 * f.P + f.A) f.r_reward[row] = f.reward[i];
+    else f.r_done[row] = f.done[i];
+  }
+  if (i == 0 && threadIdx.x == 0) {
+    f.ctr[0] = f.new_pos;
+    f.ctr[1] = f.new_size;
+  }
+}
+
 __device__ __forceinline__ const uint8_t* source_row(const uint8_t* src0, const uint8_t* src1, const int* idx,
                                                      const uint8_t* const* row_ptrs, int nsplit, int img,
                                                      long long frame_bytes) {
@@ -62,6 +81,7 @@ __global__ __launch_bounds__(kSquintThreads) void k_squint(
   } else {
     for (int i = threadIdx.x; i < chunk_bytes; i += kSquintThreads) tile[i] = g[i];
   }
+  if (dst.mode == kSqU8 && blockIdx.x == 0 && img < nsplit) ring_fields(dst, img);
   __syncthreads();
   const int n_out = C * ry * side;
   const float scale = (float)(255 * k * k);
@@ -84,6 +104,11 @@ __global__ __launch_bounds__(kSquintThreads) void k_squint(
 // batched 16-byte loads; each thread then reads its K x (K*C)-byte block rows as
 // 32-bit words (K*C % 4 == 0) and adds each byte into its channel's sum, with
 // every index known at compile time.
+typedef unsigned u4v __attribute__((ext_vector_type(4)));   // 16-byte load / store unit
+
+constexpr int kSquintCkLds = 40960;                 // LDS bytes of one k_squint_ck workgroup, at most
+constexpr int kSquintCkMax16 = kSquintCkLds / 16;   // its 16-byte loads (a multiple of 256)
+
 template <int C, int K>
 __global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ src0,
                                                    const uint8_t* __restrict__ src1, const int* __restrict__ idx,
@@ -98,18 +123,23 @@ __global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ s
   const int row_bytes = W * C;            // one source pixel row
   const long long frame_bytes = (long long)row_bytes * W;
   const int chunk16 = ry * K * row_bytes / 16;
-  const uint4* g4 = reinterpret_cast<const uint4*>(source_row(src0, src1, idx, row_ptrs, nsplit, img, frame_bytes) +
-                                                   (long long)y0 * K * row_bytes);
-  uint4* t4 = reinterpret_cast<uint4*>(tile);
-  int i = threadIdx.x;
-  for (; i + 3 * 256 < chunk16; i += 4 * 256) {
-    const uint4 a = g4[i], b = g4[i + 256], c = g4[i + 512], d = g4[i + 768];
-    t4[i] = a;
-    t4[i + 256] = b;
-    t4[i + 512] = c;
-    t4[i + 768] = d;
+  const u4v* g4 = reinterpret_cast<const u4v*>(source_row(src0, src1, idx, row_ptrs, nsplit, img, frame_bytes) +
+                                                 (long long)y0 * K * row_bytes);
+  u4v* t4 = reinterpret_cast<u4v*>(tile);
+  // every load of the chunk is in flight before the first LDS store
+  u4v v[kSquintCkMax16 / 256];
+#pragma unroll
+  for (int j = 0; j < kSquintCkMax16 / 256; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    if (i < chunk16) v[j] = g4[i];
   }
-  for (; i < chunk16; i += 256) t4[i] = g4[i];
+  // a ring insertion's small fields move while the frame loads are in flight
+  if (dst.mode == kSqU8 && blockIdx.x == 0 && img < nsplit) ring_fields(dst, img);
+#pragma unroll
+  for (int j = 0; j < kSquintCkMax16 / 256; ++j) {
+    const int i = threadIdx.x + 256 * j;
+    if (i < chunk16) t4[i] = v[j];
+  }
   __syncthreads();
   const int yl = threadIdx.x / SIDE, x = threadIdx.x % SIDE;
   if (yl >= ry) return;
@@ -131,6 +161,36 @@ __global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ s
   for (int c = 0; c < C; ++c) emit(dst, img, nsplit, C, SIDE, c, y0 + yl, x, sum[c], K * K, scale);
 }
 
+// Frames already squinted at insertion (uint8 block means, [16, 16, C]): the
+// k = 1 squint, x = q / 255 - 0.5.  One workgroup per image stages its bytes in
+// LDS with 16-byte loads; thread p then emits pixel p of every channel (CHW
+// stores, consecutive threads on consecutive pixels).
+template <int C>
+__global__ __launch_bounds__(256) void k_stored_ck(const uint8_t* __restrict__ src0,
+                                                   const uint8_t* __restrict__ src1, const int* __restrict__ idx,
+                                                   int nsplit, SqDst dst) {
+  constexpr int SIDE = 16, BYTES = SIDE * SIDE * C;
+  static_assert(BYTES % 16 == 0, "16-byte staging");
+  __shared__ __attribute__((aligned(16))) uint8_t tile[BYTES];
+  const int img = blockIdx.x;
+  const uint4* g4 = reinterpret_cast<const uint4*>(source_row(src0, src1, idx, nullptr, nsplit, img, BYTES));
+  if (threadIdx.x < BYTES / 16) reinterpret_cast<uint4*>(tile)[threadIdx.x] = g4[threadIdx.x];
+  __syncthreads();
+  const int p = threadIdx.x, y = p / SIDE, x = p % SIDE;
+#pragma unroll
+  for (int c = 0; c < C; ++c) emit(dst, img, nsplit, C, SIDE, c, y, x, tile[p * C + c], 1, 255.0f);
+}
+
+template <int C>
+static bool try_stored(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
+                       int n, int H, int W, int Cr, int k, const SqDst& dst, hipStream_t st) {
+  if (rows != nullptr || Cr != C || k != 1 || H != 16 || W != 16 || dst.mode == kSqU8) return false;
+  if (dst.row_stride != (long long)C * 256 || (uintptr_t)s0 % 16 != 0 || (s1 && (uintptr_t)s1 % 16 != 0))
+    return false;
+  k_stored_ck<C><<<n, 256, 0, st>>>(s0, s1, idx, nsplit, dst);
+  return true;
+}
+
 template <int C, int K>
 static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
                    int n, int H, int W, int Cr, int kr, const SqDst& dst, hipStream_t st) {
@@ -140,7 +200,8 @@ static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const u
   if (frame_bytes % 16 != 0 || (uintptr_t)s0 % 16 != 0 || (s1 && (uintptr_t)s1 % 16 != 0)) return false;
   const int row_bytes = K * W * C;
   int ry = 16;
-  while (ry > 1 && ry * row_bytes > 40960) ry /= 2;
+  while (ry > 1 && ry * row_bytes > kSquintCkLds) ry /= 2;
+  if (ry * row_bytes > kSquintCkLds) return false;
   if ((ry * row_bytes) % 16 != 0) return false;
   dim3 grid(16 / ry, n);
   k_squint_ck<C, K><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, dst);
@@ -171,6 +232,9 @@ static int launch(const uint8_t* s0, const uint8_t* s1, const int* idx, const ui
                           try_ck<9, 8>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
                           try_ck<3, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st)))
     return launch_status("squint_ck");
+  if (try_stored<9>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
+      try_stored<3>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st))
+    return launch_status("squint_stored");
   const int side = H / k;
   const int ry = squint_rows_per_chunk(W, C, k, side);
   const long long chunk_bytes = (long long)ry * k * W * C;
@@ -185,28 +249,29 @@ static int launch(const uint8_t* s0, const uint8_t* s1, const int* idx, const ui
 int launch_squint(const uint8_t* frames, const int* idx, int n, int H, int W, int C, int k, int bf16_out,
                   void* out, long long out_row_stride, hipStream_t st) {
   if (n == 0) return SQ_OK;
-  const SqDst dst{bf16_out ? kSqBF16 : kSqF32, out, nullptr, out_row_stride, 0, 1};
+  const SqDst dst{bf16_out ? kSqBF16 : kSqF32, out, nullptr, out_row_stride, 0, 1, {}};
   return launch(frames, nullptr, idx, nullptr, n, n, H, W, C, k, dst, st);
 }
 
 int launch_squint_pair(const uint8_t* obs, const uint8_t* next_obs, const int* idx, int B, int H, int W, int C,
                        int k, float* out, hipStream_t st) {
   const int side = H / k;
-  const SqDst dst{kSqF32, out, nullptr, (long long)C * side * side, 0, 1};
+  const SqDst dst{kSqF32, out, nullptr, (long long)C * side * side, 0, 1, {}};
   return launch(obs, next_obs, idx, nullptr, B, 2 * B, H, W, C, k, dst, st);
 }
 
 int launch_squint_rows(const uint8_t* const* rows, int n, int H, int W, int C, int k, float* out, hipStream_t st) {
   if (n == 0) return SQ_OK;
   const int side = H / k;
-  const SqDst dst{kSqF32, out, nullptr, (long long)C * side * side, 0, 1};
+  const SqDst dst{kSqF32, out, nullptr, (long long)C * side * side, 0, 1, {}};
   return launch(nullptr, nullptr, nullptr, rows, n, n, H, W, C, k, dst, st);
 }
 
 int launch_squint_insert(const uint8_t* obs, const uint8_t* next_obs, int n, int H, int W, int C, int k,
-                         uint8_t* ring_obs, uint8_t* ring_next, int pos, int cap, hipStream_t st) {
+                         uint8_t* ring_obs, uint8_t* ring_next, int pos, int cap, const RingRows& f,
+                         hipStream_t st) {
   if (n == 0) return SQ_OK;
-  const SqDst dst{kSqU8, ring_obs, ring_next, 0, pos, cap};
+  const SqDst dst{kSqU8, ring_obs, ring_next, 0, pos, cap, f};
   return launch(obs, next_obs, nullptr, nullptr, n, 2 * n, H, W, C, k, dst, st);
 }
 

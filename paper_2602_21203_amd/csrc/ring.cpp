@@ -3,6 +3,8 @@
 // as it arrives), and stored as uint8 block means at the squinted size, so an
 // update gathers (H/k)(W/k)C bytes per frame instead of H W C.
 //
+// One launch per insertion: the squint kernel's uint8 mode writes the frames,
+// and the first workgroup of each transition's obs image moves its small fields.
 // The write position and row count live on the host (insertions are ordered
 // by their stream); each insertion also stores the new row count in a device
 // int that the update's sampler reads, so a captured update graph keeps
@@ -116,10 +118,9 @@ int sq_ring_insert(sq_ring* r, const uint8_t* obs, const uint8_t* next_obs, cons
   if (n == 0) return SQ_OK;
   const int new_pos = (int)(((long long)r->pos + n) % r->cap);
   const int new_size = (int)((long long)r->size + n < r->cap ? r->size + n : r->cap);
-  SQ_TRY(launch_squint_insert(obs, next_obs, n, d.H, d.W, d.C, d.k, r->obs, r->next_obs, r->pos, r->cap, st));
-  SQ_TRY(launch_ring_fields(proprio, next_proprio, action, reward, done, n, d.proprio, d.action, r->proprio,
-                            r->next_proprio, r->action, r->reward, r->done, r->pos, r->cap, r->ctr, new_pos,
-                            new_size, st));
+  const RingRows f{proprio, next_proprio, action, reward, done, r->proprio, r->next_proprio, r->action, r->reward,
+                   r->done, d.proprio, d.action, r->ctr, new_pos, new_size};
+  SQ_TRY(launch_squint_insert(obs, next_obs, n, d.H, d.W, d.C, d.k, r->obs, r->next_obs, r->pos, r->cap, f, st));
   r->pos = new_pos;
   r->size = new_size;
   return SQ_OK;
