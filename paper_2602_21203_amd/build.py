@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libsquint.so")
 OBJ = os.path.join(HERE, "_build")
 
 SOURCES = [
-    "kernels/rng.hip", "kernels/squint.hip", "kernels/gemm.hip", "kernels/rowops.hip", "kernels/adam.hip", "kernels/serve.hip", "kernels/encoder.hip", "kernels/ring.hip",
+    "kernels/rng.hip", "kernels/squint.hip", "kernels/gemm.hip", "kernels/rowops.hip", "kernels/adam.hip", "kernels/serve.hip", "kernels/encoder.hip",
     "layout.cpp", "ops.cpp", "abi.cpp", "agent.cpp", "server.cpp", "ring.cpp",
 ]
 ARCH = os.environ.get("SQ_OFFLOAD_ARCH", "gfx950")

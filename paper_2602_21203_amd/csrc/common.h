@@ -238,22 +238,17 @@ int tanh_gauss_bwd(const float* save, const float* eps, const float* da, long lo
                    hipStream_t st);
 int mean_action(const float* head, int rows, int A, float* action, hipStream_t st);
 
-int project_target(const float* logits2, int B, int N, float v_min, float v_max, const float* reward,
-                   const float* done, const float* logp_next, const float* log_alpha, float gamma,
-                   float* m, float* tgt_row, hipStream_t st);
 int c51_project_raw(const float* p, const float* reward, const uint8_t* done, const float* bonus,
                     float gamma, int B, int N, float v_min, float v_max, float* m, hipStream_t st);
-// project_target and ce_loss in one launch: logits4 = [online twins | target twins]
+// Per row of the batch: the C51 projection m of the averaged target-twin softmax
+// (bonus -alpha log pi'), tgt_row = E_m[z], then each online twin's cross entropy
+// to m: loss_row, dlogits = (softmax - m) / B, q_row = E[z], and (part, nullable)
+// the head-bias column partials.  logits4 = [online twins | target twins] [4][B][N].
 int target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward, const float* done,
               const float* logp_next, const float* log_alpha, float gamma, float* m, float* tgt_row, float* dlogits2,
               float* loss_row, float* q_row, float* part, hipStream_t st);
-int ce_loss(const float* logits2, const float* m, int B, int N, float v_min, float v_max,
-            float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st);
 int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max, float* dlogits2,
                     float* qa_row, hipStream_t st);
-// scal: [0] alpha before, [1] alpha after, [2] alpha loss, [3] mean(-log pi)
-int alpha_step(const float* logp, int B, float target_entropy, float* log_alpha, float* grad, float* m,
-               float* v, const int* ctr, const sq_hparams* hp, float* scal, hipStream_t st);
 int finish_update(const float* loss_row, const float* q_row, const float* tgt_row, const float* logp,
                   const float* qa_row, const float* scal, int B, int actor_step, int* ctr, float* stats,
                   hipStream_t st);
@@ -277,6 +272,7 @@ struct PackArgs {
 struct GradSeg { long long begin; int H, nrows; const float* part; };
 struct GradSegs { int n; GradSeg s[20]; float* gout; };
 // The temperature step (Alg. 1), run by one extra workgroup of an Adam launch.
+// scal receives [0] alpha before, [1] alpha after, [2] alpha loss, [3] mean(-log pi).
 struct AlphaJob {
   const float* logp; int B; float target_entropy;
   float* log_alpha; float* grad; float* m; float* v; const int* ctr; float* scal;

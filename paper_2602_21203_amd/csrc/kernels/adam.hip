@@ -71,9 +71,6 @@ __device__ void alpha_block(const AlphaJob& j, float lr, float b1, float b2, flo
   j.scal[3] = ent;
 }
 
-__global__ __launch_bounds__(256) void k_alpha(AlphaJob j, float lr, float b1, float b2, float eps) {
-  alpha_block(j, lr, b1, b2, eps);
-}
 
 struct AdamArgs {
   float* p; const float* g; float* m; float* v; long long n;
@@ -215,12 +212,6 @@ int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hpa
   return launch_status("adam");
 }
 
-int alpha_step(const float* logp, int B, float target_entropy, float* log_alpha, float* grad, float* m, float* v,
-               const int* ctr, const sq_hparams* hp, float* scal, hipStream_t st) {
-  const AlphaJob j{logp, B, target_entropy, log_alpha, grad, m, v, ctr, scal};
-  k_alpha<<<1, 256, 0, st>>>(j, hp->lr, hp->beta1, hp->beta2, hp->adam_eps);
-  return launch_status("alpha_step");
-}
 
 // rows of every packed segment; padding columns are written as zero
 __global__ void k_pack(PackArgs pk, const float* __restrict__ params, const float* __restrict__ target,

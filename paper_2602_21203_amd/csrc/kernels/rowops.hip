@@ -496,40 +496,6 @@ __device__ float project_row(const float* p, int N, int lane, float v_min, float
   return wave_sum(mz);
 }
 
-// target path: p = (softmax(l1) + softmax(l2)) / 2, bonus = -exp(log_alpha) * logp_next
-__global__ __launch_bounds__(256) void k_project_target(const float* __restrict__ logits2, int B, int N, float v_min,
-                                                        float v_max, const float* __restrict__ reward,
-                                                        const float* __restrict__ done,
-                                                        const float* __restrict__ logp_next,
-                                                        const float* __restrict__ log_alpha, float gamma,
-                                                        float* __restrict__ m, float* __restrict__ tgt_row) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int b = blockIdx.x * 4 + wave;
-  if (b >= B) return;
-  float p0[kMaxAtomsPerLane], p1[kMaxAtomsPerLane];
-  softmax_row(logits2 + (long long)b * N, N, lane, p0);
-  softmax_row(logits2 + ((long long)B + b) * N, N, lane, p1);
-#pragma unroll
-  for (int t = 0; t < kMaxAtomsPerLane; ++t) p0[t] = 0.5f * (p0[t] + p1[t]);
-  const float alpha = expf(*log_alpha);
-  const float dz = (v_max - v_min) / (float)(N - 1);
-  const float mz = project_row(p0, N, lane, v_min, dz, reward[b], done[b], gamma, -alpha * logp_next[b],
-                               m + (long long)b * N);
-  if (lane == 0 && tgt_row) tgt_row[b] = mz;
-}
-
-int project_target(const float* logits2, int B, int N, float v_min, float v_max, const float* reward,
-                   const float* done, const float* logp_next, const float* log_alpha, float gamma, float* m,
-                   float* tgt_row, hipStream_t st) {
-  if (B <= 0) return SQ_OK;
-  k_project_target<<<cdiv(B, 4), 256, 0, st>>>(logits2, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
-                                               gamma, m, tgt_row);
-  return launch_status("project_target");
-}
-
-// Target projection and cross entropy of one row per wave, T atom slots per lane
-// (N <= 64 T): the same arithmetic as k_project_target followed by k_ce, with the
-// projected target kept in registers between the two.
 // Projection of one row with the hat weights of atom i restricted to the atoms j
 // that reach it.  The projected positions b_j are non-decreasing in j (every step
 // from z_j to b_j is monotone, and so is its rounding), so the j with
@@ -745,92 +711,6 @@ int c51_project_raw(const float* p, const float* reward, const uint8_t* done, co
   if (B <= 0) return SQ_OK;
   k_project<<<cdiv(B, 4), 256, 0, st>>>(p, reward, done, bonus, gamma, B, N, v_min, v_max, m);
   return launch_status("c51_project");
-}
-
-// cross entropy of both twins to m: loss_row[i][b] = -sum_j m_j log softmax_j;
-// dlogits = (softmax - m) / B; q_row[i][b] = sum_j softmax_j z_j.  One row per
-// wave, kLnRowsPerBlock rows per workgroup; with part, the workgroup also writes
-// the column sums of its rows' dlogits (summed over its waves in order) to
-// part[i][blk][N], the output-head bias partials in the LayerNorm-backward blocking.
-__global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_ce(const float* __restrict__ logits2,
-                                                            const float* __restrict__ m, int B, int N, float v_min,
-                                                            float v_max, float* __restrict__ dlogits2,
-                                                            float* __restrict__ loss_row, float* __restrict__ q_row,
-                                                            float* __restrict__ part) {
-  extern __shared__ float shc[];   // [2][kLnRowsPerBlock][N] when part is wanted
-  constexpr int R = kLnRowsPerBlock;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int b = blockIdx.x * R + wave;
-  const float dz = (v_max - v_min) / (float)(N - 1);
-  const float invB = 1.0f / (float)B;
-  for (int i = 0; i < 2; ++i) {
-    float dl[kMaxAtomsPerLane];
-#pragma unroll
-    for (int t = 0; t < kMaxAtomsPerLane; ++t) dl[t] = 0.f;
-    if (b < B) {
-      const float* l = logits2 + ((long long)i * B + b) * N;
-      float mx = -INFINITY;
-#pragma unroll
-      for (int t = 0; t < kMaxAtomsPerLane; ++t) {
-        const int j = lane + 64 * t;
-        if (j < N) mx = fmaxf(mx, l[j]);
-      }
-      mx = wave_max(mx);
-      float e[kMaxAtomsPerLane], s = 0.f;
-#pragma unroll
-      for (int t = 0; t < kMaxAtomsPerLane; ++t) {
-        const int j = lane + 64 * t;
-        e[t] = j < N ? expf(l[j] - mx) : 0.f;
-        s += e[t];
-      }
-      s = wave_sum(s);
-      const float lse = logf(s);
-      float ce = 0.f, q = 0.f;
-#pragma unroll
-      for (int t = 0; t < kMaxAtomsPerLane; ++t) {
-        const int j = lane + 64 * t;
-        if (j < N) {
-          const float mj = m[(long long)b * N + j];
-          const float pj = e[t] / s;
-          ce -= mj * (l[j] - mx - lse);
-          q += pj * (v_min + (float)j * dz);
-          dl[t] = (pj - mj) * invB;
-          dlogits2[((long long)i * B + b) * N + j] = dl[t];
-        }
-      }
-      ce = wave_sum(ce);
-      q = wave_sum(q);
-      if (lane == 0) {
-        loss_row[(long long)i * B + b] = ce;
-        q_row[(long long)i * B + b] = q;
-      }
-    }
-    if (part) {
-#pragma unroll
-      for (int t = 0; t < kMaxAtomsPerLane; ++t) {
-        const int j = lane + 64 * t;
-        if (j < N) shc[(i * R + wave) * N + j] = dl[t];
-      }
-    }
-  }
-  if (!part) return;
-  __syncthreads();
-  const int nblk = gridDim.x;
-  for (int e = threadIdx.x; e < 2 * N; e += 64 * R) {
-    const int i = e / N, j = e - i * N;
-    float sum = shc[(i * R) * N + j];
-    for (int w = 1; w < R; ++w) sum += shc[(i * R + w) * N + j];
-    part[((long long)i * nblk + blockIdx.x) * N + j] = sum;
-  }
-}
-
-int ce_loss(const float* logits2, const float* m, int B, int N, float v_min, float v_max, float* dlogits2,
-            float* loss_row, float* q_row, float* part, hipStream_t st) {
-  if (B <= 0) return SQ_OK;
-  const size_t lds = part ? (size_t)2 * kLnRowsPerBlock * N * sizeof(float) : 0;
-  k_ce<<<cdiv(B, kLnRowsPerBlock), 64 * kLnRowsPerBlock, lds, st>>>(logits2, m, B, N, v_min, v_max, dlogits2,
-                                                                      loss_row, q_row, part);
-  return launch_status("ce_loss");
 }
 
 // actor-loss head: Q_i = sum_j p_ij z_j, dL/dl_ij = -(1 / (2B)) p_ij (z_j - Q_i),
