@@ -34,6 +34,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=512)
     ap.add_argument("--capacity", type=int, default=65536)
     ap.add_argument("--frame", type=int, default=64, help="source frame side (64: k=4, 128: k=8)")
+    ap.add_argument("--side", type=int, default=16, help="squinted side (16; 32 is the higher-resolution variant)")
     ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision timing")
@@ -52,11 +53,21 @@ def parse():
     return ap.parse_args()
 
 
-def cfg_for(frame):
+def cfg_for(frame, side=16):
     c = dict(FULL)
     c["H"] = c["W"] = frame
-    c["k"] = frame // 16
+    c["k"] = frame // side
     return c
+
+
+def side_of(cfg):
+    return cfg["H"] // cfg["k"]
+
+
+def squint_kernel_name(cfg, mode=""):
+    if (cfg["C"], cfg["k"], side_of(cfg)) in ((9, 4, 16), (9, 8, 16), (9, 4, 32)):
+        return f"k_squint_ck<9,{cfg['k']},{side_of(cfg)}>" + mode
+    return "k_squint" + mode
 
 
 def time_updates(agent, rep, utd, steps, warmup):
@@ -112,7 +123,7 @@ def squint_kernel_time(cfg, rep, B, reps):
 
     from paper_2602_21203_amd import api
     idx = torch.randint(0, rep["obs"].shape[0], (2 * B,), dtype=torch.int32, device="cuda")
-    out = torch.empty((2 * B, cfg["C"], 16, 16), dtype=torch.float32, device="cuda")
+    out = torch.empty((2 * B, cfg["C"], side_of(cfg), side_of(cfg)), dtype=torch.float32, device="cuda")
     return graph_time(lambda: api.squint_downsample(cfg, rep["obs"], idx, out=out), reps)
 
 
@@ -189,19 +200,19 @@ def insert_path(cfg, rep, agent, a, n_env=1024):
     torch.cuda.synchronize()
     t_call = e0.elapsed_time(e1) / 1e3 / calls
     P, A = cfg["proprio"], cfg["action"]
-    frame_bytes = 2 * (cfg["H"] * cfg["W"] * cfg["C"] + 16 * 16 * cfg["C"])
+    frame_bytes = 2 * (cfg["H"] * cfg["W"] * cfg["C"] + side_of(cfg) ** 2 * cfg["C"])
     field_bytes = 2 * (4 * (2 * P + A + 1) + 1)
     per_call = n_env * (frame_bytes + field_bytes)
     ach = per_call / t_call / 1e9
     wall, gpu, _ = time_updates(agent, ring, a.utd, a.steps, a.warmup)
     out = {"transitions_per_insert": n_env, "ring_rows": cap,
            "insert_transitions_per_s": round(n_env / t_call, 1), "insert_us": round(t_call * 1e6, 3),
-           "roofline_insert": {"kernel": "k_squint_ck<9,4> in uint8-ring mode (one insert call: frames and fields)",
+           "roofline_insert": {"kernel": squint_kernel_name(cfg, " in uint8-ring mode (one insert call: frames and fields)"),
                                "bound": "hbm", "achieved": round(ach, 1), "peak": 8000.0, "unit": "GB/s",
                                "frac": round(ach / 8000.0, 4),
                                "traffic": measured_traffic("squint_insert_1024",
                                                            "paper_2602_21203_amd/csrc/kernels/squint.hip")
-                               if n_env == 1024 else None,
+                               if (n_env, cfg["H"], side_of(cfg)) == (1024, 64, 16) else None,
                                "algorithmic_bytes": per_call},
            "ring_updates_per_s": round(a.utd * a.steps / wall, 2),
            "ring_gpu_event_updates_per_s": round(a.utd * a.steps / gpu, 2)}
@@ -407,7 +418,7 @@ def main():
     import torch
 
     from paper_2602_21203_amd import _lib, api, synthetic
-    cfg = cfg_for(a.frame)
+    cfg = cfg_for(a.frame, a.side)
     B = a.batch
     torch.cuda.init()
     rep = synthetic.replay(a.capacity, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=0,
@@ -424,7 +435,8 @@ def main():
         "ms_per_step": round(wall / a.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": a.prec, "data": "synthetic",
         "config": {"workload": f"visual SAC update, full network, batch {B}, {a.frame}x{a.frame}x9 uint8 frames "
-                               f"squinted to 16x16, UTD {a.utd} per HIP-graph launch, replay {a.capacity} rows",
+                               f"squinted to {side_of(cfg)}x{side_of(cfg)}, UTD {a.utd} per HIP-graph launch, "
+                               f"replay {a.capacity} rows",
                    "global_batch": B, "utd": a.utd, "precision": a.prec},
         "gpu_event_updates_per_s": round(a.utd * a.steps / gpu, 2),
         "final_stats": {n: float(v) for n, v in zip(_lib.STAT_NAMES, stats[-1])},
@@ -449,13 +461,15 @@ def main():
                           "algorithmic_bytes": 3 * 2 * 512 * 512 * 4 + 2 * 512 * 4}
     # the HBM-bound step: squint gather of 2B frames (frames read + FP32 images written)
     t_k = squint_kernel_time(cfg, rep, B, a.kernel_reps)
-    bytes_per_launch = 2 * B * (cfg["H"] * cfg["W"] * cfg["C"] + cfg["C"] * 16 * 16 * 4)
+    bytes_per_launch = 2 * B * (cfg["H"] * cfg["W"] * cfg["C"] + cfg["C"] * side_of(cfg) ** 2 * 4)
     achieved = bytes_per_launch / t_k / 1e9
-    result["roofline_squint"] = {"kernel": "k_squint_ck<9,4> (gather + 4x4 area sum of 2B frames)", "bound": "hbm",
+    result["roofline_squint"] = {"kernel": squint_kernel_name(cfg, f" (gather + {cfg['k']}x{cfg['k']} area sum of 2B frames)"),
+                                 "bound": "hbm",
                                  "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
                                  "frac": round(achieved / 8000.0, 4),
                                  "traffic": measured_traffic("squint_2B_frames",
-                                                             "paper_2602_21203_amd/csrc/kernels/squint.hip"),
+                                                             "paper_2602_21203_amd/csrc/kernels/squint.hip")
+                                 if (B, cfg["H"], side_of(cfg)) == (512, 64, 16) else None,
                                  "avg_us": round(t_k * 1e6, 3), "algorithmic_bytes": bytes_per_launch}
     if a.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

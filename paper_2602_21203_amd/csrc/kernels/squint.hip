@@ -109,12 +109,12 @@ typedef unsigned u4v __attribute__((ext_vector_type(4)));   // 16-byte load / st
 constexpr int kSquintCkLds = 40960;                 // LDS bytes of one k_squint_ck workgroup, at most
 constexpr int kSquintCkMax16 = kSquintCkLds / 16;   // its 16-byte loads (a multiple of 256)
 
-template <int C, int K>
+template <int C, int K, int SIDE>
 __global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ src0,
                                                    const uint8_t* __restrict__ src1, const int* __restrict__ idx,
                                                    const uint8_t* const* __restrict__ row_ptrs, int nsplit, int W,
                                                    int ry, SqDst dst) {
-  constexpr int SIDE = 16;
+  static_assert(256 % SIDE == 0, "whole output rows per workgroup");
   constexpr int SEG = K * C;          // bytes of one block row
   static_assert(SEG % 4 == 0, "32-bit block rows");
   extern __shared__ __attribute__((aligned(16))) uint8_t tile[];
@@ -191,20 +191,20 @@ static bool try_stored(const uint8_t* s0, const uint8_t* s1, const int* idx, con
   return true;
 }
 
-template <int C, int K>
+template <int C, int K, int SIDE>
 static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
                    int n, int H, int W, int Cr, int kr, const SqDst& dst, hipStream_t st) {
-  if (Cr != C || kr != K || H / K != 16 || W != H) return false;
-  if (dst.mode != kSqU8 && dst.row_stride != (long long)C * 256) return false;
+  if (Cr != C || kr != K || H != SIDE * K || W != H) return false;
+  if (dst.mode != kSqU8 && dst.row_stride != (long long)C * SIDE * SIDE) return false;
   const long long frame_bytes = (long long)H * W * C;
   if (frame_bytes % 16 != 0 || (uintptr_t)s0 % 16 != 0 || (s1 && (uintptr_t)s1 % 16 != 0)) return false;
   const int row_bytes = K * W * C;
-  int ry = 16;
+  int ry = 256 / SIDE < SIDE ? 256 / SIDE : SIDE;   // output rows of one workgroup: one thread per pixel
   while (ry > 1 && ry * row_bytes > kSquintCkLds) ry /= 2;
   if (ry * row_bytes > kSquintCkLds) return false;
   if ((ry * row_bytes) % 16 != 0) return false;
-  dim3 grid(16 / ry, n);
-  k_squint_ck<C, K><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, dst);
+  dim3 grid(SIDE / ry, n);
+  k_squint_ck<C, K, SIDE><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, dst);
   return true;
 }
 
@@ -228,9 +228,10 @@ static int launch(const uint8_t* s0, const uint8_t* s1, const int* idx, const ui
                   int n, int H, int W, int C, int k, const SqDst& dst, hipStream_t st) {
   // per-row pointers (serving) are only known on the device and may be unaligned:
   // they take the generic byte path
-  if (rows == nullptr && (try_ck<9, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
-                          try_ck<9, 8>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
-                          try_ck<3, 4>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st)))
+  if (rows == nullptr && (try_ck<9, 4, 16>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
+                          try_ck<9, 8, 16>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
+                          try_ck<3, 4, 16>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
+                          try_ck<9, 4, 32>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st)))
     return launch_status("squint_ck");
   if (try_stored<9>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st) ||
       try_stored<3>(s0, s1, idx, rows, nsplit, n, H, W, C, k, dst, st))

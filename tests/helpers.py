@@ -15,6 +15,19 @@ GRAD_RTOL = 1e-3                       # gradients: ||d||_2 <= 1e-3 ||ref||_2 pe
 # of the longest chain (the encoder, after the critic backward) therefore carry
 # up to about one bfloat16 unit roundoff of relative difference.
 GRAD_RTOL_BF16 = 2.0 ** -8
+# On 32x32 inputs (the higher-resolution variant) the bfloat16 encoder gradients
+# are chaotic at the 1e-2 level: perturbing the parameters at FP32 rounding level
+# moves the oracle's own bfloat16-mode gradients of conv1.W by 2.4e-2 (B = 128)
+# and 1.5e-2 (B = 512).  Those tensors get 2^-5 there; FP32 stays at GRAD_RTOL.
+GRAD_RTOL_BF16_32 = 2.0 ** -5
+# bfloat16 statistics other than the critic loss: the actor-path statistics (actor
+# and temperature losses, entropy, mean Q and target) follow the sampled action
+# through many rounded operands, and the oracle's own bfloat16 mode moves them by
+# up to 3e-3 of their scale when the parameters are perturbed at FP32 rounding
+# level (2^-24 relative; measured at B = 128 on 32x32 inputs, up to 2e-4 at
+# B = 512 on 16x16).  One bfloat16 unit of their scale is the bar; the critic
+# loss (a mean of positive terms, 1e-5 under the same perturbation) keeps LOSS_RTOL.
+LOSS_RTOL_BF16 = 2.0 ** -8
 
 
 def cfg(name):
@@ -43,11 +56,16 @@ def rel_norm(got, ref):
     return float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30))
 
 
-def assert_loss(got, ref, what="", scale=None):
-    """|got - ref| <= 1e-4 * scale + 1e-6, scale = |ref| unless the statistic is a
+def assert_loss(got, ref, what="", scale=None, rtol=LOSS_RTOL):
+    """|got - ref| <= rtol * scale + 1e-6, scale = |ref| unless the statistic is a
     mean of signed terms, whose magnitude (the oracle's stat_scale) sets the scale."""
     s = abs(ref) if scale is None else max(abs(ref), scale)
-    assert abs(got - ref) <= LOSS_RTOL * s + LOSS_ATOL, f"{what}: got {got!r} ref {ref!r} scale {s!r}"
+    assert abs(got - ref) <= rtol * s + LOSS_ATOL, f"{what}: got {got!r} ref {ref!r} scale {s!r}"
+
+
+def stat_rtol(prec, name):
+    """Tolerance of an update statistic against the oracle in the same precision mode."""
+    return LOSS_RTOL if prec == 0 or name == "critic_loss" else LOSS_RTOL_BF16
 
 
 def assert_grads_per_tensor(got_flat, ref_flat, name, base, lo, hi, rtol=GRAD_RTOL):

@@ -43,7 +43,7 @@ def test_gaussian_close_to_fp64(stream_id):
     assert np.abs(got - ref).max() < 2e-5 * max(1.0, np.abs(ref).max())
 
 
-@pytest.mark.parametrize("name", ["tiny", "full", "full128"])
+@pytest.mark.parametrize("name", ["tiny", "full", "full128", "full32"])
 def test_squint_bit_exact(name):
     cfg = H.cfg(name)
     print(f"squint {name}", flush=True)
@@ -81,7 +81,8 @@ def _tensor_errs(got, ref, tab, base):
     return out
 
 
-@pytest.mark.parametrize("name,n,prec", [("tiny", 37, 0), ("full", 77, 0), ("tiny", 37, 1), ("full", 77, 1)])
+@pytest.mark.parametrize("name,n,prec", [("tiny", 37, 0), ("full", 77, 0), ("tiny", 37, 1), ("full", 77, 1),
+                                         ("full32", 45, 0), ("full32", 45, 1)])
 def test_encoder_critic_actor_ops_vs_oracle(name, n, prec):
     print(f"ops {name} n={n} prec={prec}", flush=True)
     cfg = H.cfg(name)
