@@ -294,3 +294,21 @@ def expected_q(logits, z):
     p = softmax(logits)
     q = p @ z
     return q, p * (z - q[..., None])
+
+
+def cdq_select(logits_bar, z):
+    """Clipped double-Q in categorical form: per row, the target twin whose expected
+    value sum_j softmax(l_i)_j z_j is the smaller (twin 0 on ties) supplies the whole
+    distribution.  Returns (probabilities [n, N], chosen twin index [n])."""
+    p0, p1 = softmax(logits_bar[0]), softmax(logits_bar[1])
+    pick = (p1 @ z) < (p0 @ z)
+    return np.where(pick[:, None], p1, p0), pick.astype(np.int64)
+
+
+def mse_loss(q, y):
+    """Eq. (2) for both twins: sum over twins of the batch mean of (Q_i - y)^2.
+    q [2, n], y [n].  Returns (loss, dq) with dq = 2 (Q_i - y) / n."""
+    n = y.shape[0]
+    diff = q - y[None]
+    return float(np.sum(np.mean(diff * diff, axis=1))), 2.0 * diff / n
+

@@ -9,8 +9,11 @@ choices) performs, in order:
   3. encode both halves with the current encoder (same psi for z_t, z_{t+1})
   4. target: a' ~ pi(z_{t+1}, s'), average the softmaxed twin target critics,
      shift every atom by -alpha log pi(a'), discount, project onto the atoms
-  5. critic + encoder: cross entropy of both online critics to the target,
-     backward into the critic and the encoder, one Adam step on (psi, theta)
+     (variants: the clipped double-Q target takes, per row, the twin with the
+     smaller expected value; a scalar critic, atoms = 1, uses Eq. (1) directly)
+  5. critic + encoder: cross entropy of both online critics to the target
+     (scalar critic: Eq. (2), the squared error), backward into the critic and
+     the encoder, one Adam step on (psi, theta)
   6. temperature: a ~ pi(stopgrad z_t, s) with fresh noise; gradient of
      alpha * mean(-log pi - H_target) with respect to log alpha; Adam on log alpha
   7. actor (when u % policy_freq == 0): the updated critic scores a; loss
@@ -37,7 +40,7 @@ from . import layout, nets, philox
 from .squint import squint
 
 HP_DEFAULT = dict(gamma=0.99, lr=3e-4, beta1=0.9, beta2=0.999, adam_eps=1e-8, rho=0.995,
-                  target_entropy=None, log_std_min=-5.0, log_std_max=2.0, policy_freq=1, seed=2)
+                  target_entropy=None, log_std_min=-5.0, log_std_max=2.0, policy_freq=1, seed=2, cdq=False)
 
 
 def hparams(d, **kw):
@@ -114,20 +117,37 @@ def sac_update(state, replay, d, hp, batch, bf=False):
     feat, enc_cache = nets.encoder_fwd(P, x, d.n_conv, bf)
     f_t, f_n = feat[:B], feat[B:]
 
-    # 4. distributional soft target
+    # 4. soft target: distributional (C51, atoms >= 2) or scalar (atoms == 1, Eq. (1));
+    # the twin targets are averaged, or the smaller one is taken (clipped double-Q)
     alpha = float(np.exp(P["log_alpha"][0]))
     a_n, logp_n, _ = nets.actor_fwd(P, f_n, s2, eps_next, hp.log_std_min, hp.log_std_max, bf)
     T = layout.target_view(state.target, d)
     logits_bar, _ = nets.critic_fwd(T, f_n, s2, a_n, bf)
-    p_bar = 0.5 * (nets.softmax(logits_bar[0]) + nets.softmax(logits_bar[1]))
     bonus = -alpha * logp_n
-    m = nets.c51_project(p_bar, r, done, hp.gamma, bonus, d.v_min, d.v_max)
-    z = nets.atoms(d.atoms, d.v_min, d.v_max)
+    scalar = d.atoms == 1
+    if scalar:
+        qbar = logits_bar[:, :, 0]
+        q_next = np.minimum(qbar[0], qbar[1]) if hp.cdq else 0.5 * (qbar[0] + qbar[1])
+        y = r + hp.gamma * (1.0 - done) * (q_next + bonus)
+        m, z, tgt = y[:, None], np.ones(1), y
+    else:
+        if hp.cdq:
+            p_bar, _ = nets.cdq_select(logits_bar, nets.atoms(d.atoms, d.v_min, d.v_max))
+        else:
+            p_bar = 0.5 * (nets.softmax(logits_bar[0]) + nets.softmax(logits_bar[1]))
+        m = nets.c51_project(p_bar, r, done, hp.gamma, bonus, d.v_min, d.v_max)
+        z = nets.atoms(d.atoms, d.v_min, d.v_max)
+        tgt = m @ z
 
-    # 5. critic + encoder step
+    # 5. critic + encoder step: cross entropy to m (C51) or Eq. (2) to y (scalar)
     logits, ccache = nets.critic_fwd(P, f_t, s, a_rep, bf)
-    loss_c, dlogits = nets.cross_entropy(logits, m)
-    q_rep, _ = nets.expected_q(logits, z)
+    if scalar:
+        q_rep = logits[:, :, 0]
+        loss_c, dq_c = nets.mse_loss(q_rep, y)
+        dlogits = dq_c[:, :, None]
+    else:
+        loss_c, dlogits = nets.cross_entropy(logits, m)
+        q_rep, _ = nets.expected_q(logits, z)
     g_critic, dfeat_t, _ = nets.critic_bwd(P, ccache, dlogits, bf)
     dfeat = np.concatenate([dfeat_t, np.zeros_like(f_n)])
     g_enc = nets.encoder_bwd(P, enc_cache, dfeat, d.n_conv, bf)
@@ -155,7 +175,10 @@ def sac_update(state, replay, d, hp, batch, bf=False):
     if actor_step:
         Pn = layout.view(state.params, d)
         logits_q, qcache = nets.critic_fwd(Pn, f_t, s, a_t, bf)
-        q, dq = nets.expected_q(logits_q, z)
+        if scalar:
+            q, dq = logits_q[:, :, 0], np.ones_like(logits_q)
+        else:
+            q, dq = nets.expected_q(logits_q, z)
         loss_pi = float(np.mean(alpha_new * logp_t - 0.5 * (q[0] + q[1])))
         dlogits_q = -0.5 / B * dq
         _, _, da = nets.critic_bwd(Pn, qcache, dlogits_q, bf, need_params=False, need_dfeat=False)
@@ -169,7 +192,7 @@ def sac_update(state, replay, d, hp, batch, bf=False):
     ema(state.target, state.params[slice(*blk["critic"])], hp.rho)
 
     stats = np.array([loss_c, loss_pi, loss_alpha, alpha_new, float(np.mean(-logp_t)),
-                      float(np.mean(q_rep)), float(np.mean(m @ z)), 0.0])
+                      float(np.mean(q_rep)), float(np.mean(tgt)), 0.0])
     stats[7] = 0.0 if np.all(np.isfinite(stats[:7])) else 1.0
     # magnitude of the terms each statistic averages: a mean of signed terms can
     # sit near zero, so its rounding error scales with these, not with the mean
@@ -177,9 +200,10 @@ def sac_update(state, replay, d, hp, batch, bf=False):
     stat_scale = np.array([abs(loss_c), float(np.mean(np.abs(alpha_new * logp_t) + np.abs(qa))),
                            alpha * float(np.mean(np.abs(-logp_t - hp.target_entropy))), abs(alpha_new),
                            float(np.mean(np.abs(logp_t))), float(np.mean(np.abs(q_rep))),
-                           float(np.mean(np.abs(m @ z)))])
+                           float(np.mean(np.abs(tgt)))])
     state.u = u + 1
-    return dict(idx=idx, eps_next=eps_next, eps=eps, x=x, feat=feat, m=m, logits=logits,
+    return dict(idx=idx, eps_next=eps_next, eps=eps, x=x, feat=feat, m=m, tgt=tgt, logits_bar=logits_bar,
+                logits=logits,
                 dlogits=dlogits, g_enc_critic=g_ec, g_log_alpha=g_la, g_actor=g_actor,
                 stats=stats, stat_scale=stat_scale, actor_step=actor_step, a_next=a_n, logp_next=logp_n,
                 a_t=a_t, logp_t=logp_t)
