@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision timing")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-insert", action="store_true", help="skip the insert-path (squint at insertion) timing")
+    ap.add_argument("--cdq", action="store_true", help="clipped double-Q target instead of the twin average")
+    ap.add_argument("--scalar-critic", action="store_true",
+                    help="scalar critics on the squared Bellman error instead of C51")
     ap.add_argument("--sweep", action="store_true",
                     help="UTD sweep {1,4,8,16} at batch 1024 on 128x128x9 frames (prints one JSON line)")
     ap.add_argument("--serve", action="store_true",
@@ -419,6 +422,8 @@ def main():
 
     from paper_2602_21203_amd import _lib, api, synthetic
     cfg = cfg_for(a.frame, a.side)
+    if a.scalar_critic:
+        cfg["atoms"] = 1
     B = a.batch
     torch.cuda.init()
     rep = synthetic.replay(a.capacity, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=0,
@@ -426,7 +431,7 @@ def main():
     table, _ = _lib.param_table(cfg)
     params = synthetic.init_params(table, seed=1)
     prec = _lib.SQ_BF16 if a.prec == "bf16" else _lib.SQ_F32
-    agent = api.Agent(cfg, params, B, prec=prec)
+    agent = api.Agent(cfg, params, B, prec=prec, cdq=a.cdq)
     wall, gpu, stats = time_updates(agent, rep, a.utd, a.steps, a.warmup)
     ups = a.utd * a.steps / wall
     result = {
@@ -434,7 +439,8 @@ def main():
         "value": round(ups, 2), "unit": "updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(wall / a.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": a.prec, "data": "synthetic",
-        "config": {"workload": f"visual SAC update, full network, batch {B}, {a.frame}x{a.frame}x9 uint8 frames "
+        "config": {"workload": f"visual SAC update, full network{' (scalar critics)' if a.scalar_critic else ''}"
+                               f"{' (clipped double-Q target)' if a.cdq else ''}, batch {B}, {a.frame}x{a.frame}x9 uint8 frames "
                                f"squinted to {side_of(cfg)}x{side_of(cfg)}, UTD {a.utd} per HIP-graph launch, "
                                f"replay {a.capacity} rows",
                    "global_batch": B, "utd": a.utd, "precision": a.prec},
@@ -443,7 +449,7 @@ def main():
     }
     if not a.no_compare:
         other = _lib.SQ_F32 if prec == _lib.SQ_BF16 else _lib.SQ_BF16
-        ag2 = api.Agent(cfg, params, B, prec=other)
+        ag2 = api.Agent(cfg, params, B, prec=other, cdq=a.cdq)
         w2, _, _ = time_updates(ag2, rep, a.utd, max(5, a.steps // 2), max(2, a.warmup // 2))
         result["fp32_updates_per_s" if other == _lib.SQ_F32 else "bf16_updates_per_s"] = \
             round(a.utd * max(5, a.steps // 2) / w2, 2)

@@ -62,10 +62,13 @@ typedef enum { SQ_F32 = 0, SQ_BF16 = 1 } sq_prec;
 /* Network and data dimensions (Sec. IV: 16x16 network input reached by area
  * downsampling, a small conv encoder, LayerNorm MLPs, C51 critics).
  *   C        channels of a frame stack (3 per RGB frame)
- *   H, W, k  source frame size and squint factor; H/k = W/k = 16
+ *   H, W, k  source frame size and squint factor; the network sees H/k x W/k
+ *            (16 x 16 in the paper; 32 x 32 is its higher-resolution variant)
  *   n_conv   number of 3x3 valid convs (first has stride 2), 1..4
  *   F        conv channels; proj: projection width; hidden: MLP width
- *   atoms    C51 atoms on [v_min, v_max]; proprio / action: vector sizes */
+ *   atoms    C51 atoms on [v_min, v_max] (>= 2); atoms = 1 selects a scalar
+ *            critic trained on the squared Bellman error (Eqs. (1)-(2)),
+ *            v_min / v_max unused; proprio / action: vector sizes */
 typedef struct {
   int C, H, W, k;
   int n_conv, F, proj, hidden, atoms, proprio, action;
@@ -82,6 +85,8 @@ typedef struct {
   int policy_freq;
   sq_prec prec;
   unsigned long long seed;
+  int cdq;   /* 0: average the twin targets (the paper's choice); 1: clipped double-Q,
+                the twin with the smaller expected value per row (Sec. IV Critic Design Choices) */
 } sq_hparams;
 
 /* Replay view, all device pointers, caller-owned; rows [0, size) are valid.

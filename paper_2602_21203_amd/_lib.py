@@ -31,7 +31,7 @@ class Dims(ctypes.Structure):
 class HParams(ctypes.Structure):
     _fields_ = [(n, c_float) for n in ("gamma", "lr", "beta1", "beta2", "adam_eps", "rho", "target_entropy",
                                        "log_std_min", "log_std_max")] + \
-               [("policy_freq", c_int), ("prec", c_int), ("seed", c_ull)]
+               [("policy_freq", c_int), ("prec", c_int), ("seed", c_ull), ("cdq", c_int)]
 
 
 class Replay(ctypes.Structure):
@@ -122,9 +122,10 @@ def make_dims(cfg):
 
 
 def make_hparams(action, prec=SQ_F32, gamma=0.99, lr=3e-4, beta1=0.9, beta2=0.999, adam_eps=1e-8, rho=0.995,
-                 target_entropy=None, log_std_min=-5.0, log_std_max=2.0, policy_freq=1, seed=2):
+                 target_entropy=None, log_std_min=-5.0, log_std_max=2.0, policy_freq=1, seed=2, cdq=False):
     te = -float(action) if target_entropy is None else target_entropy
-    return HParams(gamma, lr, beta1, beta2, adam_eps, rho, te, log_std_min, log_std_max, policy_freq, prec, seed)
+    return HParams(gamma, lr, beta1, beta2, adam_eps, rho, te, log_std_min, log_std_max, policy_freq, prec, seed,
+                   int(bool(cdq)))
 
 
 # canonical tensor names, in library order (the shapes come from the dims)

@@ -185,6 +185,7 @@ int c51_project(const sq_dims* dims, const float* p_next, const float* reward, c
   Net net;
   SQ_TRY(make_net(dims, &net));
   SQ_REQUIRE(n >= 0, "n < 0");
+  SQ_REQUIRE(dims->atoms >= 2, "c51_project needs a categorical critic (atoms >= 2)");
   if (n == 0) return SQ_OK;
   SQ_REQUIRE(p_next && reward && done && m, "NULL argument");
   return c51_project_raw(p_next, reward, done, bonus, gamma, n, dims->atoms, dims->v_min, dims->v_max, m,

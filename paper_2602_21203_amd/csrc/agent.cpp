@@ -156,8 +156,12 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
                              g->logits, g->crit, st));
   // distributional soft target from the averaged twin target critics (projection),
   // and the online critics' cross entropy to it, in one pass over the rows
-  SQ_TRY(target_ce(g->logits, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma, g->mt,
-                   g->tgt_row, g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st));
+  if (N == 1)
+    SQ_TRY(target_mse(g->logits, B, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma, hp.cdq, g->tgt_row,
+                      g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st));
+  else
+    SQ_TRY(target_ce(g->logits, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma,
+                     hp.cdq, g->mt, g->tgt_row, g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st));
   SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
                          g->dfeat, nullptr, st, true, true));
   SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true));
@@ -171,7 +175,10 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   if (actor_step) {
     SQ_TRY(critic_forward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->S2, S, g->act2B, A, B, g->logits_q,
                           g->aux, st));
-    SQ_TRY(expected_q_grad(g->logits_q, B, N, d.v_min, d.v_max, g->dlogits_q, g->qa_row, st));
+    if (N == 1)
+      SQ_TRY(expected_q_scalar(g->logits_q, B, g->dlogits_q, g->qa_row, st));
+    else
+      SQ_TRY(expected_q_grad(g->logits_q, B, N, d.v_min, d.v_max, g->dlogits_q, g->qa_row, st));
     SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits_q, B, g->aux, nullptr, nullptr,
                            g->da, st));
     SQ_TRY(actor_backward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
@@ -222,6 +229,10 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
   }
   if (batch <= 0 || hp->policy_freq <= 0 || (hp->prec != SQ_F32 && hp->prec != SQ_BF16)) {
     set_error("bad batch %d / policy_freq %d / prec", batch, hp->policy_freq);
+    return SQ_EINVAL;
+  }
+  if (hp->cdq != 0 && hp->cdq != 1) {
+    set_error("cdq %d is neither 0 nor 1", hp->cdq);
     return SQ_EINVAL;
   }
   if (!(hp->gamma >= 0.f && hp->gamma <= 1.f)) {

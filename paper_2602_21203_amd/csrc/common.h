@@ -244,9 +244,18 @@ int c51_project_raw(const float* p, const float* reward, const uint8_t* done, co
 // (bonus -alpha log pi'), tgt_row = E_m[z], then each online twin's cross entropy
 // to m: loss_row, dlogits = (softmax - m) / B, q_row = E[z], and (part, nullable)
 // the head-bias column partials.  logits4 = [online twins | target twins] [4][B][N].
+// cdq: the target twin with the smaller expected value supplies the distribution
+// (clipped double-Q) instead of the twin average.
 int target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward, const float* done,
-              const float* logp_next, const float* log_alpha, float gamma, float* m, float* tgt_row, float* dlogits2,
-              float* loss_row, float* q_row, float* part, hipStream_t st);
+              const float* logp_next, const float* log_alpha, float gamma, int cdq, float* m, float* tgt_row,
+              float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st);
+// The same for a scalar critic (N = 1, Eqs. (1)-(2)): squared error to
+// y = r + gamma (1 - d)(Qbar - alpha log pi').
+int target_mse(const float* logits4, int B, const float* reward, const float* done, const float* logp_next,
+               const float* log_alpha, float gamma, int cdq, float* tgt_row, float* dlogits2, float* loss_row,
+               float* q_row, float* part, hipStream_t st);
+// actor-loss head of a scalar critic: qa_row = (Q_1 + Q_2) / 2, dq2 = -1 / (2B)
+int expected_q_scalar(const float* q2, int B, float* dq2, float* qa_row, hipStream_t st);
 int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max, float* dlogits2,
                     float* qa_row, hipStream_t st);
 int finish_update(const float* loss_row, const float* q_row, const float* tgt_row, const float* logp,

@@ -569,7 +569,7 @@ __device__ __forceinline__ void softmax_regs(const float (&l)[T], int N, int lan
 // for each online twin: loss_row = CE(m, softmax), dlogits = (softmax - m) / B,
 // q_row = E[z]; part (nullable): the workgroup's column sums of dlogits per twin.
 // Every global input of a row is requested up front, so a wave waits on memory once.
-template <int T>
+template <int T, bool CDQ>
 __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
     const float* __restrict__ logits4, int B, int N, float v_min, float v_max, const float* __restrict__ reward,
     const float* __restrict__ done, const float* __restrict__ logp_next, const float* __restrict__ log_alpha,
@@ -602,8 +602,25 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
     float p0[T], p1[T], mi[T];
     softmax_regs<T>(lg[2], N, lane, p0);
     softmax_regs<T>(lg[3], N, lane, p1);
+    if constexpr (CDQ) {
+      // clipped double-Q: the twin with the smaller expected value (twin 0 on ties)
+      float e0 = 0.f, e1 = 0.f;
 #pragma unroll
-    for (int t = 0; t < T; ++t) p0[t] = 0.5f * (p0[t] + p1[t]);
+      for (int t = 0; t < T; ++t) {
+        const float zj = v_min + (float)(lane + 64 * t) * dz;
+        e0 += p0[t] * zj;
+        e1 += p1[t] * zj;
+      }
+      e0 = wave_sum(e0);
+      e1 = wave_sum(e1);
+      if (e1 < e0) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) p0[t] = p1[t];
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < T; ++t) p0[t] = 0.5f * (p0[t] + p1[t]);
+    }
     const float mz = project_row_t<T>(p0, N, lane, v_min, dz, rb, db, gamma, -expf(la) * lpb, shc2 + 2 * wave * N,
                                       shc2 + (2 * wave + 1) * N, mi);
 #pragma unroll
@@ -665,26 +682,90 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
   }
 }
 
-int target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward, const float* done,
-              const float* logp_next, const float* log_alpha, float gamma, float* m, float* tgt_row, float* dlogits2,
-              float* loss_row, float* q_row, float* part, hipStream_t st) {
-  if (B <= 0) return SQ_OK;
-  if (N < 2 || N > 64 * kMaxAtomsPerLane) return SQ_EINVAL;
+template <bool CDQ>
+static void launch_target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward,
+                             const float* done, const float* logp_next, const float* log_alpha, float gamma, float* m,
+                             float* tgt_row, float* dlogits2, float* loss_row, float* q_row, float* part,
+                             hipStream_t st) {
   const size_t lds = (size_t)(part ? 4 : 2) * kLnRowsPerBlock * N * sizeof(float);
   const dim3 grid(cdiv(B, kLnRowsPerBlock)), block(64 * kLnRowsPerBlock);
   if (N <= 64)
-    k_target_ce<1><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
-                                             m, tgt_row, dlogits2, loss_row, q_row, part);
+    k_target_ce<1, CDQ><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
+                                                  gamma, m, tgt_row, dlogits2, loss_row, q_row, part);
   else if (N <= 128)
-    k_target_ce<2><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
-                                             m, tgt_row, dlogits2, loss_row, q_row, part);
+    k_target_ce<2, CDQ><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
+                                                  gamma, m, tgt_row, dlogits2, loss_row, q_row, part);
   else if (N <= 192)
-    k_target_ce<3><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
-                                             m, tgt_row, dlogits2, loss_row, q_row, part);
+    k_target_ce<3, CDQ><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
+                                                  gamma, m, tgt_row, dlogits2, loss_row, q_row, part);
   else
-    k_target_ce<4><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma,
-                                             m, tgt_row, dlogits2, loss_row, q_row, part);
+    k_target_ce<4, CDQ><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
+                                                  gamma, m, tgt_row, dlogits2, loss_row, q_row, part);
+}
+
+int target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward, const float* done,
+              const float* logp_next, const float* log_alpha, float gamma, int cdq, float* m, float* tgt_row,
+              float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st) {
+  if (B <= 0) return SQ_OK;
+  if (N < 2 || N > 64 * kMaxAtomsPerLane) return SQ_EINVAL;
+  if (cdq)
+    launch_target_ce<true>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma, m, tgt_row,
+                           dlogits2, loss_row, q_row, part, st);
+  else
+    launch_target_ce<false>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma, m, tgt_row,
+                            dlogits2, loss_row, q_row, part, st);
   return launch_status("target_ce");
+}
+
+// Scalar critic (one output per twin; Eqs. (1)-(2)): per row,
+// y = r + gamma (1 - d)(Qbar - alpha log pi'), Qbar the twin-target average or, with
+// cdq, their minimum; each online twin's loss_row = (Q - y)^2, dlogits = 2 (Q - y) / B,
+// q_row = Q; part (nullable): column sums of dlogits per block of
+// kLnRowsPerBlock rows (thread order), one value per twin.
+__global__ __launch_bounds__(64) void k_target_mse(const float* __restrict__ logits4, int B,
+                                                   const float* __restrict__ reward, const float* __restrict__ done,
+                                                   const float* __restrict__ logp_next,
+                                                   const float* __restrict__ log_alpha, float gamma, int cdq,
+                                                   float* __restrict__ tgt_row, float* __restrict__ dlogits2,
+                                                   float* __restrict__ loss_row, float* __restrict__ q_row,
+                                                   float* __restrict__ part) {
+  constexpr int R = kLnRowsPerBlock;
+  __shared__ float sh[2][R];
+  const int t = threadIdx.x, b = blockIdx.x * R + t;
+  if (t < R) {
+    float dl[2] = {0.f, 0.f};
+    if (b < B) {
+      const float qa = logits4[(long long)2 * B + b], qb = logits4[(long long)3 * B + b];
+      const float qn = cdq ? fminf(qa, qb) : 0.5f * (qa + qb);
+      const float y = reward[b] + gamma * (1.f - done[b]) * (qn - expf(*log_alpha) * logp_next[b]);
+      tgt_row[b] = y;
+      for (int i = 0; i < 2; ++i) {
+        const float q = logits4[(long long)i * B + b];
+        const float diff = q - y;
+        loss_row[(long long)i * B + b] = diff * diff;
+        q_row[(long long)i * B + b] = q;
+        dl[i] = 2.f * diff / (float)B;
+        dlogits2[(long long)i * B + b] = dl[i];
+      }
+    }
+    sh[0][t] = dl[0];
+    sh[1][t] = dl[1];
+  }
+  __syncthreads();
+  if (part && t < 2) {
+    float s = sh[t][0];
+    for (int w = 1; w < R; ++w) s += sh[t][w];
+    part[(long long)t * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+int target_mse(const float* logits4, int B, const float* reward, const float* done, const float* logp_next,
+               const float* log_alpha, float gamma, int cdq, float* tgt_row, float* dlogits2, float* loss_row,
+               float* q_row, float* part, hipStream_t st) {
+  if (B <= 0) return SQ_OK;
+  k_target_mse<<<cdiv(B, kLnRowsPerBlock), 64, 0, st>>>(logits4, B, reward, done, logp_next, log_alpha, gamma, cdq,
+                                                        tgt_row, dlogits2, loss_row, q_row, part);
+  return launch_status("target_mse");
 }
 
 // plain projection of given probabilities (library entry point)
@@ -752,6 +833,23 @@ int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max
 
 // ---------------------------------------------------------------- end of an update
 // stats = {L_c, L_pi, L_alpha, alpha_new, entropy, mean Q, mean target, non-finite}
+// actor-loss head of a scalar critic: qa_row[b] = (Q_1 + Q_2) / 2, dL/dQ_i = -1 / (2B)
+__global__ __launch_bounds__(256) void k_expq_scalar(const float* __restrict__ q2, int B, float* __restrict__ dq2,
+                                                     float* __restrict__ qa_row) {
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const float c = -0.5f / (float)B;
+  dq2[b] = c;
+  dq2[(long long)B + b] = c;
+  qa_row[b] = 0.5f * (q2[b] + q2[(long long)B + b]);
+}
+
+int expected_q_scalar(const float* q2, int B, float* dq2, float* qa_row, hipStream_t st) {
+  if (B <= 0) return SQ_OK;
+  k_expq_scalar<<<cdiv(B, 256), 256, 0, st>>>(q2, B, dq2, qa_row);
+  return launch_status("expected_q_scalar");
+}
+
 __global__ __launch_bounds__(256) void k_finish(const float* __restrict__ loss_row, const float* __restrict__ q_row,
                                                 const float* __restrict__ tgt_row, const float* __restrict__ logp,
                                                 const float* __restrict__ qa_row, const float* __restrict__ scal,

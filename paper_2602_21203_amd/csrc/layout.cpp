@@ -29,7 +29,7 @@ int make_net(const sq_dims* d, Net* n) {
     return SQ_EINVAL;
   }
   if (d->n_conv < 1 || d->n_conv > 4 || d->F <= 0 || d->proj <= 0 || d->hidden <= 0 || d->proprio < 0 ||
-      d->action <= 0 || d->atoms < 2) {
+      d->action <= 0 || d->atoms < 1) {
     set_error("bad network dims n_conv=%d F=%d proj=%d hidden=%d atoms=%d proprio=%d action=%d", d->n_conv, d->F,
               d->proj, d->hidden, d->atoms, d->proprio, d->action);
     return SQ_EINVAL;
@@ -38,7 +38,7 @@ int make_net(const sq_dims* d, Net* n) {
     set_error("widths above the kernel limits (proj, hidden <= 1024, atoms <= 256)");
     return SQ_EINVAL;
   }
-  if (!(d->v_max > d->v_min)) { set_error("need v_max > v_min"); return SQ_EINVAL; }
+  if (d->atoms > 1 && !(d->v_max > d->v_min)) { set_error("need v_max > v_min"); return SQ_EINVAL; }
   if (!squint_ok(d->H, d->W, d->C, d->k)) {
     set_error("frame geometry %dx%dx%d / k=%d exceeds the squint kernel's tile", d->H, d->W, d->C, d->k);
     return SQ_EINVAL;

@@ -48,7 +48,10 @@ def test_invalid_dims_are_rejected_without_work():
     with pytest.raises(_lib.SquintError, match="frame dims"):
         _lib.param_count(bad)
     with pytest.raises(_lib.SquintError):
-        _lib.param_count(dict(configs.FULL, atoms=1))
+        _lib.param_count(dict(configs.FULL, atoms=0))
+    with pytest.raises(_lib.SquintError, match="v_max"):
+        _lib.param_count(dict(configs.FULL, v_min=1.0, v_max=1.0))
+    assert _lib.param_count(dict(configs.FULL, atoms=1, v_min=0.0, v_max=0.0)) == 1493335 - 2 * 100 * 513
     with pytest.raises(_lib.SquintError):
         _lib.param_count(dict(configs.FULL, hidden=2048))
     with pytest.raises(_lib.SquintError):

@@ -131,3 +131,55 @@ def test_act_matches_oracle(name, prec):
         a = ag.act(frames, prop, sample=sample, request_id=rid).cpu().numpy()
         ref = sac.act(p, d, hp, rep["obs"][:n], rep["proprio"][:n], sample, rid, bf=prec == 1)
         assert np.abs(a - ref).max() < (1e-5 if prec == 0 else 1e-2), (sample, np.abs(a - ref).max())
+
+
+@pytest.mark.parametrize("name,B,prec,atoms,cdq", [("tiny", 32, 0, None, True), ("tiny", 32, 0, 1, False),
+                                                   ("tiny", 32, 0, 1, True), ("tiny", 32, 1, 1, False),
+                                                   ("full", 512, 1, None, True), ("full", 512, 0, 1, False),
+                                                   ("full", 512, 1, 1, True)])
+def test_variant_update_matches_oracle(name, B, prec, atoms, cdq):
+    """The paper's critic ablations (Sec. IV Critic Design Choices): the clipped
+    double-Q target and the scalar critic with the squared Bellman error."""
+    print(f"variant parity {name} B={B} prec={prec} atoms={atoms} cdq={cdq}", flush=True)
+    cfg = dict(H.cfg(name))
+    if atoms is not None:
+        cfg["atoms"] = atoms
+    d = olayout.dims(**cfg)
+    tab = [(n, o, s) for n, (o, s) in olayout.offsets(d)[0].items()]
+    p = synthetic.init_params(tab, seed=1)
+    cap = 4096 if name == "tiny" else 2048
+    rep, grep = replay(name, cap)
+    ag = api.Agent(cfg, p, B, prec=prec, cdq=cdq)
+    got = ag.sac_update(grep, 1).cpu().numpy()[0]
+    hp = sac.hparams(d, cdq=cdq)
+    st = sac.new_state(d, p.astype(np.float64))
+    o = sac.sac_update(st, rep, d, hp, B, bf=prec == 1)
+    if cdq and d.atoms > 1:
+        # the twin choice is a comparison of expectations: keep it far from a tie
+        z = olayout_atoms(d)
+        e = np.exp(o["logits_bar"] - o["logits_bar"].max(-1, keepdims=True))
+        E = (e / e.sum(-1, keepdims=True)) @ z
+        assert np.min(np.abs(E[0] - E[1])) > 1e-4 * np.max(np.abs(E))
+    names = ("critic_loss", "actor_loss", "alpha_loss", "alpha", "entropy", "mean_q", "mean_target")
+    for i, nm in enumerate(names):
+        H.assert_loss(float(got[i]), float(o["stats"][i]), nm, o["stat_scale"][i], H.stat_rtol(prec, nm))
+    assert got[7] == 0.0
+    g = ag.grads.cpu().numpy().astype(np.float64)
+    blk = olayout.blocks(d)
+    tol = H.GRAD_RTOL if prec == 0 else H.GRAD_RTOL_BF16
+    worst = 0.0
+    for lo, hi, ref in ((0, blk["critic"][1], o["g_enc_critic"]), (blk["actor"][0], blk["actor"][1], o["g_actor"])):
+        for n_, (off, sh) in olayout.offsets(d)[0].items():
+            if off < lo or off >= hi:
+                continue
+            k = int(np.prod(sh))
+            e = H.rel_norm(g[off:off + k], ref[off - lo:off - lo + k])
+            worst = max(worst, e)
+            assert e <= tol, (n_, e)
+    print(f"  worst gradient rel err {worst:.2e}")
+    assert np.abs(ag.params.cpu().numpy() - st.params).max() <= 2 * 3e-4 * 1.001 + 1e-6
+    ag.close()
+
+
+def olayout_atoms(d):
+    return d.v_min + np.arange(d.atoms) * ((d.v_max - d.v_min) / (d.atoms - 1))
