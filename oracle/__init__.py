@@ -9,6 +9,8 @@ Modules
   philox    Philox4x32-10 counter RNG, replay-index sampler, Box-Muller noise
   squint    area downsampling of uint8 frames
   ring      squint at insertion (uint8 block means) and the FIFO replay ring
+  env       synthetic environment stub of the environment-step loop (point mass,
+            integer frame renderer)
   layout    canonical flat parameter layout
   nets      conv / linear / LayerNorm / heads, forward and hand-written backward
   sac       one full SAC update (critic, temperature, actor, Adam, target EMA)
