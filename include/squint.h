@@ -290,6 +290,41 @@ enum { SQ_RING_OBS = 0, SQ_RING_NEXT_OBS = 1, SQ_RING_PROPRIO = 2, SQ_RING_NEXT_
        SQ_RING_REWARD = 5, SQ_RING_DONE = 6 };
 SQ_API int sq_ring_copy_out(const sq_ring* ring, int field, int row0, int n, void* dst, sq_stream_t stream);
 
+/* ---------------------------------------------------------------- environment stub */
+/* A synthetic stand-in for the simulator of Alg. 1's outer loop (observe, act,
+ * step, store, then the UTD updates), so that the loop runs end to end on the
+ * device: per environment a point mass s[P] (P = proprio, 2..12) driven by the
+ * action (s_j <- clamp(s_j + a_{j mod A} / 8, -2, 2)), reward -|s_{0,1} - goal|^2,
+ * episodes of episode_len steps with Philox-drawn resets, and an integer
+ * renderer that draws the last three positions as discs into the frame stack
+ * ([n, H, W, C] uint8, C = 3, 6 or 9, H and W powers of two >= 8).
+ * sq_env_create allocates the state and buffers and resets every environment. */
+typedef struct sq_env sq_env;
+/* Caller-owned device buffers of the environments (n = n_envs, P = proprio). */
+typedef struct {
+  uint8_t* obs[2];        /* [n, H, W, C] observation buffers, used in turn: obs[k] is
+                             current after an even (k = 0) or odd (k = 1) number of steps */
+  float* proprio;         /* [n, P] current proprio (the environment state) */
+  uint8_t* next_obs;      /* [n, H, W, C] last transition's next observation */
+  float* proprio_t;       /* [n, P] last transition's proprio */
+  float* next_proprio;    /* [n, P] last transition's next proprio */
+  float* reward;          /* [n] */
+  uint8_t* done;          /* [n] */
+} sq_env_buffers;
+/* Allocates the small per-environment state (goal, step, episode, frame stack),
+ * resets every environment into obs[0] / proprio, and keeps the buffer pointers
+ * (the caller keeps the memory alive until sq_env_destroy). */
+SQ_API int sq_env_create(const sq_dims* dims, int n_envs, int episode_len, unsigned long long seed,
+                         const sq_env_buffers* bufs, sq_env** out);
+SQ_API int sq_env_destroy(sq_env* env);
+/* One step of every environment with action [n, A] (device): writes the
+ * transition (the previous current observation stays in its buffer as the
+ * transition's observation; next_obs, proprio_t, next_proprio, reward, done) and
+ * the next observation into the other obs buffer, which becomes current.  Store
+ * the transition before the next step, which overwrites that buffer.  The
+ * buffer parity is kept on the host, so the call cannot be captured (SQ_ECAPTURE). */
+SQ_API int sq_env_step(sq_env* env, const float* action, sq_stream_t stream);
+
 /* ---------------------------------------------------------------- serving */
 typedef void (*sq_done_cb)(unsigned long long request_id, double t_done_s, void* user);
 /* Continuous-batching act() server: a host scheduler thread fuses queued

@@ -64,7 +64,7 @@ def render(stack, H, W, C):
 
 class Env:
     def __init__(self, n, H, W, C, P, A, T, seed):
-        assert 2 <= P <= 12 and C % 3 == 0
+        assert 2 <= P <= 12 and C in (3, 6, 9)
         self.n, self.H, self.W, self.C, self.P, self.A, self.T = n, H, W, C, P, A, T
         self.k0, self.k1 = np.uint32(seed & 0xFFFFFFFF), np.uint32(seed >> 32)
         self.s = np.zeros((n, P), np.float32)

@@ -39,6 +39,11 @@ class Replay(ctypes.Structure):
                [("capacity", c_int), ("size", c_int), ("squinted", c_int), ("dev_size", c_vp)]
 
 
+class EnvBuffers(ctypes.Structure):
+    _fields_ = [("obs", c_vp * 2), ("proprio", c_vp), ("next_obs", c_vp), ("proprio_t", c_vp),
+                ("next_proprio", c_vp), ("reward", c_vp), ("done", c_vp)]
+
+
 DONE_CB = ctypes.CFUNCTYPE(None, ctypes.c_ulonglong, ctypes.c_double, ctypes.c_void_p)
 
 
@@ -84,6 +89,9 @@ def _load():
         "sq_ring_view": (c_int, [c_vp, P(Replay)]),
         "sq_ring_state": (c_int, [c_vp, P(c_int), P(c_int)]),
         "sq_ring_copy_out": (c_int, [c_vp, c_int, c_int, c_int, c_vp, c_vp]),
+        "sq_env_create": (c_int, [P(Dims), c_int, c_int, c_ull, P(EnvBuffers), P(c_vp)]),
+        "sq_env_destroy": (c_int, [c_vp]),
+        "sq_env_step": (c_int, [c_vp, c_vp, c_vp]),
         "sq_gemm": (c_int, [c_int, c_int, c_int, c_int, c_int, c_vp, c_ll, c_ll, c_ll, c_vp, c_ll, c_ll, c_ll,
                             c_vp, c_ll, c_ll, c_vp, c_ll, c_int, c_vp]),
         "sq_sample_indices": (c_int, [c_ull, ctypes.c_uint, c_int, c_int, c_vp, c_vp]),

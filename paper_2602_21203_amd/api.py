@@ -260,6 +260,62 @@ class Ring:
         return pos.value, size.value
 
 
+class Env:
+    """The synthetic environment stub (point mass, integer frame renderer) over
+    torch-owned device buffers.  obs / proprio are the current observation;
+    transition() gives the last step's transition as tensors (valid until the
+    next step)."""
+
+    def __init__(self, cfg, n_envs, episode_len=50, seed=3, device="cuda"):
+        self.cfg, self.n = cfg, int(n_envs)
+        frame = (self.n, cfg["H"], cfg["W"], cfg["C"])
+        u8, f32 = dict(dtype=torch.uint8, device=device), dict(dtype=torch.float32, device=device)
+        self.obs_buf = [torch.zeros(frame, **u8), torch.zeros(frame, **u8)]
+        self.proprio = torch.zeros((self.n, cfg["proprio"]), **f32)
+        self.next_obs = torch.zeros(frame, **u8)
+        self.proprio_t = torch.zeros((self.n, cfg["proprio"]), **f32)
+        self.next_proprio = torch.zeros((self.n, cfg["proprio"]), **f32)
+        self.reward = torch.zeros(self.n, **f32)
+        self.done = torch.zeros(self.n, **u8)
+        self.action = None
+        self.cur = 0
+        bufs = L.EnvBuffers((ctypes.c_void_p * 2)(self.obs_buf[0].data_ptr(), self.obs_buf[1].data_ptr()),
+                            self.proprio.data_ptr(), self.next_obs.data_ptr(), self.proprio_t.data_ptr(),
+                            self.next_proprio.data_ptr(), self.reward.data_ptr(), self.done.data_ptr())
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        check(L.LIB.sq_env_create(_dims(cfg), self.n, int(episode_len), int(seed), ctypes.byref(bufs),
+                                  ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def obs(self):
+        return self.obs_buf[self.cur]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            torch.cuda.synchronize()
+            L.LIB.sq_env_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, action, stream=None):
+        _req(action, torch.float32, (self.n, self.cfg["action"]), "action")
+        check(L.LIB.sq_env_step(self.handle, ptr(action), stream_handle(stream)))
+        self.action = action
+        self.cur ^= 1
+
+    def transition(self):
+        """(obs, next_obs, proprio, next_proprio, action, reward, done) of the last step."""
+        return (self.obs_buf[self.cur ^ 1], self.next_obs, self.proprio_t, self.next_proprio, self.action,
+                self.reward, self.done)
+
+
 class Agent:
     """Owns the state tensors of one agent and the library handle.
 

@@ -125,6 +125,20 @@ struct RingRows {
   int* ctr;
   int new_pos, new_size;
 };
+// env.hip: the synthetic environment stub's device state (n environments)
+struct EnvState {
+  int n, H, W, C, P, A, T;
+  unsigned k0, k1;
+  float* s;       // [n, P] proprio
+  float* g;       // [n, 2] goal
+  int* t;         // [n] step within the episode
+  int* ep;        // [n] episode number
+  int* stack;     // [n, 3, 2] pixel positions of the frame stack, newest first
+};
+int env_reset_all(const EnvState& E, uint8_t* obs, hipStream_t st);
+// prop_t receives the pre-step proprio; obs_next the observation of the next step
+int env_step(const EnvState& E, const float* action, float* prop_t, uint8_t* next_obs, float* next_prop,
+             float* reward, uint8_t* done, uint8_t* obs_next, hipStream_t st);
 // where a squint launch writes (see squint.hip)
 enum { kSqF32 = 0, kSqBF16 = 1, kSqU8 = 2 };
 struct SqDst { int mode; void* out; void* out1; long long row_stride; int pos, cap; RingRows f; };

@@ -69,6 +69,8 @@ def test_invalid_dims_are_rejected_without_work():
     assert _lib.LIB.sq_ring_insert(None, None, None, None, None, None, None, None, 1, None) == _lib.SQ_EINVAL
     assert _lib.LIB.sq_ring_view(None, None) == _lib.SQ_EINVAL
     assert _lib.LIB.sq_ring_copy_out(None, 0, 0, 1, None, None) == _lib.SQ_EINVAL
+    assert _lib.LIB.sq_env_create(ctypes.byref(d), 4, 10, 1, None, ctypes.byref(h)) == _lib.SQ_EINVAL
+    assert _lib.LIB.sq_env_step(None, None, None) == _lib.SQ_EINVAL
 
 
 def test_workspace_sizes_grow_with_rows():
