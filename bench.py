@@ -41,6 +41,12 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-insert", action="store_true", help="skip the insert-path (squint at insertion) timing")
     ap.add_argument("--cdq", action="store_true", help="clipped double-Q target instead of the twin average")
+    ap.add_argument("--env-loop", action="store_true",
+                    help="environment-step loop with the synthetic environment stub (time breakdown)")
+    ap.add_argument("--envs", type=int, default=1024)
+    ap.add_argument("--loop-utd", type=int, default=256, help="updates per environment step in --env-loop")
+    ap.add_argument("--loop-steps", type=int, default=8)
+    ap.add_argument("--loop-warmup", type=int, default=2)
     ap.add_argument("--scalar-critic", action="store_true",
                     help="scalar critics on the squared Bellman error instead of C51")
     ap.add_argument("--sweep", action="store_true",
@@ -302,6 +308,69 @@ def run_sweep(a):
     print(json.dumps(out))
 
 
+def run_env_loop(a):
+    """Alg. 1's environment-step loop end to end on the device, with the synthetic
+    environment stub in place of the simulator: per environment step, act() on
+    every environment (tanh-Gaussian samples), step the environments, store the
+    transitions by squint at insertion, then UTD updates sampling the ring.  HIP
+    events between the phases give the time breakdown."""
+    import torch
+
+    from paper_2602_21203_amd import _lib, api, synthetic
+    cfg = cfg_for(a.frame, a.side)
+    n_env, utd, B = a.envs, a.loop_utd, a.batch
+    table, _ = _lib.param_table(cfg)
+    params = synthetic.init_params(table, seed=1)
+    prec = _lib.SQ_BF16 if a.prec == "bf16" else _lib.SQ_F32
+    agent = api.Agent(cfg, params, B, prec=prec)
+    env = api.Env(cfg, n_env, episode_len=50, seed=3)
+    ring = api.Ring(cfg, a.capacity)
+    st = agent.stream
+    stats = torch.empty((utd, 8), dtype=torch.float32, device="cuda")
+    act_out = torch.empty((n_env, cfg["action"]), dtype=torch.float32, device="cuda")
+    phases = ("act", "env_step", "insert", "updates")
+    tot = dict.fromkeys(phases, 0.0)
+
+    def env_step(t, timed):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(st)
+        agent.act(env.obs, env.proprio, sample=True, request_id=t, out=act_out, stream=st)
+        ev[1].record(st)
+        env.step(act_out, stream=st)
+        ev[2].record(st)
+        ring.insert(*env.transition(), stream=st)
+        ev[3].record(st)
+        agent.sac_update(ring, utd, stats=stats, stream=st)
+        ev[4].record(st)
+        return ev
+
+    for t in range(a.loop_warmup):
+        env_step(t, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = [env_step(a.loop_warmup + t, True) for t in range(a.loop_steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for ev in evs:
+        for i, ph in enumerate(phases):
+            tot[ph] += ev[i].elapsed_time(ev[i + 1]) / 1e3
+    dev = sum(tot.values())
+    out = {"mode": "env_loop",
+           "workload": f"Alg. 1 outer loop with the synthetic environment stub: {n_env} environments, "
+                       f"{cfg['H']}x{cfg['W']}x{cfg['C']} frames squinted at insertion to {side_of(cfg)}x{side_of(cfg)}, "
+                       f"{utd} updates of batch {B} ({a.prec}) per environment step, ring {a.capacity} rows",
+           "env_steps": a.loop_steps, "env_steps_per_s": round(a.loop_steps / wall, 3),
+           "transitions_per_s": round(a.loop_steps * n_env / wall, 1),
+           "updates_per_s": round(a.loop_steps * utd / wall, 2),
+           "ms_per_env_step": {ph: round(tot[ph] / a.loop_steps * 1e3, 4) for ph in phases},
+           "share": {ph: round(tot[ph] / dev, 5) for ph in phases},
+           "final_stats": {n: float(v) for n, v in zip(_lib.STAT_NAMES, stats[-1].cpu().numpy())}}
+    ring.close()
+    env.close()
+    agent.close()
+    print(json.dumps(out))
+
+
 def run_serve(a):
     import numpy as np
     import torch
@@ -408,11 +477,11 @@ def run_report(a):
 
 def main():
     a = parse()
-    if a.sweep or a.serve or a.report:
+    if a.sweep or a.serve or a.report or a.env_loop:
         if a.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU", "n_gpus": a.gpus}))
             sys.exit(2)
-        (run_sweep if a.sweep else run_serve if a.serve else run_report)(a)
+        (run_sweep if a.sweep else run_serve if a.serve else run_report if a.report else run_env_loop)(a)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
