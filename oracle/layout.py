@@ -35,6 +35,13 @@ FULL128 = dict(FULL, H=128, W=128, k=8)
 
 def dims(**kw):
     d = SimpleNamespace(**kw)
+    if d.n_conv == 0:
+        # state-based SAC: no image and no encoder; the proprio state vector is
+        # the feature that the projections read
+        d.side, d.conv_sides, d.flat = 0, [], d.proprio
+        d.critic_in = d.proj + d.proprio + d.action
+        d.actor_in = d.proj + d.proprio
+        return d
     d.side = d.H // d.k
     s = (d.side - 3) // 2 + 1
     d.conv_sides = [s]

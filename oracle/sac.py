@@ -111,10 +111,16 @@ def sac_update(state, replay, d, hp, batch, bf=False):
     done = bt["done"].astype(np.float64)
 
     # 2-3. squint and encode both halves with the current encoder
-    # (frames stored already squinted, as by squint at insertion, carry k = 1)
-    k = replay.get("k", d.k)
-    x = np.concatenate([squint(bt["obs"], k), squint(bt["next_obs"], k)])
-    feat, enc_cache = nets.encoder_fwd(P, x, d.n_conv, bf)
+    # (frames stored already squinted, as by squint at insertion, carry k = 1);
+    # state-based SAC (no encoder) uses the states themselves as the features
+    image = d.n_conv > 0
+    if image:
+        k = replay.get("k", d.k)
+        x = np.concatenate([squint(bt["obs"], k), squint(bt["next_obs"], k)])
+        feat, enc_cache = nets.encoder_fwd(P, x, d.n_conv, bf)
+    else:
+        x = None
+        feat = np.concatenate([s, s2])
     f_t, f_n = feat[:B], feat[B:]
 
     # 4. soft target: distributional (C51, atoms >= 2) or scalar (atoms == 1, Eq. (1));
@@ -149,10 +155,10 @@ def sac_update(state, replay, d, hp, batch, bf=False):
         loss_c, dlogits = nets.cross_entropy(logits, m)
         q_rep, _ = nets.expected_q(logits, z)
     g_critic, dfeat_t, _ = nets.critic_bwd(P, ccache, dlogits, bf)
-    dfeat = np.concatenate([dfeat_t, np.zeros_like(f_n)])
-    g_enc = nets.encoder_bwd(P, enc_cache, dfeat, d.n_conv, bf)
     g_all = dict(g_critic)
-    g_all.update(g_enc)
+    if image:
+        dfeat = np.concatenate([dfeat_t, np.zeros_like(f_n)])
+        g_all.update(nets.encoder_bwd(P, enc_cache, dfeat, d.n_conv, bf))
     g_ec = _flatten(g_all, d, (blk["enc"][0], blk["critic"][1]))
     lo, hi = blk["enc"][0], blk["critic"][1]
     state.steps[0] += 1
@@ -212,9 +218,11 @@ def sac_update(state, replay, d, hp, batch, bf=False):
 def act(params, d, hp, frames, proprio, sample, request_id=0, bf=False):
     """Policy query of Alg. 1 (sample a_t from pi(f(squint(o)), s)): mean or sampled action."""
     P = layout.view(np.asarray(params, dtype=np.float64), d)
-    x = squint(frames, d.k)
-    f, _ = nets.encoder_fwd(P, x, d.n_conv, bf)
     s = np.asarray(proprio, dtype=np.float64)
+    if d.n_conv > 0:
+        f, _ = nets.encoder_fwd(P, squint(frames, d.k), d.n_conv, bf)
+    else:
+        f = s
     if not sample:
         a, _, _ = nets.actor_fwd(P, f, s, None, hp.log_std_min, hp.log_std_max, bf)
         return a

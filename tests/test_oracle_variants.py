@@ -166,3 +166,70 @@ def test_scalar_critic_loss_finite_differences():
                     loss(st0.params - h * np.eye(1, st0.params.size, c)[0])) / (2 * h) for c in coords])
     g = out["g_enc_critic"][coords]
     assert np.linalg.norm(fd - g) <= 1e-6 * np.linalg.norm(g) + 1e-9
+
+
+def _torch_state_grads(d, rep, st, hp, B, out):
+    """Gradients of one state-based update (no encoder: the states are the
+    features) from torch autograd."""
+    tab = layout.offsets(d)[0]
+    idx = philox.sample_indices(hp.seed, st.u, rep["size"], B)
+    eps_n = T(philox.gaussian(hp.seed, st.u, 1, B * d.action).reshape(B, d.action))
+    eps = T(philox.gaussian(hp.seed, st.u, 2, B * d.action).reshape(B, d.action))
+    g = lambda k: T(rep[k][idx].astype(np.float64))
+    s, s2, a, r, done = g("proprio"), g("next_proprio"), g("action"), g("reward"), g("done")
+    pt = T(st.params, True)
+    P = torch_ref.views(pt, tab)
+    alpha = P["log_alpha"][0].detach().exp()
+    N = d.atoms
+    z = d.v_min + torch.arange(N, dtype=torch.float64) * ((d.v_max - d.v_min) / (N - 1))
+    with torch.no_grad():
+        a_n, lp_n = torch_ref.actor(P, s2, s2, eps_n, hp.log_std_min, hp.log_std_max)
+        base = layout.blocks(d)["critic"][0]
+        Tt = torch_ref.views(T(st.target), {k: (o - base, sh) for k, (o, sh) in tab.items()
+                                            if k.startswith(("critic.", "q1.", "q2."))})
+        lbar = torch_ref.critic(Tt, s2, s2, a_n)
+        pbar = 0.5 * (torch.softmax(lbar[0], -1) + torch.softmax(lbar[1], -1))
+    m = T(out["m"])
+    logits = torch_ref.critic(P, s, s, a)
+    loss_c = -(m[None] * F.log_softmax(logits, -1)).sum(-1).mean(1).sum()
+    loss_c.backward()
+    g_ec = pt.grad.numpy()[: layout.blocks(d)["critic"][1]].copy()
+    pn = T(out["params_after"])
+    pa = T(st.params, True)
+    a_t, lp_t = torch_ref.actor(torch_ref.views(pa, tab), s, s, eps, hp.log_std_min, hp.log_std_max)
+    q = torch.softmax(torch_ref.critic(torch_ref.views(pn, tab), s, s, a_t), -1) @ z
+    alpha_new = math.exp(out["params_after"][layout.blocks(d)["log_alpha"][0]])
+    loss_pi = (alpha_new * lp_t - 0.5 * (q[0] + q[1])).mean()
+    loss_pi.backward()
+    a0, a1 = layout.blocks(d)["actor"]
+    m_ref = nets.c51_project_scatter(pbar.numpy(), r.numpy(), done.numpy(), hp.gamma,
+                                     -float(alpha) * lp_n.numpy(), d.v_min, d.v_max)
+    return dict(g_ec=g_ec, g_actor=pa.grad.numpy()[a0:a1], loss_c=float(loss_c.detach()),
+                loss_pi=float(loss_pi.detach()), m=m_ref)
+
+
+def test_state_based_update_gradients_vs_autograd():
+    """Fig. 7 (left) trains state-based SAC: the same update without the image
+    path, the state vector in place of the encoder features."""
+    c = dict(layout.TINY, n_conv=0, H=8, W=8, k=1, proprio=40)
+    d = layout.dims(**c)
+    assert d.flat == 40 and layout.blocks(d)["enc"] == (0, 0)
+    cpu = synthetic.replay(128, d.H, d.W, d.C, d.proprio, d.action, seed=0)
+    rep = {k: (v.numpy() if torch.is_tensor(v) else v) for k, v in cpu.items()}
+    tab = [(n, o, s) for n, (o, s) in layout.offsets(d)[0].items()]
+    p = synthetic.init_params(tab, seed=1).astype(np.float64)
+    st = sac.new_state(d, p)
+    hp = sac.hparams(d)
+    st0 = sac.copy_state(st)
+    out = sac.sac_update(st, rep, d, hp, 32)
+    out["params_after"] = st.params
+    ref = _torch_state_grads(d, rep, st0, hp, 32, out)
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+    assert rel(out["g_enc_critic"], ref["g_ec"]) < 1e-10
+    assert rel(out["g_actor"], ref["g_actor"]) < 1e-10
+    assert out["stats"][0] == pytest.approx(ref["loss_c"], rel=1e-12)
+    assert out["stats"][1] == pytest.approx(ref["loss_pi"], rel=1e-10, abs=1e-14)
+    # the target: torch's twin-averaged softmax projected by the scatter form
+    np.testing.assert_allclose(out["m"], ref["m"], atol=1e-12)
