@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--no-insert", action="store_true", help="skip the insert-path (squint at insertion) timing")
     ap.add_argument("--cdq", action="store_true", help="clipped double-Q target instead of the twin average")
+    ap.add_argument("--state", action="store_true",
+                    help="state-based SAC (no image or encoder; a 40-float state in place of the features)")
     ap.add_argument("--env-loop", action="store_true",
                     help="environment-step loop with the synthetic environment stub (time breakdown)")
     ap.add_argument("--envs", type=int, default=1024)
@@ -491,6 +493,10 @@ def main():
 
     from paper_2602_21203_amd import _lib, api, synthetic
     cfg = cfg_for(a.frame, a.side)
+    if a.state:
+        # state-based SAC: no image or encoder; a 40-float state vector feeds the
+        # projections (the replay's frames are tiny and never read)
+        cfg = dict(cfg, n_conv=0, H=8, W=8, C=3, k=1, proprio=40)
     if a.scalar_critic:
         cfg["atoms"] = 1
     B = a.batch
@@ -508,10 +514,12 @@ def main():
         "value": round(ups, 2), "unit": "updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
         "ms_per_step": round(wall / a.steps * 1e3, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": a.prec, "data": "synthetic",
-        "config": {"workload": f"visual SAC update, full network{' (scalar critics)' if a.scalar_critic else ''}"
-                               f"{' (clipped double-Q target)' if a.cdq else ''}, batch {B}, {a.frame}x{a.frame}x9 uint8 frames "
-                               f"squinted to {side_of(cfg)}x{side_of(cfg)}, UTD {a.utd} per HIP-graph launch, "
-                               f"replay {a.capacity} rows",
+        "config": {"workload": f"{'state-based' if a.state else 'visual'} SAC update, full network"
+                               f"{' (scalar critics)' if a.scalar_critic else ''}"
+                               f"{' (clipped double-Q target)' if a.cdq else ''}, batch {B}, "
+                               + ("40-float state vectors" if a.state else
+                                  f"{a.frame}x{a.frame}x9 uint8 frames squinted to {side_of(cfg)}x{side_of(cfg)}")
+                               + f", UTD {a.utd} per HIP-graph launch, replay {a.capacity} rows",
                    "global_batch": B, "utd": a.utd, "precision": a.prec},
         "gpu_event_updates_per_s": round(a.utd * a.steps / gpu, 2),
         "final_stats": {n: float(v) for n, v in zip(_lib.STAT_NAMES, stats[-1])},
@@ -534,6 +542,10 @@ def main():
                           if a.prec == "bf16" else None,
                           "avg_us": round(t_g * 1e6, 3), "algorithmic_flops": flops,
                           "algorithmic_bytes": 3 * 2 * 512 * 512 * 4 + 2 * 512 * 4}
+    if a.state:
+        agent.close()
+        print(json.dumps(result))
+        return
     # the HBM-bound step: squint gather of 2B frames (frames read + FP32 images written)
     t_k = squint_kernel_time(cfg, rep, B, a.kernel_reps)
     bytes_per_launch = 2 * B * (cfg["H"] * cfg["W"] * cfg["C"] + cfg["C"] * side_of(cfg) ** 2 * 4)

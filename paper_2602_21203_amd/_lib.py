@@ -148,12 +148,15 @@ def _names(n_conv):
 
 
 def _shapes(cfg):
-    side = cfg["H"] // cfg["k"]
-    s = (side - 3) // 2 + 1
-    for _ in range(cfg["n_conv"] - 1):
-        s -= 2
     F, P, H, A, S = cfg["F"], cfg["proj"], cfg["hidden"], cfg["action"], cfg["proprio"]
-    flat = F * s * s
+    if cfg["n_conv"] == 0:          # state-based: the proprio state is the feature
+        flat = S
+    else:
+        side = cfg["H"] // cfg["k"]
+        s = (side - 3) // 2 + 1
+        for _ in range(cfg["n_conv"] - 1):
+            s -= 2
+        flat = F * s * s
     shp = {}
     cin = cfg["C"]
     for i in range(cfg["n_conv"]):

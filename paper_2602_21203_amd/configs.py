@@ -7,6 +7,8 @@ full   64x64x9 frames (stack of 3 RGB) squinted 4x; 3 convs of 32 channels; proj
 full128  the full network on 128x128x9 frames squinted 8x
 full32   the full network on 128x128x9 frames squinted 4x to 32x32 (the higher-resolution
          variant of Sec. VI Camera Resolution Analysis): convs 32 -> 15 -> 13 -> 11
+state, state_tiny   state-based SAC (Sec. VI Generality and Timing Analysis): no image
+         and no encoder, a 40-float state vector feeds the projections
 """
 TINY = dict(C=3, H=32, W=32, k=2, n_conv=2, F=16, proj=64, hidden=64, atoms=51, proprio=12, action=6,
             v_min=-10.0, v_max=10.0)
@@ -14,4 +16,8 @@ FULL = dict(C=9, H=64, W=64, k=4, n_conv=3, F=32, proj=256, hidden=512, atoms=10
             v_min=-20.0, v_max=20.0)
 FULL128 = dict(FULL, H=128, W=128, k=8)
 FULL32 = dict(FULL, H=128, W=128, k=4)
-CONFIGS = dict(tiny=TINY, full=FULL, full128=FULL128, full32=FULL32)
+# state-based SAC (no image, no encoder): a 40-float state vector in place of the
+# features; the frame fields only size the (unused) frames of the synthetic replay
+STATE_TINY = dict(TINY, n_conv=0, H=8, W=8, k=1, proprio=40)
+STATE = dict(FULL, n_conv=0, H=8, W=8, C=3, k=1, proprio=40)
+CONFIGS = dict(tiny=TINY, full=FULL, full128=FULL128, full32=FULL32, state_tiny=STATE_TINY, state=STATE)

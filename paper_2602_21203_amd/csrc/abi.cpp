@@ -104,6 +104,7 @@ int squint_downsample(const sq_dims* dims, const uint8_t* frames, const int* idx
                       void* out, sq_stream_t stream) {
   Net net;
   SQ_TRY(make_net(dims, &net));
+  SQ_REQUIRE(dims->n_conv > 0, "state-based dims (n_conv = 0) have no frames or encoder");
   SQ_REQUIRE(n >= 0, "n < 0");
   if (n == 0) return SQ_OK;
   SQ_REQUIRE(frames && out, "NULL frames or out");
@@ -116,6 +117,7 @@ int encoder_fwd(const sq_dims* dims, sq_prec prec, const float* enc_params, cons
                 void* ws, sq_stream_t stream) {
   Net net;
   SQ_TRY(make_net(dims, &net));
+  SQ_REQUIRE(dims->n_conv > 0, "state-based dims (n_conv = 0) have no frames or encoder");
   SQ_REQUIRE(n >= 0, "n < 0");
   if (n == 0) return SQ_OK;
   SQ_REQUIRE(enc_params && x && feat && ws, "NULL argument");
@@ -135,6 +137,7 @@ int encoder_bwd(const sq_dims* dims, sq_prec prec, const float* enc_params, cons
                 float* denc_params, sq_stream_t stream) {
   Net net;
   SQ_TRY(make_net(dims, &net));
+  SQ_REQUIRE(dims->n_conv > 0, "state-based dims (n_conv = 0) have no frames or encoder");
   SQ_REQUIRE(n >= 0, "n < 0");
   SQ_REQUIRE(enc_params && ws && denc_params && (dfeat || n == 0), "NULL argument");
   Layout L;

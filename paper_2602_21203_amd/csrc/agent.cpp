@@ -36,10 +36,14 @@ int enqueue_act(const Net& net, const Layout& L, const sq_hparams& hp, const flo
                 unsigned long long request_id, float* action_out, hipStream_t st) {
   const sq_dims& d = net.d;
   const int bf = hp.prec == SQ_BF16;
-  SQ_TRY(launch_squint(frames, nullptr, n, d.H, d.W, d.C, d.k, 0, w.x, net.img, st));
-  SQ_TRY(encoder_forward(net, bf, params, L, w.x, n, w.e, st));
+  const float* feat = proprio;   // state-based: the state is the feature
+  if (d.n_conv > 0) {
+    SQ_TRY(launch_squint(frames, nullptr, n, d.H, d.W, d.C, d.k, 0, w.x, net.img, st));
+    SQ_TRY(encoder_forward(net, bf, params, L, w.x, n, w.e, st));
+    feat = w.e.h[d.n_conv - 1];
+  }
   if (sample) SQ_TRY(launch_act_noise(hp.seed, request_id, n, d.action, w.noise, st));
-  return actor_forward(net, bf, params + L.actor_begin, pack, L, w.e.h[d.n_conv - 1], net.flat, proprio, d.proprio,
+  return actor_forward(net, bf, params + L.actor_begin, pack, L, feat, net.flat, proprio, d.proprio,
                        sample ? w.noise : nullptr, n, hp.log_std_min, hp.log_std_max, action_out, nullptr, w.a, st);
 }
 
@@ -141,13 +145,18 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   float* G = g->grads;
   SQ_TRY(launch_sample_batch(hp.seed, g->ctr, R->size, R->dev_size, B, A, S, R->proprio, R->next_proprio, R->action,
                              R->reward, R->done, g->idx, g->eps2B, g->S2, g->Arep, g->r, g->dn, st));
-  // frames squinted at insertion are the k = 1 squint of the stored block means
-  if (R->squinted)
-    SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, net.side, net.side, d.C, 1, g->x, st));
-  else
-    SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, d.H, d.W, d.C, d.k, g->x, st));
-  SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st));
-  const float* feat = g->enc.h[d.n_conv - 1];
+  // state-based SAC: the sampled states [s; s'] (S2) are the features
+  const bool image = d.n_conv > 0;
+  const float* feat = g->S2;
+  if (image) {
+    // frames squinted at insertion are the k = 1 squint of the stored block means
+    if (R->squinted)
+      SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, net.side, net.side, d.C, 1, g->x, st));
+    else
+      SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, d.H, d.W, d.C, d.k, g->x, st));
+    SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st));
+    feat = g->enc.h[d.n_conv - 1];
+  }
   SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
                        g->logp2B, g->actor, st));
   // online critics on (z, s, a) and target critics on (z', s', a~') in one pass
@@ -163,8 +172,8 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
     SQ_TRY(target_ce(g->logits, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma,
                      hp.cdq, g->mt, g->tgt_row, g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st));
   SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
-                         g->dfeat, nullptr, st, true, true));
-  SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true));
+                         image ? g->dfeat : nullptr, nullptr, st, true, true));
+  if (image) SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true));
   // critic + encoder Adam (with the target EMA and the packed copies), and the
   // temperature step in one extra workgroup of the same launch
   const AlphaJob aj{g->logp2B, B, hp.target_entropy, P + L.log_alpha, G + L.log_alpha, g->m + L.log_alpha,
@@ -192,7 +201,7 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
 
 static int check_replay(const sq_agent* g, const sq_replay* R) {
   if (!R) { set_error("replay is NULL"); return SQ_EINVAL; }
-  if (!R->obs || !R->next_obs || !R->action || !R->reward || !R->done ||
+  if ((g->net.d.n_conv > 0 && (!R->obs || !R->next_obs)) || !R->action || !R->reward || !R->done ||
       (g->net.d.proprio > 0 && (!R->proprio || !R->next_proprio))) {
     set_error("replay has a NULL field");
     return SQ_EINVAL;
@@ -381,7 +390,7 @@ int act(sq_agent* g, const uint8_t* frames, const float* proprio, int n, int sam
     return SQ_EINVAL;
   }
   if (n == 0) return SQ_OK;
-  if (!frames || !action_out || (g->net.d.proprio > 0 && !proprio)) {
+  if ((g->net.d.n_conv > 0 && !frames) || !action_out || (g->net.d.proprio > 0 && !proprio)) {
     set_error("NULL argument to act");
     return SQ_EINVAL;
   }

@@ -19,6 +19,10 @@ int sq_env_create(const sq_dims* dims, int n_envs, int episode_len, unsigned lon
                   const sq_env_buffers* bufs, sq_env** out) {
   Net net;
   SQ_TRY(make_net(dims, &net));
+  if (net.d.n_conv == 0) {
+    set_error("state-based dims (n_conv = 0) have no frames to store");
+    return SQ_EINVAL;
+  }
   if (!out || !bufs || n_envs <= 0 || episode_len <= 0) {
     set_error("bad environment arguments (n_envs %d, episode_len %d)", n_envs, episode_len);
     return SQ_EINVAL;

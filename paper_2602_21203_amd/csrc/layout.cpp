@@ -1,6 +1,7 @@
 // Dimension checks and the canonical flat parameter layout.
 //
-// Order: encoder convs {W[F, Cin, 3, 3], b}; critic projection {W[proj, flat],
+// Order: encoder convs {W[F, Cin, 3, 3], b} (none in the state-based form, whose
+// features are the proprio state); critic projection {W[proj, flat],
 // b, ln gain, ln shift}; twin critics q1, q2 each {l1 W[hidden, proj+P+A], b,
 // gain, shift; l2 W[hidden, hidden], b, gain, shift; out W[atoms, hidden], b};
 // actor projection (critic projection shapes); actor {l1 W[hidden, proj+P], ...,
@@ -24,6 +25,28 @@ const char* last_error() { return g_err; }
 
 int make_net(const sq_dims* d, Net* n) {
   if (!d) { set_error("dims is NULL"); return SQ_EINVAL; }
+  if (d->n_conv == 0) {
+    // state-based SAC (no image, no encoder): the proprio vector is the state
+    // and takes the place of the encoder features; the frame fields are unused
+    if (d->proprio <= 0 || d->proj <= 0 || d->hidden <= 0 || d->action <= 0 || d->atoms < 1) {
+      set_error("bad state-based dims proprio=%d proj=%d hidden=%d atoms=%d action=%d", d->proprio, d->proj,
+                d->hidden, d->atoms, d->action);
+      return SQ_EINVAL;
+    }
+    if (d->proj > 1024 || d->hidden > 1024 || d->atoms > 256) {
+      set_error("widths above the kernel limits (proj, hidden <= 1024, atoms <= 256)");
+      return SQ_EINVAL;
+    }
+    if (d->atoms > 1 && !(d->v_max > d->v_min)) { set_error("need v_max > v_min"); return SQ_EINVAL; }
+    *n = Net{};
+    n->d = *d;
+    n->flat = d->proprio;
+    n->cin_critic = d->proj + d->proprio + d->action;
+    n->cin_actor = d->proj + d->proprio;
+    n->cpad = (n->cin_critic + 7) / 8 * 8;
+    n->apad = (n->cin_actor + 7) / 8 * 8;
+    return SQ_OK;
+  }
   if (d->C <= 0 || d->H <= 0 || d->W <= 0 || d->k <= 0 || d->H % d->k || d->W % d->k || d->H != d->W) {
     set_error("bad frame dims C=%d H=%d W=%d k=%d (need square frames with H %% k == 0)", d->C, d->H, d->W, d->k);
     return SQ_EINVAL;

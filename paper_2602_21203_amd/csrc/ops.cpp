@@ -71,6 +71,11 @@ static int grads(int bf16, const GemmProb& dx, const GemmProb* dw, float* split,
 void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
   const sq_dims& d = net.d;
   for (int i = 0; i < 4; ++i) e->h[i] = nullptr;
+  if (d.n_conv == 0) {   // state-based: no encoder
+    e->dh[0] = e->dh[1] = nullptr;
+    e->split = e->bias_part = e->enc_part = e->wprep = nullptr;
+    return;
+  }
   for (int i = 0; i < d.n_conv; ++i)
     e->h[i] = b.take<float>((size_t)n * d.F * net.conv_side[i] * net.conv_side[i]);
   e->dh[0] = e->dh[1] = nullptr;

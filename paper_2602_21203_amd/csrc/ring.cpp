@@ -56,6 +56,10 @@ extern "C" {
 int sq_ring_create(const sq_dims* dims, int capacity, sq_ring** out) {
   Net net;
   SQ_TRY(make_net(dims, &net));
+  if (net.d.n_conv == 0) {
+    set_error("state-based dims (n_conv = 0) have no frames to store");
+    return SQ_EINVAL;
+  }
   if (!out || capacity <= 0) {
     set_error("bad ring arguments (out %p, capacity %d)", (void*)out, capacity);
     return SQ_EINVAL;

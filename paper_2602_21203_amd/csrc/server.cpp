@@ -102,7 +102,7 @@ static int launch_batch(sq_server* s, Slot& sl) {
   int r = 0;
   for (const Req& q : sl.batch)
     for (int i = 0; i < q.n; ++i, ++r) {
-      h.frames[r] = q.frames + (long long)i * frame_bytes;
+      h.frames[r] = q.frames ? q.frames + (long long)i * frame_bytes : nullptr;
       h.prop[r] = q.proprio ? q.proprio + (long long)i * d.proprio : nullptr;
       h.out[r] = q.out + (long long)i * d.action;
       h.ids[r] = q.id;
@@ -114,11 +114,15 @@ static int launch_batch(sq_server* s, Slot& sl) {
   hipStream_t st = sl.st;
   SQ_TRY_HIP(hipMemcpyAsync(sl.dtab, sl.htab, tables_bytes(cap), hipMemcpyHostToDevice, st));
   const int bf = s->hp.prec == SQ_BF16;
-  SQ_TRY(launch_squint_rows(t.frames, n, d.H, d.W, d.C, d.k, sl.w.x, st));
-  SQ_TRY(encoder_forward(s->net, bf, s->params, s->L, sl.w.x, n, sl.w.e, st));
+  if (d.n_conv > 0) {
+    SQ_TRY(launch_squint_rows(t.frames, n, d.H, d.W, d.C, d.k, sl.w.x, st));
+    SQ_TRY(encoder_forward(s->net, bf, s->params, s->L, sl.w.x, n, sl.w.e, st));
+  }
   if (d.proprio > 0) SQ_TRY(gather_rows((const float* const*)t.prop, d.proprio, n, sl.prop_stage, st));
   SQ_TRY(act_noise_rows(s->hp.seed, t.ids, t.rows, t.sample, n, d.action, sl.w.noise, st));
-  SQ_TRY(actor_forward(s->net, bf, s->params + s->L.actor_begin, agent_pack(s->agent), s->L, sl.w.e.h[d.n_conv - 1],
+  // state-based: the gathered states are the features
+  const float* feat = d.n_conv > 0 ? sl.w.e.h[d.n_conv - 1] : sl.prop_stage;
+  SQ_TRY(actor_forward(s->net, bf, s->params + s->L.actor_begin, agent_pack(s->agent), s->L, feat,
                        s->net.flat,
                        sl.prop_stage, d.proprio, sl.w.noise, n, s->hp.log_std_min, s->hp.log_std_max, sl.act_stage,
                        nullptr, sl.w.a, st));
@@ -256,7 +260,7 @@ int sq_server_create(sq_agent* agent, size_t mem_budget, int max_batch_obs, int 
 
 int sq_server_submit(sq_server* s, const uint8_t* frames, const float* proprio, int n, int sample,
                      unsigned long long request_id, float* action_out, sq_done_cb cb, void* user) {
-  if (!s || !frames || !action_out || (s->net.d.proprio > 0 && !proprio) || n <= 0) {
+  if (!s || (s->net.d.n_conv > 0 && !frames) || !action_out || (s->net.d.proprio > 0 && !proprio) || n <= 0) {
     set_error("bad request arguments");
     return SQ_EINVAL;
   }

@@ -51,7 +51,9 @@ def oracle_run(name, B, cap, prec, n_updates, policy_freq=1):
 
 @pytest.mark.parametrize("name,B,cap,prec", [("tiny", 32, 4096, 0), ("full", 512, 2048, 0),
                                              ("tiny", 32, 4096, 1), ("full", 512, 2048, 1),
-                                             ("full32", 128, 512, 0), ("full32", 128, 512, 1)])
+                                             ("full32", 128, 512, 0), ("full32", 128, 512, 1),
+                                             ("state_tiny", 32, 256, 0), ("state", 512, 2048, 0),
+                                             ("state", 512, 2048, 1)])
 def test_one_update_matches_oracle(name, B, cap, prec):
     print(f"update parity {name} B={B} prec={prec}", flush=True)
     ag, stats = gpu_run(name, B, cap, prec, 1)
@@ -116,7 +118,7 @@ def test_full_size_batch_2048_runs_and_is_finite():
     assert np.all(np.isfinite(stats)) and np.all(stats[:, 7] == 0)
 
 
-@pytest.mark.parametrize("name,prec", [("tiny", 0), ("full", 0), ("full", 1)])
+@pytest.mark.parametrize("name,prec", [("tiny", 0), ("full", 0), ("full", 1), ("state", 0)])
 def test_act_matches_oracle(name, prec):
     cfg = H.cfg(name)
     d = H.odims(name)
