@@ -90,6 +90,7 @@ struct sq_agent {
   std::vector<GraphEntry> graphs;
   PackArgs pk_critic, pk_actor;   // pack refresh tables of the two Adam launches
   GradSegs gs_critic, gs_actor;   // bias / gain / shift gradients the Adam launches sum from partials
+  bool enc_seg = false;           // gs_critic also sums the fused encoder's partial gradients
 };
 
 static size_t plan_agent(sq_agent* g, char* base) {
@@ -173,7 +174,8 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
                      hp.cdq, g->mt, g->tgt_row, g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st));
   SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
                          image ? g->dfeat : nullptr, nullptr, st, true, true));
-  if (image) SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true));
+  // the fused encoder's partial gradients are summed by the critic Adam launch
+  if (image) SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true, g->enc_seg));
   // critic + encoder Adam (with the target EMA and the packed copies), and the
   // temperature step in one extra workgroup of the same launch
   const AlphaJob aj{g->logp2B, B, hp.target_entropy, P + L.log_alpha, G + L.log_alpha, g->m + L.log_alpha,
@@ -287,6 +289,14 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
     g->pk_critic.p_begin = 0;
     g->pk_actor.p_begin = L.actor_begin;
     critic_grad_segs(g->net, L, g->crit, g->B, &g->gs_critic);
+    GradSeg es;
+    if (encoder_grad_seg(g->net, L, g->enc, g->B, &es)) {
+      // the encoder block comes first in the flat vector, so the list stays sorted
+      for (int i = g->gs_critic.n; i > 0; --i) g->gs_critic.s[i] = g->gs_critic.s[i - 1];
+      g->gs_critic.s[0] = es;
+      ++g->gs_critic.n;
+      g->enc_seg = true;
+    }
     actor_grad_segs(g->net, L, g->actor, g->B, &g->gs_actor);
     g->gs_critic.gout = g->grads;
     g->gs_actor.gout = g->grads + L.actor_begin;

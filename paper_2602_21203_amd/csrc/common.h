@@ -206,6 +206,9 @@ int conv_dx(int bf16, const float* dout, const float* out, int n, int Cin, int H
 // (l < n_conv - 1) are [n][pixel][F]; the last one is NCHW (the feature vector).
 bool encoder_fused_ok(int C, int F, int n_conv, int side);
 size_t encoder_fused_part_floats(int n, long long enc_total);
+// partial-gradient rows the fused backward writes for n images ([rows][enc_total],
+// summed in row order as a GradSeg would); grad == nullptr leaves them unsummed
+int encoder_fused_part_rows(int n);
 size_t encoder_fused_prep_floats(int C, int F, int n_conv);
 int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W, float* wp, hipStream_t st);
 int encoder_fused_fwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* wp,

@@ -428,6 +428,8 @@ static int enc_fwd_t(const float* x, int n, const float* wp, const float* const*
   return launch_status("encoder_fwd");
 }
 
+int encoder_fused_part_rows(int n) { return cdiv(n, kEncBwdG); }
+
 template <bool BF16, int C, int F, int NC>
 static int enc_bwd_t(const float* x, int n, const float* dfeat, const float* wp, const float* const* h,
                      const long long* Woff, const long long* boff, long long total, float* part, float* grad,
@@ -441,6 +443,7 @@ static int enc_bwd_t(const float* x, int n, const float* dfeat, const float* wp,
   k_encoder_bwd<BF16, kEncBwdG, C, F, NC, kEncBwdThreads><<<nwg, kEncBwdThreads, 0, st>>>(
       x, n, dfeat, wp, h[0], h[1], NC > 2 ? h[2] : h[1], off, total, part);
   SQ_TRY(launch_status("encoder_bwd"));
+  if (!grad) return SQ_OK;   // the caller sums the partials (an optimiser segment)
   k_enc_reduce<<<(int)cdiv(total, 256), 256, 0, st>>>(part, nwg, total, grad);
   return launch_status("encoder_reduce");
 }

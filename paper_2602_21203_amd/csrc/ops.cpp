@@ -127,9 +127,15 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
   return SQ_OK;
 }
 
+bool encoder_grad_seg(const Net& net, const Layout& L, const EncBufs& e, int n, GradSeg* seg) {
+  if (!e.enc_part || net.d.n_conv == 0) return false;
+  *seg = GradSeg{L.enc_begin, (int)(L.enc_end - L.enc_begin), encoder_fused_part_rows(n), e.enc_part};
+  return true;
+}
+
 int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                      const float* dfeat, const EncBufs& e, float* dep, hipStream_t st,
-                     bool prepared) {
+                     bool prepared, bool defer_reduce) {
   const sq_dims& d = net.d;
   if (e.enc_part) {
     const float* W[4];
@@ -142,8 +148,8 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
       bo[i] = L.conv_b[i];
     }
     if (!prepared) SQ_TRY(encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st));
-    return encoder_fused_bwd(bf16, d.C, d.F, d.n_conv, x, n, dfeat, e.wprep, h, Wo, bo, L.enc_end, e.enc_part, dep,
-                             st);
+    return encoder_fused_bwd(bf16, d.C, d.F, d.n_conv, x, n, dfeat, e.wprep, h, Wo, bo, L.enc_end, e.enc_part,
+                             defer_reduce ? nullptr : dep, st);
   }
   const float* dh = dfeat;
   for (int i = d.n_conv - 1; i >= 0; --i) {

@@ -21,9 +21,13 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
                     const EncBufs& e, hipStream_t st);
 // prepared: the fused path's rearranged weights from encoder_forward of the same
 // parameters and precision are still in e.wprep (inside one update)
+// defer_reduce (fused path only): leave the per-workgroup partial gradients in
+// e.enc_part for the optimiser (encoder_grad_seg describes them); dep unused then
 int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                      const float* dfeat, const EncBufs& e, float* dep, hipStream_t st,
-                     bool prepared = false);
+                     bool prepared = false, bool defer_reduce = false);
+// the fused encoder's partial gradients as an optimiser segment (false: no fused path)
+bool encoder_grad_seg(const Net& net, const Layout& L, const EncBufs& e, int n, GradSeg* seg);
 
 struct DenseSave { float* xhat; float* rstd; };
 struct CriticBufs {
