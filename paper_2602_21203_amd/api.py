@@ -377,6 +377,11 @@ class Agent:
         caller.wait_stream(self.stream)
         return stats
 
+    def sync(self, stream=None):
+        """Refresh the agent's derived weight copies after params / target were
+        changed from outside (sq_agent_sync)."""
+        check(L.LIB.sq_agent_sync(self.handle, stream_handle(stream)))
+
     def act(self, frames, proprio, sample=False, request_id=0, out=None, stream=None):
         n = frames.shape[0]
         _req(frames, torch.uint8, (n, self.cfg["H"], self.cfg["W"], self.cfg["C"]), "frames")

@@ -91,6 +91,7 @@ struct sq_agent {
   PackArgs pk_critic, pk_actor;   // pack refresh tables of the two Adam launches
   GradSegs gs_critic, gs_actor;   // bias / gain / shift gradients the Adam launches sum from partials
   bool enc_seg = false;           // gs_critic also sums the fused encoder's partial gradients
+  EncPrepMap enc_map{};           // the critic Adam keeps enc.wprep current (enc_map.n > 0)
 };
 
 static size_t plan_agent(sq_agent* g, char* base) {
@@ -155,7 +156,7 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
       SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, net.side, net.side, d.C, 1, g->x, st));
     else
       SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, d.H, d.W, d.C, d.k, g->x, st));
-    SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st));
+    SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st, g->enc_map.n > 0));
     feat = g->enc.h[d.n_conv - 1];
   }
   SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
@@ -181,7 +182,7 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   const AlphaJob aj{g->logp2B, B, hp.target_entropy, P + L.log_alpha, G + L.log_alpha, g->m + L.log_alpha,
                     g->v + L.log_alpha, g->ctr, g->scal};
   SQ_TRY(adam(P, G, g->m, g->v, L.critic_end, &hp, g->ctr + CTR_TC, g->target, L.critic_begin, nullptr, &g->pk_critic,
-              st, &g->gs_critic, &aj));
+              st, &g->gs_critic, &aj, g->enc_map.n > 0 ? &g->enc_map : nullptr));
   // delayed actor step against the updated critic
   if (actor_step) {
     SQ_TRY(critic_forward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->S2, S, g->act2B, A, B, g->logits_q,
@@ -289,6 +290,9 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
     g->pk_critic.p_begin = 0;
     g->pk_actor.p_begin = L.actor_begin;
     critic_grad_segs(g->net, L, g->crit, g->B, &g->gs_critic);
+    if (g->net.d.n_conv > 0)
+      (void)encoder_fused_prep_map(g->net.d.C, g->net.d.F, g->net.d.n_conv, g->net.side, L.conv_W, g->enc.wprep,
+                                   hp->prec == SQ_BF16, &g->enc_map);
     GradSeg es;
     if (encoder_grad_seg(g->net, L, g->enc, g->B, &es)) {
       // the encoder block comes first in the flat vector, so the list stays sorted
@@ -302,6 +306,7 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
     g->gs_actor.gout = g->grads + L.actor_begin;
   }
   if (pack_weights(g->L, params, target, g->pack, g->tpack, nullptr) != SQ_OK ||
+      encoder_prepare(g->net, hp->prec == SQ_BF16, params, g->L, g->enc, nullptr) != SQ_OK ||
       hipDeviceSynchronize() != hipSuccess) {
     (void)hipFree(g->ws);
     delete g;
@@ -410,7 +415,8 @@ int act(sq_agent* g, const uint8_t* frames, const float* proprio, int n, int sam
 
 int sq_agent_sync(sq_agent* g, sq_stream_t stream) {
   if (!g) { set_error("agent is NULL"); return SQ_EINVAL; }
-  return pack_weights(g->L, g->params, g->target, g->pack, g->tpack, (hipStream_t)stream);
+  SQ_TRY(pack_weights(g->L, g->params, g->target, g->pack, g->tpack, (hipStream_t)stream));
+  return encoder_prepare(g->net, g->hp.prec == SQ_BF16, g->params, g->L, g->enc, (hipStream_t)stream);
 }
 
 int sq_agent_act_capacity(sq_agent* g, int* n) {

@@ -86,6 +86,8 @@ struct Bump {
   }
 };
 
+struct EncPrepMap;   // (defined with the optimiser's arguments below)
+
 // ------------------------------------------------------------------ kernel launchers
 // Every launcher enqueues on `st` and returns SQ_OK or SQ_EDEVICE.
 
@@ -209,6 +211,10 @@ size_t encoder_fused_part_floats(int n, long long enc_total);
 // partial-gradient rows the fused backward writes for n images ([rows][enc_total],
 // summed in row order as a GradSeg would); grad == nullptr leaves them unsummed
 int encoder_fused_part_rows(int n);
+// the prepared-copy map of the fused encoder (false when the geometry has no fused path);
+// W: flat offsets of the conv weights
+bool encoder_fused_prep_map(int C, int F, int n_conv, int side, const long long* W, float* wp, int bf16,
+                            EncPrepMap* m);
 size_t encoder_fused_prep_floats(int C, int F, int n_conv);
 int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W, float* wp, hipStream_t st);
 int encoder_fused_fwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* wp,
@@ -297,6 +303,16 @@ struct PackArgs {
 // stores it at gout[i] (the writable gradient vector of the range).
 struct GradSeg { long long begin; int H, nrows; const float* part; };
 struct GradSegs { int n; GradSeg s[20]; float* gout; };
+// Where the encoder's conv weights sit in the fused encoder's prepared copy: per
+// layer the forward order [f][tap][CP] at fb and, above the first layer, the
+// input-gradient order [tap][c][f] at bb (values rounded to bfloat16 when bf16).
+// An Adam launch given this map rewrites the prepared copy with every conv weight
+// it updates, so the copy never needs a separate preparation launch.
+struct EncPrepMap {
+  float* wp; int n, F, bf16;
+  long long lo, hi;   // flat range of the conv weights (relative to the optimiser's range)
+  long long W[4]; int cin[4], cp[4]; long long fb[4], bb[4];
+};
 // The temperature step (Alg. 1), run by one extra workgroup of an Adam launch.
 // scal receives [0] alpha before, [1] alpha after, [2] alpha loss, [3] mean(-log pi).
 struct AlphaJob {
@@ -305,7 +321,7 @@ struct AlphaJob {
 };
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
          float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st,
-         const GradSegs* gs = nullptr, const AlphaJob* aj = nullptr);
+         const GradSegs* gs = nullptr, const AlphaJob* aj = nullptr, const EncPrepMap* ep = nullptr);
 // copy the linear weights of `params` (and the critic block of `target`) into packs
 int pack_weights(const Layout& L, const float* params, const float* target, float* pack, float* tpack,
                  hipStream_t st);

@@ -76,7 +76,21 @@ struct AdamArgs {
   float* p; const float* g; float* m; float* v; long long n;
   float lr, b1, b2, eps;
   const int* step; float* ema; long long ema_begin; float rho; uint16_t* shadow;
+  EncPrepMap ep;   // ep.n == 0: no prepared encoder copy to refresh
 };
+
+// conv weight i (updated to v) in the fused encoder's prepared copy
+__device__ __forceinline__ void enc_prep_put(const EncPrepMap& e, long long i, float v) {
+  const float w = e.bf16 ? bf16_round(v) : v;
+  for (int l = 0; l < e.n; ++l) {
+    const long long o = i - e.W[l];
+    if (o < 0 || o >= (long long)e.F * e.cin[l] * 9) continue;
+    const int oi = (int)o, k = e.cin[l] * 9;
+    const int f = oi / k, r = oi - f * k, c = r / 9, tap = r - 9 * c;
+    e.wp[e.fb[l] + (long long)(f * 9 + tap) * e.cp[l] + c] = w;
+    if (l > 0) e.wp[e.bb[l] + (long long)(tap * e.cin[l] + c) * e.F + f] = w;
+  }
+}
 
 // the update of parameter i with gradient gi (packed copy position from segment s0 when it holds i)
 __device__ __forceinline__ void adam_elem(const AdamArgs& A, const PackArgs& pk, long long i, float gi, float bc1,
@@ -87,6 +101,7 @@ __device__ __forceinline__ void adam_elem(const AdamArgs& A, const PackArgs& pk,
   A.v[i] = vi;
   const float pi = A.p[i] - A.lr * (mi / bc1) / (sqrtf(vi / bc2) + A.eps);
   A.p[i] = pi;
+  if (A.ep.n && i >= A.ep.lo && i < A.ep.hi) enc_prep_put(A.ep, i, pi);
   float ei = 0.f;
   if (A.ema && i >= A.ema_begin) {
     float* e = A.ema + (i - A.ema_begin);
@@ -181,7 +196,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs 
 
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
          float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st,
-         const GradSegs* gs, const AlphaJob* aj) {
+         const GradSegs* gs, const AlphaJob* aj, const EncPrepMap* ep) {
   if (n <= 0 && !aj) return SQ_OK;
   const long long blocks = n > 0 ? (n + 256 * kAdamPer - 1) / (256 * kAdamPer) : 0;
   PackArgs none{};
@@ -206,7 +221,7 @@ int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hpa
     }
   }
   const AdamArgs A{p, g, m, v, n, hp->lr, hp->beta1, hp->beta2, hp->adam_eps, step, ema_target, ema_begin, hp->rho,
-                   shadow};
+                   shadow, ep ? *ep : EncPrepMap{}};
   k_adam<<<(unsigned)(blocks + seg_blocks + (aj ? 1 : 0)), 256, 0, st>>>(A, pk ? *pk : none, gs ? *gs : nogs,
                                                                          (int)blocks, aj ? *aj : noaj, aj ? 1 : 0);
   return launch_status("adam");

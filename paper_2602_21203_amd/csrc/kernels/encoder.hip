@@ -430,6 +430,37 @@ static int enc_fwd_t(const float* x, int n, const float* wp, const float* const*
 
 int encoder_fused_part_rows(int n) { return cdiv(n, kEncBwdG); }
 
+template <int C, int F, int NC>
+static void prep_map_t(const long long* W, EncPrepMap* m) {
+  using E = EncPrep<C, F, NC>;
+  m->n = NC;
+  m->F = F;
+  const long long fb[3] = {E::F0, E::F1, E::F2}, bb[3] = {-1, E::B1, E::B2};
+  const int cp[3] = {LG<C, F, 0>::CP, LG<C, F, 1>::CP, LG<C, F, 2>::CP};
+  m->lo = W[0];
+  m->hi = W[0];
+  for (int l = 0; l < NC; ++l) {
+    m->W[l] = W[l];
+    m->cin[l] = l == 0 ? C : F;
+    m->cp[l] = cp[l];
+    m->fb[l] = fb[l];
+    m->bb[l] = bb[l];
+    const long long end = W[l] + (long long)F * m->cin[l] * 9;
+    m->hi = end > m->hi ? end : m->hi;
+  }
+}
+
+bool encoder_fused_prep_map(int C, int F, int n_conv, int side, const long long* W, float* wp, int bf16,
+                            EncPrepMap* m) {
+  if (!encoder_fused_ok(C, F, n_conv, side) || !wp) return false;
+  *m = EncPrepMap{};
+  if (C == 9 && F == 32 && n_conv == 3) prep_map_t<9, 32, 3>(W, m);
+  else prep_map_t<3, 16, 2>(W, m);
+  m->wp = wp;
+  m->bf16 = bf16;
+  return true;
+}
+
 template <bool BF16, int C, int F, int NC>
 static int enc_bwd_t(const float* x, int n, const float* dfeat, const float* wp, const float* const* h,
                      const long long* Woff, const long long* boff, long long total, float* part, float* grad,

@@ -101,19 +101,25 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
   }
 }
 
+int encoder_prepare(const Net& net, int bf16, const float* ep, const Layout& L, const EncBufs& e, hipStream_t st) {
+  const sq_dims& d = net.d;
+  if (!e.wprep) return SQ_OK;
+  const float* W[4];
+  for (int i = 0; i < d.n_conv; ++i) W[i] = ep + L.conv_W[i];
+  return encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st);
+}
+
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
-                    const EncBufs& e, hipStream_t st) {
+                    const EncBufs& e, hipStream_t st, bool prepared) {
   const sq_dims& d = net.d;
   if (e.wprep) {
-    const float* W[4];
     const float* b[4];
     float* h[4];
     for (int i = 0; i < d.n_conv; ++i) {
-      W[i] = ep + L.conv_W[i];
       b[i] = ep + L.conv_b[i];
       h[i] = e.h[i];
     }
-    SQ_TRY(encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st));
+    if (!prepared) SQ_TRY(encoder_prepare(net, bf16, ep, L, e, st));
     return encoder_fused_fwd(bf16, d.C, d.F, d.n_conv, x, n, e.wprep, b, h, st);
   }
   const float* in = x;

@@ -17,8 +17,12 @@ struct EncBufs {
   float* enc_part;    // per-workgroup partial gradients of the fused encoder backward
 };
 void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd);
+// prepared: e.wprep already holds the rearranged weights of these parameters
+// (kept current by the optimiser through an EncPrepMap)
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
-                    const EncBufs& e, hipStream_t st);
+                    const EncBufs& e, hipStream_t st, bool prepared = false);
+// rewrite e.wprep from the parameters (fused path only; no-op otherwise)
+int encoder_prepare(const Net& net, int bf16, const float* ep, const Layout& L, const EncBufs& e, hipStream_t st);
 // prepared: the fused path's rearranged weights from encoder_forward of the same
 // parameters and precision are still in e.wprep (inside one update)
 // defer_reduce (fused path only): leave the per-workgroup partial gradients in

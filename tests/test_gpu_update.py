@@ -185,3 +185,21 @@ def test_variant_update_matches_oracle(name, B, prec, atoms, cdq):
 
 def olayout_atoms(d):
     return d.v_min + np.arange(d.atoms) * ((d.v_max - d.v_min) / (d.atoms - 1))
+
+
+@pytest.mark.parametrize("name,B,cap,prec", [("tiny", 32, 4096, 0), ("tiny", 32, 4096, 1), ("full", 512, 2048, 1)])
+def test_optimiser_kept_encoder_weights_equal_a_fresh_preparation(name, B, cap, prec):
+    """The critic Adam launch rewrites the fused encoder's rearranged weights with
+    every conv weight it updates; an agent that instead re-prepares them from the
+    parameters before each update (sq_agent_sync) must follow bit for bit."""
+    cfg = H.cfg(name)
+    _, rep = replay(name, cap)
+    a = api.Agent(cfg, H.params(name), B, prec=prec)
+    b = api.Agent(cfg, H.params(name), B, prec=prec)
+    for _ in range(4):
+        s_a = a.sac_update(rep, 1, graph=False)
+        b.sync()
+        s_b = b.sac_update(rep, 1, graph=False)
+        torch.cuda.synchronize()
+        assert torch.equal(s_a, s_b)
+    assert torch.equal(a.params, b.params) and torch.equal(a.target, b.target)
