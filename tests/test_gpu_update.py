@@ -203,3 +203,47 @@ def test_optimiser_kept_encoder_weights_equal_a_fresh_preparation(name, B, cap, 
         torch.cuda.synchronize()
         assert torch.equal(s_a, s_b)
     assert torch.equal(a.params, b.params) and torch.equal(a.target, b.target)
+
+
+@pytest.mark.parametrize("B,prec", [(100, 0), (100, 1), (1, 0)])
+def test_ragged_batch_matches_oracle(B, prec):
+    """A batch that fills no tile evenly (100 rows: 3 full 32-row tiles and a
+    4-row tail; 1 row: a single partial tile) through every kernel of the update."""
+    name, cap = "tiny", 4096
+    print(f"ragged update B={B} prec={prec}", flush=True)
+    ag, stats = gpu_run(name, B, cap, prec, 1)
+    st, outs = oracle_run(name, B, cap, prec, 1)
+    names = ("critic_loss", "actor_loss", "alpha_loss", "alpha", "entropy", "mean_q", "mean_target")
+    for i, nm in enumerate(names):
+        H.assert_loss(float(stats[0][i]), float(outs[0]["stats"][i]), nm, outs[0]["stat_scale"][i],
+                      H.stat_rtol(prec, nm))
+    d = H.odims(name)
+    blk = olayout.blocks(d)
+    g = ag.grads.cpu().numpy().astype(np.float64)
+    tol = H.GRAD_RTOL if prec == 0 else H.GRAD_RTOL_BF16
+    H.assert_grads_per_tensor(g, outs[0]["g_enc_critic"], name, 0, 0, blk["critic"][1], tol)
+    H.assert_grads_per_tensor(g, outs[0]["g_actor"], name, 0, blk["actor"][0], blk["actor"][1], tol)
+
+
+def test_degenerate_targets_match_oracle():
+    """All-terminal transitions (the target collapses to the reward: a two-atom
+    projection of a point) and gamma = 0 (the same target through the discount)."""
+    name, B, cap = "tiny", 32, 256
+    cfg = H.cfg(name)
+    d = H.odims(name)
+    cpu = synthetic.replay(cap, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=5, done_rate=1.0)
+    assert int(cpu["done"].sum()) == cap
+    rep_np = H.np_replay(cpu)
+    rep = {k: (v.cuda() if torch.is_tensor(v) else v) for k, v in cpu.items()}
+    for gamma, rp, rg in ((0.99, rep_np, rep), (0.0, dict(rep_np, done=np.zeros_like(rep_np["done"])),
+                                                dict(rep, done=torch.zeros_like(rep["done"])))):
+        ag = api.Agent(cfg, H.params(name), B, gamma=gamma)
+        got = ag.sac_update(rg, 1).cpu().numpy()[0]
+        st = sac.new_state(d, H.params(name).astype(np.float64))
+        o = sac.sac_update(st, rp, d, sac.hparams(d, gamma=gamma), B)
+        # the target is the reward itself
+        np.testing.assert_allclose(o["tgt"], rp["reward"][o["idx"]], rtol=1e-12, atol=1e-12)
+        names = ("critic_loss", "actor_loss", "alpha_loss", "alpha", "entropy", "mean_q", "mean_target")
+        for i, nm in enumerate(names):
+            H.assert_loss(float(got[i]), float(o["stats"][i]), f"gamma {gamma} {nm}", o["stat_scale"][i])
+        ag.close()
