@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "ops.h"
+#include "kernels/sample.h"
 
 namespace sq {
 
@@ -145,17 +146,19 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   const float lo = hp.log_std_min, hi = hp.log_std_max;
   float* P = g->params;
   float* G = g->grads;
-  SQ_TRY(launch_sample_batch(hp.seed, g->ctr, R->size, R->dev_size, B, A, S, R->proprio, R->next_proprio, R->action,
-                             R->reward, R->done, g->idx, g->eps2B, g->S2, g->Arep, g->r, g->dn, st));
+  const SampleArgs sa = sample_args(hp.seed, g->ctr, R->size, R->dev_size, B, A, S, R->proprio, R->next_proprio,
+                                    R->action, R->reward, R->done, g->idx, g->eps2B, g->S2, g->Arep, g->r, g->dn);
   // state-based SAC: the sampled states [s; s'] (S2) are the features
   const bool image = d.n_conv > 0;
   const float* feat = g->S2;
+  if (!image || R->squinted) SQ_TRY(launch_sample_batch(sa, st));
   if (image) {
-    // frames squinted at insertion are the k = 1 squint of the stored block means
+    // frames squinted at insertion are the k = 1 squint of the stored block means;
+    // raw frames are drawn and squinted in one launch
     if (R->squinted)
       SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, net.side, net.side, d.C, 1, g->x, st));
     else
-      SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, d.H, d.W, d.C, d.k, g->x, st));
+      SQ_TRY(launch_sample_squint(sa, R->obs, R->next_obs, d.H, d.W, d.C, d.k, g->x, st));
     SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st, g->enc_map.n > 0));
     feat = g->enc.h[d.n_conv - 1];
   }

@@ -95,11 +95,18 @@ struct EncPrepMap;   // (defined with the optimiser's arguments below)
 enum { CTR_U = 0, CTR_TC = 1, CTR_TA = 2, CTR_TALPHA = 3, CTR_N = 4 };
 
 // rng.hip
-// dev_size (nullable): the replay's row count read on the device (growing ring)
-int launch_sample_batch(unsigned long long seed, const int* ctr, int size, const int* dev_size, int B, int A, int S,
-                        const float* proprio, const float* next_proprio, const float* action,
-                        const float* reward, const uint8_t* done, int* idx, float* eps2B, float* S2,
-                        float* Arep, float* r, float* d, hipStream_t st);
+// the update's minibatch draw (kernels/sample.h); dev_size (nullable): the
+// replay's row count read on the device (growing ring)
+struct SampleArgs;
+SampleArgs sample_args(unsigned long long seed, const int* ctr, int size, const int* dev_size, int B, int A, int S,
+                       const float* proprio, const float* next_proprio, const float* action, const float* reward,
+                       const uint8_t* done, int* idx, float* eps2B, float* S2, float* Arep, float* r, float* d);
+int launch_sample_batch(const SampleArgs& s, hipStream_t st);
+// the draw and the squint of the sampled obs / next_obs rows in one launch (the
+// squint workgroups compute their rows' indices themselves); falls back to two
+// launches where the fused squint kernel does not apply
+int launch_sample_squint(const SampleArgs& s, const uint8_t* obs, const uint8_t* next_obs, int H, int W, int C,
+                         int k, float* out, hipStream_t st);
 int launch_indices(unsigned long long seed, unsigned update, int size, int n, int* idx, hipStream_t st);
 int launch_gaussian(unsigned long long seed, unsigned update, unsigned stream_id, int n, float* out,
                     hipStream_t st);

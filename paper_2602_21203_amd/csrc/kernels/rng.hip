@@ -6,61 +6,27 @@
 //   act() noise   element e of a request: counter (e, 3, id_lo, id_hi)
 #include "../common.h"
 #include "philox.h"
+#include "sample.h"
 
 namespace sq {
 
 // One thread per (row, item): every thread redraws its row's index (one Philox
-// block) and moves one item -- a proprio value of s or s', an action value, one
-// of the row's 2 x A noise values, the reward or the done flag -- so the launch
-// is as wide as the batch's fields.  eps2B rows [0, B) = stream 2, rows [B, 2B) =
-// stream 1.
-__global__ __launch_bounds__(256) void k_sample_batch(unsigned k0, unsigned k1, const int* __restrict__ ctr,
-                                                      int size, const int* __restrict__ dev_size, int B, int A,
-                                                      int S,
-                                                      const float* __restrict__ proprio,
-                                                      const float* __restrict__ next_proprio,
-                                                      const float* __restrict__ action,
-                                                      const float* __restrict__ reward,
-                                                      const uint8_t* __restrict__ done, int* __restrict__ idx,
-                                                      float* __restrict__ eps2B, float* __restrict__ S2,
-                                                      float* __restrict__ Arep, float* __restrict__ r,
-                                                      float* __restrict__ d) {
-  const int W = 2 * S + 3 * A + 2;   // items per row
+// block) and moves one item, so the launch is as wide as the batch's fields.
+__global__ __launch_bounds__(256) void k_sample_batch(SampleArgs s) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (long long)B * W) return;
-  const int b = (int)(t / W), it = (int)(t - (long long)b * W);
-  const unsigned u = (unsigned)ctr[CTR_U];
-  if (it < 3 * A + 2 && it >= A && it < 3 * A) {   // noise: no replay access
-    const int j = (it - A) % A;
-    const unsigned s = it < 2 * A ? 2u : 1u;
-    const P4 g = philox10(P4{u, s, (unsigned)(b * A + j), 0u}, k0, k1);
-    eps2B[(long long)(s == 2u ? b : B + b) * A + j] = box_muller(g.x, g.y);
-    return;
-  }
-  const P4 w = philox10(P4{u, 0u, (unsigned)b, 0u}, k0, k1);
-  const int row = (int)__umulhi(w.x, (unsigned)(dev_size ? *dev_size : size));
-  if (it < A) {
-    Arep[(long long)b * A + it] = action[(long long)row * A + it];
-  } else if (it == 3 * A) {
-    r[b] = reward[row];
-    idx[b] = row;
-  } else if (it == 3 * A + 1) {
-    d[b] = done[row] ? 1.0f : 0.0f;
-  } else {
-    const int j = it - (3 * A + 2);
-    if (j < S) S2[(long long)b * S + j] = proprio[(long long)row * S + j];
-    else S2[(long long)(B + b) * S + (j - S)] = next_proprio[(long long)row * S + (j - S)];
-  }
+  if (t < sample_items(s.B, s.A, s.S)) sample_item(s, t);
 }
 
-int launch_sample_batch(unsigned long long seed, const int* ctr, int size, const int* dev_size, int B, int A, int S,
-                        const float* proprio, const float* next_proprio, const float* action,
-                        const float* reward, const uint8_t* done, int* idx, float* eps2B, float* S2,
-                        float* Arep, float* r, float* d, hipStream_t st) {
-  const long long items = (long long)B * (2 * S + 3 * A + 2);
-  k_sample_batch<<<(unsigned)((items + 255) / 256), 256, 0, st>>>((unsigned)seed, (unsigned)(seed >> 32), ctr, size,
-                                                                  dev_size, B, A, S, proprio, next_proprio, action, reward,
-                                                                  done, idx, eps2B, S2, Arep, r, d);
+SampleArgs sample_args(unsigned long long seed, const int* ctr, int size, const int* dev_size, int B, int A, int S,
+                       const float* proprio, const float* next_proprio, const float* action, const float* reward,
+                       const uint8_t* done, int* idx, float* eps2B, float* S2, float* Arep, float* r, float* d) {
+  return SampleArgs{(unsigned)seed, (unsigned)(seed >> 32), ctr, size, dev_size, B, A, S, proprio, next_proprio,
+                    action, reward, done, idx, eps2B, S2, Arep, r, d};
+}
+
+int launch_sample_batch(const SampleArgs& s, hipStream_t st) {
+  const long long items = sample_items(s.B, s.A, s.S);
+  k_sample_batch<<<(unsigned)((items + 255) / 256), 256, 0, st>>>(s);
   return launch_status("sample_batch");
 }
 

@@ -6,6 +6,7 @@
 // insertion, the uint8 block mean (HWC, nearest with ties to even) into a FIFO ring.
 #include "../common.h"
 #include "bf16.h"
+#include "sample.h"
 
 namespace sq {
 
@@ -109,22 +110,33 @@ typedef unsigned u4v __attribute__((ext_vector_type(4)));   // 16-byte load / st
 constexpr int kSquintCkLds = 40960;                 // LDS bytes of one k_squint_ck workgroup, at most
 constexpr int kSquintCkMax16 = kSquintCkLds / 16;   // its 16-byte loads (a multiple of 256)
 
+// sa.B > 0: the launch also draws the minibatch -- workgroups with blockIdx.y >=
+// n_img (blockIdx.x == 0) take the draw's items, and the image workgroups compute
+// their replay rows with the same Philox draw instead of reading idx
 template <int C, int K, int SIDE>
 __global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ src0,
                                                    const uint8_t* __restrict__ src1, const int* __restrict__ idx,
                                                    const uint8_t* const* __restrict__ row_ptrs, int nsplit, int W,
-                                                   int ry, SqDst dst) {
+                                                   int ry, SqDst dst, SampleArgs sa, int n_img) {
   static_assert(256 % SIDE == 0, "whole output rows per workgroup");
   constexpr int SEG = K * C;          // bytes of one block row
   static_assert(SEG % 4 == 0, "32-bit block rows");
   extern __shared__ __attribute__((aligned(16))) uint8_t tile[];
   const int img = blockIdx.y;
+  if (sa.B > 0 && img >= n_img) {
+    const long long t = (long long)(img - n_img) * 256 + threadIdx.x;
+    if (blockIdx.x == 0 && t < sample_items(sa.B, sa.A, sa.S)) sample_item(sa, t);
+    return;
+  }
   const int y0 = blockIdx.x * ry;
   const int row_bytes = W * C;            // one source pixel row
   const long long frame_bytes = (long long)row_bytes * W;
   const int chunk16 = ry * K * row_bytes / 16;
-  const u4v* g4 = reinterpret_cast<const u4v*>(source_row(src0, src1, idx, row_ptrs, nsplit, img, frame_bytes) +
-                                                 (long long)y0 * K * row_bytes);
+  const uint8_t* frame =
+      sa.B > 0 ? (img < nsplit ? src0 : src1) + (long long)sample_row(sa, img < nsplit ? img : img - nsplit) *
+                                                 frame_bytes
+               : source_row(src0, src1, idx, row_ptrs, nsplit, img, frame_bytes);
+  const u4v* g4 = reinterpret_cast<const u4v*>(frame + (long long)y0 * K * row_bytes);
   u4v* t4 = reinterpret_cast<u4v*>(tile);
   // every load of the chunk is in flight before the first LDS store
   u4v v[kSquintCkMax16 / 256];
@@ -193,7 +205,8 @@ static bool try_stored(const uint8_t* s0, const uint8_t* s1, const int* idx, con
 
 template <int C, int K, int SIDE>
 static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const uint8_t* const* rows, int nsplit,
-                   int n, int H, int W, int Cr, int kr, const SqDst& dst, hipStream_t st) {
+                   int n, int H, int W, int Cr, int kr, const SqDst& dst, hipStream_t st,
+                   const SampleArgs* sa = nullptr) {
   if (Cr != C || kr != K || H != SIDE * K || W != H) return false;
   if (dst.mode != kSqU8 && dst.row_stride != (long long)C * SIDE * SIDE) return false;
   const long long frame_bytes = (long long)H * W * C;
@@ -203,8 +216,12 @@ static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const u
   while (ry > 1 && ry * row_bytes > kSquintCkLds) ry /= 2;
   if (ry * row_bytes > kSquintCkLds) return false;
   if ((ry * row_bytes) % 16 != 0) return false;
-  dim3 grid(SIDE / ry, n);
-  k_squint_ck<C, K, SIDE><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, dst);
+  const SampleArgs none{};
+  const long long extra = sa ? (sample_items(sa->B, sa->A, sa->S) + 255) / 256 : 0;
+  if (n + extra > 65535) return false;   // grid y limit
+  dim3 grid(SIDE / ry, n + extra);
+  k_squint_ck<C, K, SIDE><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, dst, sa ? *sa : none,
+                                                             n);
   return true;
 }
 
@@ -259,6 +276,19 @@ int launch_squint_pair(const uint8_t* obs, const uint8_t* next_obs, const int* i
   const int side = H / k;
   const SqDst dst{kSqF32, out, nullptr, (long long)C * side * side, 0, 1, {}};
   return launch(obs, next_obs, idx, nullptr, B, 2 * B, H, W, C, k, dst, st);
+}
+
+int launch_sample_squint(const SampleArgs& s, const uint8_t* obs, const uint8_t* next_obs, int H, int W, int C,
+                         int k, float* out, hipStream_t st) {
+  const int side = H / k, B = s.B;
+  const SqDst dst{kSqF32, out, nullptr, (long long)C * side * side, 0, 1, {}};
+  if (B > 0 && (try_ck<9, 4, 16>(obs, next_obs, nullptr, nullptr, B, 2 * B, H, W, C, k, dst, st, &s) ||
+                try_ck<9, 8, 16>(obs, next_obs, nullptr, nullptr, B, 2 * B, H, W, C, k, dst, st, &s) ||
+                try_ck<3, 4, 16>(obs, next_obs, nullptr, nullptr, B, 2 * B, H, W, C, k, dst, st, &s) ||
+                try_ck<9, 4, 32>(obs, next_obs, nullptr, nullptr, B, 2 * B, H, W, C, k, dst, st, &s)))
+    return launch_status("sample_squint");
+  SQ_TRY(launch_sample_batch(s, st));
+  return launch_squint_pair(obs, next_obs, s.idx, B, H, W, C, k, out, st);
 }
 
 int launch_squint_rows(const uint8_t* const* rows, int n, int H, int W, int C, int k, float* out, hipStream_t st) {
