@@ -110,30 +110,31 @@ typedef unsigned u4v __attribute__((ext_vector_type(4)));   // 16-byte load / st
 constexpr int kSquintCkLds = 40960;                 // LDS bytes of one k_squint_ck workgroup, at most
 constexpr int kSquintCkMax16 = kSquintCkLds / 16;   // its 16-byte loads (a multiple of 256)
 
-// sa.B > 0: the launch also draws the minibatch -- workgroups with blockIdx.y >=
-// n_img (blockIdx.x == 0) take the draw's items, and the image workgroups compute
-// their replay rows with the same Philox draw instead of reading idx
+// lead > 0: the launch also draws the minibatch -- the first lead rows of
+// workgroups (blockIdx.x == 0; dispatched first, so their latency-bound draws
+// overlap the frame loads) take the draw's items, and the image workgroups
+// compute their replay rows with the same Philox draw instead of reading idx
 template <int C, int K, int SIDE>
 __global__ __launch_bounds__(256) void k_squint_ck(const uint8_t* __restrict__ src0,
                                                    const uint8_t* __restrict__ src1, const int* __restrict__ idx,
                                                    const uint8_t* const* __restrict__ row_ptrs, int nsplit, int W,
-                                                   int ry, SqDst dst, SampleArgs sa, int n_img) {
+                                                   int ry, SqDst dst, SampleArgs sa, int lead) {
   static_assert(256 % SIDE == 0, "whole output rows per workgroup");
   constexpr int SEG = K * C;          // bytes of one block row
   static_assert(SEG % 4 == 0, "32-bit block rows");
   extern __shared__ __attribute__((aligned(16))) uint8_t tile[];
-  const int img = blockIdx.y;
-  if (sa.B > 0 && img >= n_img) {
-    const long long t = (long long)(img - n_img) * 256 + threadIdx.x;
+  if ((int)blockIdx.y < lead) {
+    const long long t = (long long)blockIdx.y * 256 + threadIdx.x;
     if (blockIdx.x == 0 && t < sample_items(sa.B, sa.A, sa.S)) sample_item(sa, t);
     return;
   }
+  const int img = blockIdx.y - lead;
   const int y0 = blockIdx.x * ry;
   const int row_bytes = W * C;            // one source pixel row
   const long long frame_bytes = (long long)row_bytes * W;
   const int chunk16 = ry * K * row_bytes / 16;
   const uint8_t* frame =
-      sa.B > 0 ? (img < nsplit ? src0 : src1) + (long long)sample_row(sa, img < nsplit ? img : img - nsplit) *
+      lead > 0 ? (img < nsplit ? src0 : src1) + (long long)sample_row(sa, img < nsplit ? img : img - nsplit) *
                                                  frame_bytes
                : source_row(src0, src1, idx, row_ptrs, nsplit, img, frame_bytes);
   const u4v* g4 = reinterpret_cast<const u4v*>(frame + (long long)y0 * K * row_bytes);
@@ -221,7 +222,7 @@ static bool try_ck(const uint8_t* s0, const uint8_t* s1, const int* idx, const u
   if (n + extra > 65535) return false;   // grid y limit
   dim3 grid(SIDE / ry, n + extra);
   k_squint_ck<C, K, SIDE><<<grid, 256, ry * row_bytes, st>>>(s0, s1, idx, rows, nsplit, W, ry, dst, sa ? *sa : none,
-                                                             n);
+                                                             (int)extra);
   return true;
 }
 
