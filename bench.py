@@ -84,14 +84,15 @@ def squint_kernel_name(cfg, mode=""):
 def time_updates(agent, rep, utd, steps, warmup):
     import torch
     stats = torch.empty((utd, 8), dtype=torch.float32, device="cuda")
+    # the training loop issues its updates on the agent's own stream
     for _ in range(warmup):
-        agent.sac_update(rep, utd, stats=stats)
+        agent.sac_update(rep, utd, stats=stats, stream=agent.stream)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(agent.stream)
     for _ in range(steps):
-        agent.sac_update(rep, utd, stats=stats)
+        agent.sac_update(rep, utd, stats=stats, stream=agent.stream)
     ev1.record(agent.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -129,13 +130,23 @@ def graph_time(fn, reps):
 
 def squint_kernel_time(cfg, rep, B, reps):
     """Average duration of the squint gather kernel (2B frames, as inside the
-    update)."""
+    update).  Every launch of the timed graph gathers its own random rows, so
+    the frames come from HBM as in the update, not from a cache that a repeated
+    gather of the same rows would keep warm."""
     import torch
 
     from paper_2602_21203_amd import api
-    idx = torch.randint(0, rep["obs"].shape[0], (2 * B,), dtype=torch.int32, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    idxs = [torch.randint(0, rep["obs"].shape[0], (2 * B,), generator=g, dtype=torch.int32, device="cuda")
+            for _ in range(reps)]
     out = torch.empty((2 * B, cfg["C"], side_of(cfg), side_of(cfg)), dtype=torch.float32, device="cuda")
-    return graph_time(lambda: api.squint_downsample(cfg, rep["obs"], idx, out=out), reps)
+    calls = [0]
+
+    def one():
+        api.squint_downsample(cfg, rep["obs"], idxs[calls[0] % reps], out=out)
+        calls[0] += 1
+    return graph_time(one, reps)
 
 
 def measured_traffic(kernel_key, source):

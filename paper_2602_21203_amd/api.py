@@ -372,9 +372,15 @@ class Agent:
         _req(stats, torch.float32, (n_updates, L.N_STATS), "stats")
         fn = L.LIB.sac_update if graph else L.LIB.sac_update_eager
         caller = stream if stream is not None else torch.cuda.current_stream()
-        self.stream.wait_stream(caller)
+        # a caller already on the agent's stream is ordered by the stream itself;
+        # any other stream is joined both ways (each join costs a cross-stream
+        # wait on the device, so loops should pass stream=agent.stream)
+        joined = caller.cuda_stream != self.stream.cuda_stream
+        if joined:
+            self.stream.wait_stream(caller)
         check(fn(self.handle, ctypes.byref(rs), n_updates, ptr(stats), stream_handle(self.stream)))
-        caller.wait_stream(self.stream)
+        if joined:
+            caller.wait_stream(self.stream)
         return stats
 
     def sync(self, stream=None):

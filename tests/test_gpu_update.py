@@ -102,6 +102,23 @@ def test_graph_equals_eager_and_is_deterministic(prec):
     np.testing.assert_array_equal(s1, s3)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_updates_on_the_agent_stream_equal_the_joined_path(prec):
+    """Updates issued on the agent's own stream (no cross-stream joins), with the
+    replay filled on another stream beforehand, give the default path's results bit for bit."""
+    a1, s1 = gpu_run("tiny", 32, 4096, prec, 2, graph=True, chunks=2)
+    cfg = H.cfg("tiny")
+    _, rep = replay("tiny", 4096)
+    a2 = api.Agent(cfg, H.params("tiny"), 32, prec=prec)
+    torch.cuda.synchronize()
+    s2 = [a2.sac_update(rep, 2, stream=a2.stream) for _ in range(2)]
+    a2.stream.synchronize()
+    s2 = torch.cat(s2).cpu().numpy()
+    for attr in ("params", "target", "m", "v", "counters"):
+        assert torch.equal(getattr(a1, attr), getattr(a2, attr)), attr
+    np.testing.assert_array_equal(s1, s2)
+
+
 def test_delayed_actor_counters_and_stats():
     ag, stats = gpu_run("tiny", 32, 4096, 0, 3, graph=True, policy_freq=2)
     np.testing.assert_array_equal(ag.counters.cpu().numpy(), [3, 3, 2, 3])
