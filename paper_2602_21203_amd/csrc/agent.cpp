@@ -22,6 +22,7 @@
 
 #include "ops.h"
 #include "kernels/sample.h"
+#include "kernels/finish.h"
 
 namespace sq {
 
@@ -82,6 +83,7 @@ struct sq_agent {
   int* idx;
   float *eps2B, *S2, *Arep, *r, *dn, *x, *dfeat, *act2B, *logp2B, *logits_t, *logits, *logits_q, *mt, *dlogits,
       *dlogits_q, *loss_row, *q_row, *tgt_row, *qa_row, *scal, *da;
+  int* ta_snap;   // the actor Adam's step count, recorded by the critic Adam launch
   EncBufs enc;
   ActorBufs actor;
   CriticBufs crit, aux;
@@ -125,6 +127,7 @@ static size_t plan_agent(sq_agent* g, char* base) {
   g->tgt_row = b.take<float>(B);
   g->qa_row = b.take<float>(B);
   g->scal = b.take<float>(8);
+  g->ta_snap = b.take<int>(1);
   g->da = b.take<float>((size_t)B * A);
   g->pack = b.take<float>(g->L.pack_total);
   g->tpack = b.take<float>(g->L.pack_critic_end);
@@ -183,7 +186,7 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   // critic + encoder Adam (with the target EMA and the packed copies), and the
   // temperature step in one extra workgroup of the same launch
   const AlphaJob aj{g->logp2B, B, hp.target_entropy, P + L.log_alpha, G + L.log_alpha, g->m + L.log_alpha,
-                    g->v + L.log_alpha, g->ctr, g->scal};
+                    g->v + L.log_alpha, g->ctr, g->scal, actor_step ? g->ta_snap : nullptr};
   SQ_TRY(adam(P, G, g->m, g->v, L.critic_end, &hp, g->ctr + CTR_TC, g->target, L.critic_begin, nullptr, &g->pk_critic,
               st, &g->gs_critic, &aj, g->enc_map.n > 0 ? &g->enc_map : nullptr));
   // delayed actor step against the updated critic
@@ -198,11 +201,15 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
                            g->da, st));
     SQ_TRY(actor_backward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
                           1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st, true));
-    SQ_TRY(adam(P + L.actor_begin, G + L.actor_begin, g->m + L.actor_begin, g->v + L.actor_begin,
-                L.actor_end - L.actor_begin, &hp, g->ctr + CTR_TA, nullptr, 0, nullptr, &g->pk_actor, st, &g->gs_actor));
+    // the actor Adam launch also ends the update in its last workgroup; its step
+    // count is the one the critic launch recorded, since that workgroup advances
+    // the counters
+    const FinishJob fj{g->loss_row, g->q_row, g->tgt_row, g->logp2B, g->qa_row, g->scal, B, 1, g->ctr, stats};
+    return adam(P + L.actor_begin, G + L.actor_begin, g->m + L.actor_begin, g->v + L.actor_begin,
+                L.actor_end - L.actor_begin, &hp, g->ta_snap, nullptr, 0, nullptr, &g->pk_actor, st, &g->gs_actor,
+                nullptr, nullptr, &fj);
   }
-  return finish_update(g->loss_row, g->q_row, g->tgt_row, g->logp2B, g->qa_row, g->scal, B, actor_step, g->ctr, stats,
-                       st);
+  return finish_update(g->loss_row, g->q_row, g->tgt_row, g->logp2B, g->qa_row, g->scal, B, 0, g->ctr, stats, st);
 }
 
 static int check_replay(const sq_agent* g, const sq_replay* R) {

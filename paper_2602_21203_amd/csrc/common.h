@@ -322,13 +322,20 @@ struct EncPrepMap {
 };
 // The temperature step (Alg. 1), run by one extra workgroup of an Adam launch.
 // scal receives [0] alpha before, [1] alpha after, [2] alpha loss, [3] mean(-log pi).
+// step_snap (nullable): also records ctr[CTR_TA] there, the step count of the
+// actor's Adam launch that follows (which may then end the update itself)
 struct AlphaJob {
   const float* logp; int B; float target_entropy;
   float* log_alpha; float* grad; float* m; float* v; const int* ctr; float* scal;
+  int* step_snap;
 };
+struct FinishJob;
+// fj: the launch's last workgroup also ends the update (statistics, counter
+// advance); `step` must then not be one of the counters it advances
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
          float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st,
-         const GradSegs* gs = nullptr, const AlphaJob* aj = nullptr, const EncPrepMap* ep = nullptr);
+         const GradSegs* gs = nullptr, const AlphaJob* aj = nullptr, const EncPrepMap* ep = nullptr,
+         const FinishJob* fj = nullptr);
 // copy the linear weights of `params` (and the critic block of `target`) into packs
 int pack_weights(const Layout& L, const float* params, const float* target, float* pack, float* tpack,
                  hipStream_t st);

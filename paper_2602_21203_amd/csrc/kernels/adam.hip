@@ -5,6 +5,7 @@
 
 #include "../common.h"
 #include "bf16.h"
+#include "finish.h"
 
 namespace sq {
 
@@ -65,6 +66,7 @@ __device__ void alpha_block(const AlphaJob& j, float lr, float b1, float b2, flo
   *j.v = vv;
   *j.log_alpha = la2;
   if (j.grad) *j.grad = gr;
+  if (j.step_snap) *j.step_snap = j.ctr[CTR_TA];
   j.scal[0] = alpha;
   j.scal[1] = expf(la2);
   j.scal[2] = gr;
@@ -133,11 +135,16 @@ __device__ __forceinline__ void adam_elem(const AdamArgs& A, const PackArgs& pk,
 // partial-gradient segments.  Then one workgroup per 64 parameters of every
 // segment: wave w sums the partial rows w, w + 4, ... of its lane's parameter,
 // the four wave sums are added in wave order (the order colsum() uses), and wave
-// 0 applies the update.  With alpha_on, the last workgroup is the temperature step.
+// 0 applies the update.  With alpha_on, the last workgroup is the temperature
+// step; with fin_on, it ends the update (statistics and counters).
 __global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs gs, int main_blocks, AlphaJob aj,
-                                              int alpha_on) {
+                                              int alpha_on, FinishJob fj, int fin_on) {
   if (alpha_on && blockIdx.x == gridDim.x - 1) {
     alpha_block(aj, A.lr, A.b1, A.b2, A.eps);
+    return;
+  }
+  if (fin_on && blockIdx.x == gridDim.x - 1) {
+    finish_block(fj);
     return;
   }
   const float t = (float)(*A.step + 1);
@@ -196,8 +203,12 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs 
 
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
          float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st,
-         const GradSegs* gs, const AlphaJob* aj, const EncPrepMap* ep) {
-  if (n <= 0 && !aj) return SQ_OK;
+         const GradSegs* gs, const AlphaJob* aj, const EncPrepMap* ep, const FinishJob* fj) {
+  if (aj && fj) {
+    set_error("adam: the temperature step and the update's end cannot share a launch");
+    return SQ_EINVAL;
+  }
+  if (n <= 0 && !aj && !fj) return SQ_OK;
   const long long blocks = n > 0 ? (n + 256 * kAdamPer - 1) / (256 * kAdamPer) : 0;
   PackArgs none{};
   GradSegs nogs{};
@@ -222,8 +233,9 @@ int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hpa
   }
   const AdamArgs A{p, g, m, v, n, hp->lr, hp->beta1, hp->beta2, hp->adam_eps, step, ema_target, ema_begin, hp->rho,
                    shadow, ep ? *ep : EncPrepMap{}};
-  k_adam<<<(unsigned)(blocks + seg_blocks + (aj ? 1 : 0)), 256, 0, st>>>(A, pk ? *pk : none, gs ? *gs : nogs,
-                                                                         (int)blocks, aj ? *aj : noaj, aj ? 1 : 0);
+  const FinishJob nofj{};
+  k_adam<<<(unsigned)(blocks + seg_blocks + (aj || fj ? 1 : 0)), 256, 0, st>>>(
+      A, pk ? *pk : none, gs ? *gs : nogs, (int)blocks, aj ? *aj : noaj, aj ? 1 : 0, fj ? *fj : nofj, fj ? 1 : 0);
   return launch_status("adam");
 }
 

@@ -14,6 +14,7 @@
 
 #include "../common.h"
 #include "tgauss.h"
+#include "finish.h"
 
 namespace sq {
 
@@ -850,47 +851,12 @@ int expected_q_scalar(const float* q2, int B, float* dq2, float* qa_row, hipStre
   return launch_status("expected_q_scalar");
 }
 
-__global__ __launch_bounds__(256) void k_finish(const float* __restrict__ loss_row, const float* __restrict__ q_row,
-                                                const float* __restrict__ tgt_row, const float* __restrict__ logp,
-                                                const float* __restrict__ qa_row, const float* __restrict__ scal,
-                                                int B, int actor_step, int* __restrict__ ctr,
-                                                float* __restrict__ stats) {
-  __shared__ float sh[256];
-  float a = 0.f, q = 0.f, tg = 0.f, pi = 0.f;
-  const float alpha_new = scal[1];
-  for (int i = threadIdx.x; i < B; i += 256) {
-    a += loss_row[i] + loss_row[B + i];
-    q += q_row[i] + q_row[B + i];
-    tg += tgt_row[i];
-    if (actor_step) pi += alpha_new * logp[i] - qa_row[i];
-  }
-  a = block_sum256(a, sh);
-  q = block_sum256(q, sh);
-  tg = block_sum256(tg, sh);
-  pi = block_sum256(pi, sh);
-  if (threadIdx.x != 0) return;
-  float o[8];
-  o[0] = a / (float)B;
-  o[1] = actor_step ? pi / (float)B : 0.f;
-  o[2] = scal[2];
-  o[3] = alpha_new;
-  o[4] = scal[3];
-  o[5] = q / (float)(2 * B);
-  o[6] = tg / (float)B;
-  int bad = 0;
-  for (int i = 0; i < 7; ++i) bad |= !isfinite(o[i]);
-  o[7] = bad ? 1.f : 0.f;
-  for (int i = 0; i < 8; ++i) stats[i] = o[i];
-  ctr[CTR_U] += 1;
-  ctr[CTR_TC] += 1;
-  ctr[CTR_TALPHA] += 1;
-  if (actor_step) ctr[CTR_TA] += 1;
-}
+__global__ __launch_bounds__(256) void k_finish(FinishJob f) { finish_block(f); }
 
 int finish_update(const float* loss_row, const float* q_row, const float* tgt_row, const float* logp,
                   const float* qa_row, const float* scal, int B, int actor_step, int* ctr, float* stats,
                   hipStream_t st) {
-  k_finish<<<1, 256, 0, st>>>(loss_row, q_row, tgt_row, logp, qa_row, scal, B, actor_step, ctr, stats);
+  k_finish<<<1, 256, 0, st>>>(FinishJob{loss_row, q_row, tgt_row, logp, qa_row, scal, B, actor_step, ctr, stats});
   return launch_status("finish_update");
 }
 
