@@ -53,7 +53,10 @@ def oracle_run(name, B, cap, prec, n_updates, policy_freq=1):
                                              ("tiny", 32, 4096, 1), ("full", 512, 2048, 1),
                                              ("full32", 128, 512, 0), ("full32", 128, 512, 1),
                                              ("state_tiny", 32, 256, 0), ("state", 512, 2048, 0),
-                                             ("state", 512, 2048, 1)])
+                                             ("state", 512, 2048, 1),
+                                             # the other benchmarked shapes: batch 2048 in BF16, and the
+                                             # UTD-sweep shape (batch 1024, 128x128 frames squinted 8x)
+                                             ("full", 2048, 4096, 1), ("full128", 1024, 1024, 1)])
 def test_one_update_matches_oracle(name, B, cap, prec):
     print(f"update parity {name} B={B} prec={prec}", flush=True)
     ag, stats = gpu_run(name, B, cap, prec, 1)
@@ -65,7 +68,7 @@ def test_one_update_matches_oracle(name, B, cap, prec):
         H.assert_loss(float(got[i]), float(ref[i]), nm, outs[0]["stat_scale"][i], H.stat_rtol(prec, nm))
         print(f"  {nm}: gpu {got[i]:.7g} oracle {ref[i]:.7g} rel {abs(got[i] - ref[i]) / abs(ref[i]):.2e}")
     assert got[7] == 0.0
-    if prec == 1:
+    if prec == 1 and B <= 512:
         # report only: distance of the bfloat16 result from pure FP64
         _, o64 = oracle_run(name, B, cap, 0, 1)
         for i, nm in enumerate(names):
