@@ -131,28 +131,30 @@ __device__ __forceinline__ void adam_elem(const AdamArgs& A, const PackArgs& pk,
   }
 }
 
-// Workgroups [0, main): 256 * kAdamPer consecutive parameters each, skipping the
-// partial-gradient segments.  Then one workgroup per 64 parameters of every
-// segment: wave w sums the partial rows w, w + 4, ... of its lane's parameter,
-// the four wave sums are added in wave order (the order colsum() uses), and wave
-// 0 applies the update.  With alpha_on, the last workgroup is the temperature
-// step; with fin_on, it ends the update (statistics and counters).
-__global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs gs, int main_blocks, AlphaJob aj,
+// Workgroups are dispatched in index order, so the ones with the longest chains
+// of dependent loads come first.  With alpha_on, workgroup 0 is the temperature
+// step; with fin_on, it ends the update (statistics and counters).  Then one
+// workgroup per 64 parameters of every partial-gradient segment: wave w sums the
+// partial rows w, w + 4, ... of its lane's parameter, the four wave sums are
+// added in wave order (the order colsum() uses), and wave 0 applies the update.
+// The rest take 256 * kAdamPer consecutive parameters each, skipping the segments.
+__global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs gs, int seg_blocks, AlphaJob aj,
                                               int alpha_on, FinishJob fj, int fin_on) {
-  if (alpha_on && blockIdx.x == gridDim.x - 1) {
-    alpha_block(aj, A.lr, A.b1, A.b2, A.eps);
-    return;
-  }
-  if (fin_on && blockIdx.x == gridDim.x - 1) {
-    finish_block(fj);
-    return;
+  int bid = (int)blockIdx.x;
+  if (alpha_on || fin_on) {
+    if (bid == 0) {
+      if (alpha_on) alpha_block(aj, A.lr, A.b1, A.b2, A.eps);
+      else finish_block(fj);
+      return;
+    }
+    --bid;
   }
   const float t = (float)(*A.step + 1);
   const float bc1 = 1.f - powf(A.b1, t);
   const float bc2 = 1.f - powf(A.b2, t);
-  if ((int)blockIdx.x >= main_blocks) {
+  if (bid < seg_blocks) {
     __shared__ float sh[4][64];
-    int b = (int)blockIdx.x - main_blocks, q = 0;
+    int b = bid, q = 0;
     while (q < gs.n && b >= (gs.s[q].H + 63) / 64) b -= (gs.s[q++].H + 63) / 64;
     if (q >= gs.n) return;
     const GradSeg& e = gs.s[q];
@@ -181,7 +183,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs 
     }
     return;
   }
-  const long long b0 = (long long)blockIdx.x * 256 * kAdamPer;
+  const long long b0 = (long long)(bid - seg_blocks) * 256 * kAdamPer;
   int s0 = -1;
   for (int s = 0; s < pk.n; ++s) {
     const long long loc = b0 + pk.p_begin - pk.seg[s].src;
@@ -235,7 +237,7 @@ int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hpa
                    shadow, ep ? *ep : EncPrepMap{}};
   const FinishJob nofj{};
   k_adam<<<(unsigned)(blocks + seg_blocks + (aj || fj ? 1 : 0)), 256, 0, st>>>(
-      A, pk ? *pk : none, gs ? *gs : nogs, (int)blocks, aj ? *aj : noaj, aj ? 1 : 0, fj ? *fj : nofj, fj ? 1 : 0);
+      A, pk ? *pk : none, gs ? *gs : nogs, (int)seg_blocks, aj ? *aj : noaj, aj ? 1 : 0, fj ? *fj : nofj, fj ? 1 : 0);
   return launch_status("adam");
 }
 
