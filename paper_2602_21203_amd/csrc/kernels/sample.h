@@ -30,7 +30,7 @@ __device__ __forceinline__ void sample_item(const SampleArgs& s, long long t) {
   const int A = s.A, S = s.S, B = s.B;
   const int W = 2 * S + 3 * A + 2;   // items per row
   const int b = (int)(t / W), it = (int)(t - (long long)b * W);
-  if (it < 3 * A + 2 && it >= A && it < 3 * A) {   // noise: no replay access
+  if (it >= A && it < 3 * A) {   // noise: no replay access
     const unsigned u = (unsigned)s.ctr[CTR_U];
     const int j = (it - A) % A;
     const unsigned st = it < 2 * A ? 2u : 1u;
