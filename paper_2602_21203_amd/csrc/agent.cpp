@@ -165,12 +165,14 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
     SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st, g->enc_map.n > 0));
     feat = g->enc.h[d.n_conv - 1];
   }
+  SQ_TRY(trunks_forward(net, bf, P + L.actor_begin, P + L.critic_begin, g->target, g->pack, g->pack, g->tpack, L, feat,
+                        flat, B, g->actor, g->crit, st));
   SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
-                       g->logp2B, g->actor, st));
+                       g->logp2B, g->actor, st, true));
   // online critics on (z, s, a) and target critics on (z', s', a~') in one pass
   SQ_TRY(critic_forward_pair(net, bf, P + L.critic_begin, g->target, g->pack, g->tpack, L, feat, flat,
                              (long long)B * flat, g->S2, S, (long long)B * S, g->Arep, g->act2B + (size_t)B * A, A, B,
-                             g->logits, g->crit, st));
+                             g->logits, g->crit, st, true));
   // distributional soft target from the averaged twin target critics (projection),
   // and the online critics' cross entropy to it, in one pass over the rows
   if (N == 1)

@@ -674,6 +674,23 @@ __global__ __launch_bounds__(kThreads) void k_gemm_pair(RProb p0, RProb p1, int 
   }
 }
 
+// Two independent forward products (both operands row-coalesced) in one launch,
+// e.g. the actor's and the critics' input projections of the same features.
+template <bool BF16>
+__global__ __launch_bounds__(kThreads) void k_gemm_pair_f(RProb p0, RProb p1, int tiles0) {
+  __shared__ __attribute__((aligned(16))) char lds[gemm_lds_bytes<BF16, 1, 1>()];
+  const StPart none{nullptr, 0, 0, 1};
+  int b = blockIdx.x;
+  if (b < tiles0) {
+    gemm_tile<BF16, 1, 1, StMat, false>(p0.a, p0.b, p0.st, none, p0.M, p0.N, p0.K, p0.K, b % p0.gx,
+                                        (b / p0.gx) % p0.gy, b / (p0.gx * p0.gy), lds);
+  } else {
+    b -= tiles0;
+    gemm_tile<BF16, 1, 1, StMat, false>(p1.a, p1.b, p1.st, none, p1.M, p1.N, p1.K, p1.K, b % p1.gx,
+                                        (b / p1.gx) % p1.gy, b / (p1.gx * p1.gy), lds);
+  }
+}
+
 // sum of split-K partials in split order, then the real store
 template <class ST>
 __global__ void k_split_reduce(StPart sp, ST st, int batch) {
@@ -819,7 +836,10 @@ int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const flo
 int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, size_t scratch_floats,
               hipStream_t st) {
   const bool e0 = p0.M <= 0 || p0.N <= 0 || p0.batch <= 0, e1 = p1.M <= 0 || p1.N <= 0 || p1.batch <= 0;
-  const bool kinds = rkind(p0.A) == 1 && rkind(p0.B) == 0 && rkind(p1.A) == 0 && rkind(p1.B) == 0;
+  // (input gradient, weight gradient) of a layer, or two forward products
+  const bool grad_kinds = rkind(p0.A) == 1 && rkind(p0.B) == 0 && rkind(p1.A) == 0 && rkind(p1.B) == 0;
+  const bool fwd_kinds = rkind(p0.A) == 1 && rkind(p0.B) == 1 && rkind(p1.A) == 1 && rkind(p1.B) == 1;
+  const bool kinds = grad_kinds || fwd_kinds;
   const bool nosplit = want_splits(p0.M, p0.N, p0.K, p0.batch, scratch, scratch_floats) == 1 &&
                        want_splits(p1.M, p1.N, p1.K, p1.batch, scratch, scratch_floats) == 1;
   const bool kok = p0.A.kalt == p0.B.kalt && p1.A.kalt == p1.B.kalt &&
@@ -831,8 +851,13 @@ int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, 
   RProb q0{rmat(p0.A), rmat(p0.B), stmat(p0.C), p0.M, p0.N, p0.K, cdiv(p0.M, kTile), cdiv(p0.N, kTile)};
   RProb q1{rmat(p1.A), rmat(p1.B), stmat(p1.C), p1.M, p1.N, p1.K, cdiv(p1.M, kTile), cdiv(p1.N, kTile)};
   const int t0 = q0.gx * q0.gy * p0.batch, t1 = q1.gx * q1.gy * p1.batch;
-  if (bf16) k_gemm_pair<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
-  else k_gemm_pair<false><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+  if (fwd_kinds) {
+    if (bf16) k_gemm_pair_f<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+    else k_gemm_pair_f<false><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+  } else {
+    if (bf16) k_gemm_pair<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+    else k_gemm_pair<false><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+  }
   return launch_status("gemm_pair");
 }
 

@@ -237,10 +237,23 @@ int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack
 // runs as a batch of 2 nets, the twin layers as a batch of 4 (online twins, then
 // target twins), so every GEMM and LayerNorm launch covers both nets.  Both
 // weight sets are read from their packed copies.  logits4 [4][n][atoms].
+// the critics' input projections on the features of s (online weights, batch 0)
+// and of s' (target weights, batch 1): c.pre [2][n][proj]
+GemmProb critic_trunk_pair_prob(const Net& net, const float* cp, const float* tcp, const float* cpack,
+                                const float* tpack, const Layout& L, const float* feat, long long ld_feat,
+                                long long sz_feat, int n, const CriticBufs& c) {
+  const int P = net.d.proj;
+  const long long c0 = L.critic_begin;
+  const Dense& T = L.ctrunk;
+  GemmProb t{n, P, net.flat, 2, MatArg{feat, ld_feat, 1, sz_feat}, MatArg{cpack + T.Wp, T.ldp, 1, 0, tpack + T.Wp, 1},
+             OutArg{c.pre, P, (long long)n * P, cp + (T.b - c0), 0, 0, 0, tcp + (T.b - c0), 1}};
+  return t;
+}
+
 int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* tcp, const float* cpack,
                         const float* tpack, const Layout& L, const float* feat, long long ld_feat, long long sz_feat,
                         const float* s, long long ld_s, long long sz_s, const float* a, const float* ta,
-                        long long ld_a, int n, float* logits4, const CriticBufs& c, hipStream_t st) {
+                        long long ld_a, int n, float* logits4, const CriticBufs& c, hipStream_t st, bool trunk_done) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, N = d.atoms, cld = net.cpad;
   const long long c0 = L.critic_begin;
@@ -250,10 +263,10 @@ int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* 
   const Dense& T = L.ctrunk;
   const Twin& q = L.q[0];
   {
-    MatArg A{feat, ld_feat, 1, sz_feat};
-    MatArg Bm{cpack + T.Wp, T.ldp, 1, 0, tpack + T.Wp, 1};
-    OutArg C{c.pre, P, (long long)n * P, cp + (T.b - c0), 0, 0, 0, tcp + (T.b - c0), 1};
-    SQ_TRY(gemm(bf16, n, P, net.flat, 2, A, Bm, C, nullptr, 0, st));
+    if (!trunk_done) {
+      const GemmProb t = critic_trunk_pair_prob(net, cp, tcp, cpack, tpack, L, feat, ld_feat, sz_feat, n, c);
+      SQ_TRY(gemm(bf16, t.M, t.N, t.K, t.batch, t.A, t.B, t.C, nullptr, 0, st));
+    }
     const LnGroups grp{1, tcp + (T.g - c0), tcp + (T.beta - c0), sz_s, ta};
     SQ_TRY(ln_act_fwd(c.pre, P, (long long)n * P, n, P, 2, cp + (T.g - c0), cp + (T.beta - c0), 0, 1, c.X1, cld,
                       (long long)n * cld, c.t.xhat, c.t.rstd, s, ld_s, d.proprio, a, ld_a, d.action, st, &grp));
@@ -398,16 +411,38 @@ void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd) {
   }
 }
 
+// the actor's input projection: a.pre [n][proj]
+GemmProb actor_trunk_prob(const Net& net, const float* ap, const float* pack, const Layout& L, const float* feat,
+                          long long ld_feat, int n, const ActorBufs& a) {
+  const int P = net.d.proj;
+  const long long a0 = L.actor_begin;
+  const WRef w{ap, pack, a0};
+  const Dense& T = L.atrunk;
+  GemmProb t{n, P, net.flat, 1, MatArg{feat, ld_feat, 1, 0}, MatArg{w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 1, 0},
+             OutArg{a.pre, P, 0, ap + (T.b - a0), 0, 0, 0}};
+  return t;
+}
+
+int trunks_forward(const Net& net, int bf16, const float* ap, const float* cp, const float* tcp, const float* pack,
+                   const float* cpack, const float* tpack, const Layout& L, const float* feat, long long ld_feat, int B,
+                   const ActorBufs& a, const CriticBufs& c, hipStream_t st) {
+  return gemm_pair(bf16, actor_trunk_prob(net, ap, pack, L, feat, ld_feat, 2 * B, a),
+                   critic_trunk_pair_prob(net, cp, tcp, cpack, tpack, L, feat, ld_feat, (long long)B * ld_feat, B, c),
+                   nullptr, 0, st);
+}
+
 int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
                   long long ld_feat, const float* s, long long ld_s, const float* eps, int n, float lo, float hi,
-                  float* action, float* logp, const ActorBufs& a, hipStream_t st) {
+                  float* action, float* logp, const ActorBufs& a, hipStream_t st, bool trunk_done) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor, ald = net.apad;
   const long long a0 = L.actor_begin;
   const WRef w{ap, pack, a0};
   const Dense& T = L.atrunk;
-  SQ_TRY(linear_fwd(bf16, n, P, net.flat, 1, feat, ld_feat, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0, ap + (T.b - a0),
-                    0, a.pre, P, 0, st));
+  if (!trunk_done) {
+    const GemmProb t = actor_trunk_prob(net, ap, pack, L, feat, ld_feat, n, a);
+    SQ_TRY(gemm(bf16, t.M, t.N, t.K, t.batch, t.A, t.B, t.C, nullptr, 0, st));
+  }
   SQ_TRY(ln_act_fwd(a.pre, P, 0, n, P, 1, ap + (T.g - a0), ap + (T.beta - a0), 0, 1, a.X1, ald, 0, a.t.xhat,
                     a.t.rstd, s, ld_s, d.proprio, nullptr, 0, 0, st));
   SQ_TRY(linear_fwd(bf16, n, H, cin, 1, a.X1, ald, 0, w.W(L.al1.W, L.al1.Wp), w.ld(L.al1.in, L.al1.ldp), 0,

@@ -51,7 +51,12 @@ void plan_critic(const Net& net, int n, Bump& b, CriticBufs* c, bool with_bwd, i
 int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* tcp, const float* cpack,
                         const float* tpack, const Layout& L, const float* feat, long long ld_feat, long long sz_feat,
                         const float* s, long long ld_s, long long sz_s, const float* a, const float* ta,
-                        long long ld_a, int n, float* logits4, const CriticBufs& c, hipStream_t st);
+                        long long ld_a, int n, float* logits4, const CriticBufs& c, hipStream_t st,
+                        bool trunk_done = false);
+// trunk_done: c.pre already holds the input projections (trunks_forward)
+GemmProb critic_trunk_pair_prob(const Net& net, const float* cp, const float* tcp, const float* cpack,
+                                const float* tpack, const Layout& L, const float* feat, long long ld_feat,
+                                long long sz_feat, int n, const CriticBufs& c);
 int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                    long long ld_feat, const float* s, long long ld_s, const float* a, long long ld_a, int n,
                    float* logits, const CriticBufs& c, hipStream_t st);
@@ -82,7 +87,17 @@ void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd);
 // eps nullable (mean action)
 int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
                   long long ld_feat, const float* s, long long ld_s, const float* eps, int n, float lo, float hi,
-                  float* action, float* logp, const ActorBufs& a, hipStream_t st);
+                  float* action, float* logp, const ActorBufs& a, hipStream_t st, bool trunk_done = false);
+// trunk_done: a.pre already holds the input projection (trunks_forward)
+GemmProb actor_trunk_prob(const Net& net, const float* ap, const float* pack, const Layout& L, const float* feat,
+                          long long ld_feat, int n, const ActorBufs& a);
+// The input projections of the update's forward pass in one launch: the actor's
+// on the 2B feature rows [s; s'] (into a.pre) and the online / target critics'
+// on the rows of s / s' (into c.pre).  They read the same features and do not
+// depend on each other.
+int trunks_forward(const Net& net, int bf16, const float* ap, const float* cp, const float* tcp, const float* pack,
+                   const float* cpack, const float* tpack, const Layout& L, const float* feat, long long ld_feat, int B,
+                   const ActorBufs& a, const CriticBufs& c, hipStream_t st);
 int actor_backward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
                    long long ld_feat, const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
