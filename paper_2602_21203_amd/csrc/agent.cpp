@@ -149,8 +149,15 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   const float lo = hp.log_std_min, hi = hp.log_std_max;
   float* P = g->params;
   float* G = g->grads;
+  // the critics' input rows [projection | s | a] (batch 0: online on s, batch 1:
+  // target on s'): the replayed actions go straight into batch 0's action columns,
+  // the target policy's actions into batch 1's (written by the policy head)
+  const int cld = net.cpad;
+  float* xa_online = g->crit.X1 + d.proj + S;
+  float* xa_target = g->crit.X1 + (size_t)B * cld + d.proj + S;
   const SampleArgs sa = sample_args(hp.seed, g->ctr, R->size, R->dev_size, B, A, S, R->proprio, R->next_proprio,
-                                    R->action, R->reward, R->done, g->idx, g->eps2B, g->S2, g->Arep, g->r, g->dn);
+                                    R->action, R->reward, R->done, g->idx, g->eps2B, g->S2, xa_online, cld, g->r,
+                                    g->dn);
   // state-based SAC: the sampled states [s; s'] (S2) are the features
   const bool image = d.n_conv > 0;
   const float* feat = g->S2;
@@ -165,10 +172,14 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
     SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st, g->enc_map.n > 0));
     feat = g->enc.h[d.n_conv - 1];
   }
-  SQ_TRY(trunks_forward(net, bf, P + L.actor_begin, P + L.critic_begin, g->target, g->pack, g->pack, g->tpack, L, feat,
-                        flat, B, g->actor, g->crit, st));
-  SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi, g->act2B,
-                       g->logp2B, g->actor, st, true));
+  SQ_TRY(trunks_forward(net, bf, P + L.actor_begin, P + L.critic_begin, g->target, g->pack, g->pack, g->tpack, L,
+                        feat, flat, g->S2, S, B, g->actor, g->crit, st));
+  ActorBufs ab = g->actor;
+  ab.xact = xa_target;
+  ab.ld_xact = cld;
+  ab.xact_row0 = B;
+  SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi,
+                       g->act2B, g->logp2B, ab, st, true));
   // online critics on (z, s, a) and target critics on (z', s', a~') in one pass
   SQ_TRY(critic_forward_pair(net, bf, P + L.critic_begin, g->target, g->pack, g->tpack, L, feat, flat,
                              (long long)B * flat, g->S2, S, (long long)B * S, g->Arep, g->act2B + (size_t)B * A, A, B,

@@ -100,7 +100,8 @@ enum { CTR_U = 0, CTR_TC = 1, CTR_TA = 2, CTR_TALPHA = 3, CTR_N = 4 };
 struct SampleArgs;
 SampleArgs sample_args(unsigned long long seed, const int* ctr, int size, const int* dev_size, int B, int A, int S,
                        const float* proprio, const float* next_proprio, const float* action, const float* reward,
-                       const uint8_t* done, int* idx, float* eps2B, float* S2, float* Arep, float* r, float* d);
+                       const uint8_t* done, int* idx, float* eps2B, float* S2, float* Arep, long long ld_arep,
+                       float* r, float* d);
 int launch_sample_batch(const SampleArgs& s, hipStream_t st);
 // the draw and the squint of the sampled obs / next_obs rows in one launch (the
 // squint workgroups compute their rows' indices themselves); falls back to two
@@ -188,9 +189,12 @@ struct OutArg {            // C(r, c) at p[z*sz + r*ld + c]
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st);
 // policy head [n][2A] = X W^T + bias with the tanh-Gaussian sample (eps given) or the
-// mean action (eps null) applied per row in the same launch; head is also stored
+// mean action (eps null) applied per row in the same launch; head is also stored.
+// xact (nullable): the actions of rows r >= xact_row0 are also written to
+// xact + (r - xact_row0) * ld_xact (a critic's input rows)
 int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const float* bias, const float* eps, float lo,
-                    float hi, float* action, float* logp, float* save, float* head, hipStream_t st);
+                    float hi, float* action, float* logp, float* save, float* head, hipStream_t st,
+                    float* xact = nullptr, long long ld_xact = 0, int xact_row0 = 0);
 struct GemmProb {
   int M, N, K, batch; MatArg A, B; OutArg C;
 };
@@ -243,6 +247,20 @@ int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, i
                float* y, long long ld_y, long long sz_y, float* xhat, float* rstd,
                const float* e1, long long ld_e1, int w1, const float* e2, long long ld_e2, int w2,
                hipStream_t st, const struct LnGroups* grp = nullptr);
+// One LayerNorm forward problem (the arguments of ln_act_fwd), and two problems of
+// the same width in one launch (two launches when they cannot share one).
+struct LnFwdJob {
+  const float* pre; long long ld_pre, sz_pre; int rows, H, batch;
+  const float* g; const float* beta; long long sz_par; int act_tanh;
+  float* y; long long ld_y, sz_y; float* xhat; float* rstd;
+  const float* e1; long long ld_e1; int w1; const float* e2; long long ld_e2; int w2;
+  LnGroups grp;
+};
+LnFwdJob ln_fwd_job(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch, const float* g,
+                    const float* beta, long long sz_par, int act_tanh, float* y, long long ld_y, long long sz_y,
+                    float* xhat, float* rstd, const float* e1, long long ld_e1, int w1, const float* e2,
+                    long long ld_e2, int w2, const LnGroups* grp = nullptr);
+int ln_act_fwd_pair(const LnFwdJob& j0, const LnFwdJob& j1, hipStream_t st);
 int ln_bwd_partial_rows(int rows);
 int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y, long long ld_y,
                long long sz_y, const float* xhat, const float* rstd, const float* g, long long sz_par,

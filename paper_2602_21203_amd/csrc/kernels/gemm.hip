@@ -138,6 +138,7 @@ struct StMat {
 // v: the tile's sums [32][ld]; tmp: >= 32 * 32 floats of LDS.  All threads call.
 struct StTanhGauss {
   const float* bias; const float* eps; float lo, hi; float* action; float* logp; float* save; float* head; int A;
+  float* xact; long long ld_xact; int xact_row0;   // second copy of the actions of rows >= xact_row0 (nullable)
   static constexpr bool ROW_FAST = false;
   static constexpr bool ROWS = true;
   __device__ void put(int, int, int, float) const {}
@@ -151,12 +152,16 @@ struct StTanhGauss {
       const int r = e / A, d = e - r * A;
       const long long row = r0 + r;
       const float mu = v[r * ld + d] + (bias ? bias[d] : 0.f);
+      float act;
       if (eps) {
         const float us = v[r * ld + A + d] + (bias ? bias[A + d] : 0.f);
         tmp[r * 32 + d] = tanh_gauss_dim(mu, us, eps[row * A + d], A, d, lo, hi, action + row * A, save + row * 3 * A);
+        act = save[row * 3 * A + 2 * A + d];
       } else {
-        action[row * A + d] = tanhf(mu);
+        act = tanhf(mu);
+        action[row * A + d] = act;
       }
+      if (xact && row >= xact_row0) xact[(row - xact_row0) * ld_xact + d] = act;
     }
     if (!eps || !logp) return;
     __syncthreads();
@@ -812,7 +817,8 @@ int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C,
 }
 
 int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const float* bias, const float* eps, float lo,
-                    float hi, float* action, float* logp, float* save, float* head, hipStream_t st) {
+                    float hi, float* action, float* logp, float* save, float* head, hipStream_t st, float* xact,
+                    long long ld_xact, int xact_row0) {
   if (n <= 0) return SQ_OK;
   if (2 * A > kTile || rkind(X) != 1 || rkind(W) != 1 || !head) {
     OutArg C{head, 2 * A, 0, bias, 0, 0, 0};
@@ -821,9 +827,14 @@ int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const flo
       return SQ_EINVAL;
     }
     SQ_TRY(gemm(bf16, n, 2 * A, K, 1, X, W, C, nullptr, 0, st));
-    return eps ? tanh_gauss_fwd(head, n, A, eps, lo, hi, action, logp, save, st) : mean_action(head, n, A, action, st);
+    SQ_TRY(eps ? tanh_gauss_fwd(head, n, A, eps, lo, hi, action, logp, save, st)
+               : mean_action(head, n, A, action, st));
+    if (xact && xact_row0 < n)
+      SQ_TRY_HIP(hipMemcpy2DAsync(xact, (size_t)ld_xact * 4, action + (size_t)xact_row0 * A, (size_t)A * 4,
+                                  (size_t)A * 4, (size_t)(n - xact_row0), hipMemcpyDeviceToDevice, st));
+    return SQ_OK;
   }
-  const StTanhGauss tg{bias, eps, lo, hi, action, logp, save, head, A};
+  const StTanhGauss tg{bias, eps, lo, hi, action, logp, save, head, A, xact, ld_xact, xact_row0};
   const StPart none{nullptr, 0, 0, 1};
   dim3 grid(cdiv(n, kTile), 1, 1);
   if (bf16)

@@ -19,9 +19,10 @@ __global__ __launch_bounds__(256) void k_sample_batch(SampleArgs s) {
 
 SampleArgs sample_args(unsigned long long seed, const int* ctr, int size, const int* dev_size, int B, int A, int S,
                        const float* proprio, const float* next_proprio, const float* action, const float* reward,
-                       const uint8_t* done, int* idx, float* eps2B, float* S2, float* Arep, float* r, float* d) {
+                       const uint8_t* done, int* idx, float* eps2B, float* S2, float* Arep, long long ld_arep,
+                       float* r, float* d) {
   return SampleArgs{(unsigned)seed, (unsigned)(seed >> 32), ctr, size, dev_size, B, A, S, proprio, next_proprio,
-                    action, reward, done, idx, eps2B, S2, Arep, r, d};
+                    action, reward, done, idx, eps2B, S2, Arep, ld_arep, r, d};
 }
 
 int launch_sample_batch(const SampleArgs& s, hipStream_t st) {

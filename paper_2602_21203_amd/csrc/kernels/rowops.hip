@@ -108,18 +108,14 @@ __device__ __forceinline__ void ln_store_row(float* __restrict__ p, int H, int l
 
 // one row per wave; the row, gain and shift are all requested before the reductions
 template <int E, bool VEC>
-__global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, long long ld_pre, long long sz_pre,
-                                                int rows, int H, const float* __restrict__ g,
-                                                const float* __restrict__ beta, long long sz_par, int act_tanh,
-                                                float* __restrict__ y, long long ld_y, long long sz_y,
-                                                float* __restrict__ xhat, float* __restrict__ rstd,
-                                                const float* __restrict__ e1, long long ld_e1, int w1,
-                                                const float* __restrict__ e2, long long ld_e2, int w2,
-                                                LnGroups grp) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int z = blockIdx.y;
-  if (row >= rows) return;
+__device__ __forceinline__ void ln_fwd_row(const float* __restrict__ pre, long long ld_pre, long long sz_pre,
+                                           int rows, int H, const float* __restrict__ g,
+                                           const float* __restrict__ beta, long long sz_par, int act_tanh,
+                                           float* __restrict__ y, long long ld_y, long long sz_y,
+                                           float* __restrict__ xhat, float* __restrict__ rstd,
+                                           const float* __restrict__ e1, long long ld_e1, int w1,
+                                           const float* __restrict__ e2, long long ld_e2, int w2,
+                                           const LnGroups& grp, int row, int z, int lane) {
   const bool second = z >= grp.zalt;
   const float* gz = second ? grp.g_alt + (z - grp.zalt) * sz_par : g + z * sz_par;
   const float* bz = second ? grp.beta_alt + (z - grp.zalt) * sz_par : beta + z * sz_par;
@@ -160,6 +156,40 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, l
   for (int j = lane; j < w2; j += 64) yr[H + w1 + j] = e2z[row * ld_e2 + j];
 }
 
+template <int E, bool VEC>
+__global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, long long ld_pre, long long sz_pre,
+                                                int rows, int H, const float* __restrict__ g,
+                                                const float* __restrict__ beta, long long sz_par, int act_tanh,
+                                                float* __restrict__ y, long long ld_y, long long sz_y,
+                                                float* __restrict__ xhat, float* __restrict__ rstd,
+                                                const float* __restrict__ e1, long long ld_e1, int w1,
+                                                const float* __restrict__ e2, long long ld_e2, int w2,
+                                                LnGroups grp) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  ln_fwd_row<E, VEC>(pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1, ld_e1,
+                     w1, e2, ld_e2, w2, grp, row, blockIdx.y, threadIdx.x & 63);
+}
+
+// row-block b (4 rows) of a job: batch b / cdiv(rows, 4)
+template <int E, bool VEC>
+__device__ __forceinline__ void ln_fwd_job_block(const LnFwdJob& j, int b) {
+  const int rb = (j.rows + 3) / 4;
+  const int row = (b % rb) * 4 + (threadIdx.x >> 6);
+  if (row >= j.rows) return;
+  ln_fwd_row<E, VEC>(j.pre, j.ld_pre, j.sz_pre, j.rows, j.H, j.g, j.beta, j.sz_par, j.act_tanh, j.y, j.ld_y, j.sz_y,
+                     j.xhat, j.rstd, j.e1, j.ld_e1, j.w1, j.e2, j.ld_e2, j.w2, j.grp, row, b / rb, threadIdx.x & 63);
+}
+
+// two LayerNorm problems of the same width in one launch: workgroups [0, blocks0)
+// take j0, the rest j1
+template <int E, bool VEC>
+__global__ __launch_bounds__(256) void k_ln_fwd_pair(LnFwdJob j0, LnFwdJob j1, int blocks0) {
+  const int b = blockIdx.x;
+  if (b < blocks0) ln_fwd_job_block<E, VEC>(j0, b);
+  else ln_fwd_job_block<E, VEC>(j1, b - blocks0);
+}
+
 static bool al16(const void* p, long long a = 0, long long b = 0) {
   return (uintptr_t)p % 16 == 0 && a % 4 == 0 && b % 4 == 0;
 }
@@ -190,6 +220,35 @@ int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, i
         pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1, ld_e1, w1, e2, ld_e2,
         w2, grp);
     return launch_status("ln_fwd");
+  });
+}
+
+LnFwdJob ln_fwd_job(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch, const float* g,
+                    const float* beta, long long sz_par, int act_tanh, float* y, long long ld_y, long long sz_y,
+                    float* xhat, float* rstd, const float* e1, long long ld_e1, int w1, const float* e2,
+                    long long ld_e2, int w2, const LnGroups* groups) {
+  return LnFwdJob{pre, ld_pre, sz_pre, rows, H, batch, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1,
+                  ld_e1, w1, e2, ld_e2, w2, groups ? *groups : LnGroups{kNoAlt, nullptr, nullptr, 0, nullptr}};
+}
+
+static int ln_fwd_alone(const LnFwdJob& j, hipStream_t st) {
+  return ln_act_fwd(j.pre, j.ld_pre, j.sz_pre, j.rows, j.H, j.batch, j.g, j.beta, j.sz_par, j.act_tanh, j.y, j.ld_y,
+                    j.sz_y, j.xhat, j.rstd, j.e1, j.ld_e1, j.w1, j.e2, j.ld_e2, j.w2, st, &j.grp);
+}
+
+static bool ln_vec(const LnFwdJob& j) {
+  return al16(j.pre, j.ld_pre, j.sz_pre) && al16(j.y, j.ld_y, j.sz_y) && al16(j.xhat, j.H);
+}
+
+int ln_act_fwd_pair(const LnFwdJob& j0, const LnFwdJob& j1, hipStream_t st) {
+  if (j0.rows <= 0 || j1.rows <= 0 || j0.batch <= 0 || j1.batch <= 0 || j0.H != j1.H || ln_vec(j0) != ln_vec(j1)) {
+    SQ_TRY(ln_fwd_alone(j0, st));
+    return ln_fwd_alone(j1, st);
+  }
+  const int blocks0 = cdiv(j0.rows, 4) * j0.batch, blocks1 = cdiv(j1.rows, 4) * j1.batch;
+  return ln_dispatch(j0.H, ln_vec(j0), [&](auto e, auto v) {
+    k_ln_fwd_pair<decltype(e)::value, decltype(v)::value><<<blocks0 + blocks1, 256, 0, st>>>(j0, j1, blocks0);
+    return launch_status("ln_fwd_pair");
   });
 }
 

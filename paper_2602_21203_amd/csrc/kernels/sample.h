@@ -1,6 +1,6 @@
 // One item of the update's minibatch draw (Alg. 1: sample a minibatch from the
 // replay buffer; uniform with replacement, Philox4x32-10 keyed by (seed, u)).
-// Items of row b: A replayed action values, 2A policy-noise values (stream 2 for
+// Items of row b: A replayed action values (row b of Arep, stride ld_arep), 2A policy-noise values (stream 2 for
 // the sample at s_t, stream 1 for s_{t+1}), the reward, the done flag, and the 2S
 // proprio values of s and s'.  Shared by the standalone sampling launch and the
 // squint launch that samples in extra workgroups; both give identical results.
@@ -14,7 +14,7 @@ struct SampleArgs {
   unsigned k0, k1; const int* ctr; int size; const int* dev_size; int B, A, S;
   const float* proprio; const float* next_proprio; const float* action; const float* reward;
   const uint8_t* done;
-  int* idx; float* eps2B; float* S2; float* Arep; float* r; float* d;
+  int* idx; float* eps2B; float* S2; float* Arep; long long ld_arep; float* r; float* d;
 };
 
 __host__ __device__ inline long long sample_items(int B, int A, int S) { return (long long)B * (2 * S + 3 * A + 2); }
@@ -40,7 +40,7 @@ __device__ __forceinline__ void sample_item(const SampleArgs& s, long long t) {
   }
   const int row = sample_row(s, b);
   if (it < A) {
-    s.Arep[(long long)b * A + it] = s.action[(long long)row * A + it];
+    s.Arep[(long long)b * s.ld_arep + it] = s.action[(long long)row * A + it];
   } else if (it == 3 * A) {
     s.r[b] = s.reward[row];
     s.idx[b] = row;

@@ -262,11 +262,9 @@ int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* 
   const long long nH = (long long)n * H;
   const Dense& T = L.ctrunk;
   const Twin& q = L.q[0];
-  {
-    if (!trunk_done) {
-      const GemmProb t = critic_trunk_pair_prob(net, cp, tcp, cpack, tpack, L, feat, ld_feat, sz_feat, n, c);
-      SQ_TRY(gemm(bf16, t.M, t.N, t.K, t.batch, t.A, t.B, t.C, nullptr, 0, st));
-    }
+  if (!trunk_done) {
+    const GemmProb t = critic_trunk_pair_prob(net, cp, tcp, cpack, tpack, L, feat, ld_feat, sz_feat, n, c);
+    SQ_TRY(gemm(bf16, t.M, t.N, t.K, t.batch, t.A, t.B, t.C, nullptr, 0, st));
     const LnGroups grp{1, tcp + (T.g - c0), tcp + (T.beta - c0), sz_s, ta};
     SQ_TRY(ln_act_fwd(c.pre, P, (long long)n * P, n, P, 2, cp + (T.g - c0), cp + (T.beta - c0), 0, 1, c.X1, cld,
                       (long long)n * cld, c.t.xhat, c.t.rstd, s, ld_s, d.proprio, a, ld_a, d.action, st, &grp));
@@ -424,11 +422,22 @@ GemmProb actor_trunk_prob(const Net& net, const float* ap, const float* pack, co
 }
 
 int trunks_forward(const Net& net, int bf16, const float* ap, const float* cp, const float* tcp, const float* pack,
-                   const float* cpack, const float* tpack, const Layout& L, const float* feat, long long ld_feat, int B,
-                   const ActorBufs& a, const CriticBufs& c, hipStream_t st) {
-  return gemm_pair(bf16, actor_trunk_prob(net, ap, pack, L, feat, ld_feat, 2 * B, a),
+                   const float* cpack, const float* tpack, const Layout& L, const float* feat, long long ld_feat,
+                   const float* s, long long ld_s, int B, const ActorBufs& a, const CriticBufs& c, hipStream_t st) {
+  SQ_TRY(gemm_pair(bf16, actor_trunk_prob(net, ap, pack, L, feat, ld_feat, 2 * B, a),
                    critic_trunk_pair_prob(net, cp, tcp, cpack, tpack, L, feat, ld_feat, (long long)B * ld_feat, B, c),
-                   nullptr, 0, st);
+                   nullptr, 0, st));
+  const int P = net.d.proj, S = net.d.proprio;
+  const long long a0 = L.actor_begin, c0 = L.critic_begin;
+  const Dense& Ta = L.atrunk;
+  const Dense& Tc = L.ctrunk;
+  const LnFwdJob ja = ln_fwd_job(a.pre, P, 0, 2 * B, P, 1, ap + (Ta.g - a0), ap + (Ta.beta - a0), 0, 1, a.X1,
+                                 net.apad, 0, a.t.xhat, a.t.rstd, s, ld_s, S, nullptr, 0, 0);
+  const LnGroups grp{1, tcp + (Tc.g - c0), tcp + (Tc.beta - c0), (long long)B * ld_s, nullptr};
+  const LnFwdJob jc = ln_fwd_job(c.pre, P, (long long)B * P, B, P, 2, cp + (Tc.g - c0), cp + (Tc.beta - c0), 0, 1,
+                                 c.X1, net.cpad, (long long)B * net.cpad, c.t.xhat, c.t.rstd, s, ld_s, S, nullptr, 0,
+                                 0, &grp);
+  return ln_act_fwd_pair(ja, jc, st);
 }
 
 int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
@@ -442,9 +451,9 @@ int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, 
   if (!trunk_done) {
     const GemmProb t = actor_trunk_prob(net, ap, pack, L, feat, ld_feat, n, a);
     SQ_TRY(gemm(bf16, t.M, t.N, t.K, t.batch, t.A, t.B, t.C, nullptr, 0, st));
+    SQ_TRY(ln_act_fwd(a.pre, P, 0, n, P, 1, ap + (T.g - a0), ap + (T.beta - a0), 0, 1, a.X1, ald, 0, a.t.xhat,
+                      a.t.rstd, s, ld_s, d.proprio, nullptr, 0, 0, st));
   }
-  SQ_TRY(ln_act_fwd(a.pre, P, 0, n, P, 1, ap + (T.g - a0), ap + (T.beta - a0), 0, 1, a.X1, ald, 0, a.t.xhat,
-                    a.t.rstd, s, ld_s, d.proprio, nullptr, 0, 0, st));
   SQ_TRY(linear_fwd(bf16, n, H, cin, 1, a.X1, ald, 0, w.W(L.al1.W, L.al1.Wp), w.ld(L.al1.in, L.al1.ldp), 0,
                     ap + (L.al1.b - a0), 0, a.pre, H, 0, st));
   SQ_TRY(ln_act_fwd(a.pre, H, 0, n, H, 1, ap + (L.al1.g - a0), ap + (L.al1.beta - a0), 0, 0, a.g1, H, 0, a.l1.xhat,
@@ -455,7 +464,8 @@ int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, 
                     a.l2.rstd, nullptr, 0, 0, nullptr, 0, 0, st));
   MatArg X{a.g2, H, 1, 0};
   MatArg Wm{w.W(L.aout.W, L.aout.Wp), w.ld(L.aout.in, L.aout.ldp), 1, 0};
-  return gemm_tanh_gauss(bf16, n, A, H, X, Wm, ap + (L.aout.b - a0), eps, lo, hi, action, logp, a.save, a.head, st);
+  return gemm_tanh_gauss(bf16, n, A, H, X, Wm, ap + (L.aout.b - a0), eps, lo, hi, action, logp, a.save, a.head, st,
+                         a.xact, a.ld_xact, a.xact_row0);
 }
 
 int actor_backward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,

@@ -53,7 +53,8 @@ int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* 
                         const float* s, long long ld_s, long long sz_s, const float* a, const float* ta,
                         long long ld_a, int n, float* logits4, const CriticBufs& c, hipStream_t st,
                         bool trunk_done = false);
-// trunk_done: c.pre already holds the input projections (trunks_forward)
+// trunk_done: c.X1 already holds the critics' input rows [projection | s | a]
+// (trunks_forward, plus the action columns written by the draw and the policy head)
 GemmProb critic_trunk_pair_prob(const Net& net, const float* cp, const float* tcp, const float* cpack,
                                 const float* tpack, const Layout& L, const float* feat, long long ld_feat,
                                 long long sz_feat, int n, const CriticBufs& c);
@@ -81,6 +82,9 @@ struct ActorBufs {
   float* dhead;        // [n][2A]
   float* part_t; float* part_l1; float* part_l2; float* part_out;
   float* split;
+  // nullable: the sampled actions of rows >= xact_row0 are also written here
+  // (row stride ld_xact), straight into a critic's input rows
+  float* xact = nullptr; long long ld_xact = 0; int xact_row0 = 0;
 };
 void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd);
 // ap: base of the actor block; pack: the whole packed-weight buffer (nullable);
@@ -88,16 +92,17 @@ void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd);
 int actor_forward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
                   long long ld_feat, const float* s, long long ld_s, const float* eps, int n, float lo, float hi,
                   float* action, float* logp, const ActorBufs& a, hipStream_t st, bool trunk_done = false);
-// trunk_done: a.pre already holds the input projection (trunks_forward)
+// trunk_done: a.X1 already holds the actor's input rows [projection | s] (trunks_forward)
 GemmProb actor_trunk_prob(const Net& net, const float* ap, const float* pack, const Layout& L, const float* feat,
                           long long ld_feat, int n, const ActorBufs& a);
-// The input projections of the update's forward pass in one launch: the actor's
-// on the 2B feature rows [s; s'] (into a.pre) and the online / target critics'
-// on the rows of s / s' (into c.pre).  They read the same features and do not
-// depend on each other.
+// The input projections of the update's forward pass and their LayerNorms, each
+// pair in one launch: the actor's on the 2B feature rows [s; s'] (a.X1 = [h | s])
+// and the online / target critics' on the rows of s / s' (c.X1 = [h | s], the
+// action columns being written by others).  They read the same features and do
+// not depend on each other.  s: the 2B proprio rows [s; s'], row stride ld_s.
 int trunks_forward(const Net& net, int bf16, const float* ap, const float* cp, const float* tcp, const float* pack,
-                   const float* cpack, const float* tpack, const Layout& L, const float* feat, long long ld_feat, int B,
-                   const ActorBufs& a, const CriticBufs& c, hipStream_t st);
+                   const float* cpack, const float* tpack, const Layout& L, const float* feat, long long ld_feat,
+                   const float* s, long long ld_s, int B, const ActorBufs& a, const CriticBufs& c, hipStream_t st);
 int actor_backward(const Net& net, int bf16, const float* ap, const float* pack, const Layout& L, const float* feat,
                    long long ld_feat, const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
