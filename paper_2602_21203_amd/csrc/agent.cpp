@@ -81,7 +81,7 @@ struct sq_agent {
   long long u_host = 0;
   // update buffers
   int* idx;
-  float *eps2B, *S2, *Arep, *r, *dn, *x, *dfeat, *act2B, *logp2B, *logits_t, *logits, *logits_q, *mt, *dlogits,
+  float *eps2B, *S2, *r, *dn, *x, *dfeat, *act2B, *logp2B, *logits_t, *logits, *logits_q, *mt, *dlogits,
       *dlogits_q, *loss_row, *q_row, *tgt_row, *qa_row, *scal, *da;
   int* ta_snap;   // the actor Adam's step count, recorded by the critic Adam launch
   EncBufs enc;
@@ -105,7 +105,6 @@ static size_t plan_agent(sq_agent* g, char* base) {
   g->idx = b.take<int>(B);
   g->eps2B = b.take<float>((size_t)2 * B * A);
   g->S2 = b.take<float>((size_t)2 * B * (S > 0 ? S : 1));
-  g->Arep = b.take<float>((size_t)B * A);
   g->r = b.take<float>(B);
   g->dn = b.take<float>(B);
   g->x = b.take<float>((size_t)2 * B * net.img);
@@ -180,10 +179,11 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   ab.xact_row0 = B;
   SQ_TRY(actor_forward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->S2, S, g->eps2B, 2 * B, lo, hi,
                        g->act2B, g->logp2B, ab, st, true));
-  // online critics on (z, s, a) and target critics on (z', s', a~') in one pass
+  // online critics on (z, s, a) and target critics on (z', s', a~') in one pass;
+  // their input rows are complete (projections, states and both action blocks)
   SQ_TRY(critic_forward_pair(net, bf, P + L.critic_begin, g->target, g->pack, g->tpack, L, feat, flat,
-                             (long long)B * flat, g->S2, S, (long long)B * S, g->Arep, g->act2B + (size_t)B * A, A, B,
-                             g->logits, g->crit, st, true));
+                             (long long)B * flat, g->S2, S, (long long)B * S, nullptr, nullptr, A, B, g->logits,
+                             g->crit, st, true));
   // distributional soft target from the averaged twin target critics (projection),
   // and the online critics' cross entropy to it, in one pass over the rows
   if (N == 1)
