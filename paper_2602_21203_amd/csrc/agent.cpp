@@ -210,10 +210,14 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
       SQ_TRY(expected_q_scalar(g->logits_q, B, g->dlogits_q, g->qa_row, st));
     else
       SQ_TRY(expected_q_grad(g->logits_q, B, N, d.v_min, d.v_max, g->dlogits_q, g->qa_row, st));
+    // the policy head's backward (d log pi scaled by the updated alpha / B) runs as
+    // the epilogue of the critic product that forms dQ/da
+    const TgBwdJob tj{g->actor.save, g->eps2B, nullptr, g->scal + 1, 1.0f / (float)B, lo, hi, g->actor.dhead,
+                      g->actor.part_out};
     SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits_q, B, g->aux, nullptr, nullptr,
-                           g->da, st));
+                           g->da, st, false, false, &tj));
     SQ_TRY(actor_backward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
-                          1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st, true));
+                          1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st, true, true));
     // the actor Adam launch also ends the update in its last workgroup; its step
     // count is the one the critic launch recorded, since that workgroup advances
     // the counters

@@ -285,6 +285,17 @@ int tanh_gauss_bwd(const float* save, const float* eps, const float* da, long lo
                    float* part,
                    hipStream_t st);
 int mean_action(const float* head, int rows, int A, float* action, hipStream_t st);
+// The arguments of tanh_gauss_bwd other than da: the policy head's backward as
+// the epilogue of the product that forms da (gemm_tg_bwd)
+struct TgBwdJob {
+  const float* save; const float* eps; const float* dlogp_vec; const float* dlogp_scalar; float scale, lo, hi;
+  float* dhead; float* part;
+};
+struct GemmProb;
+// da = dx's product ([rows][A], A <= 32 columns), then tanh_gauss_bwd on it in the
+// same launch (dx.C is not written); two launches when the product's shape or
+// operands do not allow that
+int gemm_tg_bwd(int bf16, const GemmProb& dx, int A, const TgBwdJob& tg, hipStream_t st);
 
 int c51_project_raw(const float* p, const float* reward, const uint8_t* done, const float* bonus,
                     float gamma, int B, int N, float v_min, float v_max, float* m, hipStream_t st);

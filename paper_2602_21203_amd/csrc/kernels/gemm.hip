@@ -172,6 +172,44 @@ struct StTanhGauss {
     }
   }
 };
+// The policy head's backward on a tile of da rows (v: [32][ld], columns < A), the
+// same arithmetic as the standalone kernel: du = da (1 - a^2) + dlogp 2a,
+// d u_s = (du sigma eps - dlogp) (hi - lo) / 2 (1 - tanh^2 u_s); with part, the
+// tile's column sums of dhead (rows in order) go to part[r0 / 32][2A].
+struct StTgBwd {
+  const float* save; const float* eps; const float* dlogp_vec; const float* dlogp_scalar; float scale, lo, hi;
+  float* dhead; float* part; int A;
+  static constexpr bool ROW_FAST = false;
+  static constexpr bool ROWS = true;
+  __device__ void put(int, int, int, float) const {}
+  __device__ void rows(int r0, int nr, const float* v, int ld, float* tmp) const {
+    const int t = threadIdx.x, N = 2 * A;
+    for (int e = t; e < nr * A; e += blockDim.x) {
+      const int r = e / A, d = e - r * A;
+      const long long row = r0 + r;
+      float dl = 0.f;
+      if (dlogp_vec) dl += dlogp_vec[row];
+      if (dlogp_scalar) dl += *dlogp_scalar * scale;
+      const float tus = save[row * 3 * A + d];
+      const float sd = save[row * 3 * A + A + d];
+      const float a = save[row * 3 * A + 2 * A + d];
+      const float du = v[r * ld + d] * (1.f - a * a) + dl * 2.f * a;
+      const float dls = du * sd * eps[row * A + d] - dl;
+      const float dls_out = dls * 0.5f * (hi - lo) * (1.f - tus * tus);
+      dhead[row * N + d] = du;
+      dhead[row * N + A + d] = dls_out;
+      tmp[r * N + d] = du;
+      tmp[r * N + A + d] = dls_out;
+    }
+    if (!part) return;
+    __syncthreads();
+    for (int j = t; j < N; j += blockDim.x) {
+      float sum = 0.f;
+      for (int r = 0; r < nr; ++r) sum += tmp[r * N + j];
+      part[(long long)(r0 / kTile) * N + j] = sum;
+    }
+  }
+};
 // C((n, p), c) -> out[n][c][p] (NCHW), optional bias + ReLU
 struct StConv {
   float* out; int Cout, HW; const float* bias; int relu;
@@ -842,6 +880,28 @@ int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const flo
   else
     k_gemm_r<false, 1, 1, StTanhGauss, false><<<grid, kThreads, 0, st>>>(rmat(X), rmat(W), tg, none, n, 2 * A, K, K);
   return launch_status("gemm_tanh_gauss");
+}
+
+int gemm_tg_bwd(int bf16, const GemmProb& dx, int A, const TgBwdJob& tg, hipStream_t st) {
+  const int n = dx.M;
+  if (n <= 0) return SQ_OK;
+  const bool kok = dx.A.kalt == dx.B.kalt && (dx.A.kalt == kNoAlt || dx.A.kalt % kRKC == 0);
+  if (dx.N != A || 2 * A * kTile > kTile * kTile || dx.batch != 1 || rkind(dx.A) != 1 || rkind(dx.B) != 0 || !kok ||
+      dx.C.accumulate || dx.C.bias) {
+    SQ_TRY(gemm(bf16, dx.M, dx.N, dx.K, dx.batch, dx.A, dx.B, dx.C, nullptr, 0, st));
+    return tanh_gauss_bwd(tg.save, tg.eps, dx.C.p, dx.C.ld, tg.dlogp_vec, tg.dlogp_scalar, tg.scale, tg.lo, tg.hi, n,
+                          A, tg.dhead, tg.part, st);
+  }
+  const StTgBwd ep{tg.save, tg.eps, tg.dlogp_vec, tg.dlogp_scalar, tg.scale, tg.lo, tg.hi, tg.dhead, tg.part, A};
+  const StPart none{nullptr, 0, 0, 1};
+  dim3 grid(cdiv(n, kTile), 1, 1);
+  if (bf16)
+    k_gemm_r<true, 1, 0, StTgBwd, false><<<grid, kThreads, 0, st>>>(rmat(dx.A), rmat(dx.B), ep, none, n, A, dx.K,
+                                                                     dx.K);
+  else
+    k_gemm_r<false, 1, 0, StTgBwd, false><<<grid, kThreads, 0, st>>>(rmat(dx.A), rmat(dx.B), ep, none, n, A, dx.K,
+                                                                      dx.K);
+  return launch_status("gemm_tg_bwd");
 }
 
 int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, size_t scratch_floats,

@@ -425,7 +425,7 @@ int tanh_gauss_fwd(const float* head, int rows, int A, const float* eps, float l
 // dlogp per row = (dlogp_vec ? dlogp_vec[r] : 0) + (dlogp_scalar ? *dlogp_scalar * scale : 0)
 // One row per thread, kTgRows rows per workgroup; with part, the workgroup also
 // writes the column sums of its rows of dhead (in row order) to part[blk][2A].
-constexpr int kTgRows = 64;
+constexpr int kTgRows = 32;   // a partial row per 32 rows, as the GEMM epilogue's tiles
 __global__ __launch_bounds__(kTgRows) void k_tg_bwd(const float* __restrict__ save, const float* __restrict__ eps,
                                                     const float* __restrict__ da, long long ld_da,
                                                     const float* __restrict__ dlogp_vec,

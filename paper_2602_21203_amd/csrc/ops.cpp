@@ -290,7 +290,7 @@ int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* 
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                     long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
                     float* daction, hipStream_t st,
-                    bool out_partials_done, bool defer_colsum) {
+                    bool out_partials_done, bool defer_colsum, const TgBwdJob* tg) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic, cld = net.cpad, A = d.action;
   const long long c0 = L.critic_begin;
@@ -337,6 +337,10 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
       dx.A.kalt = H;
       dx.B.kp = W1b + c0col;
       dx.B.kalt = H;
+      if (tg && !trunk && !params) {
+        // the policy head's backward is the epilogue of the product forming da
+        return gemm_tg_bwd(bf16, dx, A, *tg, st);
+      }
       SQ_TRY(grads(bf16, dx, params ? &dw1 : nullptr, c.split, st));
     } else {   // twin by twin, the second accumulating
       SQ_TRY(grads(bf16, dx, params ? &dw1 : nullptr, c.split, st));
@@ -349,6 +353,9 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
     if (trunk && daction)
       SQ_TRY_HIP(hipMemcpy2DAsync(daction, (size_t)A * 4, c.dX1 + P + d.proprio, (size_t)cld * 4, (size_t)A * 4, n,
                                   hipMemcpyDeviceToDevice, st));
+    if (tg && daction)
+      SQ_TRY(tanh_gauss_bwd(tg->save, tg->eps, daction, A, tg->dlogp_vec, tg->dlogp_scalar, tg->scale, tg->lo, tg->hi,
+                            n, A, tg->dhead, tg->part, st));
   } else if (params) {
     SQ_TRY(gemm(bf16, dw1.M, dw1.N, dw1.K, dw1.batch, dw1.A, dw1.B, dw1.C, c.split, kSplitFloats, st));
   }
@@ -472,14 +479,15 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
                    long long ld_feat, const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
                    hipStream_t st,
-                   bool defer_colsum) {
+                   bool defer_colsum, bool dhead_done) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, A = d.action, cin = net.cin_actor, ald = net.apad;
   const long long a0 = L.actor_begin;
   const WRef w{ap, pack, a0};
   const Dense& T = L.atrunk;
-  SQ_TRY(tanh_gauss_bwd(a.save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, n, A, a.dhead, a.part_out,
-                        st));
+  if (!dhead_done)
+    SQ_TRY(tanh_gauss_bwd(a.save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, n, A, a.dhead, a.part_out,
+                          st));
   {
     const GemmProb dx = prob_dx(n, 2 * A, H, 1, a.dhead, 2 * A, 0, w.W(L.aout.W, L.aout.Wp),
                                 w.ld(L.aout.in, L.aout.ldp), 0, a.dA, H, 0);

@@ -68,7 +68,10 @@ int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                     long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
                     float* daction, hipStream_t st,
-                    bool out_partials_done = false, bool defer_colsum = false);
+                    bool out_partials_done = false, bool defer_colsum = false, const TgBwdJob* tg = nullptr);
+// tg (with daction): also run the policy head's backward on daction (tanh_gauss_bwd
+// with tg's arguments); without the critic's own gradients it is the epilogue of
+// the product that forms daction, which is then not stored
 
 struct ActorBufs {
   float* pre;          // [n][max(proj, hidden)]
@@ -107,7 +110,9 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
                    long long ld_feat, const float* eps, int n, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, const ActorBufs& a, float* dap,
                    hipStream_t st,
-                   bool defer_colsum = false);
+                   bool defer_colsum = false, bool dhead_done = false);
+// dhead_done: a.dhead and a.part_out already hold the policy head's backward
+// (critic_backward with a TgBwdJob); da is then not read
 
 // act(): squint -> encoder -> actor, forward only
 struct ActBufs {
