@@ -512,12 +512,12 @@ def main():
     a = parse()
     if a.sweep or a.serve or a.report or a.env_loop:
         if a.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU", "n_gpus": a.gpus}))
+            print(json.dumps({"error": "this implementation runs on one GPU", "n_gpus": a.gpus}))
             sys.exit(2)
         (run_sweep if a.sweep else run_serve if a.serve else run_report if a.report else run_env_loop)(a)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported",
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
