@@ -9,6 +9,8 @@ full32   the full network on 128x128x9 frames squinted 4x to 32x32 (the higher-r
          variant of Sec. VI Camera Resolution Analysis): convs 32 -> 15 -> 13 -> 11
 state, state_tiny   state-based SAC (Sec. VI Generality and Timing Analysis): no image
          and no encoder, a 40-float state vector feeds the projections
+odd      the tiny geometry with widths off the kernels' tiles (projection 40, hidden 48,
+         action 17)
 """
 TINY = dict(C=3, H=32, W=32, k=2, n_conv=2, F=16, proj=64, hidden=64, atoms=51, proprio=12, action=6,
             v_min=-10.0, v_max=10.0)
@@ -20,4 +22,8 @@ FULL32 = dict(FULL, H=128, W=128, k=4)
 # features; the frame fields only size the (unused) frames of the synthetic replay
 STATE_TINY = dict(TINY, n_conv=0, H=8, W=8, k=1, proprio=40)
 STATE = dict(FULL, n_conv=0, H=8, W=8, C=3, k=1, proprio=40)
-CONFIGS = dict(tiny=TINY, full=FULL, full128=FULL128, full32=FULL32, state_tiny=STATE_TINY, state=STATE)
+# widths that are not multiples of the kernels' tiles (projection 40, hidden 48,
+# a 17-dimensional action, so the policy head spans two GEMM column tiles): the
+# paths for general shapes
+ODD = dict(TINY, proj=40, hidden=48, action=17)
+CONFIGS = dict(tiny=TINY, full=FULL, full128=FULL128, full32=FULL32, state_tiny=STATE_TINY, state=STATE, odd=ODD)

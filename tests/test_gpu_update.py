@@ -56,7 +56,9 @@ def oracle_run(name, B, cap, prec, n_updates, policy_freq=1):
                                              ("state", 512, 2048, 1),
                                              # the other benchmarked shapes: batch 2048 in BF16, and the
                                              # UTD-sweep shape (batch 1024, 128x128 frames squinted 8x)
-                                             ("full", 2048, 4096, 1), ("full128", 1024, 1024, 1)])
+                                             ("full", 2048, 4096, 1), ("full128", 1024, 1024, 1),
+                                             # widths off the kernels' tiles (the general-shape paths)
+                                             ("odd", 32, 4096, 0), ("odd", 32, 4096, 1)])
 def test_one_update_matches_oracle(name, B, cap, prec):
     print(f"update parity {name} B={B} prec={prec}", flush=True)
     ag, stats = gpu_run(name, B, cap, prec, 1)
