@@ -218,7 +218,7 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
                            g->da, st, false, false, &tj));
     SQ_TRY(actor_backward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
                           1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st, true, true));
-    // the actor Adam launch also ends the update in its last workgroup; its step
+    // the actor Adam launch also ends the update in its first workgroup; its step
     // count is the one the critic launch recorded, since that workgroup advances
     // the counters
     const FinishJob fj{g->loss_row, g->q_row, g->tgt_row, g->logp2B, g->qa_row, g->scal, B, 1, g->ctr, stats};

@@ -359,7 +359,7 @@ struct AlphaJob {
   int* step_snap;
 };
 struct FinishJob;
-// fj: the launch's last workgroup also ends the update (statistics, counter
+// fj: one more workgroup of the launch ends the update (statistics, counter
 // advance); `step` must then not be one of the counters it advances
 int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
          float* ema_target, long long ema_begin, uint16_t* shadow, const PackArgs* pk, hipStream_t st,

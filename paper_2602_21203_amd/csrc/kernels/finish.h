@@ -1,5 +1,5 @@
 // End of one update (Alg. 1 bookkeeping): the update's statistics and the step
-// counters.  One 256-thread workgroup; it runs alone, or as the last workgroup of
+// counters.  One 256-thread workgroup; it runs alone, or as the first workgroup of
 // the actor's Adam launch, whose update step count was recorded beforehand (so
 // the counters this workgroup advances are not read in that launch).
 #pragma once
