@@ -29,4 +29,25 @@ def round_bf16(x):
 
 
 def maybe(x, on):
+    """A parameter operand: rounded to bfloat16 in the bfloat16-operand mode."""
+    return round_bf16(x) if on else x
+
+
+# Sensitivity hook, off (None) in every ordinary run.  The tests' measurement of
+# the oracle's own bfloat16-mode sensitivity sets it to a function that scales a
+# computed operand by (1 + delta s) before it is rounded; parameter operands are
+# never perturbed (both sides round the same FP32 parameter values).
+_computed_perturbation = None
+
+
+def set_computed_perturbation(fn):
+    global _computed_perturbation
+    _computed_perturbation = fn
+
+
+def maybe_computed(x, on):
+    """A computed operand (activation or upstream gradient): rounded to bfloat16
+    in the bfloat16-operand mode."""
+    if on and _computed_perturbation is not None:
+        x = _computed_perturbation(np.asarray(x, dtype=np.float64))
     return round_bf16(x) if on else x

@@ -28,7 +28,7 @@ and every non-GEMM step use the unrounded values.
 """
 import numpy as np
 
-from .bf16 import maybe
+from .bf16 import maybe, maybe_computed
 
 LN_EPS = 1e-5
 LOG_2PI = float(np.log(2.0 * np.pi))
@@ -42,7 +42,7 @@ def _out(n, stride):
 
 def conv_fwd(x, W, b, stride, bf=False):
     """Valid 3x3 convolution, NCHW input, W [F, C, 3, 3]."""
-    xb, Wb = maybe(x, bf), maybe(W, bf)
+    xb, Wb = maybe_computed(x, bf), maybe(W, bf)
     n, _, H, Wd = x.shape
     Ho, Wo = _out(H, stride), _out(Wd, stride)
     y = np.zeros((n, W.shape[0], Ho, Wo))
@@ -55,7 +55,7 @@ def conv_fwd(x, W, b, stride, bf=False):
 
 def conv_bwd(dy, x, W, stride, bf=False, need_dx=True):
     """Gradients of conv_fwd: (dx or None, dW, db)."""
-    dyb, xb, Wb = maybe(dy, bf), maybe(x, bf), maybe(W, bf)
+    dyb, xb, Wb = maybe_computed(dy, bf), maybe_computed(x, bf), maybe(W, bf)
     Ho, Wo = dy.shape[2], dy.shape[3]
     dW = np.zeros(W.shape)
     dx = np.zeros(x.shape) if need_dx else None
@@ -71,12 +71,12 @@ def conv_bwd(dy, x, W, stride, bf=False, need_dx=True):
 
 # ---------------------------------------------------------------- dense layers
 def linear(x, W, b, bf=False):
-    return maybe(x, bf) @ maybe(W, bf).T + b
+    return maybe_computed(x, bf) @ maybe(W, bf).T + b
 
 
 def linear_bwd(dy, x, W, bf=False, need_dx=True):
-    dyb = maybe(dy, bf)
-    dW = dyb.T @ maybe(x, bf)
+    dyb = maybe_computed(dy, bf)
+    dW = dyb.T @ maybe_computed(x, bf)
     dx = dyb @ maybe(W, bf) if need_dx else None
     return dx, dW, dy.sum(axis=0)
 

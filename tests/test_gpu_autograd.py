@@ -143,4 +143,4 @@ def test_autograd_gradient_vs_oracle_analytic():
         ref[o:o + v.size] += v.ravel()
     blk = olayout.blocks(d)
     worst = H.assert_grads_per_tensor(g, ref[:blk["actor"][1]], name, 0, 0, blk["actor"][1])
-    print(f"  worst per-tensor rel err {worst:.2e}")
+    print(f"  worst per-tensor (rel err, tol, tensor): {worst}")
