@@ -35,7 +35,9 @@ def parse():
     ap.add_argument("--capacity", type=int, default=65536)
     ap.add_argument("--frame", type=int, default=64, help="source frame side (64: k=4, 128: k=8)")
     ap.add_argument("--side", type=int, default=16, help="squinted side (16; 32 is the higher-resolution variant)")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the closed-loop serving point")
+    ap.add_argument("--serve-rate", type=float, default=50000.0, help="Poisson point of the default line, obs/s")
+    ap.add_argument("--serve-seconds-default", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the other-precision timing")
     ap.add_argument("--kernel-reps", type=int, default=50)
@@ -55,7 +57,7 @@ def parse():
                     help="UTD sweep {1,4,8,16} at batch 1024 on 128x128x9 frames (prints one JSON line)")
     ap.add_argument("--serve", action="store_true",
                     help="Poisson act() load at 2k..50k obs/s, pools U{1..4096} (prints one JSON line)")
-    ap.add_argument("--serve-seconds", type=float, default=12.0)
+    ap.add_argument("--serve-seconds", type=float, default=30.0)
     ap.add_argument("--report", action="store_true",
                     help="errors after 1 and N updates vs the FP64 oracle, BF16 and FP32 (prints one JSON line)")
     ap.add_argument("--report-updates", type=int, default=100)
@@ -262,36 +264,108 @@ def insert_path(cfg, rep, agent, a, n_env=1024):
     return out
 
 
-def serve_latency(agent, cfg, n_req, seed=3):
-    """Closed-loop burst of n_req pools (sizes U{1..4096}) through the server."""
-    import numpy as np
+def _serve_pool(cfg):
     import torch
 
-    from paper_2602_21203_amd import api, synthetic
-    rng = np.random.default_rng(seed)
+    from paper_2602_21203_amd import synthetic
     pool = synthetic.frames(4096, cfg["H"], cfg["W"], cfg["C"], seed=11, device="cuda")
     prop = torch.randn(4096, cfg["proprio"], device="cuda")
+    torch.cuda.synchronize()
+    return pool, prop
+
+
+def _latency_summary(srv, t_sub, sizes, t0, t1):
+    lat = sorted(srv.done[j] - t_sub[j] for j in range(len(sizes)))
+    st = srv.stats()
+    pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))] * 1e3
+    return {"requests": len(sizes), "p50_ms": round(pct(0.5), 3), "p99_ms": round(pct(0.99), 3),
+            "achieved_obs_per_s": round(float(sum(sizes)) / (t1 - t0), 1),
+            "gpu_busy_frac": round(st["device_busy_s"] / (t1 - t0), 4),
+            "batches": st["batches"], "fused_batches": st["fused_batches"],
+            "max_requests_per_batch": st["max_requests_per_batch"], "max_slots_busy": st["max_slots_busy"],
+            "overlapped_batches": st["overlapped_batches"]}
+
+
+def serve_poisson(agent, cfg, pool, prop, rate, seconds, max_requests, seed=3):
+    """Poisson arrivals of pools U{1..4096} at `rate` observations/s (request rate
+    rate / 2048.5) through the continuous-batching server, for `seconds` or
+    max_requests requests, whichever comes first.  Latency = completion (host
+    steady clock, in the server's callback) - scheduled arrival."""
+    import numpy as np
+
+    from paper_2602_21203_amd import api
+    rng = np.random.default_rng(seed)
     srv = api.Server(agent, mem_budget=16 << 30, max_batch_obs=8192, n_slots=4)
-    sizes = rng.integers(1, 4097, n_req)
-    t_sub = {}
+    lam = rate / 2048.5
+    t_sub, sizes = {}, []
     t0 = time.monotonic()
-    for i, n in enumerate(sizes):
+    t_next = t0
+    while len(sizes) < max_requests and time.monotonic() - t0 < seconds:
+        t_next += rng.exponential(1.0 / lam)
+        while True:
+            now = time.monotonic()
+            if now >= t_next:
+                break
+            time.sleep(min(0.0005, t_next - now))
+        n = int(rng.integers(1, 4097))
+        t_sub[len(sizes)] = t_next
+        sizes.append(n)
+        srv.submit(pool[:n], prop[:n], len(sizes) - 1, sample=True)
+    srv.drain()
+    out = dict(offered_obs_per_s=rate, **_latency_summary(srv, t_sub, sizes, t0, time.monotonic()))
+    srv.close()
+    return out
+
+
+def serve_closed_loop(agent, cfg, pool, prop, n_req=2000, in_flight=8, seed=4):
+    """Closed-loop saturation: n_req pools U{1..4096}, a new request submitted as
+    soon as fewer than `in_flight` are outstanding."""
+    import threading
+
+    import numpy as np
+
+    from paper_2602_21203_amd import api
+    rng = np.random.default_rng(seed)
+    srv = api.Server(agent, mem_budget=16 << 30, max_batch_obs=8192, n_slots=4)
+    cv = threading.Condition()
+    base_cb = srv._on_done
+
+    def on_done(rid, t, user):
+        base_cb(rid, t, user)
+        with cv:
+            cv.notify()
+    srv._cb = api.L.DONE_CB(on_done)
+    t_sub, sizes = {}, []
+    t0 = time.monotonic()
+    for i in range(n_req):
+        with cv:
+            cv.wait_for(lambda: i - len(srv.done) < in_flight)
+        n = int(rng.integers(1, 4097))
         t_sub[i] = time.monotonic()
+        sizes.append(n)
         srv.submit(pool[:n], prop[:n], i, sample=True)
     srv.drain()
-    t1 = time.monotonic()
-    lat = [srv.done[i] - t_sub[i] for i in range(n_req)]
+    out = dict(in_flight=in_flight, **_latency_summary(srv, t_sub, sizes, t0, time.monotonic()))
     srv.close()
-    lat.sort()
-    p = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
-    return dict(p50_ms=p(0.5) * 1e3, p99_ms=p(0.99) * 1e3, obs_per_s=float(sizes.sum()) / (t1 - t0),
-                requests=int(n_req), mode="burst of pools U{1..4096}, 4 slots")
+    return out
 
 
-def cpu_baseline(cfg, B, budget_s=15.0):
-    """The FP64 oracle timed on the host cores on a bounded sample of updates."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, B, budget_s=12.0):
+    """The FP64 oracle timed on the host cores on a bounded sample of updates,
+    with the BLAS pool at all its threads and at one thread."""
     import numpy as np
     import torch
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import layout as olayout
     from oracle import sac
@@ -301,21 +375,25 @@ def cpu_baseline(cfg, B, budget_s=15.0):
     params = synthetic.init_params(table, seed=1).astype(np.float64)
     cpu = synthetic.replay(2048, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=0)
     rep = {k: (v.numpy() if torch.is_tensor(v) else v) for k, v in cpu.items()}
-    st = sac.new_state(d, params)
     hp = sac.hparams(d)
-    sac.sac_update(st, rep, d, hp, B)          # warm-up (not timed)
-    n, t0 = 0, time.perf_counter()
-    while n < 2 or (time.perf_counter() - t0 < budget_s and n < 100):
-        sac.sac_update(st, rep, d, hp, B)
-        n += 1
-    dt = time.perf_counter() - t0
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
-    return dict(value=n / dt, unit="updates/s", cores=int(cores), kind="oracle",
-                sample=f"{n} FP64 oracle updates at batch {B} (full network, 64x64x9 frames) after 1 warm-up")
+
+    def rate(budget):
+        st = sac.new_state(d, params)
+        sac.sac_update(st, rep, d, hp, B)          # warm-up (not timed)
+        n, t0 = 0, time.perf_counter()
+        while n < 2 or (time.perf_counter() - t0 < budget and n < 100):
+            sac.sac_update(st, rep, d, hp, B)
+            n += 1
+        return n, n / (time.perf_counter() - t0)
+
+    n_all, r_all = rate(budget_s)
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    with threadpool_limits(limits=1):
+        n_one, r_one = rate(budget_s)
+    return dict(value=r_all, unit="updates/s", cores=int(threads), kind="oracle",
+                sample=f"{n_all} FP64 oracle updates at batch {B} (full network, 64x64x9 frames) after 1 warm-up, "
+                       f"BLAS pool of {threads} threads; one thread: {n_one} updates",
+                cpu_model=cpu_model(), host_cpus=os.cpu_count(), one_thread_value=r_one)
 
 
 def run_sweep(a):
@@ -405,53 +483,32 @@ def run_env_loop(a):
 
 
 def run_serve(a):
-    import numpy as np
-    import torch
-
     from paper_2602_21203_amd import _lib, api, synthetic
     cfg = cfg_for(64)
     table, _ = _lib.param_table(cfg)
     params = synthetic.init_params(table, seed=1)
     agent = api.Agent(cfg, params, 32, prec=_lib.SQ_BF16)
-    pool = synthetic.frames(4096, cfg["H"], cfg["W"], cfg["C"], seed=11, device="cuda")
-    prop = torch.randn(4096, cfg["proprio"], device="cuda")
-    torch.cuda.synchronize()
-    rng = np.random.default_rng(3)
+    pool, prop = _serve_pool(cfg)
     out = {"mode": "act_serving", "workload": "act() of BF16 full network on 64x64x9 frames, pools U{1..4096}, "
                                               "Poisson arrivals, 4 stream slots, weights resident",
            "points": []}
-    for rate in (2000, 5000, 10000, 20000, 50000):
-        srv = api.Server(agent, mem_budget=16 << 30, max_batch_obs=8192, n_slots=4)
-        lam = rate / 2048.5
-        t_sub, sizes = {}, []
-        t0 = time.monotonic()
-        t_next = t0
-        i = 0
-        while time.monotonic() - t0 < a.serve_seconds:
-            t_next += rng.exponential(1.0 / lam)
-            while True:
-                now = time.monotonic()
-                if now >= t_next:
-                    break
-                time.sleep(min(0.0005, t_next - now))
-            n = int(rng.integers(1, 4097))
-            t_sub[i] = t_next
-            sizes.append(n)
-            srv.submit(pool[:n], prop[:n], i, sample=True)
-            i += 1
-        srv.drain()
-        t1 = time.monotonic()
-        lat = sorted(srv.done[j] - t_sub[j] for j in range(i))
-        srv.close()
-        pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))] * 1e3
-        out["points"].append({"offered_obs_per_s": rate, "requests": i, "p50_ms": round(pct(0.5), 3),
-                              "p99_ms": round(pct(0.99), 3), "achieved_obs_per_s": round(sum(sizes) / (t1 - t0), 1)})
+    # the configured rates (a few requests per second: each point holds what
+    # arrives in --serve-seconds), then rates that load the device, where 2000
+    # requests arrive within seconds
+    for rate in (2000, 5000, 10000, 20000, 50000, 500000, 2000000, 8000000):
+        p = serve_poisson(agent, cfg, pool, prop, rate, a.serve_seconds, 2000)
+        print(json.dumps(p), file=sys.stderr, flush=True)
+        out["points"].append(p)
+    out["closed_loop"] = [serve_closed_loop(agent, cfg, pool, prop, 2000, k) for k in (1, 4, 8, 16)]
     agent.close()
     print(json.dumps(out))
 
 
 def run_report(a):
-    """Losses, gradients and parameters after 1 and N updates: GPU BF16 and FP32 vs the FP64 oracle."""
+    """Precision report: GPU BF16 and FP32 updates against three references over
+    the same N updates -- the FP64 oracle, the oracle's bfloat16-operand mode, and
+    the FP32 GPU path -- on the loss statistics, the first update's gradients and
+    the parameters after N updates."""
     import numpy as np
     import torch
 
@@ -467,44 +524,69 @@ def run_report(a):
     gpu = {k: (v.cuda() if torch.is_tensor(v) else v) for k, v in cpu.items()}
     npr = {k: (v.numpy() if torch.is_tensor(v) else v) for k, v in cpu.items()}
     N = a.report_updates
-    st = sac.new_state(d, params.astype(np.float64))
-    hp = sac.hparams(d)
-    ref_stats, ref_g1, ref_p1 = [], None, None
-    for u in range(N):
-        if u % 10 == 0:
-            print(f"oracle update {u}/{N}", file=sys.stderr, flush=True)
-        o = sac.sac_update(st, npr, d, hp, B)
-        ref_stats.append(o["stats"])
-        if u == 0:
-            ref_g1 = np.concatenate([o["g_enc_critic"], o["g_actor"]])
-            ref_p1 = st.params.copy()
-    ref_stats = np.array(ref_stats)
-    out = {"mode": "precision_report", "batch": B, "updates": N, "workload": "full network, 64x64x9 frames",
-           "results": {}}
+    blk = olayout.blocks(d)
+
+    def flat_grads(o):
+        g = np.zeros(blk["total"])
+        g[:blk["critic"][1]] = o["g_enc_critic"]
+        g[blk["actor"][0]:blk["actor"][1]] = o["g_actor"]
+        g[blk["log_alpha"][0]] = o["g_log_alpha"][0]
+        return g
+
+    refs = {}
+    for name, bf in (("oracle_fp64", False), ("oracle_bf16_operands", True)):
+        st = sac.new_state(d, params.astype(np.float64))
+        hp = sac.hparams(d)
+        stats, g1 = [], None
+        for u in range(N):
+            if u % 10 == 0:
+                print(f"{name} update {u}/{N}", file=sys.stderr, flush=True)
+            o = sac.sac_update(st, npr, d, hp, B, bf=bf)
+            stats.append(o["stats"])
+            if u == 0:
+                g1 = flat_grads(o)
+        refs[name] = dict(stats=np.array(stats), g1=g1, pN=st.params.copy())
+    runs = {}
     for name, prec in (("bf16", _lib.SQ_BF16), ("fp32", _lib.SQ_F32)):
         ag = api.Agent(cfg, params, B, prec=prec)
         s1 = ag.sac_update(gpu, 1, graph=False).cpu().numpy()
         torch.cuda.synchronize()
         g1 = ag.grads.double().cpu().numpy()
-        p1 = ag.params.double().cpu().numpy()
-        sN = ag.sac_update(gpu, N - 1, graph=True).cpu().numpy() if N > 1 else s1
+        sN = ag.sac_update(gpu, N - 1, graph=True).cpu().numpy() if N > 1 else s1[:0]
         torch.cuda.synchronize()
-        pN = ag.params.double().cpu().numpy()
-        stats = np.concatenate([s1, sN]) if N > 1 else s1
-        ga = g1[:olayout.blocks(d)["actor"][1]]
-        rel = lambda x, y: float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-30))
-        out["results"][name] = {
-            "critic_loss_rel_err_update1": float(abs(s1[0, 0] - ref_stats[0, 0]) / abs(ref_stats[0, 0])),
-            "critic_loss_rel_err_last": float(abs(stats[-1, 0] - ref_stats[-1, 0]) / abs(ref_stats[-1, 0])),
-            "actor_loss_abs_err_update1": float(abs(s1[0, 1] - ref_stats[0, 1])),
-            "actor_loss_abs_err_last": float(abs(stats[-1, 1] - ref_stats[-1, 1])),
-            "grad_rel_err_update1": rel(ga, ref_g1),
-            "param_max_abs_err_update1": float(np.abs(p1 - ref_p1).max()),
-            "param_rel_err_last": rel(pN, st.params),
-            "max_critic_loss_rel_err_all_updates": float(np.max(np.abs(stats[:, 0] - ref_stats[:, 0]) /
-                                                                np.abs(ref_stats[:, 0]))),
-        }
+        runs[name] = dict(stats=np.concatenate([s1, sN]).astype(np.float64), g1=g1,
+                          pN=ag.params.double().cpu().numpy())
         ag.close()
+    refs["gpu_fp32"] = runs["fp32"]
+    rel = lambda x, y: float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-30))
+
+    def worst_tensor(g, r):
+        w = (0.0, "")
+        for n, (o, shp) in olayout.offsets(d)[0].items():
+            k = int(np.prod(shp))
+            w = max(w, (rel(g[o:o + k], r[o:o + k]), n))
+        return {"rel_err": w[0], "tensor": w[1]}
+
+    out = {"mode": "precision_report", "batch": B, "updates": N, "workload": "full network, 64x64x9 frames",
+           "results": {}}
+    for name, run in runs.items():
+        res = {}
+        for rname, ref in refs.items():
+            if rname == "gpu_fp32" and name == "fp32":
+                continue
+            S, R = run["stats"], ref["stats"]
+            cl = np.abs(S[:, 0] - R[:, 0]) / np.abs(R[:, 0])
+            res["vs_" + rname] = {
+                "critic_loss_rel_err_update1": float(cl[0]), "critic_loss_rel_err_last": float(cl[-1]),
+                "critic_loss_rel_err_max": float(cl.max()),
+                "critic_loss_rel_err_by_update": [float(cl[i]) for i in (0, 1, 3, 9, 29, N - 1) if i < N],
+                "actor_loss_abs_err_update1": float(abs(S[0, 1] - R[0, 1])),
+                "actor_loss_abs_err_last": float(abs(S[-1, 1] - R[-1, 1])),
+                "grad_rel_err_update1": rel(run["g1"], ref["g1"]),
+                "grad_worst_tensor_update1": worst_tensor(run["g1"], ref["g1"]),
+                "param_rel_err_last": rel(run["pN"], ref["pN"]),
+            }
+        out["results"][name] = res
     print(json.dumps(out))
 
 
@@ -575,6 +657,8 @@ def main():
                                                               "paper_2602_21203_amd/csrc/kernels/gemm.hip")
                           if a.prec == "bf16" else None,
                           "avg_us": round(t_g * 1e6, 3), "algorithmic_flops": flops,
+                          "method": "achieved = algorithmic FLOP per launch / avg_us, the start-to-start period of "
+                                    "back-to-back launches replayed from a HIP graph (HIP events on the launch stream)",
                           "algorithmic_bytes": 3 * 2 * 512 * 512 * 4 + 2 * 512 * 4}
     if a.state:
         agent.close()
@@ -600,7 +684,12 @@ def main():
     if not a.no_insert:
         result["insert_path"] = insert_path(cfg, rep, agent, a)
     if a.serve_requests > 0:
-        result["act_serving"] = serve_latency(agent, cfg, a.serve_requests)
+        pool, prop = _serve_pool(cfg)
+        result["act_serving"] = {
+            "workload": "act() of the full network (agent precision) on 64x64x9 frames, pools U{1..4096}, "
+                        "4 stream slots, weights resident",
+            "poisson": serve_poisson(agent, cfg, pool, prop, a.serve_rate, a.serve_seconds_default, 2000),
+            "closed_loop": serve_closed_loop(agent, cfg, pool, prop, a.serve_requests, 8)}
     agent.close()
     if not a.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(cfg, B)

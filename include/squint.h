@@ -7,8 +7,10 @@
  *   Ownership     the caller allocates and frees every buffer it passes; the
  *                 library only borrows them for the call (an sq_agent borrows
  *                 the buffers given to sq_agent_create for its lifetime).  The
- *                 library allocates device memory only in sq_agent_create and
- *                 sq_server_create and frees it in the matching *_destroy.
+ *                 library allocates device memory only in sq_agent_create,
+ *                 sq_server_create, sq_ring_create, sq_env_create and when
+ *                 sac_update captures a new graph, and frees it in the matching
+ *                 *_destroy (or when the graph is evicted).
  *   Streams       calls are asynchronous on `stream` (a hipStream_t; NULL is the
  *                 null stream).  No call synchronises the device except the
  *                 sq_server_* host waits.
@@ -193,14 +195,16 @@ SQ_API int actor_bwd(const sq_dims* dims, sq_prec prec, const sq_hparams* hp, co
               sq_stream_t stream);
 
 /* Adam with bias correction (the paper's gradient steps, read as Adam):
- *   t = *step + 1 (the counter itself is NOT modified),
+ *   t = *step + 1,
  *   m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
- *   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+ *   p -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps),
+ * then *step = t (a one-thread launch ordered after the update on `stream`).
  * Optionally updates an EMA target (Alg. 1 target update) for i >= ema_begin:
  *   ema_target[i - ema_begin] = rho ema_target[i - ema_begin] + (1 - rho) p_new[i],
- * and writes bfloat16 bits of p_new to p_bf16.  n elements; step: [1] int. */
+ * and writes bfloat16 bits of p_new to p_bf16.  n elements (n = 0 only advances
+ * the counter); step: [1] int, device. */
 SQ_API int adam_step(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp,
-              const int* step, uint16_t* p_bf16, float* ema_target, long long ema_begin, sq_stream_t stream);
+              int* step, uint16_t* p_bf16, float* ema_target, long long ema_begin, sq_stream_t stream);
 
 /* Batched dense product on the matrix cores, the building block of every
  * linear layer above (exposed for tests and measurement):
@@ -238,8 +242,15 @@ SQ_API int sq_agent_sync(sq_agent* agent, sq_stream_t stream);
  * summed cross entropy, step log alpha, step the actor when u % policy_freq
  * == 0, update the target EMA, write stats[u_local, 0..7] = {critic loss,
  * actor loss, alpha loss, alpha, entropy, mean Q, mean target, non-finite}.
- * The first call for a given (n_updates, replay, stats, stream) captures a HIP
- * graph; later identical calls replay it.  stats: [n_updates, 8] float. */
+ * The first call for a given (n_updates, replay contents, stream, policy_freq
+ * phase) captures a HIP graph and allocates its [n_updates, 8] statistics buffer;
+ * later calls with the same key replay the graph and copy the statistics to
+ * `stats` (so `stats` may differ between calls).  At most 8 graphs are kept per
+ * agent: a miss beyond that destroys the least recently used one after a device
+ * synchronisation.  A non-finite statistic (stats[u, 7] = 1, e.g. from a NaN
+ * reward) does not stop the update: the parameters take the non-finite step as
+ * computed, and the caller restores them.  stats: [n_updates, 8] float.
+ * Inside a caller's capture the kernels are recorded into that graph directly. */
 SQ_API int sac_update(sq_agent* agent, const sq_replay* replay, int n_updates, float* stats, sq_stream_t stream);
 /* The same sequence launched kernel by kernel, without a graph. */
 SQ_API int sac_update_eager(sq_agent* agent, const sq_replay* replay, int n_updates, float* stats, sq_stream_t stream);
@@ -327,16 +338,47 @@ SQ_API int sq_env_step(sq_env* env, const float* action, sq_stream_t stream);
 
 /* ---------------------------------------------------------------- serving */
 typedef void (*sq_done_cb)(unsigned long long request_id, double t_done_s, void* user);
-/* Continuous-batching act() server: a host scheduler thread fuses queued
- * requests (FIFO, no skipping) into one launch on a free stream slot when the
- * batch's workspace fits mem_budget; batches on different slots overlap. */
+/* Continuous-batching act() server (Alg. 1 action sampling for many environment
+ * pools): a host scheduler thread fuses queued requests (FIFO, no skipping) into
+ * one launch on a free stream slot when the batch's rows stay within
+ * max_batch_obs and its workspace fits the memory budget still free; batches
+ * on different slots overlap on the device.  A host function enqueued after each
+ * batch wakes the scheduler (no polling).  Each row's result does not depend on
+ * the rows it shares a launch with, so a request gets the same bits alone or in
+ * any mix.  The server reads the agent's weights in place (no copy). */
 SQ_API int sq_server_create(sq_agent* agent, size_t mem_budget, int max_batch_obs, int n_slots, sq_server** out);
+/* Queue one request of n observations (frames [n, H, W, C] uint8, proprio [n, P],
+ * device; action_out [n, A], device).  The buffers must stay valid until the
+ * callback (host steady-clock completion time in seconds) has run. */
 SQ_API int sq_server_submit(sq_server* srv, const uint8_t* frames, const float* proprio, int n, int sample,
                      unsigned long long request_id, float* action_out, sq_done_cb cb, void* user);
+/* Block until every queued request has completed and its callback returned. */
 SQ_API int sq_server_drain(sq_server* srv);
+/* hold = 1 pauses admissions (requests keep queueing), hold = 0 resumes them. */
+SQ_API int sq_server_hold(sq_server* srv, int hold);
+typedef struct {
+  long long batches;               /* launches */
+  long long requests, rows;        /* requests and observations launched */
+  long long fused_batches;         /* launches that fused two or more requests */
+  int max_requests_per_batch;
+  int max_slots_busy;              /* most slots holding a batch at once */
+  long long overlapped_batches;    /* batches whose device interval began before an earlier one ended */
+  double device_busy_s;            /* union of the batches' device intervals (timing events) */
+  double device_span_s;            /* first batch start to last batch end on the device */
+} sq_server_stats;
+/* Counters since sq_server_create (completed batches for the device times). */
+SQ_API int sq_server_get_stats(sq_server* srv, sq_server_stats* out /*[host]*/);
 SQ_API int sq_server_destroy(sq_server* srv);
 
 /* ---------------------------------------------------------------- test hooks */
+/* Graphs captured by sac_update so far, and graphs currently cached.  [host] */
+SQ_API int sq_agent_graph_count(const sq_agent* agent, long long* captured, int* cached);
+/* Copy of the replay rows drawn by the agent's last enqueued update (idx [batch]
+ * int, device), ordered on `stream` after that update. */
+SQ_API int sq_agent_last_indices(const sq_agent* agent, int* idx, sq_stream_t stream);
+/* Row of transition i of an insertion at write position pos in a ring of
+ * `capacity` rows: (pos + i) mod capacity, in 64-bit arithmetic.  [host] */
+SQ_API int sq_ring_row(int pos, long long i, int capacity, int* row);
 /* idx[b] = mulhi32(Philox4x32_10(ctr = (update, 0, b, 0), key = seed).w0, size). */
 SQ_API int sq_sample_indices(unsigned long long seed, unsigned int update, int size, int n, int* idx,
                       sq_stream_t stream);

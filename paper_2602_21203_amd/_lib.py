@@ -44,6 +44,12 @@ class EnvBuffers(ctypes.Structure):
                 ("next_proprio", c_vp), ("reward", c_vp), ("done", c_vp)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("batches", c_ll), ("requests", c_ll), ("rows", c_ll), ("fused_batches", c_ll),
+                ("max_requests_per_batch", c_int), ("max_slots_busy", c_int), ("overlapped_batches", c_ll),
+                ("device_busy_s", ctypes.c_double), ("device_span_s", ctypes.c_double)]
+
+
 DONE_CB = ctypes.CFUNCTYPE(None, ctypes.c_ulonglong, ctypes.c_double, ctypes.c_void_p)
 
 
@@ -83,6 +89,8 @@ def _load():
         "sq_server_submit": (c_int, [c_vp, c_vp, c_vp, c_int, c_int, c_ull, c_vp, DONE_CB, c_vp]),
         "sq_server_drain": (c_int, [c_vp]),
         "sq_server_destroy": (c_int, [c_vp]),
+        "sq_server_hold": (c_int, [c_vp, c_int]),
+        "sq_server_get_stats": (c_int, [c_vp, P(ServerStats)]),
         "sq_ring_create": (c_int, [P(Dims), c_int, P(c_vp)]),
         "sq_ring_destroy": (c_int, [c_vp]),
         "sq_ring_insert": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_int, c_vp]),
@@ -96,6 +104,9 @@ def _load():
                             c_vp, c_ll, c_ll, c_vp, c_ll, c_int, c_vp]),
         "sq_sample_indices": (c_int, [c_ull, ctypes.c_uint, c_int, c_int, c_vp, c_vp]),
         "sq_gaussian": (c_int, [c_ull, ctypes.c_uint, ctypes.c_uint, c_int, c_vp, c_vp]),
+        "sq_agent_graph_count": (c_int, [c_vp, P(c_ll), P(c_int)]),
+        "sq_agent_last_indices": (c_int, [c_vp, c_vp, c_vp]),
+        "sq_ring_row": (c_int, [c_int, c_ll, c_int, P(c_int)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -341,7 +341,6 @@ class Agent:
         check(L.LIB.sq_agent_create(_dims(cfg), ctypes.byref(self.hp), batch, ptr(self.params), ptr(self.target),
                                     ptr(self.m), ptr(self.v), ptr(self.grads), ptr(self.counters), ctypes.byref(h)))
         self.handle = h
-        self._replays = {}
         # graphs cannot be captured on the null stream: updates run on a side
         # stream ordered against the caller's current stream
         self.stream = torch.cuda.Stream(device=self.params.device)
@@ -360,13 +359,9 @@ class Agent:
 
     def sac_update(self, replay, n_updates, stats=None, graph=True, stream=None):
         """replay: a dict of device tensors (raw frames) or a Ring."""
-        if isinstance(replay, Ring):
-            rs = replay.view
-        else:
-            key = id(replay)
-            if key not in self._replays:
-                self._replays[key] = (replay, replay_struct(replay))
-            rs = self._replays[key][1]
+        # the view is rebuilt on every call (a few pointers), so a dict whose
+        # size grew or whose tensors were replaced is seen as it is now
+        rs = replay.view if isinstance(replay, Ring) else replay_struct(replay)
         if stats is None:
             stats = torch.empty((n_updates, L.N_STATS), dtype=torch.float32, device=self.params.device)
         _req(stats, torch.float32, (n_updates, L.N_STATS), "stats")
@@ -382,6 +377,21 @@ class Agent:
         if joined:
             caller.wait_stream(self.stream)
         return stats
+
+    def graph_count(self):
+        """(graphs captured so far, graphs cached) by sac_update."""
+        n, c = ctypes.c_longlong(), ctypes.c_int()
+        check(L.LIB.sq_agent_graph_count(self.handle, ctypes.byref(n), ctypes.byref(c)))
+        return n.value, c.value
+
+    def last_indices(self, stream=None):
+        """Replay rows drawn by the last enqueued update ([batch] int32, device),
+        ordered after it on the agent's stream."""
+        idx = torch.empty(self.batch, dtype=torch.int32, device=self.params.device)
+        st = self.stream if stream is None else stream
+        check(L.LIB.sq_agent_last_indices(self.handle, ptr(idx), stream_handle(st)))
+        st.synchronize()
+        return idx
 
     def sync(self, stream=None):
         """Refresh the agent's derived weight copies after params / target were
@@ -434,6 +444,16 @@ class Server:
 
     def drain(self):
         check(L.LIB.sq_server_drain(self.handle))
+
+    def hold(self, on=True):
+        """Pause (True) or resume (False) admissions; requests keep queueing."""
+        check(L.LIB.sq_server_hold(self.handle, int(bool(on))))
+
+    def stats(self):
+        """Launch counters and the device busy time of the completed batches."""
+        st = L.ServerStats()
+        check(L.LIB.sq_server_get_stats(self.handle, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in L.ServerStats._fields_}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -230,14 +230,17 @@ int actor_bwd(const sq_dims* dims, sq_prec prec, const sq_hparams* hp, const flo
                         dlogp, nullptr, 0.f, hp->log_std_min, hp->log_std_max, w.a, dparams, (hipStream_t)stream);
 }
 
-int adam_step(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, const int* step,
+int adam_step(float* p, const float* g, float* m, float* v, long long n, const sq_hparams* hp, int* step,
               uint16_t* p_bf16, float* ema_target, long long ema_begin, sq_stream_t stream) {
   SQ_REQUIRE(hp, "hp is NULL");
   SQ_REQUIRE(n >= 0, "n < 0");
-  if (n == 0) return SQ_OK;
-  SQ_REQUIRE(p && g && m && v && step, "NULL argument");
-  SQ_REQUIRE(ema_begin >= 0 && ema_begin <= n, "ema_begin out of range");
-  return adam(p, g, m, v, n, hp, step, ema_target, ema_begin, p_bf16, nullptr, (hipStream_t)stream);
+  SQ_REQUIRE(step, "step is NULL");
+  if (n > 0) {
+    SQ_REQUIRE(p && g && m && v, "NULL argument");
+    SQ_REQUIRE(ema_begin >= 0 && ema_begin <= n, "ema_begin out of range");
+    SQ_TRY(adam(p, g, m, v, n, hp, step, ema_target, ema_begin, p_bf16, nullptr, (hipStream_t)stream));
+  }
+  return launch_step_advance(step, (hipStream_t)stream);
 }
 
 int sq_gemm(sq_prec prec, int M, int N, int K, int batch, const float* A, long long a_lr, long long a_lk,

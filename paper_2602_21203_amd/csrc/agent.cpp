@@ -60,13 +60,35 @@ size_t act_bytes_per_obs(const Net& net) {
 
 using namespace sq;
 
+// A captured block of updates.  The graph writes its statistics rows into a
+// buffer of its own and copies them out in its last node, whose destination is
+// set to the caller's pointer before a launch (only when it changed), so the
+// caller's stats pointer is not part of the key.
 struct GraphEntry {
   int n_updates, phase;
-  sq_replay rep;
-  float* stats;
+  sq_replay rep;          // compared field by field (the struct has padding)
   hipStream_t stream;
+  hipGraph_t graph;       // kept for the copy node's handle
   hipGraphExec_t exec;
+  hipGraphNode_t copy_node;
+  hipKernelNodeParams copy_params;
+  float* stats;           // [n_updates, 8], library-owned
+  float* dst;             // destination of the copy node at the last launch
+  unsigned long long last_use;
 };
+
+static void destroy_entry(GraphEntry& e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.graph) (void)hipGraphDestroy(e.graph);
+  if (e.stats) (void)hipFree(e.stats);
+}
+constexpr size_t kMaxGraphs = 8;   // least recently used graph evicted beyond this
+
+static bool same_replay(const sq_replay& a, const sq_replay& b) {
+  return a.obs == b.obs && a.next_obs == b.next_obs && a.proprio == b.proprio && a.next_proprio == b.next_proprio &&
+         a.action == b.action && a.reward == b.reward && a.done == b.done && a.capacity == b.capacity &&
+         a.size == b.size && a.squinted == b.squinted && a.dev_size == b.dev_size;
+}
 
 struct sq_agent {
   Net net;
@@ -91,6 +113,8 @@ struct sq_agent {
   int act_cap;
   ActBufs actw;
   std::vector<GraphEntry> graphs;
+  unsigned long long graph_clock = 0;
+  long long graphs_captured = 0;
   PackArgs pk_critic, pk_actor;   // pack refresh tables of the two Adam launches
   GradSegs gs_critic, gs_actor;   // bias / gain / shift gradients the Adam launches sum from partials
   bool enc_seg = false;           // gs_critic also sums the fused encoder's partial gradients
@@ -353,7 +377,8 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
 
 int sq_agent_destroy(sq_agent* g) {
   if (!g) return SQ_OK;
-  for (auto& e : g->graphs) (void)hipGraphExecDestroy(e.exec);
+  if (!g->graphs.empty()) (void)hipDeviceSynchronize();
+  for (auto& e : g->graphs) destroy_entry(e);
   if (g->ws) (void)hipFree(g->ws);
   delete g;
   return SQ_OK;
@@ -367,6 +392,51 @@ int sac_update_eager(sq_agent* g, const sq_replay* R, int n_updates, float* stat
   SQ_TRY(check_replay(g, R));
   SQ_TRY(enqueue_block(g, R, n_updates, stats, (hipStream_t)stream));
   g->u_host += n_updates;
+  return SQ_OK;
+}
+
+// Capture n updates and the statistics copy on st into e (graph, exec, copy node).
+static int capture_block(sq_agent* g, const sq_replay* R, int n, hipStream_t st, GraphEntry* e) {
+  hipError_t he = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (he != hipSuccess) {
+    set_error("hipStreamBeginCapture failed: %s", hipGetErrorString(he));
+    return SQ_EDEVICE;
+  }
+  int s = enqueue_block(g, R, n, e->stats, st);
+  if (s == SQ_OK) s = launch_copy_stats(e->stats, e->dst, 8 * n, st);
+  const hipError_t ce = hipStreamEndCapture(st, &e->graph);
+  if (s != SQ_OK) return s;
+  if (ce != hipSuccess) {
+    set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
+    return SQ_EDEVICE;
+  }
+  // find the copy node (the only launch of its kernel in the graph)
+  size_t nn = 0;
+  SQ_TRY_HIP(hipGraphGetNodes(e->graph, nullptr, &nn));
+  std::vector<hipGraphNode_t> nodes(nn);
+  SQ_TRY_HIP(hipGraphGetNodes(e->graph, nodes.data(), &nn));
+  e->copy_node = nullptr;
+  for (size_t i = 0; i < nn; ++i) {
+    hipGraphNodeType t;
+    SQ_TRY_HIP(hipGraphNodeGetType(nodes[i], &t));
+    if (t != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp{};
+    SQ_TRY_HIP(hipGraphKernelNodeGetParams(nodes[i], &kp));
+    if (kp.func == copy_stats_kernel()) {
+      e->copy_node = nodes[i];
+      e->copy_params = kp;
+    }
+  }
+  if (!e->copy_node) {
+    set_error("the captured graph has no statistics copy node");
+    return SQ_EDEVICE;
+  }
+  const hipError_t ie = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    e->exec = nullptr;
+    set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
+    return SQ_EDEVICE;
+  }
   return SQ_OK;
 }
 
@@ -388,39 +458,63 @@ int sac_update(sq_agent* g, const sq_replay* R, int n_updates, float* stats, sq_
   const int phase = (int)(g->u_host % g->hp.policy_freq);
   GraphEntry* hit = nullptr;
   for (auto& e : g->graphs)
-    if (e.n_updates == n_updates && e.phase == phase && e.stats == stats && e.stream == st &&
-        memcmp(&e.rep, R, sizeof(sq_replay)) == 0)
-      hit = &e;
+    if (e.n_updates == n_updates && e.phase == phase && e.stream == st && same_replay(e.rep, *R)) hit = &e;
   if (!hit) {
-    GraphEntry e;
+    if (g->graphs.size() >= kMaxGraphs) {
+      // evict the least recently used graph; its launches may still be in flight
+      size_t old = 0;
+      for (size_t i = 1; i < g->graphs.size(); ++i)
+        if (g->graphs[i].last_use < g->graphs[old].last_use) old = i;
+      SQ_TRY_HIP(hipDeviceSynchronize());
+      destroy_entry(g->graphs[old]);
+      g->graphs.erase(g->graphs.begin() + (long)old);
+    }
+    GraphEntry e{};
     e.n_updates = n_updates;
     e.phase = phase;
     e.rep = *R;
-    e.stats = stats;
     e.stream = st;
-    SQ_TRY_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    const int s = enqueue_block(g, R, n_updates, stats, st);
-    hipGraph_t graph = nullptr;
-    const hipError_t ce = hipStreamEndCapture(st, &graph);
+    e.dst = stats;
+    if (hipMalloc(&e.stats, sizeof(float) * 8 * (size_t)n_updates) != hipSuccess) {
+      set_error("hipMalloc of the graph's %d statistics rows failed", n_updates);
+      return SQ_ENOMEM;
+    }
+    const int s = capture_block(g, R, n_updates, st, &e);
     if (s != SQ_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
+      destroy_entry(e);
       return s;
     }
-    if (ce != hipSuccess) {
-      set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ce));
-      return SQ_EDEVICE;
-    }
-    const hipError_t ie = hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (ie != hipSuccess) {
-      set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ie));
-      return SQ_EDEVICE;
-    }
     g->graphs.push_back(e);
+    ++g->graphs_captured;
     hit = &g->graphs.back();
+  }
+  hit->last_use = ++g->graph_clock;
+  if (hit->dst != stats) {
+    // point the copy node at this call's stats buffer
+    const float* src = hit->stats;
+    float* dst = stats;
+    int n = 8 * n_updates;
+    void* args[] = {&src, &dst, &n};
+    hipKernelNodeParams kp = hit->copy_params;
+    kp.kernelParams = args;
+    SQ_TRY_HIP(hipGraphExecKernelNodeSetParams(hit->exec, hit->copy_node, &kp));
+    hit->dst = stats;
   }
   SQ_TRY_HIP(hipGraphLaunch(hit->exec, st));
   g->u_host += n_updates;
+  return SQ_OK;
+}
+
+int sq_agent_graph_count(const sq_agent* g, long long* captured, int* cached) {
+  if (!g || !captured || !cached) { set_error("NULL argument to sq_agent_graph_count"); return SQ_EINVAL; }
+  *captured = g->graphs_captured;
+  *cached = (int)g->graphs.size();
+  return SQ_OK;
+}
+
+int sq_agent_last_indices(const sq_agent* g, int* idx, sq_stream_t stream) {
+  if (!g || !idx) { set_error("NULL argument to sq_agent_last_indices"); return SQ_EINVAL; }
+  SQ_TRY_HIP(hipMemcpyAsync(idx, g->idx, sizeof(int) * (size_t)g->B, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return SQ_OK;
 }
 

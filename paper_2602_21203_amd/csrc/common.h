@@ -152,6 +152,11 @@ int env_step(const EnvState& E, const float* action, float* prop_t, uint8_t* nex
 // where a squint launch writes (see squint.hip)
 enum { kSqF32 = 0, kSqBF16 = 1, kSqU8 = 2 };
 struct SqDst { int mode; void* out; void* out1; long long row_stride; int pos, cap; RingRows f; };
+// ring row of the i-th transition of an insertion at write position pos: (pos + i)
+// mod cap in 64-bit arithmetic (pos + i can pass 2^31 when cap is near 2^31 - 1)
+__host__ __device__ __forceinline__ int ring_row(int pos, long long i, int cap) {
+  return (int)(((long long)pos + i) % (long long)cap);
+}
 // squint at insertion: n transitions' obs and next_obs [n, H, W, C] -> uint8 block
 // means [side, side, C] in rows (pos + i) % cap of ring_obs / ring_next, and the
 // transitions' small fields into the same rows (f)
@@ -358,6 +363,11 @@ struct AlphaJob {
   float* log_alpha; float* grad; float* m; float* v; const int* ctr; float* scal;
   int* step_snap;
 };
+// *step += 1 in a one-thread launch (the standalone Adam step's counter)
+int launch_step_advance(int* step, hipStream_t st);
+// dst[0, n) = src[0, n) in one workgroup; copy_stats_kernel() names its kernel
+int launch_copy_stats(const float* src, float* dst, int n, hipStream_t st);
+const void* copy_stats_kernel();
 struct FinishJob;
 // fj: one more workgroup of the launch ends the update (statistics, counter
 // advance); `step` must then not be one of the counters it advances

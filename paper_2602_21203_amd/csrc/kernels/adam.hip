@@ -241,6 +241,28 @@ int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hpa
   return launch_status("adam");
 }
 
+// the standalone Adam step's counter advance, ordered after the update on its stream
+__global__ void k_step_advance(int* step) {
+  if (threadIdx.x == 0) *step += 1;
+}
+
+int launch_step_advance(int* step, hipStream_t st) {
+  k_step_advance<<<1, 64, 0, st>>>(step);
+  return launch_status("step advance");
+}
+
+// statistics rows of a captured block of updates, copied out to the caller's
+// buffer (the last node of the graph; its destination is updated per launch)
+__global__ void k_copy_stats(const float* __restrict__ src, float* __restrict__ dst, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+}
+
+int launch_copy_stats(const float* src, float* dst, int n, hipStream_t st) {
+  k_copy_stats<<<1, 256, 0, st>>>(src, dst, n);
+  return launch_status("copy stats");
+}
+
+const void* copy_stats_kernel() { return reinterpret_cast<const void*>(&k_copy_stats); }
 
 // rows of every packed segment; padding columns are written as zero
 __global__ void k_pack(PackArgs pk, const float* __restrict__ params, const float* __restrict__ target,

@@ -522,13 +522,19 @@ __device__ __forceinline__ void softmax_row(const float* l, int N, int lane, flo
 __device__ float project_row(const float* p, int N, int lane, float v_min, float dz, float r, float d, float gamma,
                              float bonus, float* m_out) {
   float bpos[kMaxAtomsPerLane];
+  int nan_lane = 0;
 #pragma unroll
   for (int t = 0; t < kMaxAtomsPerLane; ++t) {
     const int j = lane + 64 * t;
     const float zj = v_min + (float)j * dz;
     const float tz = r + gamma * (1.f - d) * (zj + bonus);
-    bpos[t] = fminf(fmaxf((tz - v_min) / dz, 0.f), (float)(N - 1));
+    const float q = (tz - v_min) / dz;
+    nan_lane |= (j < N) & (q != q);
+    bpos[t] = fminf(fmaxf(q, 0.f), (float)(N - 1));
   }
+  // fminf / fmaxf drop a NaN; a row whose shifted atoms are not numbers gets a
+  // NaN distribution instead (as the clamp of the definition keeps it)
+  const bool nan_row = __any(nan_lane);
   float mi[kMaxAtomsPerLane];
 #pragma unroll
   for (int t = 0; t < kMaxAtomsPerLane; ++t) mi[t] = 0.f;
@@ -548,6 +554,7 @@ __device__ float project_row(const float* p, int N, int lane, float v_min, float
 #pragma unroll
   for (int t = 0; t < kMaxAtomsPerLane; ++t) {
     const int i = lane + 64 * t;
+    if (nan_row) mi[t] = __builtin_nanf("");
     if (i < N) {
       m_out[i] = mi[t];
       mz += mi[t] * (v_min + (float)i * dz);
@@ -565,16 +572,23 @@ __device__ float project_row(const float* p, int N, int lane, float v_min, float
 template <int T>
 __device__ float project_row_t(const float (&p)[T], int N, int lane, float v_min, float dz, float r, float d,
                               float gamma, float bonus, float* bl, float* pl, float (&mi)[T]) {
+  int nan_lane = 0;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int j = lane + 64 * t;
     const float zj = v_min + (float)j * dz;
     const float tz = r + gamma * (1.f - d) * (zj + bonus);
     if (j < N) {
-      bl[j] = fminf(fmaxf((tz - v_min) / dz, 0.f), (float)(N - 1));
+      const float q = (tz - v_min) / dz;
+      nan_lane |= q != q;
+      bl[j] = fminf(fmaxf(q, 0.f), (float)(N - 1));
       pl[j] = p[t];
     }
   }
+  // fminf / fmaxf drop a NaN; a row whose shifted atoms are not numbers gets a
+  // NaN distribution instead (as the clamp of the definition keeps it), so the
+  // loss and the statistics of the update report it
+  const bool nan_row = __any(nan_lane);
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   float mz = 0.f;
 #pragma unroll
@@ -599,6 +613,7 @@ __device__ float project_row_t(const float (&p)[T], int N, int lane, float v_min
     }
     float acc = 0.f;
     for (int j = lo; j < hi; ++j) acc += pl[j] * fmaxf(0.f, 1.f - fabsf(bl[j] - fi));
+    if (nan_row) acc = __builtin_nanf("");
     mi[t] = acc;
     if (i < N) mz += acc * (v_min + fi * dz);
   }

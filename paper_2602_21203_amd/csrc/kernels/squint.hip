@@ -21,7 +21,7 @@ __device__ __forceinline__ void emit(const SqDst& d, int img, int nsplit, int C,
                                      int kk, float scale) {
   if (d.mode == kSqU8) {
     const bool second = img >= nsplit;
-    const int row = (d.pos + (second ? img - nsplit : img)) % d.cap;
+    const int row = ring_row(d.pos, second ? img - nsplit : img, d.cap);
     uint8_t* base = reinterpret_cast<uint8_t*>(second ? d.out1 : d.out) + (long long)row * side * side * C;
     base[((long long)y * side + x) * C + c] = (uint8_t)mean_u8(s, kk);
     return;
@@ -39,7 +39,7 @@ __device__ __forceinline__ void emit(const SqDst& d, int img, int nsplit, int C,
 __device__ __forceinline__ void ring_fields(const SqDst& d, int i) {
   const RingRows& f = d.f;
   const int W = 2 * f.P + f.A + 2;
-  const long long row = (d.pos + i) % d.cap;
+  const long long row = ring_row(d.pos, i, d.cap);
   for (int it = threadIdx.x; it < W; it += blockDim.x) {
     if (it < f.P) f.r_proprio[row * f.P + it] = f.proprio[(long long)i * f.P + it];
     else if (it < 2 * f.P) f.r_next[row * f.P + it - f.P] = f.next_proprio[(long long)i * f.P + it - f.P];

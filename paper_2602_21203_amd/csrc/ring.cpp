@@ -120,13 +120,22 @@ int sq_ring_insert(sq_ring* r, const uint8_t* obs, const uint8_t* next_obs, cons
     return SQ_ECAPTURE;
   }
   if (n == 0) return SQ_OK;
-  const int new_pos = (int)(((long long)r->pos + n) % r->cap);
+  const int new_pos = ring_row(r->pos, n, r->cap);
   const int new_size = (int)((long long)r->size + n < r->cap ? r->size + n : r->cap);
   const RingRows f{proprio, next_proprio, action, reward, done, r->proprio, r->next_proprio, r->action, r->reward,
                    r->done, d.proprio, d.action, r->ctr, new_pos, new_size};
   SQ_TRY(launch_squint_insert(obs, next_obs, n, d.H, d.W, d.C, d.k, r->obs, r->next_obs, r->pos, r->cap, f, st));
   r->pos = new_pos;
   r->size = new_size;
+  return SQ_OK;
+}
+
+int sq_ring_row(int pos, long long i, int capacity, int* row) {
+  if (!row || capacity <= 0 || pos < 0 || pos >= capacity || i < 0) {
+    set_error("sq_ring_row: need 0 <= pos < capacity, i >= 0 and a row pointer");
+    return SQ_EINVAL;
+  }
+  *row = ring_row(pos, i, capacity);
   return SQ_OK;
 }
 

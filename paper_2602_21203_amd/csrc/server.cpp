@@ -13,6 +13,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -61,7 +62,7 @@ Tables carve_tables(char* base, int cap) {
 
 struct Slot {
   hipStream_t st = nullptr;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;   // device start / end of the slot's batch (timing)
   void* dmem = nullptr;
   char* htab = nullptr;
   char* dtab = nullptr;
@@ -70,7 +71,9 @@ struct Slot {
   float* act_stage = nullptr;
   std::vector<Req> batch;
   bool busy = false;
+  bool finished = false;   // set by the stream's host function when the batch is done
   size_t bytes = 0;
+  sq_server* srv = nullptr;
 };
 
 }  // namespace
@@ -89,10 +92,27 @@ struct sq_server {
   std::condition_variable cv, idle;
   std::thread th;
   bool stop = false;
+  bool hold = false;   // admissions paused (sq_server_hold)
   size_t firing = 0;   // completions whose callbacks are running
   int error = SQ_OK;
   char errmsg[256] = {0};
+  // counters (under mu)
+  sq_server_stats st{};
+  hipEvent_t ref = nullptr;                        // time origin of the device intervals
+  std::vector<std::pair<double, double>> spans;    // device [start, end] of every batch, seconds
 };
+
+// host function enqueued after each batch: marks the slot finished and wakes
+// the scheduler (no HIP calls here)
+static void batch_done(void* arg) {
+  Slot* sl = static_cast<Slot*>(arg);
+  sq_server* s = sl->srv;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    sl->finished = true;
+  }
+  s->cv.notify_one();
+}
 
 static int launch_batch(sq_server* s, Slot& sl) {
   const sq_dims& d = s->net.d;
@@ -112,6 +132,7 @@ static int launch_batch(sq_server* s, Slot& sl) {
   const int n = r;
   Tables t = carve_tables(sl.dtab, cap);
   hipStream_t st = sl.st;
+  SQ_TRY_HIP(hipEventRecord(sl.ev0, st));
   SQ_TRY_HIP(hipMemcpyAsync(sl.dtab, sl.htab, tables_bytes(cap), hipMemcpyHostToDevice, st));
   const int bf = s->hp.prec == SQ_BF16;
   if (d.n_conv > 0) {
@@ -127,45 +148,66 @@ static int launch_batch(sq_server* s, Slot& sl) {
                        sl.prop_stage, d.proprio, sl.w.noise, n, s->hp.log_std_min, s->hp.log_std_max, sl.act_stage,
                        nullptr, sl.w.a, st));
   SQ_TRY(scatter_rows(sl.act_stage, d.action, n, t.out, st));
-  SQ_TRY_HIP(hipEventRecord(sl.ev, st));
+  SQ_TRY_HIP(hipEventRecord(sl.ev1, st));
+  SQ_TRY_HIP(hipLaunchHostFunc(st, batch_done, &sl));
   return SQ_OK;
 }
 
+// The scheduler thread owns the slots' batches; the mutex guards the queue, the
+// slots' busy / finished flags, the memory in flight and the counters.  Launches,
+// event reads and completion callbacks run with the mutex released.
 static void scheduler(sq_server* s) {
   std::vector<Req> done;
+  std::vector<Slot*> to_launch;
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
-    // completions
-    bool any_busy = false;
-    for (Slot& sl : s->slots) {
-      if (!sl.busy) continue;
-      const hipError_t q = hipEventQuery(sl.ev);
-      if (q == hipSuccess) {
-        for (const Req& r : sl.batch) done.push_back(r);
-        sl.batch.clear();
-        sl.busy = false;
-        s->in_flight -= sl.bytes;
-        sl.bytes = 0;
-      } else if (q != hipErrorNotReady) {
-        s->error = SQ_EDEVICE;
-        snprintf(s->errmsg, sizeof(s->errmsg), "act batch failed: %s", hipGetErrorString(q));
-        sl.busy = false;
-        s->in_flight -= sl.bytes;
-        sl.bytes = 0;
-        sl.batch.clear();
-      } else {
-        any_busy = true;
+    // completions: batches whose host function has run
+    std::vector<Slot*> fin;
+    for (Slot& sl : s->slots)
+      if (sl.busy && sl.finished) fin.push_back(&sl);
+    if (!fin.empty()) {
+      lk.unlock();
+      std::vector<std::pair<double, double>> spans;
+      int err = SQ_OK;
+      char msg[200] = {0};
+      for (Slot* sl : fin) {
+        float t0 = 0.f, t1 = 0.f;
+        const hipError_t e0 = hipEventElapsedTime(&t0, s->ref, sl->ev0);
+        const hipError_t e1 = hipEventElapsedTime(&t1, s->ref, sl->ev1);
+        if (e0 != hipSuccess || e1 != hipSuccess) {
+          err = SQ_EDEVICE;
+          snprintf(msg, sizeof(msg), "act batch failed: %s", hipGetErrorString(e0 != hipSuccess ? e0 : e1));
+        } else {
+          spans.emplace_back(1e-3 * t0, 1e-3 * t1);
+        }
+        for (const Req& r : sl->batch) done.push_back(r);
+      }
+      lk.lock();
+      for (Slot* sl : fin) {
+        sl->batch.clear();
+        sl->busy = false;
+        sl->finished = false;
+        s->in_flight -= sl->bytes;
+        sl->bytes = 0;
+      }
+      s->spans.insert(s->spans.end(), spans.begin(), spans.end());
+      if (err != SQ_OK && s->error == SQ_OK) {
+        s->error = err;
+        snprintf(s->errmsg, sizeof(s->errmsg), "%s", msg);
       }
     }
     // admissions: FIFO, fuse every head request that fits
+    int busy_now = 0;
+    for (Slot& sl : s->slots) busy_now += sl.busy;
     for (Slot& sl : s->slots) {
-      if (sl.busy || s->queue.empty()) continue;
-      int rows = 0;
+      if (s->hold || sl.busy || s->queue.empty()) continue;
+      int rows = 0, nreq = 0;
       while (!s->queue.empty()) {
         const Req& q = s->queue.front();
         const size_t need = (size_t)(rows + q.n) * s->per_obs;
         if (rows + q.n > s->max_batch || s->in_flight + need > s->budget) break;
         rows += q.n;
+        ++nreq;
         sl.batch.push_back(q);
         s->queue.pop_front();
       }
@@ -173,40 +215,59 @@ static void scheduler(sq_server* s) {
       sl.bytes = (size_t)rows * s->per_obs;
       s->in_flight += sl.bytes;
       sl.busy = true;
-      any_busy = true;
-      if (launch_batch(s, sl) != SQ_OK) {
-        s->error = SQ_EDEVICE;
-        snprintf(s->errmsg, sizeof(s->errmsg), "%s", sq_last_error());
-      }
+      sl.finished = false;
+      ++busy_now;
+      s->st.batches += 1;
+      s->st.requests += nreq;
+      s->st.rows += rows;
+      if (nreq > 1) s->st.fused_batches += 1;
+      if (nreq > s->st.max_requests_per_batch) s->st.max_requests_per_batch = nreq;
+      if (busy_now > s->st.max_slots_busy) s->st.max_slots_busy = busy_now;
+      to_launch.push_back(&sl);
     }
-    if (!done.empty()) {
+    if (!to_launch.empty() || !done.empty()) {
       std::vector<Req> fire;
       fire.swap(done);
+      std::vector<Slot*> launch;
+      launch.swap(to_launch);
       s->firing = fire.size();
       lk.unlock();
+      int err = SQ_OK;
+      char msg[256] = {0};
+      for (Slot* sl : launch)
+        if (launch_batch(s, *sl) != SQ_OK) {
+          err = SQ_EDEVICE;
+          snprintf(msg, sizeof(msg), "%s", sq_last_error());
+          (void)hipStreamSynchronize(sl->st);
+          batch_done(sl);   // nothing more will complete on this slot's stream
+        }
       const double t = now_s();
       for (const Req& r : fire)
         if (r.cb) r.cb(r.id, t, r.user);
       lk.lock();
       s->firing = 0;
+      if (err != SQ_OK && s->error == SQ_OK) {
+        s->error = err;
+        snprintf(s->errmsg, sizeof(s->errmsg), "%s", msg);
+      }
       continue;
     }
+    bool any_busy = false;
+    for (const Slot& sl : s->slots) any_busy |= sl.busy;
     if (!any_busy && s->queue.empty()) {
       s->idle.notify_all();
       if (s->stop) break;
-      s->cv.wait(lk);
-      continue;
     }
-    // a batch is on the device: poll its completion shortly
-    lk.unlock();
-    std::this_thread::sleep_for(std::chrono::microseconds(20));
-    lk.lock();
+    // sleep until a submit, a completion, a hold change or the stop
+    s->cv.wait(lk);
   }
 }
 
 static void free_server(sq_server* s) {
+  if (s->ref) (void)hipEventDestroy(s->ref);
   for (Slot& sl : s->slots) {
-    if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sl.ev0) (void)hipEventDestroy(sl.ev0);
+    if (sl.ev1) (void)hipEventDestroy(sl.ev1);
     if (sl.st) (void)hipStreamDestroy(sl.st);
     if (sl.dmem) (void)hipFree(sl.dmem);
     if (sl.htab) (void)hipHostFree(sl.htab);
@@ -242,7 +303,7 @@ int sq_server_create(sq_agent* agent, size_t mem_budget, int max_batch_obs, int 
     if (hipMalloc(&sl.dmem, bytes) != hipSuccess ||
         hipHostMalloc((void**)&sl.htab, tables_bytes(max_batch_obs), hipHostMallocDefault) != hipSuccess ||
         hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreate(&sl.ev0) != hipSuccess || hipEventCreate(&sl.ev1) != hipSuccess) {
       free_server(s);
       set_error("allocation of %d serving slots of %d observations failed", n_slots, max_batch_obs);
       return SQ_ENOMEM;
@@ -252,6 +313,13 @@ int sq_server_create(sq_agent* agent, size_t mem_budget, int max_batch_obs, int 
     sl.prop_stage = c.take<float>((size_t)max_batch_obs * (d.proprio > 0 ? d.proprio : 1));
     sl.act_stage = c.take<float>((size_t)max_batch_obs * d.action);
     sl.dtab = c.take<char>(tables_bytes(max_batch_obs));
+  }
+  for (Slot& sl : s->slots) sl.srv = s;
+  if (hipEventCreate(&s->ref) != hipSuccess || hipEventRecord(s->ref, s->slots[0].st) != hipSuccess ||
+      hipEventSynchronize(s->ref) != hipSuccess) {
+    free_server(s);
+    set_error("creating the server's reference event failed");
+    return SQ_EDEVICE;
   }
   s->th = std::thread(scheduler, s);
   *out = s;
@@ -295,6 +363,48 @@ int sq_server_drain(sq_server* s) {
     set_error("%s", s->errmsg);
     return s->error;
   }
+  return SQ_OK;
+}
+
+int sq_server_hold(sq_server* s, int hold) {
+  if (!s) { set_error("server is NULL"); return SQ_EINVAL; }
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->hold = hold != 0;
+  }
+  s->cv.notify_one();
+  return SQ_OK;
+}
+
+int sq_server_get_stats(sq_server* s, sq_server_stats* out) {
+  if (!s || !out) { set_error("NULL argument to sq_server_get_stats"); return SQ_EINVAL; }
+  std::vector<std::pair<double, double>> spans;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->st;
+    spans = s->spans;
+  }
+  // union of the batches' device intervals, and whether any two overlapped
+  std::sort(spans.begin(), spans.end());
+  double busy = 0.0, cur0 = 0.0, cur1 = -1.0, first = 0.0, last = 0.0;
+  long long overlaps = 0;
+  for (size_t i = 0; i < spans.size(); ++i) {
+    const auto& sp = spans[i];
+    if (i == 0) first = sp.first;
+    if (sp.second > last) last = sp.second;
+    if (sp.first < cur1) {
+      ++overlaps;
+      if (sp.second > cur1) cur1 = sp.second;
+    } else {
+      if (cur1 > cur0) busy += cur1 - cur0;
+      cur0 = sp.first;
+      cur1 = sp.second;
+    }
+  }
+  if (cur1 > cur0) busy += cur1 - cur0;
+  out->device_busy_s = busy;
+  out->device_span_s = spans.empty() ? 0.0 : last - first;
+  out->overlapped_batches = overlaps;
   return SQ_OK;
 }
 

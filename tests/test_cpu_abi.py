@@ -86,3 +86,17 @@ def test_missing_library_fails_loudly():
     env = dict(os.environ, SQ_LIB_PATH="/nonexistent/libsquint.so")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True)
     assert r.returncode != 0 and "missing" in r.stderr
+
+
+def test_ring_rows_in_64_bit():
+    """The ring row (pos + i) mod capacity, computed by the same function the
+    insert kernel uses, where pos + i passes 2^31 (capacity near 2^31 - 1)."""
+    from paper_2602_21203_amd import _lib
+    cap = 2 ** 31 - 1
+    for pos, i in ((cap - 10, 20), (cap - 1, 2 ** 31 - 1), (2 ** 30, 2 ** 31 - 1), (5, 0), (0, cap)):
+        row = ctypes.c_int()
+        assert _lib.LIB.sq_ring_row(pos, i, cap, ctypes.byref(row)) == _lib.SQ_OK
+        assert row.value == (pos + i) % cap, (pos, i, row.value)
+    row = ctypes.c_int()
+    assert _lib.LIB.sq_ring_row(cap, 1, cap, ctypes.byref(row)) == _lib.SQ_EINVAL
+    assert _lib.LIB.sq_ring_row(0, -1, cap, ctypes.byref(row)) == _lib.SQ_EINVAL

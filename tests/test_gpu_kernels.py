@@ -190,4 +190,9 @@ def test_adam_step_vs_oracle_with_ema_and_shadow():
     sac.ema(T, P[1000:], 0.995)
     assert np.abs(tgt.cpu().numpy() - T).max() < 1e-6
     assert torch.equal(shadow.view(torch.bfloat16).cpu(), p.cpu().to(torch.bfloat16))
-    assert int(step.item()) == 4
+    assert int(step.item()) == 5            # advanced on the device after the step
+    # a second step reads t = 6 from the advanced counter
+    api.adam_step(p, dev(g), m, v, hp, step)
+    sac.adam(P, g.astype(np.float64), M, V, 6, ohp)
+    assert np.abs(p.cpu().numpy() - P).max() < 2e-6
+    assert int(step.item()) == 6

@@ -33,13 +33,26 @@ def test_alone_equals_mixed_bitwise(setup):
     # alone: plain act() one request at a time
     alone = [agent.act(f, p, sample=s, request_id=rid) for f, p, rid, s in reqs]
     torch.cuda.synchronize()
-    srv = api.Server(agent, mem_budget=8 << 30, max_batch_obs=4096, n_slots=3)
+    # admissions held while the ten requests queue, then released: with at most
+    # 1100 rows per launch the scheduler fuses them into three launches, one per
+    # slot ([1, 7, 300, 2], [1000, 64, 5], [900, 33, 17]), that run at once
+    srv = api.Server(agent, mem_budget=8 << 30, max_batch_obs=1100, n_slots=3)
+    srv.hold(True)
     outs = [srv.submit(f, p, rid, sample=s) for f, p, rid, s in reqs]
+    srv.hold(False)
     srv.drain()
     torch.cuda.synchronize()
     for a, b in zip(alone, outs):
         assert torch.equal(a, b)
     assert sorted(srv.done) == [r[2] for r in reqs]
+    st = srv.stats()
+    print("  server stats:", st)
+    assert st["batches"] == 3 and st["fused_batches"] == 3 and st["max_requests_per_batch"] == 4
+    assert st["requests"] == 10 and st["rows"] == sum(sizes)
+    assert st["max_slots_busy"] == 3
+    # the three batches' device intervals overlap (timing events on the slot streams)
+    assert st["overlapped_batches"] >= 1
+    assert 0 < st["device_busy_s"] < 3 * st["device_span_s"]
     srv.close()
 
 

@@ -194,3 +194,20 @@ def test_critic_loss_finite_differences_tiny():
     fd = np.array(fd)
     g = out["g_enc_critic"][coords]
     assert np.linalg.norm(fd - g) <= 1e-6 * np.linalg.norm(g) + 1e-9
+
+
+def test_nan_reward_makes_the_update_non_finite():
+    """A NaN reward at a sampled row: the projection's clamp keeps the NaN, so the
+    row's target distribution, the critic loss and the mean target are NaN and
+    the statistics' non-finite flag is set."""
+    d = layout.dims(**layout.TINY)
+    rep = np_replay(d, 256)
+    hp = sac.hparams(d)
+    rows = philox.sample_indices(hp.seed, 0, 256, 16)
+    rep["reward"] = rep["reward"].copy()
+    rep["reward"][rows[0]] = np.nan
+    st = sac.new_state(d, synthetic.init_params(table(d), seed=1))
+    o = sac.sac_update(st, rep, d, hp, 16)
+    assert np.isnan(o["m"][0]).all() and np.isfinite(o["m"][1:]).all()
+    assert o["stats"][7] == 1.0 and np.isnan(o["stats"][0]) and np.isnan(o["stats"][6])
+    assert np.isfinite(o["stats"][[2, 3, 4, 5]]).all()
