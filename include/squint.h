@@ -150,6 +150,19 @@ SQ_API int squint_downsample(const sq_dims* dims, const uint8_t* frames, const i
  * keeps the activations for encoder_bwd and must not change in between. */
 SQ_API int encoder_fwd(const sq_dims* dims, sq_prec prec, const float* enc_params, const float* x, int n,
                 float* feat, void* ws, sq_stream_t stream);
+/* encoder_fwd for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same kernels and the same feat bits, with the scratch
+ * (rearranged weights, inner activations) in a fixed 16 MiB array that each
+ * device holds from the library's first use until the process ends.  Keeps no
+ * activations for encoder_bwd.  n above sq_encoder_noalloc_max_images returns
+ * SQ_ENOMEM with nothing enqueued.  Every call on a device shares that device's
+ * array: calls that overlap on one device (other streams or threads) race and
+ * must be ordered by the caller.  Allocates nothing. */
+SQ_API int encoder_fwd_noalloc(const sq_dims* dims, sq_prec prec, const float* enc_params, const float* x, int n,
+                               float* feat, sq_stream_t stream);
+/* Largest n encoder_fwd_noalloc accepts for these dims.  n: [host]. */
+SQ_API int sq_encoder_noalloc_max_images(const sq_dims* dims, int* n);
 /* Gradient of the encoder parameters for upstream dfeat [n, flat] (same n as the
  * forward).  denc_params: encoder block of a flat gradient vector.  The image
  * receives no gradient. */

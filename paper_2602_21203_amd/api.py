@@ -63,6 +63,25 @@ def encoder_fwd(cfg, prec, enc_params, x, ws=None, stream=None):
     return feat, ws
 
 
+def encoder_fwd_noalloc(cfg, prec, enc_params, x, feat=None, stream=None):
+    """encoder_fwd with the library's fixed scratch instead of a workspace."""
+    n = x.shape[0]
+    s = _side(cfg)
+    _req(x, torch.float32, (n, cfg["C"], s, s), "x")
+    _req(enc_params, torch.float32, name="enc_params")
+    if feat is None:
+        feat = torch.empty((n, L.feat_width(cfg)), dtype=torch.float32, device=x.device)
+    _req(feat, torch.float32, (n, L.feat_width(cfg)), "feat")
+    check(L.LIB.encoder_fwd_noalloc(_dims(cfg), prec, ptr(enc_params), ptr(x), n, ptr(feat), stream_handle(stream)))
+    return feat
+
+
+def encoder_noalloc_max_images(cfg):
+    n = ctypes.c_int()
+    check(L.LIB.sq_encoder_noalloc_max_images(_dims(cfg), ctypes.byref(n)))
+    return n.value
+
+
 def encoder_bwd(cfg, prec, enc_params, ws, dfeat, n_enc_params, stream=None):
     n = dfeat.shape[0]
     _req(dfeat, torch.float32, (n, L.feat_width(cfg)), "dfeat")
