@@ -82,15 +82,24 @@ struct AdamArgs {
 };
 
 // conv weight i (updated to v) in the fused encoder's prepared copy
+// (bfloat16 form: packed bfloat16 elements at the same element offsets)
 __device__ __forceinline__ void enc_prep_put(const EncPrepMap& e, long long i, float v) {
-  const float w = e.bf16 ? bf16_round(v) : v;
+  uint16_t* wb = reinterpret_cast<uint16_t*>(e.wp);
+  const uint16_t vb = bf16_bits(v);
   for (int l = 0; l < e.n; ++l) {
     const long long o = i - e.W[l];
     if (o < 0 || o >= (long long)e.F * e.cin[l] * 9) continue;
     const int oi = (int)o, k = e.cin[l] * 9;
     const int f = oi / k, r = oi - f * k, c = r / 9, tap = r - 9 * c;
-    e.wp[e.fb[l] + (long long)(f * 9 + tap) * e.cp[l] + c] = w;
-    if (l > 0) e.wp[e.bb[l] + (long long)(tap * e.cin[l] + c) * e.F + f] = w;
+    const long long fo = e.fb[l] + (long long)(f * 9 + tap) * e.cp[l] + c;
+    const long long bo = e.bb[l] + (long long)(tap * e.cin[l] + c) * e.F + f;
+    if (e.bf16) {
+      wb[fo] = vb;
+      if (l > 0) wb[bo] = vb;
+    } else {
+      e.wp[fo] = v;
+      if (l > 0) e.wp[bo] = v;
+    }
   }
 }
 

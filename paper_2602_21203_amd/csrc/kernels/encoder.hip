@@ -9,15 +9,19 @@
 // forward and [tap][c][f] for the input gradient (bfloat16-rounded in the
 // bfloat16 form).
 //
-// Contractions run on v_mfma_f32_16x16x4_f32.  In a chunk of 16 consecutive
-// channels of one tap, lane (li, lq) loads channels 4*lq .. 4*lq + 3 of its row
-// and of its column with one 16-byte load each and feeds them to four
+// FP32 form: contractions run on v_mfma_f32_16x16x4_f32.  In a chunk of 16
+// consecutive channels of one tap, lane (li, lq) loads channels 4*lq .. 4*lq + 3
+// of its row and of its column with one 16-byte load each and feeds them to four
 // consecutive MFMA steps, so the gather costs one LDS read and one global read
 // per four steps, at addresses fixed at compile time up to a per-lane base.
-// In the bfloat16 form every operand is rounded to a bfloat16 value once, when
-// it is written to LDS (inputs, activations, gradients after their bias sums)
-// or prepared (weights); products of bfloat16 values are exact in FP32, so the
-// FP32 matrix cores then give the bfloat16 contraction with FP32 accumulation.
+//
+// bfloat16 form (the k_*_b kernels below): activations, inputs and gradients
+// are held in LDS as bfloat16 (half the footprint, so more workgroups share a
+// CU) and contracted with v_mfma_f32_16x16x32_bf16, FP32 accumulation.  Every
+// operand is rounded to bfloat16 once, when it is written to LDS or prepared;
+// bias gradients are summed from the unrounded FP32 values.  A 32-wide k chunk
+// is one tap of 32 channels, or two taps of 16 (padded) channels, a tenth
+// phantom tap contributing zero.
 //
 // Forward: a workgroup owns G images.  Layer outputs go to LDS (next layer's
 // operand) and to HBM (FP32; [n][pixel][F] for the inner layers, NCHW for the
@@ -98,7 +102,8 @@ __global__ __launch_bounds__(256) void k_enc_prep(EncW w, float* __restrict__ wp
       const int tap = o / (F * F), r = o - tap * F * F, c = r / F, f = r - c * F;
       v = w.W[l][(f * F + c) * 9 + tap];
     }
-    wp[e] = bf16 ? bf16_round(v) : v;
+    if (bf16) reinterpret_cast<uint16_t*>(wp)[e] = bf16_bits(v);   // packed bfloat16 elements
+    else wp[e] = v;
   }
 }
 
@@ -408,9 +413,502 @@ __global__ __launch_bounds__(256) void k_enc_reduce(const float* __restrict__ pa
   }
 }
 
+// ---------------------------------------------------------------- bfloat16 form
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// layer geometry with bfloat16 storage: PS elements per LDS pixel (16-byte aligned),
+// TPM taps per 32-wide k chunk, NM chunks per 3x3 contraction
+template <int C, int F, int l> struct LB {
+  static constexpr int CIN = l == 0 ? C : F;
+  static constexpr int CP = r16(CIN);
+  static constexpr int PS = CP + 8;
+  static constexpr int HI = enc_in(l), HO = enc_out(l), S = l == 0 ? 2 : 1;
+  static constexpr int P = HO * HO;
+  static constexpr int K = CIN * 9;
+  static constexpr int DS = HO + 4;
+  static constexpr int TPM = 32 / CP;
+  static constexpr int NM = (9 + TPM - 1) / TPM;
+  static_assert(CP == 16 || CP == 32, "16 or 32 (padded) channels per tap");
+};
+
+__device__ __forceinline__ v4f mma_b(const bf16x8& a, const bf16x8& b, v4f acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
+// Workgroup barrier for LDS hand-offs only: the thread's LDS operations complete
+// before it, while its global loads stay in flight (no global memory is written
+// and read back by other threads inside these kernels).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// the chunk's tap and channel offset for lane group lq (tap 9 is the phantom tap
+// of an odd count: its weight operand is zero, its input read is clamped to tap 8)
+template <int TPM>
+__device__ __forceinline__ void chunk_tap(int mi, int lq, int& tap, int& off) {
+  if constexpr (TPM == 1) { tap = mi; off = 8 * lq; }
+  else { tap = 2 * mi + (lq >> 1); off = 8 * (lq & 1); }
+}
+
+// The weight operand of one column tile (16 filters from c0) of forward layer l,
+// as this lane's MFMA fragments of every k chunk.  When the workgroup's wave count
+// is a multiple of the layer's column tiles, a wave only ever meets one column
+// tile, so all of a wave's weight fragments can be requested up front.
+template <int C, int F, int l>
+struct WFrag {
+  using Y = LB<C, F, l>;
+  bf16x8 b[Y::NM];
+  float bias;
+  __device__ __forceinline__ void load(const __bf16* __restrict__ wf, const float* __restrict__ bs, int c0) {
+    const int lane = threadIdx.x & 63, li = lane & 15, lq = lane >> 4;
+    const __bf16* bp = wf + (c0 + li) * 9 * Y::CP;
+#pragma unroll
+    for (int mi = 0; mi < Y::NM; ++mi) {
+      int tap, off;
+      chunk_tap<Y::TPM>(mi, lq, tap, off);
+      const int tc = tap < 9 ? tap : 8;
+      b[mi] = *reinterpret_cast<const bf16x8*>(__builtin_assume_aligned(bp + tc * Y::CP + off, 16));
+      if (tap > 8) b[mi] = bf16x8{};
+    }
+    bias = bs[c0 + li];
+  }
+};
+
+// forward layer l of G images: in [G][HI][HI][PS] (bfloat16, LDS) -> post-ReLU
+// out_lds [G][HO][HO][F + 8] (bfloat16) and out_g (FP32, as the FP32 form).
+// w: the wave's weight fragments when PRE (its one column tile), else read per tile.
+template <int G, int C, int F, int l, bool TO_LDS, bool LAST, int NT, bool PRE>
+__device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16* __restrict__ wf,
+                                 const float* __restrict__ bias, float* __restrict__ out_g, int gn,
+                                 const WFrag<C, F, l>& w) {
+  using Y = LB<C, F, l>;
+  constexpr int ROWS = G * Y::P, RT = (ROWS + 15) / 16, CT = F / 16, NW = NT / 64;
+  constexpr int PSO = F + 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  for (int t = wave; t < RT * CT; t += NW) {
+    const int rt = t / CT, ct = t - rt * CT;
+    const int r0 = rt * 16, c0 = ct * 16;
+    const int row = min(r0 + li, ROWS - 1);
+    const int g = row / Y::P, p = row - g * Y::P, oy = p / Y::HO, ox = p - oy * Y::HO;
+    const __bf16* ap = in + ((g * Y::HI + oy * Y::S) * Y::HI + ox * Y::S) * Y::PS;
+    WFrag<C, F, l> wt;
+    if constexpr (!PRE) wt.load(wf, bias, c0);
+    const WFrag<C, F, l>& ww = PRE ? w : wt;
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mi = 0; mi < Y::NM; ++mi) {
+      int tap, off;
+      chunk_tap<Y::TPM>(mi, lq, tap, off);
+      const int tc = tap < 9 ? tap : 8, ky = tc / 3, kx = tc - 3 * ky;
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(ap + (ky * Y::HI + kx) * Y::PS + off);
+      acc = mma_b(a, ww.b[mi], acc);
+    }
+    const int f = c0 + li;
+    const float bv = ww.bias;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + 4 * lq + q;
+      if (r < ROWS) {
+        const int gg = r / Y::P, pp = r - gg * Y::P;
+        const float v = fmaxf(acc[q] + bv, 0.f);
+        if constexpr (TO_LDS) out_lds[(gg * Y::P + pp) * PSO + f] = (__bf16)v;
+        if (gg < gn) {
+          if constexpr (LAST) out_g[((long long)gg * F + f) * Y::P + pp] = v;
+          else out_g[((long long)gg * Y::P + pp) * F + f] = v;
+        }
+      }
+    }
+  }
+}
+
+template <int G, int C, int F, int NC, int NT>
+__global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ x, int n, const __bf16* __restrict__ wp,
+                                                      const float* __restrict__ b0, const float* __restrict__ b1,
+                                                      const float* __restrict__ b2, float* __restrict__ h0,
+                                                      float* __restrict__ h1, float* __restrict__ h2) {
+  using L0 = LB<C, F, 0>;
+  using L1 = LB<C, F, 1>;
+  using E = EncPrep<C, F, NC>;
+  constexpr int X = G * 256 * L0::PS, A0 = G * L0::P * (F + 8), A1 = NC > 2 ? G * L1::P * (F + 8) : 8;
+  constexpr int NW = NT / 64, CT = F / 16;
+  constexpr bool PRE = NW % CT == 0;   // each wave meets one column tile per layer
+  __shared__ __attribute__((aligned(16))) __bf16 lx[X];
+  __shared__ __attribute__((aligned(16))) __bf16 la0[A0];
+  __shared__ __attribute__((aligned(16))) __bf16 la1[A1];
+  const int img0 = blockIdx.x * G;
+  const int gn = n - img0 < G ? n - img0 : G;
+  // the images, then every layer's weight fragments of this wave, all requested up front
+  constexpr int RX = (G * C * 256 + NT - 1) / NT;
+  float xv[RX];
+#pragma unroll
+  for (int i = 0; i < RX; ++i) {
+    const int e = (int)threadIdx.x + NT * i;
+    xv[i] = e < gn * C * 256 ? x[(long long)img0 * C * 256 + e] : 0.f;
+  }
+  const int c0w = ((threadIdx.x >> 6) % CT) * 16;
+  WFrag<C, F, 0> w0;
+  WFrag<C, F, 1> w1;
+  WFrag<C, F, (NC > 2 ? 2 : 1)> w2;
+  if constexpr (PRE) {
+    w0.load(wp + E::F0, b0, c0w);
+    w1.load(wp + E::F1, b1, c0w);
+    if constexpr (NC > 2) w2.load(wp + E::F2, b2, c0w);
+  }
+  // images NCHW -> [g][pixel][channel] bfloat16; absent images and padding channels zero
+#pragma unroll
+  for (int i = 0; i < RX; ++i) {
+    const int e = (int)threadIdx.x + NT * i;
+    if (e < G * C * 256) {
+      const int g = e / (C * 256), r = e - g * C * 256, c = r >> 8, pix = r & 255;
+      lx[(g * 256 + pix) * L0::PS + c] = (__bf16)xv[i];
+    }
+  }
+  for (int e = threadIdx.x; e < G * 256 * (L0::CP - C); e += NT) {
+    const int gp = e / (L0::CP - C), c = C + e - gp * (L0::CP - C);
+    lx[gp * L0::PS + c] = (__bf16)0.f;
+  }
+  lds_barrier();
+  conv_fwd_layer_b<G, C, F, 0, true, false, NT, PRE>(lx, la0, wp + E::F0, b0, h0 + (long long)img0 * F * L0::P, gn,
+                                                     w0);
+  lds_barrier();
+  if constexpr (NC > 2) {
+    conv_fwd_layer_b<G, C, F, 1, true, false, NT, PRE>(la0, la1, wp + E::F1, b1, h1 + (long long)img0 * F * L1::P,
+                                                       gn, w1);
+    lds_barrier();
+    conv_fwd_layer_b<G, C, F, 2, false, true, NT, PRE>(la1, nullptr, wp + E::F2, b2,
+                                                       h2 + (long long)img0 * F * LB<C, F, 2>::P, gn, w2);
+  } else {
+    conv_fwd_layer_b<G, C, F, 1, false, true, NT, PRE>(la0, nullptr, wp + E::F1, b1,
+                                                       h1 + (long long)img0 * F * L1::P, gn, w1);
+  }
+}
+
+// Weight gradient of layer l from D (bfloat16 [G][DS][DS][F + 8], zero border of
+// 2) and the layer's input (bfloat16 [G][HI][HI][PS]): rows f, columns kc = tap *
+// CIN + c, contraction over the images' output pixels in 32-pixel chunks; each
+// lane gathers its 8 pixels of a chunk through the position table (pixel ->
+// offset in D, offset of its input patch origin), filled beforehand.
+#ifndef SQ_ENC_QTAB
+#define SQ_ENC_QTAB 1
+#endif
+#ifndef SQ_ENC_PREFETCH
+#define SQ_ENC_PREFETCH 1
+#endif
+template <int G, int C, int F, int l, int NT>
+__device__ __forceinline__ void fill_qtab(int2* qtab) {
+  using Y = LB<C, F, l>;
+  constexpr int PSF = F + 8;
+  constexpr int NPOS = G * Y::P, NQ = (NPOS + 31) / 32 * 32;
+  for (int q = threadIdx.x; q < NQ; q += NT) {
+    int2 e = make_int2(0, 0);   // pad entries: a zero border pixel of D, any finite input
+    if (q < NPOS) {
+      const int g = q / Y::P, p = q - g * Y::P, oy = p / Y::HO, ox = p - oy * Y::HO;
+      e.x = ((g * Y::DS + oy + 2) * Y::DS + ox + 2) * PSF;
+      e.y = ((g * Y::HI + oy * Y::S) * Y::HI + ox * Y::S) * Y::PS;
+    }
+    qtab[q] = e;
+  }
+}
+
+template <int G, int C, int F, int l>
+struct WTiles {
+  using Y = LB<C, F, l>;
+  static constexpr int RT = F / 16, CT = (Y::K + 15) / 16, N = RT * CT;
+};
+
+template <int G, int C, int F, int l>
+__device__ __forceinline__ void bwd_w_tile(int t, const __bf16* D, const __bf16* in, const int2* qtab,
+                                           float* __restrict__ partW) {
+  using Y = LB<C, F, l>;
+  using W = WTiles<G, C, F, l>;
+  constexpr int PSF = F + 8;
+  constexpr int NPOS = G * Y::P, NQ = (NPOS + 31) / 32 * 32;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int rt = t / W::CT, ct = t - rt * W::CT;
+  const int f0 = rt * 16, k0 = ct * 16;
+  const int kc = min(k0 + li, Y::K - 1);
+  const int tap = kc / Y::CIN, c = kc - tap * Y::CIN, ky = tap / 3, kx = tap - 3 * ky;
+  const __bf16* ap = D + f0 + li;
+  const __bf16* bp = in + (ky * Y::HI + kx) * Y::PS + c;
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int s = 0; s < NQ / 32; ++s) {
+    bf16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      // output pixel q: its place in D and its input patch origin (pad pixels
+      // read a zero border pixel of D against an arbitrary finite input)
+      const int q = 32 * s + 8 * lq + e;
+      int ox_d, ox_i;
+      if constexpr (SQ_ENC_QTAB) {
+        const int2 o = qtab[q];
+        ox_d = o.x;
+        ox_i = o.y;
+      } else {
+        const int qq = q < NPOS ? q : 0;
+        const int g = qq / Y::P, p = qq - g * Y::P, oy = p / Y::HO, ox = p - oy * Y::HO;
+        ox_d = q < NPOS ? ((g * Y::DS + oy + 2) * Y::DS + ox + 2) * PSF : 0;
+        ox_i = ((g * Y::HI + oy * Y::S) * Y::HI + ox * Y::S) * Y::PS;
+      }
+      a[e] = ap[ox_d];
+      b[e] = bp[ox_i];
+    }
+    acc = mma_b(a, b, acc);
+  }
+  const int kk = k0 + li;
+  if (kk < Y::K) {
+    const int tp = kk / Y::CIN, cc = kk - tp * Y::CIN;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) partW[(f0 + 4 * lq + q) * Y::K + cc * 9 + tp] = acc[q];
+  }
+}
+
+// Input gradient of layer l >= 1 from D_l (bfloat16): E[g][iy][ix][c] = sum over
+// taps and f of D_l[g][iy - ky][ix - kx][f] W[f][c][ky][kx], masked by the layer's
+// input (hin, FP32 [img][pixel][F]) > 0, into the interior of Dn (bfloat16,
+// zero-bordered [G][HI + 4][HI + 4][F + 8]).  The masked FP32 values of each
+// 16-row tile are also summed per channel into bpart[tile][c] (the bias gradient
+// of layer l - 1, from unrounded values: lanes' rows in order, then the four
+// lane groups as (0 + 1) + (2 + 3)).
+template <int G, int C, int F, int l>
+struct XTiles {
+  using Y = LB<C, F, l>;
+  static constexpr int ROWS = G * Y::HI * Y::HI, RT = (ROWS + 15) / 16, CT = F / 16, N = RT * CT;
+};
+
+template <int G, int C, int F, int l>
+__device__ __forceinline__ void bwd_x_tile(int t, const __bf16* D, const __bf16* __restrict__ wb,
+                                           const float* __restrict__ hin, __bf16* Dn, float* bpart, int gn) {
+  using Y = LB<C, F, l>;
+  using X = XTiles<G, C, F, l>;
+  static_assert(l >= 1, "input gradients are needed above the first layer only");
+  constexpr int PSF = F + 8, DSN = Y::HI + 4;
+  constexpr int TPM = 32 / F, NM = (9 + TPM - 1) / TPM;
+  constexpr int ROWS = X::ROWS;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int rt = t / X::CT, ct = t - rt * X::CT;
+  const int r0 = rt * 16, c0 = ct * 16;
+  const int row = min(r0 + li, ROWS - 1);
+  const int g = row / (Y::HI * Y::HI), pq = row - g * Y::HI * Y::HI, iy = pq / Y::HI, ix = pq - iy * Y::HI;
+  const __bf16* ap = D + ((g * Y::DS + iy + 2) * Y::DS + ix + 2) * PSF;
+  const __bf16* bp = wb + (c0 + li) * F;
+  const int c = c0 + li;
+  // the ReLU masks of this lane's four rows, requested before the contraction
+  float hm[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = min(r0 + 4 * lq + q, ROWS - 1), gg = r / (Y::HI * Y::HI), pp = r - gg * Y::HI * Y::HI;
+    hm[q] = gg < gn ? hin[((long long)gg * Y::HI * Y::HI + pp) * F + c] : 0.f;
+  }
+  v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int mi = 0; mi < NM; ++mi) {
+    int tap, off;
+    chunk_tap<TPM>(mi, lq, tap, off);
+    const int tc = tap < 9 ? tap : 8, ky = tc / 3, kx = tc - 3 * ky;
+    const bf16x8 a = *reinterpret_cast<const bf16x8*>(ap - (ky * Y::DS + kx) * PSF + off);
+    bf16x8 b = *reinterpret_cast<const bf16x8*>(__builtin_assume_aligned(bp + tc * F * F + off, 16));
+    if (tap > 8) b = bf16x8{};
+    acc = mma_b(a, b, acc);
+  }
+  float sum = 0.f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = r0 + 4 * lq + q;
+    if (r < ROWS) {
+      const int gg = r / (Y::HI * Y::HI), pp = r - gg * Y::HI * Y::HI, yy = pp / Y::HI, xx = pp - yy * Y::HI;
+      const float v = hm[q] > 0.f ? acc[q] : 0.f;
+      Dn[((gg * DSN + yy + 2) * DSN + xx + 2) * PSF + c] = (__bf16)v;
+      sum += v;
+    }
+  }
+  sum += __shfl_xor(sum, 16);
+  sum += __shfl_xor(sum, 32);
+  if (lq == 0) bpart[rt * F + c] = sum;
+}
+
+// Both products of a layer l >= 1 share one pass over the waves (they read the
+// same D_l and write different buffers): input-gradient tiles first (the longer
+// ones), then weight-gradient tiles.  The position table must be filled.
+template <int G, int C, int F, int l, int NT>
+__device__ __forceinline__ void bwd_layer_b(const __bf16* D, const __bf16* in, const int2* qtab,
+                                            float* __restrict__ partW, const __bf16* __restrict__ wb,
+                                            const float* __restrict__ hin, __bf16* Dn, float* bpart, int gn) {
+  using X = XTiles<G, C, F, l>;
+  using W = WTiles<G, C, F, l>;
+  const int wave = threadIdx.x >> 6;
+  for (int t = wave; t < X::N + W::N; t += NT / 64) {
+    if (t < X::N) bwd_x_tile<G, C, F, l>(t, D, wb, hin, Dn, bpart, gn);
+    else bwd_w_tile<G, C, F, l>(t - X::N, D, in, qtab, partW);
+  }
+}
+
+// every element e < N (stride NT) of a staging load, issued up front into registers
+template <int N, int NT>
+struct Prefetch {
+  static constexpr int R = (N + NT - 1) / NT;
+  float v[R > 0 ? R : 1];
+  __device__ __forceinline__ void load(const float* __restrict__ src, int valid) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int e = (int)threadIdx.x + NT * i;
+      v[i] = e < valid ? src[e] : 0.f;
+    }
+  }
+};
+
+template <int G, int C, int F, int NC, int NT>
+__global__ __launch_bounds__(NT) void k_encoder_bwd_b(const float* __restrict__ x, int n,
+                                                      const float* __restrict__ dfeat, const __bf16* __restrict__ wp,
+                                                      const float* __restrict__ h0, const float* __restrict__ h1,
+                                                      const float* __restrict__ h2, EncOffs off, long long enc_total,
+                                                      float* __restrict__ part) {
+  using L0 = LB<C, F, 0>;
+  using L1 = LB<C, F, 1>;
+  using L2 = LB<C, F, (NC > 2 ? 2 : 1)>;
+  using LL = LB<C, F, NC - 1>;
+  using E = EncPrep<C, F, NC>;
+  constexpr int PSF = F + 8;
+  constexpr int SZ0 = G * L0::DS * L0::DS * PSF;                                  // D_0
+  constexpr int SZ1 = G * L1::DS * L1::DS * PSF;                                  // D_1
+  constexpr int SZ2 = NC > 2 ? G * L2::DS * L2::DS * PSF : 8;                     // D_2
+  constexpr int R0 = SZ0 > SZ2 ? SZ0 : SZ2;   // D_2 first, D_0 last (never live together)
+  constexpr int IN0 = G * 256 * L0::PS, IN1 = G * L1::HI * L1::HI * L1::PS;
+  constexpr int RIN = IN0 > IN1 ? IN0 : IN1;
+  constexpr int RTB = (G * L1::HI * L1::HI + 15) / 16;   // most 16-row tiles of an input gradient
+  constexpr int TOPN = G * F * LL::P;                    // the top layer's upstream gradient elements
+  constexpr int NH1 = NC > 2 ? G * L2::HI * L2::HI * F : 0, NH0 = G * L1::HI * L1::HI * F, NX = G * C * 256;
+  __shared__ __attribute__((aligned(16))) __bf16 r0[R0];
+  __shared__ __attribute__((aligned(16))) __bf16 r1[SZ1];
+  __shared__ __attribute__((aligned(16))) __bf16 rin[RIN];
+  __shared__ float bpart[RTB * F > TOPN ? RTB * F : TOPN];
+  __shared__ int2 qtab[(G * L0::P + 31) / 32 * 32];
+  const int img0 = blockIdx.x * G;
+  const int gn = n - img0 < G ? n - img0 : G;
+  float* pp = part + (long long)blockIdx.x * enc_total;
+
+  // every input the workgroup stages is requested now and lands in registers while
+  // the layers above it are processed: the top layer's gradient and output, then
+  // the inputs of layers 2, 1 and 0
+  const float* hl = NC > 2 ? h2 : h1;
+  Prefetch<TOPN, NT> pd, ph;
+  pd.load(dfeat + (long long)img0 * F * LL::P, gn * F * LL::P);
+  ph.load(hl + (long long)img0 * F * LL::P, gn * F * LL::P);
+  Prefetch<NH1, NT> p1;
+  Prefetch<NH0, NT> p0;
+  Prefetch<NX, NT> px;
+  auto load1 = [&] {
+    if constexpr (NC > 2) p1.load(h1 + (long long)img0 * L2::HI * L2::HI * F, gn * L2::HI * L2::HI * F);
+  };
+  auto load0 = [&] { p0.load(h0 + (long long)img0 * L1::HI * L1::HI * F, gn * L1::HI * L1::HI * F); };
+  auto loadx = [&] { px.load(x + (long long)img0 * C * 256, gn * C * 256); };
+  if constexpr (SQ_ENC_PREFETCH) {
+    load1();
+    load0();
+    loadx();
+  }
+
+  // D_{NC-1}: zero, then the upstream gradient (NCHW) masked by the output > 0 into
+  // the interior; its bias gradient sums the same FP32 values, thread f in (g, p) order
+  __bf16* Dl = NC > 2 ? r0 : r1;
+  for (int e = threadIdx.x; e < (NC > 2 ? SZ2 : SZ1); e += NT) Dl[e] = (__bf16)0.f;
+  lds_barrier();
+#pragma unroll
+  for (int i = 0; i < Prefetch<TOPN, NT>::R; ++i) {
+    const int e = (int)threadIdx.x + NT * i;
+    if (e < TOPN) {
+      const int g = e / (F * LL::P), r = e - g * F * LL::P, f = r / LL::P, p = r - f * LL::P;
+      const int oy = p / LL::HO, ox = p - oy * LL::HO;
+      const float v = ph.v[i] > 0.f ? pd.v[i] : 0.f;
+      Dl[((g * LL::DS + oy + 2) * LL::DS + ox + 2) * PSF + f] = (__bf16)v;
+      bpart[e] = v;
+    }
+  }
+  lds_barrier();
+  if (threadIdx.x < F) {
+    const int f = threadIdx.x;
+    float sb = 0.f;
+    for (int g = 0; g < G; ++g)
+      for (int p = 0; p < LL::P; ++p) sb += bpart[(g * F + f) * LL::P + p];
+    pp[off.b[NC - 1] + f] = sb;
+  }
+  if constexpr (NC > 2) {
+    // layer 2: input h1 ([img][pixel][F] -> [g][pixel][PS]); D_2 in r0, D_1 -> r1
+    if constexpr (!SQ_ENC_PREFETCH) load1();
+#pragma unroll
+    for (int i = 0; i < Prefetch<NH1, NT>::R; ++i) {
+      const int e = (int)threadIdx.x + NT * i;
+      if (e < NH1) rin[(e / F) * L2::PS + e % F] = (__bf16)p1.v[i];
+    }
+    for (int e = threadIdx.x; e < SZ1; e += NT) r1[e] = (__bf16)0.f;
+    fill_qtab<G, C, F, 2, NT>(qtab);
+    lds_barrier();
+    bwd_layer_b<G, C, F, 2, NT>(r0, rin, qtab, pp + off.W[2], wp + E::B2,
+                                h1 + (long long)img0 * L2::HI * L2::HI * F, r1, bpart, gn);
+    lds_barrier();
+    if (threadIdx.x < F) {
+      float sb = 0.f;
+      for (int t = 0; t < (G * L2::HI * L2::HI + 15) / 16; ++t) sb += bpart[t * F + threadIdx.x];
+      pp[off.b[1] + threadIdx.x] = sb;
+    }
+  }
+  // layer 1: input h0; D_1 in r1, D_0 -> r0
+  if constexpr (!SQ_ENC_PREFETCH) load0();
+#pragma unroll
+  for (int i = 0; i < Prefetch<NH0, NT>::R; ++i) {
+    const int e = (int)threadIdx.x + NT * i;
+    if (e < NH0) rin[(e / F) * L1::PS + e % F] = (__bf16)p0.v[i];
+  }
+  for (int e = threadIdx.x; e < SZ0; e += NT) r0[e] = (__bf16)0.f;
+  fill_qtab<G, C, F, 1, NT>(qtab);
+  lds_barrier();
+  bwd_layer_b<G, C, F, 1, NT>(r1, rin, qtab, pp + off.W[1], wp + E::B1, h0 + (long long)img0 * L1::HI * L1::HI * F,
+                              r0, bpart, gn);
+  lds_barrier();
+  if (threadIdx.x < F) {
+    float sb = 0.f;
+    for (int t = 0; t < (G * L1::HI * L1::HI + 15) / 16; ++t) sb += bpart[t * F + threadIdx.x];
+    pp[off.b[0] + threadIdx.x] = sb;
+  }
+  // layer 0: input x (NCHW -> [g][pixel][channel], padding channels zero); D_0 in r0
+  if constexpr (!SQ_ENC_PREFETCH) loadx();
+#pragma unroll
+  for (int i = 0; i < Prefetch<NX, NT>::R; ++i) {
+    const int e = (int)threadIdx.x + NT * i;
+    if (e < NX) {
+      const int g = e / (C * 256), r = e - g * C * 256, c = r >> 8, pix = r & 255;
+      rin[(g * 256 + pix) * L0::PS + c] = (__bf16)px.v[i];
+    }
+  }
+  for (int e = threadIdx.x; e < G * 256 * (L0::CP - C); e += NT) {
+    const int gp = e / (L0::CP - C), c = C + e - gp * (L0::CP - C);
+    rin[gp * L0::PS + c] = (__bf16)0.f;
+  }
+  fill_qtab<G, C, F, 0, NT>(qtab);
+  lds_barrier();
+  for (int t = threadIdx.x >> 6; t < WTiles<G, C, F, 0>::N; t += NT / 64)
+    bwd_w_tile<G, C, F, 0>(t, r0, rin, qtab, pp + off.W[0]);
+}
+
 // ---------------------------------------------------------------- launchers
 constexpr int kEncFwdG = 2, kEncFwdThreads = 512;
 constexpr int kEncBwdG = 2, kEncBwdThreads = 512;
+// measured on the full network, B = 512 (forward / backward per update): one image and
+// 256 threads per forward workgroup 14.5 us (two images, 512 threads: 14.9; four, 512:
+// 18.1); 1024 threads per backward workgroup 27.2 us (512: 31.5; 256: 41.4)
+#ifndef SQ_ENC_FWD_G
+#define SQ_ENC_FWD_G 1
+#endif
+#ifndef SQ_ENC_FWD_T
+#define SQ_ENC_FWD_T 256
+#endif
+#ifndef SQ_ENC_BWD_T
+#define SQ_ENC_BWD_T 1024
+#endif
+// bfloat16 form (the backward keeps kEncBwdG images per workgroup: the partial-gradient rows follow it)
+constexpr int kEncFwdGb = SQ_ENC_FWD_G, kEncFwdThreadsb = SQ_ENC_FWD_T;
+constexpr int kEncBwdThreadsb = SQ_ENC_BWD_T;
 
 template <int C, int F, int NC>
 static int prep_t(const float* const* W, float* wp, int bf16, hipStream_t st) {
@@ -422,9 +920,16 @@ static int prep_t(const float* const* W, float* wp, int bf16, hipStream_t st) {
 
 template <bool BF16, int C, int F, int NC>
 static int enc_fwd_t(const float* x, int n, const float* wp, const float* const* b, float* const* h, hipStream_t st) {
-  const int nwg = cdiv(n, kEncFwdG);
-  k_encoder_fwd<BF16, kEncFwdG, C, F, NC, kEncFwdThreads><<<nwg, kEncFwdThreads, 0, st>>>(
-      x, n, wp, b[0], b[1], NC > 2 ? b[2] : b[1], h[0], h[1], NC > 2 ? h[2] : h[1]);
+  if constexpr (BF16) {
+    const int nwg = cdiv(n, kEncFwdGb);
+    k_encoder_fwd_b<kEncFwdGb, C, F, NC, kEncFwdThreadsb><<<nwg, kEncFwdThreadsb, 0, st>>>(
+        x, n, reinterpret_cast<const __bf16*>(wp), b[0], b[1], NC > 2 ? b[2] : b[1], h[0], h[1],
+        NC > 2 ? h[2] : h[1]);
+  } else {
+    const int nwg = cdiv(n, kEncFwdG);
+    k_encoder_fwd<false, kEncFwdG, C, F, NC, kEncFwdThreads><<<nwg, kEncFwdThreads, 0, st>>>(
+        x, n, wp, b[0], b[1], NC > 2 ? b[2] : b[1], h[0], h[1], NC > 2 ? h[2] : h[1]);
+  }
   return launch_status("encoder_fwd");
 }
 
@@ -471,8 +976,12 @@ static int enc_bwd_t(const float* x, int n, const float* dfeat, const float* wp,
     off.W[i] = Woff[i];
     off.b[i] = boff[i];
   }
-  k_encoder_bwd<BF16, kEncBwdG, C, F, NC, kEncBwdThreads><<<nwg, kEncBwdThreads, 0, st>>>(
-      x, n, dfeat, wp, h[0], h[1], NC > 2 ? h[2] : h[1], off, total, part);
+  if constexpr (BF16)
+    k_encoder_bwd_b<kEncBwdG, C, F, NC, kEncBwdThreadsb><<<nwg, kEncBwdThreadsb, 0, st>>>(
+        x, n, dfeat, reinterpret_cast<const __bf16*>(wp), h[0], h[1], NC > 2 ? h[2] : h[1], off, total, part);
+  else
+    k_encoder_bwd<false, kEncBwdG, C, F, NC, kEncBwdThreads><<<nwg, kEncBwdThreads, 0, st>>>(
+        x, n, dfeat, wp, h[0], h[1], NC > 2 ? h[2] : h[1], off, total, part);
   SQ_TRY(launch_status("encoder_bwd"));
   if (!grad) return SQ_OK;   // the caller sums the partials (an optimiser segment)
   k_enc_reduce<<<(int)cdiv(total, 256), 256, 0, st>>>(part, nwg, total, grad);
