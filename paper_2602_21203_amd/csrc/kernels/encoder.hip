@@ -232,7 +232,8 @@ __device__ void conv_bwd_weights(float* D, const float* in, int2* qtab, float* _
     for (int e = threadIdx.x; e < G * Y::DS * Y::DS * PSF; e += NT) D[e] = bf16_round(D[e]);
     __syncthreads();
   }
-  // weights: rows f (F / 16 tiles), columns kc = tap * CIN + c, contraction over output pixels
+  // weights: rows f (F / 16 tiles), columns kc = c * 9 + tap (the parameter order, so
+  // a tile's stores are 16 consecutive floats per row), contraction over output pixels
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
   constexpr int RT = F / 16, CT = (Y::K + 15) / 16;
@@ -240,7 +241,7 @@ __device__ void conv_bwd_weights(float* D, const float* in, int2* qtab, float* _
     const int rt = t / CT, ct = t - rt * CT;
     const int f0 = rt * 16, k0 = ct * 16;
     const int kc = min(k0 + li, Y::K - 1);
-    const int tap = kc / Y::CIN, c = kc - tap * Y::CIN, ky = tap / 3, kx = tap - 3 * ky;
+    const int c = kc / 9, tap = kc - 9 * c, ky = tap / 3, kx = tap - 3 * ky;
     const float* ap = D + f0 + li;
     const float* bp = in + (ky * Y::HI + kx) * Y::PS + c;
     v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
@@ -251,9 +252,8 @@ __device__ void conv_bwd_weights(float* D, const float* in, int2* qtab, float* _
     }
     const int kk = k0 + li;
     if (kk < Y::K) {
-      const int tp = kk / Y::CIN, cc = kk - tp * Y::CIN;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) partW[(f0 + 4 * lq + q) * Y::K + cc * 9 + tp] = acc[q];
+      for (int q = 0; q < 4; ++q) partW[(f0 + 4 * lq + q) * Y::K + kk] = acc[q];
     }
   }
 }
@@ -478,7 +478,7 @@ struct WFrag {
 template <int G, int C, int F, int l, bool TO_LDS, bool LAST, int NT, bool PRE>
 __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16* __restrict__ wf,
                                  const float* __restrict__ bias, float* __restrict__ out_g, int gn,
-                                 const WFrag<C, F, l>& w) {
+                                 const WFrag<C, F, l>& w, float* out_lds_f = nullptr) {
   using Y = LB<C, F, l>;
   constexpr int ROWS = G * Y::P, RT = (ROWS + 15) / 16, CT = F / 16, NW = NT / 64;
   constexpr int PSO = F + 8;
@@ -511,12 +511,15 @@ __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16
         const int gg = r / Y::P, pp = r - gg * Y::P;
         const float v = fmaxf(acc[q] + bv, 0.f);
         if constexpr (TO_LDS) out_lds[(gg * Y::P + pp) * PSO + f] = (__bf16)v;
-        if (gg < gn) {
-          if constexpr (LAST) out_g[((long long)gg * F + f) * Y::P + pp] = v;
-          else out_g[((long long)gg * Y::P + pp) * F + f] = v;
-        }
+        if constexpr (LAST) out_lds_f[(gg * F + f) * Y::P + pp] = v;   // NCHW, stored below
+        else if (gg < gn) out_g[((long long)gg * Y::P + pp) * F + f] = v;
       }
     }
+  }
+  if constexpr (LAST) {
+    // the feature rows of the workgroup's images are contiguous in NCHW order
+    lds_barrier();
+    for (int e = threadIdx.x; e < gn * F * Y::P; e += NT) out_g[e] = out_lds_f[e];
   }
 }
 
@@ -575,18 +578,22 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
                                                        gn, w1);
     lds_barrier();
     conv_fwd_layer_b<G, C, F, 2, false, true, NT, PRE>(la1, nullptr, wp + E::F2, b2,
-                                                       h2 + (long long)img0 * F * LB<C, F, 2>::P, gn, w2);
+                                                       h2 + (long long)img0 * F * LB<C, F, 2>::P, gn, w2,
+                                                       reinterpret_cast<float*>(lx));
   } else {
     conv_fwd_layer_b<G, C, F, 1, false, true, NT, PRE>(la0, nullptr, wp + E::F1, b1,
-                                                       h1 + (long long)img0 * F * L1::P, gn, w1);
+                                                       h1 + (long long)img0 * F * L1::P, gn, w1,
+                                                       reinterpret_cast<float*>(lx));
   }
 }
 
 // Weight gradient of layer l from D (bfloat16 [G][DS][DS][F + 8], zero border of
-// 2) and the layer's input (bfloat16 [G][HI][HI][PS]): rows f, columns kc = tap *
-// CIN + c, contraction over the images' output pixels in 32-pixel chunks; each
-// lane gathers its 8 pixels of a chunk through the position table (pixel ->
-// offset in D, offset of its input patch origin), filled beforehand.
+// 2) and the layer's input (bfloat16 [G][HI][HI][PS]): rows f, columns kc = c * 9
+// + tap (the parameter order, so a tile's 16 columns are 16 consecutive floats of
+// the partial gradient and its stores coalesce), contraction over the images'
+// output pixels in 32-pixel chunks; each lane gathers its 8 pixels of a chunk
+// through the position table (pixel -> offset in D, offset of its input patch
+// origin), filled beforehand.
 #ifndef SQ_ENC_QTAB
 #define SQ_ENC_QTAB 1
 #endif
@@ -627,7 +634,7 @@ __device__ __forceinline__ void bwd_w_tile(int t, const __bf16* D, const __bf16*
   const int rt = t / W::CT, ct = t - rt * W::CT;
   const int f0 = rt * 16, k0 = ct * 16;
   const int kc = min(k0 + li, Y::K - 1);
-  const int tap = kc / Y::CIN, c = kc - tap * Y::CIN, ky = tap / 3, kx = tap - 3 * ky;
+  const int c = kc / 9, tap = kc - 9 * c, ky = tap / 3, kx = tap - 3 * ky;
   const __bf16* ap = D + f0 + li;
   const __bf16* bp = in + (ky * Y::HI + kx) * Y::PS + c;
   v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
@@ -657,9 +664,8 @@ __device__ __forceinline__ void bwd_w_tile(int t, const __bf16* D, const __bf16*
   }
   const int kk = k0 + li;
   if (kk < Y::K) {
-    const int tp = kk / Y::CIN, cc = kk - tp * Y::CIN;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) partW[(f0 + 4 * lq + q) * Y::K + cc * 9 + tp] = acc[q];
+    for (int q = 0; q < 4; ++q) partW[(f0 + 4 * lq + q) * Y::K + kk] = acc[q];
   }
 }
 
