@@ -345,7 +345,7 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
       (void)encoder_fused_prep_map(g->net.d.C, g->net.d.F, g->net.d.n_conv, g->net.side, L.conv_W, g->enc.wprep,
                                    hp->prec == SQ_BF16, &g->enc_map);
     GradSeg es;
-    if (encoder_grad_seg(g->net, L, g->enc, g->B, &es)) {
+    if (encoder_grad_seg(g->net, hp->prec == SQ_BF16, L, g->enc, g->B, &es)) {
       // the encoder block comes first in the flat vector, so the list stays sorted
       for (int i = g->gs_critic.n; i > 0; --i) g->gs_critic.s[i] = g->gs_critic.s[i - 1];
       g->gs_critic.s[0] = es;

@@ -217,28 +217,29 @@ int conv_dw(int bf16, const float* x, int n, int Cin, int H, int stride, const f
 int conv_dx(int bf16, const float* dout, const float* out, int n, int Cin, int H, const float* W, int F,
             float* dx, hipStream_t st);
 
-// encoder.hip: fused encoder for 16x16 inputs and the (C, F, n_conv) shapes it is built for.
+// encoder.hip: fused encoder for the (C, F, n_conv, side) shapes it is built for.
 // The conv weights W[l] are first rewritten by encoder_fused_prep into wp
 // (encoder_fused_prep_floats floats, bfloat16-rounded in that form); the fused
 // passes read the weights from wp and the biases from b.  Inner activations h[l]
 // (l < n_conv - 1) are [n][pixel][F]; the last one is NCHW (the feature vector).
-bool encoder_fused_ok(int C, int F, int n_conv, int side);
-size_t encoder_fused_part_floats(int n, long long enc_total);
+// fused path for these dims in this precision (16 x 16: both; 32 x 32: bfloat16 form)
+bool encoder_fused_ok(int C, int F, int n_conv, int side, int bf16);
+size_t encoder_fused_part_floats(int n, long long enc_total, int side);
 // partial-gradient rows the fused backward writes for n images ([rows][enc_total],
 // summed in row order as a GradSeg would); grad == nullptr leaves them unsummed
-int encoder_fused_part_rows(int n);
-// the prepared-copy map of the fused encoder (false when the geometry has no fused path);
-// W: flat offsets of the conv weights
+int encoder_fused_part_rows(int n, int side);
+// the prepared-copy map of the fused encoder (false when the geometry has no fused path
+// in this precision); W: flat offsets of the conv weights
 bool encoder_fused_prep_map(int C, int F, int n_conv, int side, const long long* W, float* wp, int bf16,
                             EncPrepMap* m);
 size_t encoder_fused_prep_floats(int C, int F, int n_conv);
 int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W, float* wp, hipStream_t st);
-int encoder_fused_fwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* wp,
+int encoder_fused_fwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* wp,
                       const float* const* b, float* const* h, hipStream_t st);
 // partial gradients of every workgroup in part, their ordered sum in grad[0, total)
-int encoder_fused_bwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* dfeat, const float* wp,
-                      const float* const* h, const long long* Woff, const long long* boff, long long total,
-                      float* part, float* grad, hipStream_t st);
+int encoder_fused_bwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* dfeat,
+                      const float* wp, const float* const* h, const long long* Woff, const long long* boff,
+                      long long total, float* part, float* grad, hipStream_t st);
 
 // rowops.hip
 // Second parameter group of a LayerNorm batch (batches z >= zalt read their gain

@@ -1,4 +1,6 @@
-// Fused conv encoder for 16x16 squinted images (Sec. IV Encoder Design Choices):
+// Fused conv encoder for 16x16 squinted images (Sec. IV Encoder Design Choices),
+// and, in the bfloat16 form, for the 32x32 input of the camera-resolution
+// analysis (Sec. VI): 32 -> 15 -> 13 -> 11 with one image per backward workgroup.
 // 3x3 valid convolutions, the first with stride 2, ReLU after each.
 //
 // Data layout.  Inside a workgroup every activation and gradient lives in LDS
@@ -418,11 +420,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // layer geometry with bfloat16 storage: PS elements per LDS pixel (16-byte aligned),
 // TPM taps per 32-wide k chunk, NM chunks per 3x3 contraction
-template <int C, int F, int l> struct LB {
+// on SD x SD images: SD -> (SD - 3) / 2 + 1 (stride 2) -> then 2 less per layer
+template <int C, int F, int l, int SD> struct LB {
   static constexpr int CIN = l == 0 ? C : F;
   static constexpr int CP = r16(CIN);
   static constexpr int PS = CP + 8;
-  static constexpr int HI = enc_in(l), HO = enc_out(l), S = l == 0 ? 2 : 1;
+  static constexpr int O0 = (SD - 3) / 2 + 1;
+  static constexpr int HI = l == 0 ? SD : O0 - 2 * (l - 1), HO = l == 0 ? O0 : HI - 2, S = l == 0 ? 2 : 1;
   static constexpr int P = HO * HO;
   static constexpr int K = CIN * 9;
   static constexpr int DS = HO + 4;
@@ -452,9 +456,9 @@ __device__ __forceinline__ void chunk_tap(int mi, int lq, int& tap, int& off) {
 // as this lane's MFMA fragments of every k chunk.  When the workgroup's wave count
 // is a multiple of the layer's column tiles, a wave only ever meets one column
 // tile, so all of a wave's weight fragments can be requested up front.
-template <int C, int F, int l>
+template <int C, int F, int l, int SD>
 struct WFrag {
-  using Y = LB<C, F, l>;
+  using Y = LB<C, F, l, SD>;
   bf16x8 b[Y::NM];
   float bias;
   __device__ __forceinline__ void load(const __bf16* __restrict__ wf, const float* __restrict__ bs, int c0) {
@@ -475,11 +479,11 @@ struct WFrag {
 // forward layer l of G images: in [G][HI][HI][PS] (bfloat16, LDS) -> post-ReLU
 // out_lds [G][HO][HO][F + 8] (bfloat16) and out_g (FP32, as the FP32 form).
 // w: the wave's weight fragments when PRE (its one column tile), else read per tile.
-template <int G, int C, int F, int l, bool TO_LDS, bool LAST, int NT, bool PRE>
+template <int G, int C, int F, int l, int SD, bool TO_LDS, bool LAST, int NT, bool PRE>
 __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16* __restrict__ wf,
                                  const float* __restrict__ bias, float* __restrict__ out_g, int gn,
-                                 const WFrag<C, F, l>& w, float* out_lds_f = nullptr) {
-  using Y = LB<C, F, l>;
+                                 const WFrag<C, F, l, SD>& w, float* out_lds_f = nullptr) {
+  using Y = LB<C, F, l, SD>;
   constexpr int ROWS = G * Y::P, RT = (ROWS + 15) / 16, CT = F / 16, NW = NT / 64;
   constexpr int PSO = F + 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -490,9 +494,9 @@ __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16
     const int row = min(r0 + li, ROWS - 1);
     const int g = row / Y::P, p = row - g * Y::P, oy = p / Y::HO, ox = p - oy * Y::HO;
     const __bf16* ap = in + ((g * Y::HI + oy * Y::S) * Y::HI + ox * Y::S) * Y::PS;
-    WFrag<C, F, l> wt;
+    WFrag<C, F, l, SD> wt;
     if constexpr (!PRE) wt.load(wf, bias, c0);
-    const WFrag<C, F, l>& ww = PRE ? w : wt;
+    const WFrag<C, F, l, SD>& ww = PRE ? w : wt;
     v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int mi = 0; mi < Y::NM; ++mi) {
@@ -523,15 +527,15 @@ __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16
   }
 }
 
-template <int G, int C, int F, int NC, int NT>
+template <int G, int C, int F, int NC, int SD, int NT>
 __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ x, int n, const __bf16* __restrict__ wp,
                                                       const float* __restrict__ b0, const float* __restrict__ b1,
                                                       const float* __restrict__ b2, float* __restrict__ h0,
                                                       float* __restrict__ h1, float* __restrict__ h2) {
-  using L0 = LB<C, F, 0>;
-  using L1 = LB<C, F, 1>;
+  using L0 = LB<C, F, 0, SD>;
+  using L1 = LB<C, F, 1, SD>;
   using E = EncPrep<C, F, NC>;
-  constexpr int X = G * 256 * L0::PS, A0 = G * L0::P * (F + 8), A1 = NC > 2 ? G * L1::P * (F + 8) : 8;
+  constexpr int X = G * SD * SD * L0::PS, A0 = G * L0::P * (F + 8), A1 = NC > 2 ? G * L1::P * (F + 8) : 8;
   constexpr int NW = NT / 64, CT = F / 16;
   constexpr bool PRE = NW % CT == 0;   // each wave meets one column tile per layer
   __shared__ __attribute__((aligned(16))) __bf16 lx[X];
@@ -540,17 +544,17 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
   const int img0 = blockIdx.x * G;
   const int gn = n - img0 < G ? n - img0 : G;
   // the images, then every layer's weight fragments of this wave, all requested up front
-  constexpr int RX = (G * C * 256 + NT - 1) / NT;
+  constexpr int RX = (G * C * SD * SD + NT - 1) / NT;
   float xv[RX];
 #pragma unroll
   for (int i = 0; i < RX; ++i) {
     const int e = (int)threadIdx.x + NT * i;
-    xv[i] = e < gn * C * 256 ? x[(long long)img0 * C * 256 + e] : 0.f;
+    xv[i] = e < gn * C * SD * SD ? x[(long long)img0 * C * SD * SD + e] : 0.f;
   }
   const int c0w = ((threadIdx.x >> 6) % CT) * 16;
-  WFrag<C, F, 0> w0;
-  WFrag<C, F, 1> w1;
-  WFrag<C, F, (NC > 2 ? 2 : 1)> w2;
+  WFrag<C, F, 0, SD> w0;
+  WFrag<C, F, 1, SD> w1;
+  WFrag<C, F, (NC > 2 ? 2 : 1), SD> w2;
   if constexpr (PRE) {
     w0.load(wp + E::F0, b0, c0w);
     w1.load(wp + E::F1, b1, c0w);
@@ -560,28 +564,28 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
 #pragma unroll
   for (int i = 0; i < RX; ++i) {
     const int e = (int)threadIdx.x + NT * i;
-    if (e < G * C * 256) {
-      const int g = e / (C * 256), r = e - g * C * 256, c = r >> 8, pix = r & 255;
-      lx[(g * 256 + pix) * L0::PS + c] = (__bf16)xv[i];
+    if (e < G * C * SD * SD) {
+      const int g = e / (C * SD * SD), r = e - g * C * SD * SD, c = r / (SD * SD), pix = r - c * SD * SD;
+      lx[(g * SD * SD + pix) * L0::PS + c] = (__bf16)xv[i];
     }
   }
-  for (int e = threadIdx.x; e < G * 256 * (L0::CP - C); e += NT) {
+  for (int e = threadIdx.x; e < G * SD * SD * (L0::CP - C); e += NT) {
     const int gp = e / (L0::CP - C), c = C + e - gp * (L0::CP - C);
     lx[gp * L0::PS + c] = (__bf16)0.f;
   }
   lds_barrier();
-  conv_fwd_layer_b<G, C, F, 0, true, false, NT, PRE>(lx, la0, wp + E::F0, b0, h0 + (long long)img0 * F * L0::P, gn,
+  conv_fwd_layer_b<G, C, F, 0, SD, true, false, NT, PRE>(lx, la0, wp + E::F0, b0, h0 + (long long)img0 * F * L0::P, gn,
                                                      w0);
   lds_barrier();
   if constexpr (NC > 2) {
-    conv_fwd_layer_b<G, C, F, 1, true, false, NT, PRE>(la0, la1, wp + E::F1, b1, h1 + (long long)img0 * F * L1::P,
+    conv_fwd_layer_b<G, C, F, 1, SD, true, false, NT, PRE>(la0, la1, wp + E::F1, b1, h1 + (long long)img0 * F * L1::P,
                                                        gn, w1);
     lds_barrier();
-    conv_fwd_layer_b<G, C, F, 2, false, true, NT, PRE>(la1, nullptr, wp + E::F2, b2,
-                                                       h2 + (long long)img0 * F * LB<C, F, 2>::P, gn, w2,
+    conv_fwd_layer_b<G, C, F, 2, SD, false, true, NT, PRE>(la1, nullptr, wp + E::F2, b2,
+                                                       h2 + (long long)img0 * F * LB<C, F, 2, SD>::P, gn, w2,
                                                        reinterpret_cast<float*>(lx));
   } else {
-    conv_fwd_layer_b<G, C, F, 1, false, true, NT, PRE>(la0, nullptr, wp + E::F1, b1,
+    conv_fwd_layer_b<G, C, F, 1, SD, false, true, NT, PRE>(la0, nullptr, wp + E::F1, b1,
                                                        h1 + (long long)img0 * F * L1::P, gn, w1,
                                                        reinterpret_cast<float*>(lx));
   }
@@ -600,9 +604,9 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
 #ifndef SQ_ENC_PREFETCH
 #define SQ_ENC_PREFETCH 1
 #endif
-template <int G, int C, int F, int l, int NT>
+template <int G, int C, int F, int l, int SD, int NT>
 __device__ __forceinline__ void fill_qtab(int2* qtab) {
-  using Y = LB<C, F, l>;
+  using Y = LB<C, F, l, SD>;
   constexpr int PSF = F + 8;
   constexpr int NPOS = G * Y::P, NQ = (NPOS + 31) / 32 * 32;
   for (int q = threadIdx.x; q < NQ; q += NT) {
@@ -616,17 +620,17 @@ __device__ __forceinline__ void fill_qtab(int2* qtab) {
   }
 }
 
-template <int G, int C, int F, int l>
+template <int G, int C, int F, int l, int SD>
 struct WTiles {
-  using Y = LB<C, F, l>;
+  using Y = LB<C, F, l, SD>;
   static constexpr int RT = F / 16, CT = (Y::K + 15) / 16, N = RT * CT;
 };
 
-template <int G, int C, int F, int l>
+template <int G, int C, int F, int l, int SD>
 __device__ __forceinline__ void bwd_w_tile(int t, const __bf16* D, const __bf16* in, const int2* qtab,
                                            float* __restrict__ partW) {
-  using Y = LB<C, F, l>;
-  using W = WTiles<G, C, F, l>;
+  using Y = LB<C, F, l, SD>;
+  using W = WTiles<G, C, F, l, SD>;
   constexpr int PSF = F + 8;
   constexpr int NPOS = G * Y::P, NQ = (NPOS + 31) / 32 * 32;
   const int lane = threadIdx.x & 63;
@@ -676,17 +680,17 @@ __device__ __forceinline__ void bwd_w_tile(int t, const __bf16* D, const __bf16*
 // 16-row tile are also summed per channel into bpart[tile][c] (the bias gradient
 // of layer l - 1, from unrounded values: lanes' rows in order, then the four
 // lane groups as (0 + 1) + (2 + 3)).
-template <int G, int C, int F, int l>
+template <int G, int C, int F, int l, int SD>
 struct XTiles {
-  using Y = LB<C, F, l>;
+  using Y = LB<C, F, l, SD>;
   static constexpr int ROWS = G * Y::HI * Y::HI, RT = (ROWS + 15) / 16, CT = F / 16, N = RT * CT;
 };
 
-template <int G, int C, int F, int l>
+template <int G, int C, int F, int l, int SD>
 __device__ __forceinline__ void bwd_x_tile(int t, const __bf16* D, const __bf16* __restrict__ wb,
                                            const float* __restrict__ hin, __bf16* Dn, float* bpart, int gn) {
-  using Y = LB<C, F, l>;
-  using X = XTiles<G, C, F, l>;
+  using Y = LB<C, F, l, SD>;
+  using X = XTiles<G, C, F, l, SD>;
   static_assert(l >= 1, "input gradients are needed above the first layer only");
   constexpr int PSF = F + 8, DSN = Y::HI + 4;
   constexpr int TPM = 32 / F, NM = (9 + TPM - 1) / TPM;
@@ -737,16 +741,16 @@ __device__ __forceinline__ void bwd_x_tile(int t, const __bf16* D, const __bf16*
 // Both products of a layer l >= 1 share one pass over the waves (they read the
 // same D_l and write different buffers): input-gradient tiles first (the longer
 // ones), then weight-gradient tiles.  The position table must be filled.
-template <int G, int C, int F, int l, int NT>
+template <int G, int C, int F, int l, int SD, int NT>
 __device__ __forceinline__ void bwd_layer_b(const __bf16* D, const __bf16* in, const int2* qtab,
                                             float* __restrict__ partW, const __bf16* __restrict__ wb,
                                             const float* __restrict__ hin, __bf16* Dn, float* bpart, int gn) {
-  using X = XTiles<G, C, F, l>;
-  using W = WTiles<G, C, F, l>;
+  using X = XTiles<G, C, F, l, SD>;
+  using W = WTiles<G, C, F, l, SD>;
   const int wave = threadIdx.x >> 6;
   for (int t = wave; t < X::N + W::N; t += NT / 64) {
-    if (t < X::N) bwd_x_tile<G, C, F, l>(t, D, wb, hin, Dn, bpart, gn);
-    else bwd_w_tile<G, C, F, l>(t - X::N, D, in, qtab, partW);
+    if (t < X::N) bwd_x_tile<G, C, F, l, SD>(t, D, wb, hin, Dn, bpart, gn);
+    else bwd_w_tile<G, C, F, l, SD>(t - X::N, D, in, qtab, partW);
   }
 }
 
@@ -764,27 +768,27 @@ struct Prefetch {
   }
 };
 
-template <int G, int C, int F, int NC, int NT>
+template <int G, int C, int F, int NC, int SD, int NT>
 __global__ __launch_bounds__(NT) void k_encoder_bwd_b(const float* __restrict__ x, int n,
                                                       const float* __restrict__ dfeat, const __bf16* __restrict__ wp,
                                                       const float* __restrict__ h0, const float* __restrict__ h1,
                                                       const float* __restrict__ h2, EncOffs off, long long enc_total,
                                                       float* __restrict__ part) {
-  using L0 = LB<C, F, 0>;
-  using L1 = LB<C, F, 1>;
-  using L2 = LB<C, F, (NC > 2 ? 2 : 1)>;
-  using LL = LB<C, F, NC - 1>;
+  using L0 = LB<C, F, 0, SD>;
+  using L1 = LB<C, F, 1, SD>;
+  using L2 = LB<C, F, (NC > 2 ? 2 : 1), SD>;
+  using LL = LB<C, F, NC - 1, SD>;
   using E = EncPrep<C, F, NC>;
   constexpr int PSF = F + 8;
   constexpr int SZ0 = G * L0::DS * L0::DS * PSF;                                  // D_0
   constexpr int SZ1 = G * L1::DS * L1::DS * PSF;                                  // D_1
   constexpr int SZ2 = NC > 2 ? G * L2::DS * L2::DS * PSF : 8;                     // D_2
   constexpr int R0 = SZ0 > SZ2 ? SZ0 : SZ2;   // D_2 first, D_0 last (never live together)
-  constexpr int IN0 = G * 256 * L0::PS, IN1 = G * L1::HI * L1::HI * L1::PS;
+  constexpr int IN0 = G * SD * SD * L0::PS, IN1 = G * L1::HI * L1::HI * L1::PS;
   constexpr int RIN = IN0 > IN1 ? IN0 : IN1;
   constexpr int RTB = (G * L1::HI * L1::HI + 15) / 16;   // most 16-row tiles of an input gradient
   constexpr int TOPN = G * F * LL::P;                    // the top layer's upstream gradient elements
-  constexpr int NH1 = NC > 2 ? G * L2::HI * L2::HI * F : 0, NH0 = G * L1::HI * L1::HI * F, NX = G * C * 256;
+  constexpr int NH1 = NC > 2 ? G * L2::HI * L2::HI * F : 0, NH0 = G * L1::HI * L1::HI * F, NX = G * C * SD * SD;
   __shared__ __attribute__((aligned(16))) __bf16 r0[R0];
   __shared__ __attribute__((aligned(16))) __bf16 r1[SZ1];
   __shared__ __attribute__((aligned(16))) __bf16 rin[RIN];
@@ -808,7 +812,7 @@ __global__ __launch_bounds__(NT) void k_encoder_bwd_b(const float* __restrict__ 
     if constexpr (NC > 2) p1.load(h1 + (long long)img0 * L2::HI * L2::HI * F, gn * L2::HI * L2::HI * F);
   };
   auto load0 = [&] { p0.load(h0 + (long long)img0 * L1::HI * L1::HI * F, gn * L1::HI * L1::HI * F); };
-  auto loadx = [&] { px.load(x + (long long)img0 * C * 256, gn * C * 256); };
+  auto loadx = [&] { px.load(x + (long long)img0 * C * SD * SD, gn * C * SD * SD); };
   if constexpr (SQ_ENC_PREFETCH) {
     load1();
     load0();
@@ -848,9 +852,9 @@ __global__ __launch_bounds__(NT) void k_encoder_bwd_b(const float* __restrict__ 
       if (e < NH1) rin[(e / F) * L2::PS + e % F] = (__bf16)p1.v[i];
     }
     for (int e = threadIdx.x; e < SZ1; e += NT) r1[e] = (__bf16)0.f;
-    fill_qtab<G, C, F, 2, NT>(qtab);
+    fill_qtab<G, C, F, 2, SD, NT>(qtab);
     lds_barrier();
-    bwd_layer_b<G, C, F, 2, NT>(r0, rin, qtab, pp + off.W[2], wp + E::B2,
+    bwd_layer_b<G, C, F, 2, SD, NT>(r0, rin, qtab, pp + off.W[2], wp + E::B2,
                                 h1 + (long long)img0 * L2::HI * L2::HI * F, r1, bpart, gn);
     lds_barrier();
     if (threadIdx.x < F) {
@@ -867,9 +871,9 @@ __global__ __launch_bounds__(NT) void k_encoder_bwd_b(const float* __restrict__ 
     if (e < NH0) rin[(e / F) * L1::PS + e % F] = (__bf16)p0.v[i];
   }
   for (int e = threadIdx.x; e < SZ0; e += NT) r0[e] = (__bf16)0.f;
-  fill_qtab<G, C, F, 1, NT>(qtab);
+  fill_qtab<G, C, F, 1, SD, NT>(qtab);
   lds_barrier();
-  bwd_layer_b<G, C, F, 1, NT>(r1, rin, qtab, pp + off.W[1], wp + E::B1, h0 + (long long)img0 * L1::HI * L1::HI * F,
+  bwd_layer_b<G, C, F, 1, SD, NT>(r1, rin, qtab, pp + off.W[1], wp + E::B1, h0 + (long long)img0 * L1::HI * L1::HI * F,
                               r0, bpart, gn);
   lds_barrier();
   if (threadIdx.x < F) {
@@ -883,18 +887,18 @@ __global__ __launch_bounds__(NT) void k_encoder_bwd_b(const float* __restrict__ 
   for (int i = 0; i < Prefetch<NX, NT>::R; ++i) {
     const int e = (int)threadIdx.x + NT * i;
     if (e < NX) {
-      const int g = e / (C * 256), r = e - g * C * 256, c = r >> 8, pix = r & 255;
-      rin[(g * 256 + pix) * L0::PS + c] = (__bf16)px.v[i];
+      const int g = e / (C * SD * SD), r = e - g * C * SD * SD, c = r / (SD * SD), pix = r - c * SD * SD;
+      rin[(g * SD * SD + pix) * L0::PS + c] = (__bf16)px.v[i];
     }
   }
-  for (int e = threadIdx.x; e < G * 256 * (L0::CP - C); e += NT) {
+  for (int e = threadIdx.x; e < G * SD * SD * (L0::CP - C); e += NT) {
     const int gp = e / (L0::CP - C), c = C + e - gp * (L0::CP - C);
     rin[gp * L0::PS + c] = (__bf16)0.f;
   }
-  fill_qtab<G, C, F, 0, NT>(qtab);
+  fill_qtab<G, C, F, 0, SD, NT>(qtab);
   lds_barrier();
-  for (int t = threadIdx.x >> 6; t < WTiles<G, C, F, 0>::N; t += NT / 64)
-    bwd_w_tile<G, C, F, 0>(t, r0, rin, qtab, pp + off.W[0]);
+  for (int t = threadIdx.x >> 6; t < WTiles<G, C, F, 0, SD>::N; t += NT / 64)
+    bwd_w_tile<G, C, F, 0, SD>(t, r0, rin, qtab, pp + off.W[0]);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -924,14 +928,19 @@ static int prep_t(const float* const* W, float* wp, int bf16, hipStream_t st) {
   return launch_status("encoder_prep");
 }
 
-template <bool BF16, int C, int F, int NC>
+// images per backward workgroup (the partial-gradient rows follow it): two on 16 x 16
+// inputs, one on 32 x 32 (whose LDS holds one image's activations and gradients)
+constexpr int enc_bwd_g(int side) { return side == 16 ? kEncBwdG : 1; }
+
+template <bool BF16, int C, int F, int NC, int SD>
 static int enc_fwd_t(const float* x, int n, const float* wp, const float* const* b, float* const* h, hipStream_t st) {
   if constexpr (BF16) {
     const int nwg = cdiv(n, kEncFwdGb);
-    k_encoder_fwd_b<kEncFwdGb, C, F, NC, kEncFwdThreadsb><<<nwg, kEncFwdThreadsb, 0, st>>>(
+    k_encoder_fwd_b<kEncFwdGb, C, F, NC, SD, kEncFwdThreadsb><<<nwg, kEncFwdThreadsb, 0, st>>>(
         x, n, reinterpret_cast<const __bf16*>(wp), b[0], b[1], NC > 2 ? b[2] : b[1], h[0], h[1],
         NC > 2 ? h[2] : h[1]);
   } else {
+    static_assert(SD == 16, "the FP32 fused encoder is built for 16 x 16 inputs");
     const int nwg = cdiv(n, kEncFwdG);
     k_encoder_fwd<false, kEncFwdG, C, F, NC, kEncFwdThreads><<<nwg, kEncFwdThreads, 0, st>>>(
         x, n, wp, b[0], b[1], NC > 2 ? b[2] : b[1], h[0], h[1], NC > 2 ? h[2] : h[1]);
@@ -939,7 +948,7 @@ static int enc_fwd_t(const float* x, int n, const float* wp, const float* const*
   return launch_status("encoder_fwd");
 }
 
-int encoder_fused_part_rows(int n) { return cdiv(n, kEncBwdG); }
+int encoder_fused_part_rows(int n, int side) { return cdiv(n, enc_bwd_g(side)); }
 
 template <int C, int F, int NC>
 static void prep_map_t(const long long* W, EncPrepMap* m) {
@@ -963,7 +972,7 @@ static void prep_map_t(const long long* W, EncPrepMap* m) {
 
 bool encoder_fused_prep_map(int C, int F, int n_conv, int side, const long long* W, float* wp, int bf16,
                             EncPrepMap* m) {
-  if (!encoder_fused_ok(C, F, n_conv, side) || !wp) return false;
+  if (!encoder_fused_ok(C, F, n_conv, side, bf16) || !wp) return false;
   *m = EncPrepMap{};
   if (C == 9 && F == 32 && n_conv == 3) prep_map_t<9, 32, 3>(W, m);
   else prep_map_t<3, 16, 2>(W, m);
@@ -972,33 +981,39 @@ bool encoder_fused_prep_map(int C, int F, int n_conv, int side, const long long*
   return true;
 }
 
-template <bool BF16, int C, int F, int NC>
+template <bool BF16, int C, int F, int NC, int SD>
 static int enc_bwd_t(const float* x, int n, const float* dfeat, const float* wp, const float* const* h,
                      const long long* Woff, const long long* boff, long long total, float* part, float* grad,
                      hipStream_t st) {
-  const int nwg = cdiv(n, kEncBwdG);
+  constexpr int GB = enc_bwd_g(SD);
+  const int nwg = cdiv(n, GB);
   EncOffs off{};
   for (int i = 0; i < NC; ++i) {
     off.W[i] = Woff[i];
     off.b[i] = boff[i];
   }
-  if constexpr (BF16)
-    k_encoder_bwd_b<kEncBwdG, C, F, NC, kEncBwdThreadsb><<<nwg, kEncBwdThreadsb, 0, st>>>(
+  if constexpr (BF16) {
+    k_encoder_bwd_b<GB, C, F, NC, SD, kEncBwdThreadsb><<<nwg, kEncBwdThreadsb, 0, st>>>(
         x, n, dfeat, reinterpret_cast<const __bf16*>(wp), h[0], h[1], NC > 2 ? h[2] : h[1], off, total, part);
-  else
+  } else {
+    static_assert(SD == 16, "the FP32 fused encoder is built for 16 x 16 inputs");
     k_encoder_bwd<false, kEncBwdG, C, F, NC, kEncBwdThreads><<<nwg, kEncBwdThreads, 0, st>>>(
         x, n, dfeat, wp, h[0], h[1], NC > 2 ? h[2] : h[1], off, total, part);
+  }
   SQ_TRY(launch_status("encoder_bwd"));
   if (!grad) return SQ_OK;   // the caller sums the partials (an optimiser segment)
   k_enc_reduce<<<(int)cdiv(total, 256), 256, 0, st>>>(part, nwg, total, grad);
   return launch_status("encoder_reduce");
 }
 
-bool encoder_fused_ok(int C, int F, int n_conv, int side) {
-  return side == 16 && ((C == 9 && F == 32 && n_conv == 3) || (C == 3 && F == 16 && n_conv == 2));
+bool encoder_fused_ok(int C, int F, int n_conv, int side, int bf16) {
+  if (side == 16) return (C == 9 && F == 32 && n_conv == 3) || (C == 3 && F == 16 && n_conv == 2);
+  return side == 32 && bf16 && C == 9 && F == 32 && n_conv == 3;   // bfloat16 form only
 }
 
-size_t encoder_fused_part_floats(int n, long long enc_total) { return (size_t)cdiv(n, kEncBwdG) * enc_total; }
+size_t encoder_fused_part_floats(int n, long long enc_total, int side) {
+  return (size_t)encoder_fused_part_rows(n, side) * enc_total;
+}
 
 size_t encoder_fused_prep_floats(int C, int F, int n_conv) {
   if (C == 9 && F == 32 && n_conv == 3) return EncPrep<9, 32, 3>::TOTAL;
@@ -1010,23 +1025,25 @@ int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W
   return prep_t<3, 16, 2>(W, wp, bf16, st);
 }
 
-int encoder_fused_fwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* wp,
+int encoder_fused_fwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* wp,
                       const float* const* b, float* const* h, hipStream_t st) {
   if (n <= 0) return SQ_OK;
+  if (side == 32) return enc_fwd_t<true, 9, 32, 3, 32>(x, n, wp, b, h, st);
   if (C == 9 && F == 32 && n_conv == 3)
-    return bf16 ? enc_fwd_t<true, 9, 32, 3>(x, n, wp, b, h, st) : enc_fwd_t<false, 9, 32, 3>(x, n, wp, b, h, st);
-  return bf16 ? enc_fwd_t<true, 3, 16, 2>(x, n, wp, b, h, st) : enc_fwd_t<false, 3, 16, 2>(x, n, wp, b, h, st);
+    return bf16 ? enc_fwd_t<true, 9, 32, 3, 16>(x, n, wp, b, h, st) : enc_fwd_t<false, 9, 32, 3, 16>(x, n, wp, b, h, st);
+  return bf16 ? enc_fwd_t<true, 3, 16, 2, 16>(x, n, wp, b, h, st) : enc_fwd_t<false, 3, 16, 2, 16>(x, n, wp, b, h, st);
 }
 
-int encoder_fused_bwd(int bf16, int C, int F, int n_conv, const float* x, int n, const float* dfeat, const float* wp,
-                      const float* const* h, const long long* Woff, const long long* boff, long long total,
-                      float* part, float* grad, hipStream_t st) {
+int encoder_fused_bwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* dfeat,
+                      const float* wp, const float* const* h, const long long* Woff, const long long* boff,
+                      long long total, float* part, float* grad, hipStream_t st) {
   if (n <= 0) return SQ_OK;
+  if (side == 32) return enc_bwd_t<true, 9, 32, 3, 32>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st);
   if (C == 9 && F == 32 && n_conv == 3)
-    return bf16 ? enc_bwd_t<true, 9, 32, 3>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st)
-                : enc_bwd_t<false, 9, 32, 3>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st);
-  return bf16 ? enc_bwd_t<true, 3, 16, 2>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st)
-              : enc_bwd_t<false, 3, 16, 2>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st);
+    return bf16 ? enc_bwd_t<true, 9, 32, 3, 16>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st)
+                : enc_bwd_t<false, 9, 32, 3, 16>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st);
+  return bf16 ? enc_bwd_t<true, 3, 16, 2, 16>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st)
+              : enc_bwd_t<false, 3, 16, 2, 16>(x, n, dfeat, wp, h, Woff, boff, total, part, grad, st);
 }
 
 }  // namespace sq

@@ -46,13 +46,13 @@ int scratch_ptr(char** out) {
 
 // the inner layers' activations and the fused path's rearranged weights (the
 // last layer is written straight into the caller's feature buffer)
-size_t plan(const sq::Net& net, int n, char* base, sq::EncBufs* e) {
+size_t plan(const sq::Net& net, int n, char* base, sq::EncBufs* e, int bf16) {
   const sq_dims& d = net.d;
   sq::Bump b{base};
   *e = sq::EncBufs{};
   for (int i = 0; i + 1 < d.n_conv; ++i)
     e->h[i] = b.take<float>((size_t)n * d.F * net.conv_side[i] * net.conv_side[i]);
-  if (sq::encoder_fused_ok(d.C, d.F, d.n_conv, net.side))
+  if (sq::encoder_fused_ok(d.C, d.F, d.n_conv, net.side, bf16))
     e->wprep = b.take<float>(sq::encoder_fused_prep_floats(d.C, d.F, d.n_conv));
   return b.off;
 }
@@ -89,7 +89,7 @@ int encoder_fwd_noalloc(const sq_dims* dims, sq_prec prec, const float* enc_para
     return SQ_EINVAL;
   }
   EncBufs e;
-  const size_t need = plan(net, n, nullptr, &e);
+  const size_t need = plan(net, n, nullptr, &e, prec == SQ_BF16);
   if (need > kScratchBytes) {
     set_error("encoder_fwd_noalloc: %d images need %zu scratch bytes, more than the %zu it holds", n, need,
               kScratchBytes);
@@ -97,7 +97,7 @@ int encoder_fwd_noalloc(const sq_dims* dims, sq_prec prec, const float* enc_para
   }
   char* base = nullptr;
   SQ_TRY(scratch_ptr(&base));
-  plan(net, n, base, &e);
+  plan(net, n, base, &e, prec == SQ_BF16);
   e.h[dims->n_conv - 1] = feat;
   Layout L;
   make_layout(net, &L);
@@ -111,12 +111,13 @@ int sq_encoder_noalloc_max_images(const sq_dims* dims, int* n) {
     set_error("NULL n or state-based dims");
     return SQ_EINVAL;
   }
-  // the plan grows with n: the largest n whose plan fits
+  // the plan grows with n: the largest n whose plan fits (the bfloat16 form's plan,
+  // which holds the FP32 form's)
   int lo = 0, hi = 1 << 20;
   while (lo < hi) {
     const int mid = lo + (hi - lo + 1) / 2;
     EncBufs e;
-    if (plan(net, mid, nullptr, &e) <= kScratchBytes) lo = mid; else hi = mid - 1;
+    if (plan(net, mid, nullptr, &e, 1) <= kScratchBytes) lo = mid; else hi = mid - 1;
   }
   *n = lo;
   return SQ_OK;

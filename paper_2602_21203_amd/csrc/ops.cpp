@@ -83,16 +83,17 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
   e->bias_part = nullptr;
   e->enc_part = nullptr;
   e->wprep = nullptr;
-  if (encoder_fused_ok(d.C, d.F, d.n_conv, net.side)) {
+  // the workspace serves both precisions: the fused path's buffers when either has
+  // one, the general path's when the FP32 form has none
+  if (encoder_fused_ok(d.C, d.F, d.n_conv, net.side, 1)) {
     e->wprep = b.take<float>(encoder_fused_prep_floats(d.C, d.F, d.n_conv));
     if (with_bwd) {
       Layout L;
       make_layout(net, &L);
-      e->enc_part = b.take<float>(encoder_fused_part_floats(n, L.enc_end));
+      e->enc_part = b.take<float>(encoder_fused_part_floats(n, L.enc_end, net.side));
     }
-    return;
   }
-  if (with_bwd) {
+  if (with_bwd && !encoder_fused_ok(d.C, d.F, d.n_conv, net.side, 0)) {
     const size_t big = (size_t)n * d.F * net.conv_side[0] * net.conv_side[0];
     e->dh[0] = b.take<float>(big);
     e->dh[1] = b.take<float>(big);
@@ -101,9 +102,14 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd) {
   }
 }
 
+bool encoder_fused(const Net& net, int bf16, const EncBufs& e) {
+  const sq_dims& d = net.d;
+  return e.wprep && d.n_conv > 0 && encoder_fused_ok(d.C, d.F, d.n_conv, net.side, bf16);
+}
+
 int encoder_prepare(const Net& net, int bf16, const float* ep, const Layout& L, const EncBufs& e, hipStream_t st) {
   const sq_dims& d = net.d;
-  if (!e.wprep) return SQ_OK;
+  if (!encoder_fused(net, bf16, e)) return SQ_OK;
   const float* W[4];
   for (int i = 0; i < d.n_conv; ++i) W[i] = ep + L.conv_W[i];
   return encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st);
@@ -112,7 +118,7 @@ int encoder_prepare(const Net& net, int bf16, const float* ep, const Layout& L, 
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                     const EncBufs& e, hipStream_t st, bool prepared) {
   const sq_dims& d = net.d;
-  if (e.wprep) {
+  if (encoder_fused(net, bf16, e)) {
     const float* b[4];
     float* h[4];
     for (int i = 0; i < d.n_conv; ++i) {
@@ -120,7 +126,7 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
       h[i] = e.h[i];
     }
     if (!prepared) SQ_TRY(encoder_prepare(net, bf16, ep, L, e, st));
-    return encoder_fused_fwd(bf16, d.C, d.F, d.n_conv, x, n, e.wprep, b, h, st);
+    return encoder_fused_fwd(bf16, d.C, d.F, d.n_conv, net.side, x, n, e.wprep, b, h, st);
   }
   const float* in = x;
   int cin = d.C, hs = net.side;
@@ -133,9 +139,9 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
   return SQ_OK;
 }
 
-bool encoder_grad_seg(const Net& net, const Layout& L, const EncBufs& e, int n, GradSeg* seg) {
-  if (!e.enc_part || net.d.n_conv == 0) return false;
-  *seg = GradSeg{L.enc_begin, (int)(L.enc_end - L.enc_begin), encoder_fused_part_rows(n), e.enc_part};
+bool encoder_grad_seg(const Net& net, int bf16, const Layout& L, const EncBufs& e, int n, GradSeg* seg) {
+  if (!e.enc_part || !encoder_fused(net, bf16, e)) return false;
+  *seg = GradSeg{L.enc_begin, (int)(L.enc_end - L.enc_begin), encoder_fused_part_rows(n, net.side), e.enc_part};
   return true;
 }
 
@@ -143,7 +149,7 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
                      const float* dfeat, const EncBufs& e, float* dep, hipStream_t st,
                      bool prepared, bool defer_reduce) {
   const sq_dims& d = net.d;
-  if (e.enc_part) {
+  if (e.enc_part && encoder_fused(net, bf16, e)) {
     const float* W[4];
     const float* h[4];
     long long Wo[4], bo[4];
@@ -154,8 +160,8 @@ int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L,
       bo[i] = L.conv_b[i];
     }
     if (!prepared) SQ_TRY(encoder_fused_prep(bf16, d.C, d.F, d.n_conv, W, e.wprep, st));
-    return encoder_fused_bwd(bf16, d.C, d.F, d.n_conv, x, n, dfeat, e.wprep, h, Wo, bo, L.enc_end, e.enc_part,
-                             defer_reduce ? nullptr : dep, st);
+    return encoder_fused_bwd(bf16, d.C, d.F, d.n_conv, net.side, x, n, dfeat, e.wprep, h, Wo, bo, L.enc_end,
+                             e.enc_part, defer_reduce ? nullptr : dep, st);
   }
   const float* dh = dfeat;
   for (int i = d.n_conv - 1; i >= 0; --i) {

@@ -30,8 +30,11 @@ int encoder_prepare(const Net& net, int bf16, const float* ep, const Layout& L, 
 int encoder_backward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                      const float* dfeat, const EncBufs& e, float* dep, hipStream_t st,
                      bool prepared = false, bool defer_reduce = false);
-// the fused encoder's partial gradients as an optimiser segment (false: no fused path)
-bool encoder_grad_seg(const Net& net, const Layout& L, const EncBufs& e, int n, GradSeg* seg);
+// the fused encoder's partial gradients as an optimiser segment (false: no fused path
+// in this precision)
+bool encoder_grad_seg(const Net& net, int bf16, const Layout& L, const EncBufs& e, int n, GradSeg* seg);
+// whether these buffers run the fused encoder in this precision
+bool encoder_fused(const Net& net, int bf16, const EncBufs& e);
 
 struct DenseSave { float* xhat; float* rstd; };
 struct CriticBufs {

@@ -20,7 +20,7 @@ def main(names=None):
     if os.path.exists(OUT):
         with open(OUT) as f:
             old = json.load(f)
-        for k in ("cases", "act", "scaling", "fp32_deviation"):
+        for k in ("cases", "act", "scaling", "fp32_deviation", "enc_ops"):
             if k in old:
                 out[k] = old[k]
     for name, case in sensitivity.CASES.items():
@@ -32,6 +32,9 @@ def main(names=None):
         worst = max(g, key=g.get)
         print(f"{name}: worst gradient {worst} {g[worst]:.2e}, "
               f"stats max {max(out['cases'][name]['stat'].values()):.2e} ({time.time() - t:.0f} s)", flush=True)
+    if not names or "ops" in names:
+        out["enc_ops"] = {k: sensitivity.measure_enc_op(*v) for k, v in sensitivity.ENC_OP_CASES.items()}
+        print("encoder ops:", out["enc_ops"], flush=True)
     if not names or "fp32_deviation" in names:
         out["fp32_deviation"] = sensitivity.fp32_deviation()
         print("fp32 deviation (units at row RMS):", out["fp32_deviation"], flush=True)

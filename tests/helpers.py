@@ -39,6 +39,11 @@ def bf16_stat_tol(case, stat):
     return max(LOSS_RTOL, SENS_FACTOR * SENS["cases"][case]["stat"][stat])
 
 
+def bf16_enc_op_tol(case, what):
+    """Encoder op parity (features or a gradient tensor) in the bfloat16 mode."""
+    return max(GRAD_RTOL, SENS_FACTOR * SENS["enc_ops"][case][what])
+
+
 def bf16_act_tol(kind):
     return max(ACT_RTOL, SENS_FACTOR * SENS["act"][kind])
 

@@ -220,3 +220,46 @@ def fp32_deviation(case=None, rows=512):
         rms = np.sqrt(np.mean(a * a, axis=1, keepdims=True))
         out[k] = float(np.mean(np.abs(a - b) / np.maximum(rms, 1e-30)) / 2.0 ** -24)
     return out
+
+
+# the encoder op parity case (encoder_fwd / encoder_bwd alone): n random frames
+# squinted, upstream gradient N(0, 1) (the GPU test's recipe: op_batch below)
+ENC_OP_CASES = {"tiny_n37": ("tiny", 37), "full_n77": ("full", 77), "full32_n45": ("full32", 45)}
+
+
+def op_batch(cfg, n, seed=0):
+    """Inputs of the op parity tests: squinted random frames, proprio, actions."""
+    from oracle import squint
+    rng = np.random.default_rng(seed)
+    d = olayout.dims(**cfg)
+    x = squint.squint(rng.integers(0, 256, size=(n, cfg["H"], cfg["W"], cfg["C"]), dtype=np.uint8), cfg["k"])
+    s = rng.normal(size=(n, cfg["proprio"]))
+    a = rng.uniform(-1, 1, size=(n, cfg["action"]))
+    return d, x, s, a
+
+
+def measure_enc_op(name, n, n_perturb=N_PERTURB, delta=DELTA):
+    """{"feat": sens, tensor: sens, ...} of the encoder alone in the bfloat16 mode."""
+    from oracle import nets
+    cfg = dict(configs.CONFIGS[name])
+    d, x, _, _ = op_batch(cfg, n)
+    tab = [(t, o, sh) for t, (o, sh) in olayout.offsets(d)[0].items()]
+    P = olayout.view(synthetic.init_params(tab, seed=1).astype(np.float64), d)
+    xf = x.astype(np.float32).astype(np.float64)
+    f0, ec = nets.encoder_fwd(P, xf, d.n_conv, True)
+    dfeat = np.random.default_rng(1).normal(size=f0.shape)
+    g0 = nets.encoder_bwd(P, ec, dfeat, d.n_conv, True)
+    out = {"feat": 0.0}
+    out.update({t: 0.0 for t in g0})
+    rng = np.random.default_rng(PERTURB_SEED)
+    for _ in range(n_perturb):
+        obf16.set_computed_perturbation(perturbation(rng, delta))
+        try:
+            f1, ec1 = nets.encoder_fwd(P, xf, d.n_conv, True)
+            g1 = nets.encoder_bwd(P, ec1, dfeat, d.n_conv, True)
+        finally:
+            obf16.set_computed_perturbation(None)
+        out["feat"] = max(out["feat"], float(np.linalg.norm(f1 - f0) / np.linalg.norm(f0)))
+        for t in g0:
+            out[t] = max(out[t], float(np.linalg.norm(g1[t] - g0[t]) / max(np.linalg.norm(g0[t]), 1e-30)))
+    return out

@@ -10,6 +10,7 @@ from oracle import layout as olayout
 from oracle import nets, philox, sac, squint
 from paper_2602_21203_amd import synthetic
 from tests import helpers as H
+from tests import sensitivity
 
 pytestmark = pytest.mark.gpu
 
@@ -63,12 +64,7 @@ def test_squint_bit_exact(name):
 
 
 def _rand_batch(cfg, n, seed=0):
-    rng = np.random.default_rng(seed)
-    d = olayout.dims(**cfg)
-    x = squint.squint(rng.integers(0, 256, size=(n, cfg["H"], cfg["W"], cfg["C"]), dtype=np.uint8), cfg["k"])
-    s = rng.normal(size=(n, cfg["proprio"]))
-    a = rng.uniform(-1, 1, size=(n, cfg["action"]))
-    return d, x, s, a
+    return sensitivity.op_batch(cfg, n, seed)
 
 
 def _tensor_errs(got, ref, tab, base):
@@ -98,14 +94,22 @@ def test_encoder_critic_actor_ops_vs_oracle(name, n, prec):
     xf = x.astype(np.float32)
     feat_ref, ec = nets.encoder_fwd(P, xf.astype(np.float64), d.n_conv, bf)
     feat, ws = api.encoder_fwd(cfg, prec, p[:blk["enc"][1]], dev(xf))
-    assert H.rel_norm(feat.cpu().numpy(), feat_ref) < fwd_tol
+    # the bfloat16 encoder's tolerances follow the oracle's own sensitivity of this
+    # case (tests/sensitivity.py): on 32 x 32 inputs its gradients are chaotic at 5e-3
+    ecase = f"{name}_n{n}"
+    tol = (lambda what: H.bf16_enc_op_tol(ecase, what)) if bf else (lambda what: 1e-3)
+    e = H.rel_norm(feat.cpu().numpy(), feat_ref)
+    print(f"  feat err {e:.2e} tol {min(fwd_tol, tol('feat')) if not bf else max(fwd_tol, tol('feat')):.1e}")
+    assert e < (fwd_tol if not bf else max(fwd_tol, tol("feat")))
     rng = np.random.default_rng(1)
     dfeat = rng.normal(size=feat_ref.shape)
     g_ref = nets.encoder_bwd(P, ec, dfeat, d.n_conv, bf)
     g = api.encoder_bwd(cfg, prec, p[:blk["enc"][1]], ws, dev(dfeat), blk["enc"][1]).cpu().numpy()
     for nm, gr in g_ref.items():
         o, sh = tab[nm]
-        assert H.rel_norm(g[o:o + gr.size], gr.ravel()) < 1e-3, nm
+        e = H.rel_norm(g[o:o + gr.size], gr.ravel())
+        print(f"  {nm} err {e:.2e} tol {tol(nm):.1e}")
+        assert e < tol(nm), nm
     # critic (online parameters, FP64 features so both sides see the same input)
     featq = feat_ref.astype(np.float32).astype(np.float64)
     logits_ref, cc = nets.critic_fwd(P, featq, s, a, bf)

@@ -31,6 +31,7 @@ def test_table_covers_every_case_and_tensor():
         assert set(g["cases"][name]["grad"]) == set(olayout.offsets(d)[0]), name
         assert set(g["cases"][name]["stat"]) == set(sensitivity.STAT_NAMES), name
     assert set(g["act"]) >= {"mean", "sample"}
+    assert set(g["enc_ops"]) == set(sensitivity.ENC_OP_CASES)
 
 
 def test_hook_is_inert_when_off():
