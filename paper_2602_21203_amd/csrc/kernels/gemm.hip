@@ -15,6 +15,12 @@
 // result is independent of scheduling.  Long reductions (conv weight gradients)
 // are split over K across workgroups into a scratch buffer and summed in order
 // by a second kernel.
+//
+// Workgroup order: consecutive workgroups go to the eight XCDs in turn, each
+// with its own L2, so the linear workgroup id is remapped (when the tile count
+// is a multiple of 8) to give every XCD a contiguous run of tiles, ordered in
+// groups of 8 row tiles -- about an 8 x 8 block of tiles per XCD, which reads
+// half of each operand of its batch instead of all of one operand.
 #include "../common.h"
 #include "bf16.h"
 #include "tgauss.h"
@@ -228,6 +234,22 @@ struct StPart {
     part[(((long long)z * splits + s) * M + r) * N + c] = v;
   }
 };
+
+// XCD-aware tile order (see the top of the file): linear workgroup id b of a
+// gx x gy x gz grid -> tile (bx, by, bz); a bijection for any grid
+__device__ __forceinline__ void tile_of(int b, int gx, int gy, int gz, int& bx, int& by, int& bz) {
+  const int T = gx * gy * gz;
+  if (T % 8 == 0) b = (b % 8) * (T / 8) + b / 8;
+  const int per = gx * gy;
+  bz = b / per;
+  const int p = b - bz * per;
+  constexpr int GM = 8;
+  const int grp = p / (GM * gy), first = grp * GM;
+  const int gm = min(gx - first, GM);
+  const int q = p - grp * GM * gy;
+  bx = first + q % gm;
+  by = q / gm;
+}
 
 // ---------------------------------------------------------------- kernel
 // Global -> register staging of one 32 x BK operand slice.  Each thread owns
@@ -691,7 +713,10 @@ template <bool BF16, int AV, int BV, class ST, bool SPLIT>
 __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, StPart sp, int M, int N, int K,
                                                      int kchunk) {
   __shared__ __attribute__((aligned(16))) char lds[gemm_lds_bytes<BF16, AV, BV>()];
-  gemm_tile<BF16, AV, BV, ST, SPLIT>(fa, fb, st, sp, M, N, K, kchunk, blockIdx.x, blockIdx.y, blockIdx.z, lds);
+  int bx, by, bz;
+  tile_of(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), gridDim.x, gridDim.y, gridDim.z, bx, by,
+          bz);
+  gemm_tile<BF16, AV, BV, ST, SPLIT>(fa, fb, st, sp, M, N, K, kchunk, bx, by, bz, lds);
 }
 
 // Two independent products in one launch (the input and weight gradients of one

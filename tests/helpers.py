@@ -18,13 +18,12 @@ ACT_RTOL = 1e-3                        # act(): ||d||_2 <= 1e-3 ||ref||_2 over t
 # oracle, so a few rounding decisions differ and later decisions of those rows
 # follow.  How far each result moves through such flips is measured on the
 # oracle alone (tests/sensitivity.py, stored in golden/bf16_sensitivity.json by
-# golden/make_bf16_sensitivity.py): every computed operand perturbed by one FP32
-# rounding unit (2^-24 relative, random sign) before it is rounded.  Each BF16
-# tolerance is max(stated bar, SENS_FACTOR x that sensitivity), per gradient
-# tensor and per statistic.  The sensitivity grows about as delta^0.7 with the
-# perturbation size delta (measured at 2^-24, 2^-22, 2^-20), so SENS_FACTOR = 4
-# covers a pre-rounding deviation of up to about 8 FP32 rounding units; the FP32
-# path's own gradients differ from FP64 by 1-2 units.
+# golden/make_bf16_sensitivity.py): every computed operand that FP32 cannot hold
+# exactly is moved by delta = 2^-22 times the rms of its row (random sign), the
+# size of the FP32 path's own deviation from FP64, before it is rounded; the
+# mean change over 8 draws is the sensitivity.  Each BF16 tolerance is
+# max(stated bar, SENS_FACTOR x that sensitivity), per gradient tensor and per
+# statistic.
 SENS_FACTOR = 2.0
 _SENS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "bf16_sensitivity.json")
 with open(_SENS_PATH) as _f:
