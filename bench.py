@@ -185,6 +185,32 @@ def measured_mfma_busy(kernel_key, source):
     return float(m[1]) if m[0] == digest else None
 
 
+def measured_profiled_us(kernel_key, source):
+    """Mean kernel duration (us) of the standalone launches in the committed
+    kernel trace, None when the kernel's source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_counters_gemm_squint.txt")
+    if not os.path.exists(path):
+        return None
+    m = re_search(kernel_key + r"\s+source=(\w+)\s+profiled_us=([\d.]+)", open(path).read(), groups=True)
+    if m is None:
+        return None
+    digest = hashlib.sha256(open(os.path.join(ROOT, source), "rb").read()).hexdigest()[:16]
+    return float(m[1]) if m[0] == digest else None
+
+
+def profiled_figure(kernel_key, source, work, peak, scale):
+    """The roofline figure from the committed profile's kernel duration: work
+    (FLOP or bytes) per launch / profiled mean duration, against peak."""
+    us = measured_profiled_us(kernel_key, source)
+    if us is None:
+        return None
+    ach = work / (us * 1e-6) / scale
+    return {"avg_us": us, "achieved": round(ach, 2), "frac": round(ach / peak, 5),
+            "method": "the mean duration of the same standalone launches in the committed rocprofv3 kernel trace "
+                      "(profiles/sac_update_full_b512_bf16_kernels.txt, profiler attached)"}
+
+
 def re_search(pat, text, groups=False):
     import re
     m = re.search(pat, text)
@@ -659,7 +685,10 @@ def main():
                           "avg_us": round(t_g * 1e6, 3), "algorithmic_flops": flops,
                           "method": "achieved = algorithmic FLOP per launch / avg_us, the start-to-start period of "
                                     "back-to-back launches replayed from a HIP graph (HIP events on the launch stream)",
-                          "algorithmic_bytes": 3 * 2 * 512 * 512 * 4 + 2 * 512 * 4}
+                          "algorithmic_bytes": 3 * 2 * 512 * 512 * 4 + 2 * 512 * 4,
+                          "profiled": profiled_figure("gemm_twin_l2_fwd_bf16",
+                                                      "paper_2602_21203_amd/csrc/kernels/gemm.hip", flops, peak, 1e12)
+                          if a.prec == "bf16" else None}
     if a.state:
         agent.close()
         print(json.dumps(result))
@@ -675,7 +704,11 @@ def main():
                                  "traffic": measured_traffic("squint_2B_frames",
                                                              "paper_2602_21203_amd/csrc/kernels/squint.hip")
                                  if (B, cfg["H"], side_of(cfg)) == (512, 64, 16) else None,
-                                 "avg_us": round(t_k * 1e6, 3), "algorithmic_bytes": bytes_per_launch}
+                                 "avg_us": round(t_k * 1e6, 3), "algorithmic_bytes": bytes_per_launch,
+                                 "profiled": profiled_figure("squint_2B_frames",
+                                                             "paper_2602_21203_amd/csrc/kernels/squint.hip",
+                                                             bytes_per_launch, 8000.0, 1e9)
+                                 if (B, cfg["H"], side_of(cfg)) == (512, 64, 16) else None}
     if a.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = src.clone()
