@@ -32,8 +32,9 @@
  *
  * Layouts
  *   frames        [rows, H, W, C] uint8, HWC, channel c = 3*s + rgb for stack
- *                 slot s (oldest first).  H/k == W/k == 16.
- *   images        [n, C, 16, 16] float (or bfloat16 bits), CHW.
+ *                 slot s (oldest first).  H/k == W/k = S, the squinted side
+ *                 (16, or 32 for the higher-resolution variant).
+ *   images        [n, C, S, S] float (or bfloat16 bits), CHW.
  *   features      [n, flat] float, flattened (channel, y, x).
  *   parameters    one flat float vector in the canonical order reported by
  *                 sq_param_offsets (encoder convs, critic projection, twin
@@ -138,14 +139,15 @@ SQ_API int sq_workspace_bytes(const sq_dims* dims, int op, int n, size_t* bytes)
  *   S = exact integer block sum, x = fl32(fl32(S / (255 k^2)) - 0.5).
  * frames: [rows, H, W, C] uint8; idx: [n] row indices into frames (NULL = rows
  * 0..n-1; every index must be in [0, rows), not checked on the device);
- * out: [n, C, 16, 16], float (out_prec SQ_F32) or bfloat16 bits (SQ_BF16,
+ * out: [n, C, S, S], float (out_prec SQ_F32) or bfloat16 bits (SQ_BF16,
  * rounded to nearest even from the FP32 value). */
 SQ_API int squint_downsample(const sq_dims* dims, const uint8_t* frames, const int* idx, int n, sq_prec out_prec,
                       void* out, sq_stream_t stream);
 
 /* Shared conv encoder f_psi (Sec. III; Sec. IV Encoder Design Choices): n_conv
  * 3x3 valid convolutions, the first with stride 2, each followed by ReLU.
- * enc_params: the encoder block of the flat vector; x: [n, C, 16, 16] float;
+ * enc_params: the encoder block of the flat vector; x: [n, C, S, S] float (also
+ * under SQ_BF16: that form rounds x to bfloat16 once, as it stages it in LDS);
  * feat: [n, flat] float.  ws: sq_workspace_bytes(SQ_OP_ENCODER, n) bytes; it
  * keeps the activations for encoder_bwd and must not change in between. */
 SQ_API int encoder_fwd(const sq_dims* dims, sq_prec prec, const float* enc_params, const float* x, int n,
