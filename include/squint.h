@@ -394,6 +394,10 @@ SQ_API int sq_agent_last_indices(const sq_agent* agent, int* idx, sq_stream_t st
 /* Row of transition i of an insertion at write position pos in a ring of
  * `capacity` rows: (pos + i) mod capacity, in 64-bit arithmetic.  [host] */
 SQ_API int sq_ring_row(int pos, long long i, int capacity, int* row);
+/* Output tile (bx, by, bz) -> tile[0..2] that workgroup b of a gx x gy x gz
+ * linear-layer product grid computes (the XCD-aware order the product kernels
+ * use).  [host] */
+SQ_API int sq_gemm_tile_order(int b, int gx, int gy, int gz, int* tile);
 /* idx[b] = mulhi32(Philox4x32_10(ctr = (update, 0, b, 0), key = seed).w0, size). */
 SQ_API int sq_sample_indices(unsigned long long seed, unsigned int update, int size, int n, int* idx,
                       sq_stream_t stream);

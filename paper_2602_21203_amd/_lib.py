@@ -107,6 +107,7 @@ def _load():
         "sq_agent_graph_count": (c_int, [c_vp, P(c_ll), P(c_int)]),
         "sq_agent_last_indices": (c_int, [c_vp, c_vp, c_vp]),
         "sq_ring_row": (c_int, [c_int, c_ll, c_int, P(c_int)]),
+        "sq_gemm_tile_order": (c_int, [c_int, c_int, c_int, c_int, P(c_int)]),
         "encoder_fwd_noalloc": (c_int, [P(Dims), c_int, c_vp, c_vp, c_int, c_vp, c_vp]),
         "sq_encoder_noalloc_max_images": (c_int, [P(Dims), P(c_int)]),
     }

@@ -256,6 +256,16 @@ int sq_gemm(sq_prec prec, int M, int N, int K, int batch, const float* A, long l
   return gemm(prec == SQ_BF16, M, N, K, batch, a, b, c, nullptr, 0, (hipStream_t)stream);
 }
 
+int sq_gemm_tile_order(int b, int gx, int gy, int gz, int* tile) {
+  if (!tile || gx <= 0 || gy <= 0 || gz <= 0 || b < 0 || (long long)gx * gy * gz > (1LL << 30) ||
+      b >= gx * gy * gz) {
+    set_error("sq_gemm_tile_order: need a grid of positive sizes, 0 <= b < gx gy gz and a tile pointer");
+    return SQ_EINVAL;
+  }
+  tile_of(b, gx, gy, gz, tile[0], tile[1], tile[2]);
+  return SQ_OK;
+}
+
 int sq_sample_indices(unsigned long long seed, unsigned int update, int size, int n, int* idx, sq_stream_t stream) {
   SQ_REQUIRE(size > 0 && n >= 0, "need size > 0 and n >= 0");
   if (n == 0) return SQ_OK;

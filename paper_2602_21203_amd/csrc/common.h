@@ -152,6 +152,24 @@ int env_step(const EnvState& E, const float* action, float* prop_t, uint8_t* nex
 // where a squint launch writes (see squint.hip)
 enum { kSqF32 = 0, kSqBF16 = 1, kSqU8 = 2 };
 struct SqDst { int mode; void* out; void* out1; long long row_stride; int pos, cap; RingRows f; };
+// Workgroup order of the linear-layer products: consecutive workgroup ids go to
+// the eight XCDs in turn, each with its own L2, so the linear id b of a
+// gx x gy x gz grid is remapped (when the tile count is a multiple of 8) to give
+// every XCD a contiguous run of tiles, in groups of 8 row tiles -- about an 8 x 8
+// block of output tiles per XCD.  A bijection onto the tiles for any grid.
+__host__ __device__ __forceinline__ void tile_of(int b, int gx, int gy, int gz, int& bx, int& by, int& bz) {
+  const int T = gx * gy * gz;
+  if (T % 8 == 0) b = (b % 8) * (T / 8) + b / 8;
+  const int per = gx * gy;
+  bz = b / per;
+  const int p = b - bz * per;
+  constexpr int GM = 8;
+  const int grp = p / (GM * gy), first = grp * GM;
+  const int gm = gx - first < GM ? gx - first : GM;
+  const int q = p - grp * GM * gy;
+  bx = first + q % gm;
+  by = q / gm;
+}
 // ring row of the i-th transition of an insertion at write position pos: (pos + i)
 // mod cap in 64-bit arithmetic (pos + i can pass 2^31 when cap is near 2^31 - 1)
 __host__ __device__ __forceinline__ int ring_row(int pos, long long i, int cap) {

@@ -235,22 +235,6 @@ struct StPart {
   }
 };
 
-// XCD-aware tile order (see the top of the file): linear workgroup id b of a
-// gx x gy x gz grid -> tile (bx, by, bz); a bijection for any grid
-__device__ __forceinline__ void tile_of(int b, int gx, int gy, int gz, int& bx, int& by, int& bz) {
-  const int T = gx * gy * gz;
-  if (T % 8 == 0) b = (b % 8) * (T / 8) + b / 8;
-  const int per = gx * gy;
-  bz = b / per;
-  const int p = b - bz * per;
-  constexpr int GM = 8;
-  const int grp = p / (GM * gy), first = grp * GM;
-  const int gm = min(gx - first, GM);
-  const int q = p - grp * GM * gy;
-  bx = first + q % gm;
-  by = q / gm;
-}
-
 // ---------------------------------------------------------------- kernel
 // Global -> register staging of one 32 x BK operand slice.  Each thread owns
 // EL = 32 * BK / 256 elements at fixed positions; all EL loads are issued back

@@ -100,3 +100,37 @@ def test_ring_rows_in_64_bit():
     row = ctypes.c_int()
     assert _lib.LIB.sq_ring_row(cap, 1, cap, ctypes.byref(row)) == _lib.SQ_EINVAL
     assert _lib.LIB.sq_ring_row(0, -1, cap, ctypes.byref(row)) == _lib.SQ_EINVAL
+
+
+def _tile_order(gx, gy, gz):
+    from paper_2602_21203_amd import _lib
+    t = (ctypes.c_int * 3)()
+    out = []
+    for b in range(gx * gy * gz):
+        assert _lib.LIB.sq_gemm_tile_order(b, gx, gy, gz, t) == _lib.SQ_OK
+        out.append(tuple(t))
+    return out
+
+
+def test_gemm_workgroup_order_is_a_bijection():
+    """Every workgroup of a product grid computes a distinct output tile and every
+    tile is computed, for grids with and without a tile count divisible by 8."""
+    for gx, gy, gz in ((16, 16, 2), (16, 16, 4), (32, 16, 1), (16, 4, 2), (4, 16, 4), (32, 1, 1), (3, 5, 1),
+                       (7, 9, 2), (17, 3, 4), (1, 1, 1), (9, 1, 8)):
+        tiles = _tile_order(gx, gy, gz)
+        assert sorted(tiles) == sorted((x, y, z) for x in range(gx) for y in range(gy) for z in range(gz)), (gx, gy, gz)
+
+
+def test_gemm_workgroup_order_gives_each_xcd_a_block():
+    """Workgroup b runs on XCD b % 8: for the twin-layer grid (16 x 16 tiles, 2
+    batches) each XCD's 64 tiles are an 8 x 8 block of one batch, so its L2 reads
+    half of that batch's A rows and half of its W rows."""
+    tiles = _tile_order(16, 16, 2)
+    for xcd in range(8):
+        mine = [tiles[b] for b in range(xcd, len(tiles), 8)]
+        assert len({z for _, _, z in mine}) == 1
+        assert len({x for x, _, _ in mine}) == 8 and len({y for _, y, _ in mine}) == 8
+    from paper_2602_21203_amd import _lib
+    t = (ctypes.c_int * 3)()
+    assert _lib.LIB.sq_gemm_tile_order(512, 16, 16, 2, t) == _lib.SQ_EINVAL
+    assert _lib.LIB.sq_gemm_tile_order(0, 0, 16, 2, t) == _lib.SQ_EINVAL
