@@ -296,6 +296,43 @@ def test_degenerate_targets_match_oracle():
         ag.close()
 
 
+@pytest.mark.parametrize("name,B,prec", [("tiny", 32, 0), ("tiny", 32, 1), ("full", 512, 1)])
+def test_silent_heads_update_matches_its_closed_form(name, B, prec):
+    """Zero twin critic heads and all-terminal transitions: the GPU update against
+    the closed form the oracle is pinned to (critic loss 2 log N, mean Q the mean
+    atom, mean target the mean reward, head-bias gradient 1/N - mean two-hot(r),
+    every other critic and encoder gradient exactly zero), in FP32 and BF16 (the
+    zero heads make every logit exactly zero in both)."""
+    from tests.test_oracle_sac import silent_heads_case, silent_heads_closed_form
+    d = H.odims(name)
+    cap = 256
+    params, rep_np = silent_heads_case(d, cap)
+    rep = {k: (torch.as_tensor(v).cuda() if isinstance(v, np.ndarray) else v) for k, v in rep_np.items()}
+    hp = sac.hparams(d)
+    rows = philox.sample_indices(hp.seed, 0, cap, B)
+    blk = olayout.blocks(d)
+    cf = silent_heads_closed_form(d, rep_np, rows, float(np.exp(params[blk["log_alpha"][0]])))
+    ag = api.Agent(H.cfg(name), params.astype(np.float32), B, prec=prec)
+    s = ag.sac_update(rep, 1).cpu().numpy()[0].astype(np.float64)
+    np.testing.assert_array_equal(ag.last_indices().cpu().numpy(), rows)
+    g = ag.grads.cpu().numpy().astype(np.float64)
+    ag.close()
+    print(f"  {name} B={B} prec={prec}: loss {s[0]:.9g} (2 log N {cf['loss']:.9g}), mean Q {s[5]:.3g}, "
+          f"mean target {s[6]:.9g} ({cf['mean_target']:.9g})")
+    assert abs(s[0] - cf["loss"]) <= 1e-6 * cf["loss"]
+    assert abs(s[5] - cf["mean_q"]) <= 1e-6 * (abs(d.v_min) + abs(d.v_max))
+    assert abs(s[6] - cf["mean_target"]) <= 1e-6
+    assert abs(s[2] - cf["alpha0"] * (s[4] - hp.target_entropy)) <= 1e-5 * abs(s[2]) + 1e-7
+    for n, (off, shp) in olayout.offsets(d)[0].items():
+        if off >= blk["critic"][1]:
+            continue
+        k = int(np.prod(shp))
+        if n in ("q1.out.b", "q2.out.b"):
+            np.testing.assert_allclose(g[off:off + k], cf["g_bias"], rtol=0, atol=1e-6, err_msg=n)
+        elif n not in ("q1.out.W", "q2.out.W"):
+            assert np.all(g[off:off + k] == 0.0), n
+
+
 @pytest.mark.parametrize("name,B,cap", [("tiny", 32, 4096), ("full", 512, 2048), ("state", 512, 2048)])
 def test_utd_block_matches_oracle(name, B, cap):
     """Alg. 1's inner loop inside captured graphs, against the oracle's updates

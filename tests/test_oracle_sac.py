@@ -211,3 +211,65 @@ def test_nan_reward_makes_the_update_non_finite():
     assert np.isnan(o["m"][0]).all() and np.isfinite(o["m"][1:]).all()
     assert o["stats"][7] == 1.0 and np.isnan(o["stats"][0]) and np.isnan(o["stats"][6])
     assert np.isfinite(o["stats"][[2, 3, 4, 5]]).all()
+
+
+def silent_heads_case(d, cap=256, seed=1):
+    """Parameters whose twin critic heads (weights and biases, online and hence
+    the target copy) are zero, and a replay whose transitions are all terminal."""
+    params = synthetic.init_params(table(d), seed=seed).astype(np.float64)
+    offs = layout.offsets(d)[0]
+    for n in ("q1.out.W", "q1.out.b", "q2.out.W", "q2.out.b"):
+        o, shp = offs[n]
+        params[o:o + int(np.prod(shp))] = 0.0
+    rep = np_replay(d, cap)
+    rep["done"] = np.ones_like(rep["done"])
+    return params, rep
+
+
+def silent_heads_closed_form(d, rep, rows, alpha0):
+    """What one update must give when every critic logit is zero (uniform softmax
+    p = 1/N) and every transition is terminal (the shifted support collapses to
+    r, so the projected target is the two-hot of r): critic loss = 2 log N (twin
+    cross entropies summed, batch mean); mean Q = mean of the atoms; mean target
+    = mean r; head-bias gradient of each twin = 1/N - mean_b two-hot(r_b); every
+    other critic and encoder gradient zero (the heads pass nothing back)."""
+    N = d.atoms
+    z = np.linspace(d.v_min, d.v_max, N)
+    r = rep["reward"][rows].astype(np.float64)
+    b = (np.clip(r, d.v_min, d.v_max) - d.v_min) / ((d.v_max - d.v_min) / (N - 1))
+    two_hot = np.maximum(0.0, 1.0 - np.abs(b[:, None] - np.arange(N)[None, :]))
+    return dict(loss=2.0 * math.log(N), mean_q=float(z.mean()), mean_target=float(r.mean()),
+                g_bias=1.0 / N - two_hot.mean(axis=0), alpha0=alpha0)
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "full"])
+def test_whole_update_closed_form_with_silent_heads(cfg):
+    """The composition of one whole update on a case with a closed form (see
+    silent_heads_closed_form); also the temperature loss from the update's own
+    entropy statistic: loss_alpha = alpha (entropy - target entropy).  (The actor
+    loss has no closed form here: the actor scores its actions with the critic
+    after its step, whose heads are no longer zero.)"""
+    from paper_2602_21203_amd import configs
+    d = layout.dims(**configs.CONFIGS[cfg])
+    params, rep = silent_heads_case(d)
+    hp = sac.hparams(d)
+    B = 32
+    st = sac.new_state(d, params)
+    rows = philox.sample_indices(hp.seed, 0, 256, B)
+    cf = silent_heads_closed_form(d, rep, rows, float(np.exp(params[layout.blocks(d)["log_alpha"][0]])))
+    o = sac.sac_update(st, rep, d, hp, B)
+    s = o["stats"]
+    assert abs(s[0] - cf["loss"]) <= 1e-12 * cf["loss"]
+    assert abs(s[5] - cf["mean_q"]) <= 1e-12 * (abs(d.v_min) + abs(d.v_max))
+    assert abs(s[6] - cf["mean_target"]) <= 1e-12
+    assert abs(s[2] - cf["alpha0"] * (s[4] - hp.target_entropy)) <= 1e-12 * abs(s[2]) + 1e-15
+    g = o["g_enc_critic"]
+    offs = layout.offsets(d)[0]
+    for n, (off, shp) in offs.items():
+        if off >= layout.blocks(d)["critic"][1]:
+            continue
+        k = int(np.prod(shp))
+        if n in ("q1.out.b", "q2.out.b"):
+            np.testing.assert_allclose(g[off:off + k], cf["g_bias"], rtol=0, atol=1e-14)
+        elif n not in ("q1.out.W", "q2.out.W"):
+            assert np.all(g[off:off + k] == 0.0), n
