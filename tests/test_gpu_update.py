@@ -298,12 +298,13 @@ def test_degenerate_targets_match_oracle():
 
 @pytest.mark.parametrize("name,B,prec", [("tiny", 32, 0), ("tiny", 32, 1), ("full", 512, 1)])
 def test_silent_heads_update_matches_its_closed_form(name, B, prec):
-    """Zero twin critic heads and all-terminal transitions: the GPU update against
-    the closed form the oracle is pinned to (critic loss 2 log N, mean Q the mean
-    atom, mean target the mean reward, head-bias gradient 1/N - mean two-hot(r),
-    every other critic and encoder gradient exactly zero), in FP32 and BF16 (the
-    zero heads make every logit exactly zero in both)."""
-    from tests.test_oracle_sac import silent_heads_case, silent_heads_closed_form
+    """Zero twin critic heads, a constant actor head and all-terminal transitions:
+    the GPU update against the closed form the oracle is pinned to (critic loss
+    2 log N, mean Q the mean atom, mean target the mean reward, head-bias gradient
+    1/N - mean two-hot(r), every other critic and encoder gradient exactly zero,
+    the entropy of the constant head at the update's policy noise), in FP32 and
+    BF16 (the zero head weights make the logits and the actor head exact in both)."""
+    from tests.test_oracle_sac import head_entropy, silent_heads_case, silent_heads_closed_form
     d = H.odims(name)
     cap = 256
     params, rep_np = silent_heads_case(d, cap)
@@ -322,7 +323,9 @@ def test_silent_heads_update_matches_its_closed_form(name, B, prec):
     assert abs(s[0] - cf["loss"]) <= 1e-6 * cf["loss"]
     assert abs(s[5] - cf["mean_q"]) <= 1e-6 * (abs(d.v_min) + abs(d.v_max))
     assert abs(s[6] - cf["mean_target"]) <= 1e-6
-    assert abs(s[2] - cf["alpha0"] * (s[4] - hp.target_entropy)) <= 1e-5 * abs(s[2]) + 1e-7
+    ent = head_entropy(d, hp, B)
+    assert abs(s[4] - ent) <= 1e-5 * abs(ent)
+    assert abs(s[2] - cf["alpha0"] * (ent - hp.target_entropy)) <= 1e-5 * abs(s[2]) + 1e-7
     for n, (off, shp) in olayout.offsets(d)[0].items():
         if off >= blk["critic"][1]:
             continue

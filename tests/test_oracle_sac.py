@@ -213,17 +213,37 @@ def test_nan_reward_makes_the_update_non_finite():
     assert np.isfinite(o["stats"][[2, 3, 4, 5]]).all()
 
 
+HEAD_MU, HEAD_US = 0.3, -0.4   # the actor head's constant outputs in the closed-form case
+
+
 def silent_heads_case(d, cap=256, seed=1):
     """Parameters whose twin critic heads (weights and biases, online and hence
-    the target copy) are zero, and a replay whose transitions are all terminal."""
+    the target copy) are zero and whose actor head has zero weights (every row's
+    head output is its bias: mu = HEAD_MU, u_sigma = HEAD_US), and a replay whose
+    transitions are all terminal."""
     params = synthetic.init_params(table(d), seed=seed).astype(np.float64)
     offs = layout.offsets(d)[0]
-    for n in ("q1.out.W", "q1.out.b", "q2.out.W", "q2.out.b"):
+    for n in ("q1.out.W", "q1.out.b", "q2.out.W", "q2.out.b", "actor.out.W"):
         o, shp = offs[n]
         params[o:o + int(np.prod(shp))] = 0.0
+    o, _ = offs["actor.out.b"]
+    params[o:o + d.action] = HEAD_MU
+    params[o + d.action:o + 2 * d.action] = HEAD_US
     rep = np_replay(d, cap)
     rep["done"] = np.ones_like(rep["done"])
     return params, rep
+
+
+def head_entropy(d, hp, B):
+    """The update's entropy statistic, -mean log pi over the batch, when every
+    row's head is (HEAD_MU, HEAD_US): the tanh-Gaussian density (Eq. (3)) at the
+    policy noise of the sample at s_t (Philox stream 2 of update 0), written out
+    with log(1 - tanh^2 u) taken directly."""
+    eps = philox.gaussian(hp.seed, 0, 2, B * d.action).reshape(B, d.action)
+    log_sigma = hp.log_std_min + 0.5 * (hp.log_std_max - hp.log_std_min) * (math.tanh(HEAD_US) + 1.0)
+    u = HEAD_MU + math.exp(log_sigma) * eps
+    logp = np.sum(-0.5 * eps ** 2 - 0.5 * math.log(2.0 * math.pi) - log_sigma - np.log(1.0 - np.tanh(u) ** 2), axis=1)
+    return float(-np.mean(logp))
 
 
 def silent_heads_closed_form(d, rep, rows, alpha0):
@@ -245,10 +265,10 @@ def silent_heads_closed_form(d, rep, rows, alpha0):
 @pytest.mark.parametrize("cfg", ["tiny", "full"])
 def test_whole_update_closed_form_with_silent_heads(cfg):
     """The composition of one whole update on a case with a closed form (see
-    silent_heads_closed_form); also the temperature loss from the update's own
-    entropy statistic: loss_alpha = alpha (entropy - target entropy).  (The actor
-    loss has no closed form here: the actor scores its actions with the critic
-    after its step, whose heads are no longer zero.)"""
+    silent_heads_closed_form and head_entropy), and the temperature loss from it:
+    loss_alpha = alpha (entropy - target entropy).  (The actor loss has no closed
+    form here: the actor scores its actions with the critic after its step, whose
+    heads are no longer zero.)"""
     from paper_2602_21203_amd import configs
     d = layout.dims(**configs.CONFIGS[cfg])
     params, rep = silent_heads_case(d)
@@ -262,7 +282,9 @@ def test_whole_update_closed_form_with_silent_heads(cfg):
     assert abs(s[0] - cf["loss"]) <= 1e-12 * cf["loss"]
     assert abs(s[5] - cf["mean_q"]) <= 1e-12 * (abs(d.v_min) + abs(d.v_max))
     assert abs(s[6] - cf["mean_target"]) <= 1e-12
-    assert abs(s[2] - cf["alpha0"] * (s[4] - hp.target_entropy)) <= 1e-12 * abs(s[2]) + 1e-15
+    ent = head_entropy(d, hp, B)
+    assert abs(s[4] - ent) <= 1e-12 * abs(ent)
+    assert abs(s[2] - cf["alpha0"] * (ent - hp.target_entropy)) <= 1e-12 * abs(s[2]) + 1e-15
     g = o["g_enc_critic"]
     offs = layout.offsets(d)[0]
     for n, (off, shp) in offs.items():
