@@ -298,22 +298,24 @@ def test_degenerate_targets_match_oracle():
 
 @pytest.mark.parametrize("name,B,prec", [("tiny", 32, 0), ("tiny", 32, 1), ("full", 512, 1)])
 def test_silent_heads_update_matches_its_closed_form(name, B, prec):
-    """Zero twin critic heads, a constant actor head and all-terminal transitions:
-    the GPU update against the closed form the oracle is pinned to (critic loss
-    2 log N, mean Q the mean atom, mean target the mean reward, head-bias gradient
-    1/N - mean two-hot(r), every other critic and encoder gradient exactly zero,
-    the entropy of the constant head at the update's policy noise), in FP32 and
-    BF16 (the zero head weights make the logits and the actor head exact in both)."""
-    from tests.test_oracle_sac import head_entropy, silent_heads_case, silent_heads_closed_form
+    """Zero twin critic heads, a constant actor head, all-terminal transitions and
+    lr = 0: the GPU update against the closed form the oracle is pinned to (critic
+    loss 2 log N, mean Q the mean atom, mean target the mean reward, head-bias
+    gradient 1/N - mean two-hot(r), every other critic and encoder gradient
+    exactly zero, the entropy of the constant head at the update's policy noise,
+    the actor loss and the actor head-bias gradient, every other actor gradient
+    exactly zero), in FP32 and BF16 (the zero head weights make the logits and the
+    actor head exact in both)."""
+    from tests.test_oracle_sac import head_closed_form, head_entropy, silent_heads_case, silent_heads_closed_form
     d = H.odims(name)
     cap = 256
     params, rep_np = silent_heads_case(d, cap)
     rep = {k: (torch.as_tensor(v).cuda() if isinstance(v, np.ndarray) else v) for k, v in rep_np.items()}
-    hp = sac.hparams(d)
+    hp = sac.hparams(d, lr=0.0)
     rows = philox.sample_indices(hp.seed, 0, cap, B)
     blk = olayout.blocks(d)
     cf = silent_heads_closed_form(d, rep_np, rows, float(np.exp(params[blk["log_alpha"][0]])))
-    ag = api.Agent(H.cfg(name), params.astype(np.float32), B, prec=prec)
+    ag = api.Agent(H.cfg(name), params.astype(np.float32), B, prec=prec, lr=0.0)
     s = ag.sac_update(rep, 1).cpu().numpy()[0].astype(np.float64)
     np.testing.assert_array_equal(ag.last_indices().cpu().numpy(), rows)
     g = ag.grads.cpu().numpy().astype(np.float64)
@@ -326,6 +328,17 @@ def test_silent_heads_update_matches_its_closed_form(name, B, prec):
     ent = head_entropy(d, hp, B)
     assert abs(s[4] - ent) <= 1e-5 * abs(ent)
     assert abs(s[2] - cf["alpha0"] * (ent - hp.target_entropy)) <= 1e-5 * abs(s[2]) + 1e-7
+    # lr = 0: the actor loss and the actor gradient against the still-silent critic
+    assert abs(s[1] - (-cf["alpha0"] * ent - cf["mean_q"])) <= 1e-5 * abs(cf["alpha0"] * ent)
+    for n, (off, shp) in olayout.offsets(d)[0].items():
+        if not n.startswith("actor."):
+            continue
+        k = int(np.prod(shp))
+        if n == "actor.out.b":
+            ref = head_closed_form(d, hp, B, cf["alpha0"])
+            assert H.rel_norm(g[off:off + k], ref) <= 1e-5, n
+        elif n != "actor.out.W":
+            assert np.all(g[off:off + k] == 0.0), n
     for n, (off, shp) in olayout.offsets(d)[0].items():
         if off >= blk["critic"][1]:
             continue

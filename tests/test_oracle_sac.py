@@ -234,6 +234,22 @@ def silent_heads_case(d, cap=256, seed=1):
     return params, rep
 
 
+def head_closed_form(d, hp, B, alpha):
+    """With zero critic heads the critics' expected value is the mean atom for
+    every action, so with lr = 0 (the critic still silent after its step) the
+    actor loss is alpha mean(log pi) - mean atom and its gradient reaches only
+    the actor head's bias: d log pi / d mu = 2 tanh u per dimension, and
+    d log pi / d u_sigma = (-1 + 2 tanh(u) sigma eps) (hi - lo)/2 (1 - tanh^2 u_sigma),
+    each scaled by alpha / B and summed over the batch."""
+    eps = philox.gaussian(hp.seed, 0, 2, B * d.action).reshape(B, d.action)
+    lo, hi = hp.log_std_min, hp.log_std_max
+    sigma = math.exp(lo + 0.5 * (hi - lo) * (math.tanh(HEAD_US) + 1.0))
+    t = np.tanh(HEAD_MU + sigma * eps)
+    g_mu = alpha / B * np.sum(2.0 * t, axis=0)
+    g_us = alpha / B * np.sum(-1.0 + 2.0 * t * sigma * eps, axis=0) * 0.5 * (hi - lo) * (1.0 - math.tanh(HEAD_US) ** 2)
+    return np.concatenate([g_mu, g_us])
+
+
 def head_entropy(d, hp, B):
     """The update's entropy statistic, -mean log pi over the batch, when every
     row's head is (HEAD_MU, HEAD_US): the tanh-Gaussian density (Eq. (3)) at the
@@ -265,15 +281,16 @@ def silent_heads_closed_form(d, rep, rows, alpha0):
 @pytest.mark.parametrize("cfg", ["tiny", "full"])
 def test_whole_update_closed_form_with_silent_heads(cfg):
     """The composition of one whole update on a case with a closed form (see
-    silent_heads_closed_form and head_entropy), and the temperature loss from it:
-    loss_alpha = alpha (entropy - target entropy).  (The actor loss has no closed
-    form here: the actor scores its actions with the critic after its step, whose
-    heads are no longer zero.)"""
+    silent_heads_closed_form, head_entropy and head_closed_form): the critic
+    statistics and gradients, the entropy and the temperature loss
+    alpha (entropy - target entropy), and, with lr = 0 so that the critic the
+    actor scores against is still silent, the actor loss and gradient."""
     from paper_2602_21203_amd import configs
     d = layout.dims(**configs.CONFIGS[cfg])
     params, rep = silent_heads_case(d)
-    hp = sac.hparams(d)
+    hp = sac.hparams(d, lr=0.0)
     B = 32
+    offs = layout.offsets(d)[0]
     st = sac.new_state(d, params)
     rows = philox.sample_indices(hp.seed, 0, 256, B)
     cf = silent_heads_closed_form(d, rep, rows, float(np.exp(params[layout.blocks(d)["log_alpha"][0]])))
@@ -285,8 +302,21 @@ def test_whole_update_closed_form_with_silent_heads(cfg):
     ent = head_entropy(d, hp, B)
     assert abs(s[4] - ent) <= 1e-12 * abs(ent)
     assert abs(s[2] - cf["alpha0"] * (ent - hp.target_entropy)) <= 1e-12 * abs(s[2]) + 1e-15
+    # lr = 0: the actor loss and gradient against the silent critic
+    assert s[3] == cf["alpha0"]
+    assert abs(s[1] - (-cf["alpha0"] * ent - cf["mean_q"])) <= 1e-12 * abs(cf["alpha0"] * ent)
+    ga = o["g_actor"]
+    a0 = layout.blocks(d)["actor"][0]
+    for n, (off, shp) in offs.items():
+        if not n.startswith("actor."):
+            continue
+        k = int(np.prod(shp))
+        if n == "actor.out.b":
+            np.testing.assert_allclose(ga[off - a0:off - a0 + k], head_closed_form(d, hp, B, cf["alpha0"]), rtol=1e-12,
+                                       atol=1e-15)
+        elif n != "actor.out.W":
+            assert np.all(ga[off - a0:off - a0 + k] == 0.0), n
     g = o["g_enc_critic"]
-    offs = layout.offsets(d)[0]
     for n, (off, shp) in offs.items():
         if off >= layout.blocks(d)["critic"][1]:
             continue
