@@ -349,6 +349,31 @@ def test_silent_heads_update_matches_its_closed_form(name, B, prec):
             assert np.all(g[off:off + k] == 0.0), n
 
 
+@pytest.mark.parametrize("name,B,prec", [("tiny", 32, 0), ("full", 512, 1)])
+def test_silent_heads_soft_target_matches_its_closed_form(name, B, prec):
+    """Non-terminal transitions, silent critic heads, gamma = 1/4: the mean target
+    is mean_b (r_b + gamma (mean z - alpha log pi'_b)) with log pi' the constant
+    actor head's density at the noise of the sample at s_t+1 (the closed form the
+    oracle is pinned to), and the critic loss 2 log N."""
+    from tests.test_oracle_sac import head_logp, silent_heads_case
+    d = H.odims(name)
+    cap = 256
+    params, rep_np = silent_heads_case(d, cap, terminal=False)
+    rep = {k: (torch.as_tensor(v).cuda() if isinstance(v, np.ndarray) else v) for k, v in rep_np.items()}
+    hp = sac.hparams(d, gamma=0.25)
+    rows = philox.sample_indices(hp.seed, 0, cap, B)
+    alpha0 = float(np.exp(params[olayout.blocks(d)["log_alpha"][0]]))
+    r = rep_np["reward"][rows].astype(np.float64)
+    z = np.linspace(d.v_min, d.v_max, d.atoms)
+    want = float(np.mean(r + hp.gamma * (z.mean() - alpha0 * head_logp(d, hp, B, 1))))
+    ag = api.Agent(H.cfg(name), params.astype(np.float32), B, prec=prec, gamma=0.25)
+    s = ag.sac_update(rep, 1).cpu().numpy()[0].astype(np.float64)
+    ag.close()
+    print(f"  {name} B={B} prec={prec}: mean target {s[6]:.9g} (closed form {want:.9g}), loss {s[0]:.9g}")
+    assert abs(s[6] - want) <= 1e-5 * (abs(want) + 1.0)
+    assert abs(s[0] - 2.0 * math.log(d.atoms)) <= 1e-6 * s[0]
+
+
 @pytest.mark.parametrize("name,B,cap", [("tiny", 32, 4096), ("full", 512, 2048), ("state", 512, 2048)])
 def test_utd_block_matches_oracle(name, B, cap):
     """Alg. 1's inner loop inside captured graphs, against the oracle's updates

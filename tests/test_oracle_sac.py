@@ -216,7 +216,7 @@ def test_nan_reward_makes_the_update_non_finite():
 HEAD_MU, HEAD_US = 0.3, -0.4   # the actor head's constant outputs in the closed-form case
 
 
-def silent_heads_case(d, cap=256, seed=1):
+def silent_heads_case(d, cap=256, seed=1, terminal=True):
     """Parameters whose twin critic heads (weights and biases, online and hence
     the target copy) are zero and whose actor head has zero weights (every row's
     head output is its bias: mu = HEAD_MU, u_sigma = HEAD_US), and a replay whose
@@ -230,8 +230,19 @@ def silent_heads_case(d, cap=256, seed=1):
     params[o:o + d.action] = HEAD_MU
     params[o + d.action:o + 2 * d.action] = HEAD_US
     rep = np_replay(d, cap)
-    rep["done"] = np.ones_like(rep["done"])
+    rep["done"] = np.ones_like(rep["done"]) if terminal else np.zeros_like(rep["done"])
     return params, rep
+
+
+def head_logp(d, hp, B, stream):
+    """log pi of every row when every head is (HEAD_MU, HEAD_US): the
+    tanh-Gaussian density (Eq. (3)) at the policy noise of Philox stream
+    `stream` of update 0 (2: the sample at s_t, 1: at s_t+1), written out with
+    log(1 - tanh^2 u) taken directly."""
+    eps = philox.gaussian(hp.seed, 0, stream, B * d.action).reshape(B, d.action)
+    log_sigma = hp.log_std_min + 0.5 * (hp.log_std_max - hp.log_std_min) * (math.tanh(HEAD_US) + 1.0)
+    u = HEAD_MU + math.exp(log_sigma) * eps
+    return np.sum(-0.5 * eps ** 2 - 0.5 * math.log(2.0 * math.pi) - log_sigma - np.log(1.0 - np.tanh(u) ** 2), axis=1)
 
 
 def head_closed_form(d, hp, B, alpha):
@@ -251,15 +262,8 @@ def head_closed_form(d, hp, B, alpha):
 
 
 def head_entropy(d, hp, B):
-    """The update's entropy statistic, -mean log pi over the batch, when every
-    row's head is (HEAD_MU, HEAD_US): the tanh-Gaussian density (Eq. (3)) at the
-    policy noise of the sample at s_t (Philox stream 2 of update 0), written out
-    with log(1 - tanh^2 u) taken directly."""
-    eps = philox.gaussian(hp.seed, 0, 2, B * d.action).reshape(B, d.action)
-    log_sigma = hp.log_std_min + 0.5 * (hp.log_std_max - hp.log_std_min) * (math.tanh(HEAD_US) + 1.0)
-    u = HEAD_MU + math.exp(log_sigma) * eps
-    logp = np.sum(-0.5 * eps ** 2 - 0.5 * math.log(2.0 * math.pi) - log_sigma - np.log(1.0 - np.tanh(u) ** 2), axis=1)
-    return float(-np.mean(logp))
+    """The update's entropy statistic, -mean log pi of the sample at s_t."""
+    return float(-np.mean(head_logp(d, hp, B, 2)))
 
 
 def silent_heads_closed_form(d, rep, rows, alpha0):
@@ -276,6 +280,34 @@ def silent_heads_closed_form(d, rep, rows, alpha0):
     two_hot = np.maximum(0.0, 1.0 - np.abs(b[:, None] - np.arange(N)[None, :]))
     return dict(loss=2.0 * math.log(N), mean_q=float(z.mean()), mean_target=float(r.mean()),
                 g_bias=1.0 / N - two_hot.mean(axis=0), alpha0=alpha0)
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "full"])
+def test_soft_target_closed_form_with_silent_heads(cfg):
+    """Non-terminal transitions with silent critic heads: the averaged target
+    softmax is uniform, so the target distribution is the uniform one over the
+    shifted, discounted atoms r + gamma (z - alpha log pi'), projected.  With
+    gamma = 1/4 no shifted atom leaves the support, so the projection keeps the
+    mean: mean target = mean_b (r_b + gamma (mean z - alpha log pi'_b)), with
+    log pi' the constant head's density at the noise of the sample at s_t+1
+    (Philox stream 1).  The cross entropy of uniform logits is still log N per twin."""
+    from paper_2602_21203_amd import configs
+    d = layout.dims(**configs.CONFIGS[cfg])
+    params, rep = silent_heads_case(d, terminal=False)
+    hp = sac.hparams(d, gamma=0.25)
+    B = 32
+    rows = philox.sample_indices(hp.seed, 0, 256, B)
+    alpha0 = float(np.exp(params[layout.blocks(d)["log_alpha"][0]]))
+    r = rep["reward"][rows].astype(np.float64)
+    z = np.linspace(d.v_min, d.v_max, d.atoms)
+    logp_next = head_logp(d, hp, B, 1)
+    shifted = r[:, None] + hp.gamma * (z[None, :] - alpha0 * logp_next[:, None])
+    assert shifted.min() > d.v_min and shifted.max() < d.v_max   # nothing clips
+    o = sac.sac_update(sac.new_state(d, params), rep, d, hp, B)
+    s = o["stats"]
+    want = float(np.mean(r + hp.gamma * (z.mean() - alpha0 * logp_next)))
+    assert abs(s[6] - want) <= 1e-12 * (abs(want) + 1.0)
+    assert abs(s[0] - 2.0 * math.log(d.atoms)) <= 1e-12 * s[0]
 
 
 @pytest.mark.parametrize("cfg", ["tiny", "full"])
