@@ -704,21 +704,21 @@ __global__ __launch_bounds__(kThreads) void k_gemm_r(RMat fa, RMat fb, ST st, St
 }
 
 // Two independent products in one launch (the input and weight gradients of one
-// layer): workgroups [0, tiles0) take problem 0 (row-coalesced A, k-strided B),
-// the rest problem 1 (both k-strided).
+// layer): workgroups [0, tiles0) take problem 0 (A row-coalesced when AV0, else
+// k-strided; k-strided B), the rest problem 1 (both k-strided).
 struct RProb {
   RMat a, b; StMat st; int M, N, K, gx, gy;
 };
 
-template <bool BF16>
+template <bool BF16, int AV0>
 __global__ __launch_bounds__(kThreads) void k_gemm_pair(RProb p0, RProb p1, int tiles0) {
-  constexpr int L0 = gemm_lds_bytes<BF16, 1, 0>(), L1 = gemm_lds_bytes<BF16, 0, 0>();
+  constexpr int L0 = gemm_lds_bytes<BF16, AV0, 0>(), L1 = gemm_lds_bytes<BF16, 0, 0>();
   __shared__ __attribute__((aligned(16))) char lds[L0 > L1 ? L0 : L1];
   const StPart none{nullptr, 0, 0, 1};
   int b = blockIdx.x;
   if (b < tiles0) {
-    gemm_tile<BF16, 1, 0, StMat, false>(p0.a, p0.b, p0.st, none, p0.M, p0.N, p0.K, p0.K, b % p0.gx,
-                                        (b / p0.gx) % p0.gy, b / (p0.gx * p0.gy), lds);
+    gemm_tile<BF16, AV0, 0, StMat, false>(p0.a, p0.b, p0.st, none, p0.M, p0.N, p0.K, p0.K, b % p0.gx,
+                                          (b / p0.gx) % p0.gy, b / (p0.gx * p0.gy), lds);
   } else {
     b -= tiles0;
     gemm_tile<BF16, 0, 0, StMat, false>(p1.a, p1.b, p1.st, none, p1.M, p1.N, p1.K, p1.K, b % p1.gx,
@@ -917,7 +917,7 @@ int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, 
               hipStream_t st) {
   const bool e0 = p0.M <= 0 || p0.N <= 0 || p0.batch <= 0, e1 = p1.M <= 0 || p1.N <= 0 || p1.batch <= 0;
   // (input gradient, weight gradient) of a layer, or two forward products
-  const bool grad_kinds = rkind(p0.A) == 1 && rkind(p0.B) == 0 && rkind(p1.A) == 0 && rkind(p1.B) == 0;
+  const bool grad_kinds = rkind(p0.B) == 0 && rkind(p1.A) == 0 && rkind(p1.B) == 0;
   const bool fwd_kinds = rkind(p0.A) == 1 && rkind(p0.B) == 1 && rkind(p1.A) == 1 && rkind(p1.B) == 1;
   const bool kinds = grad_kinds || fwd_kinds;
   const bool nosplit = want_splits(p0.M, p0.N, p0.K, p0.batch, scratch, scratch_floats) == 1 &&
@@ -935,8 +935,11 @@ int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, 
     if (bf16) k_gemm_pair_f<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
     else k_gemm_pair_f<false><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
   } else {
-    if (bf16) k_gemm_pair<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
-    else k_gemm_pair<false><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+    const int av0 = rkind(p0.A);
+    if (bf16 && av0) k_gemm_pair<true, 1><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+    else if (bf16) k_gemm_pair<true, 0><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+    else if (av0) k_gemm_pair<false, 1><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
+    else k_gemm_pair<false, 0><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
   }
   return launch_status("gemm_pair");
 }
