@@ -222,16 +222,20 @@ def re_search(pat, text, groups=False):
 def gemm_kernel_time(prec, reps):
     """Average duration of the largest linear-layer product of the update -- the
     twin critics' second hidden layer, C[2, 512, 512] = A[2, 512, 512] W[2]^T + b
-    -- launched alone with the same kernel, shapes and operand layouts."""
+    -- launched alone with the same kernel, shapes and operand layouts (in the
+    bfloat16 mode the update's forward products read bfloat16 copies of A and W)."""
     import torch
 
-    from paper_2602_21203_amd import api
+    from paper_2602_21203_amd import _lib, api
     g = torch.Generator(device="cuda")
     g.manual_seed(5)
     A = torch.rand((2, 512, 512), generator=g, device="cuda")
     W = torch.rand((2, 512, 512), generator=g, device="cuda") - 0.5
     b = torch.rand((2, 512), generator=g, device="cuda")
     C = torch.empty((2, 512, 512), device="cuda")
+    if prec == _lib.SQ_BF16:
+        Ah, Wh = A.to(torch.bfloat16), W.to(torch.bfloat16)
+        return graph_time(lambda: api.gemm_bf16(Ah, Wh, C, bias=b), reps)
     return graph_time(lambda: api.gemm(prec, A, W, C, bias=b), reps)
 
 
@@ -675,7 +679,10 @@ def main():
     flops = 2 * 2 * 512 * 512 * 512
     peak = 2500.0 if a.prec == "bf16" else 157.3
     ach = flops / t_g / 1e12
-    result["roofline"] = {"kernel": "k_gemm_r (twin critic layer 2 forward, 2 x 512x512x512)", "bound": "mfma",
+    bf = a.prec == "bf16"
+    result["roofline"] = {"kernel": "k_gemm_h (twin critic layer 2 forward on bfloat16 operand copies, "
+                                    "2 x 512x512x512)" if bf else
+                                    "k_gemm_r (twin critic layer 2 forward, 2 x 512x512x512)", "bound": "mfma",
                           "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 5),
                           "traffic": measured_traffic("gemm_twin_l2_fwd_bf16", "paper_2602_21203_amd/csrc/kernels/gemm.hip")
                           if a.prec == "bf16" else None,
@@ -685,7 +692,8 @@ def main():
                           "avg_us": round(t_g * 1e6, 3), "algorithmic_flops": flops,
                           "method": "achieved = algorithmic FLOP per launch / avg_us, the start-to-start period of "
                                     "back-to-back launches replayed from a HIP graph (HIP events on the launch stream)",
-                          "algorithmic_bytes": 3 * 2 * 512 * 512 * 4 + 2 * 512 * 4,
+                          # A and W (bfloat16 copies, or FP32), C in FP32, the bias
+                          "algorithmic_bytes": 2 * 2 * 512 * 512 * (2 if bf else 4) + 2 * 512 * 512 * 4 + 2 * 512 * 4,
                           "profiled": profiled_figure("gemm_twin_l2_fwd_bf16",
                                                       "paper_2602_21203_amd/csrc/kernels/gemm.hip", flops, peak, 1e12)
                           if a.prec == "bf16" else None}

@@ -398,6 +398,25 @@ SQ_API int sq_ring_row(int pos, long long i, int capacity, int* row);
  * linear-layer product grid computes (the XCD-aware order the product kernels
  * use).  [host] */
 SQ_API int sq_gemm_tile_order(int b, int gx, int gy, int gz, int* tile);
+/* bfloat16 operand copies.  With on = 1 (the default), an agent created in the
+ * bfloat16 mode keeps bfloat16 copies of its packed weights and of the
+ * activations its forward products read, written by their producers, and those
+ * products read the copies: the same results, half the operand bytes.  With 0,
+ * agents created afterwards keep none and their products round the FP32
+ * operands.  Returns the previous setting.  [host] */
+SQ_API int sq_bf16_operand_copies(int on);
+/* Linear-layer products enqueued on bfloat16 copies so far in this process
+ * (launches recorded into a graph count once, at capture).  [host] */
+SQ_API int sq_bf16_copy_products(long long* n);
+/* C[z] = A[z] B[z]^T (+ bias[z*bias_sz + c]) on bfloat16 operands (bit patterns):
+ * A [batch][M] rows of a_lr elements, B [batch][N] rows of b_lr elements,
+ * k-contiguous, 16-byte aligned, rows at least K rounded up to 8 long, batches
+ * a_sz / b_sz elements apart.  The kernel the bfloat16 forward products run;
+ * FP32 accumulation in the order of sq_gemm's bfloat16 mode, so C equals
+ * sq_gemm's result on the FP32 values of A and B. */
+SQ_API int sq_gemm_bf16(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_sz,
+                        const uint16_t* B, long long b_lr, long long b_sz, float* C, long long ldc, long long c_sz,
+                        const float* bias, long long bias_sz, sq_stream_t stream);
 /* idx[b] = mulhi32(Philox4x32_10(ctr = (update, 0, b, 0), key = seed).w0, size). */
 SQ_API int sq_sample_indices(unsigned long long seed, unsigned int update, int size, int n, int* idx,
                       sq_stream_t stream);

@@ -192,6 +192,56 @@ def gemm(prec, A, B, C=None, bias=None, accumulate=False, transpose_b=True, stre
     return C
 
 
+def _bf16_operand(t, name):
+    t3 = t if t.dim() == 3 else t.unsqueeze(0)
+    if t3.dtype != torch.bfloat16 or not t3.is_cuda or t3.stride(2) != 1:
+        raise ValueError(f"{name}: bfloat16 device tensor with k-contiguous rows expected")
+    batch, rows, K = t3.shape
+    lr, sz = t3.stride(1), (t3.stride(0) if batch > 1 else 0)
+    k8 = (K + 7) // 8 * 8
+    need = t3.storage_offset() + (batch - 1) * sz + (rows - 1) * lr + k8
+    if lr % 8 or sz % 8 or lr < k8 or need > t3.untyped_storage().nbytes() // 2:
+        raise ValueError(f"{name}: rows must be 16-byte aligned and hold K rounded up to 8 elements")
+    return t3, lr, sz
+
+
+def gemm_bf16(A, B, C=None, bias=None, stream=None):
+    """C[z] = A[z] @ B[z]^T (+ bias) on bfloat16 operands (A [batch, M, K], B [batch, N, K],
+    k-contiguous rows that hold K rounded up to 8 elements): the kernel of the bfloat16
+    forward products, equal to gemm(SQ_BF16, ...) on the FP32 values of A and B."""
+    a3, a_lr, a_sz = _bf16_operand(A, "A")
+    b3, b_lr, b_sz = _bf16_operand(B, "B")
+    batch, M, K = a3.shape
+    N = b3.shape[1]
+    if b3.shape[2] != K or b3.shape[0] not in (1, batch):
+        raise ValueError("A and B disagree in K or batch")
+    if C is None:
+        C = torch.zeros((batch, M, N), dtype=torch.float32, device=A.device)
+    c3 = C if C.dim() == 3 else C.unsqueeze(0)
+    if c3.dtype != torch.float32 or c3.stride(2) != 1:
+        raise ValueError("C must be a row-major float32 tensor")
+    bias_sz = 0
+    if bias is not None:
+        bias_sz = bias.stride(0) if bias.dim() == 2 and bias.shape[0] > 1 else 0
+    check(L.LIB.sq_gemm_bf16(M, N, K, batch, ptr(a3), a_lr, a_sz, ptr(b3), b_lr, b_sz if b3.shape[0] > 1 else 0,
+                             ptr(c3), c3.stride(1), c3.stride(0) if batch > 1 else 0, ptr(bias), bias_sz,
+                             stream_handle(stream)))
+    return C
+
+
+def bf16_operand_copies(on):
+    """Whether agents created from now on in the bfloat16 mode keep bfloat16 copies of
+    their products' operands (the default); returns the previous setting."""
+    return bool(L.LIB.sq_bf16_operand_copies(int(bool(on))))
+
+
+def bf16_copy_products():
+    """Linear-layer products enqueued on bfloat16 copies so far in this process."""
+    n = ctypes.c_longlong()
+    check(L.LIB.sq_bf16_copy_products(ctypes.byref(n)))
+    return n.value
+
+
 def sample_indices(seed, update, size, n, device="cuda", stream=None):
     idx = torch.empty(n, dtype=torch.int32, device=device)
     check(L.LIB.sq_sample_indices(seed, update, size, n, ptr(idx), stream_handle(stream)))

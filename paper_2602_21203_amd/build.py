@@ -15,7 +15,7 @@ OBJ = os.path.join(HERE, "_build")
 
 SOURCES = [
     "kernels/rng.hip", "kernels/squint.hip", "kernels/gemm.hip", "kernels/rowops.hip", "kernels/adam.hip", "kernels/serve.hip", "kernels/encoder.hip", "kernels/env.hip",
-    "layout.cpp", "ops.cpp", "abi.cpp", "noalloc.hip", "agent.cpp", "server.cpp", "ring.cpp", "env.cpp",
+    "layout.cpp", "twins.cpp", "ops.cpp", "abi.cpp", "noalloc.hip", "agent.cpp", "server.cpp", "ring.cpp", "env.cpp",
 ]
 ARCH = os.environ.get("SQ_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-fvisibility=hidden",

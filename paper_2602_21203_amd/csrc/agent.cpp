@@ -99,6 +99,7 @@ struct sq_agent {
   float *pack, *tpack;   // packed linear weights of params and of the target critic
   int* ctr;
   void* ws = nullptr;
+  void* wsh = nullptr;   // bfloat16 copies of the products' operands (bfloat16 mode)
   bool own_grads = false;
   long long u_host = 0;
   // update buffers
@@ -160,6 +161,45 @@ static size_t plan_agent(sq_agent* g, char* base) {
   }
   plan_act(net, g->act_cap, b, &g->actw);
   return b.off + 256;
+}
+
+// In the bfloat16 mode the packed weights and every activation buffer that feeds
+// a forward product get bfloat16 copies, kept by their producers (LayerNorm, the
+// fused encoder, the minibatch draw, the policy head, pack and Adam), so those
+// products read half the bytes.  Only buffers whose every producer writes the
+// copy are registered.
+static int make_twins(sq_agent* g) {
+  const Net& net = g->net;
+  const sq_dims& d = net.d;
+  const size_t B = (size_t)g->B, H = (size_t)d.hidden;
+  struct Item { const float* f; size_t n; };
+  std::vector<Item> items = {
+      {g->pack, (size_t)g->L.pack_total}, {g->tpack, (size_t)g->L.pack_critic_end},
+      {g->crit.X1, 2 * B * net.cpad},     {g->crit.g1, 4 * B * H},  {g->crit.g2, 4 * B * H},
+      {g->aux.X1, B * net.cpad},          {g->aux.g1, 2 * B * H},   {g->aux.g2, 2 * B * H},
+      {g->actor.X1, 2 * B * net.apad},    {g->actor.g1, 2 * B * H}, {g->actor.g2, 2 * B * H}};
+  if (d.n_conv > 0 && encoder_fused(net, 1, g->enc)) items.push_back({g->enc.h[d.n_conv - 1], 2 * B * net.flat});
+  Bump b{nullptr};
+  for (const Item& it : items) b.take<uint16_t>(it.n);
+  const size_t bytes = b.off + 256;
+  if (hipMalloc(&g->wsh, bytes) != hipSuccess) {
+    g->wsh = nullptr;
+    set_error("hipMalloc of %zu bytes for the bfloat16 operand copies failed", bytes);
+    return SQ_ENOMEM;
+  }
+  SQ_TRY_HIP(hipMemset(g->wsh, 0, bytes));
+  Bump h{(char*)(((uintptr_t)g->wsh + 255) & ~(uintptr_t)255)};
+  for (const Item& it : items) twin_register(g, it.f, (long long)it.n, h.take<uint16_t>(it.n));
+  g->pk_critic.pack_h = g->pk_actor.pack_h = twin_of(g->pack, g->L.pack_total);
+  g->pk_critic.tpack_h = twin_of(g->tpack, g->L.pack_critic_end);
+  return SQ_OK;
+}
+
+static void free_agent(sq_agent* g) {
+  twin_unregister(g);
+  if (g->wsh) (void)hipFree(g->wsh);
+  if (g->ws) (void)hipFree(g->ws);
+  delete g;
 }
 
 static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int actor_step, hipStream_t st) {
@@ -356,17 +396,22 @@ int sq_agent_create(const sq_dims* dims, const sq_hparams* hp, int batch, float*
     g->gs_critic.gout = g->grads;
     g->gs_actor.gout = g->grads + L.actor_begin;
   }
+  if (hp->prec == SQ_BF16 && twins_enabled()) {
+    const int s = make_twins(g);
+    if (s != SQ_OK) {
+      free_agent(g);
+      return s;
+    }
+  }
   if (pack_weights(g->L, params, target, g->pack, g->tpack, nullptr) != SQ_OK ||
       encoder_prepare(g->net, hp->prec == SQ_BF16, params, g->L, g->enc, nullptr) != SQ_OK ||
       hipDeviceSynchronize() != hipSuccess) {
-    (void)hipFree(g->ws);
-    delete g;
+    free_agent(g);
     return SQ_EDEVICE;
   }
   int host_ctr[CTR_N];
   if (hipMemcpy(host_ctr, counters, sizeof(host_ctr), hipMemcpyDeviceToHost) != hipSuccess) {
-    (void)hipFree(g->ws);
-    delete g;
+    free_agent(g);
     set_error("reading the counters failed");
     return SQ_EDEVICE;
   }
@@ -379,8 +424,7 @@ int sq_agent_destroy(sq_agent* g) {
   if (!g) return SQ_OK;
   if (!g->graphs.empty()) (void)hipDeviceSynchronize();
   for (auto& e : g->graphs) destroy_entry(e);
-  if (g->ws) (void)hipFree(g->ws);
-  delete g;
+  free_agent(g);
   return SQ_OK;
 }
 

@@ -211,6 +211,21 @@ struct OutArg {            // C(r, c) at p[z*sz + r*ld + c]
 // scratch (nullable) enables a deterministic split over K for small outputs.
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st);
+// C = A B^T (+ bias) on bfloat16-stored operands (A [batch][M][a_lr], B [batch][N][b_lr],
+// k-contiguous rows), the product the bfloat16 mode runs when both operands have copies
+int gemm_bf16_stored(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_sz,
+                     const uint16_t* B, long long b_lr, long long b_sz, OutArg C, hipStream_t st);
+// twins.cpp: bfloat16 copies ("twins") of FP32 operand buffers, written by the
+// buffers' producers and read by the products in the bfloat16 mode
+int twins_enabled();
+int set_twins_enabled(int on);
+void twin_register(const void* owner, const float* f, long long n, uint16_t* h);
+void twin_unregister(const void* owner);
+// the twin of [f, f + n), or nullptr when no registered buffer holds that range
+uint16_t* twin_of(const float* f, long long n = 1);
+// products enqueued on twins so far (process-wide)
+void note_copy_product();
+long long copy_products();
 // policy head [n][2A] = X W^T + bias with the tanh-Gaussian sample (eps given) or the
 // mean action (eps null) applied per row in the same launch; head is also stored.
 // xact (nullable): the actions of rows r >= xact_row0 are also written to
@@ -252,8 +267,9 @@ bool encoder_fused_prep_map(int C, int F, int n_conv, int side, const long long*
                             EncPrepMap* m);
 size_t encoder_fused_prep_floats(int C, int F, int n_conv);
 int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W, float* wp, hipStream_t st);
+// hh (nullable, bfloat16 form only): the last layer's output is also written there rounded to bfloat16
 int encoder_fused_fwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* wp,
-                      const float* const* b, float* const* h, hipStream_t st);
+                      const float* const* b, float* const* h, hipStream_t st, uint16_t* hh = nullptr);
 // partial gradients of every workgroup in part, their ordered sum in grad[0, total)
 int encoder_fused_bwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* dfeat,
                       const float* wp, const float* const* h, const long long* Woff, const long long* boff,
@@ -279,6 +295,7 @@ struct LnFwdJob {
   float* y; long long ld_y, sz_y; float* xhat; float* rstd;
   const float* e1; long long ld_e1; int w1; const float* e2; long long ld_e2; int w2;
   LnGroups grp;
+  uint16_t* yh;   // bfloat16 copy of y (nullable; ln_fwd_job fills it)
 };
 LnFwdJob ln_fwd_job(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch, const float* g,
                     const float* beta, long long sz_par, int act_tanh, float* y, long long ld_y, long long sz_y,
@@ -356,6 +373,7 @@ int conv_bias_grad(const float* dout, const float* out, int n, int F, int HW, fl
 struct PackArgs {
   int n; PackSeg seg[16];
   float* pack; float* tpack; long long p_begin;
+  uint16_t* pack_h = nullptr; uint16_t* tpack_h = nullptr;   // their bfloat16 copies (nullable)
 };
 // Gradients that are still row-block partials: parameter i in [begin, begin + H)
 // (relative to the optimiser's range) has gradient sum_{r < nrows} part[r * H + i - begin],

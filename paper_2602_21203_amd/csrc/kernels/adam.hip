@@ -135,7 +135,11 @@ __device__ __forceinline__ void adam_elem(const AdamArgs& A, const PackArgs& pk,
     if (d < 0) d = pack_pos(pk, i, &critic);
     if (d >= 0) {
       pk.pack[d] = pi;
-      if (critic && pk.tpack && A.ema && i >= A.ema_begin) pk.tpack[d] = ei;
+      if (pk.pack_h) pk.pack_h[d] = bf16_bits(pi);
+      if (critic && pk.tpack && A.ema && i >= A.ema_begin) {
+        pk.tpack[d] = ei;
+        if (pk.tpack_h) pk.tpack_h[d] = bf16_bits(ei);
+      }
     }
   }
 }
@@ -281,8 +285,14 @@ __global__ void k_pack(PackArgs pk, const float* __restrict__ params, const floa
        e += (long long)gridDim.x * blockDim.x) {
     const long long r = e / q.ldp, c = e - r * q.ldp;
     const bool in = c < q.cols;
-    pk.pack[q.dst + e] = in ? params[q.src + r * q.cols + c] : 0.f;
-    if (q.critic && pk.tpack) pk.tpack[q.dst + e] = in ? target[q.src - critic_begin + r * q.cols + c] : 0.f;
+    const float v = in ? params[q.src + r * q.cols + c] : 0.f;
+    pk.pack[q.dst + e] = v;
+    if (pk.pack_h) pk.pack_h[q.dst + e] = bf16_bits(v);
+    if (q.critic && pk.tpack) {
+      const float t = in ? target[q.src - critic_begin + r * q.cols + c] : 0.f;
+      pk.tpack[q.dst + e] = t;
+      if (pk.tpack_h) pk.tpack_h[q.dst + e] = bf16_bits(t);
+    }
   }
 }
 
@@ -293,6 +303,8 @@ int pack_weights(const Layout& L, const float* params, const float* target, floa
   for (int i = 0; i < L.n_pack; ++i) pk.seg[i] = L.pack[i];
   pk.pack = pack;
   pk.tpack = target ? tpack : nullptr;
+  pk.pack_h = twin_of(pack, L.pack_total);
+  pk.tpack_h = target ? twin_of(tpack, L.pack_critic_end) : nullptr;
   k_pack<<<dim3(64, L.n_pack), 256, 0, st>>>(pk, params, target, L.critic_begin);
   return launch_status("pack_weights");
 }

@@ -482,7 +482,8 @@ struct WFrag {
 template <int G, int C, int F, int l, int SD, bool TO_LDS, bool LAST, int NT, bool PRE>
 __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16* __restrict__ wf,
                                  const float* __restrict__ bias, float* __restrict__ out_g, int gn,
-                                 const WFrag<C, F, l, SD>& w, float* out_lds_f = nullptr) {
+                                 const WFrag<C, F, l, SD>& w, float* out_lds_f = nullptr,
+                                 uint16_t* __restrict__ out_h = nullptr) {
   using Y = LB<C, F, l, SD>;
   constexpr int ROWS = G * Y::P, RT = (ROWS + 15) / 16, CT = F / 16, NW = NT / 64;
   constexpr int PSO = F + 8;
@@ -523,7 +524,10 @@ __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16
   if constexpr (LAST) {
     // the feature rows of the workgroup's images are contiguous in NCHW order
     lds_barrier();
-    for (int e = threadIdx.x; e < gn * F * Y::P; e += NT) out_g[e] = out_lds_f[e];
+    for (int e = threadIdx.x; e < gn * F * Y::P; e += NT) {
+      out_g[e] = out_lds_f[e];
+      if (out_h) out_h[e] = bf16_bits(out_lds_f[e]);
+    }
   }
 }
 
@@ -531,7 +535,8 @@ template <int G, int C, int F, int NC, int SD, int NT>
 __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ x, int n, const __bf16* __restrict__ wp,
                                                       const float* __restrict__ b0, const float* __restrict__ b1,
                                                       const float* __restrict__ b2, float* __restrict__ h0,
-                                                      float* __restrict__ h1, float* __restrict__ h2) {
+                                                      float* __restrict__ h1, float* __restrict__ h2,
+                                                      uint16_t* __restrict__ hh) {
   using L0 = LB<C, F, 0, SD>;
   using L1 = LB<C, F, 1, SD>;
   using E = EncPrep<C, F, NC>;
@@ -583,11 +588,13 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
     lds_barrier();
     conv_fwd_layer_b<G, C, F, 2, SD, false, true, NT, PRE>(la1, nullptr, wp + E::F2, b2,
                                                        h2 + (long long)img0 * F * LB<C, F, 2, SD>::P, gn, w2,
-                                                       reinterpret_cast<float*>(lx));
+                                                       reinterpret_cast<float*>(lx),
+                                                       hh ? hh + (long long)img0 * F * LB<C, F, 2, SD>::P : nullptr);
   } else {
     conv_fwd_layer_b<G, C, F, 1, SD, false, true, NT, PRE>(la0, nullptr, wp + E::F1, b1,
                                                        h1 + (long long)img0 * F * L1::P, gn, w1,
-                                                       reinterpret_cast<float*>(lx));
+                                                       reinterpret_cast<float*>(lx),
+                                                       hh ? hh + (long long)img0 * F * L1::P : nullptr);
   }
 }
 
@@ -933,12 +940,13 @@ static int prep_t(const float* const* W, float* wp, int bf16, hipStream_t st) {
 constexpr int enc_bwd_g(int side) { return side == 16 ? kEncBwdG : 1; }
 
 template <bool BF16, int C, int F, int NC, int SD>
-static int enc_fwd_t(const float* x, int n, const float* wp, const float* const* b, float* const* h, hipStream_t st) {
+static int enc_fwd_t(const float* x, int n, const float* wp, const float* const* b, float* const* h, uint16_t* hh,
+                     hipStream_t st) {
   if constexpr (BF16) {
     const int nwg = cdiv(n, kEncFwdGb);
     k_encoder_fwd_b<kEncFwdGb, C, F, NC, SD, kEncFwdThreadsb><<<nwg, kEncFwdThreadsb, 0, st>>>(
         x, n, reinterpret_cast<const __bf16*>(wp), b[0], b[1], NC > 2 ? b[2] : b[1], h[0], h[1],
-        NC > 2 ? h[2] : h[1]);
+        NC > 2 ? h[2] : h[1], hh);
   } else {
     static_assert(SD == 16, "the FP32 fused encoder is built for 16 x 16 inputs");
     const int nwg = cdiv(n, kEncFwdG);
@@ -1026,12 +1034,18 @@ int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W
 }
 
 int encoder_fused_fwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* wp,
-                      const float* const* b, float* const* h, hipStream_t st) {
+                      const float* const* b, float* const* h, hipStream_t st, uint16_t* hh) {
   if (n <= 0) return SQ_OK;
-  if (side == 32) return enc_fwd_t<true, 9, 32, 3, 32>(x, n, wp, b, h, st);
+  if (hh && !bf16) {
+    set_error("encoder_fused_fwd: the feature's bfloat16 copy is written by the bfloat16 form only");
+    return SQ_EINVAL;
+  }
+  if (side == 32) return enc_fwd_t<true, 9, 32, 3, 32>(x, n, wp, b, h, hh, st);
   if (C == 9 && F == 32 && n_conv == 3)
-    return bf16 ? enc_fwd_t<true, 9, 32, 3, 16>(x, n, wp, b, h, st) : enc_fwd_t<false, 9, 32, 3, 16>(x, n, wp, b, h, st);
-  return bf16 ? enc_fwd_t<true, 3, 16, 2, 16>(x, n, wp, b, h, st) : enc_fwd_t<false, 3, 16, 2, 16>(x, n, wp, b, h, st);
+    return bf16 ? enc_fwd_t<true, 9, 32, 3, 16>(x, n, wp, b, h, hh, st)
+                : enc_fwd_t<false, 9, 32, 3, 16>(x, n, wp, b, h, nullptr, st);
+  return bf16 ? enc_fwd_t<true, 3, 16, 2, 16>(x, n, wp, b, h, hh, st)
+              : enc_fwd_t<false, 3, 16, 2, 16>(x, n, wp, b, h, nullptr, st);
 }
 
 int encoder_fused_bwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* dfeat,

@@ -145,6 +145,7 @@ struct StMat {
 struct StTanhGauss {
   const float* bias; const float* eps; float lo, hi; float* action; float* logp; float* save; float* head; int A;
   float* xact; long long ld_xact; int xact_row0;   // second copy of the actions of rows >= xact_row0 (nullable)
+  uint16_t* xact_h;                                 // bfloat16 copy of xact's buffer (nullable)
   static constexpr bool ROW_FAST = false;
   static constexpr bool ROWS = true;
   __device__ void put(int, int, int, float) const {}
@@ -167,7 +168,10 @@ struct StTanhGauss {
         act = tanhf(mu);
         action[row * A + d] = act;
       }
-      if (xact && row >= xact_row0) xact[(row - xact_row0) * ld_xact + d] = act;
+      if (xact && row >= xact_row0) {
+        xact[(row - xact_row0) * ld_xact + d] = act;
+        if (xact_h) xact_h[(row - xact_row0) * ld_xact + d] = bf16_bits(act);
+      }
     }
     if (!eps || !logp) return;
     __syncthreads();
@@ -558,6 +562,41 @@ __device__ __forceinline__ void rmma(const RFrag<BF16>& a, const RFrag<BF16>& b,
   }
 }
 
+// The end of a tile: the four waves' partial tiles summed through LDS in a fixed
+// order (the buffer overlays the waves' operand tiles), then the stores or the
+// tile epilogue.  All threads call.
+template <class ST, bool SPLIT>
+__device__ __forceinline__ void tile_out(const v4f (&acc)[2][2], const ST& st, const StPart& sp, int M, int N, int m0,
+                                         int n0, int z, int split, int wave, int lane, char* lds) {
+  constexpr int RLD = kTile + 1;
+  const int li = lane & 15, lq = lane >> 4;
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        red[(wave * kTile + i * 16 + 4 * lq + q) * RLD + j * 16 + li] = acc[i][j][q];
+  __syncthreads();
+  for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
+    const int r = e / kTile, c = e - r * kTile;
+    const float v = ((red[(0 * kTile + r) * RLD + c] + red[(1 * kTile + r) * RLD + c]) +
+                     red[(2 * kTile + r) * RLD + c]) + red[(3 * kTile + r) * RLD + c];
+    const int gr = m0 + r, gc = n0 + c;
+    if constexpr (ST::ROWS && !SPLIT) {
+      red[r * RLD + c] = v;   // wave 0's slot of this element: read above by this thread only
+    } else if (gr < M && gc < N) {
+      if constexpr (SPLIT) sp.put(z, split, gr, gc, v); else st.put(z, gr, gc, v);
+    }
+  }
+  if constexpr (ST::ROWS && !SPLIT) {
+    __syncthreads();
+    st.rows(m0, min(kTile, M - m0), red, RLD, red + kTile * RLD);
+  }
+}
+
 template <bool BF16, int AV, int BV>
 constexpr int gemm_lds_bytes() {
   using LL = RLds<BF16>;
@@ -573,7 +612,6 @@ __device__ __forceinline__ void gemm_tile(const RMat& fa, const RMat& fb, const 
   using LL = RLds<BF16>;
   using T = typename LL::T;
   constexpr int KC = kRKC, G = kRG;
-  constexpr int RLD = kTile + 1;
 
   const int z = bz / (SPLIT ? sp.splits : 1);
   const int split = SPLIT ? bz % sp.splits : 0;
@@ -584,7 +622,6 @@ __device__ __forceinline__ void gemm_tile(const RMat& fa, const RMat& fb, const 
   const int kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: chunk tests stay scalar
-  const int li = lane & 15, lq = lane >> 4;
   T* wt = reinterpret_cast<T*>(lds) + wave * LL::WAVE;   // this wave's tiles: [chunk of the group][operand]
   // this wave's k range: a quarter of the workgroup's, in whole chunks
   const int span = kend > kbeg ? kend - kbeg : 0;
@@ -665,32 +702,7 @@ __device__ __forceinline__ void gemm_tile(const RMat& fa, const RMat& fb, const 
     chunk(ta, tb);
   }
 
-  // fixed-order sum of the four waves' partial tiles (the buffer overlays the waves' tiles)
-  __syncthreads();
-  float* red = reinterpret_cast<float*>(lds);
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        red[(wave * kTile + i * 16 + 4 * lq + q) * RLD + j * 16 + li] = acc[i][j][q];
-  __syncthreads();
-  for (int e = threadIdx.x; e < kTile * kTile; e += kThreads) {
-    const int r = e / kTile, c = e - r * kTile;
-    const float v = ((red[(0 * kTile + r) * RLD + c] + red[(1 * kTile + r) * RLD + c]) +
-                     red[(2 * kTile + r) * RLD + c]) + red[(3 * kTile + r) * RLD + c];
-    const int gr = m0 + r, gc = n0 + c;
-    if constexpr (ST::ROWS && !SPLIT) {
-      red[r * RLD + c] = v;   // wave 0's slot of this element: read above by this thread only
-    } else if (gr < M && gc < N) {
-      if constexpr (SPLIT) sp.put(z, split, gr, gc, v); else st.put(z, gr, gc, v);
-    }
-  }
-  if constexpr (ST::ROWS && !SPLIT) {
-    __syncthreads();
-    st.rows(m0, min(kTile, M - m0), red, RLD, red + kTile * RLD);
-  }
+  tile_out<ST, SPLIT>(acc, st, sp, M, N, m0, n0, z, split, wave, lane, lds);
 }
 
 template <bool BF16, int AV, int BV, class ST, bool SPLIT>
@@ -741,6 +753,203 @@ __global__ __launch_bounds__(kThreads) void k_gemm_pair_f(RProb p0, RProb p1, in
     gemm_tile<BF16, 1, 1, StMat, false>(p1.a, p1.b, p1.st, none, p1.M, p1.N, p1.K, p1.K, b % p1.gx,
                                         (b / p1.gx) % p1.gy, b / (p1.gx * p1.gy), lds);
   }
+}
+
+// ---------------------------------------------------------------- bfloat16-stored operands
+// Products whose two operands both have bfloat16 copies (k-contiguous rows, 16-byte
+// aligned; written by the operands' producers) read the copies: 8 elements per
+// 16-byte lane load, half the bytes and half the load instructions of the FP32
+// form, and no conversion.  The tile, the wave split of K, the chunk order and the
+// final sum are those of gemm_tile, so the result is the same bit for bit.
+// Two load forms: DIRECT, lane (li, lq) loads its own fragment (rows li and
+// 16 + li, k = 8 lq .. 8 lq + 7 of the chunk) from memory; otherwise four lanes
+// cover a row's 64 bytes of the chunk and the chunk is rearranged through the
+// wave's LDS tile.  The direct form is faster for short K ranges per wave, the
+// LDS form once each wave reads four chunks or more.
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
+
+struct HMat {
+  const uint16_t* p; long long lr, sz;
+  const uint16_t* alt; int zalt, zdiv;
+  int kmax;   // the last 8-element group start inside every row: rows hold at least kmax + 8 elements
+  __device__ __forceinline__ const uint16_t* batch(int z) const {
+    const int zi = z / zdiv;
+    return zi < zalt ? p + (long long)zi * sz : alt + (long long)(zi - zalt) * sz;
+  }
+};
+
+constexpr int kHMaxC = 4;   // chunks of a wave in flight at once
+
+// elements k >= kend of a loaded group starting at kq read as zero
+__device__ __forceinline__ u4v hmask(u4v v, int kq, int kend) {
+  const int nv = kend - kq;
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    const unsigned keep = nv >= 2 * d + 2 ? 0xffffffffu : (nv == 2 * d + 1 ? 0x0000ffffu : 0u);
+    v[d] &= keep;
+  }
+  return v;
+}
+
+// one operand's part of chunk k0: two 16-byte groups per lane
+template <bool DIRECT>
+__device__ __forceinline__ void hload(const uint16_t* base, long long lr, int kmax, int r0, int rows, int k0,
+                                      int lane, u4v (&v)[2]) {
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int r = min(r0 + (DIRECT ? 16 * j + (lane & 15) : 16 * j + (lane >> 2)), rows - 1);
+    const int kq = k0 + (DIRECT ? 8 * (lane >> 4) : 8 * (lane & 3));
+    v[j] = *reinterpret_cast<const u4v*>(base + (long long)r * lr + min(kq, kmax));
+  }
+}
+
+template <bool DIRECT>
+__device__ __forceinline__ void hmask_chunk(u4v (&v)[2], int k0, int kend, int lane) {
+  const int kq = k0 + (DIRECT ? 8 * (lane >> 4) : 8 * (lane & 3));
+#pragma unroll
+  for (int j = 0; j < 2; ++j) v[j] = hmask(v[j], kq, kend);
+}
+
+template <bool DIRECT>
+constexpr int hgemm_lds_bytes() {
+  constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
+  constexpr int TILE_BYTES = DIRECT ? 0 : 4 * RLds<true>::WAVE * 2;
+  return TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
+}
+
+template <bool DIRECT, class ST>
+__device__ __forceinline__ void gemm_tile_h(const HMat& fa, const HMat& fb, const ST& st, int M, int N, int K, int bx,
+                                            int by, int bz, char* lds) {
+  using LL = RLds<true>;
+  constexpr int KC = kRKC;
+  const int m0 = bx * kTile, n0 = by * kTile;
+  const uint16_t* ab = fa.batch(bz);
+  const uint16_t* bb = fb.batch(bz);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lq = lane >> 4;
+  // this wave's k range, as in gemm_tile: a quarter of K in whole chunks
+  const int per = ((K + 3) / 4 + KC - 1) / KC * KC;
+  const int wb = wave * per;
+  const int we = min(K, wb + per);
+  const int nch = we > wb ? (we - wb + KC - 1) / KC : 0;
+  __bf16* wt = reinterpret_cast<__bf16*>(lds) + wave * LL::WAVE;
+
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+
+  for (int g = 0; g < nch; g += kHMaxC) {
+    u4v ra[kHMaxC][2], rb[kHMaxC][2];
+#pragma unroll
+    for (int c = 0; c < kHMaxC; ++c) {
+      if (g + c < nch) {
+        const int k0 = wb + (g + c) * KC;
+        hload<DIRECT>(ab, fa.lr, fa.kmax, m0, M, k0, lane, ra[c]);
+        hload<DIRECT>(bb, fb.lr, fb.kmax, n0, N, k0, lane, rb[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kHMaxC; ++c) {
+      const int k0 = wb + (g + c) * KC;
+      if (g + c < nch && k0 + KC > we) {   // the range's partial last chunk
+        hmask_chunk<DIRECT>(ra[c], k0, we, lane);
+        hmask_chunk<DIRECT>(rb[c], k0, we, lane);
+      }
+    }
+    if constexpr (DIRECT) {
+#pragma unroll
+      for (int c = 0; c < kHMaxC; ++c) {
+        if (g + c < nch) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj)
+              acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ra[c][i]),
+                                                                   __builtin_bit_cast(bf16x8, rb[c][jj]), acc[i][jj],
+                                                                   0, 0, 0);
+        }
+      }
+    } else {
+      // two chunks per LDS round (the wave's tiles hold two chunks of both operands)
+#pragma unroll
+      for (int h = 0; h < kHMaxC; h += 2) {
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+          if (g + h + c2 < nch) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const int r = 16 * j + (lane >> 2), kq = 8 * (lane & 3);
+              *reinterpret_cast<u4v*>(wt + (2 * c2) * LL::TILE + r * LL::LDT + kq) = ra[h + c2][j];
+              *reinterpret_cast<u4v*>(wt + (2 * c2 + 1) * LL::TILE + r * LL::LDT + kq) = rb[h + c2][j];
+            }
+          }
+        }
+        lds_wave_sync();
+#pragma unroll
+        for (int c2 = 0; c2 < 2; ++c2) {
+          if (g + h + c2 < nch) {
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+              a[i] = *reinterpret_cast<const bf16x8*>(wt + (2 * c2) * LL::TILE + (16 * i + li) * LL::LDT + 8 * lq);
+              b[i] = *reinterpret_cast<const bf16x8*>(wt + (2 * c2 + 1) * LL::TILE + (16 * i + li) * LL::LDT + 8 * lq);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int jj = 0; jj < 2; ++jj)
+                acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[jj], acc[i][jj], 0, 0, 0);
+          }
+        }
+        asm volatile("" ::: "memory");
+      }
+    }
+  }
+  const StPart none{nullptr, 0, 0, 1};
+  tile_out<ST, false>(acc, st, none, M, N, m0, n0, bz, 0, wave, lane, lds);
+}
+
+template <bool DIRECT, class ST>
+__global__ __launch_bounds__(kThreads) void k_gemm_h(HMat fa, HMat fb, ST st, int M, int N, int K) {
+  __shared__ __attribute__((aligned(16))) char lds[hgemm_lds_bytes<DIRECT>()];
+  int bx, by, bz;
+  tile_of(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), gridDim.x, gridDim.y, gridDim.z, bx, by,
+          bz);
+  gemm_tile_h<DIRECT, ST>(fa, fb, st, M, N, K, bx, by, bz, lds);
+}
+
+// two forward products on bfloat16 copies in one launch (as k_gemm_pair_f)
+struct HProb {
+  HMat a, b; StMat st; int M, N, K, gx, gy;
+};
+
+template <bool DIRECT>
+__global__ __launch_bounds__(kThreads) void k_gemm_pair_h(HProb p0, HProb p1, int tiles0) {
+  __shared__ __attribute__((aligned(16))) char lds[hgemm_lds_bytes<DIRECT>()];
+  int b = blockIdx.x;
+  if (b < tiles0) {
+    gemm_tile_h<DIRECT, StMat>(p0.a, p0.b, p0.st, p0.M, p0.N, p0.K, b % p0.gx, (b / p0.gx) % p0.gy,
+                               b / (p0.gx * p0.gy), lds);
+  } else {
+    b -= tiles0;
+    gemm_tile_h<DIRECT, StMat>(p1.a, p1.b, p1.st, p1.M, p1.N, p1.K, b % p1.gx, (b / p1.gx) % p1.gy,
+                               b / (p1.gx * p1.gy), lds);
+  }
+}
+
+// rows of a small matrix copied into another's columns, and into its bfloat16 copy
+// when it has one (the unfused policy head's second action copy)
+__global__ void k_copy_rows(const float* __restrict__ src, int cols, int rows, float* __restrict__ dst, long long ld,
+                            uint16_t* __restrict__ dst_h) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int r = e / cols, c = e - r * cols;
+  const float v = src[e];
+  dst[(long long)r * ld + c] = v;
+  if (dst_h) dst_h[(long long)r * ld + c] = bf16_bits(v);
 }
 
 // sum of split-K partials in split order, then the real store
@@ -818,6 +1027,53 @@ static int want_splits(int M, int N, int K, int batch, const float* scratch, siz
   return splits;
 }
 
+// the bfloat16 copy of operand m of a product with `rows` rows and contraction K
+// over `batch` batches, when every batch it reads has one (rows k-contiguous,
+// 16-byte aligned, at least K rounded up to 8 elements long)
+static bool hmat(const MatArg& m, int rows, int K, int batch, HMat* out) {
+  if (m.kp || m.lk != 1 || m.lr % 8 || m.sz % 8 || rows <= 0 || K <= 0) return false;
+  const long long k8 = (K + 7) / 8 * 8;
+  if (m.lr < k8) return false;
+  const int nb = cdiv(batch, m.zdiv);
+  const int np = std::min(nb, m.zalt);
+  const long long ext = (long long)(rows - 1) * m.lr + k8;
+  const uint16_t* hp = np > 0 ? twin_of(m.p, (long long)(np - 1) * m.sz + ext) : nullptr;
+  if (np > 0 && (!hp || (uintptr_t)hp % 16)) return false;
+  const uint16_t* ha = nullptr;
+  if (nb > np) {
+    ha = twin_of(m.alt, (long long)(nb - np - 1) * m.sz + ext);
+    if (!ha || (uintptr_t)ha % 16) return false;
+  }
+  *out = HMat{hp, m.lr, m.sz, ha, m.zalt, m.zdiv, (int)(k8 - 8)};
+  return true;
+}
+
+// the direct load form for short per-wave K ranges (at most three chunks)
+static bool h_direct(int K) { return cdiv(cdiv(K, 4), kRKC) <= 3; }
+
+template <class ST>
+static int run_h(int M, int N, int K, int batch, const HMat& a, const HMat& b, const ST& out, hipStream_t st) {
+  dim3 grid(cdiv(M, kTile), cdiv(N, kTile), batch);
+  if (h_direct(K)) k_gemm_h<true, ST><<<grid, kThreads, 0, st>>>(a, b, out, M, N, K);
+  else k_gemm_h<false, ST><<<grid, kThreads, 0, st>>>(a, b, out, M, N, K);
+  note_copy_product();
+  return launch_status("gemm_h");
+}
+
+int gemm_bf16_stored(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_sz,
+                     const uint16_t* B, long long b_lr, long long b_sz, OutArg C, hipStream_t st) {
+  if (M <= 0 || N <= 0 || batch <= 0) return SQ_OK;
+  const long long k8 = (K + 7) / 8 * 8;
+  if (K <= 0 || !A || !B || !C.p || (uintptr_t)A % 16 || (uintptr_t)B % 16 || a_lr % 8 || b_lr % 8 || a_sz % 8 ||
+      b_sz % 8 || a_lr < k8 || b_lr < k8) {
+    set_error("gemm_bf16: operands need 16-byte aligned rows of at least K rounded up to 8 elements");
+    return SQ_EINVAL;
+  }
+  const HMat a{A, a_lr, a_sz, nullptr, kNoAlt, 1, (int)(k8 - 8)};
+  const HMat b{B, b_lr, b_sz, nullptr, kNoAlt, 1, (int)(k8 - 8)};
+  return run_h(M, N, K, batch, a, b, stmat(C), st);
+}
+
 template <bool BF16, int AV, int BV>
 static int run_r(int M, int N, int K, int batch, const MatArg& A, const MatArg& B, const StMat& out, float* scratch,
                  size_t scratch_floats, hipStream_t st) {
@@ -851,6 +1107,10 @@ int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C,
   }
   const StMat out = stmat(C);
   const int va = rkind(A), vb = rkind(B);
+  if (bf16 && want_splits(M, N, K, batch, scratch, scratch_floats) == 1) {
+    HMat ha, hb;
+    if (hmat(A, M, K, batch, &ha) && hmat(B, N, K, batch, &hb)) return run_h(M, N, K, batch, ha, hb, out, st);
+  }
   if (bf16) {
     if (va && vb) return run_r<true, 1, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
     if (va) return run_r<true, 1, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
@@ -876,14 +1136,25 @@ int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const flo
     SQ_TRY(gemm(bf16, n, 2 * A, K, 1, X, W, C, nullptr, 0, st));
     SQ_TRY(eps ? tanh_gauss_fwd(head, n, A, eps, lo, hi, action, logp, save, st)
                : mean_action(head, n, A, action, st));
-    if (xact && xact_row0 < n)
-      SQ_TRY_HIP(hipMemcpy2DAsync(xact, (size_t)ld_xact * 4, action + (size_t)xact_row0 * A, (size_t)A * 4,
-                                  (size_t)A * 4, (size_t)(n - xact_row0), hipMemcpyDeviceToDevice, st));
+    if (xact && xact_row0 < n) {
+      const int rows = n - xact_row0;
+      k_copy_rows<<<cdiv((long long)rows * A, 256), 256, 0, st>>>(action + (size_t)xact_row0 * A, A, rows, xact,
+                                                                   ld_xact, twin_of(xact, (rows - 1) * ld_xact + A));
+      return launch_status("copy_rows");
+    }
     return SQ_OK;
   }
-  const StTanhGauss tg{bias, eps, lo, hi, action, logp, save, head, A, xact, ld_xact, xact_row0};
+  uint16_t* xact_h = xact && xact_row0 < n ? twin_of(xact, (long long)(n - xact_row0 - 1) * ld_xact + A) : nullptr;
+  const StTanhGauss tg{bias, eps, lo, hi, action, logp, save, head, A, xact, ld_xact, xact_row0, xact_h};
   const StPart none{nullptr, 0, 0, 1};
   dim3 grid(cdiv(n, kTile), 1, 1);
+  HMat hx, hw;
+  if (bf16 && hmat(X, n, K, 1, &hx) && hmat(W, 2 * A, K, 1, &hw)) {
+    if (h_direct(K)) k_gemm_h<true, StTanhGauss><<<grid, kThreads, 0, st>>>(hx, hw, tg, n, 2 * A, K);
+    else k_gemm_h<false, StTanhGauss><<<grid, kThreads, 0, st>>>(hx, hw, tg, n, 2 * A, K);
+    note_copy_product();
+    return launch_status("gemm_tanh_gauss");
+  }
   if (bf16)
     k_gemm_r<true, 1, 1, StTanhGauss, false><<<grid, kThreads, 0, st>>>(rmat(X), rmat(W), tg, none, n, 2 * A, K, K);
   else
@@ -931,6 +1202,16 @@ int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, 
   RProb q0{rmat(p0.A), rmat(p0.B), stmat(p0.C), p0.M, p0.N, p0.K, cdiv(p0.M, kTile), cdiv(p0.N, kTile)};
   RProb q1{rmat(p1.A), rmat(p1.B), stmat(p1.C), p1.M, p1.N, p1.K, cdiv(p1.M, kTile), cdiv(p1.N, kTile)};
   const int t0 = q0.gx * q0.gy * p0.batch, t1 = q1.gx * q1.gy * p1.batch;
+  HMat h0a, h0b, h1a, h1b;
+  if (bf16 && fwd_kinds && hmat(p0.A, p0.M, p0.K, p0.batch, &h0a) && hmat(p0.B, p0.N, p0.K, p0.batch, &h0b) &&
+      hmat(p1.A, p1.M, p1.K, p1.batch, &h1a) && hmat(p1.B, p1.N, p1.K, p1.batch, &h1b)) {
+    const HProb r0{h0a, h0b, q0.st, p0.M, p0.N, p0.K, q0.gx, q0.gy};
+    const HProb r1{h1a, h1b, q1.st, p1.M, p1.N, p1.K, q1.gx, q1.gy};
+    if (h_direct(std::max(p0.K, p1.K))) k_gemm_pair_h<true><<<t0 + t1, kThreads, 0, st>>>(r0, r1, t0);
+    else k_gemm_pair_h<false><<<t0 + t1, kThreads, 0, st>>>(r0, r1, t0);
+    note_copy_product();
+    return launch_status("gemm_pair_h");
+  }
   if (fwd_kinds) {
     if (bf16) k_gemm_pair_f<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
     else k_gemm_pair_f<false><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);

@@ -21,8 +21,9 @@ SampleArgs sample_args(unsigned long long seed, const int* ctr, int size, const 
                        const float* proprio, const float* next_proprio, const float* action, const float* reward,
                        const uint8_t* done, int* idx, float* eps2B, float* S2, float* Arep, long long ld_arep,
                        float* r, float* d) {
+  uint16_t* Arep_h = B > 0 && A > 0 ? twin_of(Arep, (long long)(B - 1) * ld_arep + A) : nullptr;
   return SampleArgs{(unsigned)seed, (unsigned)(seed >> 32), ctr, size, dev_size, B, A, S, proprio, next_proprio,
-                    action, reward, done, idx, eps2B, S2, Arep, ld_arep, r, d};
+                    action, reward, done, idx, eps2B, S2, Arep, ld_arep, r, d, Arep_h};
 }
 
 int launch_sample_batch(const SampleArgs& s, hipStream_t st) {

@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include "../common.h"
+#include "bf16.h"
 #include "tgauss.h"
 #include "finish.h"
 
@@ -106,12 +107,34 @@ __device__ __forceinline__ void ln_store_row(float* __restrict__ p, int H, int l
   }
 }
 
-// one row per wave; the row, gain and shift are all requested before the reductions
+// the same row's bfloat16 copy (8-byte stores in the VEC mapping)
+template <int E, bool VEC>
+__device__ __forceinline__ void ln_store_row_h(uint16_t* __restrict__ p, int H, int lane, const float (&v)[E]) {
+  if constexpr (VEC) {
+#pragma unroll
+    for (int c = 0; c < E / 4; ++c) {
+      typedef unsigned u2v __attribute__((ext_vector_type(2)));
+      const u2v w{(unsigned)bf16_bits(v[4 * c]) | ((unsigned)bf16_bits(v[4 * c + 1]) << 16),
+                  (unsigned)bf16_bits(v[4 * c + 2]) | ((unsigned)bf16_bits(v[4 * c + 3]) << 16)};
+      *reinterpret_cast<u2v*>(__builtin_assume_aligned(p + 256 * c + 4 * lane, 8)) = w;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < E; ++t) {
+      const int j = lane + 64 * t;
+      if (j < H) p[j] = bf16_bits(v[t]);
+    }
+  }
+}
+
+// one row per wave; the row, gain and shift are all requested before the reductions;
+// yh (nullable): the bfloat16 copy of y, written alongside
 template <int E, bool VEC>
 __device__ __forceinline__ void ln_fwd_row(const float* __restrict__ pre, long long ld_pre, long long sz_pre,
                                            int rows, int H, const float* __restrict__ g,
                                            const float* __restrict__ beta, long long sz_par, int act_tanh,
                                            float* __restrict__ y, long long ld_y, long long sz_y,
+                                           uint16_t* __restrict__ yh,
                                            float* __restrict__ xhat, float* __restrict__ rstd,
                                            const float* __restrict__ e1, long long ld_e1, int w1,
                                            const float* __restrict__ e2, long long ld_e2, int w2,
@@ -147,13 +170,23 @@ __device__ __forceinline__ void ln_fwd_row(const float* __restrict__ pre, long l
     o[t] = act_tanh ? tanhf(a) : fmaxf(a, 0.f);
   }
   float* yr = y + z * sz_y + row * ld_y;
+  uint16_t* yhr = yh ? yh + z * sz_y + row * ld_y : nullptr;
   ln_store_row<E, VEC>(xhat + ((long long)z * rows + row) * H, H, lane, xh);
   ln_store_row<E, VEC>(yr, H, lane, o);
+  if (yhr) ln_store_row_h<E, VEC>(yhr, H, lane, o);
   if (lane == 0) rstd[(long long)z * rows + row] = rs;
   const float* e1z = e1 + z * grp.sz_e1;
   const float* e2z = second && grp.e2_alt ? grp.e2_alt : e2;
-  for (int j = lane; j < w1; j += 64) yr[H + j] = e1z[row * ld_e1 + j];
-  for (int j = lane; j < w2; j += 64) yr[H + w1 + j] = e2z[row * ld_e2 + j];
+  for (int j = lane; j < w1; j += 64) {
+    const float t = e1z[row * ld_e1 + j];
+    yr[H + j] = t;
+    if (yhr) yhr[H + j] = bf16_bits(t);
+  }
+  for (int j = lane; j < w2; j += 64) {
+    const float t = e2z[row * ld_e2 + j];
+    yr[H + w1 + j] = t;
+    if (yhr) yhr[H + w1 + j] = bf16_bits(t);
+  }
 }
 
 template <int E, bool VEC>
@@ -161,14 +194,15 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, l
                                                 int rows, int H, const float* __restrict__ g,
                                                 const float* __restrict__ beta, long long sz_par, int act_tanh,
                                                 float* __restrict__ y, long long ld_y, long long sz_y,
+                                                uint16_t* __restrict__ yh,
                                                 float* __restrict__ xhat, float* __restrict__ rstd,
                                                 const float* __restrict__ e1, long long ld_e1, int w1,
                                                 const float* __restrict__ e2, long long ld_e2, int w2,
                                                 LnGroups grp) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
-  ln_fwd_row<E, VEC>(pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1, ld_e1,
-                     w1, e2, ld_e2, w2, grp, row, blockIdx.y, threadIdx.x & 63);
+  ln_fwd_row<E, VEC>(pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, yh, xhat, rstd, e1,
+                     ld_e1, w1, e2, ld_e2, w2, grp, row, blockIdx.y, threadIdx.x & 63);
 }
 
 // row-block b (4 rows) of a job: batch b / cdiv(rows, 4)
@@ -178,7 +212,8 @@ __device__ __forceinline__ void ln_fwd_job_block(const LnFwdJob& j, int b) {
   const int row = (b % rb) * 4 + (threadIdx.x >> 6);
   if (row >= j.rows) return;
   ln_fwd_row<E, VEC>(j.pre, j.ld_pre, j.sz_pre, j.rows, j.H, j.g, j.beta, j.sz_par, j.act_tanh, j.y, j.ld_y, j.sz_y,
-                     j.xhat, j.rstd, j.e1, j.ld_e1, j.w1, j.e2, j.ld_e2, j.w2, j.grp, row, b / rb, threadIdx.x & 63);
+                     j.yh, j.xhat, j.rstd, j.e1, j.ld_e1, j.w1, j.e2, j.ld_e2, j.w2, j.grp, row, b / rb,
+                     threadIdx.x & 63);
 }
 
 // two LayerNorm problems of the same width in one launch: workgroups [0, blocks0)
@@ -207,6 +242,12 @@ static int ln_dispatch(int H, bool vec_ok, F&& f) {
   return f(std::integral_constant<int, 16>{}, std::false_type{});
 }
 
+// elements of y a LayerNorm forward writes, from its first
+static long long ln_out_extent(int rows, int H, int batch, long long ld_y, long long sz_y, int w1, int w2) {
+  if (rows <= 0 || batch <= 0) return 0;
+  return (long long)(batch - 1) * sz_y + (long long)(rows - 1) * ld_y + H + w1 + w2;
+}
+
 int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch, const float* g,
                const float* beta, long long sz_par, int act_tanh, float* y, long long ld_y, long long sz_y,
                float* xhat, float* rstd, const float* e1, long long ld_e1, int w1, const float* e2,
@@ -214,11 +255,12 @@ int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, i
   if (rows <= 0) return SQ_OK;
   const LnGroups grp = groups ? *groups : LnGroups{kNoAlt, nullptr, nullptr, 0, nullptr};
   const bool vec = al16(pre, ld_pre, sz_pre) && al16(y, ld_y, sz_y) && al16(xhat, H);
+  uint16_t* yh = twin_of(y, ln_out_extent(rows, H, batch, ld_y, sz_y, w1, w2));
   dim3 grid(cdiv(rows, 4), batch);
   return ln_dispatch(H, vec, [&](auto e, auto v) {
     k_ln_fwd<decltype(e)::value, decltype(v)::value><<<grid, 256, 0, st>>>(
-        pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1, ld_e1, w1, e2, ld_e2,
-        w2, grp);
+        pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, yh, xhat, rstd, e1, ld_e1, w1, e2,
+        ld_e2, w2, grp);
     return launch_status("ln_fwd");
   });
 }
@@ -228,7 +270,8 @@ LnFwdJob ln_fwd_job(const float* pre, long long ld_pre, long long sz_pre, int ro
                     float* xhat, float* rstd, const float* e1, long long ld_e1, int w1, const float* e2,
                     long long ld_e2, int w2, const LnGroups* groups) {
   return LnFwdJob{pre, ld_pre, sz_pre, rows, H, batch, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1,
-                  ld_e1, w1, e2, ld_e2, w2, groups ? *groups : LnGroups{kNoAlt, nullptr, nullptr, 0, nullptr}};
+                  ld_e1, w1, e2, ld_e2, w2, groups ? *groups : LnGroups{kNoAlt, nullptr, nullptr, 0, nullptr},
+                  twin_of(y, ln_out_extent(rows, H, batch, ld_y, sz_y, w1, w2))};
 }
 
 static int ln_fwd_alone(const LnFwdJob& j, hipStream_t st) {

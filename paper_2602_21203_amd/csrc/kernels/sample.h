@@ -6,6 +6,7 @@
 // squint launch that samples in extra workgroups; both give identical results.
 #pragma once
 #include "../common.h"
+#include "bf16.h"
 #include "philox.h"
 
 namespace sq {
@@ -15,6 +16,7 @@ struct SampleArgs {
   const float* proprio; const float* next_proprio; const float* action; const float* reward;
   const uint8_t* done;
   int* idx; float* eps2B; float* S2; float* Arep; long long ld_arep; float* r; float* d;
+  uint16_t* Arep_h;   // bfloat16 copy of Arep's buffer (nullable)
 };
 
 __host__ __device__ inline long long sample_items(int B, int A, int S) { return (long long)B * (2 * S + 3 * A + 2); }
@@ -40,7 +42,9 @@ __device__ __forceinline__ void sample_item(const SampleArgs& s, long long t) {
   }
   const int row = sample_row(s, b);
   if (it < A) {
-    s.Arep[(long long)b * s.ld_arep + it] = s.action[(long long)row * A + it];
+    const float a = s.action[(long long)row * A + it];
+    s.Arep[(long long)b * s.ld_arep + it] = a;
+    if (s.Arep_h) s.Arep_h[(long long)b * s.ld_arep + it] = bf16_bits(a);
   } else if (it == 3 * A) {
     s.r[b] = s.reward[row];
     s.idx[b] = row;

@@ -126,7 +126,8 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
       h[i] = e.h[i];
     }
     if (!prepared) SQ_TRY(encoder_prepare(net, bf16, ep, L, e, st));
-    return encoder_fused_fwd(bf16, d.C, d.F, d.n_conv, net.side, x, n, e.wprep, b, h, st);
+    uint16_t* hh = bf16 ? twin_of(h[d.n_conv - 1], (long long)n * net.flat) : nullptr;
+    return encoder_fused_fwd(bf16, d.C, d.F, d.n_conv, net.side, x, n, e.wprep, b, h, st, hh);
   }
   const float* in = x;
   int cin = d.C, hs = net.side;
