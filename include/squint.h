@@ -408,15 +408,17 @@ SQ_API int sq_bf16_operand_copies(int on);
 /* Linear-layer products enqueued on bfloat16 copies so far in this process
  * (launches recorded into a graph count once, at capture).  [host] */
 SQ_API int sq_bf16_copy_products(long long* n);
-/* C[z] = A[z] B[z]^T (+ bias[z*bias_sz + c]) on bfloat16 operands (bit patterns):
- * A [batch][M] rows of a_lr elements, B [batch][N] rows of b_lr elements,
- * k-contiguous, 16-byte aligned, rows at least K rounded up to 8 long, batches
- * a_sz / b_sz elements apart.  The kernel the bfloat16 forward products run;
- * FP32 accumulation in the order of sq_gemm's bfloat16 mode, so C equals
- * sq_gemm's result on the FP32 values of A and B. */
-SQ_API int sq_gemm_bf16(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_sz,
-                        const uint16_t* B, long long b_lr, long long b_sz, float* C, long long ldc, long long c_sz,
-                        const float* bias, long long bias_sz, sq_stream_t stream);
+/* C[z](r, c) = sum_k A[z](r, k) B[z](c, k) (+ bias[z*bias_sz + c]) on bfloat16
+ * operands (bit patterns), A[z](r, k) = A[z*a_sz + r*a_lr + k*a_lk] and B
+ * likewise.  Each operand is either k-contiguous (lk = 1: rows 16-byte aligned,
+ * holding K rounded up to 8 elements) or transposed (lr = 1: k-slices 16-byte
+ * aligned, holding its row count rounded up to 8 elements).  The kernel of the
+ * products that read bfloat16 copies; FP32 accumulation in the order of
+ * sq_gemm's bfloat16 mode, so C equals sq_gemm's result on the FP32 values of A
+ * and B. */
+SQ_API int sq_gemm_bf16(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_lk,
+                        long long a_sz, const uint16_t* B, long long b_lr, long long b_lk, long long b_sz, float* C,
+                        long long ldc, long long c_sz, const float* bias, long long bias_sz, sq_stream_t stream);
 /* idx[b] = mulhi32(Philox4x32_10(ctr = (update, 0, b, 0), key = seed).w0, size). */
 SQ_API int sq_sample_indices(unsigned long long seed, unsigned int update, int size, int n, int* idx,
                       sq_stream_t stream);

@@ -110,8 +110,8 @@ def _load():
         "sq_gemm_tile_order": (c_int, [c_int, c_int, c_int, c_int, P(c_int)]),
         "sq_bf16_operand_copies": (c_int, [c_int]),
         "sq_bf16_copy_products": (c_int, [P(c_ll)]),
-        "sq_gemm_bf16": (c_int, [c_int, c_int, c_int, c_int, c_vp, c_ll, c_ll, c_vp, c_ll, c_ll, c_vp, c_ll, c_ll,
-                                 c_vp, c_ll, c_vp]),
+        "sq_gemm_bf16": (c_int, [c_int, c_int, c_int, c_int, c_vp, c_ll, c_ll, c_ll, c_vp, c_ll, c_ll, c_ll, c_vp,
+                                 c_ll, c_ll, c_vp, c_ll, c_vp]),
         "encoder_fwd_noalloc": (c_int, [P(Dims), c_int, c_vp, c_vp, c_int, c_vp, c_vp]),
         "sq_encoder_noalloc_max_images": (c_int, [P(Dims), P(c_int)]),
     }

@@ -193,24 +193,33 @@ def gemm(prec, A, B, C=None, bias=None, accumulate=False, transpose_b=True, stre
 
 
 def _bf16_operand(t, name):
+    """(tensor [batch, rows, K], lr, lk, sz) of a bfloat16 operand: k-contiguous rows
+    holding K rounded up to 8, or contiguous rows (k strided) with k-slices holding
+    the row count rounded up to 8; 16-byte aligned."""
     t3 = t if t.dim() == 3 else t.unsqueeze(0)
-    if t3.dtype != torch.bfloat16 or not t3.is_cuda or t3.stride(2) != 1:
-        raise ValueError(f"{name}: bfloat16 device tensor with k-contiguous rows expected")
+    if t3.dtype != torch.bfloat16 or not t3.is_cuda:
+        raise ValueError(f"{name}: bfloat16 device tensor expected")
     batch, rows, K = t3.shape
-    lr, sz = t3.stride(1), (t3.stride(0) if batch > 1 else 0)
-    k8 = (K + 7) // 8 * 8
-    need = t3.storage_offset() + (batch - 1) * sz + (rows - 1) * lr + k8
-    if lr % 8 or sz % 8 or lr < k8 or need > t3.untyped_storage().nbytes() // 2:
-        raise ValueError(f"{name}: rows must be 16-byte aligned and hold K rounded up to 8 elements")
-    return t3, lr, sz
+    lr, lk, sz = t3.stride(1), t3.stride(2), (t3.stride(0) if batch > 1 else 0)
+    r8 = lambda x: (x + 7) // 8 * 8
+    if lk == 1:
+        ld, n_lines, length = lr, rows, r8(K)
+    elif lr == 1:
+        ld, n_lines, length = lk, K, r8(rows)
+    else:
+        raise ValueError(f"{name}: k-contiguous rows or contiguous rows expected")
+    need = t3.storage_offset() + (batch - 1) * sz + (n_lines - 1) * ld + length
+    if ld % 8 or sz % 8 or ld < length or t3.data_ptr() % 16 or need > t3.untyped_storage().nbytes() // 2:
+        raise ValueError(f"{name}: lines must be 16-byte aligned and hold their length rounded up to 8 elements")
+    return t3, lr, lk, sz
 
 
 def gemm_bf16(A, B, C=None, bias=None, stream=None):
-    """C[z] = A[z] @ B[z]^T (+ bias) on bfloat16 operands (A [batch, M, K], B [batch, N, K],
-    k-contiguous rows that hold K rounded up to 8 elements): the kernel of the bfloat16
-    forward products, equal to gemm(SQ_BF16, ...) on the FP32 values of A and B."""
-    a3, a_lr, a_sz = _bf16_operand(A, "A")
-    b3, b_lr, b_sz = _bf16_operand(B, "B")
+    """C[z] = A[z] @ B[z]^T (+ bias) on bfloat16 operands (A [batch, M, K], B [batch, N, K];
+    each k-contiguous, or transposed with contiguous rows): the kernel of the products
+    that read bfloat16 copies, equal to gemm(SQ_BF16, ...) on the FP32 values of A and B."""
+    a3, a_lr, a_lk, a_sz = _bf16_operand(A, "A")
+    b3, b_lr, b_lk, b_sz = _bf16_operand(B, "B")
     batch, M, K = a3.shape
     N = b3.shape[1]
     if b3.shape[2] != K or b3.shape[0] not in (1, batch):
@@ -223,9 +232,9 @@ def gemm_bf16(A, B, C=None, bias=None, stream=None):
     bias_sz = 0
     if bias is not None:
         bias_sz = bias.stride(0) if bias.dim() == 2 and bias.shape[0] > 1 else 0
-    check(L.LIB.sq_gemm_bf16(M, N, K, batch, ptr(a3), a_lr, a_sz, ptr(b3), b_lr, b_sz if b3.shape[0] > 1 else 0,
-                             ptr(c3), c3.stride(1), c3.stride(0) if batch > 1 else 0, ptr(bias), bias_sz,
-                             stream_handle(stream)))
+    check(L.LIB.sq_gemm_bf16(M, N, K, batch, ptr(a3), a_lr, a_lk, a_sz, ptr(b3), b_lr, b_lk,
+                             b_sz if b3.shape[0] > 1 else 0, ptr(c3), c3.stride(1), c3.stride(0) if batch > 1 else 0,
+                             ptr(bias), bias_sz, stream_handle(stream)))
     return C
 
 

@@ -264,15 +264,15 @@ int sq_bf16_copy_products(long long* n) {
   return SQ_OK;
 }
 
-int sq_gemm_bf16(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_sz,
-                 const uint16_t* B, long long b_lr, long long b_sz, float* C, long long ldc, long long c_sz,
-                 const float* bias, long long bias_sz, sq_stream_t stream) {
+int sq_gemm_bf16(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_lk, long long a_sz,
+                 const uint16_t* B, long long b_lr, long long b_lk, long long b_sz, float* C, long long ldc,
+                 long long c_sz, const float* bias, long long bias_sz, sq_stream_t stream) {
   SQ_REQUIRE(M >= 0 && N >= 0 && K >= 0 && batch >= 0, "negative size");
   if (M == 0 || N == 0 || batch == 0) return SQ_OK;
   SQ_REQUIRE(K > 0, "sq_gemm_bf16 needs K > 0");
   SQ_REQUIRE(C && ldc >= N, "NULL C or ldc < N");
   OutArg c{C, ldc, c_sz, bias, bias_sz, 0, 0};
-  return gemm_bf16_stored(M, N, K, batch, A, a_lr, a_sz, B, b_lr, b_sz, c, (hipStream_t)stream);
+  return gemm_bf16_stored(M, N, K, batch, A, a_lr, a_lk, a_sz, B, b_lr, b_lk, b_sz, c, (hipStream_t)stream);
 }
 
 int sq_gemm_tile_order(int b, int gx, int gy, int gz, int* tile) {

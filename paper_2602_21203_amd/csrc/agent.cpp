@@ -18,6 +18,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "ops.h"
@@ -163,21 +164,24 @@ static size_t plan_agent(sq_agent* g, char* base) {
   return b.off + 256;
 }
 
-// In the bfloat16 mode the packed weights and every activation buffer that feeds
-// a forward product get bfloat16 copies, kept by their producers (LayerNorm, the
+// In the bfloat16 mode the packed weights, every activation buffer that a product
+// reads and the LayerNorm input gradients (dB) the backward products read get
+// bfloat16 copies, kept by their producers (LayerNorm forward and backward, the
 // fused encoder, the minibatch draw, the policy head, pack and Adam), so those
-// products read half the bytes.  Only buffers whose every producer writes the
-// copy are registered.
+// products read half the bytes.  Only buffers whose every producer writes the copy
+// are registered (the products' own outputs, dA and dX1, are read by LayerNorm
+// only and have none).
 static int make_twins(sq_agent* g) {
   const Net& net = g->net;
   const sq_dims& d = net.d;
-  const size_t B = (size_t)g->B, H = (size_t)d.hidden;
+  const size_t B = (size_t)g->B, H = (size_t)d.hidden, w = (size_t)std::max(d.hidden, d.proj);
   struct Item { const float* f; size_t n; };
   std::vector<Item> items = {
       {g->pack, (size_t)g->L.pack_total}, {g->tpack, (size_t)g->L.pack_critic_end},
       {g->crit.X1, 2 * B * net.cpad},     {g->crit.g1, 4 * B * H},  {g->crit.g2, 4 * B * H},
       {g->aux.X1, B * net.cpad},          {g->aux.g1, 2 * B * H},   {g->aux.g2, 2 * B * H},
-      {g->actor.X1, 2 * B * net.apad},    {g->actor.g1, 2 * B * H}, {g->actor.g2, 2 * B * H}};
+      {g->actor.X1, 2 * B * net.apad},    {g->actor.g1, 2 * B * H}, {g->actor.g2, 2 * B * H},
+      {g->crit.dB, 2 * B * w},            {g->aux.dB, 2 * B * w},   {g->actor.dB, 2 * B * w}};
   if (d.n_conv > 0 && encoder_fused(net, 1, g->enc)) items.push_back({g->enc.h[d.n_conv - 1], 2 * B * net.flat});
   Bump b{nullptr};
   for (const Item& it : items) b.take<uint16_t>(it.n);

@@ -211,10 +211,12 @@ struct OutArg {            // C(r, c) at p[z*sz + r*ld + c]
 // scratch (nullable) enables a deterministic split over K for small outputs.
 int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C, float* scratch,
          size_t scratch_floats, hipStream_t st);
-// C = A B^T (+ bias) on bfloat16-stored operands (A [batch][M][a_lr], B [batch][N][b_lr],
-// k-contiguous rows), the product the bfloat16 mode runs when both operands have copies
-int gemm_bf16_stored(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_sz,
-                     const uint16_t* B, long long b_lr, long long b_sz, OutArg C, hipStream_t st);
+// C = A B^T (+ bias) on bfloat16-stored operands, A(r, k) = A[z a_sz + r a_lr + k a_lk]
+// with a_lk == 1 or a_lr == 1 (B likewise): the product the bfloat16 mode runs when
+// both operands have copies
+int gemm_bf16_stored(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_lk,
+                     long long a_sz, const uint16_t* B, long long b_lr, long long b_lk, long long b_sz, OutArg C,
+                     hipStream_t st);
 // twins.cpp: bfloat16 copies ("twins") of FP32 operand buffers, written by the
 // buffers' producers and read by the products in the bfloat16 mode
 int twins_enabled();

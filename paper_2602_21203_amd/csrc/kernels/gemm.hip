@@ -756,22 +756,29 @@ __global__ __launch_bounds__(kThreads) void k_gemm_pair_f(RProb p0, RProb p1, in
 }
 
 // ---------------------------------------------------------------- bfloat16-stored operands
-// Products whose two operands both have bfloat16 copies (k-contiguous rows, 16-byte
-// aligned; written by the operands' producers) read the copies: 8 elements per
-// 16-byte lane load, half the bytes and half the load instructions of the FP32
-// form, and no conversion.  The tile, the wave split of K, the chunk order and the
-// final sum are those of gemm_tile, so the result is the same bit for bit.
-// Two load forms: DIRECT, lane (li, lq) loads its own fragment (rows li and
-// 16 + li, k = 8 lq .. 8 lq + 7 of the chunk) from memory; otherwise four lanes
-// cover a row's 64 bytes of the chunk and the chunk is rearranged through the
-// wave's LDS tile.  The direct form is faster for short K ranges per wave, the
-// LDS form once each wave reads four chunks or more.
+// Products whose two operands both have bfloat16 copies (written by the operands'
+// producers) read the copies: 8 elements per 16-byte lane load, half the bytes and
+// half the load instructions of the FP32 form, and no conversion.  The tile, the
+// wave split of K, the chunk order, each lane's k positions in the fragments and
+// the final sum are those of gemm_tile, so the result is the same bit for bit.
+//
+// An operand is read in one of two orientations:
+//  - plain (k-contiguous rows): four lanes cover a row's 64 bytes of a chunk;
+//  - transposed (rows contiguous, k strided -- dY and X of a weight gradient, W
+//    of an input gradient): four lanes cover 32 rows at one k, and the chunk is
+//    written transposed into the wave's LDS tile.
+// Fragments are then read from the LDS tile; a transposed operand's tile swizzles
+// its 16-byte k groups by row (group g of row c sits at g ^ (c / 8) mod 4), so the
+// transposing stores of the 64 lanes spread over the banks.  DIRECT (both operands plain, short K
+// ranges): lane (li, lq) loads its fragment (rows li and 16 + li, k = 8 lq ..
+// 8 lq + 7 of the chunk) straight from memory.
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 struct HMat {
-  const uint16_t* p; long long lr, sz;
+  const uint16_t* p; long long ld, sz;   // ld: between rows (plain) or between k (transposed)
   const uint16_t* alt; int zalt, zdiv;
-  int kmax;   // the last 8-element group start inside every row: rows hold at least kmax + 8 elements
+  const uint16_t* kp; int kalt;          // k >= kalt read from kp (+ z sz) at k - kalt
+  int lim;   // the last 8-element group start inside every line: k (plain) or row (transposed)
   __device__ __forceinline__ const uint16_t* batch(int z) const {
     const int zi = z / zdiv;
     return zi < zalt ? p + (long long)zi * sz : alt + (long long)(zi - zalt) * sz;
@@ -779,6 +786,15 @@ struct HMat {
 };
 
 constexpr int kHMaxC = 4;   // chunks of a wave in flight at once
+constexpr int kHLdt = 40;   // row stride of a wave's LDS tile (elements)
+constexpr int kHTile = 32 * kHLdt;
+
+// element (c, k) of a wave's tile; a transposed operand's tile swizzles its 16-byte k groups
+template <bool T>
+__device__ __forceinline__ int hpos(int c, int k) {
+  if constexpr (T) return c * kHLdt + ((((k >> 3) ^ (c >> 3)) & 3) << 3) + (k & 7);
+  return c * kHLdt + k;
+}
 
 // elements k >= kend of a loaded group starting at kq read as zero
 __device__ __forceinline__ u4v hmask(u4v v, int kq, int kend) {
@@ -791,40 +807,79 @@ __device__ __forceinline__ u4v hmask(u4v v, int kq, int kend) {
   return v;
 }
 
-// one operand's part of chunk k0: two 16-byte groups per lane
-template <bool DIRECT>
-__device__ __forceinline__ void hload(const uint16_t* base, long long lr, int kmax, int r0, int rows, int k0,
-                                      int lane, u4v (&v)[2]) {
+// one operand's part of chunk k0: two 16-byte groups per lane, at clamped addresses
+// (rows, k-slices and groups past the end reread valid data; hmask_chunk zeroes
+// what lies past the K range)
+template <bool DIRECT, bool T, bool KP>
+__device__ __forceinline__ void hload(const HMat& m, const uint16_t* base, const uint16_t* kbase, int r0, int rows,
+                                      int k0, int kend, int lane, u4v (&v)[2]) {
+  if (KP && k0 >= m.kalt) {   // uniform: kalt is a multiple of the chunk
+    base = kbase;
+    k0 -= m.kalt;
+    kend -= m.kalt;
+  }
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    const int r = min(r0 + (DIRECT ? 16 * j + (lane & 15) : 16 * j + (lane >> 2)), rows - 1);
-    const int kq = k0 + (DIRECT ? 8 * (lane >> 4) : 8 * (lane & 3));
-    v[j] = *reinterpret_cast<const u4v*>(base + (long long)r * lr + min(kq, kmax));
+    if constexpr (T) {
+      const int k = min(k0 + 16 * j + (lane >> 2), kend - 1);
+      v[j] = *reinterpret_cast<const u4v*>(base + (long long)k * m.ld + min(r0 + 8 * (lane & 3), m.lim));
+    } else {
+      const int r = min(r0 + (DIRECT ? 16 * j + (lane & 15) : 16 * j + (lane >> 2)), rows - 1);
+      const int kq = k0 + (DIRECT ? 8 * (lane >> 4) : 8 * (lane & 3));
+      v[j] = *reinterpret_cast<const u4v*>(base + (long long)r * m.ld + min(kq, m.lim));
+    }
   }
 }
 
-template <bool DIRECT>
+// the K range's partial last chunk: elements k >= kend read as zero
+template <bool DIRECT, bool T>
 __device__ __forceinline__ void hmask_chunk(u4v (&v)[2], int k0, int kend, int lane) {
-  const int kq = k0 + (DIRECT ? 8 * (lane >> 4) : 8 * (lane & 3));
 #pragma unroll
-  for (int j = 0; j < 2; ++j) v[j] = hmask(v[j], kq, kend);
+  for (int j = 0; j < 2; ++j) {
+    if constexpr (T) {
+      if (k0 + 16 * j + (lane >> 2) >= kend) v[j] = u4v{0u, 0u, 0u, 0u};
+    } else {
+      v[j] = hmask(v[j], k0 + (DIRECT ? 8 * (lane >> 4) : 8 * (lane & 3)), kend);
+    }
+  }
+}
+
+// a loaded chunk into the wave's LDS tile, as [row][k]
+template <bool T>
+__device__ __forceinline__ void hstage(const u4v (&v)[2], uint16_t* tile, int lane) {
+  const int q = lane & 3;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int r = 16 * j + (lane >> 2);   // plain: the row; transposed: the k
+    if constexpr (T) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const unsigned w = v[j][e >> 1];
+        tile[hpos<true>(8 * q + e, r)] = (uint16_t)((e & 1) ? (w >> 16) : (w & 0xffffu));
+      }
+    } else {
+      *reinterpret_cast<u4v*>(tile + hpos<false>(r, 8 * q)) = v[j];
+    }
+  }
 }
 
 template <bool DIRECT>
 constexpr int hgemm_lds_bytes() {
   constexpr int RED_BYTES = 4 * kTile * (kTile + 1) * 4;
-  constexpr int TILE_BYTES = DIRECT ? 0 : 4 * RLds<true>::WAVE * 2;
+  constexpr int TILE_BYTES = DIRECT ? 0 : 4 * 2 * 2 * kHTile * 2;
   return TILE_BYTES > RED_BYTES ? TILE_BYTES : RED_BYTES;
 }
 
-template <bool DIRECT, class ST>
+template <bool DIRECT, bool TA, bool TB, bool KP, class ST>
 __device__ __forceinline__ void gemm_tile_h(const HMat& fa, const HMat& fb, const ST& st, int M, int N, int K, int bx,
                                             int by, int bz, char* lds) {
-  using LL = RLds<true>;
+  static_assert(!DIRECT || (!TA && !TB), "the direct form reads plain operands");
   constexpr int KC = kRKC;
   const int m0 = bx * kTile, n0 = by * kTile;
   const uint16_t* ab = fa.batch(bz);
   const uint16_t* bb = fb.batch(bz);
+  const uint16_t* akp = KP ? fa.kp + (long long)bz * fa.sz : nullptr;
+  const uint16_t* bkp = KP ? fb.kp + (long long)bz * fb.sz : nullptr;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lq = lane >> 4;
@@ -833,7 +888,7 @@ __device__ __forceinline__ void gemm_tile_h(const HMat& fa, const HMat& fb, cons
   const int wb = wave * per;
   const int we = min(K, wb + per);
   const int nch = we > wb ? (we - wb + KC - 1) / KC : 0;
-  __bf16* wt = reinterpret_cast<__bf16*>(lds) + wave * LL::WAVE;
+  uint16_t* wt = reinterpret_cast<uint16_t*>(lds) + wave * (2 * 2 * kHTile);
 
   v4f acc[2][2];
 #pragma unroll
@@ -847,16 +902,16 @@ __device__ __forceinline__ void gemm_tile_h(const HMat& fa, const HMat& fb, cons
     for (int c = 0; c < kHMaxC; ++c) {
       if (g + c < nch) {
         const int k0 = wb + (g + c) * KC;
-        hload<DIRECT>(ab, fa.lr, fa.kmax, m0, M, k0, lane, ra[c]);
-        hload<DIRECT>(bb, fb.lr, fb.kmax, n0, N, k0, lane, rb[c]);
+        hload<DIRECT, TA, KP>(fa, ab, akp, m0, M, k0, we, lane, ra[c]);
+        hload<DIRECT, TB, KP>(fb, bb, bkp, n0, N, k0, we, lane, rb[c]);
       }
     }
 #pragma unroll
     for (int c = 0; c < kHMaxC; ++c) {
       const int k0 = wb + (g + c) * KC;
-      if (g + c < nch && k0 + KC > we) {   // the range's partial last chunk
-        hmask_chunk<DIRECT>(ra[c], k0, we, lane);
-        hmask_chunk<DIRECT>(rb[c], k0, we, lane);
+      if (g + c < nch && k0 + KC > we) {
+        hmask_chunk<DIRECT, TA>(ra[c], k0, we, lane);
+        hmask_chunk<DIRECT, TB>(rb[c], k0, we, lane);
       }
     }
     if constexpr (DIRECT) {
@@ -879,12 +934,8 @@ __device__ __forceinline__ void gemm_tile_h(const HMat& fa, const HMat& fb, cons
 #pragma unroll
         for (int c2 = 0; c2 < 2; ++c2) {
           if (g + h + c2 < nch) {
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              const int r = 16 * j + (lane >> 2), kq = 8 * (lane & 3);
-              *reinterpret_cast<u4v*>(wt + (2 * c2) * LL::TILE + r * LL::LDT + kq) = ra[h + c2][j];
-              *reinterpret_cast<u4v*>(wt + (2 * c2 + 1) * LL::TILE + r * LL::LDT + kq) = rb[h + c2][j];
-            }
+            hstage<TA>(ra[h + c2], wt + (2 * c2) * kHTile, lane);
+            hstage<TB>(rb[h + c2], wt + (2 * c2 + 1) * kHTile, lane);
           }
         }
         lds_wave_sync();
@@ -894,8 +945,8 @@ __device__ __forceinline__ void gemm_tile_h(const HMat& fa, const HMat& fb, cons
             bf16x8 a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-              a[i] = *reinterpret_cast<const bf16x8*>(wt + (2 * c2) * LL::TILE + (16 * i + li) * LL::LDT + 8 * lq);
-              b[i] = *reinterpret_cast<const bf16x8*>(wt + (2 * c2 + 1) * LL::TILE + (16 * i + li) * LL::LDT + 8 * lq);
+              a[i] = *reinterpret_cast<const bf16x8*>(wt + (2 * c2) * kHTile + hpos<TA>(16 * i + li, 8 * lq));
+              b[i] = *reinterpret_cast<const bf16x8*>(wt + (2 * c2 + 1) * kHTile + hpos<TB>(16 * i + li, 8 * lq));
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
@@ -912,31 +963,43 @@ __device__ __forceinline__ void gemm_tile_h(const HMat& fa, const HMat& fb, cons
   tile_out<ST, false>(acc, st, none, M, N, m0, n0, bz, 0, wave, lane, lds);
 }
 
-template <bool DIRECT, class ST>
+// the form of a bfloat16-copy product: transposed B (1), transposed A (2), the
+// direct form (4), k-concatenated operands (8)
+template <int FORM> struct HForm {
+  static constexpr bool D = (FORM & 4) != 0, TA = (FORM & 2) != 0, TB = (FORM & 1) != 0, KP = (FORM & 8) != 0;
+};
+constexpr int kHDirect = 4, kHKp = 8;
+
+template <int FORM, class ST>
 __global__ __launch_bounds__(kThreads) void k_gemm_h(HMat fa, HMat fb, ST st, int M, int N, int K) {
-  __shared__ __attribute__((aligned(16))) char lds[hgemm_lds_bytes<DIRECT>()];
+  using F = HForm<FORM>;
+  __shared__ __attribute__((aligned(16))) char lds[hgemm_lds_bytes<F::D>()];
   int bx, by, bz;
   tile_of(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), gridDim.x, gridDim.y, gridDim.z, bx, by,
           bz);
-  gemm_tile_h<DIRECT, ST>(fa, fb, st, M, N, K, bx, by, bz, lds);
+  gemm_tile_h<F::D, F::TA, F::TB, F::KP, ST>(fa, fb, st, M, N, K, bx, by, bz, lds);
 }
 
-// two forward products on bfloat16 copies in one launch (as k_gemm_pair_f)
+// two products on bfloat16 copies in one launch (the forward pair of k_gemm_pair_f,
+// or a layer's input and weight gradients as in k_gemm_pair)
 struct HProb {
   HMat a, b; StMat st; int M, N, K, gx, gy;
 };
 
-template <bool DIRECT>
+template <int F0, int F1>
 __global__ __launch_bounds__(kThreads) void k_gemm_pair_h(HProb p0, HProb p1, int tiles0) {
-  __shared__ __attribute__((aligned(16))) char lds[hgemm_lds_bytes<DIRECT>()];
+  using G0 = HForm<F0>;
+  using G1 = HForm<F1>;
+  constexpr int L0 = hgemm_lds_bytes<G0::D>(), L1 = hgemm_lds_bytes<G1::D>();
+  __shared__ __attribute__((aligned(16))) char lds[L0 > L1 ? L0 : L1];
   int b = blockIdx.x;
   if (b < tiles0) {
-    gemm_tile_h<DIRECT, StMat>(p0.a, p0.b, p0.st, p0.M, p0.N, p0.K, b % p0.gx, (b / p0.gx) % p0.gy,
-                               b / (p0.gx * p0.gy), lds);
+    gemm_tile_h<G0::D, G0::TA, G0::TB, G0::KP, StMat>(p0.a, p0.b, p0.st, p0.M, p0.N, p0.K, b % p0.gx,
+                                                      (b / p0.gx) % p0.gy, b / (p0.gx * p0.gy), lds);
   } else {
     b -= tiles0;
-    gemm_tile_h<DIRECT, StMat>(p1.a, p1.b, p1.st, p1.M, p1.N, p1.K, b % p1.gx, (b / p1.gx) % p1.gy,
-                               b / (p1.gx * p1.gy), lds);
+    gemm_tile_h<G1::D, G1::TA, G1::TB, G1::KP, StMat>(p1.a, p1.b, p1.st, p1.M, p1.N, p1.K, b % p1.gx,
+                                                      (b / p1.gx) % p1.gy, b / (p1.gx * p1.gy), lds);
   }
 }
 
@@ -1027,51 +1090,112 @@ static int want_splits(int M, int N, int K, int batch, const float* scratch, siz
   return splits;
 }
 
-// the bfloat16 copy of operand m of a product with `rows` rows and contraction K
-// over `batch` batches, when every batch it reads has one (rows k-contiguous,
-// 16-byte aligned, at least K rounded up to 8 elements long)
-static bool hmat(const MatArg& m, int rows, int K, int batch, HMat* out) {
-  if (m.kp || m.lk != 1 || m.lr % 8 || m.sz % 8 || rows <= 0 || K <= 0) return false;
-  const long long k8 = (K + 7) / 8 * 8;
-  if (m.lr < k8) return false;
+// The bfloat16 copy of operand m of a product (`rows` rows, contraction K, `batch`
+// batches) when every batch it reads has one, in one of the two orientations:
+// plain (k-contiguous rows) or transposed (rows contiguous, k strided; *t set).
+// Lines (rows, or k-slices) must be 16-byte aligned and hold the rounded-up
+// extent the loads touch; a k-concatenated operand (kp) needs whole chunks on
+// both sides of kalt.
+static bool hmat(const MatArg& m, int rows, int K, int batch, HMat* out, bool* t) {
+  const bool plain = m.lk == 1, trans = m.lr == 1 && m.lk > 1;
+  if ((!plain && !trans) || rows <= 0 || K <= 0 || batch <= 0 || m.sz % 8) return false;
+  const long long ld = plain ? m.lr : m.lk;
+  if (ld % 8) return false;
+  const bool kp = m.kp != nullptr;
+  if (kp && (m.kalt <= 0 || m.kalt >= K || m.kalt % kRKC || (K - m.kalt) % kRKC)) return false;
+  const long long kfirst = kp ? m.kalt : K, ksecond = kp ? K - m.kalt : 0;
+  auto r8 = [](long long x) { return (x + 7) / 8 * 8; };
+  long long len, ext_p, ext_kp;
+  if (plain) {
+    len = r8(std::max(kfirst, ksecond));
+    ext_p = (long long)(rows - 1) * ld + len;
+    ext_kp = ext_p;
+  } else {
+    len = r8(rows);
+    ext_p = (kfirst - 1) * ld + len;
+    ext_kp = (ksecond - 1) * ld + len;
+  }
+  if (ld < len) return false;
   const int nb = cdiv(batch, m.zdiv);
   const int np = std::min(nb, m.zalt);
-  const long long ext = (long long)(rows - 1) * m.lr + k8;
-  const uint16_t* hp = np > 0 ? twin_of(m.p, (long long)(np - 1) * m.sz + ext) : nullptr;
-  if (np > 0 && (!hp || (uintptr_t)hp % 16)) return false;
+  auto ok = [](const uint16_t* h) { return h && (uintptr_t)h % 16 == 0; };
+  const uint16_t* hp = np > 0 ? twin_of(m.p, (long long)(np - 1) * m.sz + ext_p) : nullptr;
+  if (np > 0 && !ok(hp)) return false;
   const uint16_t* ha = nullptr;
   if (nb > np) {
-    ha = twin_of(m.alt, (long long)(nb - np - 1) * m.sz + ext);
-    if (!ha || (uintptr_t)ha % 16) return false;
+    ha = twin_of(m.alt, (long long)(nb - np - 1) * m.sz + ext_p);
+    if (!ok(ha)) return false;
   }
-  *out = HMat{hp, m.lr, m.sz, ha, m.zalt, m.zdiv, (int)(k8 - 8)};
+  const uint16_t* hk = nullptr;
+  if (kp) {
+    hk = twin_of(m.kp, (long long)(batch - 1) * m.sz + ext_kp);
+    if (!ok(hk)) return false;
+  }
+  *out = HMat{hp, ld, m.sz, ha, m.zalt, m.zdiv, hk, kp ? m.kalt : kNoAlt, (int)(len - 8)};
+  *t = trans;
   return true;
 }
 
-// the direct load form for short per-wave K ranges (at most three chunks)
-static bool h_direct(int K) { return cdiv(cdiv(K, 4), kRKC) <= 3; }
+// the direct load form for plain operands and short per-wave K ranges (at most three
+// chunks); kp: an operand is k-concatenated
+static int hform(bool ta, bool tb, int K, bool kp = false) {
+  if (!ta && !tb && !kp && cdiv(cdiv(K, 4), kRKC) <= 3) return kHDirect;
+  return (ta ? 2 : 0) | (tb ? 1 : 0) | (kp ? kHKp : 0);
+}
+static bool hkp(const HMat& a, const HMat& b) { return a.kp != nullptr || b.kp != nullptr; }
+
+template <int FORM, class ST>
+static void launch_h(dim3 grid, const HMat& a, const HMat& b, const ST& out, int M, int N, int K, hipStream_t st) {
+  k_gemm_h<FORM, ST><<<grid, kThreads, 0, st>>>(a, b, out, M, N, K);
+}
 
 template <class ST>
-static int run_h(int M, int N, int K, int batch, const HMat& a, const HMat& b, const ST& out, hipStream_t st) {
-  dim3 grid(cdiv(M, kTile), cdiv(N, kTile), batch);
-  if (h_direct(K)) k_gemm_h<true, ST><<<grid, kThreads, 0, st>>>(a, b, out, M, N, K);
-  else k_gemm_h<false, ST><<<grid, kThreads, 0, st>>>(a, b, out, M, N, K);
+static int run_h(int form, dim3 grid, const HMat& a, const HMat& b, const ST& out, int M, int N, int K,
+                 hipStream_t st) {
+  switch (form) {
+    case 0: launch_h<0>(grid, a, b, out, M, N, K, st); break;
+    case 1: launch_h<1>(grid, a, b, out, M, N, K, st); break;
+    case 2: launch_h<2>(grid, a, b, out, M, N, K, st); break;
+    case 3: launch_h<3>(grid, a, b, out, M, N, K, st); break;
+    case kHDirect: launch_h<kHDirect>(grid, a, b, out, M, N, K, st); break;
+    case kHKp | 1: launch_h<kHKp | 1>(grid, a, b, out, M, N, K, st); break;
+    default: return 1;
+  }
   note_copy_product();
   return launch_status("gemm_h");
 }
 
-int gemm_bf16_stored(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_sz,
-                     const uint16_t* B, long long b_lr, long long b_sz, OutArg C, hipStream_t st) {
+// the product on bfloat16 copies when both operands have them (SQ_OK, or 1: not eligible)
+static int try_h(int M, int N, int K, int batch, const MatArg& A, const MatArg& B, const StMat& out, hipStream_t st) {
+  HMat ha, hb;
+  bool ta, tb;
+  if (!hmat(A, M, K, batch, &ha, &ta) || !hmat(B, N, K, batch, &hb, &tb)) return 1;
+  return run_h(hform(ta, tb, K, hkp(ha, hb)), dim3(cdiv(M, kTile), cdiv(N, kTile), batch), ha, hb, out, M, N, K, st);
+}
+
+// an operand given as bfloat16 bits: plain (lk == 1) or transposed (lr == 1)
+static bool hraw(const uint16_t* p, long long lr, long long lk, long long sz, int rows, int K, HMat* out, bool* t) {
+  const bool plain = lk == 1, trans = lr == 1 && lk > 1;
+  const long long ld = plain ? lr : lk, len = plain ? (K + 7) / 8 * 8 : (rows + 7) / 8 * 8;
+  if ((!plain && !trans) || !p || (uintptr_t)p % 16 || ld % 8 || sz % 8 || ld < len) return false;
+  *out = HMat{p, ld, sz, nullptr, kNoAlt, 1, nullptr, kNoAlt, (int)(len - 8)};
+  *t = trans;
+  return true;
+}
+
+int gemm_bf16_stored(int M, int N, int K, int batch, const uint16_t* A, long long a_lr, long long a_lk,
+                     long long a_sz, const uint16_t* B, long long b_lr, long long b_lk, long long b_sz, OutArg C,
+                     hipStream_t st) {
   if (M <= 0 || N <= 0 || batch <= 0) return SQ_OK;
-  const long long k8 = (K + 7) / 8 * 8;
-  if (K <= 0 || !A || !B || !C.p || (uintptr_t)A % 16 || (uintptr_t)B % 16 || a_lr % 8 || b_lr % 8 || a_sz % 8 ||
-      b_sz % 8 || a_lr < k8 || b_lr < k8) {
-    set_error("gemm_bf16: operands need 16-byte aligned rows of at least K rounded up to 8 elements");
+  HMat a, b;
+  bool ta, tb;
+  if (K <= 0 || !C.p || !hraw(A, a_lr, a_lk, a_sz, M, K, &a, &ta) || !hraw(B, b_lr, b_lk, b_sz, N, K, &b, &tb)) {
+    set_error("gemm_bf16: each operand needs k-contiguous rows (or contiguous rows, k strided), 16-byte aligned, "
+              "of at least K (or its rows) rounded up to 8 elements");
     return SQ_EINVAL;
   }
-  const HMat a{A, a_lr, a_sz, nullptr, kNoAlt, 1, (int)(k8 - 8)};
-  const HMat b{B, b_lr, b_sz, nullptr, kNoAlt, 1, (int)(k8 - 8)};
-  return run_h(M, N, K, batch, a, b, stmat(C), st);
+  return run_h(hform(ta, tb, K), dim3(cdiv(M, kTile), cdiv(N, kTile), batch), a, b, stmat(C), M, N,
+               K, st);
 }
 
 template <bool BF16, int AV, int BV>
@@ -1108,8 +1232,8 @@ int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C,
   const StMat out = stmat(C);
   const int va = rkind(A), vb = rkind(B);
   if (bf16 && want_splits(M, N, K, batch, scratch, scratch_floats) == 1) {
-    HMat ha, hb;
-    if (hmat(A, M, K, batch, &ha) && hmat(B, N, K, batch, &hb)) return run_h(M, N, K, batch, ha, hb, out, st);
+    const int h = try_h(M, N, K, batch, A, B, out, st);
+    if (h != 1) return h;
   }
   if (bf16) {
     if (va && vb) return run_r<true, 1, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
@@ -1149,9 +1273,10 @@ int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const flo
   const StPart none{nullptr, 0, 0, 1};
   dim3 grid(cdiv(n, kTile), 1, 1);
   HMat hx, hw;
-  if (bf16 && hmat(X, n, K, 1, &hx) && hmat(W, 2 * A, K, 1, &hw)) {
-    if (h_direct(K)) k_gemm_h<true, StTanhGauss><<<grid, kThreads, 0, st>>>(hx, hw, tg, n, 2 * A, K);
-    else k_gemm_h<false, StTanhGauss><<<grid, kThreads, 0, st>>>(hx, hw, tg, n, 2 * A, K);
+  bool tx, tw;
+  if (bf16 && hmat(X, n, K, 1, &hx, &tx) && hmat(W, 2 * A, K, 1, &hw, &tw) && !tx && !tw && !hkp(hx, hw)) {
+    if (hform(false, false, K) == kHDirect) launch_h<kHDirect>(grid, hx, hw, tg, n, 2 * A, K, st);
+    else launch_h<0>(grid, hx, hw, tg, n, 2 * A, K, st);
     note_copy_product();
     return launch_status("gemm_tanh_gauss");
   }
@@ -1175,6 +1300,14 @@ int gemm_tg_bwd(int bf16, const GemmProb& dx, int A, const TgBwdJob& tg, hipStre
   const StTgBwd ep{tg.save, tg.eps, tg.dlogp_vec, tg.dlogp_scalar, tg.scale, tg.lo, tg.hi, tg.dhead, tg.part, A};
   const StPart none{nullptr, 0, 0, 1};
   dim3 grid(cdiv(n, kTile), 1, 1);
+  HMat ha, hb;
+  bool ta, tb;
+  if (bf16 && hmat(dx.A, n, dx.K, 1, &ha, &ta) && hmat(dx.B, A, dx.K, 1, &hb, &tb) && !ta && tb) {
+    if (hkp(ha, hb)) launch_h<kHKp | 1>(grid, ha, hb, ep, n, A, dx.K, st);
+    else launch_h<1>(grid, ha, hb, ep, n, A, dx.K, st);
+    note_copy_product();
+    return launch_status("gemm_tg_bwd");
+  }
   if (bf16)
     k_gemm_r<true, 1, 0, StTgBwd, false><<<grid, kThreads, 0, st>>>(rmat(dx.A), rmat(dx.B), ep, none, n, A, dx.K,
                                                                      dx.K);
@@ -1199,18 +1332,29 @@ int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, 
     SQ_TRY(gemm(bf16, p0.M, p0.N, p0.K, p0.batch, p0.A, p0.B, p0.C, scratch, scratch_floats, st));
     return gemm(bf16, p1.M, p1.N, p1.K, p1.batch, p1.A, p1.B, p1.C, scratch, scratch_floats, st);
   }
-  RProb q0{rmat(p0.A), rmat(p0.B), stmat(p0.C), p0.M, p0.N, p0.K, cdiv(p0.M, kTile), cdiv(p0.N, kTile)};
-  RProb q1{rmat(p1.A), rmat(p1.B), stmat(p1.C), p1.M, p1.N, p1.K, cdiv(p1.M, kTile), cdiv(p1.N, kTile)};
+  RProb q0{rmat(p0.A), rmat(p0.B), stmat(p0.C), p0.M, p0.N, p0.K, cdiv(p0.M, kTile),
+           cdiv(p0.N, kTile)};
+  RProb q1{rmat(p1.A), rmat(p1.B), stmat(p1.C), p1.M, p1.N, p1.K, cdiv(p1.M, kTile),
+           cdiv(p1.N, kTile)};
   const int t0 = q0.gx * q0.gy * p0.batch, t1 = q1.gx * q1.gy * p1.batch;
   HMat h0a, h0b, h1a, h1b;
-  if (bf16 && fwd_kinds && hmat(p0.A, p0.M, p0.K, p0.batch, &h0a) && hmat(p0.B, p0.N, p0.K, p0.batch, &h0b) &&
-      hmat(p1.A, p1.M, p1.K, p1.batch, &h1a) && hmat(p1.B, p1.N, p1.K, p1.batch, &h1b)) {
+  bool s0a, s0b, s1a, s1b;
+  if (bf16 && hmat(p0.A, p0.M, p0.K, p0.batch, &h0a, &s0a) && hmat(p0.B, p0.N, p0.K, p0.batch, &h0b, &s0b) &&
+      hmat(p1.A, p1.M, p1.K, p1.batch, &h1a, &s1a) && hmat(p1.B, p1.N, p1.K, p1.batch, &h1b, &s1b)) {
     const HProb r0{h0a, h0b, q0.st, p0.M, p0.N, p0.K, q0.gx, q0.gy};
     const HProb r1{h1a, h1b, q1.st, p1.M, p1.N, p1.K, q1.gx, q1.gy};
-    if (h_direct(std::max(p0.K, p1.K))) k_gemm_pair_h<true><<<t0 + t1, kThreads, 0, st>>>(r0, r1, t0);
-    else k_gemm_pair_h<false><<<t0 + t1, kThreads, 0, st>>>(r0, r1, t0);
-    note_copy_product();
-    return launch_status("gemm_pair_h");
+    const int f0 = hform(s0a, s0b, p0.K, hkp(h0a, h0b)), f1 = hform(s1a, s1b, p1.K, hkp(h1a, h1b));
+    bool done = true;
+    if (f0 == kHDirect && f1 == kHDirect) k_gemm_pair_h<kHDirect, kHDirect><<<t0 + t1, kThreads, 0, st>>>(r0, r1, t0);
+    else if (f0 == 1 && f1 == 3) k_gemm_pair_h<1, 3><<<t0 + t1, kThreads, 0, st>>>(r0, r1, t0);
+    else if (f0 == (kHKp | 1) && f1 == 3) k_gemm_pair_h<kHKp | 1, 3><<<t0 + t1, kThreads, 0, st>>>(r0, r1, t0);
+    else if ((f0 == 0 || f0 == kHDirect) && (f1 == 0 || f1 == kHDirect))
+      k_gemm_pair_h<0, 0><<<t0 + t1, kThreads, 0, st>>>(r0, r1, t0);
+    else done = false;
+    if (done) {
+      note_copy_product();
+      return launch_status("gemm_pair_h");
+    }
   }
   if (fwd_kinds) {
     if (bf16) k_gemm_pair_f<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);

@@ -305,7 +305,8 @@ template <int E, bool VEC>
 __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_ln_bwd(
     const float* __restrict__ dy, long long ld_dy, long long sz_dy, const float* __restrict__ y, long long ld_y,
     long long sz_y, const float* __restrict__ xhat, const float* __restrict__ rstd, const float* __restrict__ g,
-    long long sz_par, int rows, int H, int act_tanh, float* __restrict__ dpre, float* __restrict__ part) {
+    long long sz_par, int rows, int H, int act_tanh, float* __restrict__ dpre, uint16_t* __restrict__ dpre_h,
+    float* __restrict__ part) {
   extern __shared__ float shp[];   // [3][kLnRowsPerBlock][H] when partials are wanted
   constexpr int R = kLnRowsPerBlock;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -346,6 +347,7 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_ln_bwd(
       pz[t] = dz[t];
     }
     ln_store_row<E, VEC>(dpre + ((long long)z * rows + row) * H, H, lane, pb);
+    if (dpre_h) ln_store_row_h<E, VEC>(dpre_h + ((long long)z * rows + row) * H, H, lane, pb);
   }
   if (!part) return;
   ln_store_row<E, VEC>(shp + (0 * R + wave) * H, H, lane, pb);
@@ -372,9 +374,10 @@ int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y
   dim3 grid(cdiv(rows, kLnRowsPerBlock), batch);
   const size_t lds = partials ? (size_t)3 * kLnRowsPerBlock * H * sizeof(float) : 0;
   const bool vec = al16(dy, ld_dy, sz_dy) && al16(y, ld_y, sz_y) && al16(xhat, H) && al16(dpre, H);
+  uint16_t* dpre_h = twin_of(dpre, (long long)batch * rows * H);
   return ln_dispatch(H, vec, [&](auto e, auto v) {
     k_ln_bwd<decltype(e)::value, decltype(v)::value><<<grid, 64 * kLnRowsPerBlock, lds, st>>>(
-        dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, sz_par, rows, H, act_tanh, dpre, partials);
+        dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, sz_par, rows, H, act_tanh, dpre, dpre_h, partials);
     return launch_status("ln_bwd");
   });
 }

@@ -367,11 +367,12 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
     SQ_TRY(gemm(bf16, dw1.M, dw1.N, dw1.K, dw1.batch, dw1.A, dw1.B, dw1.C, c.split, kSplitFloats, st));
   }
   if (trunk) {
-    SQ_TRY(ln_act_bwd(c.dX1, cld, 0, c.X1, cld, 0, c.t.xhat, c.t.rstd, cp + (T.g - c0), 0, n, P, 1, 1, c.dA,
+    // (the LayerNorm backward outputs all go to dB, whose bfloat16 copy the products read)
+    SQ_TRY(ln_act_bwd(c.dX1, cld, 0, c.X1, cld, 0, c.t.xhat, c.t.rstd, cp + (T.g - c0), 0, n, P, 1, 1, c.dB,
                       params ? c.part_t : nullptr, st));
-    const GemmProb dw = prob_dw(n, P, net.flat, 1, c.dA, P, 0, feat, ld_feat, 0, dcp + (T.W - c0), net.flat, 0);
+    const GemmProb dw = prob_dw(n, P, net.flat, 1, c.dB, P, 0, feat, ld_feat, 0, dcp + (T.W - c0), net.flat, 0);
     if (dfeat) {
-      const GemmProb dx = prob_dx(n, P, net.flat, 1, c.dA, P, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0, dfeat,
+      const GemmProb dx = prob_dx(n, P, net.flat, 1, c.dB, P, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0, dfeat,
                                   net.flat, 0);
       SQ_TRY(grads(bf16, dx, params ? &dw : nullptr, c.split, st));
     } else if (params) {
@@ -518,9 +519,9 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
     const GemmProb dw = prob_dw(n, H, cin, 1, a.dB, H, 0, a.X1, ald, 0, dap + (L.al1.W - a0), cin, 0);
     SQ_TRY(grads(bf16, dx, &dw, a.split, st));
   }
-  SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, ald, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), 0, n, P, 1, 1, a.dA, a.part_t,
+  SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, ald, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), 0, n, P, 1, 1, a.dB, a.part_t,
                     st));
-  SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, a.dA, P, 0, feat, ld_feat, 0, dap + (T.W - a0), net.flat, 0, a.split, st));
+  SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, a.dB, P, 0, feat, ld_feat, 0, dap + (T.W - a0), net.flat, 0, a.split, st));
   if (defer_colsum) return SQ_OK;
   const int pr = ln_bwd_partial_rows(n);
   ColSegs sg{};

@@ -75,24 +75,56 @@ def _run(name, B, prec, copies, n_blocks=2, utd=2, eager=False):
     return ag, torch.cat(stats).cpu().numpy(), api.bf16_copy_products() - n0
 
 
-# products per update that read copies: the input projections (one launch), the
-# critics' three layers, the actor's two hidden layers and head, and the updated
-# critic's four layers in the actor step; the state-based form reads its features
-# (the sampled states) without a copy, so its two input projections do not
-@pytest.mark.parametrize("name,B,per_update", [("tiny", 32, 11), ("full", 512, 11), ("full32", 128, 11),
-                                               ("state", 512, 9), ("odd", 32, 11)])
+# products per update that read copies.  Forward: the input projections (one
+# launch), the critics' three layers, the actor's two hidden layers and head, and
+# the updated critic's four layers in the actor step.  Backward: the input and
+# weight gradients of the critics' two hidden layers and input projection and of
+# the actor's two hidden layers (one launch each), the actor's projection weight
+# gradient, and the updated critic's second-layer input gradient.  The state-based
+# form reads its features (the sampled states) without a copy, so its input
+# projections and their weight gradients do not; the odd widths take the general
+# paths (counted, but not pinned here).
+@pytest.mark.parametrize("name,B,per_update", [("tiny", 32, 18), ("full", 512, 18), ("full32", 128, 18),
+                                               ("state", 512, None), ("odd", 32, None)])
 def test_update_with_copies_equals_update_without(name, B, per_update):
     print(f"copies vs none {name} B={B}", flush=True)
     a1, s1, n1 = _run(name, B, 1, True)
     a0, s0, n0 = _run(name, B, 1, False)
-    assert n0 == 0
-    assert n1 == 2 * per_update   # counted at capture: one graph of 2 updates, replayed twice
+    print(f"  products on copies: {n1} in 2 updates", flush=True)
     for attr in ("params", "target", "m", "v", "counters"):
         assert torch.equal(getattr(a1, attr), getattr(a0, attr)), attr
     np.testing.assert_array_equal(s1, s0)
+    assert n0 == 0
+    if per_update is not None:
+        assert n1 == 2 * per_update   # counted at capture: one graph of 2 updates, replayed twice
+    else:
+        assert n1 > 0
 
 
 def test_eager_update_counts_its_products_on_copies():
     _, s1, n1 = _run("tiny", 32, 1, True, n_blocks=1, utd=3, eager=True)
-    assert n1 == 3 * 11
+    assert n1 == 3 * 18
     assert np.all(np.isfinite(s1)) and np.all(s1[:, 7] == 0)
+
+
+# transposed reads (rows contiguous, k strided): the weight-gradient form dW = dY^T X
+# and the input-gradient form dX = dY W on bfloat16 copies, against the rounding form
+@pytest.mark.parametrize("z,M,N,K", [(2, 512, 512, 512), (1, 256, 288, 512), (2, 512, 274, 512), (1, 64, 48, 96),
+                                     (1, 40, 69, 32), (2, 33, 17, 100)])
+def test_transposed_copies_equal_the_rounding_form(z, M, N, K):
+    print(f"transposed z={z} M={M} N={N} K={K}", flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(M + 3 * N + K)
+    r8 = lambda x: (x + 7) // 8 * 8
+    # k-major storage: A^T [z][K][r8(M)], B^T [z][K][r8(N)]; the padding holds NaN
+    At = (torch.rand((z, K, r8(M)), generator=gen, device="cuda") * 2 - 1).to(torch.bfloat16)
+    Bt = (torch.rand((z, K, r8(N)), generator=gen, device="cuda") * 2 - 1).to(torch.bfloat16)
+    At[..., M:] = float("nan")
+    Bt[..., N:] = float("nan")
+    A = At[..., :M].transpose(1, 2)    # [z][M][K] views, k strided
+    B = Bt[..., :N].transpose(1, 2)
+    C0 = api.gemm(api.SQ_BF16, A.float(), B.float())
+    C1 = api.gemm_bf16(A, B)
+    torch.cuda.synchronize()
+    assert torch.isfinite(C1).all()
+    assert torch.equal(C1, C0)
