@@ -108,6 +108,7 @@ struct sq_agent {
   float *eps2B, *S2, *r, *dn, *x, *dfeat, *act2B, *logp2B, *logits_t, *logits, *logits_q, *mt, *dlogits,
       *dlogits_q, *loss_row, *q_row, *tgt_row, *qa_row, *scal, *da;
   int* ta_snap;   // the actor Adam's step count, recorded by the critic Adam launch
+  int dlp;        // row stride of dlogits / dlogits_q (the atoms rounded up to 8: 16-byte aligned rows)
   EncBufs enc;
   ActorBufs actor;
   CriticBufs crit, aux;
@@ -145,8 +146,9 @@ static size_t plan_agent(sq_agent* g, char* base) {
   g->logits_t = g->logits ? g->logits + (size_t)2 * B * N : nullptr;
   g->logits_q = b.take<float>((size_t)2 * B * N);
   g->mt = b.take<float>((size_t)B * N);
-  g->dlogits = b.take<float>((size_t)2 * B * N);
-  g->dlogits_q = b.take<float>((size_t)2 * B * N);
+  g->dlp = N > 1 ? (N + 7) / 8 * 8 : N;
+  g->dlogits = b.take<float>((size_t)2 * B * g->dlp);
+  g->dlogits_q = b.take<float>((size_t)2 * B * g->dlp);
   g->loss_row = b.take<float>((size_t)2 * B);
   g->q_row = b.take<float>((size_t)2 * B);
   g->tgt_row = b.take<float>(B);
@@ -168,7 +170,9 @@ static size_t plan_agent(sq_agent* g, char* base) {
 // reads and the LayerNorm input gradients (dB) the backward products read get
 // bfloat16 copies, kept by their producers (LayerNorm forward and backward, the
 // fused encoder, the minibatch draw, the policy head, pack and Adam), so those
-// products read half the bytes.  Only buffers whose every producer writes the copy
+// products read half the bytes; so do the heads' gradients (dlogits, dhead, rows
+// padded to 16-byte multiples), written by the cross-entropy, expected-Q and
+// policy-head backward kernels.  Only buffers whose every producer writes the copy
 // are registered (the products' own outputs, dA and dX1, are read by LayerNorm
 // only and have none).
 static int make_twins(sq_agent* g) {
@@ -181,7 +185,12 @@ static int make_twins(sq_agent* g) {
       {g->crit.X1, 2 * B * net.cpad},     {g->crit.g1, 4 * B * H},  {g->crit.g2, 4 * B * H},
       {g->aux.X1, B * net.cpad},          {g->aux.g1, 2 * B * H},   {g->aux.g2, 2 * B * H},
       {g->actor.X1, 2 * B * net.apad},    {g->actor.g1, 2 * B * H}, {g->actor.g2, 2 * B * H},
-      {g->crit.dB, 2 * B * w},            {g->aux.dB, 2 * B * w},   {g->actor.dB, 2 * B * w}};
+      {g->crit.dB, 2 * B * w},            {g->aux.dB, 2 * B * w},   {g->actor.dB, 2 * B * w},
+      {g->actor.dhead, 2 * B * (size_t)g->actor.ldh}};
+  if (d.atoms > 1) {   // the C51 heads' gradients (the scalar heads' have one column)
+    items.push_back({g->dlogits, 2 * B * (size_t)g->dlp});
+    items.push_back({g->dlogits_q, 2 * B * (size_t)g->dlp});
+  }
   if (d.n_conv > 0 && encoder_fused(net, 1, g->enc)) items.push_back({g->enc.h[d.n_conv - 1], 2 * B * net.flat});
   Bump b{nullptr};
   for (const Item& it : items) b.take<uint16_t>(it.n);
@@ -259,9 +268,9 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
                       g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st));
   else
     SQ_TRY(target_ce(g->logits, B, N, d.v_min, d.v_max, g->r, g->dn, g->logp2B + B, P + L.log_alpha, hp.gamma,
-                     hp.cdq, g->mt, g->tgt_row, g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st));
+                     hp.cdq, g->mt, g->tgt_row, g->dlogits, g->loss_row, g->q_row, g->crit.part_out, st, g->dlp));
   SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits, B, g->crit, G + L.critic_begin,
-                         image ? g->dfeat : nullptr, nullptr, st, true, true));
+                         image ? g->dfeat : nullptr, nullptr, st, true, true, nullptr, g->dlp));
   // the fused encoder's partial gradients are summed by the critic Adam launch
   if (image) SQ_TRY(encoder_backward(net, bf, P, L, g->x, B, g->dfeat, g->enc, G, st, true, g->enc_seg));
   // critic + encoder Adam (with the target EMA and the packed copies), and the
@@ -277,13 +286,13 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
     if (N == 1)
       SQ_TRY(expected_q_scalar(g->logits_q, B, g->dlogits_q, g->qa_row, st));
     else
-      SQ_TRY(expected_q_grad(g->logits_q, B, N, d.v_min, d.v_max, g->dlogits_q, g->qa_row, st));
+      SQ_TRY(expected_q_grad(g->logits_q, B, N, d.v_min, d.v_max, g->dlogits_q, g->qa_row, st, g->dlp));
     // the policy head's backward (d log pi scaled by the updated alpha / B) runs as
     // the epilogue of the critic product that forms dQ/da
     const TgBwdJob tj{g->actor.save, g->eps2B, nullptr, g->scal + 1, 1.0f / (float)B, lo, hi, g->actor.dhead,
-                      g->actor.part_out};
+                      g->actor.part_out, g->actor.ldh};
     SQ_TRY(critic_backward(net, bf, P + L.critic_begin, g->pack, L, feat, flat, g->dlogits_q, B, g->aux, nullptr, nullptr,
-                           g->da, st, false, false, &tj));
+                           g->da, st, false, false, &tj, g->dlp));
     SQ_TRY(actor_backward(net, bf, P + L.actor_begin, g->pack, L, feat, flat, g->eps2B, B, g->da, A, nullptr, g->scal + 1,
                           1.0f / (float)B, lo, hi, g->actor, G + L.actor_begin, st, true, true));
     // the actor Adam launch also ends the update in its first workgroup; its step

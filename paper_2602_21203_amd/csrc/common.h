@@ -323,16 +323,17 @@ int tanh_gauss_fwd(const float* head, int rows, int A, const float* eps, float l
                    float* logp, float* save, hipStream_t st);
 // part (nullable): column sums of dhead per block of tanh_gauss_partial_rows rows
 int tanh_gauss_partial_rows(int rows);
+// dhead rows ldh floats apart (0: 2A)
 int tanh_gauss_bwd(const float* save, const float* eps, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, int rows, int A, float* dhead,
-                   float* part,
-                   hipStream_t st);
+                   float* part, hipStream_t st, int ldh = 0);
 int mean_action(const float* head, int rows, int A, float* action, hipStream_t st);
 // The arguments of tanh_gauss_bwd other than da: the policy head's backward as
 // the epilogue of the product that forms da (gemm_tg_bwd)
 struct TgBwdJob {
   const float* save; const float* eps; const float* dlogp_vec; const float* dlogp_scalar; float scale, lo, hi;
   float* dhead; float* part;
+  int ldh = 0;   // dhead's row stride (0: 2A)
 };
 struct GemmProb;
 // da = dx's product ([rows][A], A <= 32 columns), then tanh_gauss_bwd on it in the
@@ -348,9 +349,10 @@ int c51_project_raw(const float* p, const float* reward, const uint8_t* done, co
 // the head-bias column partials.  logits4 = [online twins | target twins] [4][B][N].
 // cdq: the target twin with the smaller expected value supplies the distribution
 // (clipped double-Q) instead of the twin average.
+// (dlogits2 rows ld_dl floats apart, 0: N; the bfloat16 copy is written when the buffer has one)
 int target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward, const float* done,
               const float* logp_next, const float* log_alpha, float gamma, int cdq, float* m, float* tgt_row,
-              float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st);
+              float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st, int ld_dl = 0);
 // The same for a scalar critic (N = 1, Eqs. (1)-(2)): squared error to
 // y = r + gamma (1 - d)(Qbar - alpha log pi').
 int target_mse(const float* logits4, int B, const float* reward, const float* done, const float* logp_next,
@@ -359,7 +361,7 @@ int target_mse(const float* logits4, int B, const float* reward, const float* do
 // actor-loss head of a scalar critic: qa_row = (Q_1 + Q_2) / 2, dq2 = -1 / (2B)
 int expected_q_scalar(const float* q2, int B, float* dq2, float* qa_row, hipStream_t st);
 int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max, float* dlogits2,
-                    float* qa_row, hipStream_t st);
+                    float* qa_row, hipStream_t st, int ld_dl = 0);
 int finish_update(const float* loss_row, const float* q_row, const float* tgt_row, const float* logp,
                   const float* qa_row, const float* scal, int B, int actor_step, int* ctr, float* stats,
                   hipStream_t st);

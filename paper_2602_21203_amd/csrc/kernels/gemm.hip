@@ -189,6 +189,9 @@ struct StTanhGauss {
 struct StTgBwd {
   const float* save; const float* eps; const float* dlogp_vec; const float* dlogp_scalar; float scale, lo, hi;
   float* dhead; float* part; int A;
+  int ldh;             // dhead's row stride
+  uint16_t* dhead_h;   // its bfloat16 copy (nullable)
+  int off;             // da starts at column off of the tile
   static constexpr bool ROW_FAST = false;
   static constexpr bool ROWS = true;
   __device__ void put(int, int, int, float) const {}
@@ -203,11 +206,15 @@ struct StTgBwd {
       const float tus = save[row * 3 * A + d];
       const float sd = save[row * 3 * A + A + d];
       const float a = save[row * 3 * A + 2 * A + d];
-      const float du = v[r * ld + d] * (1.f - a * a) + dl * 2.f * a;
+      const float du = v[r * ld + off + d] * (1.f - a * a) + dl * 2.f * a;
       const float dls = du * sd * eps[row * A + d] - dl;
       const float dls_out = dls * 0.5f * (hi - lo) * (1.f - tus * tus);
-      dhead[row * N + d] = du;
-      dhead[row * N + A + d] = dls_out;
+      dhead[row * ldh + d] = du;
+      dhead[row * ldh + A + d] = dls_out;
+      if (dhead_h) {
+        dhead_h[row * ldh + d] = bf16_bits(du);
+        dhead_h[row * ldh + A + d] = bf16_bits(dls_out);
+      }
       tmp[r * N + d] = du;
       tmp[r * N + A + d] = dls_out;
     }
@@ -1290,23 +1297,36 @@ int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const flo
 int gemm_tg_bwd(int bf16, const GemmProb& dx, int A, const TgBwdJob& tg, hipStream_t st) {
   const int n = dx.M;
   if (n <= 0) return SQ_OK;
+  const int ldh = tg.ldh > 0 ? tg.ldh : 2 * A;
   const bool kok = dx.A.kalt == dx.B.kalt && (dx.A.kalt == kNoAlt || dx.A.kalt % kRKC == 0);
   if (dx.N != A || 2 * A * kTile > kTile * kTile || dx.batch != 1 || rkind(dx.A) != 1 || rkind(dx.B) != 0 || !kok ||
       dx.C.accumulate || dx.C.bias) {
     SQ_TRY(gemm(bf16, dx.M, dx.N, dx.K, dx.batch, dx.A, dx.B, dx.C, nullptr, 0, st));
     return tanh_gauss_bwd(tg.save, tg.eps, dx.C.p, dx.C.ld, tg.dlogp_vec, tg.dlogp_scalar, tg.scale, tg.lo, tg.hi, n,
-                          A, tg.dhead, tg.part, st);
+                          A, tg.dhead, tg.part, st, ldh);
   }
-  const StTgBwd ep{tg.save, tg.eps, tg.dlogp_vec, tg.dlogp_scalar, tg.scale, tg.lo, tg.hi, tg.dhead, tg.part, A};
+  uint16_t* dhead_h = twin_of(tg.dhead, (long long)(n - 1) * ldh + 2 * A);
+  StTgBwd ep{tg.save, tg.eps, tg.dlogp_vec, tg.dlogp_scalar, tg.scale, tg.lo, tg.hi, tg.dhead, tg.part, A,
+             ldh, dhead_h, 0};
   const StPart none{nullptr, 0, 0, 1};
   dim3 grid(cdiv(n, kTile), 1, 1);
   HMat ha, hb;
   bool ta, tb;
-  if (bf16 && hmat(dx.A, n, dx.K, 1, &ha, &ta) && hmat(dx.B, A, dx.K, 1, &hb, &tb) && !ta && tb) {
-    if (hkp(ha, hb)) launch_h<kHKp | 1>(grid, ha, hb, ep, n, A, dx.K, st);
-    else launch_h<1>(grid, ha, hb, ep, n, A, dx.K, st);
-    note_copy_product();
-    return launch_status("gemm_tg_bwd");
+  if (bf16 && hmat(dx.A, n, dx.K, 1, &ha, &ta) && !ta) {
+    // on bfloat16 copies the product reads da's weight columns from the 16-byte
+    // aligned group that holds them: the window starts `off` columns earlier and
+    // the epilogue skips them
+    for (int off = 0; off < 8 && A + off <= kTile; ++off) {
+      MatArg bw = dx.B;
+      bw.p -= off;
+      if (bw.kp) bw.kp -= off;
+      if (!hmat(bw, A + off, dx.K, 1, &hb, &tb) || !tb) continue;
+      ep.off = off;
+      if (hkp(ha, hb)) launch_h<kHKp | 1>(grid, ha, hb, ep, n, A + off, dx.K, st);
+      else launch_h<1>(grid, ha, hb, ep, n, A + off, dx.K, st);
+      note_copy_product();
+      return launch_status("gemm_tg_bwd");
+    }
   }
   if (bf16)
     k_gemm_r<true, 1, 0, StTgBwd, false><<<grid, kThreads, 0, st>>>(rmat(dx.A), rmat(dx.B), ep, none, n, A, dx.K,

@@ -477,6 +477,7 @@ __global__ __launch_bounds__(kTgRows) void k_tg_bwd(const float* __restrict__ sa
                                                     const float* __restrict__ dlogp_vec,
                                                     const float* __restrict__ dlogp_scalar, float scale, float lo,
                                                     float hi, int rows, int A, float* __restrict__ dhead,
+                                                    int ldh, uint16_t* __restrict__ dhead_h,
                                                     float* __restrict__ part) {
   extern __shared__ float sht[];   // [kTgRows][2A] when part is wanted
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -495,8 +496,12 @@ __global__ __launch_bounds__(kTgRows) void k_tg_bwd(const float* __restrict__ sa
       du = dav * (1.f - a * a) + dl * 2.f * a;
       const float dls = du * sd * e - dl;
       dls_out = dls * 0.5f * (hi - lo) * (1.f - tus * tus);
-      dhead[(long long)r * 2 * A + d] = du;
-      dhead[(long long)r * 2 * A + A + d] = dls_out;
+      dhead[(long long)r * ldh + d] = du;
+      dhead[(long long)r * ldh + A + d] = dls_out;
+      if (dhead_h) {
+        dhead_h[(long long)r * ldh + d] = bf16_bits(du);
+        dhead_h[(long long)r * ldh + A + d] = bf16_bits(dls_out);
+      }
     }
     if (part) {
       sht[threadIdx.x * 2 * A + d] = du;
@@ -516,11 +521,13 @@ int tanh_gauss_partial_rows(int rows) { return cdiv(rows, kTgRows); }
 
 int tanh_gauss_bwd(const float* save, const float* eps, const float* da, long long ld_da, const float* dlogp_vec,
                    const float* dlogp_scalar, float scale, float lo, float hi, int rows, int A, float* dhead,
-                   float* part, hipStream_t st) {
+                   float* part, hipStream_t st, int ldh) {
   if (rows <= 0) return SQ_OK;
+  if (ldh <= 0) ldh = 2 * A;
   const size_t lds = part ? (size_t)kTgRows * 2 * A * sizeof(float) : 0;
+  uint16_t* dhead_h = twin_of(dhead, (long long)(rows - 1) * ldh + 2 * A);
   k_tg_bwd<<<cdiv(rows, kTgRows), kTgRows, lds, st>>>(save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi,
-                                                     rows, A, dhead, part);
+                                                     rows, A, dhead, ldh, dhead_h, part);
   return launch_status("tanh_gauss_bwd");
 }
 
@@ -694,8 +701,8 @@ template <int T, bool CDQ>
 __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
     const float* __restrict__ logits4, int B, int N, float v_min, float v_max, const float* __restrict__ reward,
     const float* __restrict__ done, const float* __restrict__ logp_next, const float* __restrict__ log_alpha,
-    float gamma, float* __restrict__ m_out, float* __restrict__ tgt_row, float* __restrict__ dlogits2,
-    float* __restrict__ loss_row, float* __restrict__ q_row, float* __restrict__ part) {
+    float gamma, float* __restrict__ m_out, float* __restrict__ tgt_row, float* __restrict__ dlogits2, int ld_dl,
+    uint16_t* __restrict__ dl_h, float* __restrict__ loss_row, float* __restrict__ q_row, float* __restrict__ part) {
   // [kLnRowsPerBlock][2][N] projected positions and probabilities of each wave's
   // row, then [2][kLnRowsPerBlock][N] head-bias partials when part is wanted
   extern __shared__ float shc2[];
@@ -774,7 +781,8 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
           ce -= mi[t] * (lg[i][t] - mx - lse);
           q += pj * (v_min + (float)j * dz);
           dl[i][t] = (pj - mi[t]) * invB;
-          dlogits2[((long long)i * B + b) * N + j] = dl[i][t];
+          dlogits2[((long long)i * B + b) * ld_dl + j] = dl[i][t];
+          if (dl_h) dl_h[((long long)i * B + b) * ld_dl + j] = bf16_bits(dl[i][t]);
         }
       }
       ce = wave_sum(ce);
@@ -806,35 +814,38 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_target_ce(
 template <bool CDQ>
 static void launch_target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward,
                              const float* done, const float* logp_next, const float* log_alpha, float gamma, float* m,
-                             float* tgt_row, float* dlogits2, float* loss_row, float* q_row, float* part,
-                             hipStream_t st) {
+                             float* tgt_row, float* dlogits2, int ld_dl, uint16_t* dl_h, float* loss_row,
+                             float* q_row, float* part, hipStream_t st) {
   const size_t lds = (size_t)(part ? 4 : 2) * kLnRowsPerBlock * N * sizeof(float);
   const dim3 grid(cdiv(B, kLnRowsPerBlock)), block(64 * kLnRowsPerBlock);
   if (N <= 64)
     k_target_ce<1, CDQ><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
-                                                  gamma, m, tgt_row, dlogits2, loss_row, q_row, part);
+                                                  gamma, m, tgt_row, dlogits2, ld_dl, dl_h, loss_row, q_row, part);
   else if (N <= 128)
     k_target_ce<2, CDQ><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
-                                                  gamma, m, tgt_row, dlogits2, loss_row, q_row, part);
+                                                  gamma, m, tgt_row, dlogits2, ld_dl, dl_h, loss_row, q_row, part);
   else if (N <= 192)
     k_target_ce<3, CDQ><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
-                                                  gamma, m, tgt_row, dlogits2, loss_row, q_row, part);
+                                                  gamma, m, tgt_row, dlogits2, ld_dl, dl_h, loss_row, q_row, part);
   else
     k_target_ce<4, CDQ><<<grid, block, lds, st>>>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha,
-                                                  gamma, m, tgt_row, dlogits2, loss_row, q_row, part);
+                                                  gamma, m, tgt_row, dlogits2, ld_dl, dl_h, loss_row, q_row, part);
 }
 
 int target_ce(const float* logits4, int B, int N, float v_min, float v_max, const float* reward, const float* done,
               const float* logp_next, const float* log_alpha, float gamma, int cdq, float* m, float* tgt_row,
-              float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st) {
+              float* dlogits2, float* loss_row, float* q_row, float* part, hipStream_t st, int ld_dl) {
   if (B <= 0) return SQ_OK;
   if (N < 2 || N > 64 * kMaxAtomsPerLane) return SQ_EINVAL;
+  if (ld_dl <= 0) ld_dl = N;
+  if (ld_dl < N) return SQ_EINVAL;
+  uint16_t* dl_h = twin_of(dlogits2, (long long)(2 * B - 1) * ld_dl + N);
   if (cdq)
     launch_target_ce<true>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma, m, tgt_row,
-                           dlogits2, loss_row, q_row, part, st);
+                           dlogits2, ld_dl, dl_h, loss_row, q_row, part, st);
   else
     launch_target_ce<false>(logits4, B, N, v_min, v_max, reward, done, logp_next, log_alpha, gamma, m, tgt_row,
-                            dlogits2, loss_row, q_row, part, st);
+                            dlogits2, ld_dl, dl_h, loss_row, q_row, part, st);
   return launch_status("target_ce");
 }
 
@@ -918,7 +929,8 @@ int c51_project_raw(const float* p, const float* reward, const uint8_t* done, co
 // actor-loss head: Q_i = sum_j p_ij z_j, dL/dl_ij = -(1 / (2B)) p_ij (z_j - Q_i),
 // qa_row[b] = (Q_1 + Q_2) / 2
 __global__ __launch_bounds__(256) void k_expq(const float* __restrict__ logits2, int B, int N, float v_min,
-                                              float v_max, float* __restrict__ dlogits2, float* __restrict__ qa_row) {
+                                              float v_max, float* __restrict__ dlogits2, int ld_dl,
+                                              uint16_t* __restrict__ dl_h, float* __restrict__ qa_row) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int b = blockIdx.x * 4 + wave;
   if (b >= B) return;
@@ -938,7 +950,11 @@ __global__ __launch_bounds__(256) void k_expq(const float* __restrict__ logits2,
 #pragma unroll
     for (int t = 0; t < kMaxAtomsPerLane; ++t) {
       const int j = lane + 64 * t;
-      if (j < N) dlogits2[((long long)i * B + b) * N + j] = c * p[t] * ((v_min + (float)j * dz) - q);
+      if (j < N) {
+        const float g = c * p[t] * ((v_min + (float)j * dz) - q);
+        dlogits2[((long long)i * B + b) * ld_dl + j] = g;
+        if (dl_h) dl_h[((long long)i * B + b) * ld_dl + j] = bf16_bits(g);
+      }
     }
     qsum += q;
   }
@@ -946,9 +962,12 @@ __global__ __launch_bounds__(256) void k_expq(const float* __restrict__ logits2,
 }
 
 int expected_q_grad(const float* logits2, int B, int N, float v_min, float v_max, float* dlogits2, float* qa_row,
-                    hipStream_t st) {
+                    hipStream_t st, int ld_dl) {
   if (B <= 0) return SQ_OK;
-  k_expq<<<cdiv(B, 4), 256, 0, st>>>(logits2, B, N, v_min, v_max, dlogits2, qa_row);
+  if (ld_dl <= 0) ld_dl = N;
+  if (ld_dl < N) return SQ_EINVAL;
+  uint16_t* dl_h = twin_of(dlogits2, (long long)(2 * B - 1) * ld_dl + N);
+  k_expq<<<cdiv(B, 4), 256, 0, st>>>(logits2, B, N, v_min, v_max, dlogits2, ld_dl, dl_h, qa_row);
   return launch_status("expected_q");
 }
 

@@ -297,24 +297,25 @@ int critic_forward_pair(const Net& net, int bf16, const float* cp, const float* 
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                     long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
                     float* daction, hipStream_t st,
-                    bool out_partials_done, bool defer_colsum, const TgBwdJob* tg) {
+                    bool out_partials_done, bool defer_colsum, const TgBwdJob* tg, int ld_dl) {
   const sq_dims& d = net.d;
   const int H = d.hidden, P = d.proj, N = d.atoms, cin = net.cin_critic, cld = net.cpad, A = d.action;
   const long long c0 = L.critic_begin;
   const long long tw = L.q[1].l1.W - L.q[0].l1.W;
   const WRef w{cp, cpack, c0};
   const long long twW = cpack ? L.q[1].l1.Wp - L.q[0].l1.Wp : tw;
-  const long long nH = (long long)n * H, nN = (long long)n * N;
+  const long long nH = (long long)n * H;
   const Dense& T = L.ctrunk;
   const Twin& q = L.q[0];
   const bool params = dcp != nullptr;
   const bool trunk = params || dfeat != nullptr;
   // output heads
-  if (params && !out_partials_done) SQ_TRY(col_partials(dlogits, N, nN, n, N, 2, c.part_out, st));
+  const long long ldl = ld_dl > 0 ? ld_dl : N, nL = (long long)n * ldl;
+  if (params && !out_partials_done) SQ_TRY(col_partials(dlogits, ldl, nL, n, N, 2, c.part_out, st));
   {
-    const GemmProb dx = prob_dx(n, N, H, 2, dlogits, N, nN, w.W(q.out.W, q.out.Wp), w.ld(q.out.in, q.out.ldp), twW,
+    const GemmProb dx = prob_dx(n, N, H, 2, dlogits, ldl, nL, w.W(q.out.W, q.out.Wp), w.ld(q.out.in, q.out.ldp), twW,
                                 c.dA, H, nH);
-    const GemmProb dw = prob_dw(n, N, H, 2, dlogits, N, nN, c.g2, H, nH, dcp + (q.out.W - c0), H, tw);
+    const GemmProb dw = prob_dw(n, N, H, 2, dlogits, ldl, nL, c.g2, H, nH, dcp + (q.out.W - c0), H, tw);
     SQ_TRY(grads(bf16, dx, params ? &dw : nullptr, c.split, st));
   }
   // second hidden layer
@@ -362,7 +363,7 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
                                   hipMemcpyDeviceToDevice, st));
     if (tg && daction)
       SQ_TRY(tanh_gauss_bwd(tg->save, tg->eps, daction, A, tg->dlogp_vec, tg->dlogp_scalar, tg->scale, tg->lo, tg->hi,
-                            n, A, tg->dhead, tg->part, st));
+                            n, A, tg->dhead, tg->part, st, tg->ldh));
   } else if (params) {
     SQ_TRY(gemm(bf16, dw1.M, dw1.N, dw1.K, dw1.batch, dw1.A, dw1.B, dw1.C, c.split, kSplitFloats, st));
   }
@@ -409,13 +410,14 @@ void plan_actor(const Net& net, int n, Bump& b, ActorBufs* a, bool with_bwd) {
   a->g2 = b.take<float>((size_t)n * H);
   a->head = b.take<float>((size_t)n * 2 * A);
   a->save = b.take<float>((size_t)n * 3 * A);
+  a->ldh = (2 * A + 7) / 8 * 8;   // dhead rows 16-byte aligned (the products read its bfloat16 copy)
   a->dA = a->dB = a->dX1 = a->dhead = a->part_t = a->part_l1 = a->part_l2 = a->part_out = a->split = nullptr;
   if (with_bwd) {
     const int pr = ln_bwd_partial_rows(n);
     a->dA = b.take<float>((size_t)n * w);
     a->dB = b.take<float>((size_t)n * w);
     a->dX1 = b.take<float>((size_t)n * P);
-    a->dhead = b.take<float>((size_t)n * 2 * A);
+    a->dhead = b.take<float>((size_t)n * a->ldh);
     a->part_t = b.take<float>((size_t)3 * pr * P);
     a->part_l1 = b.take<float>((size_t)3 * pr * H);
     a->part_l2 = b.take<float>((size_t)3 * pr * H);
@@ -495,11 +497,11 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
   const Dense& T = L.atrunk;
   if (!dhead_done)
     SQ_TRY(tanh_gauss_bwd(a.save, eps, da, ld_da, dlogp_vec, dlogp_scalar, scale, lo, hi, n, A, a.dhead, a.part_out,
-                          st));
+                          st, a.ldh));
   {
-    const GemmProb dx = prob_dx(n, 2 * A, H, 1, a.dhead, 2 * A, 0, w.W(L.aout.W, L.aout.Wp),
+    const GemmProb dx = prob_dx(n, 2 * A, H, 1, a.dhead, a.ldh, 0, w.W(L.aout.W, L.aout.Wp),
                                 w.ld(L.aout.in, L.aout.ldp), 0, a.dA, H, 0);
-    const GemmProb dw = prob_dw(n, 2 * A, H, 1, a.dhead, 2 * A, 0, a.g2, H, 0, dap + (L.aout.W - a0), H, 0);
+    const GemmProb dw = prob_dw(n, 2 * A, H, 1, a.dhead, a.ldh, 0, a.g2, H, 0, dap + (L.aout.W - a0), H, 0);
     SQ_TRY(grads(bf16, dx, &dw, a.split, st));
   }
   SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g2, H, 0, a.l2.xhat, a.l2.rstd, ap + (L.al2.g - a0), 0, n, H, 1, 0, a.dB, a.part_l2,

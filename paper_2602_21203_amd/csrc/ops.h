@@ -71,7 +71,8 @@ int critic_forward(const Net& net, int bf16, const float* cp, const float* cpack
 int critic_backward(const Net& net, int bf16, const float* cp, const float* cpack, const Layout& L, const float* feat,
                     long long ld_feat, const float* dlogits, int n, const CriticBufs& c, float* dcp, float* dfeat,
                     float* daction, hipStream_t st,
-                    bool out_partials_done = false, bool defer_colsum = false, const TgBwdJob* tg = nullptr);
+                    bool out_partials_done = false, bool defer_colsum = false, const TgBwdJob* tg = nullptr,
+                    int ld_dl = 0);   // dlogits rows ld_dl floats apart (0: atoms)
 // tg (with daction): also run the policy head's backward on daction (tanh_gauss_bwd
 // with tg's arguments); without the critic's own gradients it is the epilogue of
 // the product that forms daction, which is then not stored
@@ -85,7 +86,8 @@ struct ActorBufs {
   float* save;         // [n][3A]
   float* dA; float* dB;  // [n][max(hidden, proj)]
   float* dX1;          // [n][proj]
-  float* dhead;        // [n][2A]
+  float* dhead;        // [n][ldh], the first 2A columns
+  int ldh;
   float* part_t; float* part_l1; float* part_l2; float* part_out;
   float* split;
   // nullable: the sampled actions of rows >= xact_row0 are also written here

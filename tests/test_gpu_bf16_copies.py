@@ -75,16 +75,16 @@ def _run(name, B, prec, copies, n_blocks=2, utd=2, eager=False):
     return ag, torch.cat(stats).cpu().numpy(), api.bf16_copy_products() - n0
 
 
-# products per update that read copies.  Forward: the input projections (one
-# launch), the critics' three layers, the actor's two hidden layers and head, and
-# the updated critic's four layers in the actor step.  Backward: the input and
-# weight gradients of the critics' two hidden layers and input projection and of
-# the actor's two hidden layers (one launch each), the actor's projection weight
-# gradient, and the updated critic's second-layer input gradient.  The state-based
-# form reads its features (the sampled states) without a copy, so its input
-# projections and their weight gradients do not; the odd widths take the general
-# paths (counted, but not pinned here).
-@pytest.mark.parametrize("name,B,per_update", [("tiny", 32, 18), ("full", 512, 18), ("full32", 128, 18),
+# products per update that read copies: all 22.  Forward: the input projections
+# (one launch), the critics' three layers, the actor's two hidden layers and head,
+# and the updated critic's four layers in the actor step.  Backward: the input and
+# weight gradients of the critics' three layers and input projection and of the
+# actor's three layers (one launch each), the actor's projection weight gradient,
+# and in the actor step the updated critic's output and second-layer input
+# gradients and the dQ/da product.  The state-based form reads its features (the
+# sampled states) without a copy, so its input projections and their weight
+# gradients do not; the odd widths take the general paths (counted, not pinned).
+@pytest.mark.parametrize("name,B,per_update", [("tiny", 32, 22), ("full", 512, 22), ("full32", 128, 22),
                                                ("state", 512, None), ("odd", 32, None)])
 def test_update_with_copies_equals_update_without(name, B, per_update):
     print(f"copies vs none {name} B={B}", flush=True)
@@ -103,7 +103,7 @@ def test_update_with_copies_equals_update_without(name, B, per_update):
 
 def test_eager_update_counts_its_products_on_copies():
     _, s1, n1 = _run("tiny", 32, 1, True, n_blocks=1, utd=3, eager=True)
-    assert n1 == 3 * 18
+    assert n1 == 3 * 22
     assert np.all(np.isfinite(s1)) and np.all(s1[:, 7] == 0)
 
 
