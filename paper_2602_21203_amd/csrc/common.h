@@ -269,6 +269,11 @@ bool encoder_fused_prep_map(int C, int F, int n_conv, int side, const long long*
                             EncPrepMap* m);
 size_t encoder_fused_prep_floats(int C, int F, int n_conv);
 int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W, float* wp, hipStream_t st);
+// The minibatch draw, the squint of its obs / next_obs frames (x: FP32 [2B][C][side][side] written for
+// the backward) and the bfloat16 encoder forward in one launch; 1 when the geometry has no such form
+int encoder_fused_fwd_squint(const SampleArgs& sa, const uint8_t* obs, const uint8_t* next_obs, int H, int W, int C,
+                             int F, int n_conv, int k, float* x, const float* wp, const float* const* b,
+                             float* const* h, uint16_t* hh, hipStream_t st);
 // hh (nullable, bfloat16 form only): the last layer's output is also written there rounded to bfloat16
 int encoder_fused_fwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* wp,
                       const float* const* b, float* const* h, hipStream_t st, uint16_t* hh = nullptr);
@@ -281,8 +286,12 @@ int encoder_fused_bwd(int bf16, int C, int F, int n_conv, int side, const float*
 // Second parameter group of a LayerNorm batch (batches z >= zalt read their gain
 // and shift from g_alt / beta_alt, their second extra block from e2_alt), and the
 // batch stride of the first extra block.
+// Batches z >= zalt take the alternative (target-critic) gain and shift; no
+// backward runs through them, so their x-hat and rstd are not stored unless
+// save_alt is set.
 struct LnGroups {
   int zalt; const float* g_alt; const float* beta_alt; long long sz_e1; const float* e2_alt;
+  int save_alt = 0;
 };
 int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch,
                const float* g, const float* beta, long long sz_par, int act_tanh,

@@ -38,6 +38,7 @@
 // kernel adds the partials in workgroup order, so the result is deterministic.
 #include "../common.h"
 #include "bf16.h"
+#include "sample.h"
 
 namespace sq {
 
@@ -531,12 +532,22 @@ __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16
   }
 }
 
-template <int G, int C, int F, int NC, int SD, int NT>
+// SQK > 0: the launch also draws the minibatch and squints its frames (factor
+// SQK, raw uint8 HWC frames of side SD * SQK): the first `lead` workgroups take
+// the draw's items (as in the squint launch), and image workgroup i computes
+// replay row i of the draw itself (obs rows, then next_obs rows), sums each
+// output pixel's SQK x SQK block per channel (thread p owns pixel p), and writes
+// x = sum / (255 SQK^2) - 0.5 both to xout (FP32 CHW, for the backward) and,
+// rounded, to the first layer's LDS input: the separate squint launch and the
+// round trip of x disappear.  The arithmetic is the squint kernel's.
+template <int G, int C, int F, int NC, int SD, int NT, int SQK = 0>
 __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ x, int n, const __bf16* __restrict__ wp,
                                                       const float* __restrict__ b0, const float* __restrict__ b1,
                                                       const float* __restrict__ b2, float* __restrict__ h0,
                                                       float* __restrict__ h1, float* __restrict__ h2,
-                                                      uint16_t* __restrict__ hh) {
+                                                      uint16_t* __restrict__ hh, const uint8_t* __restrict__ obs,
+                                                      const uint8_t* __restrict__ next_obs, SampleArgs sa, int lead,
+                                                      float* __restrict__ xout) {
   using L0 = LB<C, F, 0, SD>;
   using L1 = LB<C, F, 1, SD>;
   using E = EncPrep<C, F, NC>;
@@ -546,15 +557,40 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
   __shared__ __attribute__((aligned(16))) __bf16 lx[X];
   __shared__ __attribute__((aligned(16))) __bf16 la0[A0];
   __shared__ __attribute__((aligned(16))) __bf16 la1[A1];
-  const int img0 = blockIdx.x * G;
+  if constexpr (SQK > 0) {
+    if ((int)blockIdx.x < lead) {
+      const long long t = (long long)blockIdx.x * NT + threadIdx.x;
+      if (t < sample_items(sa.B, sa.A, sa.S)) sample_item(sa, t);
+      return;
+    }
+  }
+  const int img0 = ((int)blockIdx.x - (SQK > 0 ? lead : 0)) * G;
   const int gn = n - img0 < G ? n - img0 : G;
   // the images, then every layer's weight fragments of this wave, all requested up front
-  constexpr int RX = (G * C * SD * SD + NT - 1) / NT;
+  constexpr int RX = SQK > 0 ? 1 : (G * C * SD * SD + NT - 1) / NT;
+  constexpr int SEG = SQK * C;   // bytes of one source block row (squint form)
+  constexpr int NWD = SQK > 0 ? SQK * SEG / 4 : 1;
   float xv[RX];
+  unsigned fw[NWD];
+  if constexpr (SQK > 0) {
+    static_assert(G == 1 && NT == SD * SD && SEG % 4 == 0, "one thread per output pixel, 32-bit block rows");
+    const int p = threadIdx.x, y = p / SD, xq = p - y * SD;
+    constexpr int Wsrc = SD * SQK;
+    const bool second = img0 >= sa.B;
+    const uint8_t* frame = (second ? next_obs : obs) +
+                           (long long)sample_row(sa, second ? img0 - sa.B : img0) * Wsrc * Wsrc * C;
 #pragma unroll
-  for (int i = 0; i < RX; ++i) {
-    const int e = (int)threadIdx.x + NT * i;
-    xv[i] = e < gn * C * SD * SD ? x[(long long)img0 * C * SD * SD + e] : 0.f;
+    for (int r = 0; r < SQK; ++r) {
+      const unsigned* w = reinterpret_cast<const unsigned*>(frame + ((long long)(y * SQK + r) * Wsrc + xq * SQK) * C);
+#pragma unroll
+      for (int q = 0; q < SEG / 4; ++q) fw[r * (SEG / 4) + q] = w[q];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < RX; ++i) {
+      const int e = (int)threadIdx.x + NT * i;
+      xv[i] = e < gn * C * SD * SD ? x[(long long)img0 * C * SD * SD + e] : 0.f;
+    }
   }
   const int c0w = ((threadIdx.x >> 6) % CT) * 16;
   WFrag<C, F, 0, SD> w0;
@@ -565,13 +601,36 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
     w1.load(wp + E::F1, b1, c0w);
     if constexpr (NC > 2) w2.load(wp + E::F2, b2, c0w);
   }
-  // images NCHW -> [g][pixel][channel] bfloat16; absent images and padding channels zero
+  if constexpr (SQK > 0) {
+    // each byte of the block rows into its channel's integer sum, then x
+    int sum[C];
 #pragma unroll
-  for (int i = 0; i < RX; ++i) {
-    const int e = (int)threadIdx.x + NT * i;
-    if (e < G * C * SD * SD) {
-      const int g = e / (C * SD * SD), r = e - g * C * SD * SD, c = r / (SD * SD), pix = r - c * SD * SD;
-      lx[(g * SD * SD + pix) * L0::PS + c] = (__bf16)xv[i];
+    for (int c = 0; c < C; ++c) sum[c] = 0;
+#pragma unroll
+    for (int r = 0; r < SQK; ++r)
+#pragma unroll
+      for (int q = 0; q < SEG / 4; ++q) {
+        const unsigned v = fw[r * (SEG / 4) + q];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) sum[(4 * q + b) % C] += (int)((v >> (8 * b)) & 0xFFu);
+      }
+    const float scale = (float)(255 * SQK * SQK);
+    const int p = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float v = (float)sum[c] / scale - 0.5f;
+      xout[((long long)img0 * C + c) * SD * SD + p] = v;
+      lx[p * L0::PS + c] = (__bf16)v;
+    }
+  } else {
+    // images NCHW -> [g][pixel][channel] bfloat16; absent images and padding channels zero
+#pragma unroll
+    for (int i = 0; i < RX; ++i) {
+      const int e = (int)threadIdx.x + NT * i;
+      if (e < G * C * SD * SD) {
+        const int g = e / (C * SD * SD), r = e - g * C * SD * SD, c = r / (SD * SD), pix = r - c * SD * SD;
+        lx[(g * SD * SD + pix) * L0::PS + c] = (__bf16)xv[i];
+      }
     }
   }
   for (int e = threadIdx.x; e < G * SD * SD * (L0::CP - C); e += NT) {
@@ -946,7 +1005,7 @@ static int enc_fwd_t(const float* x, int n, const float* wp, const float* const*
     const int nwg = cdiv(n, kEncFwdGb);
     k_encoder_fwd_b<kEncFwdGb, C, F, NC, SD, kEncFwdThreadsb><<<nwg, kEncFwdThreadsb, 0, st>>>(
         x, n, reinterpret_cast<const __bf16*>(wp), b[0], b[1], NC > 2 ? b[2] : b[1], h[0], h[1],
-        NC > 2 ? h[2] : h[1], hh);
+        NC > 2 ? h[2] : h[1], hh, nullptr, nullptr, SampleArgs{}, 0, nullptr);
   } else {
     static_assert(SD == 16, "the FP32 fused encoder is built for 16 x 16 inputs");
     const int nwg = cdiv(n, kEncFwdG);
@@ -1046,6 +1105,23 @@ int encoder_fused_fwd(int bf16, int C, int F, int n_conv, int side, const float*
                 : enc_fwd_t<false, 9, 32, 3, 16>(x, n, wp, b, h, nullptr, st);
   return bf16 ? enc_fwd_t<true, 3, 16, 2, 16>(x, n, wp, b, h, hh, st)
               : enc_fwd_t<false, 3, 16, 2, 16>(x, n, wp, b, h, nullptr, st);
+}
+
+int encoder_fused_fwd_squint(const SampleArgs& sa, const uint8_t* obs, const uint8_t* next_obs, int H, int W, int C,
+                             int F, int n_conv, int k, float* x, const float* wp, const float* const* b,
+                             float* const* h, uint16_t* hh, hipStream_t st) {
+  const int n = 2 * sa.B;
+  if (n <= 0) return SQ_OK;
+  // the headline geometry: 64 x 64 x 9 frames squinted 4x into the 16 x 16 encoder, one image per
+  // 256-thread workgroup (a thread per output pixel), 16-byte aligned frames
+  if (!(C == 9 && F == 32 && n_conv == 3 && k == 4 && H == 64 && W == 64 && kEncFwdGb == 1 &&
+        kEncFwdThreadsb == 256) || (uintptr_t)obs % 4 || (uintptr_t)next_obs % 4)
+    return 1;
+  const int lead = (int)((sample_items(sa.B, sa.A, sa.S) + kEncFwdThreadsb - 1) / kEncFwdThreadsb);
+  k_encoder_fwd_b<1, 9, 32, 3, 16, 256, 4><<<lead + n, 256, 0, st>>>(
+      nullptr, n, reinterpret_cast<const __bf16*>(wp), b[0], b[1], b[2], h[0], h[1], h[2], hh, obs, next_obs, sa,
+      lead, x);
+  return launch_status("encoder_fwd_squint");
 }
 
 int encoder_fused_bwd(int bf16, int C, int F, int n_conv, int side, const float* x, int n, const float* dfeat,

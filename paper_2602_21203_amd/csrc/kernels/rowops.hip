@@ -171,10 +171,11 @@ __device__ __forceinline__ void ln_fwd_row(const float* __restrict__ pre, long l
   }
   float* yr = y + z * sz_y + row * ld_y;
   uint16_t* yhr = yh ? yh + z * sz_y + row * ld_y : nullptr;
-  ln_store_row<E, VEC>(xhat + ((long long)z * rows + row) * H, H, lane, xh);
+  const bool save = !second || grp.save_alt;
+  if (save) ln_store_row<E, VEC>(xhat + ((long long)z * rows + row) * H, H, lane, xh);
   ln_store_row<E, VEC>(yr, H, lane, o);
   if (yhr) ln_store_row_h<E, VEC>(yhr, H, lane, o);
-  if (lane == 0) rstd[(long long)z * rows + row] = rs;
+  if (save && lane == 0) rstd[(long long)z * rows + row] = rs;
   const float* e1z = e1 + z * grp.sz_e1;
   const float* e2z = second && grp.e2_alt ? grp.e2_alt : e2;
   for (int j = lane; j < w1; j += 64) {

@@ -7,6 +7,7 @@
 // The twin critics run as batch 2 of the same launch (twin parameter blocks
 // are a fixed stride apart in the flat vector).
 #include "ops.h"
+#include "kernels/sample.h"
 
 #include <algorithm>
 
@@ -138,6 +139,22 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
     hs = net.conv_side[i];
   }
   return SQ_OK;
+}
+
+int encoder_forward_squint(const Net& net, const float* ep, const Layout& L, const SampleArgs& sa,
+                           const uint8_t* obs, const uint8_t* next_obs, float* x, const EncBufs& e, hipStream_t st,
+                           bool prepared) {
+  const sq_dims& d = net.d;
+  if (!encoder_fused(net, 1, e) || d.n_conv != 3) return 1;
+  const float* b[4];
+  float* h[4];
+  for (int i = 0; i < d.n_conv; ++i) {
+    b[i] = ep + L.conv_b[i];
+    h[i] = e.h[i];
+  }
+  if (!prepared) SQ_TRY(encoder_prepare(net, 1, ep, L, e, st));
+  uint16_t* hh = twin_of(h[d.n_conv - 1], (long long)2 * sa.B * net.flat);
+  return encoder_fused_fwd_squint(sa, obs, next_obs, d.H, d.W, d.C, d.F, d.n_conv, d.k, x, e.wprep, b, h, hh, st);
 }
 
 bool encoder_grad_seg(const Net& net, int bf16, const Layout& L, const EncBufs& e, int n, GradSeg* seg) {
