@@ -237,25 +237,23 @@ static int enqueue_update(sq_agent* g, const sq_replay* R, float* stats, int act
   // state-based SAC: the sampled states [s; s'] (S2) are the features
   const bool image = d.n_conv > 0;
   const float* feat = g->S2;
-  if (!image || R->squinted) SQ_TRY(launch_sample_batch(sa, st));
-  if (image) {
+  // in bfloat16 the draw and the squint run inside the encoder's launch where the geometry allows
+  int fused = kNotApplicable;
+  if (image && bf)
+    fused = encoder_forward_squint(net, P, L, sa, R->obs, R->next_obs, g->x, g->enc, st, g->enc_map.n > 0,
+                                   R->squinted != 0);
+  if (fused != kNotApplicable) SQ_TRY(fused);
+  if (fused == kNotApplicable && (!image || R->squinted)) SQ_TRY(launch_sample_batch(sa, st));
+  if (image && fused == kNotApplicable) {
     // frames squinted at insertion are the k = 1 squint of the stored block means;
     // raw frames are drawn and squinted in one launch
-    // (in bfloat16 the draw and the squint run inside the encoder's launch where the geometry allows)
-    int fused = 1;
-    if (!R->squinted && bf)
-      fused = encoder_forward_squint(net, P, L, sa, R->obs, R->next_obs, g->x, g->enc, st, g->enc_map.n > 0);
-    if (fused != 1) {
-      SQ_TRY(fused);
-    } else {
-      if (R->squinted)
-        SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, net.side, net.side, d.C, 1, g->x, st));
-      else
-        SQ_TRY(launch_sample_squint(sa, R->obs, R->next_obs, d.H, d.W, d.C, d.k, g->x, st));
-      SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st, g->enc_map.n > 0));
-    }
-    feat = g->enc.h[d.n_conv - 1];
+    if (R->squinted)
+      SQ_TRY(launch_squint_pair(R->obs, R->next_obs, g->idx, B, net.side, net.side, d.C, 1, g->x, st));
+    else
+      SQ_TRY(launch_sample_squint(sa, R->obs, R->next_obs, d.H, d.W, d.C, d.k, g->x, st));
+    SQ_TRY(encoder_forward(net, bf, P, L, g->x, 2 * B, g->enc, st, g->enc_map.n > 0));
   }
+  if (image) feat = g->enc.h[d.n_conv - 1];
   SQ_TRY(trunks_forward(net, bf, P + L.actor_begin, P + L.critic_begin, g->target, g->pack, g->pack, g->tpack, L,
                         feat, flat, g->S2, S, B, g->actor, g->crit, st));
   ActorBufs ab = g->actor;

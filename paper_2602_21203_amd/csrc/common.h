@@ -38,6 +38,10 @@ inline int launch_status(const char* what) {
 
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
+// returned by a launcher whose fused or specialised form does not apply to its
+// arguments (nothing enqueued; the caller takes the general path)
+constexpr int kNotApplicable = -1;
+
 // ------------------------------------------------------------------ derived dims
 struct Net {
   sq_dims d;
@@ -270,7 +274,8 @@ bool encoder_fused_prep_map(int C, int F, int n_conv, int side, const long long*
 size_t encoder_fused_prep_floats(int C, int F, int n_conv);
 int encoder_fused_prep(int bf16, int C, int F, int n_conv, const float* const* W, float* wp, hipStream_t st);
 // The minibatch draw, the squint of its obs / next_obs frames (x: FP32 [2B][C][side][side] written for
-// the backward) and the bfloat16 encoder forward in one launch; 1 when the geometry has no such form
+// the backward) and the bfloat16 encoder forward in one launch; kNotApplicable when the geometry has
+// no such form
 int encoder_fused_fwd_squint(const SampleArgs& sa, const uint8_t* obs, const uint8_t* next_obs, int H, int W, int C,
                              int F, int n_conv, int k, float* x, const float* wp, const float* const* b,
                              float* const* h, uint16_t* hh, hipStream_t st);

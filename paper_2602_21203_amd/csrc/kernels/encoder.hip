@@ -533,13 +533,14 @@ __device__ void conv_fwd_layer_b(const __bf16* in, __bf16* out_lds, const __bf16
 }
 
 // SQK > 0: the launch also draws the minibatch and squints its frames (factor
-// SQK, raw uint8 HWC frames of side SD * SQK): the first `lead` workgroups take
-// the draw's items (as in the squint launch), and image workgroup i computes
-// replay row i of the draw itself (obs rows, then next_obs rows), sums each
-// output pixel's SQK x SQK block per channel (thread p owns pixel p), and writes
-// x = sum / (255 SQK^2) - 0.5 both to xout (FP32 CHW, for the backward) and,
-// rounded, to the first layer's LDS input: the separate squint launch and the
-// round trip of x disappear.  The arithmetic is the squint kernel's.
+// SQK, uint8 HWC frames of side SD * SQK; SQK = 1: the block means stored in a
+// ring at insertion): the first `lead` workgroups take the draw's items (as in
+// the squint launch), and image workgroup i computes replay row i of the draw
+// itself (obs rows, then next_obs rows), sums each output pixel's SQK x SQK
+// block per channel (thread p owns pixel p), and writes x = sum / (255 SQK^2) -
+// 0.5 both to xout (FP32 CHW, for the backward) and, rounded, to the first
+// layer's LDS input: the separate draw / squint launches and the round trip of x
+// disappear.  The arithmetic is the squint kernels'.
 template <int G, int C, int F, int NC, int SD, int NT, int SQK = 0>
 __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ x, int n, const __bf16* __restrict__ wp,
                                                       const float* __restrict__ b0, const float* __restrict__ b1,
@@ -569,21 +570,28 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
   // the images, then every layer's weight fragments of this wave, all requested up front
   constexpr int RX = SQK > 0 ? 1 : (G * C * SD * SD + NT - 1) / NT;
   constexpr int SEG = SQK * C;   // bytes of one source block row (squint form)
-  constexpr int NWD = SQK > 0 ? SQK * SEG / 4 : 1;
+  constexpr int NWD = SQK > 1 ? SQK * SEG / 4 : (SQK == 1 ? C : 1);
   float xv[RX];
-  unsigned fw[NWD];
+  unsigned fw[NWD];   // the block rows as 32-bit words (SQK > 1), or the pixel's C bytes (SQK = 1)
   if constexpr (SQK > 0) {
-    static_assert(G == 1 && NT == SD * SD && SEG % 4 == 0, "one thread per output pixel, 32-bit block rows");
+    static_assert(G == 1 && NT == SD * SD && (SQK == 1 || SEG % 4 == 0),
+                  "one thread per output pixel, 32-bit block rows");
     const int p = threadIdx.x, y = p / SD, xq = p - y * SD;
     constexpr int Wsrc = SD * SQK;
     const bool second = img0 >= sa.B;
     const uint8_t* frame = (second ? next_obs : obs) +
                            (long long)sample_row(sa, second ? img0 - sa.B : img0) * Wsrc * Wsrc * C;
+    if constexpr (SQK == 1) {
 #pragma unroll
-    for (int r = 0; r < SQK; ++r) {
-      const unsigned* w = reinterpret_cast<const unsigned*>(frame + ((long long)(y * SQK + r) * Wsrc + xq * SQK) * C);
+      for (int c = 0; c < C; ++c) fw[c] = frame[(long long)p * C + c];
+    } else {
 #pragma unroll
-      for (int q = 0; q < SEG / 4; ++q) fw[r * (SEG / 4) + q] = w[q];
+      for (int r = 0; r < SQK; ++r) {
+        const unsigned* w =
+            reinterpret_cast<const unsigned*>(frame + ((long long)(y * SQK + r) * Wsrc + xq * SQK) * C);
+#pragma unroll
+        for (int q = 0; q < SEG / 4; ++q) fw[r * (SEG / 4) + q] = w[q];
+      }
     }
   } else {
 #pragma unroll
@@ -605,15 +613,17 @@ __global__ __launch_bounds__(NT) void k_encoder_fwd_b(const float* __restrict__ 
     // each byte of the block rows into its channel's integer sum, then x
     int sum[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) sum[c] = 0;
+    for (int c = 0; c < C; ++c) sum[c] = SQK == 1 ? (int)fw[c] : 0;
+    if constexpr (SQK > 1) {
 #pragma unroll
-    for (int r = 0; r < SQK; ++r)
+      for (int r = 0; r < SQK; ++r)
 #pragma unroll
-      for (int q = 0; q < SEG / 4; ++q) {
-        const unsigned v = fw[r * (SEG / 4) + q];
+        for (int q = 0; q < SEG / 4; ++q) {
+          const unsigned v = fw[r * (SEG / 4) + q];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) sum[(4 * q + b) % C] += (int)((v >> (8 * b)) & 0xFFu);
-      }
+          for (int b = 0; b < 4; ++b) sum[(4 * q + b) % C] += (int)((v >> (8 * b)) & 0xFFu);
+        }
+    }
     const float scale = (float)(255 * SQK * SQK);
     const int p = threadIdx.x;
 #pragma unroll
@@ -1112,15 +1122,20 @@ int encoder_fused_fwd_squint(const SampleArgs& sa, const uint8_t* obs, const uin
                              float* const* h, uint16_t* hh, hipStream_t st) {
   const int n = 2 * sa.B;
   if (n <= 0) return SQ_OK;
-  // the headline geometry: 64 x 64 x 9 frames squinted 4x into the 16 x 16 encoder, one image per
-  // 256-thread workgroup (a thread per output pixel), 16-byte aligned frames
-  if (!(C == 9 && F == 32 && n_conv == 3 && k == 4 && H == 64 && W == 64 && kEncFwdGb == 1 &&
-        kEncFwdThreadsb == 256) || (uintptr_t)obs % 4 || (uintptr_t)next_obs % 4)
-    return 1;
+  // the headline geometry: 64 x 64 x 9 frames squinted 4x (or their 16 x 16 block means stored in a
+  // ring, k = 1) into the 16 x 16 encoder, one image per 256-thread workgroup (a thread per output pixel)
+  if (!(C == 9 && F == 32 && n_conv == 3 && kEncFwdGb == 1 && kEncFwdThreadsb == 256)) return kNotApplicable;
+  const bool raw = k == 4 && H == 64 && W == 64 && (uintptr_t)obs % 4 == 0 && (uintptr_t)next_obs % 4 == 0;
+  const bool stored = k == 1 && H == 16 && W == 16;
+  if (!raw && !stored) return kNotApplicable;
   const int lead = (int)((sample_items(sa.B, sa.A, sa.S) + kEncFwdThreadsb - 1) / kEncFwdThreadsb);
-  k_encoder_fwd_b<1, 9, 32, 3, 16, 256, 4><<<lead + n, 256, 0, st>>>(
-      nullptr, n, reinterpret_cast<const __bf16*>(wp), b[0], b[1], b[2], h[0], h[1], h[2], hh, obs, next_obs, sa,
-      lead, x);
+  const __bf16* wb = reinterpret_cast<const __bf16*>(wp);
+  if (raw)
+    k_encoder_fwd_b<1, 9, 32, 3, 16, 256, 4><<<lead + n, 256, 0, st>>>(nullptr, n, wb, b[0], b[1], b[2], h[0], h[1],
+                                                                       h[2], hh, obs, next_obs, sa, lead, x);
+  else
+    k_encoder_fwd_b<1, 9, 32, 3, 16, 256, 1><<<lead + n, 256, 0, st>>>(nullptr, n, wb, b[0], b[1], b[2], h[0], h[1],
+                                                                       h[2], hh, obs, next_obs, sa, lead, x);
   return launch_status("encoder_fwd_squint");
 }
 

@@ -1166,17 +1166,17 @@ static int run_h(int form, dim3 grid, const HMat& a, const HMat& b, const ST& ou
     case 3: launch_h<3>(grid, a, b, out, M, N, K, st); break;
     case kHDirect: launch_h<kHDirect>(grid, a, b, out, M, N, K, st); break;
     case kHKp | 1: launch_h<kHKp | 1>(grid, a, b, out, M, N, K, st); break;
-    default: return 1;
+    default: return kNotApplicable;
   }
   note_copy_product();
   return launch_status("gemm_h");
 }
 
-// the product on bfloat16 copies when both operands have them (SQ_OK, or 1: not eligible)
+// the product on bfloat16 copies when both operands have them (kNotApplicable: not eligible)
 static int try_h(int M, int N, int K, int batch, const MatArg& A, const MatArg& B, const StMat& out, hipStream_t st) {
   HMat ha, hb;
   bool ta, tb;
-  if (!hmat(A, M, K, batch, &ha, &ta) || !hmat(B, N, K, batch, &hb, &tb)) return 1;
+  if (!hmat(A, M, K, batch, &ha, &ta) || !hmat(B, N, K, batch, &hb, &tb)) return kNotApplicable;
   return run_h(hform(ta, tb, K, hkp(ha, hb)), dim3(cdiv(M, kTile), cdiv(N, kTile), batch), ha, hb, out, M, N, K, st);
 }
 
@@ -1240,7 +1240,7 @@ int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C,
   const int va = rkind(A), vb = rkind(B);
   if (bf16 && want_splits(M, N, K, batch, scratch, scratch_floats) == 1) {
     const int h = try_h(M, N, K, batch, A, B, out, st);
-    if (h != 1) return h;
+    if (h != kNotApplicable) return h;
   }
   if (bf16) {
     if (va && vb) return run_r<true, 1, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);

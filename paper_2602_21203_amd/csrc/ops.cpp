@@ -143,9 +143,9 @@ int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, 
 
 int encoder_forward_squint(const Net& net, const float* ep, const Layout& L, const SampleArgs& sa,
                            const uint8_t* obs, const uint8_t* next_obs, float* x, const EncBufs& e, hipStream_t st,
-                           bool prepared) {
+                           bool prepared, bool stored) {
   const sq_dims& d = net.d;
-  if (!encoder_fused(net, 1, e) || d.n_conv != 3) return 1;
+  if (!encoder_fused(net, 1, e) || d.n_conv != 3) return kNotApplicable;
   const float* b[4];
   float* h[4];
   for (int i = 0; i < d.n_conv; ++i) {
@@ -154,7 +154,11 @@ int encoder_forward_squint(const Net& net, const float* ep, const Layout& L, con
   }
   if (!prepared) SQ_TRY(encoder_prepare(net, 1, ep, L, e, st));
   uint16_t* hh = twin_of(h[d.n_conv - 1], (long long)2 * sa.B * net.flat);
-  return encoder_fused_fwd_squint(sa, obs, next_obs, d.H, d.W, d.C, d.F, d.n_conv, d.k, x, e.wprep, b, h, hh, st);
+  // stored frames are the block means at the squinted side: their squint is k = 1
+  return stored ? encoder_fused_fwd_squint(sa, obs, next_obs, net.side, net.side, d.C, d.F, d.n_conv, 1, x, e.wprep,
+                                           b, h, hh, st)
+                : encoder_fused_fwd_squint(sa, obs, next_obs, d.H, d.W, d.C, d.F, d.n_conv, d.k, x, e.wprep, b, h,
+                                           hh, st);
 }
 
 bool encoder_grad_seg(const Net& net, int bf16, const Layout& L, const EncBufs& e, int n, GradSeg* seg) {

@@ -22,10 +22,11 @@ void plan_encoder(const Net& net, int n, Bump& b, EncBufs* e, bool with_bwd);
 int encoder_forward(const Net& net, int bf16, const float* ep, const Layout& L, const float* x, int n,
                     const EncBufs& e, hipStream_t st, bool prepared = false);
 // bfloat16: the minibatch draw sa, the squint of its frames into x (2 sa.B images)
-// and the encoder forward in one launch; 1 when that form does not apply
+// and the encoder forward in one launch; kNotApplicable when that form does not apply.
+// stored: the frames are the block means a ring stored at insertion
 int encoder_forward_squint(const Net& net, const float* ep, const Layout& L, const SampleArgs& sa,
                            const uint8_t* obs, const uint8_t* next_obs, float* x, const EncBufs& e, hipStream_t st,
-                           bool prepared);
+                           bool prepared, bool stored);
 // rewrite e.wprep from the parameters (fused path only; no-op otherwise)
 int encoder_prepare(const Net& net, int bf16, const float* ep, const Layout& L, const EncBufs& e, hipStream_t st);
 // prepared: the fused path's rearranged weights from encoder_forward of the same

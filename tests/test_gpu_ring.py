@@ -122,3 +122,37 @@ def test_ring_update_graph_replays_match_eager():
         assert torch.equal(s_g, s_e), i
     assert torch.equal(a_graph.params, a_eager.params)
     r.close()
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_ring_update_on_block_constant_frames_equals_raw_update(prec):
+    """Frames constant over each k x k block: the ring stores their block means
+    exactly, so updates sampling the ring (the stored frames' k = 1 squint) equal
+    the updates on the raw frames bit for bit.  In bfloat16 both run the draw and
+    the squint inside the encoder's launch, from the raw blocks and from the
+    stored means; in FP32 both take the separate draw and squint launches."""
+    name, B, n = "full", 128, 256
+    print(f"block-constant ring vs raw prec={prec}", flush=True)
+    cfg = H.cfg(name)
+    rep = raw_batch(cfg, n, seed=61)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(61)
+    side, k = cfg["H"] // cfg["k"], cfg["k"]
+    for f in ("obs", "next_obs"):
+        base = torch.randint(0, 256, (n, side, side, cfg["C"]), generator=g, device="cuda", dtype=torch.uint8)
+        rep[f] = base.repeat_interleave(k, 1).repeat_interleave(k, 2).contiguous()
+    ring = api.Ring(cfg, n)
+    ring.insert(*(rep[f] for f in FIELDS))
+    raw = dict(rep, size=n)
+    a_raw = api.Agent(cfg, H.params(name), B, prec=prec)
+    a_ring = api.Agent(cfg, H.params(name), B, prec=prec)
+    s_raw = a_raw.sac_update(raw, 2)
+    s_ring = a_ring.sac_update(ring, 2)
+    torch.cuda.synchronize()
+    assert torch.isfinite(s_raw).all()
+    assert torch.equal(s_raw, s_ring)
+    for attr in ("params", "target", "m", "v", "counters"):
+        assert torch.equal(getattr(a_raw, attr), getattr(a_ring, attr)), attr
+    a_raw.close()
+    a_ring.close()
+    ring.close()
