@@ -203,6 +203,17 @@ static int make_twins(sq_agent* g) {
   SQ_TRY_HIP(hipMemset(g->wsh, 0, bytes));
   Bump h{(char*)(((uintptr_t)g->wsh + 255) & ~(uintptr_t)255)};
   for (const Item& it : items) twin_register(g, it.f, (long long)it.n, h.take<uint16_t>(it.n));
+  // the hidden layers' ReLU outputs are read through their copies only (the
+  // products read the copies; the LayerNorm backward recomputes the ReLU mask), so
+  // their FP32 values are not kept.  That needs rows the copy loads can read (a
+  // width that is a multiple of 8) and, for the critics' second layer, a copy of
+  // the head gradient its weight gradient is taken against (the C51 heads)
+  if (H % 8 == 0) {
+    std::vector<Item> drop = {{g->crit.g1, 4 * B * H}, {g->aux.g1, 2 * B * H},  {g->aux.g2, 2 * B * H},
+                              {g->actor.g1, 2 * B * H}, {g->actor.g2, 2 * B * H}};
+    if (d.atoms > 1) drop.push_back({g->crit.g2, 4 * B * H});
+    for (const Item& it : drop) fp32_drop_register(g, it.f, (long long)it.n);
+  }
   g->pk_critic.pack_h = g->pk_actor.pack_h = twin_of(g->pack, g->L.pack_total);
   g->pk_critic.tpack_h = twin_of(g->tpack, g->L.pack_critic_end);
   return SQ_OK;

@@ -229,6 +229,10 @@ void twin_register(const void* owner, const float* f, long long n, uint16_t* h);
 void twin_unregister(const void* owner);
 // the twin of [f, f + n), or nullptr when no registered buffer holds that range
 uint16_t* twin_of(const float* f, long long n = 1);
+// FP32 values no longer kept: [f, f + n)'s producers write the twin only (owner's
+// registration); fp32_dropped(p) tells whether p lies in such a range
+void fp32_drop_register(const void* owner, const float* f, long long n);
+bool fp32_dropped(const float* f);
 // products enqueued on twins so far (process-wide)
 void note_copy_product();
 long long copy_products();
@@ -312,6 +316,7 @@ struct LnFwdJob {
   const float* e1; long long ld_e1; int w1; const float* e2; long long ld_e2; int w2;
   LnGroups grp;
   uint16_t* yh;   // bfloat16 copy of y (nullable; ln_fwd_job fills it)
+  int y32;        // y stored in FP32 too (ln_fwd_job: unless its buffer's FP32 values were dropped)
 };
 LnFwdJob ln_fwd_job(const float* pre, long long ld_pre, long long sz_pre, int rows, int H, int batch, const float* g,
                     const float* beta, long long sz_par, int act_tanh, float* y, long long ld_y, long long sz_y,
@@ -319,9 +324,12 @@ LnFwdJob ln_fwd_job(const float* pre, long long ld_pre, long long sz_pre, int ro
                     long long ld_e2, int w2, const LnGroups* grp = nullptr);
 int ln_act_fwd_pair(const LnFwdJob& j0, const LnFwdJob& j1, hipStream_t st);
 int ln_bwd_partial_rows(int rows);
+// y: the forward's output (read for tanh only); beta: the shift (read for ReLU,
+// whose mask is recomputed from x-hat, gain and shift); g and beta sz_par apart
 int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y, long long ld_y,
-               long long sz_y, const float* xhat, const float* rstd, const float* g, long long sz_par,
-               int rows, int H, int batch, int act_tanh, float* dpre, float* partials, hipStream_t st);
+               long long sz_y, const float* xhat, const float* rstd, const float* g, const float* beta,
+               long long sz_par, int rows, int H, int batch, int act_tanh, float* dpre, float* partials,
+               hipStream_t st);
 int col_partials(const float* src, long long ld, long long sz, int rows, int N, int batch, float* part,
                  hipStream_t st);
 // column sums of partial rows: part [batch][k][nrows][H] -> out[kk][z*out_sz + c]

@@ -1086,6 +1086,16 @@ static StMat stmat(const OutArg& c) {
   return StMat{c.p, c.ld, c.sz, c.bias, c.bias_sz, c.accumulate, c.relu, c.bias_alt, c.bias_zalt};
 }
 
+// A product on the FP32 values of an operand whose owner keeps only its bfloat16
+// copy would read stale data: refuse it (the copy-reading form did not apply).
+static bool fp32_ok(const MatArg& m) {
+  return !fp32_dropped(m.p) && !(m.alt && fp32_dropped(m.alt)) && !(m.kp && fp32_dropped(m.kp));
+}
+static int refuse_dropped(const char* what) {
+  set_error("%s: an operand keeps only its bfloat16 copy, which this product's shape cannot read", what);
+  return SQ_EINVAL;
+}
+
 // the K split gemm() would choose (1: none)
 static int want_splits(int M, int N, int K, int batch, const float* scratch, size_t scratch_floats) {
   const int tiles = cdiv(M, kTile) * cdiv(N, kTile) * batch;
@@ -1238,10 +1248,13 @@ int gemm(int bf16, int M, int N, int K, int batch, MatArg A, MatArg B, OutArg C,
   }
   const StMat out = stmat(C);
   const int va = rkind(A), vb = rkind(B);
-  if (bf16 && want_splits(M, N, K, batch, scratch, scratch_floats) == 1) {
+  // the copy form does not split K; an operand without FP32 values takes it unsplit
+  const bool fp32 = fp32_ok(A) && fp32_ok(B);
+  if (bf16 && (!fp32 || want_splits(M, N, K, batch, scratch, scratch_floats) == 1)) {
     const int h = try_h(M, N, K, batch, A, B, out, st);
     if (h != kNotApplicable) return h;
   }
+  if (!fp32) return refuse_dropped("gemm");
   if (bf16) {
     if (va && vb) return run_r<true, 1, 1>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
     if (va) return run_r<true, 1, 0>(M, N, K, batch, A, B, out, scratch, scratch_floats, st);
@@ -1287,6 +1300,7 @@ int gemm_tanh_gauss(int bf16, int n, int A, int K, MatArg X, MatArg W, const flo
     note_copy_product();
     return launch_status("gemm_tanh_gauss");
   }
+  if (!fp32_ok(X) || !fp32_ok(W)) return refuse_dropped("gemm_tanh_gauss");
   if (bf16)
     k_gemm_r<true, 1, 1, StTanhGauss, false><<<grid, kThreads, 0, st>>>(rmat(X), rmat(W), tg, none, n, 2 * A, K, K);
   else
@@ -1328,6 +1342,7 @@ int gemm_tg_bwd(int bf16, const GemmProb& dx, int A, const TgBwdJob& tg, hipStre
       return launch_status("gemm_tg_bwd");
     }
   }
+  if (!fp32_ok(dx.A) || !fp32_ok(dx.B)) return refuse_dropped("gemm_tg_bwd");
   if (bf16)
     k_gemm_r<true, 1, 0, StTgBwd, false><<<grid, kThreads, 0, st>>>(rmat(dx.A), rmat(dx.B), ep, none, n, A, dx.K,
                                                                      dx.K);
@@ -1376,6 +1391,7 @@ int gemm_pair(int bf16, const GemmProb& p0, const GemmProb& p1, float* scratch, 
       return launch_status("gemm_pair_h");
     }
   }
+  if (!fp32_ok(p0.A) || !fp32_ok(p0.B) || !fp32_ok(p1.A) || !fp32_ok(p1.B)) return refuse_dropped("gemm_pair");
   if (fwd_kinds) {
     if (bf16) k_gemm_pair_f<true><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);
     else k_gemm_pair_f<false><<<t0 + t1, kThreads, 0, st>>>(q0, q1, t0);

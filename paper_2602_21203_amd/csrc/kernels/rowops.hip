@@ -91,6 +91,18 @@ __device__ __forceinline__ void ln_load_row(const float* __restrict__ p, int H, 
   }
 }
 
+// a per-column parameter row (gain, shift) in the lane mapping above, read element by
+// element (its start need not be 16-byte aligned); under VEC every column is < H
+template <int E, bool VEC>
+__device__ __forceinline__ void ln_load_par(const float* __restrict__ p, int H, int lane, float (&v)[E]) {
+#pragma unroll
+  for (int t = 0; t < E; ++t) {
+    const int j = ln_col<E, VEC>(lane, t);
+    if constexpr (VEC) v[t] = p[j];
+    else v[t] = j < H ? p[j] : 0.f;
+  }
+}
+
 template <int E, bool VEC>
 __device__ __forceinline__ void ln_store_row(float* __restrict__ p, int H, int lane, const float (&v)[E]) {
   if constexpr (VEC) {
@@ -134,7 +146,7 @@ __device__ __forceinline__ void ln_fwd_row(const float* __restrict__ pre, long l
                                            int rows, int H, const float* __restrict__ g,
                                            const float* __restrict__ beta, long long sz_par, int act_tanh,
                                            float* __restrict__ y, long long ld_y, long long sz_y,
-                                           uint16_t* __restrict__ yh,
+                                           uint16_t* __restrict__ yh, int y32,
                                            float* __restrict__ xhat, float* __restrict__ rstd,
                                            const float* __restrict__ e1, long long ld_e1, int w1,
                                            const float* __restrict__ e2, long long ld_e2, int w2,
@@ -144,12 +156,8 @@ __device__ __forceinline__ void ln_fwd_row(const float* __restrict__ pre, long l
   const float* bz = second ? grp.beta_alt + (z - grp.zalt) * sz_par : beta + z * sz_par;
   float v[E], gv[E], bv[E];
   ln_load_row<E, VEC>(pre + z * sz_pre + row * ld_pre, H, lane, v);
-#pragma unroll
-  for (int t = 0; t < E; ++t) {
-    const int j = ln_col<E, VEC>(lane, t);
-    gv[t] = j < H ? gz[j] : 0.f;
-    bv[t] = j < H ? bz[j] : 0.f;
-  }
+  ln_load_par<E, VEC>(gz, H, lane, gv);
+  ln_load_par<E, VEC>(bz, H, lane, bv);
   float s = 0.f;
 #pragma unroll
   for (int t = 0; t < E; ++t) s += v[t];
@@ -166,14 +174,14 @@ __device__ __forceinline__ void ln_fwd_row(const float* __restrict__ pre, long l
 #pragma unroll
   for (int t = 0; t < E; ++t) {
     xh[t] = (v[t] - mean) * rs;
-    const float a = gv[t] * xh[t] + bv[t];
+    const float a = __builtin_fmaf(gv[t], xh[t], bv[t]);   // the backward recomputes it bit for bit
     o[t] = act_tanh ? tanhf(a) : fmaxf(a, 0.f);
   }
   float* yr = y + z * sz_y + row * ld_y;
   uint16_t* yhr = yh ? yh + z * sz_y + row * ld_y : nullptr;
   const bool save = !second || grp.save_alt;
   if (save) ln_store_row<E, VEC>(xhat + ((long long)z * rows + row) * H, H, lane, xh);
-  ln_store_row<E, VEC>(yr, H, lane, o);
+  if (y32) ln_store_row<E, VEC>(yr, H, lane, o);
   if (yhr) ln_store_row_h<E, VEC>(yhr, H, lane, o);
   if (save && lane == 0) rstd[(long long)z * rows + row] = rs;
   const float* e1z = e1 + z * grp.sz_e1;
@@ -195,15 +203,15 @@ __global__ __launch_bounds__(256) void k_ln_fwd(const float* __restrict__ pre, l
                                                 int rows, int H, const float* __restrict__ g,
                                                 const float* __restrict__ beta, long long sz_par, int act_tanh,
                                                 float* __restrict__ y, long long ld_y, long long sz_y,
-                                                uint16_t* __restrict__ yh,
+                                                uint16_t* __restrict__ yh, int y32,
                                                 float* __restrict__ xhat, float* __restrict__ rstd,
                                                 const float* __restrict__ e1, long long ld_e1, int w1,
                                                 const float* __restrict__ e2, long long ld_e2, int w2,
                                                 LnGroups grp) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= rows) return;
-  ln_fwd_row<E, VEC>(pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, yh, xhat, rstd, e1,
-                     ld_e1, w1, e2, ld_e2, w2, grp, row, blockIdx.y, threadIdx.x & 63);
+  ln_fwd_row<E, VEC>(pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, yh, y32, xhat, rstd,
+                     e1, ld_e1, w1, e2, ld_e2, w2, grp, row, blockIdx.y, threadIdx.x & 63);
 }
 
 // row-block b (4 rows) of a job: batch b / cdiv(rows, 4)
@@ -213,7 +221,7 @@ __device__ __forceinline__ void ln_fwd_job_block(const LnFwdJob& j, int b) {
   const int row = (b % rb) * 4 + (threadIdx.x >> 6);
   if (row >= j.rows) return;
   ln_fwd_row<E, VEC>(j.pre, j.ld_pre, j.sz_pre, j.rows, j.H, j.g, j.beta, j.sz_par, j.act_tanh, j.y, j.ld_y, j.sz_y,
-                     j.yh, j.xhat, j.rstd, j.e1, j.ld_e1, j.w1, j.e2, j.ld_e2, j.w2, j.grp, row, b / rb,
+                     j.yh, j.y32, j.xhat, j.rstd, j.e1, j.ld_e1, j.w1, j.e2, j.ld_e2, j.w2, j.grp, row, b / rb,
                      threadIdx.x & 63);
 }
 
@@ -243,6 +251,13 @@ static int ln_dispatch(int H, bool vec_ok, F&& f) {
   return f(std::integral_constant<int, 16>{}, std::false_type{});
 }
 
+// whether the LayerNorm forward stores y in FP32: always, unless its owner dropped
+// the FP32 values of y's buffer (a ReLU output with a bfloat16 copy, no copied
+// columns: the backward recomputes the ReLU mask from x-hat, gain and shift)
+static int ln_keeps_fp32(const float* y, const uint16_t* yh, int act_tanh, int extra_cols) {
+  return (yh && !act_tanh && extra_cols == 0 && fp32_dropped(y)) ? 0 : 1;
+}
+
 // elements of y a LayerNorm forward writes, from its first
 static long long ln_out_extent(int rows, int H, int batch, long long ld_y, long long sz_y, int w1, int w2) {
   if (rows <= 0 || batch <= 0) return 0;
@@ -257,11 +272,12 @@ int ln_act_fwd(const float* pre, long long ld_pre, long long sz_pre, int rows, i
   const LnGroups grp = groups ? *groups : LnGroups{kNoAlt, nullptr, nullptr, 0, nullptr};
   const bool vec = al16(pre, ld_pre, sz_pre) && al16(y, ld_y, sz_y) && al16(xhat, H);
   uint16_t* yh = twin_of(y, ln_out_extent(rows, H, batch, ld_y, sz_y, w1, w2));
+  const int y32 = ln_keeps_fp32(y, yh, act_tanh, w1 + w2);
   dim3 grid(cdiv(rows, 4), batch);
   return ln_dispatch(H, vec, [&](auto e, auto v) {
     k_ln_fwd<decltype(e)::value, decltype(v)::value><<<grid, 256, 0, st>>>(
-        pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, yh, xhat, rstd, e1, ld_e1, w1, e2,
-        ld_e2, w2, grp);
+        pre, ld_pre, sz_pre, rows, H, g, beta, sz_par, act_tanh, y, ld_y, sz_y, yh, y32, xhat, rstd, e1, ld_e1, w1,
+        e2, ld_e2, w2, grp);
     return launch_status("ln_fwd");
   });
 }
@@ -270,9 +286,10 @@ LnFwdJob ln_fwd_job(const float* pre, long long ld_pre, long long sz_pre, int ro
                     const float* beta, long long sz_par, int act_tanh, float* y, long long ld_y, long long sz_y,
                     float* xhat, float* rstd, const float* e1, long long ld_e1, int w1, const float* e2,
                     long long ld_e2, int w2, const LnGroups* groups) {
+  uint16_t* yh = twin_of(y, ln_out_extent(rows, H, batch, ld_y, sz_y, w1, w2));
   return LnFwdJob{pre, ld_pre, sz_pre, rows, H, batch, g, beta, sz_par, act_tanh, y, ld_y, sz_y, xhat, rstd, e1,
                   ld_e1, w1, e2, ld_e2, w2, groups ? *groups : LnGroups{kNoAlt, nullptr, nullptr, 0, nullptr},
-                  twin_of(y, ln_out_extent(rows, H, batch, ld_y, sz_y, w1, w2))};
+                  yh, ln_keeps_fp32(y, yh, act_tanh, w1 + w2)};
 }
 
 static int ln_fwd_alone(const LnFwdJob& j, hipStream_t st) {
@@ -306,8 +323,8 @@ template <int E, bool VEC>
 __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_ln_bwd(
     const float* __restrict__ dy, long long ld_dy, long long sz_dy, const float* __restrict__ y, long long ld_y,
     long long sz_y, const float* __restrict__ xhat, const float* __restrict__ rstd, const float* __restrict__ g,
-    long long sz_par, int rows, int H, int act_tanh, float* __restrict__ dpre, uint16_t* __restrict__ dpre_h,
-    float* __restrict__ part) {
+    const float* __restrict__ beta, long long sz_par, int rows, int H, int act_tanh, float* __restrict__ dpre,
+    uint16_t* __restrict__ dpre_h, float* __restrict__ part) {
   extern __shared__ float shp[];   // [3][kLnRowsPerBlock][H] when partials are wanted
   constexpr int R = kLnRowsPerBlock;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -315,26 +332,26 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_ln_bwd(
   const int nblk = gridDim.x;
   const int row = blk * R + wave;
   const float* gz = g + z * sz_par;
+  const float* bz = beta + z * sz_par;
   float pb[E], pg[E], pz[E];
 #pragma unroll
   for (int t = 0; t < E; ++t) pb[t] = pg[t] = pz[t] = 0.f;
   if (row < rows) {
+    // the activation's derivative: tanh' = 1 - y^2 from y; the ReLU mask from the
+    // recomputed pre-activation fma(g, x-hat, shift) > 0 (y > 0 exactly when it is)
+    // yv: y's row (tanh) or the shift (ReLU), one load pattern for both
     float dv[E], yv[E], xh[E], gv[E];
     ln_load_row<E, VEC>(dy + z * sz_dy + row * ld_dy, H, lane, dv);
-    ln_load_row<E, VEC>(y + z * sz_y + row * ld_y, H, lane, yv);
     ln_load_row<E, VEC>(xhat + ((long long)z * rows + row) * H, H, lane, xh);
-#pragma unroll
-    for (int t = 0; t < E; ++t) {
-      const int j = ln_col<E, VEC>(lane, t);
-      gv[t] = j < H ? gz[j] : 0.f;
-    }
+    ln_load_par<E, VEC>(gz, H, lane, gv);
+    ln_load_par<E, VEC>(act_tanh ? y + z * sz_y + row * ld_y : bz, H, lane, yv);
     const float rs = rstd[(long long)z * rows + row];
     float dz[E];
     float s1 = 0.f, s2 = 0.f;
 #pragma unroll
     for (int t = 0; t < E; ++t) {
       const float yy = yv[t];
-      dz[t] = dv[t] * (act_tanh ? (1.f - yy * yy) : (yy > 0.f ? 1.f : 0.f));
+      dz[t] = dv[t] * (act_tanh ? (1.f - yy * yy) : (__builtin_fmaf(gv[t], xh[t], yy) > 0.f ? 1.f : 0.f));
       const float dx = dz[t] * gv[t];
       s1 += dx;
       s2 += dx * xh[t];
@@ -369,16 +386,20 @@ __global__ __launch_bounds__(64 * kLnRowsPerBlock) void k_ln_bwd(
 int ln_bwd_partial_rows(int rows) { return cdiv(rows, kLnRowsPerBlock); }
 
 int ln_act_bwd(const float* dy, long long ld_dy, long long sz_dy, const float* y, long long ld_y, long long sz_y,
-               const float* xhat, const float* rstd, const float* g, long long sz_par, int rows, int H, int batch,
-               int act_tanh, float* dpre, float* partials, hipStream_t st) {
+               const float* xhat, const float* rstd, const float* g, const float* beta, long long sz_par, int rows,
+               int H, int batch, int act_tanh, float* dpre, float* partials, hipStream_t st) {
   if (rows <= 0) return SQ_OK;
+  if (act_tanh ? !y : !beta) {
+    set_error("ln_act_bwd: tanh needs y, ReLU needs the shift");
+    return SQ_EINVAL;
+  }
   dim3 grid(cdiv(rows, kLnRowsPerBlock), batch);
   const size_t lds = partials ? (size_t)3 * kLnRowsPerBlock * H * sizeof(float) : 0;
-  const bool vec = al16(dy, ld_dy, sz_dy) && al16(y, ld_y, sz_y) && al16(xhat, H) && al16(dpre, H);
+  const bool vec = al16(dy, ld_dy, sz_dy) && al16(xhat, H) && al16(dpre, H);
   uint16_t* dpre_h = twin_of(dpre, (long long)batch * rows * H);
   return ln_dispatch(H, vec, [&](auto e, auto v) {
     k_ln_bwd<decltype(e)::value, decltype(v)::value><<<grid, 64 * kLnRowsPerBlock, lds, st>>>(
-        dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, sz_par, rows, H, act_tanh, dpre, dpre_h, partials);
+        dy, ld_dy, sz_dy, y, ld_y, sz_y, xhat, rstd, g, beta, sz_par, rows, H, act_tanh, dpre, dpre_h, partials);
     return launch_status("ln_bwd");
   });
 }

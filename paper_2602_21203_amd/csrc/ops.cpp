@@ -340,8 +340,8 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
     SQ_TRY(grads(bf16, dx, params ? &dw : nullptr, c.split, st));
   }
   // second hidden layer
-  SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g2, H, nH, c.l2.xhat, c.l2.rstd, cp + (q.l2.g - c0), tw, n, H, 2, 0, c.dB,
-                    params ? c.part_l2 : nullptr, st));
+  SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g2, H, nH, c.l2.xhat, c.l2.rstd, cp + (q.l2.g - c0), cp + (q.l2.beta - c0), tw,
+                    n, H, 2, 0, c.dB, params ? c.part_l2 : nullptr, st));
   {
     const GemmProb dx = prob_dx(n, H, H, 2, c.dB, H, nH, w.W(q.l2.W, q.l2.Wp), w.ld(q.l2.in, q.l2.ldp), twW, c.dA,
                                 H, nH);
@@ -350,8 +350,8 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
   }
   // first hidden layer; the shared input [h | s | a] collects the gradient of both
   // twins as one contraction over k = (twin, hidden unit)
-  SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g1, H, nH, c.l1.xhat, c.l1.rstd, cp + (q.l1.g - c0), tw, n, H, 2, 0, c.dB,
-                    params ? c.part_l1 : nullptr, st));
+  SQ_TRY(ln_act_bwd(c.dA, H, nH, c.g1, H, nH, c.l1.xhat, c.l1.rstd, cp + (q.l1.g - c0), cp + (q.l1.beta - c0), tw,
+                    n, H, 2, 0, c.dB, params ? c.part_l1 : nullptr, st));
   const float* W1a = w.W(L.q[0].l1.W, L.q[0].l1.Wp);
   const float* W1b = w.W(L.q[1].l1.W, L.q[1].l1.Wp);
   const long long ld1 = w.ld(q.l1.in, q.l1.ldp);
@@ -390,8 +390,8 @@ int critic_backward(const Net& net, int bf16, const float* cp, const float* cpac
   }
   if (trunk) {
     // (the LayerNorm backward outputs all go to dB, whose bfloat16 copy the products read)
-    SQ_TRY(ln_act_bwd(c.dX1, cld, 0, c.X1, cld, 0, c.t.xhat, c.t.rstd, cp + (T.g - c0), 0, n, P, 1, 1, c.dB,
-                      params ? c.part_t : nullptr, st));
+    SQ_TRY(ln_act_bwd(c.dX1, cld, 0, c.X1, cld, 0, c.t.xhat, c.t.rstd, cp + (T.g - c0), cp + (T.beta - c0), 0, n,
+                      P, 1, 1, c.dB, params ? c.part_t : nullptr, st));
     const GemmProb dw = prob_dw(n, P, net.flat, 1, c.dB, P, 0, feat, ld_feat, 0, dcp + (T.W - c0), net.flat, 0);
     if (dfeat) {
       const GemmProb dx = prob_dx(n, P, net.flat, 1, c.dB, P, 0, w.W(T.W, T.Wp), w.ld(T.in, T.ldp), 0, dfeat,
@@ -525,16 +525,16 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
     const GemmProb dw = prob_dw(n, 2 * A, H, 1, a.dhead, a.ldh, 0, a.g2, H, 0, dap + (L.aout.W - a0), H, 0);
     SQ_TRY(grads(bf16, dx, &dw, a.split, st));
   }
-  SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g2, H, 0, a.l2.xhat, a.l2.rstd, ap + (L.al2.g - a0), 0, n, H, 1, 0, a.dB, a.part_l2,
-                    st));
+  SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g2, H, 0, a.l2.xhat, a.l2.rstd, ap + (L.al2.g - a0), ap + (L.al2.beta - a0), 0, n,
+                    H, 1, 0, a.dB, a.part_l2, st));
   {
     const GemmProb dx = prob_dx(n, H, H, 1, a.dB, H, 0, w.W(L.al2.W, L.al2.Wp), w.ld(L.al2.in, L.al2.ldp), 0, a.dA,
                                 H, 0);
     const GemmProb dw = prob_dw(n, H, H, 1, a.dB, H, 0, a.g1, H, 0, dap + (L.al2.W - a0), H, 0);
     SQ_TRY(grads(bf16, dx, &dw, a.split, st));
   }
-  SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g1, H, 0, a.l1.xhat, a.l1.rstd, ap + (L.al1.g - a0), 0, n, H, 1, 0, a.dB, a.part_l1,
-                    st));
+  SQ_TRY(ln_act_bwd(a.dA, H, 0, a.g1, H, 0, a.l1.xhat, a.l1.rstd, ap + (L.al1.g - a0), ap + (L.al1.beta - a0), 0, n,
+                    H, 1, 0, a.dB, a.part_l1, st));
   {
     // only the projection columns of the actor input need a gradient
     const GemmProb dx = prob_dx(n, H, P, 1, a.dB, H, 0, w.W(L.al1.W, L.al1.Wp), w.ld(L.al1.in, L.al1.ldp), 0,
@@ -542,8 +542,8 @@ int actor_backward(const Net& net, int bf16, const float* ap, const float* pack,
     const GemmProb dw = prob_dw(n, H, cin, 1, a.dB, H, 0, a.X1, ald, 0, dap + (L.al1.W - a0), cin, 0);
     SQ_TRY(grads(bf16, dx, &dw, a.split, st));
   }
-  SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, ald, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), 0, n, P, 1, 1, a.dB, a.part_t,
-                    st));
+  SQ_TRY(ln_act_bwd(a.dX1, P, 0, a.X1, ald, 0, a.t.xhat, a.t.rstd, ap + (T.g - a0), ap + (T.beta - a0), 0, n, P, 1,
+                    1, a.dB, a.part_t, st));
   SQ_TRY(linear_dw(bf16, n, P, net.flat, 1, a.dB, P, 0, feat, ld_feat, 0, dap + (T.W - a0), net.flat, 0, a.split, st));
   if (defer_colsum) return SQ_OK;
   const int pr = ln_bwd_partial_rows(n);
