@@ -638,59 +638,98 @@ __device__ float project_row(const float* p, int N, int lane, float v_min, float
   return wave_sum(mz);
 }
 
-// Projection of one row with the hat weights of atom i restricted to the atoms j
-// that reach it.  The projected positions b_j are non-decreasing in j (every step
-// from z_j to b_j is monotone, and so is its rounding), so the j with
-// |b_j - i| < 1 form one run [lo, hi), found by bisection over b in the wave's
-// LDS slice; the terms skipped elsewhere are exact zeros, so m_i is the same sum,
-// in the same j order, as the walk over every atom.
+// Projection of one row by segments.  The projected positions b_j are
+// non-decreasing in j (every step from z_j to b_j is monotone, and so is its
+// rounding), so their integer parts l_j are too, and the atoms j sharing an l form
+// one contiguous segment.  Atom j's hat weight max(0, 1 - |b_j - i|) is 1 - f_j at
+// i = l_j and f_j at l_j + 1 (f_j = b_j - l_j), zero elsewhere; so m_i is the sum of
+// p (1 - f) over segment i plus the sum of p f over segment i - 1.  A segmented
+// inclusive scan across the wave (fixed order, non-negative terms) leaves each
+// segment's two sums at its last atom, which stores them at atoms l and l + 1 of
+// the wave's LDS slices ma and mc; atoms that no segment reaches stay zero.  Every
+// row costs the same, also one whose positions all coincide (a terminal
+// transition puts every atom at the reward).
 template <int T>
 __device__ float project_row_t(const float (&p)[T], int N, int lane, float v_min, float dz, float r, float d,
-                              float gamma, float bonus, float* bl, float* pl, float (&mi)[T]) {
+                              float gamma, float bonus, float* ma, float* mc, float (&mi)[T]) {
   int nan_lane = 0;
+  int l[T], hd[T];
+  float a[T], c[T];
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int j = lane + 64 * t;
     const float zj = v_min + (float)j * dz;
     const float tz = r + gamma * (1.f - d) * (zj + bonus);
+    l[t] = N;          // past the last atom: a segment of its own, holding zeros
+    a[t] = c[t] = 0.f;
     if (j < N) {
       const float q = (tz - v_min) / dz;
       nan_lane |= q != q;
-      bl[j] = fminf(fmaxf(q, 0.f), (float)(N - 1));
-      pl[j] = p[t];
+      const float b = fminf(fmaxf(q, 0.f), (float)(N - 1));
+      l[t] = (int)b;
+      const float f = b - (float)l[t];
+      a[t] = p[t] * (1.f - f);
+      c[t] = p[t] * f;
+      ma[j] = 0.f;
+      mc[j] = 0.f;
     }
   }
   // fminf / fmaxf drop a NaN; a row whose shifted atoms are not numbers gets a
   // NaN distribution instead (as the clamp of the definition keeps it), so the
   // loss and the statistics of the update report it
   const bool nan_row = __any(nan_lane);
+  // segment heads: the first atom, and every atom whose l differs from its predecessor's
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    int prev = __shfl_up(l[t], 1);
+    if (lane == 0) prev = t > 0 ? __builtin_amdgcn_readlane(l[t - 1], 63) : -1;
+    hd[t] = l[t] != prev;
+  }
+  // scan each 64-atom slot; hd becomes "a head lies between the slot's start and here"
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+      const float ya = __shfl_up(a[t], o), yc = __shfl_up(c[t], o);
+      const int yh = __shfl_up(hd[t], o);
+      if (lane >= o) {
+        if (!hd[t]) {
+          a[t] = ya + a[t];
+          c[t] = yc + c[t];
+        }
+        hd[t] |= yh;
+      }
+    }
+  }
+  // atoms of a slot before its first head continue the previous slot's last segment
+#pragma unroll
+  for (int t = 1; t < T; ++t) {
+    const float ca = lane_read(a[t - 1], 63), cc = lane_read(c[t - 1], 63);
+    if (!hd[t]) {
+      a[t] = ca + a[t];
+      c[t] = cc + c[t];
+    }
+  }
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the zeros land before the segment sums
+#pragma unroll
+  for (int t = 0; t < T; ++t) {
+    const int j = lane + 64 * t;
+    int next = __shfl_down(l[t], 1);
+    if (lane == 63) next = t + 1 < T ? __builtin_amdgcn_readlane(l[t + 1], 0) : N;
+    if (j < N && next != l[t]) {
+      ma[l[t]] = a[t];
+      if (l[t] + 1 < N) mc[l[t] + 1] = c[t];
+    }
+  }
   asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
   float mz = 0.f;
 #pragma unroll
   for (int t = 0; t < T; ++t) {
     const int i = lane + 64 * t;
-    const float fi = (float)i;
-    // lo: first j with b_j - i > -1; hi: first j with b_j - i >= 1
-    int lo = 0, hi = 0;
-    if (i < N) {
-      int a = 0, c = N;
-      while (a < c) {
-        const int h = (a + c) >> 1;
-        if (bl[h] - fi > -1.f) c = h; else a = h + 1;
-      }
-      lo = a;
-      c = N;
-      while (a < c) {
-        const int h = (a + c) >> 1;
-        if (bl[h] - fi >= 1.f) c = h; else a = h + 1;
-      }
-      hi = a;
-    }
-    float acc = 0.f;
-    for (int j = lo; j < hi; ++j) acc += pl[j] * fmaxf(0.f, 1.f - fabsf(bl[j] - fi));
+    float acc = i < N ? ma[i] + mc[i] : 0.f;
     if (nan_row) acc = __builtin_nanf("");
     mi[t] = acc;
-    if (i < N) mz += acc * (v_min + fi * dz);
+    if (i < N) mz += acc * (v_min + (float)i * dz);
   }
   return wave_sum(mz);
 }
