@@ -391,6 +391,11 @@ SQ_API int sq_agent_graph_count(const sq_agent* agent, long long* captured, int*
 /* Copy of the replay rows drawn by the agent's last enqueued update (idx [batch]
  * int, device), ordered on `stream` after that update. */
 SQ_API int sq_agent_last_indices(const sq_agent* agent, int* idx, sq_stream_t stream);
+/* Copy of the projected target distribution m of the agent's last enqueued
+ * update (Eq. (1) in categorical form, the C51 projection of the twin-target
+ * softmax: m [batch][atoms] float, device), ordered on `stream` after that update.
+ * SQ_EINVAL for scalar critics (atoms = 1), which have no distribution. */
+SQ_API int sq_agent_last_target(const sq_agent* agent, float* m, sq_stream_t stream);
 /* Row of transition i of an insertion at write position pos in a ring of
  * `capacity` rows: (pos + i) mod capacity, in 64-bit arithmetic.  [host] */
 SQ_API int sq_ring_row(int pos, long long i, int capacity, int* row);

@@ -106,6 +106,7 @@ def _load():
         "sq_gaussian": (c_int, [c_ull, ctypes.c_uint, ctypes.c_uint, c_int, c_vp, c_vp]),
         "sq_agent_graph_count": (c_int, [c_vp, P(c_ll), P(c_int)]),
         "sq_agent_last_indices": (c_int, [c_vp, c_vp, c_vp]),
+        "sq_agent_last_target": (c_int, [c_vp, c_vp, c_vp]),
         "sq_ring_row": (c_int, [c_int, c_ll, c_int, P(c_int)]),
         "sq_gemm_tile_order": (c_int, [c_int, c_int, c_int, c_int, P(c_int)]),
         "sq_bf16_operand_copies": (c_int, [c_int]),

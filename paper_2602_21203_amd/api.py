@@ -471,6 +471,16 @@ class Agent:
         st.synchronize()
         return idx
 
+    def last_target(self, stream=None):
+        """Projected target distribution m of the last enqueued update ([batch,
+        atoms] float32, device; C51 heads only), ordered after it on the agent's
+        stream."""
+        m = torch.empty((self.batch, self.cfg["atoms"]), dtype=torch.float32, device=self.params.device)
+        st = self.stream if stream is None else stream
+        check(L.LIB.sq_agent_last_target(self.handle, ptr(m), stream_handle(st)))
+        st.synchronize()
+        return m
+
     def sync(self, stream=None):
         """Refresh the agent's derived weight copies after params / target were
         changed from outside (sq_agent_sync)."""

@@ -592,6 +592,17 @@ int sq_agent_last_indices(const sq_agent* g, int* idx, sq_stream_t stream) {
   return SQ_OK;
 }
 
+int sq_agent_last_target(const sq_agent* g, float* m, sq_stream_t stream) {
+  if (!g || !m) { set_error("NULL argument to sq_agent_last_target"); return SQ_EINVAL; }
+  if (g->net.d.atoms < 2) {
+    set_error("sq_agent_last_target: scalar critics have no target distribution");
+    return SQ_EINVAL;
+  }
+  SQ_TRY_HIP(hipMemcpyAsync(m, g->mt, sizeof(float) * (size_t)g->B * g->net.d.atoms, hipMemcpyDeviceToDevice,
+                            (hipStream_t)stream));
+  return SQ_OK;
+}
+
 int act(sq_agent* g, const uint8_t* frames, const float* proprio, int n, int sample, unsigned long long request_id,
         float* action_out, sq_stream_t stream) {
   if (!g) { set_error("agent is NULL"); return SQ_EINVAL; }

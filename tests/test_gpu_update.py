@@ -296,6 +296,52 @@ def test_degenerate_targets_match_oracle():
         ag.close()
 
 
+# (config, batch, replay rows, terminal rate, gamma, precision): the update's own
+# mix, many and only terminal rows (every shifted atom of a row on one point), and
+# gamma = 1 without terminals (the widest spread of positions)
+@pytest.mark.parametrize("name,B,cap,done_rate,gamma,prec", [
+    ("tiny", 32, 256, 0.01, 0.99, 0), ("tiny", 32, 256, 0.5, 0.99, 0), ("tiny", 32, 256, 1.0, 0.99, 0),
+    ("tiny", 32, 256, 0.0, 1.0, 0), ("full", 512, 2048, 0.01, 0.99, 0), ("full", 512, 2048, 0.3, 0.99, 0),
+    ("full", 512, 2048, 0.3, 0.99, 1)])
+def test_projected_target_matches_oracle(name, B, cap, done_rate, gamma, prec):
+    """The update's projected target distribution m (Eq. (1) in categorical form:
+    the twin-target softmax average projected onto the support) element by
+    element against the oracle's, in FP32, and invariants of the GPU's m that
+    hold exactly whatever the rounding: no negative mass, each row's mass that of
+    a softmax (1 up to FP32 summation), and a terminal row's mass on at most two
+    adjacent atoms (all of its shifted atoms sit at the reward).  Bar for FP32:
+    the positions b and the bonus -alpha log pi' carry FP32 rounding of at most
+    1e-4 atoms on these supports, which moves each hat weight, and so each m_i (a
+    sum of weights times probabilities that total 1), by at most that; the
+    softmax adds about 1e-6."""
+    print(f"projected target {name} B={B} done_rate={done_rate} gamma={gamma} prec={prec}", flush=True)
+    cfg = H.cfg(name)
+    d = H.odims(name)
+    cpu = synthetic.replay(cap, cfg["H"], cfg["W"], cfg["C"], cfg["proprio"], cfg["action"], seed=11,
+                           done_rate=done_rate)
+    rep_np = H.np_replay(cpu)
+    rep = {k: (v.cuda() if torch.is_tensor(v) else v) for k, v in cpu.items()}
+    ag = api.Agent(cfg, H.params(name), B, prec=prec, gamma=gamma)
+    ag.sac_update(rep, 1)
+    m = ag.last_target().cpu().numpy().astype(np.float64)
+    idx = ag.last_indices().cpu().numpy()
+    ag.close()
+    assert m.shape == (B, d.atoms)
+    assert np.all(np.isfinite(m)) and m.min() >= 0.0
+    np.testing.assert_allclose(m.sum(axis=1), 1.0, rtol=0, atol=1e-5)
+    done = rep_np["done"][idx] != 0
+    for b in np.flatnonzero(done):
+        nz = np.flatnonzero(m[b])
+        assert 1 <= len(nz) <= 2 and nz[-1] - nz[0] <= 1, (b, nz)
+    if prec == 0:
+        st = sac.new_state(d, H.params(name).astype(np.float64))
+        o = sac.sac_update(st, rep_np, d, sac.hparams(d, gamma=gamma), B)
+        np.testing.assert_array_equal(idx, o["idx"])
+        err = np.abs(m - o["m"]).max()
+        print(f"  max |m - m_oracle| {err:.3e}", flush=True)
+        assert err <= 1e-4 + 1e-5
+
+
 @pytest.mark.parametrize("name,B,prec", [("tiny", 32, 0), ("tiny", 32, 1), ("full", 512, 1)])
 def test_silent_heads_update_matches_its_closed_form(name, B, prec):
     """Zero twin critic heads, a constant actor head, all-terminal transitions and
