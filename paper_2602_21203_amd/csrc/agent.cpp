@@ -214,6 +214,13 @@ static int make_twins(sq_agent* g) {
     if (d.atoms > 1) drop.push_back({g->crit.g2, 4 * B * H});
     for (const Item& it : drop) fp32_drop_register(g, it.f, (long long)it.n);
   }
+  // the target critic's packed weights are read only by the target batches of the
+  // critic products, through their copies, where the inputs are images (the
+  // state-based first layer reads the sampled states, which have no copy)
+  if (H % 8 == 0 && d.n_conv > 0) {
+    fp32_drop_register(g, g->tpack, (long long)g->L.pack_critic_end);
+    g->pk_critic.tpack32 = 0;
+  }
   g->pk_critic.pack_h = g->pk_actor.pack_h = twin_of(g->pack, g->L.pack_total);
   g->pk_critic.tpack_h = twin_of(g->tpack, g->L.pack_critic_end);
   return SQ_OK;

@@ -400,6 +400,7 @@ struct PackArgs {
   int n; PackSeg seg[16];
   float* pack; float* tpack; long long p_begin;
   uint16_t* pack_h = nullptr; uint16_t* tpack_h = nullptr;   // their bfloat16 copies (nullable)
+  int tpack32 = 1;   // 0: the optimiser refreshes only tpack's bfloat16 copy (its FP32 values are not kept)
 };
 // Gradients that are still row-block partials: parameter i in [begin, begin + H)
 // (relative to the optimiser's range) has gradient sum_{r < nrows} part[r * H + i - begin],

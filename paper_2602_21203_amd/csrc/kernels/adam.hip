@@ -24,12 +24,15 @@ __device__ __forceinline__ long long pack_pos(const PackArgs& pk, long long i, i
   return -1;
 }
 
-// Each workgroup updates 256 * kAdamPer consecutive parameters.  The packed
-// segment holding the workgroup's first parameter is found once; parameters of
-// that segment map to their packed position with one division, the rare others
-// (a workgroup straddling a segment boundary) search the table.  Gradients given
-// as row-block partials (gs) are summed here, in row order.
-constexpr int kAdamPer = 4;
+// Each workgroup updates 256 * PER consecutive parameters (PER = 4, or 2 where
+// that leaves fewer than kAdamMinPerCU element workgroups per compute unit: the
+// actor's launch measured 10.2 against 11.4 us with 2, the critic's 20.3 against
+// 18.1 us).  The packed segment holding the workgroup's first parameter is found
+// once; parameters of that segment map to their packed position with one
+// division, the rare others (a workgroup straddling a segment boundary) search
+// the table.  Gradients given as row-block partials (gs) are summed here, in row
+// order.  Every parameter's update is independent, so PER changes no result.
+constexpr int kAdamCUs = 256, kAdamMinPerCU = 3;
 
 // fixed-order sum over the 256 threads; valid in thread 0
 __device__ float adam_block_sum(float v, float* sh) {
@@ -137,7 +140,7 @@ __device__ __forceinline__ void adam_elem(const AdamArgs& A, const PackArgs& pk,
       pk.pack[d] = pi;
       if (pk.pack_h) pk.pack_h[d] = bf16_bits(pi);
       if (critic && pk.tpack && A.ema && i >= A.ema_begin) {
-        pk.tpack[d] = ei;
+        if (pk.tpack32) pk.tpack[d] = ei;
         if (pk.tpack_h) pk.tpack_h[d] = bf16_bits(ei);
       }
     }
@@ -150,7 +153,8 @@ __device__ __forceinline__ void adam_elem(const AdamArgs& A, const PackArgs& pk,
 // workgroup per 64 parameters of every partial-gradient segment: wave w sums the
 // partial rows w, w + 4, ... of its lane's parameter, the four wave sums are
 // added in wave order (the order colsum() uses), and wave 0 applies the update.
-// The rest take 256 * kAdamPer consecutive parameters each, skipping the segments.
+// The rest take 256 * PER consecutive parameters each, skipping the segments.
+template <int PER>
 __global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs gs, int seg_blocks, AlphaJob aj,
                                               int alpha_on, FinishJob fj, int fin_on) {
   int bid = (int)blockIdx.x;
@@ -196,7 +200,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs 
     }
     return;
   }
-  const long long b0 = (long long)(bid - seg_blocks) * 256 * kAdamPer;
+  const long long b0 = (long long)(bid - seg_blocks) * 256 * PER;
   int s0 = -1;
   for (int s = 0; s < pk.n; ++s) {
     const long long loc = b0 + pk.p_begin - pk.seg[s].src;
@@ -206,7 +210,7 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs A, PackArgs pk, GradSegs 
   int q0 = 0;
   while (q0 < gs.n && gs.s[q0].begin + gs.s[q0].H <= b0) ++q0;
 #pragma unroll
-  for (int u = 0; u < kAdamPer; ++u) {
+  for (int u = 0; u < PER; ++u) {
     const long long i = b0 + u * 256 + threadIdx.x;
     if (i >= A.n) break;
     int q = q0;
@@ -224,7 +228,8 @@ int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hpa
     return SQ_EINVAL;
   }
   if (n <= 0 && !aj && !fj) return SQ_OK;
-  const long long blocks = n > 0 ? (n + 256 * kAdamPer - 1) / (256 * kAdamPer) : 0;
+  const int per = (n + 1023) / 1024 >= (long long)kAdamMinPerCU * kAdamCUs ? 4 : 2;
+  const long long blocks = n > 0 ? (n + 256 * per - 1) / (256 * per) : 0;
   PackArgs none{};
   GradSegs nogs{};
   AlphaJob noaj{};
@@ -249,8 +254,13 @@ int adam(float* p, const float* g, float* m, float* v, long long n, const sq_hpa
   const AdamArgs A{p, g, m, v, n, hp->lr, hp->beta1, hp->beta2, hp->adam_eps, step, ema_target, ema_begin, hp->rho,
                    shadow, ep ? *ep : EncPrepMap{}};
   const FinishJob nofj{};
-  k_adam<<<(unsigned)(blocks + seg_blocks + (aj || fj ? 1 : 0)), 256, 0, st>>>(
-      A, pk ? *pk : none, gs ? *gs : nogs, (int)seg_blocks, aj ? *aj : noaj, aj ? 1 : 0, fj ? *fj : nofj, fj ? 1 : 0);
+  const unsigned grid = (unsigned)(blocks + seg_blocks + (aj || fj ? 1 : 0));
+  if (per == 4)
+    k_adam<4><<<grid, 256, 0, st>>>(A, pk ? *pk : none, gs ? *gs : nogs, (int)seg_blocks, aj ? *aj : noaj, aj ? 1 : 0,
+                                    fj ? *fj : nofj, fj ? 1 : 0);
+  else
+    k_adam<2><<<grid, 256, 0, st>>>(A, pk ? *pk : none, gs ? *gs : nogs, (int)seg_blocks, aj ? *aj : noaj, aj ? 1 : 0,
+                                    fj ? *fj : nofj, fj ? 1 : 0);
   return launch_status("adam");
 }
 
