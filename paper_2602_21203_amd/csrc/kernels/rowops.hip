@@ -199,7 +199,7 @@ __device__ __forceinline__ void ln_fwd_row(const float* __restrict__ pre, long l
 }
 
 // rows (one per wave) per LayerNorm forward workgroup: 8 measured 0.2-0.5 % more
-// bfloat16 updates/s than 4 on two boxes (half the workgroups, the same per-row work)
+// bfloat16 updates/s than 4 (half the workgroups, the same per-row work)
 constexpr int kLnFwdRows = 8;
 
 template <int E, bool VEC>
